@@ -1,0 +1,169 @@
+/*
+ * igamg — multigrid solver for multi-patch isogeometric discretizations of the
+ * Poisson problem on AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Takacs, "Fast multigrid solvers for conforming and non-conforming
+ * multi-patch Isogeometric Analysis" (arXiv:1902.01818).
+ *   - model problem -Delta u = f, u = 0 on the boundary: Section 2, eq. model
+ *   - patches G_k:(0,1)^d -> Omega_k, tensor B-splines of degree p, maximum
+ *     smoothness: Section 2, eqs. omega:1, omega:2, local
+ *   - conforming space: Section 2, eq. igaspace0; SIPG space and bilinear
+ *     form: Section 3, eqs. igaspace, model:discr2, penalty of the finest grid
+ *     on every level: eq. a:galerkin
+ *   - V-cycle: Algorithm 1; hybrid smoother: Algorithm 2 (Section 6);
+ *     Gauss-Seidel: Section 4; subspace corrected mass smoother: Section 5,
+ *     eq. Ldef; stopping rule and PCG: Section 4.
+ *
+ * Conventions common to all entry points
+ *   - Every function returns an int status: 0 = success, < 0 = error,
+ *     > 0 = warning (IGAMG_ENOCONV).  No C++ exception crosses this boundary.
+ *     igamg_last_error() returns a thread-local message for the last error.
+ *   - Vectors passed to the device entry points are caller-owned device
+ *     pointers (float64, contiguous), in the compact ordering: patches in array
+ *     order, inside a patch lexicographic with x fastest, unknowns with a
+ *     non-zero trace on the boundary skipped; in the conforming case a glued
+ *     interface unknown keeps the index of its first visit.  Several
+ *     right-hand sides are stored one after the other ([nrhs][N]).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device entry
+ *     points are asynchronous on that stream unless stated otherwise.
+ *   - A context owns all device memory it allocates; igamg_destroy frees it.
+ *     A context must not be used from two host threads at the same time.
+ */
+#ifndef IGAMG_H
+#define IGAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IGAMG_OK 0
+#define IGAMG_EINVAL (-1)       /* invalid argument or geometry */
+#define IGAMG_EUNSUPPORTED (-2) /* valid input this library does not handle */
+#define IGAMG_ENOMEM (-3)       /* device allocation failed / over budget */
+#define IGAMG_EHIP (-4)         /* HIP runtime error */
+#define IGAMG_ENOCONV 1         /* warning: tolerance not reached in maxit */
+
+/* discretization (Sections 2 and 3) */
+#define IGAMG_SIPG 0
+#define IGAMG_CONFORMING 1
+/* smoother: Algorithm 2 (hybrid), Algorithm 1 with eq. Ldef (SCMS), Section 4 (GS) */
+#define IGAMG_SMOOTHER_HYBRID 0
+#define IGAMG_SMOOTHER_SCMS 1
+#define IGAMG_SMOOTHER_GS 2
+/* arithmetic of the cycle (the outer iteration is always float64) */
+#define IGAMG_FP64 0
+#define IGAMG_FP32 1
+/* outer iteration: PCG (Section 4), multigrid as solver (Section 4, "-i d") */
+#define IGAMG_OUTER_PCG 0
+#define IGAMG_OUTER_MG 1
+#define IGAMG_OUTER_FCG 2
+
+/* Multi-patch geometry (Section 2, eqs. omega:1/omega:2, Assumption 1).
+ * Each patch map is the multilinear interpolation of its 2^dim corners; corner
+ * b has parameter coordinates (bit_0(b), ..., bit_{dim-1}(b)), x fastest.
+ * Patches that share a full side must traverse it with the same orientation.
+ * All pointers are host pointers, read during igamg_setup only. */
+typedef struct {
+  int dim;                /* 2 or 3 */
+  int n_patches;          /* K >= 1 */
+  const double *corners;  /* [n_patches][2^dim][dim] */
+  const int32_t *elems;   /* [n_patches][dim] elements per direction on the finest level */
+} igamg_patches;
+
+typedef struct {
+  int discretization; /* IGAMG_SIPG or IGAMG_CONFORMING */
+  int smoother;       /* IGAMG_SMOOTHER_* */
+  int mu;             /* 1 = V-cycle, 2 = W-cycle (Algorithm 1) */
+  int nu;             /* smoothing steps (Algorithm 1/2) */
+  double damping_tau; /* tau of eq. Ldef */
+  double scaling_delta; /* SCMS scaling sigma = 1/(delta h^2), Section 5 */
+  int precision;      /* IGAMG_FP64 / IGAMG_FP32 (cycle arithmetic) */
+  int outer;          /* IGAMG_OUTER_* */
+  int gs_tile;        /* Gauss-Seidel tile width T >= p of the colour ordering, 0 = 4(p+1) */
+  int coarse_min;     /* halve element counts while all are even and their half >= coarse_min; 0 = 2 */
+  int timing;         /* 1 = record per-kernel-family event timings (igamg_kernel_stats) */
+} igamg_options;
+
+typedef struct {
+  int iterations;          /* outer iterations performed */
+  double rel_residual;     /* ||r_k|| / ||f|| of the outer recurrence at exit */
+  double true_rel_residual;/* ||f - A u|| / ||f|| recomputed in float64 at exit */
+  double seconds;          /* wall time of the solve on the host */
+  double *history;         /* optional host array [maxit+1] of relative residuals, or NULL */
+} igamg_solve_info;
+
+typedef struct igamg_ctx igamg_ctx;
+
+/* Fill *o with the defaults (SIPG, hybrid, V(1,1), tau 0.25, delta 0.1, FP64, PCG). */
+void igamg_default_options(igamg_options *o);
+
+/* Host only, no GPU work: device bytes igamg_setup will allocate for this
+ * problem (used for admission by memory footprint).  Errors: IGAMG_EINVAL. */
+int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o,
+                    size_t *bytes);
+
+/* Build the grid hierarchy (uniform dyadic refinement, Section 2), the
+ * operators of every level (SIPG: penalty sigma p^2/h with the finest h,
+ * eq. a:galerkin), transfer operators (canonical embedding, Section 4),
+ * smoother data (Section 5: SCMS factors, interface piece factorizations;
+ * Section 4: Gauss-Seidel colouring) and the coarse Cholesky factorization.
+ * degree >= 1; penalty_sigma > 0 (SIPG only).  Synchronizes `stream`.
+ * Errors: IGAMG_EINVAL (dim, degree, non-positive Jacobian, conforming
+ * interface mismatch), IGAMG_EUNSUPPORTED (flipped interface orientation,
+ * Gauss-Seidel with the conforming space), IGAMG_ENOMEM, IGAMG_EHIP.
+ * On success *out owns the context. */
+int igamg_setup(const igamg_patches *patches, int degree, double penalty_sigma,
+                const igamg_options *o, void *stream, igamg_ctx **out);
+
+/* Number N of unknowns on the finest level (compact ordering). */
+int igamg_num_dofs(const igamg_ctx *ctx, int64_t *n);
+/* Number of grid levels L+1. */
+int igamg_num_levels(const igamg_ctx *ctx, int *levels);
+
+/* y = A_L x (eq. linear:system / linear:system:0), float64; x, y device [nrhs][N].
+ * The volume part is evaluated matrix-free by sum factorization. */
+int igamg_apply(igamg_ctx *ctx, const double *x, double *y, int nrhs, void *stream);
+
+/* One multigrid cycle u <- MG(L, f, u) (Algorithm 1 or 2 per options), u
+ * in/out, f in; device [nrhs][N]; internal arithmetic per o->precision. */
+int igamg_vcycle(igamg_ctx *ctx, const double *f, double *u, int nrhs, void *stream);
+
+/* Solve A_L u = rhs until ||rhs - A u|| / ||rhs|| <= tol (Section 4) with the
+ * outer iteration of the options (PCG preconditioned by one cycle, or the cycle
+ * used directly).  u: device in/out (initial guess used if use_initial_guess,
+ * else zero).  info: host array [nrhs] or NULL.  Synchronizes `stream` once
+ * per outer iteration (convergence test).  Returns IGAMG_ENOCONV if a
+ * right-hand side missed tol within maxit; u then holds the last iterate. */
+int igamg_solve(igamg_ctx *ctx, const double *rhs, double *u, int nrhs, double tol,
+                int maxit, int use_initial_guess, igamg_solve_info *info, void *stream);
+
+/* f_i = (f, phi_i) for f = d pi^2 prod sin(pi x) (exact solution prod sin(pi x),
+ * Section 2), Gauss quadrature with p+1 points; f device [N]. */
+int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream);
+
+/* Device bytes owned by the context. */
+int igamg_memory(const igamg_ctx *ctx, size_t *bytes);
+
+/* Per-kernel-family event timings recorded since the last reset when the
+ * context was set up with o->timing = 1.  names: host array of `cap` char
+ * buffers of 32 bytes; ms / launches: host arrays [cap].  *count = families
+ * written.  reset != 0 clears the counters after reading.  Synchronizes. */
+int igamg_kernel_stats(igamg_ctx *ctx, int cap, char (*names)[32], double *ms,
+                       int64_t *launches, int *count, int reset);
+
+/* Algorithmic bytes moved and flops of one launch of a kernel family on the
+ * finest level (the roofline model of the library's kernels). */
+int igamg_kernel_model(igamg_ctx *ctx, const char *family, double *bytes, double *flops);
+
+int igamg_destroy(igamg_ctx *ctx);
+const char *igamg_strerror(int code);
+const char *igamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGAMG_H */

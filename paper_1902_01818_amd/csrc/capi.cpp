@@ -1,0 +1,254 @@
+// extern "C" boundary of the library (declarations and contracts: include/igamg.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "context.h"
+#include "kernels.h"
+
+struct igamg_ctx {
+  igamg::Context c;
+};
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const igamg::Error &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return IGAMG_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return IGAMG_EINVAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return IGAMG_EINVAL;
+  }
+}
+
+void flush_timers(igamg::Context &c) {
+  HIPCHK(hipStreamSynchronize(c.stream));
+  for (auto &kv : c.timers) {
+    for (auto &pe : kv.second.pending) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, pe.first, pe.second));
+      kv.second.ms += ms;
+      kv.second.pool.push_back(pe);
+    }
+    kv.second.pending.clear();
+  }
+}
+}  // namespace
+
+extern "C" {
+
+void igamg_default_options(igamg_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->discretization = IGAMG_SIPG;
+  o->smoother = IGAMG_SMOOTHER_HYBRID;
+  o->mu = 1;
+  o->nu = 1;
+  o->damping_tau = 0.25;
+  o->scaling_delta = 0.1;
+  o->precision = IGAMG_FP64;
+  o->outer = IGAMG_OUTER_PCG;
+  o->gs_tile = 0;
+  o->coarse_min = 0;
+  o->timing = 0;
+}
+
+int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o,
+                    size_t *bytes) {
+  return guarded([&] {
+    if (!bytes || !o) igamg::fail(IGAMG_EINVAL, "null argument");
+    *bytes = igamg::estimate_footprint(patches, degree, o);
+    return IGAMG_OK;
+  });
+}
+
+int igamg_setup(const igamg_patches *patches, int degree, double penalty_sigma,
+                const igamg_options *o, void *stream, igamg_ctx **out) {
+  return guarded([&] {
+    if (!out) igamg::fail(IGAMG_EINVAL, "null output pointer");
+    *out = nullptr;
+    igamg_ctx *ctx = new igamg_ctx();
+    try {
+      igamg::build_context(ctx->c, patches, degree, penalty_sigma, o, (hipStream_t)stream);
+    } catch (...) {
+      (void)hipStreamSynchronize((hipStream_t)stream);
+      delete ctx;
+      throw;
+    }
+    *out = ctx;
+    return IGAMG_OK;
+  });
+}
+
+int igamg_num_dofs(const igamg_ctx *ctx, int64_t *n) {
+  return guarded([&] {
+    if (!ctx || !n) igamg::fail(IGAMG_EINVAL, "null argument");
+    *n = ctx->c.lv.back().N;
+    return IGAMG_OK;
+  });
+}
+
+int igamg_num_levels(const igamg_ctx *ctx, int *levels) {
+  return guarded([&] {
+    if (!ctx || !levels) igamg::fail(IGAMG_EINVAL, "null argument");
+    *levels = (int)ctx->c.lv.size();
+    return IGAMG_OK;
+  });
+}
+
+int igamg_apply(igamg_ctx *ctx, const double *x, double *y, int nrhs, void *stream) {
+  return guarded([&] {
+    if (!ctx || !x || !y || nrhs < 1) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    igamg::Context &c = ctx->c;
+    c.stream = (hipStream_t)stream;
+    igamg::LevelData &L = c.lv.back();
+    const int top = (int)c.lv.size() - 1;
+    for (int j = 0; j < nrhs; ++j) {
+      igamg::k_fill(c.x, 0.0, L.Ntorn, c.stream);
+      igamg::k_scatter_compact(x + (size_t)j * L.N, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, c.stream);
+      igamg::apply_torn(c, top, c.x, nullptr, nullptr, c.qq, 1.0);
+      igamg::k_gather_compact(c.qq, L.N, c.d_fin_cp, c.d_fin_cidx, 0, y + (size_t)j * L.N, c.stream);
+    }
+    HIPCHK(hipGetLastError());
+    return IGAMG_OK;
+  });
+}
+
+int igamg_vcycle(igamg_ctx *ctx, const double *f, double *u, int nrhs, void *stream) {
+  return guarded([&] {
+    if (!ctx || !f || !u || nrhs < 1) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    igamg::Context &c = ctx->c;
+    c.stream = (hipStream_t)stream;
+    igamg::LevelData &L = c.lv.back();
+    const int top = (int)c.lv.size() - 1;
+    for (int j = 0; j < nrhs; ++j) {
+      igamg::k_fill(c.ff, 0.0, L.Ntorn, c.stream);
+      igamg::k_scatter_compact(f + (size_t)j * L.N, L.N, c.d_fin_cp, c.d_fin_cidx, c.ff, c.stream);
+      igamg::k_copy_weighted(c.ff, L.d_weight, L.f, L.Ntorn, c.stream);
+      igamg::k_fill(L.u, 0.0, L.Ntorn, c.stream);
+      igamg::k_scatter_compact(u + (size_t)j * L.N, L.N, c.d_fin_cp, c.d_fin_cidx, L.u, c.stream);
+      igamg::vcycle_torn(c, top);
+      igamg::k_gather_compact(L.u, L.N, c.d_fin_cp, c.d_fin_cidx, 0, u + (size_t)j * L.N, c.stream);
+    }
+    HIPCHK(hipGetLastError());
+    return IGAMG_OK;
+  });
+}
+
+int igamg_solve(igamg_ctx *ctx, const double *rhs, double *u, int nrhs, double tol, int maxit,
+                int use_initial_guess, igamg_solve_info *info, void *stream) {
+  return guarded([&] {
+    if (!ctx || !rhs || !u || nrhs < 1 || maxit < 0 || !(tol >= 0))
+      igamg::fail(IGAMG_EINVAL, "invalid argument");
+    igamg::Context &c = ctx->c;
+    c.stream = (hipStream_t)stream;
+    const long long N = c.lv.back().N;
+    int status = IGAMG_OK;
+    for (int j = 0; j < nrhs; ++j) {
+      int s = igamg::solve_compact(c, rhs + (size_t)j * N, u + (size_t)j * N, tol, maxit,
+                                   use_initial_guess, info ? info + j : nullptr);
+      if (s != IGAMG_OK) status = s;
+    }
+    HIPCHK(hipGetLastError());
+    return status;
+  });
+}
+
+int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream) {
+  return guarded([&] {
+    if (!ctx || !f) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    igamg::Context &c = ctx->c;
+    c.stream = (hipStream_t)stream;
+    igamg::LevelData &L = c.lv.back();
+    igamg::k_load_manufactured(c, L, c.qq);
+    // every copy holds its patch's integral: the assembled value is their sum
+    igamg::k_gather_compact(c.qq, L.N, c.d_fin_cp, c.d_fin_cidx, 1, f, c.stream);
+    HIPCHK(hipGetLastError());
+    return IGAMG_OK;
+  });
+}
+
+int igamg_memory(const igamg_ctx *ctx, size_t *bytes) {
+  return guarded([&] {
+    if (!ctx || !bytes) igamg::fail(IGAMG_EINVAL, "null argument");
+    *bytes = ctx->c.arena.bytes;
+    return IGAMG_OK;
+  });
+}
+
+int igamg_kernel_stats(igamg_ctx *ctx, int cap, char (*names)[32], double *ms, int64_t *launches,
+                       int *count, int reset) {
+  return guarded([&] {
+    if (!ctx || !count) igamg::fail(IGAMG_EINVAL, "null argument");
+    igamg::Context &c = ctx->c;
+    flush_timers(c);
+    int n = 0;
+    for (auto &kv : c.timers) {
+      if (n < cap) {
+        if (names) {
+          std::strncpy(names[n], kv.first.c_str(), 31);
+          names[n][31] = 0;
+        }
+        if (ms) ms[n] = kv.second.ms;
+        if (launches) launches[n] = kv.second.launches;
+      }
+      ++n;
+      if (reset) {
+        kv.second.ms = 0;
+        kv.second.launches = 0;
+      }
+    }
+    *count = n < cap ? n : cap;
+    return IGAMG_OK;
+  });
+}
+
+int igamg_kernel_model(igamg_ctx *ctx, const char *family, double *bytes, double *flops) {
+  return guarded([&] {
+    if (!ctx || !family || !bytes || !flops) igamg::fail(IGAMG_EINVAL, "null argument");
+    igamg::Context &c = ctx->c;
+    if (std::string(family) == "vol_apply") {
+      *bytes = c.model_vol_bytes;
+      *flops = c.model_vol_flops;
+      return IGAMG_OK;
+    }
+    igamg::fail(IGAMG_EINVAL, "no model for this kernel family");
+  });
+}
+
+int igamg_destroy(igamg_ctx *ctx) {
+  return guarded([&] {
+    if (!ctx) return IGAMG_OK;
+    (void)hipStreamSynchronize(ctx->c.stream);
+    delete ctx;
+    return IGAMG_OK;
+  });
+}
+
+const char *igamg_strerror(int code) {
+  switch (code) {
+    case IGAMG_OK: return "success";
+    case IGAMG_EINVAL: return "invalid argument";
+    case IGAMG_EUNSUPPORTED: return "unsupported input";
+    case IGAMG_ENOMEM: return "out of device memory";
+    case IGAMG_EHIP: return "HIP runtime error";
+    case IGAMG_ENOCONV: return "tolerance not reached";
+    default: return "unknown status";
+  }
+}
+
+const char *igamg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// The solver context: hierarchy, device data and work vectors.
+#pragma once
+#include <array>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace igamg {
+
+// device allocation owned by the context
+struct Arena {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  T *alloc(size_t n) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) fail(IGAMG_ENOMEM, "hipMalloc failed");
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    return (T *)p;
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    T *p = alloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+struct GsClass {
+  GsTile *tiles;
+  int count;
+};
+
+struct LevelData {
+  int l = 0;
+  int K = 0;
+  std::vector<PatchDev> pd;                 // host copy
+  PatchDev *d_pd = nullptr;
+  long long Ntorn = 0;
+  long long N = 0;                          // compact unknowns
+  std::vector<unsigned char> mask;          // 1 = free, 0 = Dirichlet
+  std::vector<int> comp;                    // torn -> compact (-1 Dirichlet)
+  std::vector<int> rep;                     // compact -> representative torn
+  std::vector<std::vector<int>> copies;     // compact -> all torn copies (conforming)
+  // element tables of this level (distinct element counts share entries)
+  std::vector<double> tabB, tabD;
+  double *d_tabB = nullptr, *d_tabD = nullptr;
+  // interface CSR over torn rows: all interface terms, cross-patch part flagged
+  std::vector<int> if_ptr, if_col;
+  std::vector<double> if_val;
+  std::vector<unsigned char> if_cross;
+  int *d_if_ptr = nullptr, *d_if_col = nullptr;
+  double *d_if_val = nullptr;
+  int *d_cx_ptr = nullptr, *d_cx_col = nullptr;
+  double *d_cx_val = nullptr;
+  // same-side interface entries added to the stencil (torn row, stencil slot, value)
+  // volume stencil + inverse diagonal (Gauss-Seidel)
+  double *d_stencil = nullptr, *d_invdiag = nullptr;
+  unsigned char *d_mask = nullptr;
+  double *d_weight = nullptr;  // 1 on the representative copy of a free unknown
+  // glue groups (conforming): CSR of torn copies of every shared unknown
+  int n_glue = 0;
+  int *d_glue_ptr = nullptr, *d_glue_idx = nullptr;
+  // tiles
+  VolTile *d_vtiles = nullptr;
+  int n_vtiles = 0;
+  std::vector<GsClass> gs;  // classes in key order
+  // SCMS interiors: four batched GEMM stages
+  GemmItem *d_gemm[4] = {nullptr, nullptr, nullptr, nullptr};
+  int n_gemm = 0;
+  int gemm_maxM = 0, gemm_maxN = 0;
+  // interface pieces
+  PieceDev *d_pieces = nullptr;
+  int n_pieces = 0, max_piece = 0;
+  int *d_piece_idx = nullptr, *d_piece_cp = nullptr, *d_piece_cidx = nullptr;
+  double *d_piece_inv = nullptr;
+  // transfer tables between this level and the next coarser one
+  int *d_P_lo = nullptr, *d_R_lo = nullptr;
+  double *d_P_val = nullptr, *d_R_val = nullptr;
+  int PW = 0, RW = 0;
+  // work vectors
+  double *f = nullptr, *u = nullptr, *r = nullptr;
+};
+
+struct TimerFamily {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+
+struct Context {
+  int d = 2, p = 2, K = 0;
+  igamg_options opt{};
+  double sigma_pen = 5.0;
+  GaussRule gr{};
+  std::vector<std::array<double, 24>> corners;   // [K][8*3]
+  std::vector<std::array<int, 3>> elems_fine;
+  // topology
+  std::vector<std::vector<int>> vid;              // [K][2^d] vertex ids
+  struct Iface {
+    int k, dk, sk, l, dl, sl;
+    double eta;
+  };
+  std::vector<Iface> ifaces;
+  std::vector<std::array<unsigned char, 6>> boundary;  // [K][2*dir+s]
+  std::vector<int> color;
+  int n_colors = 1;
+  std::vector<double> measure;
+  std::vector<LevelData> lv;                      // level 0 = coarsest
+  // coarse solve
+  int N0 = 0;
+  double *d_A0inv = nullptr;
+  int *d_c0_rep = nullptr;       // compact -> rep torn on level 0
+  int *d_c0_cp = nullptr, *d_c0_cidx = nullptr;  // compact -> copies CSR
+  // finest-level maps (ABI)
+  int *d_fin_rep = nullptr, *d_fin_cp = nullptr, *d_fin_cidx = nullptr;
+  // outer iteration vectors (torn layout, finest level)
+  double *x = nullptr, *rr = nullptr, *z = nullptr, *pp = nullptr, *qq = nullptr, *ff = nullptr;
+  double *d_red = nullptr;       // reduction partials
+  double *d_scal = nullptr;      // device scalars
+  double *h_scal = nullptr;      // pinned host mirror
+  // SCMS scratch
+  double *scratch1 = nullptr, *scratch2 = nullptr;
+  hipStream_t stream = nullptr;
+  Arena arena;
+  std::map<std::string, TimerFamily> timers;
+  // roofline model inputs
+  double model_vol_flops = 0, model_vol_bytes = 0;
+
+  void launch_begin(const char *fam, hipEvent_t *b, hipEvent_t *e);
+  void launch_end(const char *fam, hipEvent_t b, hipEvent_t e);
+  ~Context();
+};
+
+void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
+                   const igamg_options *o, hipStream_t s);
+size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_options *o);
+
+// cycle / outer iteration (cycle.cpp)
+void apply_torn(Context &c, int l, const double *u, const double *f, const double *fw, double *r,
+                double alpha);
+void vcycle_torn(Context &c, int l);
+int solve_compact(Context &c, const double *rhs, double *u, double tol, int maxit, int use_x0,
+                  igamg_solve_info *info);
+
+}  // namespace igamg

@@ -1,0 +1,82 @@
+// Internal data structures of the igamg library (host setup, kernels, cycle).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/igamg.h"
+
+namespace igamg {
+
+constexpr int MAXP = 8;   // largest spline degree
+constexpr int MAXQ = 12;  // largest Gauss rule
+
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+#define HIPCHK(x)                                                                \
+  do {                                                                           \
+    hipError_t e_ = (x);                                                         \
+    if (e_ != hipSuccess)                                                        \
+      ::igamg::fail(IGAMG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Gauss-Legendre rule on [0,1], passed to kernels by value.
+struct GaussRule {
+  int q;
+  double x[MAXQ];
+  double w[MAXQ];
+};
+
+// One patch on one level, as the kernels see it.
+struct PatchDev {
+  double corners[8][3];
+  int n[3];          // basis functions per direction (nel + p); 1 in unused directions
+  int nel[3];        // elements per direction
+  int stride[3];     // tensor strides (x fastest)
+  long long off;     // offset of the patch tensor in the level vector
+  int tab[3];        // offset of the direction's 1D element tables ([e][g][a] entries)
+  int xp[3];         // prolongation rows from the coarser level: offset into lo / val tables
+  int xr[3];         // restriction rows to the coarser level (on the coarse patch entry)
+  int color;         // patch colour of the Gauss-Seidel ordering
+  double scms_scale; // tau / gamma_k
+  double sigma;      // SCMS scaling 1/(delta h^2)
+};
+
+struct VolTile {
+  int patch;
+  int e0[3];
+};
+
+struct GsTile {
+  int patch;
+  int i0[3];
+};
+
+// Batched GEMM item: C = A * B with strided operands (row / column strides),
+// optional epilogues: divide by (sigma + lam_r[m] + lam_c[n]); C += scale * acc.
+struct GemmItem {
+  const void *A;
+  const void *B;
+  void *C;
+  int M, N, K;
+  long long a_r, a_c, b_r, b_c, c_r, c_c;
+  const double *lam_r;
+  const double *lam_c;
+  double sigma;
+  double scale;
+};
+
+// Interface piece of the additive smoother (eq. Ldef): dense inverse of P^T A P.
+struct PieceDev {
+  long long inv_off;  // offset of the n x n inverse in the value array
+  int n;
+  int idx_off;        // gather indices (one torn index per piece unknown)
+  int cp_off;         // scatter CSR row pointer offset (n+1 entries)
+};
+
+}  // namespace igamg

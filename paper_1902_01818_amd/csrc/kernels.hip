@@ -1,0 +1,827 @@
+// HIP kernels of the multigrid cycle for gfx950 (MI355X).
+//
+//  * volume operator: per-patch stiffness (Section 2, eq. model) applied
+//    matrix-free by sum factorization over element tiles staged in LDS, the
+//    metric |det J| J^-1 J^-T recomputed from the patch corners at every
+//    Gauss point;
+//  * interface terms of the SIPG form (Section 3, eq. model:discr2) as a
+//    sparse row-gather over the unknowns next to interfaces;
+//  * multicolour Gauss-Seidel (Section 4) over tiles of a fixed colour order;
+//  * the subspace corrected mass smoother (Section 5, eq. Ldef): patch
+//    interiors by fast diagonalization = four batched GEMMs, interface pieces
+//    by dense inverses of P^T A P;
+//  * canonical embedding / its transpose between dyadic levels (Section 4);
+//  * direct coarse solve and deterministic reductions of the outer PCG.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "geom.h"
+#include "kernels.h"
+
+namespace igamg {
+
+namespace {
+
+constexpr int BS = 256;
+
+inline unsigned nblocks(long long n, int bs = BS) {
+  long long b = (n + bs - 1) / bs;
+  if (b < 1) b = 1;
+  if (b > 65535LL * 64) b = 65535LL * 64;
+  return (unsigned)b;
+}
+
+struct TimeScope {
+  Context &c;
+  const char *fam;
+  hipEvent_t b = nullptr, e = nullptr;
+  TimeScope(Context &c_, const char *f) : c(c_), fam(f) {
+    if (c.opt.timing) c.launch_begin(fam, &b, &e);
+  }
+  ~TimeScope() {
+    if (c.opt.timing) c.launch_end(fam, b, e);
+  }
+};
+
+__device__ inline void atomic_add(double *a, double v) { unsafeAtomicAdd(a, v); }
+
+// ---------------------------------------------------------------------------
+// elementwise
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(double *x, double v, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void copy_weighted_kernel(const double *x, const double *w, double *y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = w ? w[i] * x[i] : x[i];
+}
+
+__global__ void axpy_kernel(double a, const double *x, double *y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+// ---------------------------------------------------------------------------
+// setup: stencil (volume stiffness rows) assembly, gather form
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void stencil_kernel(const PatchDev *pd, int K, const double *tabB, const double *tabD,
+                               GaussRule gr, int p, long long ntorn, double *st) {
+  const int S1 = 2 * p + 1;
+  int S = 1;
+  for (int d = 0; d < D; ++d) S *= S1;
+  long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (tid >= ntorn * S) return;
+  long long t = tid / S;
+  int o = (int)(tid % S);
+  int k = 0;
+  while (k + 1 < K && pd[k + 1].off <= t) ++k;
+  const PatchDev &pt = pd[k];
+  long long loc = t - pt.off;
+  int i[3] = {0, 0, 0}, j[3] = {0, 0, 0};
+  bool ok = true;
+  int oo = o;
+  for (int d = 0; d < D; ++d) {
+    i[d] = (int)(loc % pt.n[d]);
+    loc /= pt.n[d];
+    j[d] = i[d] + (oo % S1) - p;
+    oo /= S1;
+    if (j[d] < 0 || j[d] >= pt.n[d]) ok = false;
+  }
+  st[tid] = ok ? vol_entry<D>(pt, tabB, tabD, gr, p, i, j) : 0.0;
+}
+
+__global__ void stencil_add_kernel(const int *rows, const int *slots, const double *vals, int n,
+                                   double *st, int S) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) st[(long long)rows[i] * S + slots[i]] += vals[i];
+}
+
+__global__ void invdiag_kernel(const double *st, int S, int center, const unsigned char *mask,
+                               double *invd, long long n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) invd[i] = mask[i] ? 1.0 / st[i * S + center] : 0.0;
+}
+
+// (f, phi_i) for f = d pi^2 prod sin(pi x), gather over the support of phi_i
+template <int D>
+__global__ void load_kernel(const PatchDev *pd, int K, const double *tabB, GaussRule gr, int p,
+                            const unsigned char *mask, long long ntorn, double *out) {
+  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= ntorn) return;
+  int k = 0;
+  while (k + 1 < K && pd[k + 1].off <= t) ++k;
+  const PatchDev &pt = pd[k];
+  long long loc = t - pt.off;
+  int i[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < D; ++d) {
+    i[d] = (int)(loc % pt.n[d]);
+    loc /= pt.n[d];
+    lo[d] = i[d] - p < 0 ? 0 : i[d] - p;
+    hi[d] = i[d] > pt.nel[d] - 1 ? pt.nel[d] - 1 : i[d];
+  }
+  if (!mask[t]) {
+    out[t] = 0.0;
+    return;
+  }
+  const int q = gr.q, P1 = p + 1;
+  double sum = 0.0;
+  int e[3] = {lo[0], lo[1], lo[2]};
+  for (;;) {
+    int g[3] = {0, 0, 0};
+    for (;;) {
+      double xh[D], w = 1.0, phi = 1.0;
+      for (int d = 0; d < D; ++d) {
+        xh[d] = ((double)e[d] + gr.x[g[d]]) / (double)pt.nel[d];
+        w *= gr.w[g[d]] / (double)pt.nel[d];
+        phi *= tabB[(size_t)pt.tab[d] + ((size_t)e[d] * q + g[d]) * P1 + (i[d] - e[d])];
+      }
+      double J[D][D], Ji[D][D], X[D];
+      multilinear_jac<D>(pt.corners, xh, J);
+      double det = inverse<D>(J, Ji);
+      multilinear_map<D>(pt.corners, xh, X);
+      double fx = D * M_PI * M_PI;
+      for (int d = 0; d < D; ++d) fx *= sin(M_PI * X[d]);
+      sum += w * (det < 0 ? -det : det) * fx * phi;
+      int d = 0;
+      while (d < D && ++g[d] == q) g[d++] = 0;
+      if (d == D) break;
+    }
+    int d = 0;
+    while (d < D && ++e[d] > hi[d]) {
+      e[d] = lo[d];
+      ++d;
+    }
+    if (d == D) break;
+  }
+  out[t] = sum;
+}
+
+// ---------------------------------------------------------------------------
+// interface terms: r = mask (beta f + alpha A_if u)   (one thread per unknown)
+// ---------------------------------------------------------------------------
+__global__ void iface_kernel(long long n, const unsigned char *mask, const int *ptr, const int *col,
+                             const double *val, const double *u, const double *f,
+                             const double *fw, double beta, double alpha, double *r) {
+  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (!mask[t]) {
+    r[t] = 0.0;
+    return;
+  }
+  double s = 0.0;
+  for (int e = ptr[t]; e < ptr[t + 1]; ++e) s += val[e] * u[col[e]];
+  double v = alpha * s;
+  if (f) v += beta * (fw ? fw[t] : 1.0) * f[t];
+  r[t] = v;
+}
+
+// ---------------------------------------------------------------------------
+// volume operator, 2D, sum factorization on a TE x TE element tile
+// r += alpha * A_vol u  (atomic accumulation of the tile's outputs)
+// ---------------------------------------------------------------------------
+template <int P, int TE>
+__global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const PatchDev *pd,
+                                                    const double *tabB, const double *tabD,
+                                                    GaussRule gr, const double *__restrict__ u,
+                                                    double *__restrict__ r,
+                                                    const unsigned char *__restrict__ mask,
+                                                    double alpha) {
+  constexpr int Q = P + 1, P1 = P + 1;
+  constexpr int ND = TE + P;   // unknowns per direction touched by the tile
+  constexpr int NQ = TE * Q;   // Gauss points per direction in the tile
+  __shared__ double sU[ND * ND];
+  __shared__ double sA0[ND * NQ], sA1[ND * NQ];
+  __shared__ double sV0[NQ * NQ], sV1[NQ * NQ];
+  __shared__ double sBx[NQ * P1], sDx[NQ * P1], sBy[NQ * P1], sDy[NQ * P1];
+  __shared__ double sC[4][3];
+  const VolTile tl = tiles[blockIdx.x];
+  const PatchDev &pt = pd[tl.patch];
+  const int tid = threadIdx.x;
+  const int ex0 = tl.e0[0], ey0 = tl.e0[1];
+  const int nex = min(TE, pt.nel[0] - ex0), ney = min(TE, pt.nel[1] - ey0);
+  const int nx = pt.n[0];
+  const long long off = pt.off;
+  if (tid < 12) sC[tid / 3][tid % 3] = pt.corners[tid / 3][tid % 3];
+  for (int i = tid; i < NQ * P1; i += blockDim.x) {
+    int gq = i / P1;
+    bool okx = gq < nex * Q, oky = gq < ney * Q;
+    sBx[i] = okx ? tabB[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : 0.0;
+    sDx[i] = okx ? tabD[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : 0.0;
+    sBy[i] = oky ? tabB[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : 0.0;
+    sDy[i] = oky ? tabD[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : 0.0;
+  }
+  for (int i = tid; i < ND * ND; i += blockDim.x) {
+    int rr = i / ND, cc = i % ND;
+    sU[i] = (rr < ney + P && cc < nex + P) ? u[off + (long long)(ey0 + rr) * nx + ex0 + cc] : 0.0;
+  }
+  __syncthreads();
+  // x-contraction: A0 = values, A1 = derivatives, rows = unknown rows
+  for (int i = tid; i < ND * NQ; i += blockDim.x) {
+    int rr = i / NQ, gx = i % NQ;
+    int e = gx / Q;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int a = 0; a < P1; ++a) {
+      double uv = sU[rr * ND + e + a];
+      a0 += sBx[gx * P1 + a] * uv;
+      a1 += sDx[gx * P1 + a] * uv;
+    }
+    sA0[i] = a0;
+    sA1[i] = a1;
+  }
+  __syncthreads();
+  // y-contraction + metric at the Gauss points
+  const double hx = 1.0 / pt.nel[0], hy = 1.0 / pt.nel[1];
+  for (int i = tid; i < NQ * NQ; i += blockDim.x) {
+    int gy = i / NQ, gx = i % NQ;
+    double v0 = 0.0, v1 = 0.0;
+    if (gy < ney * Q && gx < nex * Q) {
+      int ey = gy / Q;
+      double ux = 0.0, uy = 0.0;
+#pragma unroll
+      for (int b = 0; b < P1; ++b) {
+        ux += sBy[gy * P1 + b] * sA1[(ey + b) * NQ + gx];
+        uy += sDy[gy * P1 + b] * sA0[(ey + b) * NQ + gx];
+      }
+      int ex = gx / Q;
+      int qx = gx - ex * Q, qy = gy - ey * Q;
+      double xh[2] = {((double)(ex0 + ex) + gr.x[qx]) * hx, ((double)(ey0 + ey) + gr.x[qy]) * hy};
+      double G[2][2];
+      metric<2>(sC, xh, gr.w[qx] * hx * gr.w[qy] * hy, G);
+      v0 = G[0][0] * ux + G[0][1] * uy;
+      v1 = G[1][0] * ux + G[1][1] * uy;
+    }
+    sV0[i] = v0;
+    sV1[i] = v1;
+  }
+  __syncthreads();
+  // transposed y-contraction: rows = output unknown rows
+  for (int i = tid; i < ND * NQ; i += blockDim.x) {
+    int rr = i / NQ, gx = i % NQ;
+    double s1 = 0.0, s0 = 0.0;
+    int elo = max(0, rr - P), ehi = min(ney - 1, rr);
+    for (int e = elo; e <= ehi; ++e) {
+      int a = rr - e;
+#pragma unroll
+      for (int g = 0; g < Q; ++g) {
+        int gy = e * Q + g;
+        s1 += sBy[gy * P1 + a] * sV0[gy * NQ + gx];
+        s0 += sDy[gy * P1 + a] * sV1[gy * NQ + gx];
+      }
+    }
+    sA1[i] = s1;
+    sA0[i] = s0;
+  }
+  __syncthreads();
+  // transposed x-contraction and accumulation
+  for (int i = tid; i < ND * ND; i += blockDim.x) {
+    int rr = i / ND, cc = i % ND;
+    if (rr >= ney + P || cc >= nex + P) continue;
+    double y = 0.0;
+    int elo = max(0, cc - P), ehi = min(nex - 1, cc);
+    for (int e = elo; e <= ehi; ++e) {
+      int a = cc - e;
+#pragma unroll
+      for (int g = 0; g < Q; ++g) {
+        int gx = e * Q + g;
+        y += sDx[gx * P1 + a] * sA1[rr * NQ + gx] + sBx[gx * P1 + a] * sA0[rr * NQ + gx];
+      }
+    }
+    long long t = off + (long long)(ey0 + rr) * nx + ex0 + cc;
+    if (mask[t]) atomic_add(&r[t], alpha * y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// glue (conforming): y <- sum of copies on every copy
+// ---------------------------------------------------------------------------
+__global__ void glue_kernel(int ng, const int *ptr, const int *idx, double *y) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  double s = 0.0;
+  for (int e = ptr[g]; e < ptr[g + 1]; ++e) s += y[idx[e]];
+  for (int e = ptr[g]; e < ptr[g + 1]; ++e) y[idx[e]] = s;
+}
+
+// ---------------------------------------------------------------------------
+// multicolour Gauss-Seidel on one class of tiles (2D)
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void gs2d_kernel(const GsTile *tiles, const PatchDev *pd,
+                                                   const double *__restrict__ st,
+                                                   const double *__restrict__ invd,
+                                                   const int *__restrict__ cx_ptr,
+                                                   const int *__restrict__ cx_col,
+                                                   const double *__restrict__ cx_val,
+                                                   const double *__restrict__ f, double *u,
+                                                   const unsigned char *__restrict__ mask, int T,
+                                                   int backward, int G) {
+  extern __shared__ double sU[];
+  constexpr int S1 = 2 * P + 1, S = S1 * S1, Q1 = P + 1;
+  const int W = T + 2 * P;
+  const GsTile tl = tiles[blockIdx.x];
+  const PatchDev &pt = pd[tl.patch];
+  const int nx = pt.n[0], ny = pt.n[1];
+  const int x0 = tl.i0[0], y0 = tl.i0[1];
+  const int wx0 = x0 - P, wy0 = y0 - P;
+  const long long off = pt.off;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < W * W; i += blockDim.x) {
+    int gy = wy0 + i / W, gx = wx0 + i % W;
+    sU[i] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? u[off + (long long)gy * nx + gx] : 0.0;
+  }
+  __syncthreads();
+  const int tx = min(T, nx - x0), ty = min(T, ny - y0);
+  const int rows_per_pass = blockDim.x / G;
+  const int lane = tid % G;
+  for (int ph = 0; ph < Q1 * Q1; ++ph) {
+    int s = backward ? Q1 * Q1 - 1 - ph : ph;
+    int sy = s / Q1, sx = s % Q1;
+    int fx = x0 + (((sx - x0 % Q1) % Q1) + Q1) % Q1;
+    int fy = y0 + (((sy - y0 % Q1) % Q1) + Q1) % Q1;
+    int cxn = fx < x0 + tx ? (x0 + tx - 1 - fx) / Q1 + 1 : 0;
+    int cyn = fy < y0 + ty ? (y0 + ty - 1 - fy) / Q1 + 1 : 0;
+    int nrows = cxn * cyn;
+    for (int base = 0; base < nrows; base += rows_per_pass) {
+      int row = base + tid / G;
+      bool active = row < nrows;
+      double acc = 0.0;
+      int ix = 0, iy = 0;
+      long long t = 0;
+      if (active) {
+        ix = fx + (row % cxn) * Q1;
+        iy = fy + (row / cxn) * Q1;
+        t = off + (long long)iy * nx + ix;
+        const double *srow = st + t * S;
+        for (int o = lane; o < S; o += G) {
+          int oy = o / S1 - P, ox = o % S1 - P;
+          acc += srow[o] * sU[(iy + oy - wy0) * W + (ix + ox - wx0)];
+        }
+        for (int e = cx_ptr[t] + lane; e < cx_ptr[t + 1]; e += G) acc += cx_val[e] * u[cx_col[e]];
+      }
+      for (int m = G / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, G);
+      if (active && lane == 0 && mask[t]) {
+        int li = (iy - wy0) * W + (ix - wx0);
+        sU[li] = sU[li] + (f[t] - acc) * invd[t];
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < tx * ty; i += blockDim.x) {
+    int iy = y0 + i / tx, ix = x0 + i % tx;
+    u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched GEMM (float64), 64x64 output tile, 4x4 per thread, K chunks of 16
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmItem *items) {
+  const GemmItem it = items[blockIdx.z];
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  if (m0 >= it.M || n0 >= it.N) return;
+  __shared__ double sA[16][64 + 1];
+  __shared__ double sB[16][64 + 1];
+  const double *A = (const double *)it.A;
+  const double *B = (const double *)it.B;
+  const int tid = threadIdx.x;
+  const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < it.K; k0 += 16) {
+    for (int i = tid; i < 16 * 64; i += 256) {
+      int kk = i / 64, mm = i % 64;
+      int m = m0 + mm, k = k0 + kk;
+      sA[kk][mm] = (m < it.M && k < it.K) ? A[m * it.a_r + k * it.a_c] : 0.0;
+      int n = n0 + mm;
+      sB[kk][mm] = (n < it.N && k < it.K) ? B[k * it.b_r + n * it.b_c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        a[x] = sA[kk][tm + x];
+        b[x] = sB[kk][tn + x];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+    }
+    __syncthreads();
+  }
+  double *C = (double *)it.C;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      int m = m0 + tm + x, n = n0 + tn + y;
+      if (m >= it.M || n >= it.N) continue;
+      double v = acc[x][y];
+      if (it.lam_r) v /= (it.sigma + it.lam_r[m] + it.lam_c[n]);
+      double *cp = C + m * it.c_r + n * it.c_c;
+      if (it.scale != 0.0)
+        *cp += it.scale * v;
+      else
+        *cp = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// interface pieces: u[copies] += inv(P^T A P) r[piece]   (one block per piece)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void piece_kernel(const PieceDev *pieces, const int *idx,
+                                                    const int *cp, const int *cidx,
+                                                    const double *inv, const double *r, double *u,
+                                                    double scale) {
+  extern __shared__ double sr[];
+  const PieceDev pc = pieces[blockIdx.x];
+  const int n = pc.n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sr[i] = r[idx[pc.idx_off + i]];
+  __syncthreads();
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
+  const double *M = inv + pc.inv_off;
+  for (int i = wave; i < n; i += nw) {
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += M[(long long)i * n + j] * sr[j];
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) {
+      int b = cp[pc.cp_off + i], e = cp[pc.cp_off + i + 1];
+      for (int c = b; c < e; ++c) u[cidx[c]] += scale * s;
+    }
+  }
+}
+
+// coarse solve: gather (sum of copies), dense inverse, scatter to all copies
+__global__ __launch_bounds__(256) void coarse_kernel(int n, const double *inv, const int *cp,
+                                                     const int *cidx, const double *f, double *u) {
+  extern __shared__ double sr[];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int c = cp[i]; c < cp[i + 1]; ++c) s += f[cidx[c]];
+    sr[i] = s;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
+  for (int i = blockIdx.x * nw + wave; i < n; i += gridDim.x * nw) {
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += inv[(long long)i * n + j] * sr[j];
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0)
+      for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transfers (2D): restriction r_c = P^T (w r_f), prolongation u_f += P e_c
+// ---------------------------------------------------------------------------
+__global__ void restrict2d_kernel(const PatchDev *pf, const PatchDev *pc, int K, const int *Rlo,
+                                  const double *Rval, int RW, const double *rf, const double *wf,
+                                  const unsigned char *maskc, long long nc_tot, double *rc) {
+  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nc_tot) return;
+  int k = 0;
+  while (k + 1 < K && pc[k + 1].off <= t) ++k;
+  const PatchDev &C = pc[k], &F = pf[k];
+  long long loc = t - C.off;
+  int jx = (int)(loc % C.n[0]), jy = (int)(loc / C.n[0]);
+  if (!maskc[t]) {
+    rc[t] = 0.0;
+    return;
+  }
+  const int rx = F.xr[0] + jx, ry = F.xr[1] + jy;
+  const int lx = Rlo[rx], ly = Rlo[ry];
+  double s = 0.0;
+  for (int a = 0; a < RW; ++a) {
+    int iy = ly + a;
+    double vy = Rval[(long long)ry * RW + a];
+    if (vy == 0.0 || iy >= F.n[1]) continue;
+    double sx = 0.0;
+    for (int b = 0; b < RW; ++b) {
+      int ix = lx + b;
+      double vx = Rval[(long long)rx * RW + b];
+      if (vx == 0.0 || ix >= F.n[0]) continue;
+      long long tf = F.off + (long long)iy * F.n[0] + ix;
+      sx += vx * wf[tf] * rf[tf];
+    }
+    s += vy * sx;
+  }
+  rc[t] = s;
+}
+
+__global__ void prolong2d_kernel(const PatchDev *pf, const PatchDev *pc, int K, const int *Plo,
+                                 const double *Pval, int PW, const double *ec,
+                                 const unsigned char *maskf, long long nf_tot, double *uf) {
+  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nf_tot) return;
+  int k = 0;
+  while (k + 1 < K && pf[k + 1].off <= t) ++k;
+  const PatchDev &F = pf[k], &C = pc[k];
+  if (!maskf[t]) return;
+  long long loc = t - F.off;
+  int ix = (int)(loc % F.n[0]), iy = (int)(loc / F.n[0]);
+  const int px = F.xp[0] + ix, py = F.xp[1] + iy;
+  const int lx = Plo[px], ly = Plo[py];
+  double s = 0.0;
+  for (int a = 0; a < PW; ++a) {
+    int jy = ly + a;
+    double vy = Pval[(long long)py * PW + a];
+    if (vy == 0.0 || jy >= C.n[1]) continue;
+    double sx = 0.0;
+    for (int b = 0; b < PW; ++b) {
+      int jx = lx + b;
+      double vx = Pval[(long long)px * PW + b];
+      if (vx == 0.0 || jx >= C.n[0]) continue;
+      sx += vx * ec[C.off + (long long)jy * C.n[0] + jx];
+    }
+    s += vy * sx;
+  }
+  uf[t] += s;
+}
+
+// ---------------------------------------------------------------------------
+// compact <-> torn
+// ---------------------------------------------------------------------------
+__global__ void scatter_compact_kernel(const double *xc, long long N, const int *cp, const int *cidx,
+                                       double *xt) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double v = xc[i];
+  for (int c = cp[i]; c < cp[i + 1]; ++c) xt[cidx[c]] = v;
+}
+
+__global__ void gather_compact_kernel(const double *xt, long long N, const int *cp, const int *cidx,
+                                      int sum, double *xc) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  if (!sum) {
+    xc[i] = xt[cidx[cp[i]]];
+    return;
+  }
+  double s = 0.0;
+  for (int c = cp[i]; c < cp[i + 1]; ++c) s += xt[cidx[c]];
+  xc[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions: fixed grid, fixed-order trees
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;
+
+__device__ inline double block_sum(double v, double *sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const double *b,
+                                                          const double *w, long long n,
+                                                          double *part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    s += (w ? w[i] : 1.0) * a[i] * b[i];
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// mode 0: scal[slot] = sum; 1: alpha = rz / sum; 2: beta = sum / rz, rz = sum
+__global__ __launch_bounds__(256) void dot_final_kernel(const double *part, int nb, double *scal,
+                                                        int slot, int mode) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    scal[slot] = t;
+    if (mode == 1) scal[S_ALPHA] = scal[S_RZ] / t;
+    if (mode == 2) {
+      scal[S_BETA] = t / scal[S_RZ];
+      scal[S_RZ] = t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void pcg_xr_kernel(double *x, double *r, const double *p,
+                                                     const double *q, const double *w, long long n,
+                                                     const double *scal, double *part) {
+  __shared__ double sh[256];
+  const double alpha = scal[S_ALPHA];
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += w[i] * ri * ri;
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void pcg_p_kernel(double *p, const double *z, long long n, const double *scal) {
+  const double beta = scal[S_BETA];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+}  // namespace
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+void k_fill(double *x, double v, long long n, hipStream_t s) {
+  fill_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, s>>>(x, v, n);
+}
+void k_copy_weighted(const double *x, const double *w, double *y, long long n, hipStream_t s) {
+  copy_weighted_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, s>>>(x, w, y, n);
+}
+void k_axpy(double a, const double *x, double *y, long long n, hipStream_t s) {
+  axpy_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, s>>>(a, x, y, n);
+}
+
+void k_stencil_assemble(Context &c, LevelData &L) {
+  int S = 1;
+  for (int d = 0; d < c.d; ++d) S *= (2 * c.p + 1);
+  long long tot = L.Ntorn * S;
+  if (c.d == 2)
+    stencil_kernel<2><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
+                                                         L.Ntorn, L.d_stencil);
+  else
+    stencil_kernel<3><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
+                                                         L.Ntorn, L.d_stencil);
+  HIPCHK(hipGetLastError());
+}
+
+void k_stencil_add(const int *rows, const int *slots, const double *vals, int n, double *stencil,
+                   int S, hipStream_t s) {
+  if (n == 0) return;
+  stencil_add_kernel<<<nblocks(n), BS, 0, s>>>(rows, slots, vals, n, stencil, S);
+}
+
+void k_invdiag(const double *stencil, int S, int center, const unsigned char *mask, double *invd,
+               long long n, hipStream_t s) {
+  invdiag_kernel<<<nblocks(n), BS, 0, s>>>(stencil, S, center, mask, invd, n);
+}
+
+void k_load_manufactured(Context &c, LevelData &L, double *out) {
+  if (c.d == 2)
+    load_kernel<2><<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, c.gr, c.p,
+                                                          L.d_mask, L.Ntorn, out);
+  else
+    load_kernel<3><<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, c.gr, c.p,
+                                                          L.d_mask, L.Ntorn, out);
+}
+
+void k_iface_apply(Context &c, LevelData &L, const double *u, const double *f, const double *fw,
+                   double beta, double alpha, double *r) {
+  TimeScope ts(c, "iface_apply");
+  iface_kernel<<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.Ntorn, L.d_mask, L.d_if_ptr, L.d_if_col,
+                                                      L.d_if_val, u, f, fw, beta, alpha, r);
+}
+
+template <int P, int TE>
+static void launch_vol2d(Context &c, LevelData &L, const double *u, double *r, double alpha) {
+  vol2d_kernel<P, TE><<<L.n_vtiles, 256, 0, c.stream>>>(L.d_vtiles, L.d_pd, L.d_tabB, L.d_tabD,
+                                                        c.gr, u, r, L.d_mask, alpha);
+}
+
+int vol_tile_2d(int p) { return p <= 4 ? 8 : (p <= 6 ? 6 : 4); }
+
+void k_vol_apply(Context &c, LevelData &L, const double *u, double *r, double alpha) {
+  TimeScope ts(c, "vol_apply");
+  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D volume operator not built");
+  switch (c.p) {
+    case 1: launch_vol2d<1, 8>(c, L, u, r, alpha); break;
+    case 2: launch_vol2d<2, 8>(c, L, u, r, alpha); break;
+    case 3: launch_vol2d<3, 8>(c, L, u, r, alpha); break;
+    case 4: launch_vol2d<4, 8>(c, L, u, r, alpha); break;
+    case 5: launch_vol2d<5, 6>(c, L, u, r, alpha); break;
+    case 6: launch_vol2d<6, 6>(c, L, u, r, alpha); break;
+    case 7: launch_vol2d<7, 4>(c, L, u, r, alpha); break;
+    case 8: launch_vol2d<8, 4>(c, L, u, r, alpha); break;
+    default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+  }
+}
+
+void k_glue_sum(LevelData &L, double *y, hipStream_t s) {
+  if (L.n_glue == 0) return;
+  glue_kernel<<<nblocks(L.n_glue), BS, 0, s>>>(L.n_glue, L.d_glue_ptr, L.d_glue_idx, y);
+}
+
+template <int P>
+static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward) {
+  int T = c.opt.gs_tile;
+  int W = T + 2 * P;
+  int rows = ((T + P) / (P + 1)) * ((T + P) / (P + 1));
+  int G = 64;
+  while (G > 1 && rows * G > 256) G >>= 1;
+  if (G > 64) G = 64;
+  gs2d_kernel<P><<<cl.count, 256, (size_t)W * W * sizeof(double), c.stream>>>(
+      cl.tiles, L.d_pd, L.d_stencil, L.d_invdiag, L.d_cx_ptr, L.d_cx_col, L.d_cx_val, L.f, L.u,
+      L.d_mask, T, backward ? 1 : 0, G);
+}
+
+void k_gs_sweep(Context &c, LevelData &L, bool backward) {
+  TimeScope ts(c, "gauss_seidel");
+  int nc = (int)L.gs.size();
+  for (int ii = 0; ii < nc; ++ii) {
+    const GsClass &cl = L.gs[backward ? nc - 1 - ii : ii];
+    if (cl.count == 0) continue;
+    switch (c.p) {
+      case 1: launch_gs2d<1>(c, L, cl, backward); break;
+      case 2: launch_gs2d<2>(c, L, cl, backward); break;
+      case 3: launch_gs2d<3>(c, L, cl, backward); break;
+      case 4: launch_gs2d<4>(c, L, cl, backward); break;
+      case 5: launch_gs2d<5>(c, L, cl, backward); break;
+      case 6: launch_gs2d<6>(c, L, cl, backward); break;
+      case 7: launch_gs2d<7>(c, L, cl, backward); break;
+      case 8: launch_gs2d<8>(c, L, cl, backward); break;
+      default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+    }
+  }
+}
+
+void k_scms_interior(Context &c, LevelData &L) {
+  TimeScope ts(c, "scms_gemm");
+  if (L.n_gemm == 0) return;
+  dim3 grid((L.gemm_maxN + 63) / 64, (L.gemm_maxM + 63) / 64, L.n_gemm);
+  for (int st = 0; st < 4; ++st) gemm_kernel<<<grid, 256, 0, c.stream>>>(L.d_gemm[st]);
+}
+
+void k_pieces(Context &c, LevelData &L, const double *r, double *u) {
+  TimeScope ts(c, "pieces");
+  if (L.n_pieces == 0) return;
+  piece_kernel<<<L.n_pieces, 256, (size_t)L.max_piece * sizeof(double), c.stream>>>(
+      L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, L.d_piece_inv, r, u,
+      c.opt.damping_tau);
+}
+
+void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc) {
+  TimeScope ts(c, "restrict");
+  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
+  restrict2d_kernel<<<nblocks(C.Ntorn), BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_R_lo, F.d_R_val,
+                                                           F.RW, rf, F.d_weight, C.d_mask, C.Ntorn,
+                                                           rc);
+}
+
+void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, double *uf) {
+  TimeScope ts(c, "prolong");
+  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
+  prolong2d_kernel<<<nblocks(F.Ntorn), BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_P_lo, F.d_P_val,
+                                                          F.PW, ec, F.d_mask, F.Ntorn, uf);
+}
+
+void k_coarse_solve(Context &c, const double *f0, double *u0) {
+  TimeScope ts(c, "coarse");
+  int nb = std::max(1, std::min(64, (c.N0 + 15) / 16));
+  coarse_kernel<<<nb, 256, (size_t)c.N0 * sizeof(double), c.stream>>>(c.N0, c.d_A0inv, c.d_c0_cp,
+                                                                      c.d_c0_cidx, f0, u0);
+}
+
+void k_scatter_compact(const double *xc, long long N, const int *cp, const int *cidx, double *xt,
+                       hipStream_t s) {
+  scatter_compact_kernel<<<nblocks(N), BS, 0, s>>>(xc, N, cp, cidx, xt);
+}
+
+void k_gather_compact(const double *xt, long long N, const int *cp, const int *cidx, int sum,
+                      double *xc, hipStream_t s) {
+  gather_compact_kernel<<<nblocks(N), BS, 0, s>>>(xt, N, cp, cidx, sum, xc);
+}
+
+void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode) {
+  TimeScope ts(c, "blas1");
+  dot_partial_kernel<<<RED_BLOCKS, 256, 0, c.stream>>>(a, b, c.lv.back().d_weight, n, c.d_red);
+  dot_final_kernel<<<1, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, slot, mode);
+}
+
+void k_pcg_update_xr(Context &c, long long n) {
+  TimeScope ts(c, "blas1");
+  pcg_xr_kernel<<<RED_BLOCKS, 256, 0, c.stream>>>(c.x, c.rr, c.pp, c.qq, c.lv.back().d_weight, n,
+                                                  c.d_scal, c.d_red);
+  dot_final_kernel<<<1, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
+}
+
+void k_pcg_update_p(Context &c, long long n) {
+  TimeScope ts(c, "blas1");
+  pcg_p_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, c.stream>>>(c.pp, c.z, n, c.d_scal);
+}
+
+}  // namespace igamg

@@ -1,0 +1,1030 @@
+// Setup of the multigrid hierarchy: topology of the patch layout, grid
+// levels, unknown numbering, interface terms of the SIPG form, smoother data
+// and the coarse factorization.  Host work is plain C++; the volume stencils
+// of the Gauss-Seidel smoother are assembled on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <unordered_map>
+
+#include "context.h"
+#include "geom.h"
+#include "hostmath.h"
+#include "kernels.h"
+
+namespace igamg {
+
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+int vol_tile_2d(int p);
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+void Context::launch_begin(const char *fam, hipEvent_t *b, hipEvent_t *e) {
+  TimerFamily &t = timers[fam];
+  if (t.pool.empty()) {
+    hipEvent_t x, y;
+    HIPCHK(hipEventCreate(&x));
+    HIPCHK(hipEventCreate(&y));
+    t.pool.push_back({x, y});
+  }
+  *b = t.pool.back().first;
+  *e = t.pool.back().second;
+  t.pool.pop_back();
+  HIPCHK(hipEventRecord(*b, stream));
+}
+
+void Context::launch_end(const char *fam, hipEvent_t b, hipEvent_t e) {
+  TimerFamily &t = timers[fam];
+  HIPCHK(hipEventRecord(e, stream));
+  t.pending.push_back({b, e});
+  t.launches += 1;
+  if (t.pending.size() > 256) {  // bound the number of outstanding events
+    HIPCHK(hipEventSynchronize(e));
+    for (auto &pe : t.pending) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, pe.first, pe.second));
+      t.ms += ms;
+      t.pool.push_back(pe);
+    }
+    t.pending.clear();
+  }
+}
+
+Context::~Context() {
+  for (auto &kv : timers) {
+    for (auto &pe : kv.second.pending) {
+      (void)hipEventDestroy(pe.first);
+      (void)hipEventDestroy(pe.second);
+    }
+    for (auto &pe : kv.second.pool) {
+      (void)hipEventDestroy(pe.first);
+      (void)hipEventDestroy(pe.second);
+    }
+  }
+  if (h_scal) (void)hipHostFree(h_scal);
+  arena.release();
+}
+
+// ---------------------------------------------------------------------------
+// topology (Section 2, eq. omega:1 and Assumption 1)
+// ---------------------------------------------------------------------------
+static std::vector<int> side_corners(int d, int dir, int s) {
+  std::vector<int> out;
+  std::vector<int> tang;
+  for (int g = 0; g < d; ++g)
+    if (g != dir) tang.push_back(g);
+  for (int tb = 0; tb < (1 << (d - 1)); ++tb) {
+    int b = s << dir;
+    for (size_t j = 0; j < tang.size(); ++j) b |= ((tb >> j) & 1) << tang[j];
+    out.push_back(b);
+  }
+  return out;
+}
+
+static void build_topology(Context &c) {
+  const int d = c.d, K = c.K, nc = 1 << d;
+  std::map<std::array<long long, 3>, int> keys;
+  c.vid.assign(K, std::vector<int>(nc));
+  for (int k = 0; k < K; ++k)
+    for (int b = 0; b < nc; ++b) {
+      std::array<long long, 3> key{0, 0, 0};
+      for (int a = 0; a < d; ++a) key[a] = std::llround(c.corners[k][b * 3 + a] * 1e9);
+      auto it = keys.find(key);
+      if (it == keys.end()) it = keys.emplace(key, (int)keys.size()).first;
+      c.vid[k][b] = it->second;
+    }
+  c.boundary.assign(K, std::array<unsigned char, 6>{1, 1, 1, 1, 1, 1});
+  for (int k = 0; k < K; ++k)
+    for (int dir = d; dir < 3; ++dir) c.boundary[k][2 * dir] = c.boundary[k][2 * dir + 1] = 0;
+  for (int k = 0; k < K; ++k)
+    for (int l = k + 1; l < K; ++l)
+      for (int dk = 0; dk < d; ++dk)
+        for (int sk = 0; sk < 2; ++sk) {
+          std::vector<int> ck = side_corners(d, dk, sk);
+          std::vector<int> vk;
+          for (int b : ck) vk.push_back(c.vid[k][b]);
+          for (int dl = 0; dl < d; ++dl)
+            for (int sl = 0; sl < 2; ++sl) {
+              std::vector<int> cl = side_corners(d, dl, sl);
+              std::vector<int> vl;
+              for (int b : cl) vl.push_back(c.vid[l][b]);
+              std::vector<int> a = vk, bb = vl;
+              std::sort(a.begin(), a.end());
+              std::sort(bb.begin(), bb.end());
+              if (a != bb) continue;
+              if (vk != vl) fail(IGAMG_EUNSUPPORTED, "interface with flipped orientation");
+              c.ifaces.push_back({k, dk, sk, l, dl, sl, 0.0});
+              c.boundary[k][2 * dk + sk] = 0;
+              c.boundary[l][2 * dl + sl] = 0;
+            }
+        }
+  std::vector<std::vector<int>> nbr(K);
+  for (auto &f : c.ifaces) {
+    nbr[f.k].push_back(f.l);
+    nbr[f.l].push_back(f.k);
+  }
+  c.color.assign(K, 0);
+  c.n_colors = 1;
+  for (int k = 0; k < K; ++k) {
+    std::vector<char> taken(K + 1, 0);
+    for (int j : nbr[k])
+      if (j < k) taken[c.color[j]] = 1;
+    int col = 0;
+    while (taken[col]) ++col;
+    c.color[k] = col;
+    c.n_colors = std::max(c.n_colors, col + 1);
+  }
+  // patch measures (Gauss, exact for multilinear maps) and orientation check
+  GaussRule g4 = gauss_rule(4);
+  c.measure.assign(K, 0.0);
+  for (int k = 0; k < K; ++k) {
+    double cs[8][3] = {};
+    for (int b = 0; b < nc; ++b)
+      for (int a = 0; a < d; ++a) cs[b][a] = c.corners[k][b * 3 + a];
+    int gi[3] = {0, 0, 0};
+    double m = 0.0;
+    for (;;) {
+      double xh[3], w = 1.0;
+      for (int a = 0; a < d; ++a) {
+        xh[a] = g4.x[gi[a]];
+        w *= g4.w[gi[a]];
+      }
+      double det;
+      if (d == 2) {
+        double J[2][2];
+        multilinear_jac<2>(cs, xh, J);
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      } else {
+        double J[3][3], Ji[3][3];
+        multilinear_jac<3>(cs, xh, J);
+        det = inverse<3>(J, Ji);
+      }
+      if (!(det > 0)) fail(IGAMG_EINVAL, "patch map with non-positive Jacobian determinant");
+      m += w * det;
+      int a = 0;
+      while (a < d && ++gi[a] == 4) gi[a++] = 0;
+      if (a == d) break;
+    }
+    c.measure[k] = m;
+  }
+  // penalty sigma p^2 / h with the finest physical element size (eq. a:galerkin)
+  for (auto &f : c.ifaces) {
+    auto h = [&](int k) {
+      int ne = 0;
+      for (int a = 0; a < d; ++a) ne = std::max(ne, c.elems_fine[k][a]);
+      return std::pow(c.measure[k], 1.0 / d) / ne;
+    };
+    f.eta = c.sigma_pen * c.p * c.p / std::min(h(f.k), h(f.l));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// levels
+// ---------------------------------------------------------------------------
+static std::vector<std::vector<std::array<int, 3>>> level_elements(const Context &c) {
+  std::vector<std::vector<std::array<int, 3>>> out;
+  std::vector<std::array<int, 3>> e = c.elems_fine;
+  out.push_back(e);
+  int cmin = c.opt.coarse_min > 0 ? c.opt.coarse_min : 2;
+  for (;;) {
+    bool ok = true;
+    for (auto &a : e)
+      for (int g = 0; g < c.d; ++g)
+        if (a[g] % 2 != 0 || a[g] / 2 < cmin) ok = false;
+    if (!ok) break;
+    for (auto &a : e)
+      for (int g = 0; g < c.d; ++g) a[g] /= 2;
+    out.push_back(e);
+  }
+  std::reverse(out.begin(), out.end());
+  return out;
+}
+
+static long long torn_index(const PatchDev &pt, const int *i) {
+  return pt.off + (long long)i[0] + (long long)i[1] * pt.stride[1] + (long long)i[2] * pt.stride[2];
+}
+
+static void build_level_dofs(Context &c, LevelData &L, const std::vector<std::array<int, 3>> &el) {
+  const int d = c.d, K = c.K, p = c.p;
+  L.K = K;
+  L.pd.assign(K, PatchDev{});
+  std::map<int, int> tab_of_nel;
+  long long off = 0;
+  for (int k = 0; k < K; ++k) {
+    PatchDev &pt = L.pd[k];
+    for (int b = 0; b < (1 << d); ++b)
+      for (int a = 0; a < d; ++a) pt.corners[b][a] = c.corners[k][b * 3 + a];
+    for (int g = 0; g < 3; ++g) {
+      pt.nel[g] = g < d ? el[k][g] : 1;
+      pt.n[g] = g < d ? el[k][g] + p : 1;
+    }
+    pt.stride[0] = 1;
+    pt.stride[1] = pt.n[0];
+    pt.stride[2] = pt.n[0] * pt.n[1];
+    pt.off = off;
+    off += (long long)pt.n[0] * pt.n[1] * pt.n[2];
+    pt.color = c.color[k];
+    for (int g = 0; g < d; ++g) {
+      int ne = pt.nel[g];
+      auto it = tab_of_nel.find(ne);
+      if (it == tab_of_nel.end()) {
+        std::vector<double> B, D;
+        element_tables(ne, p, c.gr, B, D);
+        int o = (int)L.tabB.size();
+        L.tabB.insert(L.tabB.end(), B.begin(), B.end());
+        L.tabD.insert(L.tabD.end(), D.begin(), D.end());
+        it = tab_of_nel.emplace(ne, o).first;
+      }
+      pt.tab[g] = it->second;
+    }
+  }
+  L.Ntorn = off;
+  // Dirichlet: non-vanishing trace on a boundary side
+  L.mask.assign(L.Ntorn, 1);
+  for (int k = 0; k < K; ++k) {
+    const PatchDev &pt = L.pd[k];
+    for (long long loc = 0; loc < (long long)pt.n[0] * pt.n[1] * pt.n[2]; ++loc) {
+      int i[3] = {(int)(loc % pt.n[0]), (int)((loc / pt.n[0]) % pt.n[1]),
+                  (int)(loc / ((long long)pt.n[0] * pt.n[1]))};
+      for (int g = 0; g < d; ++g)
+        for (int s = 0; s < 2; ++s)
+          if (c.boundary[k][2 * g + s] && i[g] == (s ? pt.n[g] - 1 : 0)) L.mask[pt.off + loc] = 0;
+    }
+  }
+  // conforming: glue patch-boundary unknowns by their Greville points
+  std::vector<int> group(L.Ntorn, -1);
+  int ngroups = 0;
+  if (c.opt.discretization == IGAMG_CONFORMING) {
+    std::map<std::array<long long, 3>, int> gkey;
+    for (int k = 0; k < K; ++k) {
+      const PatchDev &pt = L.pd[k];
+      std::vector<std::vector<double>> grev(d);
+      for (int g = 0; g < d; ++g) {
+        std::vector<double> t = open_knots(pt.nel[g], p);
+        for (int i = 0; i < pt.n[g]; ++i) {
+          double s = 0;
+          for (int j = 1; j <= p; ++j) s += t[i + j];
+          grev[g].push_back(s / p);
+        }
+      }
+      for (long long loc = 0; loc < (long long)pt.n[0] * pt.n[1] * pt.n[2]; ++loc) {
+        int i[3] = {(int)(loc % pt.n[0]), (int)((loc / pt.n[0]) % pt.n[1]),
+                    (int)(loc / ((long long)pt.n[0] * pt.n[1]))};
+        bool bd = false;
+        for (int g = 0; g < d; ++g) bd |= (i[g] == 0 || i[g] == pt.n[g] - 1);
+        if (!bd) continue;
+        double xh[3] = {0, 0, 0}, X[3] = {0, 0, 0};
+        for (int g = 0; g < d; ++g) xh[g] = grev[g][i[g]];
+        if (d == 2)
+          multilinear_map<2>(pt.corners, xh, X);
+        else
+          multilinear_map<3>(pt.corners, xh, X);
+        std::array<long long, 3> key{0, 0, 0};
+        for (int a = 0; a < d; ++a) key[a] = std::llround(X[a] * 1e9);
+        auto it = gkey.find(key);
+        if (it == gkey.end()) it = gkey.emplace(key, ngroups++).first;
+        group[pt.off + loc] = it->second;
+      }
+    }
+    std::vector<unsigned char> gd(ngroups, 1);
+    for (long long t = 0; t < L.Ntorn; ++t)
+      if (group[t] >= 0 && !L.mask[t]) gd[group[t]] = 0;
+    for (long long t = 0; t < L.Ntorn; ++t)
+      if (group[t] >= 0) L.mask[t] = gd[group[t]];
+    // Assumption 2: both sides of an interface carry the same glued unknowns
+    for (auto &f : c.ifaces) {
+      auto side_groups = [&](int k, int dir, int s) {
+        std::vector<int> gs;
+        const PatchDev &pt = L.pd[k];
+        for (long long loc = 0; loc < (long long)pt.n[0] * pt.n[1] * pt.n[2]; ++loc) {
+          int i[3] = {(int)(loc % pt.n[0]), (int)((loc / pt.n[0]) % pt.n[1]),
+                      (int)(loc / ((long long)pt.n[0] * pt.n[1]))};
+          if (i[dir] == (s ? pt.n[dir] - 1 : 0)) gs.push_back(group[pt.off + loc]);
+        }
+        std::sort(gs.begin(), gs.end());
+        return gs;
+      };
+      if (side_groups(f.k, f.dk, f.sk) != side_groups(f.l, f.dl, f.sl))
+        fail(IGAMG_EINVAL, "conforming discretization needs fully matching interfaces");
+    }
+  }
+  // compact numbering
+  L.comp.assign(L.Ntorn, -1);
+  L.rep.clear();
+  L.copies.clear();
+  std::vector<int> gcomp(ngroups, -1);
+  for (long long t = 0; t < L.Ntorn; ++t) {
+    if (!L.mask[t]) continue;
+    int g = group[t];
+    if (g >= 0 && gcomp[g] >= 0) {
+      L.comp[t] = gcomp[g];
+      L.copies[gcomp[g]].push_back((int)t);
+      continue;
+    }
+    int ci = (int)L.rep.size();
+    L.comp[t] = ci;
+    L.rep.push_back((int)t);
+    L.copies.push_back({(int)t});
+    if (g >= 0) gcomp[g] = ci;
+  }
+  L.N = (long long)L.rep.size();
+}
+
+// ---------------------------------------------------------------------------
+// SIPG interface terms (Section 3, eq. model:discr2) by Gauss quadrature on
+// the union of both sides' breakpoints
+// ---------------------------------------------------------------------------
+struct SideEval {
+  double v[MAXP + 1][MAXP + 1][2];          // unused placeholder (kept small)
+};
+
+static void build_interfaces(Context &c, LevelData &L) {
+  const int d = c.d, p = c.p, q = p + 1;
+  GaussRule gq = gauss_rule(q);
+  std::unordered_map<unsigned long long, double> acc;
+  acc.reserve(1 << 16);
+  for (auto &f : c.ifaces) {
+    const PatchDev &pk = L.pd[f.k], &pl = L.pd[f.l];
+    int tk[2], tl[2], nt = 0;
+    for (int g = 0; g < d; ++g)
+      if (g != f.dk) tk[nt++] = g;
+    nt = 0;
+    for (int g = 0; g < d; ++g)
+      if (g != f.dl) tl[nt++] = g;
+    // merged breakpoints per tangential direction: m / lcm
+    std::vector<std::vector<double>> pts(d - 1), wts(d - 1);
+    for (int j = 0; j < d - 1; ++j) {
+      long long na = pk.nel[tk[j]], nb = pl.nel[tl[j]];
+      long long Lc = std::lcm(na, nb);
+      std::vector<long long> ms;
+      for (long long i = 0; i <= na; ++i) ms.push_back(i * (Lc / na));
+      for (long long i = 0; i <= nb; ++i) ms.push_back(i * (Lc / nb));
+      std::sort(ms.begin(), ms.end());
+      ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
+      for (size_t s = 0; s + 1 < ms.size(); ++s) {
+        double a = (double)ms[s] / (double)Lc, b = (double)ms[s + 1] / (double)Lc;
+        for (int g = 0; g < q; ++g) {
+          pts[j].push_back(a + (b - a) * gq.x[g]);
+          wts[j].push_back((b - a) * gq.w[g]);
+        }
+      }
+    }
+    std::vector<double> kn[2][3];
+    for (int g = 0; g < d; ++g) {
+      kn[0][g] = open_knots(pk.nel[g], p);
+      kn[1][g] = open_knots(pl.nel[g], p);
+    }
+    size_t n0 = pts[0].size(), n1 = d == 3 ? pts[1].size() : 1;
+    const int nside = 2;  // normal layers carrying value or derivative
+    int ntan = 1;
+    for (int j = 0; j < d - 1; ++j) ntan *= (p + 1);
+    const int nact = nside * ntan;
+    std::vector<long long> idx(2 * nact);
+    std::vector<double> val(2 * nact), dn(2 * nact);
+    for (size_t i1 = 0; i1 < n1; ++i1)
+      for (size_t i0 = 0; i0 < n0; ++i0) {
+        double tpar[2] = {pts[0][i0], d == 3 ? pts[1][i1] : 0.0};
+        double wt = wts[0][i0] * (d == 3 ? wts[1][i1] : 1.0);
+        // physical normal and surface element from side k
+        double J[3][3] = {}, Ji[3][3] = {}, nrm[3] = {0, 0, 0}, ds = 0.0;
+        double xk[3] = {0, 0, 0}, xl[3] = {0, 0, 0};
+        xk[f.dk] = f.sk;
+        xl[f.dl] = f.sl;
+        for (int j = 0; j < d - 1; ++j) {
+          xk[tk[j]] = tpar[j];
+          xl[tl[j]] = tpar[j];
+        }
+        double Jl[3][3] = {}, Jli[3][3] = {};
+        if (d == 2) {
+          double J2[2][2], Ji2[2][2], Jl2[2][2], Jli2[2][2];
+          multilinear_jac<2>(pk.corners, xk, J2);
+          inverse<2>(J2, Ji2);
+          multilinear_jac<2>(pl.corners, xl, Jl2);
+          inverse<2>(Jl2, Jli2);
+          for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+              J[a][b] = J2[a][b];
+              Ji[a][b] = Ji2[a][b];
+              Jl[a][b] = Jl2[a][b];
+              Jli[a][b] = Jli2[a][b];
+            }
+          ds = std::hypot(J[0][tk[0]], J[1][tk[0]]);
+        } else {
+          double J3[3][3], Ji3[3][3], Jl3[3][3], Jli3[3][3];
+          multilinear_jac<3>(pk.corners, xk, J3);
+          inverse<3>(J3, Ji3);
+          multilinear_jac<3>(pl.corners, xl, Jl3);
+          inverse<3>(Jl3, Jli3);
+          std::memcpy(J, J3, sizeof(J3));
+          std::memcpy(Ji, Ji3, sizeof(Ji3));
+          std::memcpy(Jl, Jl3, sizeof(Jl3));
+          std::memcpy(Jli, Jli3, sizeof(Jli3));
+          double a[3], b[3];
+          for (int r = 0; r < 3; ++r) {
+            a[r] = J[r][tk[0]];
+            b[r] = J[r][tk[1]];
+          }
+          double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2],
+                 cz = a[0] * b[1] - a[1] * b[0];
+          ds = std::sqrt(cx * cx + cy * cy + cz * cz);
+        }
+        // outer normal of Omega_k: J^-T e_dk (sign of the side), normalized
+        double sgn = f.sk ? 1.0 : -1.0, nn = 0.0;
+        for (int a = 0; a < d; ++a) {
+          nrm[a] = sgn * Ji[f.dk][a];
+          nn += nrm[a] * nrm[a];
+        }
+        nn = std::sqrt(nn);
+        for (int a = 0; a < d; ++a) nrm[a] /= nn;
+        double w = wt * ds;
+        // evaluate both sides
+        for (int side = 0; side < 2; ++side) {
+          const PatchDev &pt = side ? pl : pk;
+          const int dir = side ? f.dl : f.dk, s = side ? f.sl : f.sk;
+          const int *tg = side ? tl : tk;
+          const double(*Jinv)[3] = side ? Jli : Ji;
+          double cvec[3] = {0, 0, 0};  // J^-1 n
+          for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) cvec[a] += Jinv[a][b] * nrm[b];
+          double bv[3][MAXP + 1], bd[3][MAXP + 1];
+          int first[3];
+          for (int g = 0; g < d; ++g) {
+            double x;
+            int e;
+            if (g == dir) {
+              x = (double)s;
+              e = s ? pt.nel[g] - 1 : 0;
+            } else {
+              int j = (g == tg[0]) ? 0 : 1;
+              x = tpar[j];
+              e = std::min(pt.nel[g] - 1, (int)std::floor(x * pt.nel[g]));
+            }
+            double out[2][MAXP + 1];
+            bspline_span_ders(kn[side][g], p, p + e, x, 1, out);
+            for (int a = 0; a <= p; ++a) {
+              bv[g][a] = out[0][a];
+              bd[g][a] = out[1][a];
+            }
+            first[g] = e;
+          }
+          // active functions: two normal layers next to the side x tangential (p+1)^(d-1)
+          for (int a = 0; a < nact; ++a) {
+            int lay = a % nside, rest = a / nside;
+            int li[3];
+            li[dir] = s ? p - lay : lay;  // local index inside the element
+            for (int j = 0; j < d - 1; ++j) {
+              li[tg[j]] = rest % (p + 1);
+              rest /= (p + 1);
+            }
+            double value = 1.0, grad[3];
+            for (int g = 0; g < d; ++g) value *= bv[g][li[g]];
+            for (int g = 0; g < d; ++g) {
+              grad[g] = bd[g][li[g]];
+              for (int h = 0; h < d; ++h)
+                if (h != g) grad[g] *= bv[h][li[h]];
+            }
+            double dnv = 0.0;
+            for (int g = 0; g < d; ++g) dnv += grad[g] * cvec[g];
+            int gi[3] = {0, 0, 0};
+            for (int g = 0; g < d; ++g) gi[g] = first[g] + li[g];
+            idx[side * nact + a] = torn_index(pt, gi);
+            val[side * nact + a] = side ? -value : value;  // jump [u] = u_k - u_l
+            dn[side * nact + a] = dnv;
+          }
+        }
+        const double eta = f.eta;
+        for (int A = 0; A < 2 * nact; ++A) {
+          if (val[A] == 0.0 && dn[A] == 0.0) continue;
+          for (int B = 0; B < 2 * nact; ++B) {
+            double v = eta * val[A] * val[B] - 0.5 * dn[A] * val[B] - 0.5 * val[A] * dn[B];
+            if (v == 0.0) continue;
+            unsigned long long key = ((unsigned long long)idx[A] << 32) | (unsigned long long)idx[B];
+            acc[key] += w * v;
+          }
+        }
+      }
+  }
+  // CSR over torn rows (Dirichlet rows / columns dropped)
+  std::vector<std::pair<unsigned long long, double>> ent(acc.begin(), acc.end());
+  std::sort(ent.begin(), ent.end());
+  L.if_ptr.assign(L.Ntorn + 1, 0);
+  L.if_col.clear();
+  L.if_val.clear();
+  L.if_cross.clear();
+  auto patch_of = [&](long long t) {
+    int k = 0;
+    while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
+    return k;
+  };
+  for (auto &e : ent) {
+    long long r = (long long)(e.first >> 32), cc = (long long)(e.first & 0xffffffffULL);
+    if (!L.mask[r] || !L.mask[cc]) continue;
+    L.if_ptr[r + 1]++;
+    L.if_col.push_back((int)cc);
+    L.if_val.push_back(e.second);
+    L.if_cross.push_back(patch_of(r) != patch_of(cc));
+  }
+  for (long long t = 0; t < L.Ntorn; ++t) L.if_ptr[t + 1] += L.if_ptr[t];
+}
+
+// A(t1, t2) of the torn operator: volume entry (same patch) + interface entry
+static double torn_entry_iface(const LevelData &L, long long t1, long long t2) {
+  int b = L.if_ptr.empty() ? 0 : L.if_ptr[t1], e = L.if_ptr.empty() ? 0 : L.if_ptr[t1 + 1];
+  auto it = std::lower_bound(L.if_col.begin() + b, L.if_col.begin() + e, (int)t2);
+  if (it != L.if_col.begin() + e && *it == (int)t2) return L.if_val[it - L.if_col.begin()];
+  return 0.0;
+}
+
+// Dense P^T A P over a set of compact unknowns (conforming: summed over copies).
+static std::vector<double> dense_block(const Context &c, const LevelData &L,
+                                       const std::vector<int> &comps) {
+  const int d = c.d, p = c.p;
+  const int n = (int)comps.size();
+  std::unordered_map<long long, int> loc;  // torn copy -> local index
+  for (int a = 0; a < n; ++a)
+    for (int t : L.copies[comps[a]]) loc[t] = a;
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int a = 0; a < n; ++a)
+    for (int t1 : L.copies[comps[a]]) {
+      int k = 0;
+      while (k + 1 < L.K && L.pd[k + 1].off <= t1) ++k;
+      const PatchDev &pt = L.pd[k];
+      long long lc = t1 - pt.off;
+      int i[3] = {(int)(lc % pt.n[0]), (int)((lc / pt.n[0]) % pt.n[1]),
+                  (int)(lc / ((long long)pt.n[0] * pt.n[1]))};
+      int lo[3], hi[3];
+      for (int g = 0; g < 3; ++g) {
+        lo[g] = g < d ? std::max(0, i[g] - p) : 0;
+        hi[g] = g < d ? std::min(pt.n[g] - 1, i[g] + p) : 0;
+      }
+      for (int j2 = lo[2]; j2 <= hi[2]; ++j2)
+        for (int j1 = lo[1]; j1 <= hi[1]; ++j1)
+          for (int j0 = lo[0]; j0 <= hi[0]; ++j0) {
+            int j[3] = {j0, j1, j2};
+            long long t2 = torn_index(pt, j);
+            auto it = loc.find(t2);
+            if (it == loc.end()) continue;
+            double v = d == 2 ? vol_entry<2>(pt, L.tabB.data(), L.tabD.data(), c.gr, p, i, j)
+                              : vol_entry<3>(pt, L.tabB.data(), L.tabD.data(), c.gr, p, i, j);
+            A[(size_t)a * n + it->second] += v;
+          }
+      if (!L.if_ptr.empty())
+        for (int e = L.if_ptr[t1]; e < L.if_ptr[t1 + 1]; ++e) {
+          auto it = loc.find(L.if_col[e]);
+          if (it != loc.end()) A[(size_t)a * n + it->second] += L.if_val[e];
+        }
+    }
+  return A;
+}
+
+// ---------------------------------------------------------------------------
+// smoother data
+// ---------------------------------------------------------------------------
+static void build_pieces(Context &c, LevelData &L) {
+  const int d = c.d;
+  std::map<std::vector<int>, int> key2piece;
+  std::vector<std::vector<int>> members;
+  for (long long ci = 0; ci < L.N; ++ci) {
+    long long t = L.rep[ci];
+    int k = 0;
+    while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
+    const PatchDev &pt = L.pd[k];
+    long long lc = t - pt.off;
+    int i[3] = {(int)(lc % pt.n[0]), (int)((lc / pt.n[0]) % pt.n[1]),
+                (int)(lc / ((long long)pt.n[0] * pt.n[1]))};
+    int fixed[3] = {-1, -1, -1};
+    bool interior = true;
+    for (int g = 0; g < d; ++g) {
+      if (i[g] == 0) fixed[g] = 0;
+      if (i[g] == pt.n[g] - 1) fixed[g] = 1;
+      if (fixed[g] >= 0) interior = false;
+    }
+    if (interior) continue;
+    std::vector<int> key;
+    for (int b = 0; b < (1 << d); ++b) {
+      bool ok = true;
+      for (int g = 0; g < d; ++g)
+        if (fixed[g] >= 0 && ((b >> g) & 1) != fixed[g]) ok = false;
+      if (ok) key.push_back(c.vid[k][b]);
+    }
+    std::sort(key.begin(), key.end());
+    auto it = key2piece.find(key);
+    if (it == key2piece.end()) {
+      it = key2piece.emplace(key, (int)members.size()).first;
+      members.push_back({});
+    }
+    members[it->second].push_back((int)ci);
+  }
+  std::vector<PieceDev> pcs;
+  std::vector<int> idx, cp, cidx;
+  std::vector<double> inv;
+  L.max_piece = 0;
+  for (auto &m : members) {
+    PieceDev pc{};
+    pc.n = (int)m.size();
+    pc.inv_off = (long long)inv.size();
+    pc.idx_off = (int)idx.size();
+    pc.cp_off = (int)cp.size();
+    for (int ci : m) {
+      idx.push_back(L.rep[ci]);
+      cp.push_back((int)cidx.size());
+      for (int t : L.copies[ci]) cidx.push_back(t);
+    }
+    cp.push_back((int)cidx.size());
+    std::vector<double> A = dense_block(c, L, m);
+    std::vector<double> Ai = spd_inverse(A, pc.n);
+    inv.insert(inv.end(), Ai.begin(), Ai.end());
+    pcs.push_back(pc);
+    L.max_piece = std::max(L.max_piece, pc.n);
+  }
+  L.n_pieces = (int)pcs.size();
+  L.d_pieces = c.arena.upload(pcs, c.stream);
+  L.d_piece_idx = c.arena.upload(idx, c.stream);
+  L.d_piece_cp = c.arena.upload(cp, c.stream);
+  L.d_piece_cidx = c.arena.upload(cidx, c.stream);
+  L.d_piece_inv = c.arena.upload(inv, c.stream);
+}
+
+static void build_scms(Context &c, LevelData &L) {
+  const int p = c.p;
+  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D SCMS not built");
+  std::map<int, std::pair<double *, double *>> qtab;  // nel -> (Q, lam)
+  for (int k = 0; k < L.K; ++k)
+    for (int g = 0; g < c.d; ++g) {
+      int ne = L.pd[k].nel[g];
+      if (qtab.count(ne)) continue;
+      std::vector<double> Q, lam;
+      scms_factors_1d(ne, p, Q, lam);
+      qtab[ne] = {c.arena.upload(Q, c.stream), c.arena.upload(lam, c.stream)};
+    }
+  size_t scr = 0;
+  for (int k = 0; k < L.K; ++k) scr += (size_t)(L.pd[k].n[0] - 2) * (L.pd[k].n[1] - 2);
+  double *s1 = c.arena.alloc<double>(scr), *s2 = c.arena.alloc<double>(scr);
+  std::vector<GemmItem> st[4];
+  size_t so = 0;
+  L.gemm_maxM = L.gemm_maxN = 0;
+  for (int k = 0; k < L.K; ++k) {
+    PatchDev &pt = L.pd[k];
+    int nx = pt.n[0], mx = pt.n[0] - 2, my = pt.n[1] - 2;
+    double *Qx = qtab[pt.nel[0]].first, *Qy = qtab[pt.nel[1]].first;
+    double *lx = qtab[pt.nel[0]].second, *ly = qtab[pt.nel[1]].second;
+    double *S1 = s1 + so, *S2 = s2 + so;
+    so += (size_t)mx * my;
+    double *rin = L.r + pt.off + nx + 1;
+    double *uin = L.u + pt.off + nx + 1;
+    double h = 1.0 / std::max(pt.nel[0], pt.nel[1]);
+    pt.sigma = 1.0 / (c.opt.scaling_delta * h * h);
+    double gamma = std::pow(c.measure[k], (c.d - 2.0) / c.d);
+    pt.scms_scale = c.opt.damping_tau / gamma;
+    GemmItem a{};
+    // 1) S1 = R Qx
+    a = GemmItem{rin, Qx, S1, my, mx, mx, nx, 1, mx, 1, mx, 1, nullptr, nullptr, 0.0, 0.0};
+    st[0].push_back(a);
+    // 2) S2 = Qy^T S1 ./ (sigma + ly + lx)
+    a = GemmItem{Qy, S1, S2, my, mx, my, 1, my, mx, 1, mx, 1, ly, lx, pt.sigma, 0.0};
+    st[1].push_back(a);
+    // 3) S1 = S2 Qx^T
+    a = GemmItem{S2, Qx, S1, my, mx, mx, mx, 1, 1, mx, mx, 1, nullptr, nullptr, 0.0, 0.0};
+    st[2].push_back(a);
+    // 4) U += scale * Qy S1
+    a = GemmItem{Qy, S1, uin, my, mx, my, my, 1, mx, 1, nx, 1, nullptr, nullptr, 0.0,
+                 pt.scms_scale};
+    st[3].push_back(a);
+    L.gemm_maxM = std::max(L.gemm_maxM, my);
+    L.gemm_maxN = std::max(L.gemm_maxN, mx);
+  }
+  L.n_gemm = L.K;
+  for (int s = 0; s < 4; ++s) L.d_gemm[s] = c.arena.upload(st[s], c.stream);
+}
+
+static void build_gs(Context &c, LevelData &L) {
+  const int d = c.d, T = c.opt.gs_tile;
+  if (d != 2) fail(IGAMG_EUNSUPPORTED, "3D Gauss-Seidel not built");
+  for (int col = 0; col < c.n_colors; ++col)
+    for (int par = 0; par < (1 << d); ++par) {
+      std::vector<GsTile> tiles;
+      for (int k = 0; k < L.K; ++k) {
+        if (c.color[k] != col) continue;
+        const PatchDev &pt = L.pd[k];
+        int nb[3] = {1, 1, 1};
+        for (int g = 0; g < d; ++g) nb[g] = (pt.n[g] + T - 1) / T;
+        for (int b1 = 0; b1 < nb[1]; ++b1)
+          for (int b0 = 0; b0 < nb[0]; ++b0) {
+            int pr = (b0 & 1) | ((b1 & 1) << 1);
+            if (pr != par) continue;
+            tiles.push_back(GsTile{k, {b0 * T, b1 * T, 0}});
+          }
+      }
+      GsClass cl;
+      cl.count = (int)tiles.size();
+      cl.tiles = c.arena.upload(tiles, c.stream);
+      L.gs.push_back(cl);
+    }
+}
+
+static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
+  const int p = c.p, d = c.d;
+  struct Tab {
+    int prow, rrow;
+  };
+  std::map<int, Tab> tabs;
+  std::vector<std::vector<double>> Ps;
+  std::vector<int> ncs;
+  int PW = 1, RW = 1;
+  for (int k = 0; k < F.K; ++k)
+    for (int g = 0; g < d; ++g) {
+      int ncel = C.pd[k].nel[g];
+      if (F.pd[k].nel[g] != 2 * ncel) fail(IGAMG_EINVAL, "levels are not dyadic");
+      if (tabs.count(ncel)) continue;
+      tabs[ncel] = Tab{0, 0};
+      Ps.push_back(embedding_1d(ncel, p));
+      ncs.push_back(ncel);
+    }
+  // widths
+  for (size_t t = 0; t < Ps.size(); ++t) {
+    int nc = ncs[t] + p, nf = 2 * ncs[t] + p;
+    const std::vector<double> &P = Ps[t];
+    for (int i = 0; i < nf; ++i) {
+      int a = -1, b = -1;
+      for (int j = 0; j < nc; ++j)
+        if (P[(size_t)i * nc + j] != 0.0) {
+          if (a < 0) a = j;
+          b = j;
+        }
+      if (a >= 0) PW = std::max(PW, b - a + 1);
+    }
+    for (int j = 0; j < nc; ++j) {
+      int a = -1, b = -1;
+      for (int i = 0; i < nf; ++i)
+        if (P[(size_t)i * nc + j] != 0.0) {
+          if (a < 0) a = i;
+          b = i;
+        }
+      if (a >= 0) RW = std::max(RW, b - a + 1);
+    }
+  }
+  std::vector<int> Plo, Rlo;
+  std::vector<double> Pv, Rv;
+  size_t t = 0;
+  for (auto &kv : tabs) {
+    int ncel = kv.first;
+    size_t ti = std::find(ncs.begin(), ncs.end(), ncel) - ncs.begin();
+    const std::vector<double> &P = Ps[ti];
+    int nc = ncel + p, nf = 2 * ncel + p;
+    kv.second.prow = (int)Plo.size();
+    kv.second.rrow = (int)Rlo.size();
+    for (int i = 0; i < nf; ++i) {
+      int a = 0;
+      while (a < nc && P[(size_t)i * nc + a] == 0.0) ++a;
+      if (a == nc) a = 0;
+      Plo.push_back(a);
+      for (int w = 0; w < PW; ++w) Pv.push_back(a + w < nc ? P[(size_t)i * nc + a + w] : 0.0);
+    }
+    for (int j = 0; j < nc; ++j) {
+      int a = 0;
+      while (a < nf && P[(size_t)a * nc + j] == 0.0) ++a;
+      if (a == nf) a = 0;
+      Rlo.push_back(a);
+      for (int w = 0; w < RW; ++w) Rv.push_back(a + w < nf ? P[(size_t)(a + w) * nc + j] : 0.0);
+    }
+    ++t;
+  }
+  for (int k = 0; k < F.K; ++k)
+    for (int g = 0; g < d; ++g) {
+      const Tab &tb = tabs[C.pd[k].nel[g]];
+      F.pd[k].xp[g] = tb.prow;
+      F.pd[k].xr[g] = tb.rrow;
+    }
+  F.PW = PW;
+  F.RW = RW;
+  F.d_P_lo = c.arena.upload(Plo, c.stream);
+  F.d_P_val = c.arena.upload(Pv, c.stream);
+  F.d_R_lo = c.arena.upload(Rlo, c.stream);
+  F.d_R_val = c.arena.upload(Rv, c.stream);
+}
+
+static void build_maps(Context &c, const LevelData &L, int **d_cp, int **d_cidx) {
+  std::vector<int> cp, cidx;
+  for (long long ci = 0; ci < L.N; ++ci) {
+    cp.push_back((int)cidx.size());
+    for (int t : L.copies[ci]) cidx.push_back(t);
+  }
+  cp.push_back((int)cidx.size());
+  *d_cp = c.arena.upload(cp, c.stream);
+  *d_cidx = c.arena.upload(cidx, c.stream);
+}
+
+// ---------------------------------------------------------------------------
+void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
+                   const igamg_options *o, hipStream_t s) {
+  if (!P || !o) fail(IGAMG_EINVAL, "null argument");
+  if (P->dim != 2 && P->dim != 3) fail(IGAMG_EINVAL, "dim must be 2 or 3");
+  if (P->dim == 3) fail(IGAMG_EUNSUPPORTED, "3D problems are not built yet");
+  if (P->n_patches < 1 || !P->corners || !P->elems) fail(IGAMG_EINVAL, "no patches");
+  if (degree < 1 || degree > MAXP) fail(IGAMG_EINVAL, "degree out of range 1..8");
+  c.d = P->dim;
+  c.p = degree;
+  c.K = P->n_patches;
+  c.opt = *o;
+  c.stream = s;
+  c.sigma_pen = sigma;
+  if (c.opt.gs_tile <= 0) c.opt.gs_tile = 4 * (degree + 1);
+  if (c.opt.gs_tile < degree) fail(IGAMG_EINVAL, "gs_tile must be >= degree");
+  if (c.opt.mu < 1) c.opt.mu = 1;
+  if (c.opt.nu < 1) c.opt.nu = 1;
+  if (c.opt.discretization == IGAMG_SIPG && !(sigma > 0)) fail(IGAMG_EINVAL, "penalty must be positive");
+  const bool use_gs = c.opt.smoother != IGAMG_SMOOTHER_SCMS;
+  const bool use_scms = c.opt.smoother != IGAMG_SMOOTHER_GS;
+  if (c.opt.discretization == IGAMG_CONFORMING && use_gs)
+    fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel ordering is defined for the SIPG space only");
+  if (c.opt.precision != IGAMG_FP64) fail(IGAMG_EUNSUPPORTED, "mixed precision not built yet");
+  c.gr = gauss_rule(degree + 1);
+  const int nc = 1 << c.d;
+  c.corners.assign(c.K, {});
+  c.elems_fine.assign(c.K, {1, 1, 1});
+  for (int k = 0; k < c.K; ++k) {
+    for (int b = 0; b < nc; ++b)
+      for (int a = 0; a < c.d; ++a) c.corners[k][b * 3 + a] = P->corners[((size_t)k * nc + b) * c.d + a];
+    for (int a = 0; a < c.d; ++a) {
+      int e = P->elems[(size_t)k * c.d + a];
+      if (e < 1) fail(IGAMG_EINVAL, "element counts must be positive");
+      c.elems_fine[k][a] = e;
+    }
+  }
+  build_topology(c);
+  auto lev_el = level_elements(c);
+  const int NL = (int)lev_el.size();
+  c.lv.resize(NL);
+  const int S1 = 2 * c.p + 1;
+  int S = 1;
+  for (int g = 0; g < c.d; ++g) S *= S1;
+  int center = 0;
+  for (int g = 0, m = 1; g < c.d; ++g, m *= S1) center += c.p * m;
+  for (int l = 0; l < NL; ++l) {
+    LevelData &L = c.lv[l];
+    L.l = l;
+    build_level_dofs(c, L, lev_el[l]);
+    if (c.opt.discretization == IGAMG_SIPG) build_interfaces(c, L);
+    L.d_tabB = c.arena.upload(L.tabB, c.stream);
+    L.d_tabD = c.arena.upload(L.tabD, c.stream);
+    L.d_mask = c.arena.upload(L.mask, c.stream);
+    std::vector<double> w(L.Ntorn, 0.0);
+    for (long long ci = 0; ci < L.N; ++ci) w[L.rep[ci]] = 1.0;
+    L.d_weight = c.arena.upload(w, c.stream);
+    std::vector<int> ip = L.if_ptr.empty() ? std::vector<int>(L.Ntorn + 1, 0) : L.if_ptr;
+    L.d_if_ptr = c.arena.upload(ip, c.stream);
+    L.d_if_col = c.arena.upload(L.if_col, c.stream);
+    L.d_if_val = c.arena.upload(L.if_val, c.stream);
+    // cross-patch part for Gauss-Seidel, same-side part added to the stencil
+    std::vector<int> cxp(L.Ntorn + 1, 0), cxc, srow, sslot;
+    std::vector<double> cxv, sval;
+    for (long long t = 0; t < L.Ntorn; ++t) {
+      cxp[t + 1] = cxp[t];
+      if (L.if_ptr.empty()) continue;
+      for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e) {
+        if (L.if_cross[e]) {
+          cxc.push_back(L.if_col[e]);
+          cxv.push_back(L.if_val[e]);
+          cxp[t + 1]++;
+        } else {
+          int k = 0;
+          while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
+          const PatchDev &pt = L.pd[k];
+          long long a = t - pt.off, b = L.if_col[e] - pt.off;
+          int slot = 0, m = 1;
+          for (int g = 0; g < c.d; ++g) {
+            int ia = (int)(a % pt.n[g]), ib = (int)(b % pt.n[g]);
+            a /= pt.n[g];
+            b /= pt.n[g];
+            if (std::abs(ib - ia) > c.p) fail(IGAMG_EINVAL, "interface coupling outside the stencil");
+            slot += (ib - ia + c.p) * m;
+            m *= S1;
+          }
+          srow.push_back((int)t);
+          sslot.push_back(slot);
+          sval.push_back(L.if_val[e]);
+        }
+      }
+    }
+    L.d_cx_ptr = c.arena.upload(cxp, c.stream);
+    L.d_cx_col = c.arena.upload(cxc, c.stream);
+    L.d_cx_val = c.arena.upload(cxv, c.stream);
+    // volume tiles
+    std::vector<VolTile> vt;
+    int TE = vol_tile_2d(c.p);
+    for (int k = 0; k < c.K; ++k)
+      for (int e1 = 0; e1 < L.pd[k].nel[1]; e1 += TE)
+        for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, 0}});
+    L.n_vtiles = (int)vt.size();
+    L.d_vtiles = c.arena.upload(vt, c.stream);
+    // glue groups
+    std::vector<int> gp{0}, gi;
+    for (long long ci = 0; ci < L.N; ++ci)
+      if (L.copies[ci].size() > 1) {
+        for (int t : L.copies[ci]) gi.push_back(t);
+        gp.push_back((int)gi.size());
+      }
+    L.n_glue = (int)gp.size() - 1;
+    L.d_glue_ptr = c.arena.upload(gp, c.stream);
+    L.d_glue_idx = c.arena.upload(gi, c.stream);
+    // work vectors
+    L.f = c.arena.alloc<double>(L.Ntorn);
+    L.u = c.arena.alloc<double>(L.Ntorn);
+    L.r = c.arena.alloc<double>(L.Ntorn);
+    k_fill(L.f, 0.0, L.Ntorn, c.stream);
+    k_fill(L.u, 0.0, L.Ntorn, c.stream);
+    k_fill(L.r, 0.0, L.Ntorn, c.stream);
+    if (l >= 1) {
+      build_transfer(c, L, c.lv[l - 1]);
+      if (use_gs) {
+        L.d_stencil = c.arena.alloc<double>((size_t)L.Ntorn * S);
+        L.d_invdiag = c.arena.alloc<double>(L.Ntorn);
+        build_gs(c, L);
+      }
+      if (use_scms) {
+        build_scms(c, L);
+        build_pieces(c, L);
+      }
+    }
+    L.d_pd = c.arena.upload(L.pd, c.stream);
+    if (l >= 1 && use_gs) {
+      k_stencil_assemble(c, L);
+      int *dr = c.arena.upload(srow, c.stream), *ds = c.arena.upload(sslot, c.stream);
+      double *dv = c.arena.upload(sval, c.stream);
+      k_stencil_add(dr, ds, dv, (int)srow.size(), L.d_stencil, S, c.stream);
+      k_invdiag(L.d_stencil, S, center, L.d_mask, L.d_invdiag, L.Ntorn, c.stream);
+    }
+  }
+  // coarse level: dense inverse of A_0 (Cholesky based)
+  {
+    LevelData &L0 = c.lv[0];
+    std::vector<int> all(L0.N);
+    std::iota(all.begin(), all.end(), 0);
+    std::vector<double> A0 = dense_block(c, L0, all);
+    c.N0 = (int)L0.N;
+    std::vector<double> A0i = spd_inverse(A0, c.N0);
+    c.d_A0inv = c.arena.upload(A0i, c.stream);
+    build_maps(c, L0, &c.d_c0_cp, &c.d_c0_cidx);
+  }
+  LevelData &LF = c.lv.back();
+  build_maps(c, LF, &c.d_fin_cp, &c.d_fin_cidx);
+  const long long nt = LF.Ntorn;
+  c.x = c.arena.alloc<double>(nt);
+  c.rr = c.arena.alloc<double>(nt);
+  c.z = c.arena.alloc<double>(nt);
+  c.pp = c.arena.alloc<double>(nt);
+  c.qq = c.arena.alloc<double>(nt);
+  c.ff = c.arena.alloc<double>(nt);
+  for (double *v : {c.x, c.rr, c.z, c.pp, c.qq, c.ff}) k_fill(v, 0.0, nt, c.stream);
+  c.d_red = c.arena.alloc<double>(1024);
+  c.d_scal = c.arena.alloc<double>(S_COUNT);
+  k_fill(c.d_scal, 0.0, S_COUNT, c.stream);
+  HIPCHK(hipHostMalloc((void **)&c.h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+  // roofline model of the volume operator on the finest level
+  {
+    double fl = 0.0;
+    const int q = c.p + 1, P1 = c.p + 1;
+    for (int k = 0; k < c.K; ++k) {
+      const PatchDev &pt = LF.pd[k];
+      double Qx = (double)pt.nel[0] * q, Qy = (double)pt.nel[1] * q;
+      fl += 2.0 * 2.0 * pt.n[1] * Qx * P1;   // x-contraction, values + derivatives
+      fl += 2.0 * 2.0 * Qy * Qx * P1;         // y-contraction
+      fl += Qx * Qy * 60.0;                   // metric from the corners + 2x2 product
+      fl += 2.0 * 2.0 * pt.n[1] * Qx * P1;    // transposed y-contraction (per output row)
+      fl += 2.0 * 2.0 * pt.n[1] * pt.n[0] * P1 * q;  // transposed x-contraction
+    }
+    c.model_vol_flops = fl;
+    c.model_vol_bytes = 3.0 * 8.0 * (double)nt;  // read u, read + write r
+  }
+  HIPCHK(hipStreamSynchronize(c.stream));
+  HIPCHK(hipGetLastError());
+}
+
+size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_options *o) {
+  if (!P || P->dim < 2 || P->dim > 3 || P->n_patches < 1 || degree < 1)
+    fail(IGAMG_EINVAL, "invalid problem");
+  const int d = P->dim, p = degree;
+  double per_level_dofs = 0.0;
+  long long fine = 0;
+  for (int k = 0; k < P->n_patches; ++k) {
+    long long n = 1;
+    for (int a = 0; a < d; ++a) n *= (P->elems[(size_t)k * d + a] + p);
+    fine += n;
+  }
+  // levels shrink by 2^d; geometric sum bounded by 2^d/(2^d-1)
+  per_level_dofs = fine * (double)(1 << d) / ((1 << d) - 1);
+  int S = 1;
+  for (int a = 0; a < d; ++a) S *= (2 * p + 1);
+  bool gs = o->smoother != IGAMG_SMOOTHER_SCMS;
+  double bytes = per_level_dofs * 8.0 * (5 + (gs ? S + 1 : 0) + 2);
+  bytes += fine * 8.0 * 6;
+  return (size_t)bytes + (64u << 20);
+}
+
+}  // namespace igamg

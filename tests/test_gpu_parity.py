@@ -1,0 +1,92 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (float64 end to end, the two sides differ only in rounding
+order, atomics and quadrature-node rounding):
+  operator apply            1e-12 relative
+  one cycle                 1e-11 relative
+  PCG iterates k = 1..K     1e-10 relative
+  final solution            1e-10 relative, equal iteration counts (+-1)
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_common import cached_oracle, gpu_solver, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = [("c1", 1), ("c1", 2), ("c2", 16), ("c2", 8)]
+
+
+def _to_gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+@pytest.fixture(scope="module", params=CASES, ids=["%s/%d" % c for c in CASES])
+def pair(request):
+    name, scale = request.param
+    gs_tile = None
+    cfg, ob = cached_oracle(name, scale)
+    sv = gpu_solver(cfg, gs_tile=ob.gs_tile if not cfg["conforming"] else 0)
+    yield cfg, ob, sv
+    sv.close()
+
+
+def test_sizes(pair):
+    cfg, ob, sv = pair
+    assert sv.n_dofs == ob.N
+    assert sv.n_levels == len(ob.levels)
+
+
+def test_apply(pair):
+    cfg, ob, sv = pair
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((2, ob.N))
+    y = sv.apply(_to_gpu(x)).cpu().numpy()
+    for j in range(2):
+        assert rel_err(y[j], ob.apply(x[j])) < 1e-12
+
+
+def test_load_manufactured(pair):
+    cfg, ob, sv = pair
+    f = sv.load_manufactured().cpu().numpy()
+    assert rel_err(f, ob.load_manufactured()) < 1e-12
+
+
+def test_one_cycle(pair):
+    cfg, ob, sv = pair
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(ob.N)
+    u0 = rng.standard_normal(ob.N) * 0.1
+    ug = sv.vcycle(_to_gpu(f), _to_gpu(u0)).cpu().numpy()
+    uo = ob.mg(ob.L, f, u0.copy())
+    assert rel_err(ug, uo) < 1e-11
+
+
+def test_pcg_iterates(pair):
+    cfg, ob, sv = pair
+    f = workloads.normal_rhs(ob.N, 2002)
+    _, its, hist, iterates = ob.pcg(f)
+    fg = _to_gpu(f)
+    for k in range(1, min(its, 6) + 1):
+        u, info = sv.solve(fg, tol=1e-8, maxit=k)
+        assert rel_err(u.cpu().numpy(), iterates[k - 1]) < 1e-10, k
+
+
+def test_solve_final(pair):
+    cfg, ob, sv = pair
+    f = ob.load_manufactured() if cfg["rhs"] == "manufactured" else workloads.normal_rhs(ob.N, 2002)
+    uo, its, hist, _ = ob.pcg(f)
+    u, info = sv.solve(_to_gpu(f), tol=1e-8, maxit=200, history=True)
+    ug = u.cpu().numpy()
+    assert abs(info[0]["iterations"] - its) <= 1
+    assert info[0]["converged"]
+    assert rel_err(ug, uo) < 1e-10 * max(1, its)
+    # true residual with the oracle's matrix
+    A = ob.A[-1]
+    assert np.linalg.norm(f - A @ ug) / np.linalg.norm(f) <= 1.01e-8
+    assert abs(info[0]["true_rel_residual"] - np.linalg.norm(f - A @ ug) / np.linalg.norm(f)) < 1e-12
+    np.testing.assert_allclose(info[0]["history"][:len(hist)], hist[:len(info[0]["history"])],
+                               rtol=1e-6, atol=1e-14)
