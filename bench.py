@@ -1,0 +1,161 @@
+"""Benchmark: solves/s of the hybrid-smoother multigrid PCG solver to relative
+residual 1e-8 on one MI355X, with the roofline position of the dominant
+kernel and the FP64 CPU oracle timed on the host beside it.
+
+Workload (default): 2D SIPG on the unit square split into 4x4 bilinear
+patches (corners perturbed by up to 10% of the patch width, seed 1902),
+checkerboard 64/96 elements per direction (non-matching interfaces),
+degree 4, penalty 5 p^2/h, V(1,1) cycle with the hybrid smoother
+(forward Gauss-Seidel + SCMS / SCMS + backward Gauss-Seidel, damping 0.25,
+scaling 0.1), float64 PCG, N(0,1) right-hand side (seed 2002), 115,652
+unknowns, 6 grid levels.  One step = one complete solve; the right-hand side
+is resident in HBM before the timed region starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}   # GB/s, TFLOP/s (MI355X)
+
+
+def cpu_baseline(cfg, f, its_gpu, budget_s=15.0):
+    """Oracle (plain FP64 CPU reference) on the same workload: setup excluded
+    (as on the GPU), full PCG solves repeated until budget_s of CPU work."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    pb = oracle.setup(cfg["corners"], cfg["elems"], cfg["p"], sigma=cfg["sigma"],
+                      conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
+                      delta=cfg["delta"])
+    n = 0
+    t0 = time.perf_counter()
+    its = None
+    while True:
+        _, its, _, _ = pb.pcg(f)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="solves/s", cores=int(threads), kind="oracle",
+                sample="%d full PCG solve(s) of the benchmark problem (%d iterations each, "
+                       "setup excluded), %.1f s" % (n, its, dt),
+                iterations=its)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_1902_01818_amd import igamg
+
+    cfg = workloads.config("c2")
+    sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
+                      conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
+                      delta=cfg["delta"], timing=False)
+    N = sv.n_dofs
+    f_host = workloads.normal_rhs(N, cfg["rhs"][1])
+    f = torch.from_numpy(f_host).cuda()
+    u = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        sv.solve(f, u, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+
+    # dominant kernel on the finest level: the family with the most event time
+    # in one untimed instrumented solve
+    top = sv.n_levels - 1
+    family = args.family
+    if family is None:
+        sv.set_timing("")
+        sv.solve(f, u, tol=1e-8, maxit=200)
+        st = sv.kernel_stats(reset=True)
+        fams = {}
+        for key, v in st.items():
+            fam = key.split("/")[0]
+            fams[fam] = fams.get(fam, 0.0) + v["ms"]
+        modelled = [k for k in ("gauss_seidel", "vol_apply", "scms_gemm", "iface_apply") if k in fams]
+        family = max(modelled, key=lambda k: fams[k])
+    # timed region: only the dominant family on the finest level is event-timed
+    sv.set_timing("%s/%d" % (family, top))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        _, info = sv.solve(f, u, tol=1e-8, maxit=200)
+        infos.append(info[0])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = sv.kernel_stats(reset=True)
+    sv.set_timing(None)
+    key = "%s/%d" % (family, top)
+    launches = st[key]["launches"]
+    avg_s = st[key]["ms"] / 1e3 / max(launches, 1)
+    mbytes, mflops = sv.kernel_model(family, top)
+    if family in ("vol_apply", "scms_gemm"):
+        achieved = mflops / avg_s / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=PEAK["fp64"], unit="TFLOP/s")
+    else:
+        achieved = mbytes / avg_s / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = key
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches"] = launches
+    roof["model_bytes_per_launch"] = mbytes
+    roof["model_flops_per_launch"] = mflops
+
+    its = infos[-1]["iterations"]
+    ok = all(i["converged"] and i["true_rel_residual"] <= 1e-8 * 1.01 for i in infos)
+    value = args.steps / dt
+    line = {
+        "metric": "solves/s to rel.res 1e-8 (FP64 MG-PCG)",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D SIPG, 4x4 bilinear patches (10% seeded perturbation), "
+                               "checkerboard 64/96 elements, p=4, sigma=5, hybrid V(1,1), "
+                               "FP64 PCG to 1e-8",
+                   "dofs": N, "levels": sv.n_levels, "iterations": its,
+                   "vcycles_per_s": value * (its + 1),
+                   "true_rel_residual": infos[-1]["true_rel_residual"], "all_converged": ok},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(cfg, f_host, its)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

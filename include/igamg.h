@@ -155,9 +155,17 @@ int igamg_memory(const igamg_ctx *ctx, size_t *bytes);
 int igamg_kernel_stats(igamg_ctx *ctx, int cap, char (*names)[32], double *ms,
                        int64_t *launches, int *count, int reset);
 
-/* Algorithmic bytes moved and flops of one launch of a kernel family on the
- * finest level (the roofline model of the library's kernels). */
-int igamg_kernel_model(igamg_ctx *ctx, const char *family, double *bytes, double *flops);
+/* Per-kernel-family event timing filter: families are keyed "<family>/<level>"
+ * (e.g. "vol_apply/5"); only keys starting with `filter` are timed ("" = all),
+ * filter == NULL switches timing off.  Events are recorded on the launch
+ * stream around every matching launch. */
+int igamg_set_timing(igamg_ctx *ctx, const char *filter);
+
+/* Algorithmic bytes moved and flops of one launch of a kernel family
+ * ("vol_apply", "gauss_seidel", "scms_gemm", "iface_apply") on a level
+ * (level < 0: finest): the roofline model of the library's kernels. */
+int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, double *bytes,
+                       double *flops);
 
 int igamg_destroy(igamg_ctx *ctx);
 const char *igamg_strerror(int code);

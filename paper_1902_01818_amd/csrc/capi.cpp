@@ -215,16 +215,25 @@ int igamg_kernel_stats(igamg_ctx *ctx, int cap, char (*names)[32], double *ms, i
   });
 }
 
-int igamg_kernel_model(igamg_ctx *ctx, const char *family, double *bytes, double *flops) {
+int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, double *bytes,
+                       double *flops) {
   return guarded([&] {
     if (!ctx || !family || !bytes || !flops) igamg::fail(IGAMG_EINVAL, "null argument");
     igamg::Context &c = ctx->c;
-    if (std::string(family) == "vol_apply") {
-      *bytes = c.model_vol_bytes;
-      *flops = c.model_vol_flops;
-      return IGAMG_OK;
-    }
-    igamg::fail(IGAMG_EINVAL, "no model for this kernel family");
+    if (level < 0) level = (int)c.lv.size() - 1;
+    if (level >= (int)c.lv.size()) igamg::fail(IGAMG_EINVAL, "level out of range");
+    igamg::kernel_model(c, family, level, bytes, flops);
+    return IGAMG_OK;
+  });
+}
+
+int igamg_set_timing(igamg_ctx *ctx, const char *filter) {
+  return guarded([&] {
+    if (!ctx) igamg::fail(IGAMG_EINVAL, "null argument");
+    igamg::Context &c = ctx->c;
+    c.opt.timing = filter ? 1 : 0;
+    c.timing_filter = filter ? filter : "";
+    return IGAMG_OK;
   });
 }
 

@@ -136,8 +136,7 @@ struct Context {
   hipStream_t stream = nullptr;
   Arena arena;
   std::map<std::string, TimerFamily> timers;
-  // roofline model inputs
-  double model_vol_flops = 0, model_vol_bytes = 0;
+  std::string timing_filter;  // time only families whose key starts with this
 
   void launch_begin(const char *fam, hipEvent_t *b, hipEvent_t *e);
   void launch_end(const char *fam, hipEvent_t b, hipEvent_t e);
@@ -147,6 +146,9 @@ struct Context {
 void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
                    const igamg_options *o, hipStream_t s);
 size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_options *o);
+// algorithmic bytes / flops of one launch of a kernel family on a level
+void kernel_model(const Context &c, const std::string &family, int level, double *bytes,
+                  double *flops);
 
 // cycle / outer iteration (cycle.cpp)
 void apply_torn(Context &c, int l, const double *u, const double *f, const double *fw, double *r,

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 
 #include "geom.h"
 #include "kernels.h"
@@ -32,15 +33,21 @@ inline unsigned nblocks(long long n, int bs = BS) {
   return (unsigned)b;
 }
 
+// Event timing of one launch (or launch group) of a kernel family on a level,
+// recorded on the launch stream when the family matches the context's filter.
 struct TimeScope {
   Context &c;
-  const char *fam;
+  std::string key;
+  bool on = false;
   hipEvent_t b = nullptr, e = nullptr;
-  TimeScope(Context &c_, const char *f) : c(c_), fam(f) {
-    if (c.opt.timing) c.launch_begin(fam, &b, &e);
+  TimeScope(Context &c_, const char *f, int level) : c(c_) {
+    if (!c.opt.timing) return;
+    key = std::string(f) + "/" + std::to_string(level);
+    on = c.timing_filter.empty() || key.rfind(c.timing_filter, 0) == 0;
+    if (on) c.launch_begin(key.c_str(), &b, &e);
   }
   ~TimeScope() {
-    if (c.opt.timing) c.launch_end(fam, b, e);
+    if (on) c.launch_end(key.c_str(), b, e);
   }
 };
 
@@ -692,7 +699,7 @@ void k_load_manufactured(Context &c, LevelData &L, double *out) {
 
 void k_iface_apply(Context &c, LevelData &L, const double *u, const double *f, const double *fw,
                    double beta, double alpha, double *r) {
-  TimeScope ts(c, "iface_apply");
+  TimeScope ts(c, "iface_apply", L.l);
   iface_kernel<<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.Ntorn, L.d_mask, L.d_if_ptr, L.d_if_col,
                                                       L.d_if_val, u, f, fw, beta, alpha, r);
 }
@@ -706,7 +713,7 @@ static void launch_vol2d(Context &c, LevelData &L, const double *u, double *r, d
 int vol_tile_2d(int p) { return p <= 4 ? 8 : (p <= 6 ? 6 : 4); }
 
 void k_vol_apply(Context &c, LevelData &L, const double *u, double *r, double alpha) {
-  TimeScope ts(c, "vol_apply");
+  TimeScope ts(c, "vol_apply", L.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D volume operator not built");
   switch (c.p) {
     case 1: launch_vol2d<1, 8>(c, L, u, r, alpha); break;
@@ -740,11 +747,11 @@ static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backwa
 }
 
 void k_gs_sweep(Context &c, LevelData &L, bool backward) {
-  TimeScope ts(c, "gauss_seidel");
   int nc = (int)L.gs.size();
   for (int ii = 0; ii < nc; ++ii) {
     const GsClass &cl = L.gs[backward ? nc - 1 - ii : ii];
     if (cl.count == 0) continue;
+    TimeScope ts(c, "gauss_seidel", L.l);
     switch (c.p) {
       case 1: launch_gs2d<1>(c, L, cl, backward); break;
       case 2: launch_gs2d<2>(c, L, cl, backward); break;
@@ -760,14 +767,14 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward) {
 }
 
 void k_scms_interior(Context &c, LevelData &L) {
-  TimeScope ts(c, "scms_gemm");
+  TimeScope ts(c, "scms_gemm", L.l);
   if (L.n_gemm == 0) return;
   dim3 grid((L.gemm_maxN + 63) / 64, (L.gemm_maxM + 63) / 64, L.n_gemm);
   for (int st = 0; st < 4; ++st) gemm_kernel<<<grid, 256, 0, c.stream>>>(L.d_gemm[st]);
 }
 
 void k_pieces(Context &c, LevelData &L, const double *r, double *u) {
-  TimeScope ts(c, "pieces");
+  TimeScope ts(c, "pieces", L.l);
   if (L.n_pieces == 0) return;
   piece_kernel<<<L.n_pieces, 256, (size_t)L.max_piece * sizeof(double), c.stream>>>(
       L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, L.d_piece_inv, r, u,
@@ -775,7 +782,7 @@ void k_pieces(Context &c, LevelData &L, const double *r, double *u) {
 }
 
 void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc) {
-  TimeScope ts(c, "restrict");
+  TimeScope ts(c, "restrict", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
   restrict2d_kernel<<<nblocks(C.Ntorn), BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_R_lo, F.d_R_val,
                                                            F.RW, rf, F.d_weight, C.d_mask, C.Ntorn,
@@ -783,14 +790,14 @@ void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double
 }
 
 void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, double *uf) {
-  TimeScope ts(c, "prolong");
+  TimeScope ts(c, "prolong", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
   prolong2d_kernel<<<nblocks(F.Ntorn), BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_P_lo, F.d_P_val,
                                                           F.PW, ec, F.d_mask, F.Ntorn, uf);
 }
 
 void k_coarse_solve(Context &c, const double *f0, double *u0) {
-  TimeScope ts(c, "coarse");
+  TimeScope ts(c, "coarse", 0);
   int nb = std::max(1, std::min(64, (c.N0 + 15) / 16));
   coarse_kernel<<<nb, 256, (size_t)c.N0 * sizeof(double), c.stream>>>(c.N0, c.d_A0inv, c.d_c0_cp,
                                                                       c.d_c0_cidx, f0, u0);
@@ -807,20 +814,20 @@ void k_gather_compact(const double *xt, long long N, const int *cp, const int *c
 }
 
 void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode) {
-  TimeScope ts(c, "blas1");
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   dot_partial_kernel<<<RED_BLOCKS, 256, 0, c.stream>>>(a, b, c.lv.back().d_weight, n, c.d_red);
   dot_final_kernel<<<1, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, slot, mode);
 }
 
 void k_pcg_update_xr(Context &c, long long n) {
-  TimeScope ts(c, "blas1");
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   pcg_xr_kernel<<<RED_BLOCKS, 256, 0, c.stream>>>(c.x, c.rr, c.pp, c.qq, c.lv.back().d_weight, n,
                                                   c.d_scal, c.d_red);
   dot_final_kernel<<<1, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
 }
 
 void k_pcg_update_p(Context &c, long long n) {
-  TimeScope ts(c, "blas1");
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   pcg_p_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, c.stream>>>(c.pp, c.z, n, c.d_scal);
 }
 

@@ -986,24 +986,54 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   c.d_scal = c.arena.alloc<double>(S_COUNT);
   k_fill(c.d_scal, 0.0, S_COUNT, c.stream);
   HIPCHK(hipHostMalloc((void **)&c.h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
-  // roofline model of the volume operator on the finest level
-  {
-    double fl = 0.0;
-    const int q = c.p + 1, P1 = c.p + 1;
-    for (int k = 0; k < c.K; ++k) {
-      const PatchDev &pt = LF.pd[k];
-      double Qx = (double)pt.nel[0] * q, Qy = (double)pt.nel[1] * q;
-      fl += 2.0 * 2.0 * pt.n[1] * Qx * P1;   // x-contraction, values + derivatives
-      fl += 2.0 * 2.0 * Qy * Qx * P1;         // y-contraction
-      fl += Qx * Qy * 60.0;                   // metric from the corners + 2x2 product
-      fl += 2.0 * 2.0 * pt.n[1] * Qx * P1;    // transposed y-contraction (per output row)
-      fl += 2.0 * 2.0 * pt.n[1] * pt.n[0] * P1 * q;  // transposed x-contraction
-    }
-    c.model_vol_flops = fl;
-    c.model_vol_bytes = 3.0 * 8.0 * (double)nt;  // read u, read + write r
-  }
   HIPCHK(hipStreamSynchronize(c.stream));
   HIPCHK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// roofline model: algorithmic work of one launch (not counting redundant
+// loads of tile halos or recomputation)
+// ---------------------------------------------------------------------------
+void kernel_model(const Context &c, const std::string &fam, int level, double *bytes,
+                  double *flops) {
+  const LevelData &L = c.lv[level];
+  const double nt = (double)L.Ntorn;
+  const int q = c.p + 1, P1 = c.p + 1;
+  int S = 1;
+  for (int g = 0; g < c.d; ++g) S *= (2 * c.p + 1);
+  double nnz = L.if_col.size(), ncross = 0;
+  for (unsigned char x : L.if_cross) ncross += x;
+  *bytes = 0;
+  *flops = 0;
+  if (fam == "vol_apply") {
+    for (int k = 0; k < c.K; ++k) {
+      const PatchDev &pt = L.pd[k];
+      double Qx = (double)pt.nel[0] * q, Qy = (double)pt.nel[1] * q;
+      *flops += 4.0 * pt.n[1] * Qx * P1;        // x-contraction (values and derivatives)
+      *flops += 4.0 * Qy * Qx * P1;             // y-contraction
+      *flops += 60.0 * Qx * Qy;                 // metric from the corners, 2x2 product
+      *flops += 4.0 * pt.n[1] * Qx * P1;        // transposed y-contraction
+      *flops += 4.0 * pt.n[1] * pt.n[0] * Qx / pt.nel[0] * P1;  // transposed x-contraction
+    }
+    *bytes = 3.0 * 8.0 * nt;                    // read u, read and write r
+  } else if (fam == "gauss_seidel") {
+    int launches = 0;
+    for (const GsClass &cl : L.gs) launches += cl.count > 0;
+    if (launches == 0) launches = 1;
+    *bytes = (nt * (8.0 * S + 8.0 * 4 + 4.0) + ncross * 20.0) / launches;
+    *flops = (2.0 * S * nt + 2.0 * ncross) / launches;
+  } else if (fam == "scms_gemm") {
+    for (int k = 0; k < c.K; ++k) {
+      double mx = L.pd[k].n[0] - 2, my = L.pd[k].n[1] - 2;
+      *flops += 2.0 * (mx * my * mx + my * my * mx + my * mx * mx + my * my * mx);
+      *bytes += 8.0 * (mx * my * (1 + 2 + 4) + 2 * (mx * mx + my * my));
+    }
+  } else if (fam == "iface_apply") {
+    *bytes = nt * (8.0 + 8.0 + 1.0 + 4.0) + nnz * (4.0 + 8.0 + 8.0);
+    *flops = 2.0 * nnz;
+  } else {
+    fail(IGAMG_EINVAL, "no model for this kernel family");
+  }
 }
 
 size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_options *o) {

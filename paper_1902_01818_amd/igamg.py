@@ -63,8 +63,9 @@ _lib.igamg_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
 _lib.igamg_kernel_stats.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
                                     ctypes.c_int]
-_lib.igamg_kernel_model.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
-                                    ctypes.POINTER(ctypes.c_double)]
+_lib.igamg_kernel_model.argtypes = [_vp, ctypes.c_char_p, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.igamg_set_timing.argtypes = [_vp, ctypes.c_char_p]
 _lib.igamg_destroy.argtypes = [_vp]
 _lib.igamg_strerror.restype = ctypes.c_char_p
 _lib.igamg_last_error.restype = ctypes.c_char_p
@@ -72,7 +73,8 @@ _lib.igamg_last_error.restype = ctypes.c_char_p
 EXPORTED = ["igamg_default_options", "igamg_footprint", "igamg_setup", "igamg_num_dofs",
             "igamg_num_levels", "igamg_apply", "igamg_vcycle", "igamg_solve",
             "igamg_load_manufactured", "igamg_memory", "igamg_kernel_stats",
-            "igamg_kernel_model", "igamg_destroy", "igamg_strerror", "igamg_last_error"]
+            "igamg_kernel_model", "igamg_set_timing", "igamg_destroy", "igamg_strerror",
+            "igamg_last_error"]
 
 
 class IgamgError(RuntimeError):
@@ -215,11 +217,16 @@ class Solver:
             out[nm] = dict(ms=ms[i], launches=int(launches[i]))
         return out
 
-    def kernel_model(self, family):
+    def kernel_model(self, family, level=-1):
         b, f = ctypes.c_double(), ctypes.c_double()
-        _check(_lib.igamg_kernel_model(self._h, family.encode(), ctypes.byref(b), ctypes.byref(f)),
-               "igamg_kernel_model")
+        _check(_lib.igamg_kernel_model(self._h, family.encode(), level, ctypes.byref(b),
+                                       ctypes.byref(f)), "igamg_kernel_model")
         return b.value, f.value
+
+    def set_timing(self, filter):
+        """None = off, "" = all families, else a "<family>/<level>" prefix."""
+        _check(_lib.igamg_set_timing(self._h, None if filter is None else filter.encode()),
+               "igamg_set_timing")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,43 @@
+"""Parity at the full size of the benchmark workload (2D SIPG, 4x4 bilinear
+patches, 64/96 elements, p = 4, 115,652 unknowns, 6 levels), in the launch
+configuration the benchmark times."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_common import cached_oracle, gpu_solver, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def full_pair():
+    cfg, ob = cached_oracle("c2", 1)
+    sv = gpu_solver(cfg)           # library defaults, as in bench.py
+    assert ob.gs_tile == 4 * (cfg["p"] + 1)
+    yield cfg, ob, sv
+    sv.close()
+
+
+def test_full_apply_and_cycle(full_pair):
+    cfg, ob, sv = full_pair
+    assert sv.n_dofs == ob.N == 115652 and sv.n_levels == 6
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(ob.N)
+    y = sv.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel_err(y, ob.apply(x)) < 1e-12
+    f = workloads.normal_rhs(ob.N, 2002)
+    z = sv.vcycle(torch.from_numpy(f).cuda(), torch.zeros(ob.N, dtype=torch.float64).cuda())
+    assert rel_err(z.cpu().numpy(), ob.vcycle(f)) < 1e-11
+
+
+def test_full_solve(full_pair):
+    cfg, ob, sv = full_pair
+    f = workloads.normal_rhs(ob.N, 2002)
+    uo, its, hist, _ = ob.pcg(f)
+    u, info = sv.solve(torch.from_numpy(f).cuda(), tol=1e-8, maxit=200)
+    ug = u.cpu().numpy()
+    assert info[0]["converged"] and abs(info[0]["iterations"] - its) <= 1
+    assert rel_err(ug, uo) < 1e-9
+    assert np.linalg.norm(f - ob.A[-1] @ ug) / np.linalg.norm(f) <= 1.01e-8
