@@ -83,7 +83,7 @@ typedef struct {
   double scaling_delta; /* SCMS scaling sigma = 1/(delta h^2), Section 5 */
   int precision;      /* IGAMG_FP64 / IGAMG_FP32 (cycle arithmetic) */
   int outer;          /* IGAMG_OUTER_* */
-  int gs_tile;        /* Gauss-Seidel tile width T >= p of the colour ordering, 0 = 4(p+1) */
+  int gs_tile;        /* Gauss-Seidel tile width T >= p of the colour ordering, 0 = 2(p+1) */
   int coarse_min;     /* halve element counts while all are even and their half >= coarse_min; 0 = 2 */
   int timing;         /* 1 = record per-kernel-family event timings (igamg_kernel_stats) */
 } igamg_options;

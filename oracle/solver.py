@@ -38,7 +38,7 @@ class OracleProblem:
         self.smoother = smoother
         self.mu, self.nu = mu, nu
         self.tau, self.delta = tau, delta
-        self.gs_tile = 4 * (p + 1) if gs_tile is None else gs_tile
+        self.gs_tile = 2 * (p + 1) if gs_tile is None else gs_tile
         if conforming and smoother in ("gs", "hybrid"):
             raise NotImplementedError("Gauss-Seidel ordering is defined for SIPG only")
         self.eta = None if conforming else penalty(self.topo, elems, p, sigma)

@@ -387,6 +387,113 @@ __global__ __launch_bounds__(256) void gs2d_kernel(const GsTile *tiles, const Pa
   }
 }
 
+// Fast path for the tile width T = 2(p+1): a tile holds four unknowns of every
+// colour class, one wavefront updates one of them.  The stencil rows of the
+// next D classes are prefetched into registers while the current class is
+// processed; f minus the cross-patch couplings (constant during the launch:
+// neighbouring patches carry another patch colour) and 1/a_ii are staged in
+// LDS together with the window of u.
+template <int P>
+__global__ __launch_bounds__(256) void gs2d_fast_kernel(const GsTile *tiles, const PatchDev *pd,
+                                                        const double *__restrict__ st,
+                                                        const double *__restrict__ invd,
+                                                        const int *__restrict__ cx_ptr,
+                                                        const int *__restrict__ cx_col,
+                                                        const double *__restrict__ cx_val,
+                                                        const double *__restrict__ f, double *u,
+                                                        const unsigned char *__restrict__ mask,
+                                                        int backward) {
+  constexpr int Q1 = P + 1, T = 2 * Q1, W = T + 2 * P;
+  constexpr int S1 = 2 * P + 1, S = S1 * S1;
+  constexpr int C = (S + 63) / 64;
+  constexpr int NPH = Q1 * Q1;
+  constexpr int D0 = 48 / C;
+  constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
+  __shared__ double sU[W * W];
+  __shared__ double sB[T * T];
+  __shared__ double sI[T * T];
+  const GsTile tl = tiles[blockIdx.x];
+  const PatchDev &pt = pd[tl.patch];
+  const int nx = pt.n[0], ny = pt.n[1];
+  const int x0 = tl.i0[0], y0 = tl.i0[1];
+  const int wx0 = x0 - P, wy0 = y0 - P;
+  const long long off = pt.off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < W * W; i += 256) {
+    int gy = wy0 + i / W, gx = wx0 + i % W;
+    sU[i] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? u[off + (long long)gy * nx + gx] : 0.0;
+  }
+  for (int i = tid; i < T * T; i += 256) {
+    int iy = y0 + i / T, ix = x0 + i % T;
+    double b = 0.0, di = 0.0;
+    if (ix < nx && iy < ny) {
+      long long t = off + (long long)iy * nx + ix;
+      if (mask[t]) {
+        b = f[t];
+        for (int e = cx_ptr[t]; e < cx_ptr[t + 1]; ++e) b -= cx_val[e] * u[cx_col[e]];
+        di = invd[t];
+      }
+    }
+    sB[i] = b;
+    sI[i] = di;
+  }
+  double buf[D][C];
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    int ph = backward ? NPH - 1 - s : s;
+    int ix = x0 + ph % Q1 + (wave & 1) * Q1, iy = y0 + ph / Q1 + (wave >> 1) * Q1;
+    bool ok = ix < nx && iy < ny;
+    const double *srow = st + (off + (long long)iy * nx + ix) * S;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int o = lane + 64 * c;
+      buf[s][c] = (ok && o < S) ? srow[o] : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NPH; ++s) {
+    const int ph = backward ? NPH - 1 - s : s;
+    const int ix = x0 + ph % Q1 + (wave & 1) * Q1, iy = y0 + ph / Q1 + (wave >> 1) * Q1;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int o = lane + 64 * c;
+      if (o < S) {
+        int oy = o / S1, ox = o % S1;
+        acc += buf[s % D][c] * sU[(iy - y0 + oy) * W + (ix - x0 + ox)];
+      }
+    }
+    if (s + D < NPH) {
+      const int s2 = s + D;
+      const int ph2 = backward ? NPH - 1 - s2 : s2;
+      const int jx = x0 + ph2 % Q1 + (wave & 1) * Q1, jy = y0 + ph2 / Q1 + (wave >> 1) * Q1;
+      const bool ok = jx < nx && jy < ny;
+      const double *srow = st + (off + (long long)jy * nx + jx) * S;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        int o = lane + 64 * c;
+        buf[s % D][c] = (ok && o < S) ? srow[o] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+    if (lane == 0 && ix < nx && iy < ny) {
+      const int li = (iy - y0) * T + (ix - x0);
+      const double di = sI[li];
+      if (di != 0.0) {
+        const int wi = (iy - wy0) * W + (ix - wx0);
+        sU[wi] += (sB[li] - acc) * di;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < T * T; i += 256) {
+    int iy = y0 + i / T, ix = x0 + i % T;
+    if (ix < nx && iy < ny) u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // batched GEMM (float64), 64x64 output tile, 4x4 per thread, K chunks of 16
 // ---------------------------------------------------------------------------
@@ -736,6 +843,12 @@ void k_glue_sum(LevelData &L, double *y, hipStream_t s) {
 template <int P>
 static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward) {
   int T = c.opt.gs_tile;
+  if (T == 2 * (P + 1)) {
+    gs2d_fast_kernel<P><<<cl.count, 256, 0, c.stream>>>(cl.tiles, L.d_pd, L.d_stencil, L.d_invdiag,
+                                                        L.d_cx_ptr, L.d_cx_col, L.d_cx_val, L.f,
+                                                        L.u, L.d_mask, backward ? 1 : 0);
+    return;
+  }
   int W = T + 2 * P;
   int rows = ((T + P) / (P + 1)) * ((T + P) / (P + 1));
   int G = 64;

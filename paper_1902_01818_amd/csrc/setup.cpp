@@ -834,7 +834,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   c.opt = *o;
   c.stream = s;
   c.sigma_pen = sigma;
-  if (c.opt.gs_tile <= 0) c.opt.gs_tile = 4 * (degree + 1);
+  if (c.opt.gs_tile <= 0) c.opt.gs_tile = 2 * (degree + 1);
   if (c.opt.gs_tile < degree) fail(IGAMG_EINVAL, "gs_tile must be >= degree");
   if (c.opt.mu < 1) c.opt.mu = 1;
   if (c.opt.nu < 1) c.opt.nu = 1;

@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 def full_pair():
     cfg, ob = cached_oracle("c2", 1)
     sv = gpu_solver(cfg)           # library defaults, as in bench.py
-    assert ob.gs_tile == 4 * (cfg["p"] + 1)
+    assert ob.gs_tile == 2 * (cfg["p"] + 1)
     yield cfg, ob, sv
     sv.close()
 

@@ -17,18 +17,19 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-CASES = [("c1", 1), ("c1", 2), ("c2", 16), ("c2", 8)]
+# (config, scale, Gauss-Seidel tile width; None = default 2(p+1), which takes
+# the register-prefetch kernel, 4(p+1) takes the generic tile kernel)
+CASES = [("c1", 1, None), ("c1", 2, None), ("c2", 16, None), ("c2", 8, None), ("c2", 8, 20)]
 
 
 def _to_gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
 
 
-@pytest.fixture(scope="module", params=CASES, ids=["%s/%d" % c for c in CASES])
+@pytest.fixture(scope="module", params=CASES, ids=["%s/%d/T%s" % c for c in CASES])
 def pair(request):
-    name, scale = request.param
-    gs_tile = None
-    cfg, ob = cached_oracle(name, scale)
+    name, scale, gs_tile = request.param
+    cfg, ob = cached_oracle(name, scale, gs_tile)
     sv = gpu_solver(cfg, gs_tile=ob.gs_tile if not cfg["conforming"] else 0)
     yield cfg, ob, sv
     sv.close()
