@@ -64,6 +64,13 @@ struct LevelData {
   double *d_if_val = nullptr;
   int *d_cx_ptr = nullptr, *d_cx_col = nullptr;
   double *d_cx_val = nullptr;
+  // rows carrying interface terms (lane-parallel part of the residual kernel)
+  unsigned char *d_has_if = nullptr;
+  int *d_if_rows = nullptr;
+  int n_if_rows = 0;
+  // cross-patch couplings per Gauss-Seidel tile: (row inside tile, column, value)
+  int *d_gcx_li = nullptr, *d_gcx_col = nullptr;
+  double *d_gcx_val = nullptr;
   // same-side interface entries added to the stencil (torn row, stencil slot, value)
   // volume stencil + inverse diagonal (Gauss-Seidel)
   double *d_stencil = nullptr, *d_invdiag = nullptr;

@@ -55,6 +55,7 @@ struct VolTile {
 struct GsTile {
   int patch;
   int i0[3];
+  int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
 };
 
 // Batched GEMM item: C = A * B with strided operands (row / column strides),

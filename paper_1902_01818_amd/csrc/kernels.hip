@@ -53,6 +53,39 @@ struct TimeScope {
 
 __device__ inline void atomic_add(double *a, double v) { unsafeAtomicAdd(a, v); }
 
+// Cross-lane sums without LDS traffic: DPP row shifts build an inclusive scan
+// inside every row of 16 lanes (lane 15 of a row then holds the row sum); the
+// wavefront total combines the four row sums with readlane.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double row16_scan(double v) {
+  v += dpp_move<0x111>(v);  // row_shr:1
+  v += dpp_move<0x112>(v);  // row_shr:2
+  v += dpp_move<0x114>(v);  // row_shr:4
+  v += dpp_move<0x118>(v);  // row_shr:8
+  return v;
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the 64 lanes of the wavefront (uniform result)
+__device__ inline double wave_sum(double v) {
+  v = row16_scan(v);
+  return (readlane_d(v, 15) + readlane_d(v, 31)) + (readlane_d(v, 47) + readlane_d(v, 63));
+}
+
 // ---------------------------------------------------------------------------
 // elementwise
 // ---------------------------------------------------------------------------
@@ -173,20 +206,40 @@ __global__ void load_kernel(const PatchDev *pd, int K, const double *tabB, Gauss
 // ---------------------------------------------------------------------------
 // interface terms: r = mask (beta f + alpha A_if u)   (one thread per unknown)
 // ---------------------------------------------------------------------------
-__global__ void iface_kernel(long long n, const unsigned char *mask, const int *ptr, const int *col,
-                             const double *val, const double *u, const double *f,
-                             const double *fw, double beta, double alpha, double *r) {
-  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  if (!mask[t]) {
-    r[t] = 0.0;
+__global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
+                                                    const unsigned char *__restrict__ mask,
+                                                    const unsigned char *__restrict__ has_if,
+                                                    const int *__restrict__ rows, int nrows,
+                                                    const int *__restrict__ ptr,
+                                                    const int *__restrict__ col,
+                                                    const double *__restrict__ val,
+                                                    const double *__restrict__ u,
+                                                    const double *__restrict__ f,
+                                                    const double *__restrict__ fw, double beta,
+                                                    double alpha, double *__restrict__ r) {
+  if ((int)blockIdx.x < nb_plain) {
+    // unknowns without interface couplings: r = mask beta (w) f
+    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= n || has_if[t]) return;
+    double v = 0.0;
+    if (mask[t] && f) v = beta * (fw ? fw[t] : 1.0) * f[t];
+    r[t] = v;
     return;
   }
+  // unknowns next to an interface: 16 lanes per row
+  const int g = ((int)blockIdx.x - nb_plain) * (blockDim.x / 16) + threadIdx.x / 16;
+  const int lane = threadIdx.x % 16;
+  const bool ok = g < nrows;
+  const int t = ok ? rows[g] : 0;
   double s = 0.0;
-  for (int e = ptr[t]; e < ptr[t + 1]; ++e) s += val[e] * u[col[e]];
-  double v = alpha * s;
-  if (f) v += beta * (fw ? fw[t] : 1.0) * f[t];
-  r[t] = v;
+  if (ok)
+    for (int e = ptr[t] + lane; e < ptr[t + 1]; e += 16) s += val[e] * u[col[e]];
+  s = row16_scan(s);
+  if (ok && lane == 15) {
+    double v = alpha * s;
+    if (f) v += beta * (fw ? fw[t] : 1.0) * f[t];
+    r[t] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -397,7 +450,7 @@ template <int P>
 __global__ __launch_bounds__(256) void gs2d_fast_kernel(const GsTile *tiles, const PatchDev *pd,
                                                         const double *__restrict__ st,
                                                         const double *__restrict__ invd,
-                                                        const int *__restrict__ cx_ptr,
+                                                        const int *__restrict__ cx_li,
                                                         const int *__restrict__ cx_col,
                                                         const double *__restrict__ cx_val,
                                                         const double *__restrict__ f, double *u,
@@ -430,13 +483,16 @@ __global__ __launch_bounds__(256) void gs2d_fast_kernel(const GsTile *tiles, con
       long long t = off + (long long)iy * nx + ix;
       if (mask[t]) {
         b = f[t];
-        for (int e = cx_ptr[t]; e < cx_ptr[t + 1]; ++e) b -= cx_val[e] * u[cx_col[e]];
         di = invd[t];
       }
     }
     sB[i] = b;
     sI[i] = di;
   }
+  __syncthreads();
+  // cross-patch couplings of the tile rows, one entry per thread
+  for (int e = tl.cx_off + tid; e < tl.cx_off + tl.cx_n; e += 256)
+    unsafeAtomicAdd(&sB[cx_li[e]], -cx_val[e] * u[cx_col[e]]);
   double buf[D][C];
 #pragma unroll
   for (int s = 0; s < D; ++s) {
@@ -476,8 +532,7 @@ __global__ __launch_bounds__(256) void gs2d_fast_kernel(const GsTile *tiles, con
         buf[s % D][c] = (ok && o < S) ? srow[o] : 0.0;
       }
     }
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+    acc = wave_sum(acc);
     if (lane == 0 && ix < nx && iy < ny) {
       const int li = (iy - y0) * T + (ix - x0);
       const double di = sI[li];
@@ -508,15 +563,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem *items) {
   const int tid = threadIdx.x;
   const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
   double acc[4][4] = {};
+  double ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = tid + 256 * x;
+      const int kk = i / 64, mm = i % 64;
+      const int m = m0 + mm, n = n0 + mm, k = k0 + kk;
+      ra[x] = (m < it.M && k < it.K) ? A[m * it.a_r + k * it.a_c] : 0.0;
+      rb[x] = (n < it.N && k < it.K) ? B[k * it.b_r + n * it.b_c] : 0.0;
+    }
+  };
+  gload(0);
   for (int k0 = 0; k0 < it.K; k0 += 16) {
-    for (int i = tid; i < 16 * 64; i += 256) {
-      int kk = i / 64, mm = i % 64;
-      int m = m0 + mm, k = k0 + kk;
-      sA[kk][mm] = (m < it.M && k < it.K) ? A[m * it.a_r + k * it.a_c] : 0.0;
-      int n = n0 + mm;
-      sB[kk][mm] = (n < it.N && k < it.K) ? B[k * it.b_r + n * it.b_c] : 0.0;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = tid + 256 * x;
+      sA[i / 64][i % 64] = ra[x];
+      sB[i / 64][i % 64] = rb[x];
     }
     __syncthreads();
+    if (k0 + 16 < it.K) gload(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       double a[4], b[4];
@@ -537,7 +604,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem *items) {
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
-      int m = m0 + tm + x, n = n0 + tn + y;
+      const int m = m0 + tm + x, n = n0 + tn + y;
       if (m >= it.M || n >= it.N) continue;
       double v = acc[x][y];
       if (it.lam_r) v /= (it.sigma + it.lam_r[m] + it.lam_c[n]);
@@ -550,7 +617,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem *items) {
 }
 
 // ---------------------------------------------------------------------------
-// interface pieces: u[copies] += inv(P^T A P) r[piece]   (one block per piece)
+// interface pieces: u[copies] += tau inv(P^T A P) r[piece].  Grid (piece, row
+// block); the symmetric inverse is read as column j, row i = inv[j*n + i], so
+// consecutive threads (rows) read consecutive addresses.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void piece_kernel(const PieceDev *pieces, const int *idx,
                                                     const int *cp, const int *cidx,
@@ -559,22 +628,26 @@ __global__ __launch_bounds__(256) void piece_kernel(const PieceDev *pieces, cons
   extern __shared__ double sr[];
   const PieceDev pc = pieces[blockIdx.x];
   const int n = pc.n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) sr[i] = r[idx[pc.idx_off + i]];
+  const int i = blockIdx.y * blockDim.x + threadIdx.x;
+  if ((int)(blockIdx.y * blockDim.x) >= n) return;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sr[j] = r[idx[pc.idx_off + j]];
   __syncthreads();
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
-  const double *M = inv + pc.inv_off;
-  for (int i = wave; i < n; i += nw) {
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += M[(long long)i * n + j] * sr[j];
-    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0) {
-      int b = cp[pc.cp_off + i], e = cp[pc.cp_off + i + 1];
-      for (int c = b; c < e; ++c) u[cidx[c]] += scale * s;
-    }
+  if (i >= n) return;
+  const double *M = inv + pc.inv_off + i;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    s0 += M[(long long)j * n] * sr[j];
+    s1 += M[(long long)(j + 1) * n] * sr[j + 1];
+    s2 += M[(long long)(j + 2) * n] * sr[j + 2];
+    s3 += M[(long long)(j + 3) * n] * sr[j + 3];
   }
+  for (; j < n; ++j) s0 += M[(long long)j * n] * sr[j];
+  const double y = scale * ((s0 + s1) + (s2 + s3));
+  for (int c = cp[pc.cp_off + i]; c < cp[pc.cp_off + i + 1]; ++c) u[cidx[c]] += y;
 }
 
-// coarse solve: gather (sum of copies), dense inverse, scatter to all copies
+// coarse solve: gather (sum of copies), dense symmetric inverse, scatter to all copies
 __global__ __launch_bounds__(256) void coarse_kernel(int n, const double *inv, const int *cp,
                                                      const int *cidx, const double *f, double *u) {
   extern __shared__ double sr[];
@@ -584,56 +657,77 @@ __global__ __launch_bounds__(256) void coarse_kernel(int n, const double *inv, c
     sr[i] = s;
   }
   __syncthreads();
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
-  for (int i = blockIdx.x * nw + wave; i < n; i += gridDim.x * nw) {
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += inv[(long long)i * n + j] * sr[j];
-    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0)
-      for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = s;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *M = inv + i;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    s0 += M[(long long)j * n] * sr[j];
+    s1 += M[(long long)(j + 1) * n] * sr[j + 1];
+    s2 += M[(long long)(j + 2) * n] * sr[j + 2];
+    s3 += M[(long long)(j + 3) * n] * sr[j + 3];
   }
+  for (; j < n; ++j) s0 += M[(long long)j * n] * sr[j];
+  const double y = (s0 + s1) + (s2 + s3);
+  for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = y;
 }
 
 // ---------------------------------------------------------------------------
-// transfers (2D): restriction r_c = P^T (w r_f), prolongation u_f += P e_c
+// transfers (2D): restriction r_c = P^T (w r_f), prolongation u_f += P e_c.
+// The 1D factors are banded (at most MAXW entries per row / column); the band
+// of the thread's unknown is held in registers.
 // ---------------------------------------------------------------------------
-__global__ void restrict2d_kernel(const PatchDev *pf, const PatchDev *pc, int K, const int *Rlo,
-                                  const double *Rval, int RW, const double *rf, const double *wf,
-                                  const unsigned char *maskc, long long nc_tot, double *rc) {
+constexpr int MAXW = 12;
+
+__global__ __launch_bounds__(256) void restrict2d_kernel(const PatchDev *pf, const PatchDev *pc,
+                                                         int K, const int *Rlo, const double *Rval,
+                                                         int RW, const double *rf,
+                                                         const double *wf,
+                                                         const unsigned char *maskc,
+                                                         long long nc_tot, double *rc) {
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= nc_tot) return;
   int k = 0;
   while (k + 1 < K && pc[k + 1].off <= t) ++k;
   const PatchDev &C = pc[k], &F = pf[k];
-  long long loc = t - C.off;
-  int jx = (int)(loc % C.n[0]), jy = (int)(loc / C.n[0]);
   if (!maskc[t]) {
     rc[t] = 0.0;
     return;
   }
+  long long loc = t - C.off;
+  const int jx = (int)(loc % C.n[0]), jy = (int)(loc / C.n[0]);
   const int rx = F.xr[0] + jx, ry = F.xr[1] + jy;
   const int lx = Rlo[rx], ly = Rlo[ry];
+  double vx[MAXW], vy[MAXW];
+#pragma unroll
+  for (int a = 0; a < MAXW; ++a) {
+    vx[a] = a < RW ? Rval[(long long)rx * RW + a] : 0.0;
+    vy[a] = a < RW ? Rval[(long long)ry * RW + a] : 0.0;
+  }
   double s = 0.0;
-  for (int a = 0; a < RW; ++a) {
-    int iy = ly + a;
-    double vy = Rval[(long long)ry * RW + a];
-    if (vy == 0.0 || iy >= F.n[1]) continue;
-    double sx = 0.0;
-    for (int b = 0; b < RW; ++b) {
-      int ix = lx + b;
-      double vx = Rval[(long long)rx * RW + b];
-      if (vx == 0.0 || ix >= F.n[0]) continue;
-      long long tf = F.off + (long long)iy * F.n[0] + ix;
-      sx += vx * wf[tf] * rf[tf];
+#pragma unroll
+  for (int a = 0; a < MAXW; ++a) {
+    const int iy = ly + a;
+    if (a < RW && iy < F.n[1]) {
+      double sx = 0.0;
+      const long long rowoff = F.off + (long long)iy * F.n[0];
+#pragma unroll
+      for (int b = 0; b < MAXW; ++b) {
+        const int ix = lx + b;
+        if (b < RW && ix < F.n[0]) sx += vx[b] * (wf[rowoff + ix] * rf[rowoff + ix]);
+      }
+      s += vy[a] * sx;
     }
-    s += vy * sx;
   }
   rc[t] = s;
 }
 
-__global__ void prolong2d_kernel(const PatchDev *pf, const PatchDev *pc, int K, const int *Plo,
-                                 const double *Pval, int PW, const double *ec,
-                                 const unsigned char *maskf, long long nf_tot, double *uf) {
+__global__ __launch_bounds__(256) void prolong2d_kernel(const PatchDev *pf, const PatchDev *pc,
+                                                        int K, const int *Plo, const double *Pval,
+                                                        int PW, const double *ec,
+                                                        const unsigned char *maskf,
+                                                        long long nf_tot, double *uf) {
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= nf_tot) return;
   int k = 0;
@@ -641,22 +735,29 @@ __global__ void prolong2d_kernel(const PatchDev *pf, const PatchDev *pc, int K, 
   const PatchDev &F = pf[k], &C = pc[k];
   if (!maskf[t]) return;
   long long loc = t - F.off;
-  int ix = (int)(loc % F.n[0]), iy = (int)(loc / F.n[0]);
+  const int ix = (int)(loc % F.n[0]), iy = (int)(loc / F.n[0]);
   const int px = F.xp[0] + ix, py = F.xp[1] + iy;
   const int lx = Plo[px], ly = Plo[py];
+  double vx[MAXW], vy[MAXW];
+#pragma unroll
+  for (int a = 0; a < MAXW; ++a) {
+    vx[a] = a < PW ? Pval[(long long)px * PW + a] : 0.0;
+    vy[a] = a < PW ? Pval[(long long)py * PW + a] : 0.0;
+  }
   double s = 0.0;
-  for (int a = 0; a < PW; ++a) {
-    int jy = ly + a;
-    double vy = Pval[(long long)py * PW + a];
-    if (vy == 0.0 || jy >= C.n[1]) continue;
-    double sx = 0.0;
-    for (int b = 0; b < PW; ++b) {
-      int jx = lx + b;
-      double vx = Pval[(long long)px * PW + b];
-      if (vx == 0.0 || jx >= C.n[0]) continue;
-      sx += vx * ec[C.off + (long long)jy * C.n[0] + jx];
+#pragma unroll
+  for (int a = 0; a < MAXW; ++a) {
+    const int jy = ly + a;
+    if (a < PW && jy < C.n[1]) {
+      double sx = 0.0;
+      const long long rowoff = C.off + (long long)jy * C.n[0];
+#pragma unroll
+      for (int b = 0; b < MAXW; ++b) {
+        const int jx = lx + b;
+        if (b < PW && jx < C.n[0]) sx += vx[b] * ec[rowoff + jx];
+      }
+      s += vy[a] * sx;
     }
-    s += vy * sx;
   }
   uf[t] += s;
 }
@@ -807,8 +908,11 @@ void k_load_manufactured(Context &c, LevelData &L, double *out) {
 void k_iface_apply(Context &c, LevelData &L, const double *u, const double *f, const double *fw,
                    double beta, double alpha, double *r) {
   TimeScope ts(c, "iface_apply", L.l);
-  iface_kernel<<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.Ntorn, L.d_mask, L.d_if_ptr, L.d_if_col,
-                                                      L.d_if_val, u, f, fw, beta, alpha, r);
+  const int nb_plain = (int)nblocks(L.Ntorn);
+  const int nb_rows = (L.n_if_rows + 15) / 16;
+  iface_kernel<<<nb_plain + nb_rows, BS, 0, c.stream>>>(
+      L.Ntorn, nb_plain, L.d_mask, L.d_has_if, L.d_if_rows, L.n_if_rows, L.d_if_ptr, L.d_if_col,
+      L.d_if_val, u, f, fw, beta, alpha, r);
 }
 
 template <int P, int TE>
@@ -845,7 +949,7 @@ static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backwa
   int T = c.opt.gs_tile;
   if (T == 2 * (P + 1)) {
     gs2d_fast_kernel<P><<<cl.count, 256, 0, c.stream>>>(cl.tiles, L.d_pd, L.d_stencil, L.d_invdiag,
-                                                        L.d_cx_ptr, L.d_cx_col, L.d_cx_val, L.f,
+                                                        L.d_gcx_li, L.d_gcx_col, L.d_gcx_val, L.f,
                                                         L.u, L.d_mask, backward ? 1 : 0);
     return;
   }
@@ -889,7 +993,8 @@ void k_scms_interior(Context &c, LevelData &L) {
 void k_pieces(Context &c, LevelData &L, const double *r, double *u) {
   TimeScope ts(c, "pieces", L.l);
   if (L.n_pieces == 0) return;
-  piece_kernel<<<L.n_pieces, 256, (size_t)L.max_piece * sizeof(double), c.stream>>>(
+  dim3 grid(L.n_pieces, (L.max_piece + 255) / 256);
+  piece_kernel<<<grid, 256, (size_t)L.max_piece * sizeof(double), c.stream>>>(
       L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, L.d_piece_inv, r, u,
       c.opt.damping_tau);
 }
@@ -911,7 +1016,7 @@ void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, dou
 
 void k_coarse_solve(Context &c, const double *f0, double *u0) {
   TimeScope ts(c, "coarse", 0);
-  int nb = std::max(1, std::min(64, (c.N0 + 15) / 16));
+  int nb = (c.N0 + 255) / 256;
   coarse_kernel<<<nb, 256, (size_t)c.N0 * sizeof(double), c.stream>>>(c.N0, c.d_A0inv, c.d_c0_cp,
                                                                       c.d_c0_cidx, f0, u0);
 }

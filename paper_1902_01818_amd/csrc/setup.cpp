@@ -706,11 +706,13 @@ static void build_scms(Context &c, LevelData &L) {
 static void build_gs(Context &c, LevelData &L) {
   const int d = c.d, T = c.opt.gs_tile;
   if (d != 2) fail(IGAMG_EUNSUPPORTED, "3D Gauss-Seidel not built");
-  for (int col = 0; col < c.n_colors; ++col)
+  std::vector<int> li, col;
+  std::vector<double> val;
+  for (int colr = 0; colr < c.n_colors; ++colr)
     for (int par = 0; par < (1 << d); ++par) {
       std::vector<GsTile> tiles;
       for (int k = 0; k < L.K; ++k) {
-        if (c.color[k] != col) continue;
+        if (c.color[k] != colr) continue;
         const PatchDev &pt = L.pd[k];
         int nb[3] = {1, 1, 1};
         for (int g = 0; g < d; ++g) nb[g] = (pt.n[g] + T - 1) / T;
@@ -718,7 +720,21 @@ static void build_gs(Context &c, LevelData &L) {
           for (int b0 = 0; b0 < nb[0]; ++b0) {
             int pr = (b0 & 1) | ((b1 & 1) << 1);
             if (pr != par) continue;
-            tiles.push_back(GsTile{k, {b0 * T, b1 * T, 0}});
+            GsTile tl{k, {b0 * T, b1 * T, 0}, (int)li.size(), 0};
+            // cross-patch couplings of the tile rows
+            for (int iy = b1 * T; iy < std::min(pt.n[1], (b1 + 1) * T); ++iy)
+              for (int ix = b0 * T; ix < std::min(pt.n[0], (b0 + 1) * T); ++ix) {
+                long long t = pt.off + (long long)iy * pt.n[0] + ix;
+                if (L.if_ptr.empty()) continue;
+                for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e)
+                  if (L.if_cross[e]) {
+                    li.push_back((iy - b1 * T) * T + (ix - b0 * T));
+                    col.push_back(L.if_col[e]);
+                    val.push_back(L.if_val[e]);
+                  }
+              }
+            tl.cx_n = (int)li.size() - tl.cx_off;
+            tiles.push_back(tl);
           }
       }
       GsClass cl;
@@ -726,6 +742,9 @@ static void build_gs(Context &c, LevelData &L) {
       cl.tiles = c.arena.upload(tiles, c.stream);
       L.gs.push_back(cl);
     }
+  L.d_gcx_li = c.arena.upload(li, c.stream);
+  L.d_gcx_col = c.arena.upload(col, c.stream);
+  L.d_gcx_val = c.arena.upload(val, c.stream);
 }
 
 static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
@@ -801,6 +820,7 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
       F.pd[k].xp[g] = tb.prow;
       F.pd[k].xr[g] = tb.rrow;
     }
+  if (PW > 12 || RW > 12) fail(IGAMG_EUNSUPPORTED, "transfer band wider than the kernels hold");
   F.PW = PW;
   F.RW = RW;
   F.d_P_lo = c.arena.upload(Plo, c.stream);
@@ -911,6 +931,18 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
           sval.push_back(L.if_val[e]);
         }
       }
+    }
+    {
+      std::vector<unsigned char> has(L.Ntorn, 0);
+      std::vector<int> rows;
+      for (long long t = 0; t < L.Ntorn; ++t)
+        if (!L.if_ptr.empty() && L.if_ptr[t + 1] > L.if_ptr[t]) {
+          has[t] = 1;
+          rows.push_back((int)t);
+        }
+      L.n_if_rows = (int)rows.size();
+      L.d_has_if = c.arena.upload(has, c.stream);
+      L.d_if_rows = c.arena.upload(rows, c.stream);
     }
     L.d_cx_ptr = c.arena.upload(cxp, c.stream);
     L.d_cx_col = c.arena.upload(cxc, c.stream);
