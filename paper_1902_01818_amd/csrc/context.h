@@ -83,10 +83,10 @@ struct LevelData {
   VolTile *d_vtiles = nullptr;
   int n_vtiles = 0;
   std::vector<GsClass> gs;  // classes in key order
-  // SCMS interiors: four batched GEMM stages
-  GemmItem *d_gemm[4] = {nullptr, nullptr, nullptr, nullptr};
-  int n_gemm = 0;
-  int gemm_maxM = 0, gemm_maxN = 0;
+  // SCMS interiors: forward (Q^T R Q ./ D) and backward (Q W Q^T) row-block products
+  Fd2Item *d_fd[2] = {nullptr, nullptr};
+  int n_fd = 0;
+  int fd_rows = 0, fd_K1 = 0, fd_N = 0;
   // interface pieces
   PieceDev *d_pieces = nullptr;
   int n_pieces = 0, max_piece = 0;

@@ -58,14 +58,17 @@ struct GsTile {
   int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
 };
 
-// Batched GEMM item: C = A * B with strided operands (row / column strides),
-// optional epilogues: divide by (sigma + lam_r[m] + lam_c[n]); C += scale * acc.
-struct GemmItem {
-  const void *A;
-  const void *B;
-  void *C;
-  int M, N, K;
-  long long a_r, a_c, b_r, b_c, c_r, c_c;
+// Two chained products on a block of 16 rows (fast-diagonalization step of the
+// subspace corrected mass smoother): Z = L[rows, :] M1, R = Z M2, then either
+// O[rows, :] = R / (sigma + lam_r[row] + lam_c[col]) (lam_r != null) or
+// O[rows, :] += scale R.  All operands are row-major with unit column stride.
+struct Fd2Item {
+  const double *L;   // rows x K1, row stride l_r
+  const double *M1;  // K1 x N, row stride m1_r
+  const double *M2;  // N x N, row stride m2_r
+  double *O;         // rows x N, row stride o_r
+  long long l_r, m1_r, m2_r, o_r;
+  int rows, K1, N;
   const double *lam_r;
   const double *lam_c;
   double sigma;

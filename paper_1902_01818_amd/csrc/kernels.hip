@@ -440,43 +440,43 @@ __global__ __launch_bounds__(256) void gs2d_kernel(const GsTile *tiles, const Pa
   }
 }
 
-// Fast path for the tile width T = 2(p+1): a tile holds four unknowns of every
-// colour class, one wavefront updates one of them.  The stencil rows of the
-// next D classes are prefetched into registers while the current class is
-// processed; f minus the cross-patch couplings (constant during the launch:
-// neighbouring patches carry another patch colour) and 1/a_ii are staged in
-// LDS together with the window of u.
+// One wavefront per tile (T = 2(p+1)): the four unknowns of a colour class
+// are updated by four groups of 16 lanes; the row sum of each group comes out
+// of a DPP scan in its last lane, so no barrier between wavefronts is needed.
+// Stencil rows of the next D classes are prefetched into registers.
 template <int P>
-__global__ __launch_bounds__(256) void gs2d_fast_kernel(const GsTile *tiles, const PatchDev *pd,
-                                                        const double *__restrict__ st,
-                                                        const double *__restrict__ invd,
-                                                        const int *__restrict__ cx_li,
-                                                        const int *__restrict__ cx_col,
-                                                        const double *__restrict__ cx_val,
-                                                        const double *__restrict__ f, double *u,
-                                                        const unsigned char *__restrict__ mask,
-                                                        int backward) {
+__global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, const PatchDev *pd,
+                                                       const double *__restrict__ st,
+                                                       const double *__restrict__ invd,
+                                                       const int *__restrict__ cx_li,
+                                                       const int *__restrict__ cx_col,
+                                                       const double *__restrict__ cx_val,
+                                                       const double *__restrict__ f, double *u,
+                                                       const unsigned char *__restrict__ mask,
+                                                       int backward) {
   constexpr int Q1 = P + 1, T = 2 * Q1, W = T + 2 * P;
   constexpr int S1 = 2 * P + 1, S = S1 * S1;
-  constexpr int C = (S + 63) / 64;
+  constexpr int C = (S + 15) / 16;
   constexpr int NPH = Q1 * Q1;
   constexpr int D0 = 48 / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
   __shared__ double sU[W * W];
   __shared__ double sB[T * T];
   __shared__ double sI[T * T];
+  __shared__ int sOff[C * 16];
   const GsTile tl = tiles[blockIdx.x];
   const PatchDev &pt = pd[tl.patch];
   const int nx = pt.n[0], ny = pt.n[1];
   const int x0 = tl.i0[0], y0 = tl.i0[1];
   const int wx0 = x0 - P, wy0 = y0 - P;
   const long long off = pt.off;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < W * W; i += 256) {
+  const int lane = threadIdx.x, grp = lane >> 4, l16 = lane & 15;
+  const int ax = (grp & 1) * Q1, ay = (grp >> 1) * Q1;
+  for (int i = lane; i < W * W; i += 64) {
     int gy = wy0 + i / W, gx = wx0 + i % W;
     sU[i] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? u[off + (long long)gy * nx + gx] : 0.0;
   }
-  for (int i = tid; i < T * T; i += 256) {
+  for (int i = lane; i < T * T; i += 64) {
     int iy = y0 + i / T, ix = x0 + i % T;
     double b = 0.0, di = 0.0;
     if (ix < nx && iy < ny) {
@@ -489,188 +489,223 @@ __global__ __launch_bounds__(256) void gs2d_fast_kernel(const GsTile *tiles, con
     sB[i] = b;
     sI[i] = di;
   }
+  // LDS offset of stencil slot o relative to the row's own window position
+  for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
   __syncthreads();
-  // cross-patch couplings of the tile rows, one entry per thread
-  for (int e = tl.cx_off + tid; e < tl.cx_off + tl.cx_n; e += 256)
+  for (int e = tl.cx_off + lane; e < tl.cx_off + tl.cx_n; e += 64)
     unsafeAtomicAdd(&sB[cx_li[e]], -cx_val[e] * u[cx_col[e]]);
   double buf[D][C];
 #pragma unroll
   for (int s = 0; s < D; ++s) {
-    int ph = backward ? NPH - 1 - s : s;
-    int ix = x0 + ph % Q1 + (wave & 1) * Q1, iy = y0 + ph / Q1 + (wave >> 1) * Q1;
-    bool ok = ix < nx && iy < ny;
+    const int ph = backward ? NPH - 1 - s : s;
+    const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
+    const bool ok = ix < nx && iy < ny;
     const double *srow = st + (off + (long long)iy * nx + ix) * S;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      int o = lane + 64 * c;
+      const int o = l16 + 16 * c;
       buf[s][c] = (ok && o < S) ? srow[o] : 0.0;
     }
   }
+  int soff[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) soff[c] = 0;
   __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) soff[c] = sOff[l16 + 16 * c];
 #pragma unroll
   for (int s = 0; s < NPH; ++s) {
     const int ph = backward ? NPH - 1 - s : s;
-    const int ix = x0 + ph % Q1 + (wave & 1) * Q1, iy = y0 + ph / Q1 + (wave >> 1) * Q1;
+    const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
+    const int wi = (iy - wy0) * W + (ix - wx0);
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      int o = lane + 64 * c;
-      if (o < S) {
-        int oy = o / S1, ox = o % S1;
-        acc += buf[s % D][c] * sU[(iy - y0 + oy) * W + (ix - x0 + ox)];
-      }
-    }
+    for (int c = 0; c < C; ++c) acc += buf[s % D][c] * sU[wi + soff[c]];
     if (s + D < NPH) {
       const int s2 = s + D;
       const int ph2 = backward ? NPH - 1 - s2 : s2;
-      const int jx = x0 + ph2 % Q1 + (wave & 1) * Q1, jy = y0 + ph2 / Q1 + (wave >> 1) * Q1;
+      const int jx = x0 + ph2 % Q1 + ax, jy = y0 + ph2 / Q1 + ay;
       const bool ok = jx < nx && jy < ny;
       const double *srow = st + (off + (long long)jy * nx + jx) * S;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        int o = lane + 64 * c;
+        const int o = l16 + 16 * c;
         buf[s % D][c] = (ok && o < S) ? srow[o] : 0.0;
       }
     }
-    acc = wave_sum(acc);
-    if (lane == 0 && ix < nx && iy < ny) {
+    acc = row16_scan(acc);
+    if (l16 == 15 && ix < nx && iy < ny) {
       const int li = (iy - y0) * T + (ix - x0);
       const double di = sI[li];
-      if (di != 0.0) {
-        const int wi = (iy - wy0) * W + (ix - wx0);
-        sU[wi] += (sB[li] - acc) * di;
-      }
+      if (di != 0.0) sU[wi] += (sB[li] - acc) * di;
     }
     __syncthreads();
   }
-  for (int i = tid; i < T * T; i += 256) {
+  for (int i = lane; i < T * T; i += 64) {
     int iy = y0 + i / T, ix = x0 + i % T;
     if (ix < nx && iy < ny) u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
   }
 }
 
 // ---------------------------------------------------------------------------
-// batched GEMM (float64), 64x64 output tile, 4x4 per thread, K chunks of 16
+// Row-block products of the fast diagonalization (see Fd2Item).  A block of
+// 256 threads owns 16 rows: thread (rg, cg) accumulates rows 4rg..4rg+3 and
+// columns cg + 64j; B is streamed through LDS in chunks of 8 rows with the
+// next chunk held in registers while the current one is used.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmItem *items) {
-  const GemmItem it = items[blockIdx.z];
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  if (m0 >= it.M || n0 >= it.N) return;
-  __shared__ double sA[16][64 + 1];
-  __shared__ double sB[16][64 + 1];
-  const double *A = (const double *)it.A;
-  const double *B = (const double *)it.B;
-  const int tid = threadIdx.x;
-  const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
-  double acc[4][4] = {};
-  double ra[4], rb[4];
+template <int NJ>
+__device__ inline void rowblock_product(const double *A, int lda, const double *__restrict__ B,
+                                        long long b_r, int K, int N, double *sM,
+                                        double acc[4][NJ]) {
+  constexpr int WB = 64 * NJ;      // LDS row length of a chunk
+  constexpr int LPT = 2 * NJ;      // 8 * WB / 256 loads per thread
+  const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
+  double pre[LPT];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int i = tid + 256 * x;
-      const int kk = i / 64, mm = i % 64;
-      const int m = m0 + mm, n = n0 + mm, k = k0 + kk;
-      ra[x] = (m < it.M && k < it.K) ? A[m * it.a_r + k * it.a_c] : 0.0;
-      rb[x] = (n < it.N && k < it.K) ? B[k * it.b_r + n * it.b_c] : 0.0;
+    for (int x = 0; x < LPT; ++x) {
+      const int e = tid + 256 * x;
+      const int kk = e / WB, col = e % WB;
+      pre[x] = (k0 + kk < K && col < N) ? B[(long long)(k0 + kk) * b_r + col] : 0.0;
     }
   };
   gload(0);
-  for (int k0 = 0; k0 < it.K; k0 += 16) {
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    __syncthreads();
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int i = tid + 256 * x;
-      sA[i / 64][i % 64] = ra[x];
-      sB[i / 64][i % 64] = rb[x];
+    for (int x = 0; x < LPT; ++x) {
+      const int e = tid + 256 * x;
+      sM[(e / WB) * WB + e % WB] = pre[x];
     }
     __syncthreads();
-    if (k0 + 16 < it.K) gload(k0 + 16);
+    if (k0 + 8 < K) gload(k0 + 8);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+    for (int kk = 0; kk < 8; ++kk) {
+      double a[4], b[NJ];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        a[x] = sA[kk][tm + x];
-        b[x] = sB[kk][tn + x];
-      }
+      for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
     }
-    __syncthreads();
   }
-  double *C = (double *)it.C;
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pad) {
+  constexpr int WB = 64 * NJ;
+  extern __shared__ double sm[];
+  const Fd2Item it = items[blockIdx.y];
+  const int i0 = blockIdx.x * 16;
+  if (i0 >= it.rows) return;
+  double *sL = sm;                 // 16 x (K1pad + 8), zero padded
+  double *sZ = sL + 16 * (K1pad + 8);  // 16 x WB
+  double *sM = sZ + 16 * WB;       // 8 x WB
+  const int lda = K1pad + 8;
+  const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
+  const int nrow = min(16, it.rows - i0);
+  for (int e = tid; e < 16 * lda; e += 256) {
+    const int i = e / lda, a = e % lda;
+    sL[e] = (i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : 0.0;
+  }
+  double acc[4][NJ];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int m = m0 + tm + x, n = n0 + tn + y;
-      if (m >= it.M || n >= it.N) continue;
-      double v = acc[x][y];
-      if (it.lam_r) v /= (it.sigma + it.lam_r[m] + it.lam_c[n]);
-      double *cp = C + m * it.c_r + n * it.c_c;
-      if (it.scale != 0.0)
-        *cp += it.scale * v;
-      else
-        *cp = v;
+    for (int j = 0; j < NJ; ++j) acc[r][j] = 0.0;
+  rowblock_product<NJ>(sL, lda, it.M1, it.m1_r, it.K1, it.N, sM, acc);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      sZ[(4 * rg + r) * WB + cg + 64 * j] = acc[r][j];
+      acc[r][j] = 0.0;
     }
+  rowblock_product<NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * rg + r;
+    if (i >= nrow) continue;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int col = cg + 64 * j;
+      if (col >= it.N) continue;
+      double v = acc[r][j];
+      double *o = it.O + (long long)(i0 + i) * it.o_r + col;
+      if (it.lam_r)
+        *o = v / (it.sigma + it.lam_r[i0 + i] + it.lam_c[col]);
+      else
+        *o += it.scale * v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// interface pieces: u[copies] += tau inv(P^T A P) r[piece].  Grid (piece, row
-// block); the symmetric inverse is read as column j, row i = inv[j*n + i], so
-// consecutive threads (rows) read consecutive addresses.
+// Dense solves with stored symmetric inverses: a block of 1024 threads owns 64
+// rows; wavefront w sums the columns j = w (mod 16) with lane = row, so the
+// 64 lanes read 64 consecutive entries of column j (= row j, by symmetry);
+// the 16 partial sums are added in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void piece_kernel(const PieceDev *pieces, const int *idx,
-                                                    const int *cp, const int *cidx,
-                                                    const double *inv, const double *r, double *u,
-                                                    double scale) {
-  extern __shared__ double sr[];
+__device__ inline double block_rows_matvec(const double *M, int n, int row0, const double *sr,
+                                           double *spart) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = row0 + lane;
+  double s0 = 0.0, s1 = 0.0;
+  if (i < n) {
+    const double *col = M + i;
+    int j = w;
+    for (; j + 16 < n; j += 32) {
+      s0 += col[(long long)j * n] * sr[j];
+      s1 += col[(long long)(j + 16) * n] * sr[j + 16];
+    }
+    if (j < n) s0 += col[(long long)j * n] * sr[j];
+  }
+  spart[w * 64 + lane] = s0 + s1;
+  __syncthreads();
+  double y = 0.0;
+  if (w == 0)
+    for (int k = 0; k < 16; ++k) y += spart[k * 64 + lane];
+  return y;  // valid in wavefront 0
+}
+
+// interface pieces: u[copies] += tau inv(P^T A P) r[piece]; grid (piece, row block)
+__global__ __launch_bounds__(1024) void piece_kernel(const PieceDev *pieces, const int *idx,
+                                                     const int *cp, const int *cidx,
+                                                     const double *inv, const double *r, double *u,
+                                                     double scale) {
+  extern __shared__ double sm[];
+  __shared__ double spart[16 * 64];
   const PieceDev pc = pieces[blockIdx.x];
   const int n = pc.n;
-  const int i = blockIdx.y * blockDim.x + threadIdx.x;
-  if ((int)(blockIdx.y * blockDim.x) >= n) return;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) sr[j] = r[idx[pc.idx_off + j]];
+  const int row0 = blockIdx.y * 64;
+  if (row0 >= n) return;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sm[j] = r[idx[pc.idx_off + j]];
   __syncthreads();
-  if (i >= n) return;
-  const double *M = inv + pc.inv_off + i;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int j = 0;
-  for (; j + 4 <= n; j += 4) {
-    s0 += M[(long long)j * n] * sr[j];
-    s1 += M[(long long)(j + 1) * n] * sr[j + 1];
-    s2 += M[(long long)(j + 2) * n] * sr[j + 2];
-    s3 += M[(long long)(j + 3) * n] * sr[j + 3];
-  }
-  for (; j < n; ++j) s0 += M[(long long)j * n] * sr[j];
-  const double y = scale * ((s0 + s1) + (s2 + s3));
-  for (int c = cp[pc.cp_off + i]; c < cp[pc.cp_off + i + 1]; ++c) u[cidx[c]] += y;
+  const double y = block_rows_matvec(inv + pc.inv_off, n, row0, sm, spart);
+  const int i = row0 + (int)threadIdx.x;
+  if (threadIdx.x < 64 && i < n)
+    for (int c = cp[pc.cp_off + i]; c < cp[pc.cp_off + i + 1]; ++c) u[cidx[c]] += scale * y;
 }
 
 // coarse solve: gather (sum of copies), dense symmetric inverse, scatter to all copies
-__global__ __launch_bounds__(256) void coarse_kernel(int n, const double *inv, const int *cp,
-                                                     const int *cidx, const double *f, double *u) {
-  extern __shared__ double sr[];
+__global__ __launch_bounds__(1024) void coarse_kernel(int n, const double *inv, const int *cp,
+                                                      const int *cidx, const double *f, double *u) {
+  extern __shared__ double sm[];
+  __shared__ double spart[16 * 64];
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double s = 0.0;
     for (int c = cp[i]; c < cp[i + 1]; ++c) s += f[cidx[c]];
-    sr[i] = s;
+    sm[i] = s;
   }
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double *M = inv + i;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int j = 0;
-  for (; j + 4 <= n; j += 4) {
-    s0 += M[(long long)j * n] * sr[j];
-    s1 += M[(long long)(j + 1) * n] * sr[j + 1];
-    s2 += M[(long long)(j + 2) * n] * sr[j + 2];
-    s3 += M[(long long)(j + 3) * n] * sr[j + 3];
-  }
-  for (; j < n; ++j) s0 += M[(long long)j * n] * sr[j];
-  const double y = (s0 + s1) + (s2 + s3);
-  for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = y;
+  const int row0 = blockIdx.x * 64;
+  const double y = block_rows_matvec(inv, n, row0, sm, spart);
+  const int i = row0 + (int)threadIdx.x;
+  if (threadIdx.x < 64 && i < n)
+    for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = y;
 }
 
 // ---------------------------------------------------------------------------
@@ -948,9 +983,9 @@ template <int P>
 static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward) {
   int T = c.opt.gs_tile;
   if (T == 2 * (P + 1)) {
-    gs2d_fast_kernel<P><<<cl.count, 256, 0, c.stream>>>(cl.tiles, L.d_pd, L.d_stencil, L.d_invdiag,
-                                                        L.d_gcx_li, L.d_gcx_col, L.d_gcx_val, L.f,
-                                                        L.u, L.d_mask, backward ? 1 : 0);
+    gs2d_wave_kernel<P><<<cl.count, 64, 0, c.stream>>>(cl.tiles, L.d_pd, L.d_stencil, L.d_invdiag,
+                                                       L.d_gcx_li, L.d_gcx_col, L.d_gcx_val, L.f,
+                                                       L.u, L.d_mask, backward ? 1 : 0);
     return;
   }
   int W = T + 2 * P;
@@ -983,18 +1018,35 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward) {
   }
 }
 
+template <int NJ>
+static void launch_fd2(Context &c, LevelData &L, int stage) {
+  constexpr int WB = 64 * NJ;
+  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + 8 * WB) * sizeof(double);
+  dim3 grid((L.fd_rows + 15) / 16, L.n_fd);
+  fd2_kernel<NJ><<<grid, 256, lds, c.stream>>>(L.d_fd[stage], L.fd_K1);
+}
+
 void k_scms_interior(Context &c, LevelData &L) {
-  TimeScope ts(c, "scms_gemm", L.l);
-  if (L.n_gemm == 0) return;
-  dim3 grid((L.gemm_maxN + 63) / 64, (L.gemm_maxM + 63) / 64, L.n_gemm);
-  for (int st = 0; st < 4; ++st) gemm_kernel<<<grid, 256, 0, c.stream>>>(L.d_gemm[st]);
+  TimeScope ts(c, "scms", L.l);
+  if (L.n_fd == 0) return;
+  const int nj = (L.fd_N + 63) / 64;
+  for (int st = 0; st < 2; ++st) {
+    switch (nj) {
+      case 1: launch_fd2<1>(c, L, st); break;
+      case 2: launch_fd2<2>(c, L, st); break;
+      case 3: launch_fd2<3>(c, L, st); break;
+      case 4: launch_fd2<4>(c, L, st); break;
+      case 5: launch_fd2<5>(c, L, st); break;
+      default: fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
+    }
+  }
 }
 
 void k_pieces(Context &c, LevelData &L, const double *r, double *u) {
   TimeScope ts(c, "pieces", L.l);
   if (L.n_pieces == 0) return;
-  dim3 grid(L.n_pieces, (L.max_piece + 255) / 256);
-  piece_kernel<<<grid, 256, (size_t)L.max_piece * sizeof(double), c.stream>>>(
+  dim3 grid(L.n_pieces, (L.max_piece + 63) / 64);
+  piece_kernel<<<grid, 1024, (size_t)L.max_piece * sizeof(double), c.stream>>>(
       L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, L.d_piece_inv, r, u,
       c.opt.damping_tau);
 }
@@ -1016,8 +1068,8 @@ void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, dou
 
 void k_coarse_solve(Context &c, const double *f0, double *u0) {
   TimeScope ts(c, "coarse", 0);
-  int nb = (c.N0 + 255) / 256;
-  coarse_kernel<<<nb, 256, (size_t)c.N0 * sizeof(double), c.stream>>>(c.N0, c.d_A0inv, c.d_c0_cp,
+  int nb = (c.N0 + 63) / 64;
+  coarse_kernel<<<nb, 1024, (size_t)c.N0 * sizeof(double), c.stream>>>(c.N0, c.d_A0inv, c.d_c0_cp,
                                                                       c.d_c0_cidx, f0, u0);
 }
 

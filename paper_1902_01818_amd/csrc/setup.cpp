@@ -651,30 +651,46 @@ static void build_pieces(Context &c, LevelData &L) {
   L.d_piece_inv = c.arena.upload(inv, c.stream);
 }
 
+static std::vector<double> transpose(const std::vector<double> &A, int n) {
+  std::vector<double> T((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T[(size_t)j * n + i] = A[(size_t)i * n + j];
+  return T;
+}
+
+// Patch interiors of the subspace corrected mass smoother (Section 5): with
+// the 1D factors Q (Q^T M Q = I) and lam, L_T^-1 r = gamma^-1 (Qy x Qx)
+// diag(1/(sigma + lam_y + lam_x)) (Qy x Qx)^T r, evaluated as
+//   W = (Qy^T R Qx) ./ D   and   U += (tau/gamma) Qy W Qx^T
+// on the interior block R of the patch tensor.
 static void build_scms(Context &c, LevelData &L) {
   const int p = c.p;
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D SCMS not built");
-  std::map<int, std::pair<double *, double *>> qtab;  // nel -> (Q, lam)
+  struct QT {
+    double *Q, *QT, *lam;
+  };
+  std::map<int, QT> qtab;
   for (int k = 0; k < L.K; ++k)
     for (int g = 0; g < c.d; ++g) {
       int ne = L.pd[k].nel[g];
       if (qtab.count(ne)) continue;
       std::vector<double> Q, lam;
       scms_factors_1d(ne, p, Q, lam);
-      qtab[ne] = {c.arena.upload(Q, c.stream), c.arena.upload(lam, c.stream)};
+      int n = ne + p - 2;
+      qtab[ne] = QT{c.arena.upload(Q, c.stream), c.arena.upload(transpose(Q, n), c.stream),
+                    c.arena.upload(lam, c.stream)};
     }
   size_t scr = 0;
   for (int k = 0; k < L.K; ++k) scr += (size_t)(L.pd[k].n[0] - 2) * (L.pd[k].n[1] - 2);
-  double *s1 = c.arena.alloc<double>(scr), *s2 = c.arena.alloc<double>(scr);
-  std::vector<GemmItem> st[4];
+  double *wbuf = c.arena.alloc<double>(scr);
+  std::vector<Fd2Item> fa, fb;
   size_t so = 0;
-  L.gemm_maxM = L.gemm_maxN = 0;
+  L.fd_rows = L.fd_K1 = L.fd_N = 0;
   for (int k = 0; k < L.K; ++k) {
     PatchDev &pt = L.pd[k];
-    int nx = pt.n[0], mx = pt.n[0] - 2, my = pt.n[1] - 2;
-    double *Qx = qtab[pt.nel[0]].first, *Qy = qtab[pt.nel[1]].first;
-    double *lx = qtab[pt.nel[0]].second, *ly = qtab[pt.nel[1]].second;
-    double *S1 = s1 + so, *S2 = s2 + so;
+    const int nx = pt.n[0], mx = pt.n[0] - 2, my = pt.n[1] - 2;
+    const QT &qx = qtab[pt.nel[0]], &qy = qtab[pt.nel[1]];
+    double *Wk = wbuf + so;
     so += (size_t)mx * my;
     double *rin = L.r + pt.off + nx + 1;
     double *uin = L.u + pt.off + nx + 1;
@@ -682,25 +698,20 @@ static void build_scms(Context &c, LevelData &L) {
     pt.sigma = 1.0 / (c.opt.scaling_delta * h * h);
     double gamma = std::pow(c.measure[k], (c.d - 2.0) / c.d);
     pt.scms_scale = c.opt.damping_tau / gamma;
-    GemmItem a{};
-    // 1) S1 = R Qx
-    a = GemmItem{rin, Qx, S1, my, mx, mx, nx, 1, mx, 1, mx, 1, nullptr, nullptr, 0.0, 0.0};
-    st[0].push_back(a);
-    // 2) S2 = Qy^T S1 ./ (sigma + ly + lx)
-    a = GemmItem{Qy, S1, S2, my, mx, my, 1, my, mx, 1, mx, 1, ly, lx, pt.sigma, 0.0};
-    st[1].push_back(a);
-    // 3) S1 = S2 Qx^T
-    a = GemmItem{S2, Qx, S1, my, mx, mx, mx, 1, 1, mx, mx, 1, nullptr, nullptr, 0.0, 0.0};
-    st[2].push_back(a);
-    // 4) U += scale * Qy S1
-    a = GemmItem{Qy, S1, uin, my, mx, my, my, 1, mx, 1, nx, 1, nullptr, nullptr, 0.0,
-                 pt.scms_scale};
-    st[3].push_back(a);
-    L.gemm_maxM = std::max(L.gemm_maxM, my);
-    L.gemm_maxN = std::max(L.gemm_maxN, mx);
+    // forward: W = (Qy^T R) Qx ./ (sigma + lam_y + lam_x)
+    fa.push_back(Fd2Item{qy.QT, rin, qx.Q, Wk, my, nx, mx, mx, my, my, mx, qy.lam, qx.lam,
+                         pt.sigma, 0.0});
+    // backward: U += scale (Qy W) Qx^T
+    fb.push_back(Fd2Item{qy.Q, Wk, qx.QT, uin, my, mx, mx, nx, my, my, mx, nullptr, nullptr, 0.0,
+                         pt.scms_scale});
+    L.fd_rows = std::max(L.fd_rows, my);
+    L.fd_K1 = std::max(L.fd_K1, my);
+    L.fd_N = std::max(L.fd_N, mx);
   }
-  L.n_gemm = L.K;
-  for (int s = 0; s < 4; ++s) L.d_gemm[s] = c.arena.upload(st[s], c.stream);
+  if (L.fd_N > 320 || L.fd_K1 > 320) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
+  L.n_fd = L.K;
+  L.d_fd[0] = c.arena.upload(fa, c.stream);
+  L.d_fd[1] = c.arena.upload(fb, c.stream);
 }
 
 static void build_gs(Context &c, LevelData &L) {
@@ -1054,7 +1065,7 @@ void kernel_model(const Context &c, const std::string &fam, int level, double *b
     if (launches == 0) launches = 1;
     *bytes = (nt * (8.0 * S + 8.0 * 4 + 4.0) + ncross * 20.0) / launches;
     *flops = (2.0 * S * nt + 2.0 * ncross) / launches;
-  } else if (fam == "scms_gemm") {
+  } else if (fam == "scms") {
     for (int k = 0; k < c.K; ++k) {
       double mx = L.pd[k].n[0] - 2, my = L.pd[k].n[1] - 2;
       *flops += 2.0 * (mx * my * mx + my * my * mx + my * mx * mx + my * my * mx);
