@@ -63,13 +63,11 @@ static void mg(Context &c, int l) {
   const int reps = (l == 1) ? 1 : c.opt.mu;
   for (int rep = 0; rep < reps; ++rep) {
     residual(c, l, L.u, L.f, L.r);
-    k_restrict(c, L, C, L.r, C.f);
-    if (l == 1) {
+    k_restrict(c, L, C, L.r, C.f, l == 1 ? nullptr : C.u);
+    if (l == 1)
       k_coarse_solve(c, C.f, C.u);
-    } else {
-      k_fill(C.u, 0.0, C.Ntorn, c.stream);
+    else
       mg(c, l - 1);
-    }
     k_prolong_add(c, L, C, C.u, L.u);
   }
   // post-smoothing
@@ -83,13 +81,18 @@ static void mg(Context &c, int l) {
 
 void vcycle_torn(Context &c, int l) { mg(c, l); }
 
-// z = MG(L, r, 0) on the finest level
-static void precondition(Context &c, const double *r, double *z) {
+// z = MG(L, r, 0) on the finest level.  z is the finest level's iterate L.u
+// (c.z aliases it); it must be zero on entry.  In the SIPG space the
+// distributed right-hand side equals r itself, so the cycle reads r directly.
+static void precondition(Context &c, double *r) {
   LevelData &L = c.lv.back();
-  k_copy_weighted(r, L.d_weight, L.f, L.Ntorn, c.stream);
-  k_fill(L.u, 0.0, L.Ntorn, c.stream);
+  double *f_saved = L.f;
+  if (L.n_glue > 0)
+    k_copy_weighted(r, L.d_weight, L.f, L.Ntorn, c.stream);
+  else
+    L.f = r;
   mg(c, (int)c.lv.size() - 1);
-  HIPCHK(hipMemcpyAsync(z, L.u, L.Ntorn * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+  L.f = f_saved;
 }
 
 static double read_scalar(Context &c, int slot) {
@@ -135,7 +138,8 @@ int solve_compact(Context &c, const double *rhs, double *u, double tol, int maxi
         if (res <= tol) break;
       }
     } else {
-      precondition(c, c.rr, c.z);
+      k_fill(c.z, 0.0, nt, c.stream);
+      precondition(c, c.rr);
       k_dot(c, c.rr, c.z, nt, S_RZ, 0);
       HIPCHK(hipMemcpyAsync(c.pp, c.z, nt * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
       for (it = 1; it <= maxit; ++it) {
@@ -145,7 +149,7 @@ int solve_compact(Context &c, const double *rhs, double *u, double tol, int maxi
         res = std::sqrt(read_scalar(c, S_RR)) / nf;
         if (info && info->history) info->history[it] = res;
         if (res <= tol) break;
-        precondition(c, c.rr, c.z);
+        precondition(c, c.rr);                          // z zeroed by the update above
         k_dot(c, c.rr, c.z, nt, S_RZNEW, 2);            // beta = rz_new / rz
         k_pcg_update_p(c, nt);                          // p = z + beta p
       }

@@ -27,7 +27,9 @@ void k_scms_interior(Context &c, LevelData &L);
 void k_pieces(Context &c, LevelData &L, const double *r, double *u);
 
 // transfer between level l (fine) and l-1 (coarse)
-void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc);
+// rc = P^T (w rf); if uc_zero != null it is set to zero (coarse initial guess)
+void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc,
+                double *uc_zero);
 void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, double *uf);
 void k_coarse_solve(Context &c, const double *f0, double *u0);
 
@@ -40,6 +42,7 @@ void k_gather_compact(const double *xt, long long N, const int *cp, const int *c
 // deterministic reductions and PCG updates (device scalars in c.d_scal)
 enum Scalar { S_RZ = 0, S_PQ, S_RR, S_RZNEW, S_FF, S_ALPHA, S_BETA, S_TMP, S_COUNT };
 void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode);
+// x += alpha p, r -= alpha q, ||r||^2 (weighted); also zeroes the cycle iterate z
 void k_pcg_update_xr(Context &c, long long n);
 void k_pcg_update_p(Context &c, long long n);
 void k_axpy(double a, const double *x, double *y, long long n, hipStream_t s);

@@ -73,6 +73,23 @@ __device__ inline double row16_scan(double v) {
   return v;
 }
 
+// same scan with bound_ctrl (lanes without a source read 0): no zero moves
+template <int CTRL>
+__device__ inline double dpp_move_bc(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+  int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double row16_scan_fast(double v) {
+  v += dpp_move_bc<0x111>(v);
+  v += dpp_move_bc<0x112>(v);
+  v += dpp_move_bc<0x114>(v);
+  v += dpp_move_bc<0x118>(v);
+  return v;
+}
+
 __device__ inline double readlane_d(double v, int lane) {
   long long b = __double_as_longlong(v);
   int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
@@ -116,10 +133,15 @@ __global__ void stencil_kernel(const PatchDev *pd, int K, const double *tabB, co
   const int S1 = 2 * p + 1;
   int S = 1;
   for (int d = 0; d < D; ++d) S *= S1;
+  const int SP = (S + 15) / 16 * 16;  // rows padded to whole 16-lane groups
   long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (tid >= ntorn * S) return;
-  long long t = tid / S;
-  int o = (int)(tid % S);
+  if (tid >= ntorn * SP) return;
+  long long t = tid / SP;
+  int o = (int)(tid % SP);
+  if (o >= S) {
+    st[tid] = 0.0;
+    return;
+  }
   int k = 0;
   while (k + 1 < K && pd[k + 1].off <= t) ++k;
   const PatchDev &pt = pd[k];
@@ -419,7 +441,7 @@ __global__ __launch_bounds__(256) void gs2d_kernel(const GsTile *tiles, const Pa
         ix = fx + (row % cxn) * Q1;
         iy = fy + (row / cxn) * Q1;
         t = off + (long long)iy * nx + ix;
-        const double *srow = st + t * S;
+        const double *srow = st + t * ((S + 15) / 16 * 16);
         for (int o = lane; o < S; o += G) {
           int oy = o / S1 - P, ox = o % S1 - P;
           acc += srow[o] * sU[(iy + oy - wy0) * W + (ix + ox - wx0)];
@@ -442,8 +464,11 @@ __global__ __launch_bounds__(256) void gs2d_kernel(const GsTile *tiles, const Pa
 
 // One wavefront per tile (T = 2(p+1)): the four unknowns of a colour class
 // are updated by four groups of 16 lanes; the row sum of each group comes out
-// of a DPP scan in its last lane, so no barrier between wavefronts is needed.
-// Stencil rows of the next D classes are prefetched into registers.
+// of a DPP scan in its last lane.  A single wavefront executes its LDS
+// operations in program order, so a class reads the values the previous
+// class wrote without a barrier.  Stencil rows of the next D classes are
+// prefetched into registers; f minus the cross-patch couplings and 1/a_ii
+// sit in LDS as one 16-byte pair per unknown.
 template <int P>
 __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, const PatchDev *pd,
                                                        const double *__restrict__ st,
@@ -457,12 +482,12 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
   constexpr int Q1 = P + 1, T = 2 * Q1, W = T + 2 * P;
   constexpr int S1 = 2 * P + 1, S = S1 * S1;
   constexpr int C = (S + 15) / 16;
+  constexpr int SP = 16 * C;  // padded row length (zero coefficients beyond S)
   constexpr int NPH = Q1 * Q1;
   constexpr int D0 = 48 / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
   __shared__ double sU[W * W];
-  __shared__ double sB[T * T];
-  __shared__ double sI[T * T];
+  __shared__ double2 sBD[T * T];
   __shared__ int sOff[C * 16];
   const GsTile tl = tiles[blockIdx.x];
   const PatchDev &pt = pd[tl.patch];
@@ -486,31 +511,46 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
         di = invd[t];
       }
     }
-    sB[i] = b;
-    sI[i] = di;
+    sBD[i] = make_double2(b, di);
   }
-  // LDS offset of stencil slot o relative to the row's own window position
   for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
   __syncthreads();
-  for (int e = tl.cx_off + lane; e < tl.cx_off + tl.cx_n; e += 64)
-    unsafeAtomicAdd(&sB[cx_li[e]], -cx_val[e] * u[cx_col[e]]);
-  double buf[D][C];
+  // cross-patch couplings: batches of 8 entries per lane, all loads in flight
+  for (int base = 0; base < tl.cx_n; base += 64 * 8) {
+    int cl[8], cc[8];
+    double cv[8], cu[8];
 #pragma unroll
-  for (int s = 0; s < D; ++s) {
+    for (int j = 0; j < 8; ++j) {
+      const int e = base + lane + 64 * j;
+      const bool ok = e < tl.cx_n;
+      cl[j] = ok ? cx_li[tl.cx_off + e] : -1;
+      cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
+      cv[j] = ok ? cx_val[tl.cx_off + e] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cu[j] = u[cc[j]];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (cl[j] >= 0) unsafeAtomicAdd(&sBD[cl[j]].x, -cv[j] * cu[j]);
+  }
+  // row of this lane's group in class s; rows outside the patch read the
+  // tile origin (always inside) and are not updated
+  auto row_ptr = [&](int s) {
     const int ph = backward ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
     const bool ok = ix < nx && iy < ny;
-    const double *srow = st + (off + (long long)iy * nx + ix) * S;
+    const long long t = ok ? off + (long long)iy * nx + ix : off + (long long)y0 * nx + x0;
+    return st + t * SP + l16;
+  };
+  double buf[D][C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int o = l16 + 16 * c;
-      buf[s][c] = (ok && o < S) ? srow[o] : 0.0;
-    }
+  for (int s = 0; s < D; ++s) {
+    const double *srow = row_ptr(s);
+#pragma unroll
+    for (int c = 0; c < C; ++c) buf[s][c] = srow[16 * c];
   }
-  int soff[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) soff[c] = 0;
   __syncthreads();
+  int soff[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) soff[c] = sOff[l16 + 16 * c];
 #pragma unroll
@@ -518,29 +558,29 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
     const int ph = backward ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
     const int wi = (iy - wy0) * W + (ix - wx0);
+    const int li = (iy - y0) * T + (ix - x0);
+    double uv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) uv[c] = sU[wi + soff[c]];
+    const double uold = sU[wi];
+    const double2 bd = sBD[li];
+    // u + (b - a.u) d, split so that the LDS reads are consumed before the scan
+    double ubd = fma(bd.x, bd.y, uold);
+    asm volatile("" : "+v"(ubd));  // keep these reads in the batch of this class
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc += buf[s % D][c] * sU[wi + soff[c]];
+    for (int c = 0; c < C; ++c) acc += buf[s % D][c] * uv[c];
     if (s + D < NPH) {
-      const int s2 = s + D;
-      const int ph2 = backward ? NPH - 1 - s2 : s2;
-      const int jx = x0 + ph2 % Q1 + ax, jy = y0 + ph2 / Q1 + ay;
-      const bool ok = jx < nx && jy < ny;
-      const double *srow = st + (off + (long long)jy * nx + jx) * S;
+      const double *srow = row_ptr(s + D);
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int o = l16 + 16 * c;
-        buf[s % D][c] = (ok && o < S) ? srow[o] : 0.0;
-      }
+      for (int c = 0; c < C; ++c) buf[s % D][c] = srow[16 * c];
     }
-    acc = row16_scan(acc);
-    if (l16 == 15 && ix < nx && iy < ny) {
-      const int li = (iy - y0) * T + (ix - x0);
-      const double di = sI[li];
-      if (di != 0.0) sU[wi] += (sB[li] - acc) * di;
-    }
-    __syncthreads();
+    acc = row16_scan_fast(acc);
+    if (l16 == 15 && ix < nx && iy < ny) sU[wi] = fma(-acc, bd.y, ubd);
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
   }
+  __syncthreads();
   for (int i = lane; i < T * T; i += 64) {
     int iy = y0 + i / T, ix = x0 + i % T;
     if (ix < nx && iy < ny) u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
@@ -720,9 +760,11 @@ __global__ __launch_bounds__(256) void restrict2d_kernel(const PatchDev *pf, con
                                                          int RW, const double *rf,
                                                          const double *wf,
                                                          const unsigned char *maskc,
-                                                         long long nc_tot, double *rc) {
+                                                         long long nc_tot, double *rc,
+                                                         double *uc_zero) {
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= nc_tot) return;
+  if (uc_zero) uc_zero[t] = 0.0;  // zero initial guess of the coarse cycle
   int k = 0;
   while (k + 1 < K && pc[k + 1].off <= t) ++k;
   const PatchDev &C = pc[k], &F = pf[k];
@@ -870,12 +912,14 @@ __global__ __launch_bounds__(256) void dot_final_kernel(const double *part, int 
 
 __global__ __launch_bounds__(256) void pcg_xr_kernel(double *x, double *r, const double *p,
                                                      const double *q, const double *w, long long n,
-                                                     const double *scal, double *part) {
+                                                     const double *scal, double *part,
+                                                     double *z_zero) {
   __shared__ double sh[256];
   const double alpha = scal[S_ALPHA];
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
+    z_zero[i] = 0.0;
     x[i] += alpha * p[i];
     double ri = r[i] - alpha * q[i];
     r[i] = ri;
@@ -910,7 +954,7 @@ void k_axpy(double a, const double *x, double *y, long long n, hipStream_t s) {
 void k_stencil_assemble(Context &c, LevelData &L) {
   int S = 1;
   for (int d = 0; d < c.d; ++d) S *= (2 * c.p + 1);
-  long long tot = L.Ntorn * S;
+  long long tot = L.Ntorn * ((S + 15) / 16 * 16);
   if (c.d == 2)
     stencil_kernel<2><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
                                                          L.Ntorn, L.d_stencil);
@@ -1051,12 +1095,13 @@ void k_pieces(Context &c, LevelData &L, const double *r, double *u) {
       c.opt.damping_tau);
 }
 
-void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc) {
+void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc,
+                double *uc_zero) {
   TimeScope ts(c, "restrict", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
   restrict2d_kernel<<<nblocks(C.Ntorn), BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_R_lo, F.d_R_val,
                                                            F.RW, rf, F.d_weight, C.d_mask, C.Ntorn,
-                                                           rc);
+                                                           rc, uc_zero);
 }
 
 void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, double *uf) {
@@ -1092,7 +1137,7 @@ void k_dot(Context &c, const double *a, const double *b, long long n, int slot, 
 void k_pcg_update_xr(Context &c, long long n) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   pcg_xr_kernel<<<RED_BLOCKS, 256, 0, c.stream>>>(c.x, c.rr, c.pp, c.qq, c.lv.back().d_weight, n,
-                                                  c.d_scal, c.d_red);
+                                                  c.d_scal, c.d_red, c.z);
   dot_final_kernel<<<1, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
 }
 

@@ -895,6 +895,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   const int S1 = 2 * c.p + 1;
   int S = 1;
   for (int g = 0; g < c.d; ++g) S *= S1;
+  const int SP = (S + 15) / 16 * 16;  // stencil rows padded to 16-lane groups
   int center = 0;
   for (int g = 0, m = 1; g < c.d; ++g, m *= S1) center += c.p * m;
   for (int l = 0; l < NL; ++l) {
@@ -986,7 +987,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     if (l >= 1) {
       build_transfer(c, L, c.lv[l - 1]);
       if (use_gs) {
-        L.d_stencil = c.arena.alloc<double>((size_t)L.Ntorn * S);
+        L.d_stencil = c.arena.alloc<double>((size_t)L.Ntorn * SP);
         L.d_invdiag = c.arena.alloc<double>(L.Ntorn);
         build_gs(c, L);
       }
@@ -1000,8 +1001,8 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       k_stencil_assemble(c, L);
       int *dr = c.arena.upload(srow, c.stream), *ds = c.arena.upload(sslot, c.stream);
       double *dv = c.arena.upload(sval, c.stream);
-      k_stencil_add(dr, ds, dv, (int)srow.size(), L.d_stencil, S, c.stream);
-      k_invdiag(L.d_stencil, S, center, L.d_mask, L.d_invdiag, L.Ntorn, c.stream);
+      k_stencil_add(dr, ds, dv, (int)srow.size(), L.d_stencil, SP, c.stream);
+      k_invdiag(L.d_stencil, SP, center, L.d_mask, L.d_invdiag, L.Ntorn, c.stream);
     }
   }
   // coarse level: dense inverse of A_0 (Cholesky based)
@@ -1020,11 +1021,11 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   const long long nt = LF.Ntorn;
   c.x = c.arena.alloc<double>(nt);
   c.rr = c.arena.alloc<double>(nt);
-  c.z = c.arena.alloc<double>(nt);
+  c.z = LF.u;  // the preconditioner output is the finest cycle iterate
   c.pp = c.arena.alloc<double>(nt);
   c.qq = c.arena.alloc<double>(nt);
   c.ff = c.arena.alloc<double>(nt);
-  for (double *v : {c.x, c.rr, c.z, c.pp, c.qq, c.ff}) k_fill(v, 0.0, nt, c.stream);
+  for (double *v : {c.x, c.rr, c.pp, c.qq, c.ff}) k_fill(v, 0.0, nt, c.stream);
   c.d_red = c.arena.alloc<double>(1024);
   c.d_scal = c.arena.alloc<double>(S_COUNT);
   k_fill(c.d_scal, 0.0, S_COUNT, c.stream);
@@ -1063,7 +1064,7 @@ void kernel_model(const Context &c, const std::string &fam, int level, double *b
     int launches = 0;
     for (const GsClass &cl : L.gs) launches += cl.count > 0;
     if (launches == 0) launches = 1;
-    *bytes = (nt * (8.0 * S + 8.0 * 4 + 4.0) + ncross * 20.0) / launches;
+    *bytes = (nt * (8.0 * ((S + 15) / 16 * 16) + 8.0 * 4 + 4.0) + ncross * 20.0) / launches;
     *flops = (2.0 * S * nt + 2.0 * ncross) / launches;
   } else if (fam == "scms") {
     for (int k = 0; k < c.K; ++k) {
