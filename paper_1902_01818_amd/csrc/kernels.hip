@@ -497,42 +497,55 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
   const long long off = pt.off;
   const int lane = threadIdx.x, grp = lane >> 4, l16 = lane & 15;
   const int ax = (grp & 1) * Q1, ay = (grp >> 1) * Q1;
-  for (int i = lane; i < W * W; i += 64) {
-    int gy = wy0 + i / W, gx = wx0 + i % W;
-    sU[i] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? u[off + (long long)gy * nx + gx] : 0.0;
+  // Prologue: every global load that does not depend on another one is issued
+  // before the first wait (u window, f, 1/a_ii -- zero on Dirichlet unknowns
+  // by construction -- and the cross-coupling lists); u at the cross columns
+  // follows in a second round.
+  constexpr int NW = (W * W + 63) / 64, NT = (T * T + 63) / 64;
+  double wv[NW], fv[NT], dv[NT];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int i = lane + 64 * j;
+    const int gy = wy0 + i / W, gx = wx0 + i % W;
+    const bool ok = i < W * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    wv[j] = ok ? u[off + (long long)gy * nx + gx] : 0.0;
   }
-  for (int i = lane; i < T * T; i += 64) {
-    int iy = y0 + i / T, ix = x0 + i % T;
-    double b = 0.0, di = 0.0;
-    if (ix < nx && iy < ny) {
-      long long t = off + (long long)iy * nx + ix;
-      if (mask[t]) {
-        b = f[t];
-        di = invd[t];
-      }
-    }
-    sBD[i] = make_double2(b, di);
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int i = lane + 64 * j;
+    const int iy = y0 + i / T, ix = x0 + i % T;
+    const bool ok = i < T * T && ix < nx && iy < ny;
+    const long long t = off + (long long)iy * nx + ix;
+    fv[j] = ok ? f[t] : 0.0;
+    dv[j] = ok ? invd[t] : 0.0;
   }
+  const int ncx = tl.cx_n < 64 * 8 ? tl.cx_n : 64 * 8;
+  int cl[8], cc[8];
+  double cv[8], cu[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = lane + 64 * j;
+    const bool ok = e < ncx;
+    cl[j] = ok ? cx_li[tl.cx_off + e] : -1;
+    cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
+    cv[j] = ok ? cx_val[tl.cx_off + e] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) cu[j] = u[cc[j]];
+#pragma unroll
+  for (int j = 0; j < NW; ++j)
+    if (lane + 64 * j < W * W) sU[lane + 64 * j] = wv[j];
+#pragma unroll
+  for (int j = 0; j < NT; ++j)
+    if (lane + 64 * j < T * T) sBD[lane + 64 * j] = make_double2(fv[j], dv[j]);
   for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
   __syncthreads();
-  // cross-patch couplings: batches of 8 entries per lane, all loads in flight
-  for (int base = 0; base < tl.cx_n; base += 64 * 8) {
-    int cl[8], cc[8];
-    double cv[8], cu[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int e = base + lane + 64 * j;
-      const bool ok = e < tl.cx_n;
-      cl[j] = ok ? cx_li[tl.cx_off + e] : -1;
-      cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
-      cv[j] = ok ? cx_val[tl.cx_off + e] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) cu[j] = u[cc[j]];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (cl[j] >= 0) unsafeAtomicAdd(&sBD[cl[j]].x, -cv[j] * cu[j]);
-  }
+  for (int j = 0; j < 8; ++j)
+    if (cl[j] >= 0) unsafeAtomicAdd(&sBD[cl[j]].x, -cv[j] * cu[j]);
+  // tiles with more than 512 cross couplings (not produced by the layouts here)
+  for (int e = 64 * 8 + lane; e < tl.cx_n; e += 64)
+    unsafeAtomicAdd(&sBD[cx_li[tl.cx_off + e]].x, -cx_val[tl.cx_off + e] * u[cx_col[tl.cx_off + e]]);
   // row of this lane's group in class s; rows outside the patch read the
   // tile origin (always inside) and are not updated
   auto row_ptr = [&](int s) {
