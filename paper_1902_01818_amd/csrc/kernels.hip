@@ -335,10 +335,19 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
       int ex = gx / Q;
       int qx = gx - ex * Q, qy = gy - ey * Q;
       double xh[2] = {((double)(ex0 + ex) + gr.x[qx]) * hx, ((double)(ey0 + ey) + gr.x[qy]) * hy};
-      double G[2][2];
-      metric<2>(sC, xh, gr.w[qx] * hx * gr.w[qy] * hy, G);
-      v0 = G[0][0] * ux + G[0][1] * uy;
-      v1 = G[1][0] * ux + G[1][1] * uy;
+      // metric w |det J| J^-1 J^-T = (w / |det J|) adj(J) adj(J)^T: one division
+      const double ex_ = xh[0], ey_ = xh[1];
+      const double j00 = (1.0 - ey_) * (sC[1][0] - sC[0][0]) + ey_ * (sC[3][0] - sC[2][0]);
+      const double j10 = (1.0 - ey_) * (sC[1][1] - sC[0][1]) + ey_ * (sC[3][1] - sC[2][1]);
+      const double j01 = (1.0 - ex_) * (sC[2][0] - sC[0][0]) + ex_ * (sC[3][0] - sC[1][0]);
+      const double j11 = (1.0 - ex_) * (sC[2][1] - sC[0][1]) + ex_ * (sC[3][1] - sC[1][1]);
+      const double det = j00 * j11 - j01 * j10;
+      const double sc = gr.w[qx] * hx * gr.w[qy] * hy / fabs(det);
+      const double g00 = sc * (j11 * j11 + j01 * j01);
+      const double g01 = -sc * (j11 * j10 + j01 * j00);
+      const double g11 = sc * (j10 * j10 + j00 * j00);
+      v0 = g00 * ux + g01 * uy;
+      v1 = g01 * ux + g11 * uy;
     }
     sV0[i] = v0;
     sV1[i] = v1;
@@ -607,11 +616,17 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
 // next chunk held in registers while the current one is used.
 // ---------------------------------------------------------------------------
 template <int NJ>
+struct FdShape {
+  static constexpr int WB = 64 * NJ;                          // LDS row length of a chunk
+  static constexpr int KC = NJ == 1 ? 64 : (NJ == 2 ? 32 : (NJ <= 4 ? 16 : 8));  // rows per chunk
+  static constexpr int LPT = KC * WB / 256;                   // chunk loads per thread
+};
+
+template <int NJ>
 __device__ inline void rowblock_product(const double *A, int lda, const double *__restrict__ B,
                                         long long b_r, int K, int N, double *sM,
                                         double acc[4][NJ]) {
-  constexpr int WB = 64 * NJ;      // LDS row length of a chunk
-  constexpr int LPT = 2 * NJ;      // 8 * WB / 256 loads per thread
+  constexpr int WB = FdShape<NJ>::WB, KC = FdShape<NJ>::KC, LPT = FdShape<NJ>::LPT;
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
   double pre[LPT];
   auto gload = [&](int k0) {
@@ -623,26 +638,26 @@ __device__ inline void rowblock_product(const double *A, int lda, const double *
     }
   };
   gload(0);
-  for (int k0 = 0; k0 < K; k0 += 8) {
+  for (int k0 = 0; k0 < K; k0 += KC) {
     __syncthreads();
 #pragma unroll
-    for (int x = 0; x < LPT; ++x) {
-      const int e = tid + 256 * x;
-      sM[(e / WB) * WB + e % WB] = pre[x];
-    }
+    for (int x = 0; x < LPT; ++x) sM[tid + 256 * x] = pre[x];
     __syncthreads();
-    if (k0 + 8 < K) gload(k0 + 8);
+    if (k0 + KC < K) gload(k0 + KC);
+    const int kend = min(KC, ((K - k0) + 7) / 8 * 8);
+    for (int kk = 0; kk < kend; kk += 8) {
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      double a[4], b[NJ];
+      for (int k2 = 0; k2 < 8; ++k2) {
+        double a[4], b[NJ];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk];
+        for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk + k2];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
+        for (int j = 0; j < NJ; ++j) b[j] = sM[(kk + k2) * WB + cg + 64 * j];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
+          for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
+      }
     }
   }
 }
@@ -650,14 +665,15 @@ __device__ inline void rowblock_product(const double *A, int lda, const double *
 template <int NJ>
 __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pad) {
   constexpr int WB = 64 * NJ;
+  constexpr int KC = FdShape<NJ>::KC;
   extern __shared__ double sm[];
   const Fd2Item it = items[blockIdx.y];
   const int i0 = blockIdx.x * 16;
   if (i0 >= it.rows) return;
-  double *sL = sm;                 // 16 x (K1pad + 8), zero padded
-  double *sZ = sL + 16 * (K1pad + 8);  // 16 x WB
-  double *sM = sZ + 16 * WB;       // 8 x WB
-  const int lda = K1pad + 8;
+  const int lda = (K1pad + KC - 1) / KC * KC + KC;  // zero padded past K1
+  double *sL = sm;                 // 16 x lda
+  double *sZ = sL + 16 * lda;      // 16 x (WB + KC), zero padded past N
+  double *sM = sZ + 16 * (WB + KC);  // KC x WB
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
   const int nrow = min(16, it.rows - i0);
   for (int e = tid; e < 16 * lda; e += 256) {
@@ -670,14 +686,15 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pa
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[r][j] = 0.0;
   rowblock_product<NJ>(sL, lda, it.M1, it.m1_r, it.K1, it.N, sM, acc);
+  for (int e = tid; e < 16 * KC; e += 256) sZ[(e / KC) * (WB + KC) + WB + e % KC] = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      sZ[(4 * rg + r) * WB + cg + 64 * j] = acc[r][j];
+      sZ[(4 * rg + r) * (WB + KC) + cg + 64 * j] = acc[r][j];
       acc[r][j] = 0.0;
     }
-  rowblock_product<NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
+  rowblock_product<NJ>(sZ, WB + KC, it.M2, it.m2_r, it.N, it.N, sM, acc);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = 4 * rg + r;
@@ -1077,8 +1094,9 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward) {
 
 template <int NJ>
 static void launch_fd2(Context &c, LevelData &L, int stage) {
-  constexpr int WB = 64 * NJ;
-  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + 8 * WB) * sizeof(double);
+  constexpr int WB = FdShape<NJ>::WB, KC = FdShape<NJ>::KC;
+  const int lda = (L.fd_K1 + KC - 1) / KC * KC + KC;
+  const size_t lds = (size_t)(16 * lda + 16 * (WB + KC) + KC * WB) * sizeof(double);
   dim3 grid((L.fd_rows + 15) / 16, L.n_fd);
   fd2_kernel<NJ><<<grid, 256, lds, c.stream>>>(L.d_fd[stage], L.fd_K1);
 }
