@@ -616,17 +616,11 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
 // next chunk held in registers while the current one is used.
 // ---------------------------------------------------------------------------
 template <int NJ>
-struct FdShape {
-  static constexpr int WB = 64 * NJ;                          // LDS row length of a chunk
-  static constexpr int KC = NJ == 1 ? 64 : (NJ == 2 ? 32 : (NJ <= 4 ? 16 : 8));  // rows per chunk
-  static constexpr int LPT = KC * WB / 256;                   // chunk loads per thread
-};
-
-template <int NJ>
 __device__ inline void rowblock_product(const double *A, int lda, const double *__restrict__ B,
                                         long long b_r, int K, int N, double *sM,
                                         double acc[4][NJ]) {
-  constexpr int WB = FdShape<NJ>::WB, KC = FdShape<NJ>::KC, LPT = FdShape<NJ>::LPT;
+  constexpr int WB = 64 * NJ;      // LDS row length of a chunk
+  constexpr int LPT = 2 * NJ;      // 8 * WB / 256 loads per thread
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
   double pre[LPT];
   auto gload = [&](int k0) {
@@ -638,26 +632,26 @@ __device__ inline void rowblock_product(const double *A, int lda, const double *
     }
   };
   gload(0);
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  for (int k0 = 0; k0 < K; k0 += 8) {
     __syncthreads();
 #pragma unroll
-    for (int x = 0; x < LPT; ++x) sM[tid + 256 * x] = pre[x];
+    for (int x = 0; x < LPT; ++x) {
+      const int e = tid + 256 * x;
+      sM[(e / WB) * WB + e % WB] = pre[x];
+    }
     __syncthreads();
-    if (k0 + KC < K) gload(k0 + KC);
-    const int kend = min(KC, ((K - k0) + 7) / 8 * 8);
-    for (int kk = 0; kk < kend; kk += 8) {
+    if (k0 + 8 < K) gload(k0 + 8);
 #pragma unroll
-      for (int k2 = 0; k2 < 8; ++k2) {
-        double a[4], b[NJ];
+    for (int kk = 0; kk < 8; ++kk) {
+      double a[4], b[NJ];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk + k2];
+      for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) b[j] = sM[(kk + k2) * WB + cg + 64 * j];
+      for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
-      }
+        for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
     }
   }
 }
@@ -665,15 +659,14 @@ __device__ inline void rowblock_product(const double *A, int lda, const double *
 template <int NJ>
 __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pad) {
   constexpr int WB = 64 * NJ;
-  constexpr int KC = FdShape<NJ>::KC;
   extern __shared__ double sm[];
   const Fd2Item it = items[blockIdx.y];
   const int i0 = blockIdx.x * 16;
   if (i0 >= it.rows) return;
-  const int lda = (K1pad + KC - 1) / KC * KC + KC;  // zero padded past K1
-  double *sL = sm;                 // 16 x lda
-  double *sZ = sL + 16 * lda;      // 16 x (WB + KC), zero padded past N
-  double *sM = sZ + 16 * (WB + KC);  // KC x WB
+  double *sL = sm;                 // 16 x (K1pad + 8), zero padded
+  double *sZ = sL + 16 * (K1pad + 8);  // 16 x WB
+  double *sM = sZ + 16 * WB;       // 8 x WB
+  const int lda = K1pad + 8;
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
   const int nrow = min(16, it.rows - i0);
   for (int e = tid; e < 16 * lda; e += 256) {
@@ -686,15 +679,14 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pa
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[r][j] = 0.0;
   rowblock_product<NJ>(sL, lda, it.M1, it.m1_r, it.K1, it.N, sM, acc);
-  for (int e = tid; e < 16 * KC; e += 256) sZ[(e / KC) * (WB + KC) + WB + e % KC] = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      sZ[(4 * rg + r) * (WB + KC) + cg + 64 * j] = acc[r][j];
+      sZ[(4 * rg + r) * WB + cg + 64 * j] = acc[r][j];
       acc[r][j] = 0.0;
     }
-  rowblock_product<NJ>(sZ, WB + KC, it.M2, it.m2_r, it.N, it.N, sM, acc);
+  rowblock_product<NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = 4 * rg + r;
@@ -1094,9 +1086,8 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward) {
 
 template <int NJ>
 static void launch_fd2(Context &c, LevelData &L, int stage) {
-  constexpr int WB = FdShape<NJ>::WB, KC = FdShape<NJ>::KC;
-  const int lda = (L.fd_K1 + KC - 1) / KC * KC + KC;
-  const size_t lds = (size_t)(16 * lda + 16 * (WB + KC) + KC * WB) * sizeof(double);
+  constexpr int WB = 64 * NJ;
+  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + 8 * WB) * sizeof(double);
   dim3 grid((L.fd_rows + 15) / 16, L.n_fd);
   fd2_kernel<NJ><<<grid, 256, lds, c.stream>>>(L.d_fd[stage], L.fd_K1);
 }
