@@ -27,6 +27,22 @@ sys.path.insert(0, ROOT)
 PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}   # GB/s, TFLOP/s (MI355X)
 
 
+KERNEL_OF_FAMILY = {"gauss_seidel": "gs2d_wave_kernel", "vol_apply": "vol2d_kernel",
+                    "scms": "fd2_kernel", "iface_apply": "iface_kernel"}
+
+
+def source_hash(family="gauss_seidel"):
+    """Hash of the device source of the family's kernel (its definition in
+    kernels.hip): counter-based traffic figures are valid only for the kernel
+    they were measured on."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1902_01818_amd", "csrc", "kernels.hip")).read()
+    name = KERNEL_OF_FAMILY[family]
+    i = src.index("void %s(" % name)
+    j = src.index("\n}\n", i)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()[:16]
+
+
 def cpu_baseline(cfg, f, its_gpu, budget_s=15.0):
     """Oracle (plain FP64 CPU reference) on the same workload: setup excluded
     (as on the GPU), full PCG solves repeated until budget_s of CPU work."""
@@ -61,6 +77,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed region, copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -152,6 +170,20 @@ def main():
                    "true_rel_residual": infos[-1]["true_rel_residual"], "all_converged": ok},
         "roofline": roof,
     }
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = n * 8
+    traffic_file = os.path.join(ROOT, "profiles", "traffic_%s_c2_fp64.json" % family)
+    if os.path.exists(traffic_file):
+        with open(traffic_file) as fh:
+            tr = json.load(fh)
+        # counters taken on the same kernel source and workload (checked by hash)
+        if tr.get("source_hash") == source_hash(family) and tr.get("traffic_bytes"):
+            roof["traffic"] = tr["traffic_bytes"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, f_host, its)
     print(json.dumps(line))

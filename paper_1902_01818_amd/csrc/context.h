@@ -146,7 +146,7 @@ struct Context {
   std::string timing_filter;  // time only families whose key starts with this
 
   void launch_begin(const char *fam, hipEvent_t *b, hipEvent_t *e);
-  void launch_end(const char *fam, hipEvent_t b, hipEvent_t e);
+  void launch_end(const char *fam, hipEvent_t b, hipEvent_t e, int launches = 1);
   ~Context();
 };
 

@@ -47,8 +47,9 @@ struct TimeScope {
     if (on) c.launch_begin(key.c_str(), &b, &e);
   }
   ~TimeScope() {
-    if (on) c.launch_end(key.c_str(), b, e);
+    if (on) c.launch_end(key.c_str(), b, e, n);
   }
+  int n = 1;  // kernel launches covered by this event pair
 };
 
 __device__ inline void atomic_add(double *a, double v) { unsafeAtomicAdd(a, v); }
@@ -1065,11 +1066,14 @@ static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backwa
 }
 
 void k_gs_sweep(Context &c, LevelData &L, bool backward) {
+  // one event pair around the sweep (its class launches run back to back)
+  TimeScope ts(c, "gauss_seidel", L.l);
+  ts.n = 0;
   int nc = (int)L.gs.size();
   for (int ii = 0; ii < nc; ++ii) {
     const GsClass &cl = L.gs[backward ? nc - 1 - ii : ii];
     if (cl.count == 0) continue;
-    TimeScope ts(c, "gauss_seidel", L.l);
+    ++ts.n;
     switch (c.p) {
       case 1: launch_gs2d<1>(c, L, cl, backward); break;
       case 2: launch_gs2d<2>(c, L, cl, backward); break;

@@ -39,11 +39,11 @@ void Context::launch_begin(const char *fam, hipEvent_t *b, hipEvent_t *e) {
   HIPCHK(hipEventRecord(*b, stream));
 }
 
-void Context::launch_end(const char *fam, hipEvent_t b, hipEvent_t e) {
+void Context::launch_end(const char *fam, hipEvent_t b, hipEvent_t e, int launches) {
   TimerFamily &t = timers[fam];
   HIPCHK(hipEventRecord(e, stream));
   t.pending.push_back({b, e});
-  t.launches += 1;
+  t.launches += launches;
   if (t.pending.size() > 256) {  // bound the number of outstanding events
     HIPCHK(hipEventSynchronize(e));
     for (auto &pe : t.pending) {
