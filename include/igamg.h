@@ -54,10 +54,17 @@ extern "C" {
 #define IGAMG_SMOOTHER_HYBRID 0
 #define IGAMG_SMOOTHER_SCMS 1
 #define IGAMG_SMOOTHER_GS 2
-/* arithmetic of the cycle (the outer iteration is always float64) */
+/* Arithmetic of the cycle.  The outer iteration, its residuals, the
+ * convergence test and the coarsest-level solve are float64 always; with
+ * IGAMG_FP32 every other kernel of the cycle stores and computes in float32
+ * (operator data rounded once at setup), i.e. the cycle is a float32
+ * preconditioner inside a float64 Krylov iteration (an extension beyond the
+ * paper, which computes in float64 throughout). */
 #define IGAMG_FP64 0
 #define IGAMG_FP32 1
-/* outer iteration: PCG (Section 4), multigrid as solver (Section 4, "-i d") */
+/* Outer iteration: PCG preconditioned by one cycle (Section 4); the cycle
+ * used directly as the solver (Section 4); flexible CG (Polak-Ribiere beta,
+ * robust to a preconditioner that is not exactly symmetric, e.g. float32). */
 #define IGAMG_OUTER_PCG 0
 #define IGAMG_OUTER_MG 1
 #define IGAMG_OUTER_FCG 2
@@ -86,6 +93,8 @@ typedef struct {
   int gs_tile;        /* Gauss-Seidel tile width T >= p of the colour ordering, 0 = 2(p+1) */
   int coarse_min;     /* halve element counts while all are even and their half >= coarse_min; 0 = 2 */
   int timing;         /* 1 = record per-kernel-family event timings (igamg_kernel_stats) */
+  int max_rhs;        /* right-hand sides processed together by one call (work-vector
+                         capacity, 0 = 1); larger nrhs are split into batches of max_rhs */
 } igamg_options;
 
 typedef struct {
@@ -98,7 +107,8 @@ typedef struct {
 
 typedef struct igamg_ctx igamg_ctx;
 
-/* Fill *o with the defaults (SIPG, hybrid, V(1,1), tau 0.25, delta 0.1, FP64, PCG). */
+/* Fill *o with the defaults (SIPG, hybrid, V(1,1), tau 0.25, delta 0.1, FP64, PCG,
+ * one right-hand side per batch). */
 void igamg_default_options(igamg_options *o);
 
 /* Host only, no GPU work: device bytes igamg_setup will allocate for this
@@ -129,15 +139,22 @@ int igamg_num_levels(const igamg_ctx *ctx, int *levels);
 int igamg_apply(igamg_ctx *ctx, const double *x, double *y, int nrhs, void *stream);
 
 /* One multigrid cycle u <- MG(L, f, u) (Algorithm 1 or 2 per options), u
- * in/out, f in; device [nrhs][N]; internal arithmetic per o->precision. */
+ * in/out, f in; device [nrhs][N]; internal arithmetic per o->precision.
+ * Right-hand sides go through the cycle max_rhs at a time (one launch per
+ * kernel and batch). */
 int igamg_vcycle(igamg_ctx *ctx, const double *f, double *u, int nrhs, void *stream);
 
 /* Solve A_L u = rhs until ||rhs - A u|| / ||rhs|| <= tol (Section 4) with the
- * outer iteration of the options (PCG preconditioned by one cycle, or the cycle
- * used directly).  u: device in/out (initial guess used if use_initial_guess,
- * else zero).  info: host array [nrhs] or NULL.  Synchronizes `stream` once
- * per outer iteration (convergence test).  Returns IGAMG_ENOCONV if a
- * right-hand side missed tol within maxit; u then holds the last iterate. */
+ * outer iteration of the options (PCG or flexible CG preconditioned by one
+ * cycle, or the cycle used directly); the residual tested is the float64
+ * recurrence residual of the outer iteration.  u: device in/out (initial
+ * guess used if use_initial_guess, else zero).  info: host array [nrhs] or
+ * NULL (iterations = the iteration at which that right-hand side met tol).
+ * Right-hand sides are solved max_rhs at a time, each with its own scalars;
+ * a converged one is frozen while the rest of its batch iterates.
+ * Synchronizes `stream` once per outer iteration (convergence test).
+ * Returns IGAMG_ENOCONV if a right-hand side missed tol within maxit; u then
+ * holds its last iterate. */
 int igamg_solve(igamg_ctx *ctx, const double *rhs, double *u, int nrhs, double tol,
                 int maxit, int use_initial_guess, igamg_solve_info *info, void *stream);
 

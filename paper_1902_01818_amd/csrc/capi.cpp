@@ -1,6 +1,7 @@
 // extern "C" boundary of the library (declarations and contracts: include/igamg.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -63,6 +64,7 @@ void igamg_default_options(igamg_options *o) {
   o->gs_tile = 0;
   o->coarse_min = 0;
   o->timing = 0;
+  o->max_rhs = 0;
 }
 
 int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o,
@@ -114,12 +116,15 @@ int igamg_apply(igamg_ctx *ctx, const double *x, double *y, int nrhs, void *stre
     igamg::Context &c = ctx->c;
     c.stream = (hipStream_t)stream;
     igamg::LevelData &L = c.lv.back();
-    const int top = (int)c.lv.size() - 1;
-    for (int j = 0; j < nrhs; ++j) {
-      igamg::k_fill(c.x, 0.0, L.Ntorn, c.stream);
-      igamg::k_scatter_compact(x + (size_t)j * L.N, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, c.stream);
-      igamg::apply_torn(c, top, c.x, nullptr, nullptr, c.qq, 1.0);
-      igamg::k_gather_compact(c.qq, L.N, c.d_fin_cp, c.d_fin_cidx, 0, y + (size_t)j * L.N, c.stream);
+    const long long nt = L.Ntorn;
+    for (int j0 = 0; j0 < nrhs; j0 += c.nb) {
+      const int nb = std::min(c.nb, nrhs - j0);
+      igamg::k_fill(c.x, 0.0, nt * nb, c.stream);
+      igamg::k_scatter_compact(x + (size_t)j0 * L.N, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, nt, nb,
+                               c.stream);
+      igamg::apply64(c, c.x, nullptr, nullptr, c.qq, 1.0, nb);
+      igamg::k_gather_compact(c.qq, L.N, c.d_fin_cp, c.d_fin_cidx, 0, y + (size_t)j0 * L.N, nt, nb,
+                              c.stream);
     }
     HIPCHK(hipGetLastError());
     return IGAMG_OK;
@@ -131,16 +136,10 @@ int igamg_vcycle(igamg_ctx *ctx, const double *f, double *u, int nrhs, void *str
     if (!ctx || !f || !u || nrhs < 1) igamg::fail(IGAMG_EINVAL, "invalid argument");
     igamg::Context &c = ctx->c;
     c.stream = (hipStream_t)stream;
-    igamg::LevelData &L = c.lv.back();
-    const int top = (int)c.lv.size() - 1;
-    for (int j = 0; j < nrhs; ++j) {
-      igamg::k_fill(c.ff, 0.0, L.Ntorn, c.stream);
-      igamg::k_scatter_compact(f + (size_t)j * L.N, L.N, c.d_fin_cp, c.d_fin_cidx, c.ff, c.stream);
-      igamg::k_copy_weighted(c.ff, L.d_weight, L.f, L.Ntorn, c.stream);
-      igamg::k_fill(L.u, 0.0, L.Ntorn, c.stream);
-      igamg::k_scatter_compact(u + (size_t)j * L.N, L.N, c.d_fin_cp, c.d_fin_cidx, L.u, c.stream);
-      igamg::vcycle_torn(c, top);
-      igamg::k_gather_compact(L.u, L.N, c.d_fin_cp, c.d_fin_cidx, 0, u + (size_t)j * L.N, c.stream);
+    const long long N = c.lv.back().N;
+    for (int j0 = 0; j0 < nrhs; j0 += c.nb) {
+      const int nb = std::min(c.nb, nrhs - j0);
+      igamg::vcycle_compact(c, f + (size_t)j0 * N, u + (size_t)j0 * N, nb);
     }
     HIPCHK(hipGetLastError());
     return IGAMG_OK;
@@ -156,9 +155,10 @@ int igamg_solve(igamg_ctx *ctx, const double *rhs, double *u, int nrhs, double t
     c.stream = (hipStream_t)stream;
     const long long N = c.lv.back().N;
     int status = IGAMG_OK;
-    for (int j = 0; j < nrhs; ++j) {
-      int s = igamg::solve_compact(c, rhs + (size_t)j * N, u + (size_t)j * N, tol, maxit,
-                                   use_initial_guess, info ? info + j : nullptr);
+    for (int j0 = 0; j0 < nrhs; j0 += c.nb) {
+      const int nb = std::min(c.nb, nrhs - j0);
+      int s = igamg::solve_batch(c, rhs + (size_t)j0 * N, u + (size_t)j0 * N, nb, tol, maxit,
+                                 use_initial_guess, info ? info + j0 : nullptr);
       if (s != IGAMG_OK) status = s;
     }
     HIPCHK(hipGetLastError());
@@ -174,7 +174,7 @@ int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream) {
     igamg::LevelData &L = c.lv.back();
     igamg::k_load_manufactured(c, L, c.qq);
     // every copy holds its patch's integral: the assembled value is their sum
-    igamg::k_gather_compact(c.qq, L.N, c.d_fin_cp, c.d_fin_cidx, 1, f, c.stream);
+    igamg::k_gather_compact(c.qq, L.N, c.d_fin_cp, c.d_fin_cidx, 1, f, L.Ntorn, 1, c.stream);
     HIPCHK(hipGetLastError());
     return IGAMG_OK;
   });

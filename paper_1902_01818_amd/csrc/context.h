@@ -30,6 +30,19 @@ struct Arena {
     if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return p;
   }
+  // upload a float64 host array as T (host copy kept alive until the stream syncs)
+  template <typename T>
+  T *upload_as(const std::vector<double> &v, hipStream_t s) {
+    staging.emplace_back();
+    std::vector<char> &buf = staging.back();
+    buf.resize(v.size() * sizeof(T));
+    T *h = (T *)buf.data();
+    for (size_t i = 0; i < v.size(); ++i) h[i] = (T)v[i];
+    T *p = alloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, h, v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  std::vector<std::vector<char>> staging;
   void release() {
     for (void *p : ptrs) (void)hipFree(p);
     ptrs.clear();
@@ -40,6 +53,21 @@ struct Arena {
 struct GsClass {
   GsTile *tiles;
   int count;
+};
+
+// Arrays of one level in one arithmetic precision.  Work vectors hold a batch
+// of right-hand sides, one after the other with stride Ntorn.
+template <typename T>
+struct LevelArrays {
+  T *f = nullptr, *u = nullptr, *r = nullptr;  // cycle right-hand side, iterate, residual
+  T *stencil = nullptr, *invdiag = nullptr;    // Gauss-Seidel rows (volume + same-side interface)
+  T *if_val = nullptr;                         // interface CSR values
+  T *gcx_val = nullptr;                        // cross-patch couplings per Gauss-Seidel tile
+  T *piece_inv = nullptr;                      // inverses of the interface pieces
+  T *P_val = nullptr, *R_val = nullptr;        // banded 1D embeddings (from the coarser level)
+  T *weight = nullptr;                         // 1 on the representative copy of a free unknown
+  T *wscratch = nullptr;                       // fast-diagonalization intermediate
+  Fd2Item<T> *fd[2] = {nullptr, nullptr};      // patch interiors: forward, backward
 };
 
 struct LevelData {
@@ -61,21 +89,13 @@ struct LevelData {
   std::vector<double> if_val;
   std::vector<unsigned char> if_cross;
   int *d_if_ptr = nullptr, *d_if_col = nullptr;
-  double *d_if_val = nullptr;
-  int *d_cx_ptr = nullptr, *d_cx_col = nullptr;
-  double *d_cx_val = nullptr;
   // rows carrying interface terms (lane-parallel part of the residual kernel)
   unsigned char *d_has_if = nullptr;
   int *d_if_rows = nullptr;
   int n_if_rows = 0;
-  // cross-patch couplings per Gauss-Seidel tile: (row inside tile, column, value)
+  // cross-patch couplings per Gauss-Seidel tile: (row inside tile, column)
   int *d_gcx_li = nullptr, *d_gcx_col = nullptr;
-  double *d_gcx_val = nullptr;
-  // same-side interface entries added to the stencil (torn row, stencil slot, value)
-  // volume stencil + inverse diagonal (Gauss-Seidel)
-  double *d_stencil = nullptr, *d_invdiag = nullptr;
   unsigned char *d_mask = nullptr;
-  double *d_weight = nullptr;  // 1 on the representative copy of a free unknown
   // glue groups (conforming): CSR of torn copies of every shared unknown
   int n_glue = 0;
   int *d_glue_ptr = nullptr, *d_glue_idx = nullptr;
@@ -83,22 +103,26 @@ struct LevelData {
   VolTile *d_vtiles = nullptr;
   int n_vtiles = 0;
   std::vector<GsClass> gs;  // classes in key order
-  // SCMS interiors: forward (Q^T R Q ./ D) and backward (Q W Q^T) row-block products
-  Fd2Item *d_fd[2] = {nullptr, nullptr};
+  // SCMS interiors
   int n_fd = 0;
   int fd_rows = 0, fd_K1 = 0, fd_N = 0;
+  long long wscratch_n = 0;
   // interface pieces
   PieceDev *d_pieces = nullptr;
   int n_pieces = 0, max_piece = 0;
   int *d_piece_idx = nullptr, *d_piece_cp = nullptr, *d_piece_cidx = nullptr;
-  double *d_piece_inv = nullptr;
   // transfer tables between this level and the next coarser one
   int *d_P_lo = nullptr, *d_R_lo = nullptr;
-  double *d_P_val = nullptr, *d_R_val = nullptr;
   int PW = 0, RW = 0;
-  // work vectors
-  double *f = nullptr, *u = nullptr, *r = nullptr;
+  LevelArrays<double> a64;
+  LevelArrays<float> a32;
+  template <typename T>
+  LevelArrays<T> &arr();
 };
+template <>
+inline LevelArrays<double> &LevelData::arr<double>() { return a64; }
+template <>
+inline LevelArrays<float> &LevelData::arr<float>() { return a32; }
 
 struct TimerFamily {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -112,6 +136,7 @@ struct Context {
   igamg_options opt{};
   double sigma_pen = 5.0;
   GaussRule gr{};
+  int nb = 1;  // right-hand sides the work vectors hold (batch capacity)
   std::vector<std::array<double, 24>> corners;   // [K][8*3]
   std::vector<std::array<int, 3>> elems_fine;
   // topology
@@ -126,25 +151,26 @@ struct Context {
   int n_colors = 1;
   std::vector<double> measure;
   std::vector<LevelData> lv;                      // level 0 = coarsest
-  // coarse solve
+  // coarse solve (float64 always)
   int N0 = 0;
   double *d_A0inv = nullptr;
-  int *d_c0_rep = nullptr;       // compact -> rep torn on level 0
   int *d_c0_cp = nullptr, *d_c0_cidx = nullptr;  // compact -> copies CSR
   // finest-level maps (ABI)
-  int *d_fin_rep = nullptr, *d_fin_cp = nullptr, *d_fin_cidx = nullptr;
-  // outer iteration vectors (torn layout, finest level)
+  int *d_fin_cp = nullptr, *d_fin_cidx = nullptr;
+  // outer iteration vectors (float64, torn layout, finest level, [nb][Ntorn])
   double *x = nullptr, *rr = nullptr, *z = nullptr, *pp = nullptr, *qq = nullptr, *ff = nullptr;
-  double *d_red = nullptr;       // reduction partials
-  double *d_scal = nullptr;      // device scalars
+  double *rold = nullptr;        // previous residual (flexible CG)
+  double *d_red = nullptr;       // reduction partials [nb][RED_BLOCKS]
+  double *d_scal = nullptr;      // device scalars [nb][S_COUNT]
   double *h_scal = nullptr;      // pinned host mirror
-  // SCMS scratch
-  double *scratch1 = nullptr, *scratch2 = nullptr;
+  int *d_active = nullptr;       // per right-hand side: 1 = still iterating
+  int *h_active = nullptr;       // pinned host mirror (written only after a stream sync)
   hipStream_t stream = nullptr;
   Arena arena;
   std::map<std::string, TimerFamily> timers;
   std::string timing_filter;  // time only families whose key starts with this
 
+  bool fp32() const { return opt.precision == IGAMG_FP32; }
   void launch_begin(const char *fam, hipEvent_t *b, hipEvent_t *e);
   void launch_end(const char *fam, hipEvent_t b, hipEvent_t e, int launches = 1);
   ~Context();
@@ -157,11 +183,11 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
 void kernel_model(const Context &c, const std::string &family, int level, double *bytes,
                   double *flops);
 
-// cycle / outer iteration (cycle.cpp)
-void apply_torn(Context &c, int l, const double *u, const double *f, const double *fw, double *r,
-                double alpha);
-void vcycle_torn(Context &c, int l);
-int solve_compact(Context &c, const double *rhs, double *u, double tol, int maxit, int use_x0,
-                  igamg_solve_info *info);
+// cycle / outer iteration (cycle.cpp); vectors in torn layout, nrhs <= c.nb
+void apply64(Context &c, const double *u, const double *f, const double *fw, double *r,
+             double alpha, int nrhs);
+void vcycle_compact(Context &c, const double *f, double *u, int nrhs);
+int solve_batch(Context &c, const double *rhs, double *u, int nrhs, double tol, int maxit,
+                int use_x0, igamg_solve_info *info);
 
 }  // namespace igamg

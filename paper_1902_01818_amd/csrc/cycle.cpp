@@ -10,6 +10,9 @@
 //    unknown sum to its value (restriction of a weighted residual produces
 //    exactly this form).  In the SIPG space every unknown has one copy and
 //    both forms coincide.
+// Every vector holds a batch of right-hand sides ([nrhs][Ntorn]).  The cycle
+// runs in the context's arithmetic T (float64 or float32); the outer
+// iteration, its residuals and the convergence test are float64 always.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -20,155 +23,256 @@
 
 namespace igamg {
 
-// r = f - A u on level l (f distributed, result consistent)
-static void residual(Context &c, int l, const double *u, const double *f, double *r) {
-  LevelData &L = c.lv[l];
-  k_iface_apply(c, L, u, f, nullptr, 1.0, -1.0, r);
-  k_vol_apply(c, L, u, r, -1.0);
-  k_glue_sum(L, r, c.stream);
-}
+namespace {
 
-void apply_torn(Context &c, int l, const double *u, const double *f, const double *fw, double *r,
-                double alpha) {
-  LevelData &L = c.lv[l];
-  k_iface_apply(c, L, u, f, fw, 1.0, alpha, r);
-  k_vol_apply(c, L, u, r, alpha);
-  k_glue_sum(L, r, c.stream);
+// r = f - A u on level L (f distributed, result consistent)
+template <typename T>
+void residual(Context &c, LevelData &L, const T *u, const T *f, T *r, int nb) {
+  k_iface_apply<T>(c, L, u, f, nullptr, (T)1, (T)-1, r, nb);
+  k_vol_apply<T>(c, L, u, r, (T)-1, nb);
+  k_glue_sum<T>(L, r, nb, c.stream);
 }
 
 // one step of the additive piece smoother (eq. Ldef): u += tau sum_T P_T L_T^-1 P_T^T r
-static void scms_step(Context &c, int l) {
-  LevelData &L = c.lv[l];
-  residual(c, l, L.u, L.f, L.r);
-  k_scms_interior(c, L);
-  k_pieces(c, L, L.r, L.u);
+template <typename T>
+void scms_step(Context &c, LevelData &L, int nb) {
+  LevelArrays<T> &A = L.arr<T>();
+  residual<T>(c, L, A.u, A.f, A.r, nb);
+  k_scms_interior<T>(c, L, nb);
+  k_pieces<T>(c, L, nb);
 }
 
-static void mg(Context &c, int l) {
+template <typename T>
+void mg(Context &c, int l, int nb) {
   LevelData &L = c.lv[l];
+  LevelArrays<T> &A = L.arr<T>();
   if (l == 0) {
-    k_coarse_solve(c, L.f, L.u);
+    k_coarse_solve<T>(c, A.f, A.u, nb);
     return;
   }
   const int sm = c.opt.smoother;
   // pre-smoothing
   if (sm == IGAMG_SMOOTHER_GS) {
-    for (int i = 0; i < c.opt.nu; ++i) k_gs_sweep(c, L, false);
+    for (int i = 0; i < c.opt.nu; ++i) k_gs_sweep<T>(c, L, false, nb);
   } else {
-    if (sm == IGAMG_SMOOTHER_HYBRID) k_gs_sweep(c, L, false);
-    for (int i = 0; i < c.opt.nu; ++i) scms_step(c, l);
+    if (sm == IGAMG_SMOOTHER_HYBRID) k_gs_sweep<T>(c, L, false, nb);
+    for (int i = 0; i < c.opt.nu; ++i) scms_step<T>(c, L, nb);
   }
   // coarse-grid correction
   LevelData &C = c.lv[l - 1];
+  LevelArrays<T> &AC = C.arr<T>();
   const int reps = (l == 1) ? 1 : c.opt.mu;
   for (int rep = 0; rep < reps; ++rep) {
-    residual(c, l, L.u, L.f, L.r);
-    k_restrict(c, L, C, L.r, C.f, l == 1 ? nullptr : C.u);
+    residual<T>(c, L, A.u, A.f, A.r, nb);
+    k_restrict<T>(c, L, C, A.r, AC.f, l == 1 ? nullptr : AC.u, nb);
     if (l == 1)
-      k_coarse_solve(c, C.f, C.u);
+      k_coarse_solve<T>(c, AC.f, AC.u, nb);
     else
-      mg(c, l - 1);
-    k_prolong_add(c, L, C, C.u, L.u);
+      mg<T>(c, l - 1, nb);
+    k_prolong_add<T>(c, L, C, AC.u, A.u, nb);
   }
   // post-smoothing
   if (sm == IGAMG_SMOOTHER_GS) {
-    for (int i = 0; i < c.opt.nu; ++i) k_gs_sweep(c, L, true);
+    for (int i = 0; i < c.opt.nu; ++i) k_gs_sweep<T>(c, L, true, nb);
   } else {
-    for (int i = 0; i < c.opt.nu; ++i) scms_step(c, l);
-    if (sm == IGAMG_SMOOTHER_HYBRID) k_gs_sweep(c, L, true);
+    for (int i = 0; i < c.opt.nu; ++i) scms_step<T>(c, L, nb);
+    if (sm == IGAMG_SMOOTHER_HYBRID) k_gs_sweep<T>(c, L, true, nb);
   }
 }
 
-void vcycle_torn(Context &c, int l) { mg(c, l); }
-
-// z = MG(L, r, 0) on the finest level.  z is the finest level's iterate L.u
-// (c.z aliases it); it must be zero on entry.  In the SIPG space the
-// distributed right-hand side equals r itself, so the cycle reads r directly.
-static void precondition(Context &c, double *r) {
-  LevelData &L = c.lv.back();
-  double *f_saved = L.f;
-  if (L.n_glue > 0)
-    k_copy_weighted(r, L.d_weight, L.f, L.Ntorn, c.stream);
+void mg_top(Context &c, int nb) {
+  if (c.fp32())
+    mg<float>(c, (int)c.lv.size() - 1, nb);
   else
-    L.f = r;
-  mg(c, (int)c.lv.size() - 1);
-  L.f = f_saved;
+    mg<double>(c, (int)c.lv.size() - 1, nb);
 }
 
-static double read_scalar(Context &c, int slot) {
-  HIPCHK(hipMemcpyAsync(c.h_scal + slot, c.d_scal + slot, sizeof(double), hipMemcpyDeviceToHost,
-                        c.stream));
+// Finest cycle input from a float64 torn vector: f = w .* x (consistent ->
+// distributed) in the cycle arithmetic; zero_u also clears the iterate.
+void set_cycle_rhs(Context &c, const double *x, int nb, bool zero_u) {
+  LevelData &L = c.lv.back();
+  const long long nt = L.Ntorn;
+  if (c.fp32()) {
+    k_convert<double, float>(x, L.a32.weight, L.a32.f, nt, nb, c.stream,
+                             zero_u ? L.a32.u : nullptr);
+  } else {
+    k_convert<double, double>(x, L.a64.weight, L.a64.f, nt, nb, c.stream,
+                              zero_u ? L.a64.u : nullptr);
+  }
+}
+
+// z = MG(L, r, 0) on the finest level (z = c.z).  In float64 z is the finest
+// iterate itself and must be zero on entry (the outer update clears it).
+void precondition(Context &c, const double *r, int nb) {
+  LevelData &L = c.lv.back();
+  const long long nt = L.Ntorn;
+  if (c.fp32()) {
+    set_cycle_rhs(c, r, nb, true);
+    mg<float>(c, (int)c.lv.size() - 1, nb);
+    k_convert<float, double>(L.a32.u, nullptr, c.z, nt, nb, c.stream);
+    return;
+  }
+  // In the SIPG space the distributed right-hand side equals r itself, so the
+  // cycle reads r directly.
+  double *f_saved = L.a64.f;
+  if (L.n_glue > 0)
+    set_cycle_rhs(c, r, nb, false);
+  else
+    L.a64.f = const_cast<double *>(r);
+  mg<double>(c, (int)c.lv.size() - 1, nb);
+  L.a64.f = f_saved;
+}
+
+void read_scalars(Context &c, int nb) {
+  HIPCHK(hipMemcpyAsync(c.h_scal, c.d_scal, (size_t)nb * S_COUNT * sizeof(double),
+                        hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipStreamSynchronize(c.stream));
-  return c.h_scal[slot];
 }
 
-int solve_compact(Context &c, const double *rhs, double *u, double tol, int maxit, int use_x0,
-                  igamg_solve_info *info) {
+void upload_active(Context &c, int nb) {
+  HIPCHK(hipMemcpyAsync(c.d_active, c.h_active, (size_t)nb * sizeof(int),
+                        hipMemcpyHostToDevice, c.stream));
+}
+
+}  // namespace
+
+void apply64(Context &c, const double *u, const double *f, const double *fw, double *r,
+             double alpha, int nb) {
+  LevelData &L = c.lv.back();
+  k_iface_apply<double>(c, L, u, f, fw, 1.0, alpha, r, nb);
+  k_vol_apply<double>(c, L, u, r, alpha, nb);
+  k_glue_sum<double>(L, r, nb, c.stream);
+}
+
+void vcycle_compact(Context &c, const double *f, double *u, int nb) {
+  LevelData &L = c.lv.back();
+  const long long nt = L.Ntorn;
+  k_fill(c.ff, 0.0, nt * nb, c.stream);
+  k_scatter_compact(f, L.N, c.d_fin_cp, c.d_fin_cidx, c.ff, nt, nb, c.stream);
+  k_fill(c.x, 0.0, nt * nb, c.stream);
+  k_scatter_compact(u, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, nt, nb, c.stream);
+  set_cycle_rhs(c, c.ff, nb, false);
+  if (c.fp32())
+    k_convert<double, float>(c.x, nullptr, L.a32.u, nt, nb, c.stream);
+  else
+    k_convert<double, double>(c.x, nullptr, L.a64.u, nt, nb, c.stream);
+  mg_top(c, nb);
+  if (c.fp32())
+    k_convert<float, double>(L.a32.u, nullptr, c.x, nt, nb, c.stream);
+  else
+    k_convert<double, double>(L.a64.u, nullptr, c.x, nt, nb, c.stream);
+  k_gather_compact(c.x, L.N, c.d_fin_cp, c.d_fin_cidx, 0, u, nt, nb, c.stream);
+}
+
+int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, int maxit,
+                int use_x0, igamg_solve_info *info) {
   auto t0 = std::chrono::steady_clock::now();
   LevelData &L = c.lv.back();
-  const int top = (int)c.lv.size() - 1;
   const long long nt = L.Ntorn;
-  k_fill(c.ff, 0.0, nt, c.stream);
-  k_scatter_compact(rhs, L.N, c.d_fin_cp, c.d_fin_cidx, c.ff, c.stream);
-  k_fill(c.x, 0.0, nt, c.stream);
+  const size_t bytes = (size_t)nt * nb * sizeof(double);
+  k_fill(c.ff, 0.0, nt * nb, c.stream);
+  k_scatter_compact(rhs, L.N, c.d_fin_cp, c.d_fin_cidx, c.ff, nt, nb, c.stream);
+  k_fill(c.x, 0.0, nt * nb, c.stream);
   if (use_x0) {
-    k_scatter_compact(u, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, c.stream);
-    apply_torn(c, top, c.x, c.ff, L.d_weight, c.rr, -1.0);  // r = f - A x
+    k_scatter_compact(u, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, nt, nb, c.stream);
+    apply64(c, c.x, c.ff, L.a64.weight, c.rr, -1.0, nb);  // r = f - A x
   } else {
-    HIPCHK(hipMemcpyAsync(c.rr, c.ff, nt * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(c.rr, c.ff, bytes, hipMemcpyDeviceToDevice, c.stream));
   }
-  k_dot(c, c.ff, c.ff, nt, S_FF, 0);
-  const double ff = read_scalar(c, S_FF);
-  const double nf = std::sqrt(ff);
-  k_dot(c, c.rr, c.rr, nt, S_RR, 0);
-  double res = nf > 0 ? std::sqrt(read_scalar(c, S_RR)) / nf : 0.0;
-  int it = 0;
-  if (info && info->history) info->history[0] = res;
-  if (nf > 0 && res > tol) {
+  k_dot(c, c.ff, c.ff, nt, S_FF, 0, nb);
+  k_dot(c, c.rr, c.rr, nt, S_RR, 0, nb);
+  read_scalars(c, nb);
+  std::vector<double> nf(nb), res(nb);
+  std::vector<int> its(nb, 0);
+  int n_active = 0;
+  for (int j = 0; j < nb; ++j) {
+    const double *sc = c.h_scal + (size_t)j * S_COUNT;
+    nf[j] = std::sqrt(sc[S_FF]);
+    res[j] = nf[j] > 0 ? std::sqrt(sc[S_RR]) / nf[j] : 0.0;
+    if (info && info[j].history) info[j].history[0] = res[j];
+    c.h_active[j] = (nf[j] > 0 && res[j] > tol) ? 1 : 0;
+    n_active += c.h_active[j];
+  }
+  upload_active(c, nb);
+  // host-side convergence bookkeeping after an update of S_RR
+  auto check = [&](int it) {
+    read_scalars(c, nb);
+    bool changed = false;
+    for (int j = 0; j < nb; ++j) {
+      if (!c.h_active[j]) continue;
+      res[j] = std::sqrt(c.h_scal[(size_t)j * S_COUNT + S_RR]) / nf[j];
+      its[j] = it;
+      if (info && info[j].history) info[j].history[it] = res[j];
+      if (res[j] <= tol) {
+        c.h_active[j] = 0;
+        --n_active;
+        changed = true;
+      }
+    }
+    if (changed && n_active > 0) upload_active(c, nb);
+  };
+  if (n_active > 0) {
     if (c.opt.outer == IGAMG_OUTER_MG) {
-      for (it = 1; it <= maxit; ++it) {
-        k_copy_weighted(c.ff, L.d_weight, L.f, nt, c.stream);
-        HIPCHK(hipMemcpyAsync(L.u, c.x, nt * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-        mg(c, top);
-        HIPCHK(hipMemcpyAsync(c.x, L.u, nt * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-        apply_torn(c, top, c.x, c.ff, L.d_weight, c.rr, -1.0);
-        k_dot(c, c.rr, c.rr, nt, S_RR, 0);
-        res = std::sqrt(read_scalar(c, S_RR)) / nf;
-        if (info && info->history) info->history[it] = res;
-        if (res <= tol) break;
+      for (int it = 1; it <= maxit && n_active > 0; ++it) {
+        set_cycle_rhs(c, c.ff, nb, false);
+        if (c.fp32())
+          k_convert<double, float>(c.x, nullptr, L.a32.u, nt, nb, c.stream);
+        else
+          k_convert<double, double>(c.x, nullptr, L.a64.u, nt, nb, c.stream);
+        mg_top(c, nb);
+        // converged right-hand sides keep their iterate
+        if (c.fp32())
+          k_convert<float, double>(L.a32.u, nullptr, c.x, nt, nb, c.stream, nullptr, c.d_active);
+        else
+          k_convert<double, double>(L.a64.u, nullptr, c.x, nt, nb, c.stream, nullptr, c.d_active);
+        apply64(c, c.x, c.ff, L.a64.weight, c.rr, -1.0, nb);
+        k_dot(c, c.rr, c.rr, nt, S_RR, 0, nb);
+        check(it);
       }
     } else {
-      k_fill(c.z, 0.0, nt, c.stream);
-      precondition(c, c.rr);
-      k_dot(c, c.rr, c.z, nt, S_RZ, 0);
-      HIPCHK(hipMemcpyAsync(c.pp, c.z, nt * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-      for (it = 1; it <= maxit; ++it) {
-        apply_torn(c, top, c.pp, nullptr, nullptr, c.qq, 1.0);  // q = A p
-        k_dot(c, c.pp, c.qq, nt, S_PQ, 1);              // alpha = rz / pq
-        k_pcg_update_xr(c, nt);                         // x += alpha p, r -= alpha q, rr
-        res = std::sqrt(read_scalar(c, S_RR)) / nf;
-        if (info && info->history) info->history[it] = res;
-        if (res <= tol) break;
-        precondition(c, c.rr);                          // z zeroed by the update above
-        k_dot(c, c.rr, c.z, nt, S_RZNEW, 2);            // beta = rz_new / rz
-        k_pcg_update_p(c, nt);                          // p = z + beta p
+      const bool fcg = c.opt.outer == IGAMG_OUTER_FCG;
+      if (!c.fp32()) k_fill(c.z, 0.0, nt * nb, c.stream);
+      precondition(c, c.rr, nb);
+      k_dot(c, c.rr, c.z, nt, S_RZ, 0, nb);
+      HIPCHK(hipMemcpyAsync(c.pp, c.z, bytes, hipMemcpyDeviceToDevice, c.stream));
+      for (int it = 1; it <= maxit; ++it) {
+        apply64(c, c.pp, nullptr, nullptr, c.qq, 1.0, nb);  // q = A p
+        k_dot(c, c.pp, c.qq, nt, S_PQ, 1, nb);               // alpha = rz / pq
+        k_pcg_update_xr(c, nt, nb, fcg);  // x += alpha p, r -= alpha q, rr; z = 0
+        check(it);
+        if (n_active == 0) break;
+        precondition(c, c.rr, nb);
+        if (fcg)
+          k_dot_fcg(c, nt, nb);  // beta = (z, r - r_old) / rz
+        else
+          k_dot(c, c.rr, c.z, nt, S_RZNEW, 2, nb);  // beta = rz_new / rz
+        k_pcg_update_p(c, nt, nb);                  // p = z + beta p
       }
     }
   }
-  if (it > maxit) it = maxit;
-  k_gather_compact(c.x, L.N, c.d_fin_cp, c.d_fin_cidx, 0, u, c.stream);
+  k_gather_compact(c.x, L.N, c.d_fin_cp, c.d_fin_cidx, 0, u, nt, nb, c.stream);
   // true residual in float64
-  apply_torn(c, top, c.x, c.ff, L.d_weight, c.qq, -1.0);
-  k_dot(c, c.qq, c.qq, nt, S_TMP, 0);
-  double tres = nf > 0 ? std::sqrt(read_scalar(c, S_TMP)) / nf : 0.0;
+  apply64(c, c.x, c.ff, L.a64.weight, c.qq, -1.0, nb);
+  k_dot(c, c.qq, c.qq, nt, S_TMP, 0, nb);
+  read_scalars(c, nb);
   auto t1 = std::chrono::steady_clock::now();
-  if (info) {
-    info->iterations = it;
-    info->rel_residual = res;
-    info->true_rel_residual = tres;
-    info->seconds = std::chrono::duration<double>(t1 - t0).count();
+  int status = IGAMG_OK;
+  for (int j = 0; j < nb; ++j) {
+    const bool ok = nf[j] == 0 || res[j] <= tol;
+    if (!ok) status = IGAMG_ENOCONV;
+    if (info) {
+      info[j].iterations = its[j];
+      info[j].rel_residual = res[j];
+      info[j].true_rel_residual =
+          nf[j] > 0 ? std::sqrt(c.h_scal[(size_t)j * S_COUNT + S_TMP]) / nf[j] : 0.0;
+      info[j].seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
   }
-  return res <= tol || nf == 0 ? IGAMG_OK : IGAMG_ENOCONV;
+  // leave every right-hand side active for the next call's kernels (the
+  // stream was synchronized above, so no copy still reads the mirror)
+  for (int j = 0; j < nb; ++j) c.h_active[j] = 1;
+  upload_active(c, nb);
+  return status;
 }
 
 }  // namespace igamg

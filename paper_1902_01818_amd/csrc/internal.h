@@ -61,18 +61,21 @@ struct GsTile {
 // Two chained products on a block of 16 rows (fast-diagonalization step of the
 // subspace corrected mass smoother): Z = L[rows, :] M1, R = Z M2, then either
 // O[rows, :] = R / (sigma + lam_r[row] + lam_c[col]) (lam_r != null) or
-// O[rows, :] += scale R.  All operands are row-major with unit column stride.
+// O[rows, :] += scale R.  All operands are row-major with unit column stride;
+// *_z is the element stride between right-hand sides of a batch (0 = shared).
+template <typename T>
 struct Fd2Item {
-  const double *L;   // rows x K1, row stride l_r
-  const double *M1;  // K1 x N, row stride m1_r
-  const double *M2;  // N x N, row stride m2_r
-  double *O;         // rows x N, row stride o_r
+  const T *L;   // rows x K1, row stride l_r
+  const T *M1;  // K1 x N, row stride m1_r
+  const T *M2;  // N x N, row stride m2_r
+  T *O;         // rows x N, row stride o_r
   long long l_r, m1_r, m2_r, o_r;
+  long long m1_z, o_z;
   int rows, K1, N;
-  const double *lam_r;
-  const double *lam_c;
-  double sigma;
-  double scale;
+  const T *lam_r;
+  const T *lam_c;
+  T sigma;
+  T scale;
 };
 
 // Interface piece of the additive smoother (eq. Ldef): dense inverse of P^T A P.

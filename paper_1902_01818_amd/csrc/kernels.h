@@ -1,50 +1,72 @@
-// Kernel launchers (kernels.hip).  All launches are asynchronous on `s`.
+// Kernel launchers (kernels.hip).  All launches are asynchronous on the
+// context stream (or `s`).  Work vectors of the cycle carry a batch of nrhs
+// right-hand sides with stride Ntorn; operator data is shared by the batch.
 #pragma once
 #include "context.h"
 
 namespace igamg {
 
-void k_fill(double *x, double v, long long n, hipStream_t s);
-void k_copy_weighted(const double *x, const double *w, double *y, long long n, hipStream_t s);
+constexpr int RED_BLOCKS = 256;  // partial sums per right-hand side of a reduction
+
+// elementwise (batched: n values per right-hand side, nrhs of them)
+template <typename T>
+void k_fill(T *x, T v, long long n, hipStream_t s);
+// y = w .* x converted to To (w = null: plain conversion), per right-hand side;
+// zero (optional) is cleared alongside; with `active`, right-hand sides j with
+// active[j] == 0 are skipped
+template <typename Ti, typename To>
+void k_convert(const Ti *x, const To *w, To *y, long long n, int nrhs, hipStream_t s,
+               To *zero = nullptr, const int *active = nullptr);
 
 // setup
-void k_stencil_assemble(Context &c, LevelData &L);
+void k_stencil_assemble(Context &c, LevelData &L, double *out);
 void k_stencil_add(const int *rows, const int *slots, const double *vals, int n, double *stencil,
                    int S, hipStream_t s);
 void k_invdiag(const double *stencil, int S, int center, const unsigned char *mask, double *invd,
                long long n, hipStream_t s);
 void k_load_manufactured(Context &c, LevelData &L, double *out);
 
-// operator: r = mask*(beta f + alpha A u); volume part by sum factorization
-void k_iface_apply(Context &c, LevelData &L, const double *u, const double *f, const double *fw,
-                   double beta, double alpha, double *r);
-void k_vol_apply(Context &c, LevelData &L, const double *u, double *r, double alpha);
-void k_glue_sum(LevelData &L, double *y, hipStream_t s);
+// operator: r = mask (beta fw.*f + alpha A u); volume part by sum factorization
+template <typename T>
+void k_iface_apply(Context &c, LevelData &L, const T *u, const T *f, const T *fw, T beta, T alpha,
+                   T *r, int nrhs);
+template <typename T>
+void k_vol_apply(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs);
+template <typename T>
+void k_glue_sum(LevelData &L, T *y, int nrhs, hipStream_t s);
 
-// smoothers
-void k_gs_sweep(Context &c, LevelData &L, bool backward);
-void k_scms_interior(Context &c, LevelData &L);
-void k_pieces(Context &c, LevelData &L, const double *r, double *u);
+// smoothers (on L.arr<T>().f / .u / .r)
+template <typename T>
+void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs);
+template <typename T>
+void k_scms_interior(Context &c, LevelData &L, int nrhs);
+template <typename T>
+void k_pieces(Context &c, LevelData &L, int nrhs);
 
-// transfer between level l (fine) and l-1 (coarse)
-// rc = P^T (w rf); if uc_zero != null it is set to zero (coarse initial guess)
-void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc,
-                double *uc_zero);
-void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, double *uf);
-void k_coarse_solve(Context &c, const double *f0, double *u0);
+// transfer between level F (fine) and C (coarse); restriction also zeroes
+// uc_zero (the coarse initial guess) when given
+template <typename T>
+void k_restrict(Context &c, LevelData &F, LevelData &C, const T *rf, T *rc, T *uc_zero, int nrhs);
+template <typename T>
+void k_prolong_add(Context &c, LevelData &F, LevelData &C, const T *ec, T *uf, int nrhs);
+template <typename T>
+void k_coarse_solve(Context &c, const T *f0, T *u0, int nrhs);
 
-// compact <-> torn
+// compact <-> torn (float64, batched: compact stride N, torn stride Ntorn)
 void k_scatter_compact(const double *xc, long long N, const int *cp, const int *cidx, double *xt,
-                       hipStream_t s);
+                       long long Ntorn, int nrhs, hipStream_t s);
 void k_gather_compact(const double *xt, long long N, const int *cp, const int *cidx, int sum,
-                      double *xc, hipStream_t s);
+                      double *xc, long long Ntorn, int nrhs, hipStream_t s);
 
-// deterministic reductions and PCG updates (device scalars in c.d_scal)
-enum Scalar { S_RZ = 0, S_PQ, S_RR, S_RZNEW, S_FF, S_ALPHA, S_BETA, S_TMP, S_COUNT };
-void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode);
-// x += alpha p, r -= alpha q, ||r||^2 (weighted); also zeroes the cycle iterate z
-void k_pcg_update_xr(Context &c, long long n);
-void k_pcg_update_p(Context &c, long long n);
-void k_axpy(double a, const double *x, double *y, long long n, hipStream_t s);
+// deterministic reductions and outer updates; scalars per right-hand side in
+// c.d_scal[j * S_COUNT + slot]; c.d_active masks converged right-hand sides
+enum Scalar { S_RZ = 0, S_PQ, S_RR, S_RZNEW, S_FF, S_ALPHA, S_BETA, S_TMP, S_ZRO, S_COUNT };
+// mode 0: scal[slot] = sum; 1: alpha = rz / sum; 2: beta = sum / rz, rz = sum
+void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode, int nrhs);
+// flexible CG: beta = ((z, r) - (z, r_old)) / rz, rz = (z, r)
+void k_dot_fcg(Context &c, long long n, int nrhs);
+// x += alpha p, r -= alpha q, ||r||^2 into S_RR; zeroes z; optionally keeps r_old
+void k_pcg_update_xr(Context &c, long long n, int nrhs, bool keep_rold);
+void k_pcg_update_p(Context &c, long long n, int nrhs);
 
 }  // namespace igamg

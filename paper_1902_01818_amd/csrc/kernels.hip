@@ -6,12 +6,18 @@
 //    Gauss point;
 //  * interface terms of the SIPG form (Section 3, eq. model:discr2) as a
 //    sparse row-gather over the unknowns next to interfaces;
-//  * multicolour Gauss-Seidel (Section 4) over tiles of a fixed colour order;
+//  * multicolour Gauss-Seidel (Section 4): one wavefront per tile of a fixed
+//    colour order;
 //  * the subspace corrected mass smoother (Section 5, eq. Ldef): patch
-//    interiors by fast diagonalization = four batched GEMMs, interface pieces
-//    by dense inverses of P^T A P;
+//    interiors by fast diagonalization (two fused row-block kernels),
+//    interface pieces by dense inverses of P^T A P;
 //  * canonical embedding / its transpose between dyadic levels (Section 4);
-//  * direct coarse solve and deterministic reductions of the outer PCG.
+//  * direct coarse solve (float64) and deterministic reductions of the outer
+//    conjugate gradient iteration.
+// Cycle kernels are templates on the storage / arithmetic type (double or
+// float) and process a batch of right-hand sides (a grid dimension) that
+// share all operator data; vectors of the batch follow each other with
+// stride Ntorn.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,6 +46,7 @@ struct TimeScope {
   std::string key;
   bool on = false;
   hipEvent_t b = nullptr, e = nullptr;
+  int n = 1;  // kernel launches covered by this event pair
   TimeScope(Context &c_, const char *f, int level) : c(c_) {
     if (!c.opt.timing) return;
     key = std::string(f) + "/" + std::to_string(level);
@@ -49,84 +56,72 @@ struct TimeScope {
   ~TimeScope() {
     if (on) c.launch_end(key.c_str(), b, e, n);
   }
-  int n = 1;  // kernel launches covered by this event pair
 };
 
-__device__ inline void atomic_add(double *a, double v) { unsafeAtomicAdd(a, v); }
-
-// Cross-lane sums without LDS traffic: DPP row shifts build an inclusive scan
-// inside every row of 16 lanes (lane 15 of a row then holds the row sum); the
-// wavefront total combines the four row sums with readlane.
+// Cross-lane sums without LDS traffic: DPP row shifts (bound_ctrl: lanes
+// without a source read 0) build an inclusive scan inside every row of 16
+// lanes; lane 15 of a row then holds the row sum.
 template <int CTRL>
-__device__ inline double dpp_move(double v) {
-  long long b = __double_as_longlong(v);
-  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ inline double row16_scan(double v) {
-  v += dpp_move<0x111>(v);  // row_shr:1
-  v += dpp_move<0x112>(v);  // row_shr:2
-  v += dpp_move<0x114>(v);  // row_shr:4
-  v += dpp_move<0x118>(v);  // row_shr:8
-  return v;
-}
-
-// same scan with bound_ctrl (lanes without a source read 0): no zero moves
-template <int CTRL>
-__device__ inline double dpp_move_bc(double v) {
+__device__ inline double dpp_shift(double v) {
   long long b = __double_as_longlong(v);
   int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, true);
   int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-
-__device__ inline double row16_scan_fast(double v) {
-  v += dpp_move_bc<0x111>(v);
-  v += dpp_move_bc<0x112>(v);
-  v += dpp_move_bc<0x114>(v);
-  v += dpp_move_bc<0x118>(v);
+template <int CTRL>
+__device__ inline float dpp_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <typename T>
+__device__ inline T row16_scan(T v) {
+  v += dpp_shift<0x111>(v);  // row_shr:1
+  v += dpp_shift<0x112>(v);  // row_shr:2
+  v += dpp_shift<0x114>(v);  // row_shr:4
+  v += dpp_shift<0x118>(v);  // row_shr:8
   return v;
 }
 
-__device__ inline double readlane_d(double v, int lane) {
-  long long b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// sum over the 64 lanes of the wavefront (uniform result)
-__device__ inline double wave_sum(double v) {
-  v = row16_scan(v);
-  return (readlane_d(v, 15) + readlane_d(v, 31)) + (readlane_d(v, 47) + readlane_d(v, 63));
-}
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  using type = double2;
+};
+template <>
+struct Pair2<float> {
+  using type = float2;
+};
 
 // ---------------------------------------------------------------------------
 // elementwise
 // ---------------------------------------------------------------------------
-__global__ void fill_kernel(double *x, double v, long long n) {
+template <typename T>
+__global__ void fill_kernel(T *x, T v, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     x[i] = v;
 }
 
-__global__ void copy_weighted_kernel(const double *x, const double *w, double *y, long long n) {
+// y = w .* x (w may be null), converted; zero[i] = 0 alongside when given;
+// right-hand sides with active[j] == 0 are left alone.  grid.y = right-hand side
+template <typename Ti, typename To>
+__global__ void convert_kernel(const Ti *x, const To *w, To *y, long long n, To *zero,
+                               const int *active) {
+  const long long z = blockIdx.y;
+  if (active && !active[z]) return;
+  x += z * n;
+  y += z * n;
+  if (zero) zero += z * n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    y[i] = w ? w[i] * x[i] : x[i];
-}
-
-__global__ void axpy_kernel(double a, const double *x, double *y, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    y[i] += a * x[i];
+       i += (long long)gridDim.x * blockDim.x) {
+    y[i] = w ? w[i] * (To)x[i] : (To)x[i];
+    if (zero) zero[i] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// setup: stencil (volume stiffness rows) assembly, gather form
+// setup: stencil (volume stiffness rows) assembly, gather form; rows padded
+// to whole 16-lane groups (zero coefficients)
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ void stencil_kernel(const PatchDev *pd, int K, const double *tabB, const double *tabD,
@@ -134,7 +129,7 @@ __global__ void stencil_kernel(const PatchDev *pd, int K, const double *tabB, co
   const int S1 = 2 * p + 1;
   int S = 1;
   for (int d = 0; d < D; ++d) S *= S1;
-  const int SP = (S + 15) / 16 * 16;  // rows padded to whole 16-lane groups
+  const int SP = (S + 15) / 16 * 16;
   long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (tid >= ntorn * SP) return;
   long long t = tid / SP;
@@ -227,65 +222,74 @@ __global__ void load_kernel(const PatchDev *pd, int K, const double *tabB, Gauss
 }
 
 // ---------------------------------------------------------------------------
-// interface terms: r = mask (beta f + alpha A_if u)   (one thread per unknown)
+// interface terms: r = mask (beta fw.*f + alpha A_if u).  Blocks below nb_plain
+// handle unknowns without interface couplings (one thread each); the others
+// give 16 lanes to each unknown next to an interface.  grid.y = right-hand side.
 // ---------------------------------------------------------------------------
+template <typename T>
 __global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
                                                     const unsigned char *__restrict__ mask,
                                                     const unsigned char *__restrict__ has_if,
                                                     const int *__restrict__ rows, int nrows,
                                                     const int *__restrict__ ptr,
                                                     const int *__restrict__ col,
-                                                    const double *__restrict__ val,
-                                                    const double *__restrict__ u,
-                                                    const double *__restrict__ f,
-                                                    const double *__restrict__ fw, double beta,
-                                                    double alpha, double *__restrict__ r) {
+                                                    const T *__restrict__ val,
+                                                    const T *__restrict__ u,
+                                                    const T *__restrict__ f,
+                                                    const T *__restrict__ fw, T beta, T alpha,
+                                                    T *__restrict__ r) {
+  const long long zo = (long long)blockIdx.y * n;
+  u += zo;
+  r += zo;
+  if (f) f += zo;
   if ((int)blockIdx.x < nb_plain) {
-    // unknowns without interface couplings: r = mask beta (w) f
     long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= n || has_if[t]) return;
-    double v = 0.0;
-    if (mask[t] && f) v = beta * (fw ? fw[t] : 1.0) * f[t];
+    T v = 0;
+    if (mask[t] && f) v = beta * (fw ? fw[t] : (T)1) * f[t];
     r[t] = v;
     return;
   }
-  // unknowns next to an interface: 16 lanes per row
   const int g = ((int)blockIdx.x - nb_plain) * (blockDim.x / 16) + threadIdx.x / 16;
   const int lane = threadIdx.x % 16;
   const bool ok = g < nrows;
   const int t = ok ? rows[g] : 0;
-  double s = 0.0;
+  T s = 0;
   if (ok)
     for (int e = ptr[t] + lane; e < ptr[t + 1]; e += 16) s += val[e] * u[col[e]];
   s = row16_scan(s);
   if (ok && lane == 15) {
-    double v = alpha * s;
-    if (f) v += beta * (fw ? fw[t] : 1.0) * f[t];
+    T v = alpha * s;
+    if (f) v += beta * (fw ? fw[t] : (T)1) * f[t];
     r[t] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
-// volume operator, 2D, sum factorization on a TE x TE element tile
-// r += alpha * A_vol u  (atomic accumulation of the tile's outputs)
+// volume operator, 2D, sum factorization on a TE x TE element tile:
+// r += alpha * A_vol u (atomic accumulation of the tile's outputs).  The
+// geometry (metric) is evaluated in float64 and rounded to T.
+// grid.x = tile, grid.y = right-hand side.
 // ---------------------------------------------------------------------------
-template <int P, int TE>
+template <typename T, int P, int TE>
 __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const PatchDev *pd,
                                                     const double *tabB, const double *tabD,
-                                                    GaussRule gr, const double *__restrict__ u,
-                                                    double *__restrict__ r,
+                                                    GaussRule gr, const T *__restrict__ u,
+                                                    T *__restrict__ r,
                                                     const unsigned char *__restrict__ mask,
-                                                    double alpha) {
+                                                    T alpha, long long vs) {
   constexpr int Q = P + 1, P1 = P + 1;
   constexpr int ND = TE + P;   // unknowns per direction touched by the tile
   constexpr int NQ = TE * Q;   // Gauss points per direction in the tile
-  __shared__ double sU[ND * ND];
-  __shared__ double sA0[ND * NQ], sA1[ND * NQ];
-  __shared__ double sV0[NQ * NQ], sV1[NQ * NQ];
-  __shared__ double sBx[NQ * P1], sDx[NQ * P1], sBy[NQ * P1], sDy[NQ * P1];
+  __shared__ T sU[ND * ND];
+  __shared__ T sA0[ND * NQ], sA1[ND * NQ];
+  __shared__ T sV0[NQ * NQ], sV1[NQ * NQ];
+  __shared__ T sBx[NQ * P1], sDx[NQ * P1], sBy[NQ * P1], sDy[NQ * P1];
   __shared__ double sC[4][3];
   const VolTile tl = tiles[blockIdx.x];
   const PatchDev &pt = pd[tl.patch];
+  u += (long long)blockIdx.y * vs;
+  r += (long long)blockIdx.y * vs;
   const int tid = threadIdx.x;
   const int ex0 = tl.e0[0], ey0 = tl.e0[1];
   const int nex = min(TE, pt.nel[0] - ex0), ney = min(TE, pt.nel[1] - ey0);
@@ -295,24 +299,24 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
   for (int i = tid; i < NQ * P1; i += blockDim.x) {
     int gq = i / P1;
     bool okx = gq < nex * Q, oky = gq < ney * Q;
-    sBx[i] = okx ? tabB[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : 0.0;
-    sDx[i] = okx ? tabD[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : 0.0;
-    sBy[i] = oky ? tabB[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : 0.0;
-    sDy[i] = oky ? tabD[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : 0.0;
+    sBx[i] = okx ? (T)tabB[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : (T)0;
+    sDx[i] = okx ? (T)tabD[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : (T)0;
+    sBy[i] = oky ? (T)tabB[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
+    sDy[i] = oky ? (T)tabD[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
   }
   for (int i = tid; i < ND * ND; i += blockDim.x) {
     int rr = i / ND, cc = i % ND;
-    sU[i] = (rr < ney + P && cc < nex + P) ? u[off + (long long)(ey0 + rr) * nx + ex0 + cc] : 0.0;
+    sU[i] = (rr < ney + P && cc < nex + P) ? u[off + (long long)(ey0 + rr) * nx + ex0 + cc] : (T)0;
   }
   __syncthreads();
   // x-contraction: A0 = values, A1 = derivatives, rows = unknown rows
   for (int i = tid; i < ND * NQ; i += blockDim.x) {
     int rr = i / NQ, gx = i % NQ;
     int e = gx / Q;
-    double a0 = 0.0, a1 = 0.0;
+    T a0 = 0, a1 = 0;
 #pragma unroll
     for (int a = 0; a < P1; ++a) {
-      double uv = sU[rr * ND + e + a];
+      T uv = sU[rr * ND + e + a];
       a0 += sBx[gx * P1 + a] * uv;
       a1 += sDx[gx * P1 + a] * uv;
     }
@@ -324,10 +328,10 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
   const double hx = 1.0 / pt.nel[0], hy = 1.0 / pt.nel[1];
   for (int i = tid; i < NQ * NQ; i += blockDim.x) {
     int gy = i / NQ, gx = i % NQ;
-    double v0 = 0.0, v1 = 0.0;
+    T v0 = 0, v1 = 0;
     if (gy < ney * Q && gx < nex * Q) {
       int ey = gy / Q;
-      double ux = 0.0, uy = 0.0;
+      T ux = 0, uy = 0;
 #pragma unroll
       for (int b = 0; b < P1; ++b) {
         ux += sBy[gy * P1 + b] * sA1[(ey + b) * NQ + gx];
@@ -335,18 +339,18 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
       }
       int ex = gx / Q;
       int qx = gx - ex * Q, qy = gy - ey * Q;
-      double xh[2] = {((double)(ex0 + ex) + gr.x[qx]) * hx, ((double)(ey0 + ey) + gr.x[qy]) * hy};
       // metric w |det J| J^-1 J^-T = (w / |det J|) adj(J) adj(J)^T: one division
-      const double ex_ = xh[0], ey_ = xh[1];
-      const double j00 = (1.0 - ey_) * (sC[1][0] - sC[0][0]) + ey_ * (sC[3][0] - sC[2][0]);
-      const double j10 = (1.0 - ey_) * (sC[1][1] - sC[0][1]) + ey_ * (sC[3][1] - sC[2][1]);
-      const double j01 = (1.0 - ex_) * (sC[2][0] - sC[0][0]) + ex_ * (sC[3][0] - sC[1][0]);
-      const double j11 = (1.0 - ex_) * (sC[2][1] - sC[0][1]) + ex_ * (sC[3][1] - sC[1][1]);
+      const double xe = ((double)(ex0 + ex) + gr.x[qx]) * hx;
+      const double ye = ((double)(ey0 + ey) + gr.x[qy]) * hy;
+      const double j00 = (1.0 - ye) * (sC[1][0] - sC[0][0]) + ye * (sC[3][0] - sC[2][0]);
+      const double j10 = (1.0 - ye) * (sC[1][1] - sC[0][1]) + ye * (sC[3][1] - sC[2][1]);
+      const double j01 = (1.0 - xe) * (sC[2][0] - sC[0][0]) + xe * (sC[3][0] - sC[1][0]);
+      const double j11 = (1.0 - xe) * (sC[2][1] - sC[0][1]) + xe * (sC[3][1] - sC[1][1]);
       const double det = j00 * j11 - j01 * j10;
       const double sc = gr.w[qx] * hx * gr.w[qy] * hy / fabs(det);
-      const double g00 = sc * (j11 * j11 + j01 * j01);
-      const double g01 = -sc * (j11 * j10 + j01 * j00);
-      const double g11 = sc * (j10 * j10 + j00 * j00);
+      const T g00 = (T)(sc * (j11 * j11 + j01 * j01));
+      const T g01 = (T)(-sc * (j11 * j10 + j01 * j00));
+      const T g11 = (T)(sc * (j10 * j10 + j00 * j00));
       v0 = g00 * ux + g01 * uy;
       v1 = g01 * ux + g11 * uy;
     }
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
   // transposed y-contraction: rows = output unknown rows
   for (int i = tid; i < ND * NQ; i += blockDim.x) {
     int rr = i / NQ, gx = i % NQ;
-    double s1 = 0.0, s0 = 0.0;
+    T s1 = 0, s0 = 0;
     int elo = max(0, rr - P), ehi = min(ney - 1, rr);
     for (int e = elo; e <= ehi; ++e) {
       int a = rr - e;
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
   for (int i = tid; i < ND * ND; i += blockDim.x) {
     int rr = i / ND, cc = i % ND;
     if (rr >= ney + P || cc >= nex + P) continue;
-    double y = 0.0;
+    T y = 0;
     int elo = max(0, cc - P), ehi = min(nex - 1, cc);
     for (int e = elo; e <= ehi; ++e) {
       int a = cc - e;
@@ -387,120 +391,59 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
       }
     }
     long long t = off + (long long)(ey0 + rr) * nx + ex0 + cc;
-    if (mask[t]) atomic_add(&r[t], alpha * y);
+    if (mask[t]) unsafeAtomicAdd(&r[t], alpha * y);
   }
 }
 
 // ---------------------------------------------------------------------------
-// glue (conforming): y <- sum of copies on every copy
+// glue (conforming): y <- sum of copies on every copy; grid.y = right-hand side
 // ---------------------------------------------------------------------------
-__global__ void glue_kernel(int ng, const int *ptr, const int *idx, double *y) {
+template <typename T>
+__global__ void glue_kernel(int ng, const int *ptr, const int *idx, T *y, long long vs) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ng) return;
-  double s = 0.0;
+  y += (long long)blockIdx.y * vs;
+  T s = 0;
   for (int e = ptr[g]; e < ptr[g + 1]; ++e) s += y[idx[e]];
   for (int e = ptr[g]; e < ptr[g + 1]; ++e) y[idx[e]] = s;
 }
 
 // ---------------------------------------------------------------------------
-// multicolour Gauss-Seidel on one class of tiles (2D)
+// Multicolour Gauss-Seidel, one wavefront per tile of 2(p+1) x 2(p+1)
+// unknowns: the four unknowns of a colour class inside the tile are updated
+// by four groups of 16 lanes; the row sum of each group comes out of a DPP
+// scan in its last lane.  A single wavefront executes its LDS operations in
+// program order, so a class reads what the previous class wrote without a
+// barrier.  Stencil rows (padded to 16-lane groups) of the next D classes are
+// prefetched into registers; f minus the cross-patch couplings (neighbouring
+// patches carry another patch colour, so their values are constant during the
+// launch) and 1/a_ii sit in LDS as one pair per unknown.
+// grid.x = tile, grid.y = right-hand side.
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(256) void gs2d_kernel(const GsTile *tiles, const PatchDev *pd,
-                                                   const double *__restrict__ st,
-                                                   const double *__restrict__ invd,
-                                                   const int *__restrict__ cx_ptr,
-                                                   const int *__restrict__ cx_col,
-                                                   const double *__restrict__ cx_val,
-                                                   const double *__restrict__ f, double *u,
-                                                   const unsigned char *__restrict__ mask, int T,
-                                                   int backward, int G) {
-  extern __shared__ double sU[];
-  constexpr int S1 = 2 * P + 1, S = S1 * S1, Q1 = P + 1;
-  const int W = T + 2 * P;
-  const GsTile tl = tiles[blockIdx.x];
-  const PatchDev &pt = pd[tl.patch];
-  const int nx = pt.n[0], ny = pt.n[1];
-  const int x0 = tl.i0[0], y0 = tl.i0[1];
-  const int wx0 = x0 - P, wy0 = y0 - P;
-  const long long off = pt.off;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < W * W; i += blockDim.x) {
-    int gy = wy0 + i / W, gx = wx0 + i % W;
-    sU[i] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? u[off + (long long)gy * nx + gx] : 0.0;
-  }
-  __syncthreads();
-  const int tx = min(T, nx - x0), ty = min(T, ny - y0);
-  const int rows_per_pass = blockDim.x / G;
-  const int lane = tid % G;
-  for (int ph = 0; ph < Q1 * Q1; ++ph) {
-    int s = backward ? Q1 * Q1 - 1 - ph : ph;
-    int sy = s / Q1, sx = s % Q1;
-    int fx = x0 + (((sx - x0 % Q1) % Q1) + Q1) % Q1;
-    int fy = y0 + (((sy - y0 % Q1) % Q1) + Q1) % Q1;
-    int cxn = fx < x0 + tx ? (x0 + tx - 1 - fx) / Q1 + 1 : 0;
-    int cyn = fy < y0 + ty ? (y0 + ty - 1 - fy) / Q1 + 1 : 0;
-    int nrows = cxn * cyn;
-    for (int base = 0; base < nrows; base += rows_per_pass) {
-      int row = base + tid / G;
-      bool active = row < nrows;
-      double acc = 0.0;
-      int ix = 0, iy = 0;
-      long long t = 0;
-      if (active) {
-        ix = fx + (row % cxn) * Q1;
-        iy = fy + (row / cxn) * Q1;
-        t = off + (long long)iy * nx + ix;
-        const double *srow = st + t * ((S + 15) / 16 * 16);
-        for (int o = lane; o < S; o += G) {
-          int oy = o / S1 - P, ox = o % S1 - P;
-          acc += srow[o] * sU[(iy + oy - wy0) * W + (ix + ox - wx0)];
-        }
-        for (int e = cx_ptr[t] + lane; e < cx_ptr[t + 1]; e += G) acc += cx_val[e] * u[cx_col[e]];
-      }
-      for (int m = G / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, G);
-      if (active && lane == 0 && mask[t]) {
-        int li = (iy - wy0) * W + (ix - wx0);
-        sU[li] = sU[li] + (f[t] - acc) * invd[t];
-      }
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < tx * ty; i += blockDim.x) {
-    int iy = y0 + i / tx, ix = x0 + i % tx;
-    u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
-  }
-}
-
-// One wavefront per tile (T = 2(p+1)): the four unknowns of a colour class
-// are updated by four groups of 16 lanes; the row sum of each group comes out
-// of a DPP scan in its last lane.  A single wavefront executes its LDS
-// operations in program order, so a class reads the values the previous
-// class wrote without a barrier.  Stencil rows of the next D classes are
-// prefetched into registers; f minus the cross-patch couplings and 1/a_ii
-// sit in LDS as one 16-byte pair per unknown.
-template <int P>
+template <typename T, int P>
 __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, const PatchDev *pd,
-                                                       const double *__restrict__ st,
-                                                       const double *__restrict__ invd,
+                                                       const T *__restrict__ st,
+                                                       const T *__restrict__ invd,
                                                        const int *__restrict__ cx_li,
                                                        const int *__restrict__ cx_col,
-                                                       const double *__restrict__ cx_val,
-                                                       const double *__restrict__ f, double *u,
-                                                       const unsigned char *__restrict__ mask,
-                                                       int backward) {
-  constexpr int Q1 = P + 1, T = 2 * Q1, W = T + 2 * P;
+                                                       const T *__restrict__ cx_val,
+                                                       const T *__restrict__ f, T *u,
+                                                       int backward, long long vs) {
+  using T2 = typename Pair2<T>::type;
+  constexpr int Q1 = P + 1, TT = 2 * Q1, W = TT + 2 * P;
   constexpr int S1 = 2 * P + 1, S = S1 * S1;
   constexpr int C = (S + 15) / 16;
   constexpr int SP = 16 * C;  // padded row length (zero coefficients beyond S)
   constexpr int NPH = Q1 * Q1;
-  constexpr int D0 = 48 / C;
+  constexpr int D0 = (sizeof(T) == 8 ? 48 : 96) / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
-  __shared__ double sU[W * W];
-  __shared__ double2 sBD[T * T];
+  __shared__ T sU[W * W];
+  __shared__ T2 sBD[TT * TT];
   __shared__ int sOff[C * 16];
   const GsTile tl = tiles[blockIdx.x];
   const PatchDev &pt = pd[tl.patch];
+  f += (long long)blockIdx.y * vs;
+  u += (long long)blockIdx.y * vs;
   const int nx = pt.n[0], ny = pt.n[1];
   const int x0 = tl.i0[0], y0 = tl.i0[1];
   const int wx0 = x0 - P, wy0 = y0 - P;
@@ -508,37 +451,37 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
   const int lane = threadIdx.x, grp = lane >> 4, l16 = lane & 15;
   const int ax = (grp & 1) * Q1, ay = (grp >> 1) * Q1;
   // Prologue: every global load that does not depend on another one is issued
-  // before the first wait (u window, f, 1/a_ii -- zero on Dirichlet unknowns
-  // by construction -- and the cross-coupling lists); u at the cross columns
+  // before the first wait (u window, f, 1/a_ii -- zero on Dirichlet unknowns by
+  // construction -- and the cross-coupling lists); u at the cross columns
   // follows in a second round.
-  constexpr int NW = (W * W + 63) / 64, NT = (T * T + 63) / 64;
-  double wv[NW], fv[NT], dv[NT];
+  constexpr int NW = (W * W + 63) / 64, NT = (TT * TT + 63) / 64;
+  T wv[NW], fv[NT], dv[NT];
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
     const int i = lane + 64 * j;
     const int gy = wy0 + i / W, gx = wx0 + i % W;
     const bool ok = i < W * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    wv[j] = ok ? u[off + (long long)gy * nx + gx] : 0.0;
+    wv[j] = ok ? u[off + (long long)gy * nx + gx] : (T)0;
   }
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int i = lane + 64 * j;
-    const int iy = y0 + i / T, ix = x0 + i % T;
-    const bool ok = i < T * T && ix < nx && iy < ny;
+    const int iy = y0 + i / TT, ix = x0 + i % TT;
+    const bool ok = i < TT * TT && ix < nx && iy < ny;
     const long long t = off + (long long)iy * nx + ix;
-    fv[j] = ok ? f[t] : 0.0;
-    dv[j] = ok ? invd[t] : 0.0;
+    fv[j] = ok ? f[t] : (T)0;
+    dv[j] = ok ? invd[t] : (T)0;
   }
   const int ncx = tl.cx_n < 64 * 8 ? tl.cx_n : 64 * 8;
   int cl[8], cc[8];
-  double cv[8], cu[8];
+  T cv[8], cu[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int e = lane + 64 * j;
     const bool ok = e < ncx;
     cl[j] = ok ? cx_li[tl.cx_off + e] : -1;
     cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
-    cv[j] = ok ? cx_val[tl.cx_off + e] : 0.0;
+    cv[j] = ok ? cx_val[tl.cx_off + e] : (T)0;
   }
 #pragma unroll
   for (int j = 0; j < 8; ++j) cu[j] = u[cc[j]];
@@ -547,7 +490,12 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
     if (lane + 64 * j < W * W) sU[lane + 64 * j] = wv[j];
 #pragma unroll
   for (int j = 0; j < NT; ++j)
-    if (lane + 64 * j < T * T) sBD[lane + 64 * j] = make_double2(fv[j], dv[j]);
+    if (lane + 64 * j < TT * TT) {
+      T2 bd;
+      bd.x = fv[j];
+      bd.y = dv[j];
+      sBD[lane + 64 * j] = bd;
+    }
   for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
   __syncthreads();
 #pragma unroll
@@ -565,10 +513,10 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
     const long long t = ok ? off + (long long)iy * nx + ix : off + (long long)y0 * nx + x0;
     return st + t * SP + l16;
   };
-  double buf[D][C];
+  T buf[D][C];
 #pragma unroll
   for (int s = 0; s < D; ++s) {
-    const double *srow = row_ptr(s);
+    const T *srow = row_ptr(s);
 #pragma unroll
     for (int c = 0; c < C; ++c) buf[s][c] = srow[16 * c];
   }
@@ -581,31 +529,31 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
     const int ph = backward ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
     const int wi = (iy - wy0) * W + (ix - wx0);
-    const int li = (iy - y0) * T + (ix - x0);
-    double uv[C];
+    const int li = (iy - y0) * TT + (ix - x0);
+    T uv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) uv[c] = sU[wi + soff[c]];
-    const double uold = sU[wi];
-    const double2 bd = sBD[li];
+    const T uold = sU[wi];
+    const T2 bd = sBD[li];
     // u + (b - a.u) d, split so that the LDS reads are consumed before the scan
-    double ubd = fma(bd.x, bd.y, uold);
+    T ubd = fma(bd.x, bd.y, uold);
     asm volatile("" : "+v"(ubd));  // keep these reads in the batch of this class
-    double acc = 0.0;
+    T acc = 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) acc += buf[s % D][c] * uv[c];
     if (s + D < NPH) {
-      const double *srow = row_ptr(s + D);
+      const T *srow = row_ptr(s + D);
 #pragma unroll
       for (int c = 0; c < C; ++c) buf[s % D][c] = srow[16 * c];
     }
-    acc = row16_scan_fast(acc);
+    acc = row16_scan(acc);
     if (l16 == 15 && ix < nx && iy < ny) sU[wi] = fma(-acc, bd.y, ubd);
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
   }
   __syncthreads();
-  for (int i = lane; i < T * T; i += 64) {
-    int iy = y0 + i / T, ix = x0 + i % T;
+  for (int i = lane; i < TT * TT; i += 64) {
+    int iy = y0 + i / TT, ix = x0 + i % TT;
     if (ix < nx && iy < ny) u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
   }
 }
@@ -615,21 +563,21 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
 // 256 threads owns 16 rows: thread (rg, cg) accumulates rows 4rg..4rg+3 and
 // columns cg + 64j; B is streamed through LDS in chunks of 8 rows with the
 // next chunk held in registers while the current one is used.
+// grid.x = row block, grid.y = item (patch), grid.z = right-hand side.
 // ---------------------------------------------------------------------------
-template <int NJ>
-__device__ inline void rowblock_product(const double *A, int lda, const double *__restrict__ B,
-                                        long long b_r, int K, int N, double *sM,
-                                        double acc[4][NJ]) {
-  constexpr int WB = 64 * NJ;      // LDS row length of a chunk
-  constexpr int LPT = 2 * NJ;      // 8 * WB / 256 loads per thread
+template <typename T, int NJ>
+__device__ inline void rowblock_product(const T *A, int lda, const T *__restrict__ B, long long b_r,
+                                        int K, int N, T *sM, T acc[4][NJ]) {
+  constexpr int WB = 64 * NJ;  // LDS row length of a chunk
+  constexpr int LPT = 2 * NJ;  // 8 * WB / 256 loads per thread
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
-  double pre[LPT];
+  T pre[LPT];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int x = 0; x < LPT; ++x) {
       const int e = tid + 256 * x;
       const int kk = e / WB, col = e % WB;
-      pre[x] = (k0 + kk < K && col < N) ? B[(long long)(k0 + kk) * b_r + col] : 0.0;
+      pre[x] = (k0 + kk < K && col < N) ? B[(long long)(k0 + kk) * b_r + col] : (T)0;
     }
   };
   gload(0);
@@ -644,7 +592,7 @@ __device__ inline void rowblock_product(const double *A, int lda, const double *
     if (k0 + 8 < K) gload(k0 + 8);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      double a[4], b[NJ];
+      T a[4], b[NJ];
 #pragma unroll
       for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk];
 #pragma unroll
@@ -657,37 +605,40 @@ __device__ inline void rowblock_product(const double *A, int lda, const double *
   }
 }
 
-template <int NJ>
-__global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pad) {
+template <typename T, int NJ>
+__global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K1pad) {
   constexpr int WB = 64 * NJ;
-  extern __shared__ double sm[];
-  const Fd2Item it = items[blockIdx.y];
+  extern __shared__ char smraw[];
+  T *sm = (T *)smraw;
+  const Fd2Item<T> it = items[blockIdx.y];
   const int i0 = blockIdx.x * 16;
   if (i0 >= it.rows) return;
-  double *sL = sm;                 // 16 x (K1pad + 8), zero padded
-  double *sZ = sL + 16 * (K1pad + 8);  // 16 x WB
-  double *sM = sZ + 16 * WB;       // 8 x WB
+  const T *M1 = it.M1 + (long long)blockIdx.z * it.m1_z;
+  T *O = it.O + (long long)blockIdx.z * it.o_z;
+  T *sL = sm;                     // 16 x (K1pad + 8), zero padded
+  T *sZ = sL + 16 * (K1pad + 8);  // 16 x WB
+  T *sM = sZ + 16 * WB;           // 8 x WB
   const int lda = K1pad + 8;
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
   const int nrow = min(16, it.rows - i0);
   for (int e = tid; e < 16 * lda; e += 256) {
     const int i = e / lda, a = e % lda;
-    sL[e] = (i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : 0.0;
+    sL[e] = (i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : (T)0;
   }
-  double acc[4][NJ];
+  T acc[4][NJ];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[r][j] = 0.0;
-  rowblock_product<NJ>(sL, lda, it.M1, it.m1_r, it.K1, it.N, sM, acc);
+    for (int j = 0; j < NJ; ++j) acc[r][j] = 0;
+  rowblock_product<T, NJ>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       sZ[(4 * rg + r) * WB + cg + 64 * j] = acc[r][j];
-      acc[r][j] = 0.0;
+      acc[r][j] = 0;
     }
-  rowblock_product<NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
+  rowblock_product<T, NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = 4 * rg + r;
@@ -696,8 +647,8 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pa
     for (int j = 0; j < NJ; ++j) {
       const int col = cg + 64 * j;
       if (col >= it.N) continue;
-      double v = acc[r][j];
-      double *o = it.O + (long long)(i0 + i) * it.o_r + col;
+      T v = acc[r][j];
+      T *o = O + (long long)(i0 + i) * it.o_r + col;
       if (it.lam_r)
         *o = v / (it.sigma + it.lam_r[i0 + i] + it.lam_c[col]);
       else
@@ -712,13 +663,13 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item *items, int K1pa
 // 64 lanes read 64 consecutive entries of column j (= row j, by symmetry);
 // the 16 partial sums are added in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
-__device__ inline double block_rows_matvec(const double *M, int n, int row0, const double *sr,
-                                           double *spart) {
+template <typename T>
+__device__ inline T block_rows_matvec(const T *M, int n, int row0, const T *sr, T *spart) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = row0 + lane;
-  double s0 = 0.0, s1 = 0.0;
+  T s0 = 0, s1 = 0;
   if (i < n) {
-    const double *col = M + i;
+    const T *col = M + i;
     int j = w;
     for (; j + 16 < n; j += 32) {
       s0 += col[(long long)j * n] * sr[j];
@@ -728,89 +679,102 @@ __device__ inline double block_rows_matvec(const double *M, int n, int row0, con
   }
   spart[w * 64 + lane] = s0 + s1;
   __syncthreads();
-  double y = 0.0;
+  T y = 0;
   if (w == 0)
     for (int k = 0; k < 16; ++k) y += spart[k * 64 + lane];
   return y;  // valid in wavefront 0
 }
 
-// interface pieces: u[copies] += tau inv(P^T A P) r[piece]; grid (piece, row block)
+// interface pieces: u[copies] += tau inv(P^T A P) r[piece];
+// grid (piece, row block, right-hand side)
+template <typename T>
 __global__ __launch_bounds__(1024) void piece_kernel(const PieceDev *pieces, const int *idx,
-                                                     const int *cp, const int *cidx,
-                                                     const double *inv, const double *r, double *u,
-                                                     double scale) {
-  extern __shared__ double sm[];
-  __shared__ double spart[16 * 64];
+                                                     const int *cp, const int *cidx, const T *inv,
+                                                     const T *r, T *u, T scale, long long vs) {
+  extern __shared__ char smraw[];
+  T *sm = (T *)smraw;
+  __shared__ T spart[16 * 64];
   const PieceDev pc = pieces[blockIdx.x];
   const int n = pc.n;
   const int row0 = blockIdx.y * 64;
   if (row0 >= n) return;
+  r += (long long)blockIdx.z * vs;
+  u += (long long)blockIdx.z * vs;
   for (int j = threadIdx.x; j < n; j += blockDim.x) sm[j] = r[idx[pc.idx_off + j]];
   __syncthreads();
-  const double y = block_rows_matvec(inv + pc.inv_off, n, row0, sm, spart);
+  const T y = block_rows_matvec<T>(inv + pc.inv_off, n, row0, sm, spart);
   const int i = row0 + (int)threadIdx.x;
   if (threadIdx.x < 64 && i < n)
     for (int c = cp[pc.cp_off + i]; c < cp[pc.cp_off + i + 1]; ++c) u[cidx[c]] += scale * y;
 }
 
-// coarse solve: gather (sum of copies), dense symmetric inverse, scatter to all copies
+// coarse solve in float64 whatever T: gather (sum of copies), dense symmetric
+// inverse, scatter to all copies; grid (row block, right-hand side)
+template <typename T>
 __global__ __launch_bounds__(1024) void coarse_kernel(int n, const double *inv, const int *cp,
-                                                      const int *cidx, const double *f, double *u) {
-  extern __shared__ double sm[];
+                                                      const int *cidx, const T *f, T *u,
+                                                      long long vs) {
+  extern __shared__ char smraw[];
+  double *sm = (double *)smraw;
   __shared__ double spart[16 * 64];
+  f += (long long)blockIdx.y * vs;
+  u += (long long)blockIdx.y * vs;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double s = 0.0;
-    for (int c = cp[i]; c < cp[i + 1]; ++c) s += f[cidx[c]];
+    for (int c = cp[i]; c < cp[i + 1]; ++c) s += (double)f[cidx[c]];
     sm[i] = s;
   }
   __syncthreads();
   const int row0 = blockIdx.x * 64;
-  const double y = block_rows_matvec(inv, n, row0, sm, spart);
+  const double y = block_rows_matvec<double>(inv, n, row0, sm, spart);
   const int i = row0 + (int)threadIdx.x;
   if (threadIdx.x < 64 && i < n)
-    for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = y;
+    for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = (T)y;
 }
 
 // ---------------------------------------------------------------------------
 // transfers (2D): restriction r_c = P^T (w r_f), prolongation u_f += P e_c.
 // The 1D factors are banded (at most MAXW entries per row / column); the band
-// of the thread's unknown is held in registers.
+// of the thread's unknown is held in registers.  grid.y = right-hand side.
 // ---------------------------------------------------------------------------
 constexpr int MAXW = 12;
 
+template <typename T>
 __global__ __launch_bounds__(256) void restrict2d_kernel(const PatchDev *pf, const PatchDev *pc,
-                                                         int K, const int *Rlo, const double *Rval,
-                                                         int RW, const double *rf,
-                                                         const double *wf,
+                                                         int K, const int *Rlo, const T *Rval,
+                                                         int RW, const T *rf, const T *wf,
                                                          const unsigned char *maskc,
-                                                         long long nc_tot, double *rc,
-                                                         double *uc_zero) {
+                                                         long long nc_tot, T *rc, T *uc_zero,
+                                                         long long vsf) {
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= nc_tot) return;
-  if (uc_zero) uc_zero[t] = 0.0;  // zero initial guess of the coarse cycle
+  const long long zc = (long long)blockIdx.y * nc_tot;
+  rf += (long long)blockIdx.y * vsf;
+  rc += zc;
+  if (uc_zero) uc_zero[zc + t] = 0;  // zero initial guess of the coarse cycle
   int k = 0;
   while (k + 1 < K && pc[k + 1].off <= t) ++k;
   const PatchDev &C = pc[k], &F = pf[k];
   if (!maskc[t]) {
-    rc[t] = 0.0;
+    rc[t] = 0;
     return;
   }
   long long loc = t - C.off;
   const int jx = (int)(loc % C.n[0]), jy = (int)(loc / C.n[0]);
   const int rx = F.xr[0] + jx, ry = F.xr[1] + jy;
   const int lx = Rlo[rx], ly = Rlo[ry];
-  double vx[MAXW], vy[MAXW];
+  T vx[MAXW], vy[MAXW];
 #pragma unroll
   for (int a = 0; a < MAXW; ++a) {
-    vx[a] = a < RW ? Rval[(long long)rx * RW + a] : 0.0;
-    vy[a] = a < RW ? Rval[(long long)ry * RW + a] : 0.0;
+    vx[a] = a < RW ? Rval[(long long)rx * RW + a] : (T)0;
+    vy[a] = a < RW ? Rval[(long long)ry * RW + a] : (T)0;
   }
-  double s = 0.0;
+  T s = 0;
 #pragma unroll
   for (int a = 0; a < MAXW; ++a) {
     const int iy = ly + a;
     if (a < RW && iy < F.n[1]) {
-      double sx = 0.0;
+      T sx = 0;
       const long long rowoff = F.off + (long long)iy * F.n[0];
 #pragma unroll
       for (int b = 0; b < MAXW; ++b) {
@@ -823,13 +787,16 @@ __global__ __launch_bounds__(256) void restrict2d_kernel(const PatchDev *pf, con
   rc[t] = s;
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void prolong2d_kernel(const PatchDev *pf, const PatchDev *pc,
-                                                        int K, const int *Plo, const double *Pval,
-                                                        int PW, const double *ec,
+                                                        int K, const int *Plo, const T *Pval,
+                                                        int PW, const T *ec,
                                                         const unsigned char *maskf,
-                                                        long long nf_tot, double *uf) {
+                                                        long long nf_tot, T *uf, long long vsc) {
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= nf_tot) return;
+  ec += (long long)blockIdx.y * vsc;
+  uf += (long long)blockIdx.y * nf_tot;
   int k = 0;
   while (k + 1 < K && pf[k + 1].off <= t) ++k;
   const PatchDev &F = pf[k], &C = pc[k];
@@ -838,18 +805,18 @@ __global__ __launch_bounds__(256) void prolong2d_kernel(const PatchDev *pf, cons
   const int ix = (int)(loc % F.n[0]), iy = (int)(loc / F.n[0]);
   const int px = F.xp[0] + ix, py = F.xp[1] + iy;
   const int lx = Plo[px], ly = Plo[py];
-  double vx[MAXW], vy[MAXW];
+  T vx[MAXW], vy[MAXW];
 #pragma unroll
   for (int a = 0; a < MAXW; ++a) {
-    vx[a] = a < PW ? Pval[(long long)px * PW + a] : 0.0;
-    vy[a] = a < PW ? Pval[(long long)py * PW + a] : 0.0;
+    vx[a] = a < PW ? Pval[(long long)px * PW + a] : (T)0;
+    vy[a] = a < PW ? Pval[(long long)py * PW + a] : (T)0;
   }
-  double s = 0.0;
+  T s = 0;
 #pragma unroll
   for (int a = 0; a < MAXW; ++a) {
     const int jy = ly + a;
     if (a < PW && jy < C.n[1]) {
-      double sx = 0.0;
+      T sx = 0;
       const long long rowoff = C.off + (long long)jy * C.n[0];
 #pragma unroll
       for (int b = 0; b < MAXW; ++b) {
@@ -863,20 +830,24 @@ __global__ __launch_bounds__(256) void prolong2d_kernel(const PatchDev *pf, cons
 }
 
 // ---------------------------------------------------------------------------
-// compact <-> torn
+// compact <-> torn (grid.y = right-hand side)
 // ---------------------------------------------------------------------------
 __global__ void scatter_compact_kernel(const double *xc, long long N, const int *cp, const int *cidx,
-                                       double *xt) {
+                                       double *xt, long long nt) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= N) return;
+  xc += (long long)blockIdx.y * N;
+  xt += (long long)blockIdx.y * nt;
   double v = xc[i];
   for (int c = cp[i]; c < cp[i + 1]; ++c) xt[cidx[c]] = v;
 }
 
 __global__ void gather_compact_kernel(const double *xt, long long N, const int *cp, const int *cidx,
-                                      int sum, double *xc) {
+                                      int sum, double *xc, long long nt) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= N) return;
+  xc += (long long)blockIdx.y * N;
+  xt += (long long)blockIdx.y * nt;
   if (!sum) {
     xc[i] = xt[cidx[cp[i]]];
     return;
@@ -887,10 +858,10 @@ __global__ void gather_compact_kernel(const double *xt, long long N, const int *
 }
 
 // ---------------------------------------------------------------------------
-// deterministic reductions: fixed grid, fixed-order trees
+// deterministic reductions: fixed grid, fixed-order trees.  Partials of
+// right-hand side j sit at part[j * RED_BLOCKS ...]; the final kernels run
+// one block per right-hand side.
 // ---------------------------------------------------------------------------
-constexpr int RED_BLOCKS = 512;
-
 __device__ inline double block_sum(double v, double *sh) {
   const int tid = threadIdx.x;
   sh[tid] = v;
@@ -908,18 +879,22 @@ __global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const
                                                           const double *w, long long n,
                                                           double *part) {
   __shared__ double sh[256];
+  a += (long long)blockIdx.y * n;
+  b += (long long)blockIdx.y * n;
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     s += (w ? w[i] : 1.0) * a[i] * b[i];
   double t = block_sum(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
 // mode 0: scal[slot] = sum; 1: alpha = rz / sum; 2: beta = sum / rz, rz = sum
 __global__ __launch_bounds__(256) void dot_final_kernel(const double *part, int nb, double *scal,
                                                         int slot, int mode) {
   __shared__ double sh[256];
+  part += (long long)blockIdx.x * nb;
+  scal += (long long)blockIdx.x * S_COUNT;
   double s = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
   double t = block_sum(s, sh);
@@ -933,30 +908,84 @@ __global__ __launch_bounds__(256) void dot_final_kernel(const double *part, int 
   }
 }
 
+// flexible CG (Polak-Ribiere form): partial sums of (z, r) and (z, r_old)
+__global__ __launch_bounds__(256) void dot2_partial_kernel(const double *z, const double *r,
+                                                           const double *ro, const double *w,
+                                                           long long n, double *part) {
+  __shared__ double sh[256];
+  const long long zo = (long long)blockIdx.y * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double zw = w[i] * z[zo + i];
+    s1 += zw * r[zo + i];
+    s2 += zw * ro[zo + i];
+  }
+  double t1 = block_sum(s1, sh);
+  double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    const long long k = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * k] = t1;
+    part[2 * k + 1] = t2;
+  }
+}
+
+__global__ __launch_bounds__(256) void dot2_final_kernel(const double *part, int nb, double *scal) {
+  __shared__ double sh[256];
+  part += (long long)blockIdx.x * nb * 2;
+  scal += (long long)blockIdx.x * S_COUNT;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    s1 += part[2 * i];
+    s2 += part[2 * i + 1];
+  }
+  double t1 = block_sum(s1, sh);
+  double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    scal[S_BETA] = (t1 - t2) / scal[S_RZ];
+    scal[S_RZ] = t1;
+    scal[S_ZRO] = t2;
+  }
+}
+
+// x += alpha p, r -= alpha q on the right-hand sides still iterating (r_old
+// keeps r before the update when given); ||r||_w^2 partials for all; z = 0
 __global__ __launch_bounds__(256) void pcg_xr_kernel(double *x, double *r, const double *p,
                                                      const double *q, const double *w, long long n,
                                                      const double *scal, double *part,
-                                                     double *z_zero) {
+                                                     double *z_zero, double *rold,
+                                                     const int *active) {
   __shared__ double sh[256];
-  const double alpha = scal[S_ALPHA];
+  const int j = blockIdx.y;
+  const long long zo = (long long)j * n;
+  const bool act = active[j] != 0;
+  const double alpha = scal[(long long)j * S_COUNT + S_ALPHA];
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    z_zero[i] = 0.0;
-    x[i] += alpha * p[i];
-    double ri = r[i] - alpha * q[i];
-    r[i] = ri;
+    z_zero[zo + i] = 0.0;
+    double ri = r[zo + i];
+    if (act) {
+      if (rold) rold[zo + i] = ri;
+      x[zo + i] += alpha * p[zo + i];
+      ri -= alpha * q[zo + i];
+      r[zo + i] = ri;
+    }
     s += w[i] * ri * ri;
   }
   double t = block_sum(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) part[(long long)j * gridDim.x + blockIdx.x] = t;
 }
 
-__global__ void pcg_p_kernel(double *p, const double *z, long long n, const double *scal) {
-  const double beta = scal[S_BETA];
+__global__ void pcg_p_kernel(double *p, const double *z, long long n, const double *scal,
+                             const int *active) {
+  const int j = blockIdx.y;
+  if (!active[j]) return;
+  const long long zo = (long long)j * n;
+  const double beta = scal[(long long)j * S_COUNT + S_BETA];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+    p[zo + i] = z[zo + i] + beta * p[zo + i];
 }
 
 }  // namespace
@@ -964,26 +993,36 @@ __global__ void pcg_p_kernel(double *p, const double *z, long long n, const doub
 // ===========================================================================
 // launchers
 // ===========================================================================
-void k_fill(double *x, double v, long long n, hipStream_t s) {
-  fill_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, s>>>(x, v, n);
+template <typename T>
+void k_fill(T *x, T v, long long n, hipStream_t s) {
+  fill_kernel<T><<<std::min<unsigned>(nblocks(n), 4096), BS, 0, s>>>(x, v, n);
 }
-void k_copy_weighted(const double *x, const double *w, double *y, long long n, hipStream_t s) {
-  copy_weighted_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, s>>>(x, w, y, n);
-}
-void k_axpy(double a, const double *x, double *y, long long n, hipStream_t s) {
-  axpy_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, s>>>(a, x, y, n);
-}
+template void k_fill<double>(double *, double, long long, hipStream_t);
+template void k_fill<float>(float *, float, long long, hipStream_t);
 
-void k_stencil_assemble(Context &c, LevelData &L) {
+template <typename Ti, typename To>
+void k_convert(const Ti *x, const To *w, To *y, long long n, int nrhs, hipStream_t s, To *zero,
+               const int *active) {
+  dim3 grid(std::min<unsigned>(nblocks(n), 2048), nrhs);
+  convert_kernel<Ti, To><<<grid, BS, 0, s>>>(x, w, y, n, zero, active);
+}
+template void k_convert<double, double>(const double *, const double *, double *, long long, int,
+                                        hipStream_t, double *, const int *);
+template void k_convert<double, float>(const double *, const float *, float *, long long, int,
+                                       hipStream_t, float *, const int *);
+template void k_convert<float, double>(const float *, const double *, double *, long long, int,
+                                       hipStream_t, double *, const int *);
+
+void k_stencil_assemble(Context &c, LevelData &L, double *out) {
   int S = 1;
   for (int d = 0; d < c.d; ++d) S *= (2 * c.p + 1);
   long long tot = L.Ntorn * ((S + 15) / 16 * 16);
   if (c.d == 2)
     stencil_kernel<2><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
-                                                         L.Ntorn, L.d_stencil);
+                                                         L.Ntorn, out);
   else
     stencil_kernel<3><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
-                                                         L.Ntorn, L.d_stencil);
+                                                         L.Ntorn, out);
   HIPCHK(hipGetLastError());
 }
 
@@ -1007,65 +1046,70 @@ void k_load_manufactured(Context &c, LevelData &L, double *out) {
                                                           L.d_mask, L.Ntorn, out);
 }
 
-void k_iface_apply(Context &c, LevelData &L, const double *u, const double *f, const double *fw,
-                   double beta, double alpha, double *r) {
+template <typename T>
+void k_iface_apply(Context &c, LevelData &L, const T *u, const T *f, const T *fw, T beta, T alpha,
+                   T *r, int nrhs) {
   TimeScope ts(c, "iface_apply", L.l);
   const int nb_plain = (int)nblocks(L.Ntorn);
   const int nb_rows = (L.n_if_rows + 15) / 16;
-  iface_kernel<<<nb_plain + nb_rows, BS, 0, c.stream>>>(
-      L.Ntorn, nb_plain, L.d_mask, L.d_has_if, L.d_if_rows, L.n_if_rows, L.d_if_ptr, L.d_if_col,
-      L.d_if_val, u, f, fw, beta, alpha, r);
+  dim3 grid(nb_plain + nb_rows, nrhs);
+  iface_kernel<T><<<grid, BS, 0, c.stream>>>(L.Ntorn, nb_plain, L.d_mask, L.d_has_if, L.d_if_rows,
+                                             L.n_if_rows, L.d_if_ptr, L.d_if_col,
+                                             L.arr<T>().if_val, u, f, fw, beta, alpha, r);
 }
-
-template <int P, int TE>
-static void launch_vol2d(Context &c, LevelData &L, const double *u, double *r, double alpha) {
-  vol2d_kernel<P, TE><<<L.n_vtiles, 256, 0, c.stream>>>(L.d_vtiles, L.d_pd, L.d_tabB, L.d_tabD,
-                                                        c.gr, u, r, L.d_mask, alpha);
-}
+template void k_iface_apply<double>(Context &, LevelData &, const double *, const double *,
+                                    const double *, double, double, double *, int);
+template void k_iface_apply<float>(Context &, LevelData &, const float *, const float *,
+                                   const float *, float, float, float *, int);
 
 int vol_tile_2d(int p) { return p <= 4 ? 8 : (p <= 6 ? 6 : 4); }
 
-void k_vol_apply(Context &c, LevelData &L, const double *u, double *r, double alpha) {
+template <typename T, int P, int TE>
+static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
+  dim3 grid(L.n_vtiles, nrhs);
+  vol2d_kernel<T, P, TE><<<grid, 256, 0, c.stream>>>(L.d_vtiles, L.d_pd, L.d_tabB, L.d_tabD, c.gr,
+                                                     u, r, L.d_mask, alpha, L.Ntorn);
+}
+
+template <typename T>
+void k_vol_apply(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
   TimeScope ts(c, "vol_apply", L.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D volume operator not built");
   switch (c.p) {
-    case 1: launch_vol2d<1, 8>(c, L, u, r, alpha); break;
-    case 2: launch_vol2d<2, 8>(c, L, u, r, alpha); break;
-    case 3: launch_vol2d<3, 8>(c, L, u, r, alpha); break;
-    case 4: launch_vol2d<4, 8>(c, L, u, r, alpha); break;
-    case 5: launch_vol2d<5, 6>(c, L, u, r, alpha); break;
-    case 6: launch_vol2d<6, 6>(c, L, u, r, alpha); break;
-    case 7: launch_vol2d<7, 4>(c, L, u, r, alpha); break;
-    case 8: launch_vol2d<8, 4>(c, L, u, r, alpha); break;
+    case 1: launch_vol2d<T, 1, 8>(c, L, u, r, alpha, nrhs); break;
+    case 2: launch_vol2d<T, 2, 8>(c, L, u, r, alpha, nrhs); break;
+    case 3: launch_vol2d<T, 3, 8>(c, L, u, r, alpha, nrhs); break;
+    case 4: launch_vol2d<T, 4, 8>(c, L, u, r, alpha, nrhs); break;
+    case 5: launch_vol2d<T, 5, 6>(c, L, u, r, alpha, nrhs); break;
+    case 6: launch_vol2d<T, 6, 6>(c, L, u, r, alpha, nrhs); break;
+    case 7: launch_vol2d<T, 7, 4>(c, L, u, r, alpha, nrhs); break;
+    case 8: launch_vol2d<T, 8, 4>(c, L, u, r, alpha, nrhs); break;
     default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
   }
 }
+template void k_vol_apply<double>(Context &, LevelData &, const double *, double *, double, int);
+template void k_vol_apply<float>(Context &, LevelData &, const float *, float *, float, int);
 
-void k_glue_sum(LevelData &L, double *y, hipStream_t s) {
+template <typename T>
+void k_glue_sum(LevelData &L, T *y, int nrhs, hipStream_t s) {
   if (L.n_glue == 0) return;
-  glue_kernel<<<nblocks(L.n_glue), BS, 0, s>>>(L.n_glue, L.d_glue_ptr, L.d_glue_idx, y);
+  dim3 grid(nblocks(L.n_glue), nrhs);
+  glue_kernel<T><<<grid, BS, 0, s>>>(L.n_glue, L.d_glue_ptr, L.d_glue_idx, y, L.Ntorn);
+}
+template void k_glue_sum<double>(LevelData &, double *, int, hipStream_t);
+template void k_glue_sum<float>(LevelData &, float *, int, hipStream_t);
+
+template <typename T, int P>
+static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
+  LevelArrays<T> &A = L.arr<T>();
+  dim3 grid(cl.count, nrhs);
+  gs2d_wave_kernel<T, P><<<grid, 64, 0, c.stream>>>(cl.tiles, L.d_pd, A.stencil, A.invdiag,
+                                                    L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
+                                                    backward ? 1 : 0, L.Ntorn);
 }
 
-template <int P>
-static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward) {
-  int T = c.opt.gs_tile;
-  if (T == 2 * (P + 1)) {
-    gs2d_wave_kernel<P><<<cl.count, 64, 0, c.stream>>>(cl.tiles, L.d_pd, L.d_stencil, L.d_invdiag,
-                                                       L.d_gcx_li, L.d_gcx_col, L.d_gcx_val, L.f,
-                                                       L.u, L.d_mask, backward ? 1 : 0);
-    return;
-  }
-  int W = T + 2 * P;
-  int rows = ((T + P) / (P + 1)) * ((T + P) / (P + 1));
-  int G = 64;
-  while (G > 1 && rows * G > 256) G >>= 1;
-  if (G > 64) G = 64;
-  gs2d_kernel<P><<<cl.count, 256, (size_t)W * W * sizeof(double), c.stream>>>(
-      cl.tiles, L.d_pd, L.d_stencil, L.d_invdiag, L.d_cx_ptr, L.d_cx_col, L.d_cx_val, L.f, L.u,
-      L.d_mask, T, backward ? 1 : 0, G);
-}
-
-void k_gs_sweep(Context &c, LevelData &L, bool backward) {
+template <typename T>
+void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs) {
   // one event pair around the sweep (its class launches run back to back)
   TimeScope ts(c, "gauss_seidel", L.l);
   ts.n = 0;
@@ -1075,101 +1119,135 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward) {
     if (cl.count == 0) continue;
     ++ts.n;
     switch (c.p) {
-      case 1: launch_gs2d<1>(c, L, cl, backward); break;
-      case 2: launch_gs2d<2>(c, L, cl, backward); break;
-      case 3: launch_gs2d<3>(c, L, cl, backward); break;
-      case 4: launch_gs2d<4>(c, L, cl, backward); break;
-      case 5: launch_gs2d<5>(c, L, cl, backward); break;
-      case 6: launch_gs2d<6>(c, L, cl, backward); break;
-      case 7: launch_gs2d<7>(c, L, cl, backward); break;
-      case 8: launch_gs2d<8>(c, L, cl, backward); break;
+      case 1: launch_gs2d<T, 1>(c, L, cl, backward, nrhs); break;
+      case 2: launch_gs2d<T, 2>(c, L, cl, backward, nrhs); break;
+      case 3: launch_gs2d<T, 3>(c, L, cl, backward, nrhs); break;
+      case 4: launch_gs2d<T, 4>(c, L, cl, backward, nrhs); break;
+      case 5: launch_gs2d<T, 5>(c, L, cl, backward, nrhs); break;
+      case 6: launch_gs2d<T, 6>(c, L, cl, backward, nrhs); break;
+      case 7: launch_gs2d<T, 7>(c, L, cl, backward, nrhs); break;
+      case 8: launch_gs2d<T, 8>(c, L, cl, backward, nrhs); break;
       default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
     }
   }
 }
+template void k_gs_sweep<double>(Context &, LevelData &, bool, int);
+template void k_gs_sweep<float>(Context &, LevelData &, bool, int);
 
-template <int NJ>
-static void launch_fd2(Context &c, LevelData &L, int stage) {
+template <typename T, int NJ>
+static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
   constexpr int WB = 64 * NJ;
-  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + 8 * WB) * sizeof(double);
-  dim3 grid((L.fd_rows + 15) / 16, L.n_fd);
-  fd2_kernel<NJ><<<grid, 256, lds, c.stream>>>(L.d_fd[stage], L.fd_K1);
+  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + 8 * WB) * sizeof(T);
+  dim3 grid((L.fd_rows + 15) / 16, L.n_fd, nrhs);
+  fd2_kernel<T, NJ><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], L.fd_K1);
 }
 
-void k_scms_interior(Context &c, LevelData &L) {
+template <typename T>
+void k_scms_interior(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "scms", L.l);
   if (L.n_fd == 0) return;
   const int nj = (L.fd_N + 63) / 64;
   for (int st = 0; st < 2; ++st) {
     switch (nj) {
-      case 1: launch_fd2<1>(c, L, st); break;
-      case 2: launch_fd2<2>(c, L, st); break;
-      case 3: launch_fd2<3>(c, L, st); break;
-      case 4: launch_fd2<4>(c, L, st); break;
-      case 5: launch_fd2<5>(c, L, st); break;
+      case 1: launch_fd2<T, 1>(c, L, st, nrhs); break;
+      case 2: launch_fd2<T, 2>(c, L, st, nrhs); break;
+      case 3: launch_fd2<T, 3>(c, L, st, nrhs); break;
+      case 4: launch_fd2<T, 4>(c, L, st, nrhs); break;
+      case 5: launch_fd2<T, 5>(c, L, st, nrhs); break;
       default: fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
     }
   }
 }
+template void k_scms_interior<double>(Context &, LevelData &, int);
+template void k_scms_interior<float>(Context &, LevelData &, int);
 
-void k_pieces(Context &c, LevelData &L, const double *r, double *u) {
+template <typename T>
+void k_pieces(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "pieces", L.l);
   if (L.n_pieces == 0) return;
-  dim3 grid(L.n_pieces, (L.max_piece + 63) / 64);
-  piece_kernel<<<grid, 1024, (size_t)L.max_piece * sizeof(double), c.stream>>>(
-      L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, L.d_piece_inv, r, u,
-      c.opt.damping_tau);
+  LevelArrays<T> &A = L.arr<T>();
+  dim3 grid(L.n_pieces, (L.max_piece + 63) / 64, nrhs);
+  piece_kernel<T><<<grid, 1024, (size_t)L.max_piece * sizeof(T), c.stream>>>(
+      L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, A.piece_inv, A.r, A.u,
+      (T)c.opt.damping_tau, L.Ntorn);
 }
+template void k_pieces<double>(Context &, LevelData &, int);
+template void k_pieces<float>(Context &, LevelData &, int);
 
-void k_restrict(Context &c, LevelData &F, LevelData &C, const double *rf, double *rc,
-                double *uc_zero) {
+template <typename T>
+void k_restrict(Context &c, LevelData &F, LevelData &C, const T *rf, T *rc, T *uc_zero, int nrhs) {
   TimeScope ts(c, "restrict", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
-  restrict2d_kernel<<<nblocks(C.Ntorn), BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_R_lo, F.d_R_val,
-                                                           F.RW, rf, F.d_weight, C.d_mask, C.Ntorn,
-                                                           rc, uc_zero);
+  dim3 grid(nblocks(C.Ntorn), nrhs);
+  restrict2d_kernel<T><<<grid, BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_R_lo, F.arr<T>().R_val,
+                                                  F.RW, rf, F.arr<T>().weight, C.d_mask, C.Ntorn,
+                                                  rc, uc_zero, F.Ntorn);
 }
+template void k_restrict<double>(Context &, LevelData &, LevelData &, const double *, double *,
+                                 double *, int);
+template void k_restrict<float>(Context &, LevelData &, LevelData &, const float *, float *, float *,
+                                int);
 
-void k_prolong_add(Context &c, LevelData &F, LevelData &C, const double *ec, double *uf) {
+template <typename T>
+void k_prolong_add(Context &c, LevelData &F, LevelData &C, const T *ec, T *uf, int nrhs) {
   TimeScope ts(c, "prolong", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
-  prolong2d_kernel<<<nblocks(F.Ntorn), BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_P_lo, F.d_P_val,
-                                                          F.PW, ec, F.d_mask, F.Ntorn, uf);
+  dim3 grid(nblocks(F.Ntorn), nrhs);
+  prolong2d_kernel<T><<<grid, BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_P_lo, F.arr<T>().P_val,
+                                                 F.PW, ec, F.d_mask, F.Ntorn, uf, C.Ntorn);
 }
+template void k_prolong_add<double>(Context &, LevelData &, LevelData &, const double *, double *,
+                                    int);
+template void k_prolong_add<float>(Context &, LevelData &, LevelData &, const float *, float *, int);
 
-void k_coarse_solve(Context &c, const double *f0, double *u0) {
+template <typename T>
+void k_coarse_solve(Context &c, const T *f0, T *u0, int nrhs) {
   TimeScope ts(c, "coarse", 0);
-  int nb = (c.N0 + 63) / 64;
-  coarse_kernel<<<nb, 1024, (size_t)c.N0 * sizeof(double), c.stream>>>(c.N0, c.d_A0inv, c.d_c0_cp,
-                                                                      c.d_c0_cidx, f0, u0);
+  dim3 grid((c.N0 + 63) / 64, nrhs);
+  coarse_kernel<T><<<grid, 1024, (size_t)c.N0 * sizeof(double), c.stream>>>(
+      c.N0, c.d_A0inv, c.d_c0_cp, c.d_c0_cidx, f0, u0, c.lv[0].Ntorn);
 }
+template void k_coarse_solve<double>(Context &, const double *, double *, int);
+template void k_coarse_solve<float>(Context &, const float *, float *, int);
 
 void k_scatter_compact(const double *xc, long long N, const int *cp, const int *cidx, double *xt,
-                       hipStream_t s) {
-  scatter_compact_kernel<<<nblocks(N), BS, 0, s>>>(xc, N, cp, cidx, xt);
+                       long long Ntorn, int nrhs, hipStream_t s) {
+  dim3 grid(nblocks(N), nrhs);
+  scatter_compact_kernel<<<grid, BS, 0, s>>>(xc, N, cp, cidx, xt, Ntorn);
 }
 
 void k_gather_compact(const double *xt, long long N, const int *cp, const int *cidx, int sum,
-                      double *xc, hipStream_t s) {
-  gather_compact_kernel<<<nblocks(N), BS, 0, s>>>(xt, N, cp, cidx, sum, xc);
+                      double *xc, long long Ntorn, int nrhs, hipStream_t s) {
+  dim3 grid(nblocks(N), nrhs);
+  gather_compact_kernel<<<grid, BS, 0, s>>>(xt, N, cp, cidx, sum, xc, Ntorn);
 }
 
-void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode) {
+void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode, int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
-  dot_partial_kernel<<<RED_BLOCKS, 256, 0, c.stream>>>(a, b, c.lv.back().d_weight, n, c.d_red);
-  dot_final_kernel<<<1, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, slot, mode);
+  dot_partial_kernel<<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(a, b, c.lv.back().a64.weight, n,
+                                                                    c.d_red);
+  dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, slot, mode);
 }
 
-void k_pcg_update_xr(Context &c, long long n) {
+void k_dot_fcg(Context &c, long long n, int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
-  pcg_xr_kernel<<<RED_BLOCKS, 256, 0, c.stream>>>(c.x, c.rr, c.pp, c.qq, c.lv.back().d_weight, n,
-                                                  c.d_scal, c.d_red, c.z);
-  dot_final_kernel<<<1, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
+  dot2_partial_kernel<<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
+      c.z, c.rr, c.rold, c.lv.back().a64.weight, n, c.d_red);
+  dot2_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal);
 }
 
-void k_pcg_update_p(Context &c, long long n) {
+void k_pcg_update_xr(Context &c, long long n, int nrhs, bool keep_rold) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
-  pcg_p_kernel<<<std::min<unsigned>(nblocks(n), 4096), BS, 0, c.stream>>>(c.pp, c.z, n, c.d_scal);
+  pcg_xr_kernel<<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
+      c.x, c.rr, c.pp, c.qq, c.lv.back().a64.weight, n, c.d_scal, c.d_red, c.z,
+      keep_rold ? c.rold : nullptr, c.d_active);
+  dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
+}
+
+void k_pcg_update_p(Context &c, long long n, int nrhs) {
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
+  dim3 grid(std::min<unsigned>(nblocks(n), 2048), nrhs);
+  pcg_p_kernel<<<grid, BS, 0, c.stream>>>(c.pp, c.z, n, c.d_scal, c.d_active);
 }
 
 }  // namespace igamg

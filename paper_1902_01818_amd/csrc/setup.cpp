@@ -68,6 +68,7 @@ Context::~Context() {
     }
   }
   if (h_scal) (void)hipHostFree(h_scal);
+  if (h_active) (void)hipHostFree(h_active);
   arena.release();
 }
 
@@ -648,7 +649,10 @@ static void build_pieces(Context &c, LevelData &L) {
   L.d_piece_idx = c.arena.upload(idx, c.stream);
   L.d_piece_cp = c.arena.upload(cp, c.stream);
   L.d_piece_cidx = c.arena.upload(cidx, c.stream);
-  L.d_piece_inv = c.arena.upload(inv, c.stream);
+  if (c.fp32())
+    L.a32.piece_inv = c.arena.upload_as<float>(inv, c.stream);
+  else
+    L.a64.piece_inv = c.arena.upload_as<double>(inv, c.stream);
 }
 
 static std::vector<double> transpose(const std::vector<double> &A, int n) {
@@ -663,11 +667,13 @@ static std::vector<double> transpose(const std::vector<double> &A, int n) {
 // diag(1/(sigma + lam_y + lam_x)) (Qy x Qx)^T r, evaluated as
 //   W = (Qy^T R Qx) ./ D   and   U += (tau/gamma) Qy W Qx^T
 // on the interior block R of the patch tensor.
+template <typename T>
 static void build_scms(Context &c, LevelData &L) {
   const int p = c.p;
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D SCMS not built");
+  LevelArrays<T> &A = L.arr<T>();
   struct QT {
-    double *Q, *QT, *lam;
+    T *Q, *QT, *lam;
   };
   std::map<int, QT> qtab;
   for (int k = 0; k < L.K; ++k)
@@ -677,45 +683,48 @@ static void build_scms(Context &c, LevelData &L) {
       std::vector<double> Q, lam;
       scms_factors_1d(ne, p, Q, lam);
       int n = ne + p - 2;
-      qtab[ne] = QT{c.arena.upload(Q, c.stream), c.arena.upload(transpose(Q, n), c.stream),
-                    c.arena.upload(lam, c.stream)};
+      qtab[ne] = QT{c.arena.upload_as<T>(Q, c.stream), c.arena.upload_as<T>(transpose(Q, n), c.stream),
+                    c.arena.upload_as<T>(lam, c.stream)};
     }
   size_t scr = 0;
   for (int k = 0; k < L.K; ++k) scr += (size_t)(L.pd[k].n[0] - 2) * (L.pd[k].n[1] - 2);
-  double *wbuf = c.arena.alloc<double>(scr);
-  std::vector<Fd2Item> fa, fb;
+  L.wscratch_n = (long long)scr;
+  A.wscratch = c.arena.alloc<T>(scr * c.nb);
+  std::vector<Fd2Item<T>> fa, fb;
   size_t so = 0;
   L.fd_rows = L.fd_K1 = L.fd_N = 0;
+  const long long nt = L.Ntorn, ns = (long long)scr;
   for (int k = 0; k < L.K; ++k) {
     PatchDev &pt = L.pd[k];
     const int nx = pt.n[0], mx = pt.n[0] - 2, my = pt.n[1] - 2;
     const QT &qx = qtab[pt.nel[0]], &qy = qtab[pt.nel[1]];
-    double *Wk = wbuf + so;
+    T *Wk = A.wscratch + so;
     so += (size_t)mx * my;
-    double *rin = L.r + pt.off + nx + 1;
-    double *uin = L.u + pt.off + nx + 1;
+    T *rin = A.r + pt.off + nx + 1;
+    T *uin = A.u + pt.off + nx + 1;
     double h = 1.0 / std::max(pt.nel[0], pt.nel[1]);
     pt.sigma = 1.0 / (c.opt.scaling_delta * h * h);
     double gamma = std::pow(c.measure[k], (c.d - 2.0) / c.d);
     pt.scms_scale = c.opt.damping_tau / gamma;
     // forward: W = (Qy^T R) Qx ./ (sigma + lam_y + lam_x)
-    fa.push_back(Fd2Item{qy.QT, rin, qx.Q, Wk, my, nx, mx, mx, my, my, mx, qy.lam, qx.lam,
-                         pt.sigma, 0.0});
+    fa.push_back(Fd2Item<T>{qy.QT, rin, qx.Q, Wk, my, nx, mx, mx, nt, ns, my, my, mx, qy.lam,
+                            qx.lam, (T)pt.sigma, (T)0});
     // backward: U += scale (Qy W) Qx^T
-    fb.push_back(Fd2Item{qy.Q, Wk, qx.QT, uin, my, mx, mx, nx, my, my, mx, nullptr, nullptr, 0.0,
-                         pt.scms_scale});
+    fb.push_back(Fd2Item<T>{qy.Q, Wk, qx.QT, uin, my, mx, mx, nx, ns, nt, my, my, mx, nullptr,
+                            nullptr, (T)0, (T)pt.scms_scale});
     L.fd_rows = std::max(L.fd_rows, my);
     L.fd_K1 = std::max(L.fd_K1, my);
     L.fd_N = std::max(L.fd_N, mx);
   }
   if (L.fd_N > 320 || L.fd_K1 > 320) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
   L.n_fd = L.K;
-  L.d_fd[0] = c.arena.upload(fa, c.stream);
-  L.d_fd[1] = c.arena.upload(fb, c.stream);
+  A.fd[0] = c.arena.upload(fa, c.stream);
+  A.fd[1] = c.arena.upload(fb, c.stream);
 }
 
 static void build_gs(Context &c, LevelData &L) {
   const int d = c.d, T = c.opt.gs_tile;
+  if (T != 2 * (c.p + 1)) fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel tiles of width 2(p+1) only");
   if (d != 2) fail(IGAMG_EUNSUPPORTED, "3D Gauss-Seidel not built");
   std::vector<int> li, col;
   std::vector<double> val;
@@ -755,7 +764,10 @@ static void build_gs(Context &c, LevelData &L) {
     }
   L.d_gcx_li = c.arena.upload(li, c.stream);
   L.d_gcx_col = c.arena.upload(col, c.stream);
-  L.d_gcx_val = c.arena.upload(val, c.stream);
+  if (c.fp32())
+    L.a32.gcx_val = c.arena.upload_as<float>(val, c.stream);
+  else
+    L.a64.gcx_val = c.arena.upload_as<double>(val, c.stream);
 }
 
 static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
@@ -835,9 +847,14 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
   F.PW = PW;
   F.RW = RW;
   F.d_P_lo = c.arena.upload(Plo, c.stream);
-  F.d_P_val = c.arena.upload(Pv, c.stream);
   F.d_R_lo = c.arena.upload(Rlo, c.stream);
-  F.d_R_val = c.arena.upload(Rv, c.stream);
+  if (c.fp32()) {
+    F.a32.P_val = c.arena.upload_as<float>(Pv, c.stream);
+    F.a32.R_val = c.arena.upload_as<float>(Rv, c.stream);
+  } else {
+    F.a64.P_val = c.arena.upload_as<double>(Pv, c.stream);
+    F.a64.R_val = c.arena.upload_as<double>(Rv, c.stream);
+  }
 }
 
 static void build_maps(Context &c, const LevelData &L, int **d_cp, int **d_cidx) {
@@ -852,6 +869,21 @@ static void build_maps(Context &c, const LevelData &L, int **d_cp, int **d_cidx)
 }
 
 // ---------------------------------------------------------------------------
+template <typename T>
+static void alloc_work(Context &c, LevelData &L) {
+  LevelArrays<T> &A = L.arr<T>();
+  const size_t n = (size_t)L.Ntorn * c.nb;
+  A.f = c.arena.alloc<T>(n);
+  A.u = c.arena.alloc<T>(n);
+  A.r = c.arena.alloc<T>(n);
+  for (T *v : {A.f, A.u, A.r}) k_fill<T>(v, (T)0, (long long)n, c.stream);
+}
+
+template <typename T>
+static T *upload_vals(Context &c, const std::vector<double> &v) {
+  return c.arena.upload_as<T>(v, c.stream);
+}
+
 void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
                    const igamg_options *o, hipStream_t s) {
   if (!P || !o) fail(IGAMG_EINVAL, "null argument");
@@ -869,12 +901,20 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   if (c.opt.gs_tile < degree) fail(IGAMG_EINVAL, "gs_tile must be >= degree");
   if (c.opt.mu < 1) c.opt.mu = 1;
   if (c.opt.nu < 1) c.opt.nu = 1;
+  if (c.opt.max_rhs < 0 || c.opt.max_rhs > 4096) fail(IGAMG_EINVAL, "max_rhs out of range 0..4096");
+  c.nb = c.opt.max_rhs > 0 ? c.opt.max_rhs : 1;
   if (c.opt.discretization == IGAMG_SIPG && !(sigma > 0)) fail(IGAMG_EINVAL, "penalty must be positive");
   const bool use_gs = c.opt.smoother != IGAMG_SMOOTHER_SCMS;
   const bool use_scms = c.opt.smoother != IGAMG_SMOOTHER_GS;
   if (c.opt.discretization == IGAMG_CONFORMING && use_gs)
     fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel ordering is defined for the SIPG space only");
-  if (c.opt.precision != IGAMG_FP64) fail(IGAMG_EUNSUPPORTED, "mixed precision not built yet");
+  if (use_gs && c.opt.gs_tile != 2 * (degree + 1))
+    fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel tiles of width 2(p+1) only");
+  if (c.opt.precision != IGAMG_FP64 && c.opt.precision != IGAMG_FP32)
+    fail(IGAMG_EINVAL, "unknown precision");
+  if (c.opt.outer < IGAMG_OUTER_PCG || c.opt.outer > IGAMG_OUTER_FCG)
+    fail(IGAMG_EINVAL, "unknown outer iteration");
+  const bool f32 = c.fp32();
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
@@ -901,6 +941,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   for (int l = 0; l < NL; ++l) {
     LevelData &L = c.lv[l];
     L.l = l;
+    const bool finest = l == NL - 1;
     build_level_dofs(c, L, lev_el[l]);
     if (c.opt.discretization == IGAMG_SIPG) build_interfaces(c, L);
     L.d_tabB = c.arena.upload(L.tabB, c.stream);
@@ -908,40 +949,43 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     L.d_mask = c.arena.upload(L.mask, c.stream);
     std::vector<double> w(L.Ntorn, 0.0);
     for (long long ci = 0; ci < L.N; ++ci) w[L.rep[ci]] = 1.0;
-    L.d_weight = c.arena.upload(w, c.stream);
     std::vector<int> ip = L.if_ptr.empty() ? std::vector<int>(L.Ntorn + 1, 0) : L.if_ptr;
     L.d_if_ptr = c.arena.upload(ip, c.stream);
     L.d_if_col = c.arena.upload(L.if_col, c.stream);
-    L.d_if_val = c.arena.upload(L.if_val, c.stream);
-    // cross-patch part for Gauss-Seidel, same-side part added to the stencil
-    std::vector<int> cxp(L.Ntorn + 1, 0), cxc, srow, sslot;
-    std::vector<double> cxv, sval;
+    // cycle arithmetic on every level; the finest level also keeps the
+    // float64 operator and weights of the outer iteration
+    if (f32) {
+      L.a32.weight = upload_vals<float>(c, w);
+      L.a32.if_val = upload_vals<float>(c, L.if_val);
+    }
+    if (!f32 || finest) {
+      L.a64.weight = upload_vals<double>(c, w);
+      L.a64.if_val = upload_vals<double>(c, L.if_val);
+    }
+    // same-side interface terms are added to the Gauss-Seidel stencil rows;
+    // cross-patch terms are kept per tile (build_gs)
+    std::vector<int> srow, sslot;
+    std::vector<double> sval;
     for (long long t = 0; t < L.Ntorn; ++t) {
-      cxp[t + 1] = cxp[t];
       if (L.if_ptr.empty()) continue;
       for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e) {
-        if (L.if_cross[e]) {
-          cxc.push_back(L.if_col[e]);
-          cxv.push_back(L.if_val[e]);
-          cxp[t + 1]++;
-        } else {
-          int k = 0;
-          while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
-          const PatchDev &pt = L.pd[k];
-          long long a = t - pt.off, b = L.if_col[e] - pt.off;
-          int slot = 0, m = 1;
-          for (int g = 0; g < c.d; ++g) {
-            int ia = (int)(a % pt.n[g]), ib = (int)(b % pt.n[g]);
-            a /= pt.n[g];
-            b /= pt.n[g];
-            if (std::abs(ib - ia) > c.p) fail(IGAMG_EINVAL, "interface coupling outside the stencil");
-            slot += (ib - ia + c.p) * m;
-            m *= S1;
-          }
-          srow.push_back((int)t);
-          sslot.push_back(slot);
-          sval.push_back(L.if_val[e]);
+        if (L.if_cross[e]) continue;
+        int k = 0;
+        while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
+        const PatchDev &pt = L.pd[k];
+        long long a = t - pt.off, b = L.if_col[e] - pt.off;
+        int slot = 0, m = 1;
+        for (int g = 0; g < c.d; ++g) {
+          int ia = (int)(a % pt.n[g]), ib = (int)(b % pt.n[g]);
+          a /= pt.n[g];
+          b /= pt.n[g];
+          if (std::abs(ib - ia) > c.p) fail(IGAMG_EINVAL, "interface coupling outside the stencil");
+          slot += (ib - ia + c.p) * m;
+          m *= S1;
         }
+        srow.push_back((int)t);
+        sslot.push_back(slot);
+        sval.push_back(L.if_val[e]);
       }
     }
     {
@@ -956,9 +1000,6 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       L.d_has_if = c.arena.upload(has, c.stream);
       L.d_if_rows = c.arena.upload(rows, c.stream);
     }
-    L.d_cx_ptr = c.arena.upload(cxp, c.stream);
-    L.d_cx_col = c.arena.upload(cxc, c.stream);
-    L.d_cx_val = c.arena.upload(cxv, c.stream);
     // volume tiles
     std::vector<VolTile> vt;
     int TE = vol_tile_2d(c.p);
@@ -977,61 +1018,93 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     L.n_glue = (int)gp.size() - 1;
     L.d_glue_ptr = c.arena.upload(gp, c.stream);
     L.d_glue_idx = c.arena.upload(gi, c.stream);
-    // work vectors
-    L.f = c.arena.alloc<double>(L.Ntorn);
-    L.u = c.arena.alloc<double>(L.Ntorn);
-    L.r = c.arena.alloc<double>(L.Ntorn);
-    k_fill(L.f, 0.0, L.Ntorn, c.stream);
-    k_fill(L.u, 0.0, L.Ntorn, c.stream);
-    k_fill(L.r, 0.0, L.Ntorn, c.stream);
+    // work vectors ([nb][Ntorn]); the finest float64 iterate is the output of
+    // the preconditioner in float64 cycles
+    if (f32)
+      alloc_work<float>(c, L);
+    else
+      alloc_work<double>(c, L);
     if (l >= 1) {
       build_transfer(c, L, c.lv[l - 1]);
-      if (use_gs) {
-        L.d_stencil = c.arena.alloc<double>((size_t)L.Ntorn * SP);
-        L.d_invdiag = c.arena.alloc<double>(L.Ntorn);
-        build_gs(c, L);
-      }
+      if (use_gs) build_gs(c, L);
       if (use_scms) {
-        build_scms(c, L);
+        if (f32)
+          build_scms<float>(c, L);
+        else
+          build_scms<double>(c, L);
         build_pieces(c, L);
       }
     }
     L.d_pd = c.arena.upload(L.pd, c.stream);
     if (l >= 1 && use_gs) {
-      k_stencil_assemble(c, L);
+      // volume rows + same-side interface terms, assembled in float64
+      double *st64 = nullptr, *id64 = nullptr;
+      std::vector<void *> tmp;
+      if (f32) {
+        HIPCHK(hipMalloc((void **)&st64, (size_t)L.Ntorn * SP * sizeof(double)));
+        tmp.push_back(st64);
+        HIPCHK(hipMalloc((void **)&id64, (size_t)L.Ntorn * sizeof(double)));
+        tmp.push_back(id64);
+      } else {
+        st64 = L.a64.stencil = c.arena.alloc<double>((size_t)L.Ntorn * SP);
+        id64 = L.a64.invdiag = c.arena.alloc<double>(L.Ntorn);
+      }
+      k_stencil_assemble(c, L, st64);
       int *dr = c.arena.upload(srow, c.stream), *ds = c.arena.upload(sslot, c.stream);
       double *dv = c.arena.upload(sval, c.stream);
-      k_stencil_add(dr, ds, dv, (int)srow.size(), L.d_stencil, SP, c.stream);
-      k_invdiag(L.d_stencil, SP, center, L.d_mask, L.d_invdiag, L.Ntorn, c.stream);
+      k_stencil_add(dr, ds, dv, (int)srow.size(), st64, SP, c.stream);
+      k_invdiag(st64, SP, center, L.d_mask, id64, L.Ntorn, c.stream);
+      if (f32) {
+        L.a32.stencil = c.arena.alloc<float>((size_t)L.Ntorn * SP);
+        L.a32.invdiag = c.arena.alloc<float>(L.Ntorn);
+        k_convert<double, float>(st64, nullptr, L.a32.stencil, (long long)L.Ntorn * SP, 1, c.stream);
+        k_convert<double, float>(id64, nullptr, L.a32.invdiag, L.Ntorn, 1, c.stream);
+        HIPCHK(hipStreamSynchronize(c.stream));
+        for (void *q : tmp) HIPCHK(hipFree(q));
+      }
     }
   }
-  // coarse level: dense inverse of A_0 (Cholesky based)
+  // coarse level: dense inverse of A_0 (Cholesky based), float64 always
   {
     LevelData &L0 = c.lv[0];
     std::vector<int> all(L0.N);
     std::iota(all.begin(), all.end(), 0);
     std::vector<double> A0 = dense_block(c, L0, all);
     c.N0 = (int)L0.N;
+    if ((size_t)c.N0 * sizeof(double) > 64 * 1024)
+      fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve kernel");
     std::vector<double> A0i = spd_inverse(A0, c.N0);
     c.d_A0inv = c.arena.upload(A0i, c.stream);
     build_maps(c, L0, &c.d_c0_cp, &c.d_c0_cidx);
   }
   LevelData &LF = c.lv.back();
   build_maps(c, LF, &c.d_fin_cp, &c.d_fin_cidx);
-  const long long nt = LF.Ntorn;
+  // outer iteration vectors, float64, [nb][Ntorn]
+  const size_t nt = (size_t)LF.Ntorn * c.nb;
   c.x = c.arena.alloc<double>(nt);
   c.rr = c.arena.alloc<double>(nt);
-  c.z = LF.u;  // the preconditioner output is the finest cycle iterate
+  c.z = f32 ? c.arena.alloc<double>(nt) : LF.a64.u;  // float64 cycles write z in place
   c.pp = c.arena.alloc<double>(nt);
   c.qq = c.arena.alloc<double>(nt);
   c.ff = c.arena.alloc<double>(nt);
-  for (double *v : {c.x, c.rr, c.pp, c.qq, c.ff}) k_fill(v, 0.0, nt, c.stream);
-  c.d_red = c.arena.alloc<double>(1024);
-  c.d_scal = c.arena.alloc<double>(S_COUNT);
-  k_fill(c.d_scal, 0.0, S_COUNT, c.stream);
-  HIPCHK(hipHostMalloc((void **)&c.h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+  for (double *v : {c.x, c.rr, c.z, c.pp, c.qq, c.ff}) k_fill(v, 0.0, (long long)nt, c.stream);
+  if (c.opt.outer == IGAMG_OUTER_FCG) {
+    c.rold = c.arena.alloc<double>(nt);
+    k_fill(c.rold, 0.0, (long long)nt, c.stream);
+  }
+  c.d_red = c.arena.alloc<double>((size_t)2 * RED_BLOCKS * c.nb);
+  c.d_scal = c.arena.alloc<double>((size_t)S_COUNT * c.nb);
+  k_fill(c.d_scal, 0.0, (long long)S_COUNT * c.nb, c.stream);
+  c.d_active = c.arena.alloc<int>(c.nb);
+  HIPCHK(hipHostMalloc((void **)&c.h_active, (size_t)c.nb * sizeof(int), hipHostMallocDefault));
+  for (int j = 0; j < c.nb; ++j) c.h_active[j] = 1;
+  HIPCHK(hipMemcpyAsync(c.d_active, c.h_active, c.nb * sizeof(int), hipMemcpyHostToDevice,
+                        c.stream));
+  HIPCHK(hipHostMalloc((void **)&c.h_scal, (size_t)S_COUNT * c.nb * sizeof(double),
+                       hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(c.stream));
   HIPCHK(hipGetLastError());
+  c.arena.staging.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -1042,6 +1115,7 @@ void kernel_model(const Context &c, const std::string &fam, int level, double *b
                   double *flops) {
   const LevelData &L = c.lv[level];
   const double nt = (double)L.Ntorn;
+  const double wb = c.fp32() ? 4.0 : 8.0;  // bytes of a value in the cycle arithmetic
   const int q = c.p + 1, P1 = c.p + 1;
   int S = 1;
   for (int g = 0; g < c.d; ++g) S *= (2 * c.p + 1);
@@ -1059,21 +1133,21 @@ void kernel_model(const Context &c, const std::string &fam, int level, double *b
       *flops += 4.0 * pt.n[1] * Qx * P1;        // transposed y-contraction
       *flops += 4.0 * pt.n[1] * pt.n[0] * Qx / pt.nel[0] * P1;  // transposed x-contraction
     }
-    *bytes = 3.0 * 8.0 * nt;                    // read u, read and write r
+    *bytes = 3.0 * wb * nt;                     // read u, read and write r
   } else if (fam == "gauss_seidel") {
     int launches = 0;
     for (const GsClass &cl : L.gs) launches += cl.count > 0;
     if (launches == 0) launches = 1;
-    *bytes = (nt * (8.0 * ((S + 15) / 16 * 16) + 8.0 * 4 + 4.0) + ncross * 20.0) / launches;
+    *bytes = (nt * (wb * ((S + 15) / 16 * 16) + wb * 4) + ncross * (8.0 + 2.0 * wb)) / launches;
     *flops = (2.0 * S * nt + 2.0 * ncross) / launches;
   } else if (fam == "scms") {
     for (int k = 0; k < c.K; ++k) {
       double mx = L.pd[k].n[0] - 2, my = L.pd[k].n[1] - 2;
       *flops += 2.0 * (mx * my * mx + my * my * mx + my * mx * mx + my * my * mx);
-      *bytes += 8.0 * (mx * my * (1 + 2 + 4) + 2 * (mx * mx + my * my));
+      *bytes += wb * (mx * my * (1 + 2 + 4) + 2 * (mx * mx + my * my));
     }
   } else if (fam == "iface_apply") {
-    *bytes = nt * (8.0 + 8.0 + 1.0 + 4.0) + nnz * (4.0 + 8.0 + 8.0);
+    *bytes = nt * (wb + wb + 1.0 + 1.0) + nnz * (4.0 + wb + wb);
     *flops = 2.0 * nnz;
   } else {
     fail(IGAMG_EINVAL, "no model for this kernel family");
@@ -1081,10 +1155,11 @@ void kernel_model(const Context &c, const std::string &fam, int level, double *b
 }
 
 size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_options *o) {
-  if (!P || P->dim < 2 || P->dim > 3 || P->n_patches < 1 || degree < 1)
+  if (!P || !o || P->dim < 2 || P->dim > 3 || P->n_patches < 1 || degree < 1 || !P->elems)
     fail(IGAMG_EINVAL, "invalid problem");
   const int d = P->dim, p = degree;
-  double per_level_dofs = 0.0;
+  const int nb = o->max_rhs > 0 ? o->max_rhs : 1;
+  const double wb = o->precision == IGAMG_FP32 ? 4.0 : 8.0;
   long long fine = 0;
   for (int k = 0; k < P->n_patches; ++k) {
     long long n = 1;
@@ -1092,12 +1167,20 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
     fine += n;
   }
   // levels shrink by 2^d; geometric sum bounded by 2^d/(2^d-1)
-  per_level_dofs = fine * (double)(1 << d) / ((1 << d) - 1);
+  const double all_levels = fine * (double)(1 << d) / ((1 << d) - 1);
   int S = 1;
   for (int a = 0; a < d; ++a) S *= (2 * p + 1);
-  bool gs = o->smoother != IGAMG_SMOOTHER_SCMS;
-  double bytes = per_level_dofs * 8.0 * (5 + (gs ? S + 1 : 0) + 2);
-  bytes += fine * 8.0 * 6;
+  const int SP = (S + 15) / 16 * 16;
+  const bool gs = o->smoother != IGAMG_SMOOTHER_SCMS;
+  const bool scms = o->smoother != IGAMG_SMOOTHER_GS;
+  // per unknown and level: f, u, r per right-hand side, SCMS intermediate,
+  // stencil row and 1/a_ii, weight, masks and index maps
+  double per = wb * (3.0 * nb + (scms ? nb : 0) + (gs ? SP + 1 : 0) + 1) + 16.0;
+  double bytes = all_levels * per;
+  // outer float64 vectors [nb][Ntorn]: x, r, z, p, q, f (+ r_old)
+  bytes += fine * 8.0 * nb * (7 + (o->outer == IGAMG_OUTER_FCG ? 1 : 0));
+  // float32 setup assembles the stencil in float64 first (freed afterwards)
+  if (gs && wb == 4.0) bytes += fine * 8.0 * (SP + 1);
   return (size_t)bytes + (64u << 20);
 }
 

@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
                 ("damping_tau", ctypes.c_double), ("scaling_delta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("outer", ctypes.c_int),
                 ("gs_tile", ctypes.c_int), ("coarse_min", ctypes.c_int),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("max_rhs", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -107,7 +107,7 @@ def _patches(corners, elems):
 
 
 def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1, nu=1,
-                 precision="fp64", outer="pcg", gs_tile=0, coarse_min=0, timing=False):
+                 precision="fp64", outer="pcg", gs_tile=0, coarse_min=0, timing=False, max_rhs=0):
     o = Options()
     _lib.igamg_default_options(ctypes.byref(o))
     o.discretization = CONFORMING if conforming else SIPG
@@ -118,6 +118,7 @@ def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1,
     o.outer = OUTERS[outer]
     o.gs_tile, o.coarse_min = gs_tile, coarse_min
     o.timing = 1 if timing else 0
+    o.max_rhs = max_rhs
     return o
 
 
@@ -186,7 +187,7 @@ class Solver:
         for j in range(ncol):
             d = dict(iterations=infos[j].iterations, rel_residual=infos[j].rel_residual,
                      true_rel_residual=infos[j].true_rel_residual, seconds=infos[j].seconds,
-                     converged=code == OK)
+                     converged=infos[j].rel_residual <= tol)
             if history:
                 d["history"] = hist[j][:infos[j].iterations + 1].copy()
             out.append(d)
