@@ -114,6 +114,8 @@ struct LevelData {
   // transfer tables between this level and the next coarser one
   int *d_P_lo = nullptr, *d_R_lo = nullptr;
   int PW = 0, RW = 0;
+  XferTile *d_rtiles = nullptr, *d_ptiles = nullptr;  // coarse-side / fine-side output tiles
+  int n_rtiles = 0, n_ptiles = 0;
   LevelArrays<double> a64;
   LevelArrays<float> a32;
   template <typename T>

@@ -52,6 +52,17 @@ struct VolTile {
   int e0[3];
 };
 
+// Output tile of a transfer kernel (2D): up to 16 x 16 outputs of one patch
+// and the window of input entries they read, all resolved at setup so that
+// the kernel's loads depend on this record only.
+struct XferTile {
+  long long in_off, out_off;  // patch offsets in the input / output level vectors
+  int in_nx, out_nx;          // x extents of the input / output patch tensors
+  int o0[2], no[2];           // first output index and output count per direction
+  int base[2];                // band-table row of the first output per direction
+  int w0[2], wn[2];           // input window origin and extent per direction
+};
+
 struct GsTile {
   int patch;
   int i0[3];

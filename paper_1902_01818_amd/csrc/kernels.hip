@@ -435,6 +435,8 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
   constexpr int C = (S + 15) / 16;
   constexpr int SP = 16 * C;  // padded row length (zero coefficients beyond S)
   constexpr int NPH = Q1 * Q1;
+  // rows prefetched D classes ahead (deeper prefetch measured slower: the
+  // longer prologue outweighs the hidden latency)
   constexpr int D0 = (sizeof(T) == 8 ? 48 : 96) / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
   __shared__ T sU[W * W];
@@ -535,19 +537,25 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
     for (int c = 0; c < C; ++c) uv[c] = sU[wi + soff[c]];
     const T uold = sU[wi];
     const T2 bd = sBD[li];
-    // u + (b - a.u) d, split so that the LDS reads are consumed before the scan
-    T ubd = fma(bd.x, bd.y, uold);
-    asm volatile("" : "+v"(ubd));  // keep these reads in the batch of this class
-    T acc = 0;
+    // two independent partial sums halve the dependent multiply-add chain
+    T acc0 = 0, acc1 = 0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc += buf[s % D][c] * uv[c];
+    for (int c = 0; c < C; c += 2) acc0 += buf[s % D][c] * uv[c];
+#pragma unroll
+    for (int c = 1; c < C; c += 2) acc1 += buf[s % D][c] * uv[c];
+    // u + (b - a.u) d: every LDS value of the class is consumed before the
+    // scan, so the reads go out as one batch and none is sunk past the scan
+    T ubd = fma(bd.x, bd.y, uold);
+    T acc = acc0 + acc1;
+    T dinv = bd.y;
+    asm volatile("" : "+v"(acc), "+v"(ubd), "+v"(dinv));
     if (s + D < NPH) {
       const T *srow = row_ptr(s + D);
 #pragma unroll
       for (int c = 0; c < C; ++c) buf[s % D][c] = srow[16 * c];
     }
     acc = row16_scan(acc);
-    if (l16 == 15 && ix < nx && iy < ny) sU[wi] = fma(-acc, bd.y, ubd);
+    if (l16 == 15 && ix < nx && iy < ny) sU[wi] = fma(-acc, dinv, ubd);
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
   }
@@ -561,15 +569,22 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
 // ---------------------------------------------------------------------------
 // Row-block products of the fast diagonalization (see Fd2Item).  A block of
 // 256 threads owns 16 rows: thread (rg, cg) accumulates rows 4rg..4rg+3 and
-// columns cg + 64j; B is streamed through LDS in chunks of 8 rows with the
-// next chunk held in registers while the current one is used.
+// columns cg + 64j; B is streamed through LDS in chunks of KC rows, the next
+// chunk held in registers while the current one is used.  Long chunks keep
+// the number of dependent global-load round trips per block small.
 // grid.x = row block, grid.y = item (patch), grid.z = right-hand side.
 // ---------------------------------------------------------------------------
+template <int NJ>
+struct Fd2Shape {
+  static constexpr int WB = 64 * NJ;            // LDS row length of a chunk
+  static constexpr int KC = NJ <= 3 ? 32 : 16;  // rows per chunk
+};
+
 template <typename T, int NJ>
 __device__ inline void rowblock_product(const T *A, int lda, const T *__restrict__ B, long long b_r,
                                         int K, int N, T *sM, T acc[4][NJ]) {
-  constexpr int WB = 64 * NJ;  // LDS row length of a chunk
-  constexpr int LPT = 2 * NJ;  // 8 * WB / 256 loads per thread
+  constexpr int WB = Fd2Shape<NJ>::WB, KC = Fd2Shape<NJ>::KC;
+  constexpr int LPT = KC * WB / 256;  // loads per thread and chunk
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
   T pre[LPT];
   auto gload = [&](int k0) {
@@ -581,33 +596,34 @@ __device__ inline void rowblock_product(const T *A, int lda, const T *__restrict
     }
   };
   gload(0);
-  for (int k0 = 0; k0 < K; k0 += 8) {
+  for (int k0 = 0; k0 < K; k0 += KC) {
     __syncthreads();
 #pragma unroll
-    for (int x = 0; x < LPT; ++x) {
-      const int e = tid + 256 * x;
-      sM[(e / WB) * WB + e % WB] = pre[x];
-    }
+    for (int x = 0; x < LPT; ++x) sM[tid + 256 * x] = pre[x];
     __syncthreads();
-    if (k0 + 8 < K) gload(k0 + 8);
+    if (k0 + KC < K) gload(k0 + KC);
+    // groups of 8 rows, fully unrolled so that their LDS reads go out
+    // together; rows past K are zero in sM and in A's padding
+    for (int k8 = 0; k8 < KC && k0 + k8 < K; k8 += 8) {
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      T a[4], b[NJ];
+      for (int kk = k8; kk < k8 + 8; ++kk) {
+        T a[4], b[NJ];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk];
+        for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
+        for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
+          for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
+      }
     }
   }
 }
 
 template <typename T, int NJ>
 __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K1pad) {
-  constexpr int WB = 64 * NJ;
+  constexpr int WB = Fd2Shape<NJ>::WB;
   extern __shared__ char smraw[];
   T *sm = (T *)smraw;
   const Fd2Item<T> it = items[blockIdx.y];
@@ -615,15 +631,24 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K
   if (i0 >= it.rows) return;
   const T *M1 = it.M1 + (long long)blockIdx.z * it.m1_z;
   T *O = it.O + (long long)blockIdx.z * it.o_z;
-  T *sL = sm;                     // 16 x (K1pad + 8), zero padded
-  T *sZ = sL + 16 * (K1pad + 8);  // 16 x WB
-  T *sM = sZ + 16 * WB;           // 8 x WB
   const int lda = K1pad + 8;
+  T *sL = sm;              // 16 x lda, zero padded
+  T *sZ = sL + 16 * lda;   // 16 x WB
+  T *sM = sZ + 16 * WB;    // KC x WB
   const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
   const int nrow = min(16, it.rows - i0);
-  for (int e = tid; e < 16 * lda; e += 256) {
-    const int i = e / lda, a = e % lda;
-    sL[e] = (i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : (T)0;
+  // rows of L: eight independent loads per thread and round trip
+  for (int e0 = 0; e0 < 16 * lda; e0 += 256 * 8) {
+    T v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + tid + 256 * j;
+      const int i = e / lda, a = e % lda;
+      v[j] = (e < 16 * lda && i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (e0 + tid + 256 * j < 16 * lda) sL[e0 + tid + 256 * j] = v[j];
   }
   T acc[4][NJ];
 #pragma unroll
@@ -733,100 +758,85 @@ __global__ __launch_bounds__(1024) void coarse_kernel(int n, const double *inv, 
 }
 
 // ---------------------------------------------------------------------------
-// transfers (2D): restriction r_c = P^T (w r_f), prolongation u_f += P e_c.
-// The 1D factors are banded (at most MAXW entries per row / column); the band
-// of the thread's unknown is held in registers.  grid.y = right-hand side.
+// Transfers (2D), one 16 x 16 output tile per block:
+//   out[oy, ox] (+)= sum_a sum_b vy[oy][a] vx[ox][b] in[lo_y[oy] + a, lo_x[ox] + b]
+// with the banded 1D factors (at most MAXW entries per output index).
+// Restriction: in = w .* r on the fine patch, out = coarse residual (zero on
+// Dirichlet rows), the band of coarse index j being column j of the 1D
+// embedding; the coarse iterate is cleared alongside.  Prolongation: in = the
+// coarse correction, out = fine iterate += (free rows only).  The tile's
+// input window is staged in LDS in one coalesced round of loads, then
+// contracted in x and in y.  grid.x = tile, grid.y = right-hand side.
 // ---------------------------------------------------------------------------
 constexpr int MAXW = 12;
+constexpr int XT = 16, XW = 64;
 
-template <typename T>
-__global__ __launch_bounds__(256) void restrict2d_kernel(const PatchDev *pf, const PatchDev *pc,
-                                                         int K, const int *Rlo, const T *Rval,
-                                                         int RW, const T *rf, const T *wf,
-                                                         const unsigned char *maskc,
-                                                         long long nc_tot, T *rc, T *uc_zero,
-                                                         long long vsf) {
-  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= nc_tot) return;
-  const long long zc = (long long)blockIdx.y * nc_tot;
-  rf += (long long)blockIdx.y * vsf;
-  rc += zc;
-  if (uc_zero) uc_zero[zc + t] = 0;  // zero initial guess of the coarse cycle
-  int k = 0;
-  while (k + 1 < K && pc[k + 1].off <= t) ++k;
-  const PatchDev &C = pc[k], &F = pf[k];
-  if (!maskc[t]) {
-    rc[t] = 0;
-    return;
+template <typename T, bool RESTRICT>
+__global__ __launch_bounds__(256) void transfer2d_kernel(
+    const XferTile *tiles, const int *__restrict__ lo, const T *__restrict__ val, int W,
+    const T *__restrict__ in, const T *__restrict__ win, const unsigned char *__restrict__ mask_out,
+    T *out, T *zero_out, long long vs_in, long long vs_out) {
+  constexpr int NL = XW * XW / 256;  // window loads per thread
+  __shared__ T sIn[XW * XW];
+  __shared__ T sX[XW * XT];
+  __shared__ T sV[2][XT][MAXW];
+  __shared__ int sLo[2][XT];
+  const XferTile tl = tiles[blockIdx.x];
+  in += (long long)blockIdx.y * vs_in;
+  out += (long long)blockIdx.y * vs_out;
+  if (zero_out) zero_out += (long long)blockIdx.y * vs_out;
+  const int tid = threadIdx.x;
+  // one round of independent loads: window (row r = e / XW, column e % XW),
+  // band starts and values
+  T wv[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int e = tid + 256 * j, r = e / XW, cc = e % XW;
+    const bool ok = r < tl.wn[1] && cc < tl.wn[0];
+    const long long t = tl.in_off + (long long)(tl.w0[1] + r) * tl.in_nx + tl.w0[0] + cc;
+    T v = ok ? in[t] : (T)0;
+    if (RESTRICT && ok) v *= win[t];
+    wv[j] = v;
   }
-  long long loc = t - C.off;
-  const int jx = (int)(loc % C.n[0]), jy = (int)(loc / C.n[0]);
-  const int rx = F.xr[0] + jx, ry = F.xr[1] + jy;
-  const int lx = Rlo[rx], ly = Rlo[ry];
-  T vx[MAXW], vy[MAXW];
+  if (tid < 2 * XT) {
+    // per-direction fields selected without indexing the record by a lane value
+    const int g = tid / XT, o = tid % XT;
+    const int no = g ? tl.no[1] : tl.no[0];
+    const int row = (g ? tl.base[1] : tl.base[0]) + min(o, no - 1);
+    sLo[g][o] = lo[row] - (g ? tl.w0[1] : tl.w0[0]);
 #pragma unroll
-  for (int a = 0; a < MAXW; ++a) {
-    vx[a] = a < RW ? Rval[(long long)rx * RW + a] : (T)0;
-    vy[a] = a < RW ? Rval[(long long)ry * RW + a] : (T)0;
+    for (int a = 0; a < MAXW; ++a)
+      sV[g][o][a] = (a < W && o < no) ? val[(long long)row * W + a] : (T)0;
   }
-  T s = 0;
 #pragma unroll
-  for (int a = 0; a < MAXW; ++a) {
-    const int iy = ly + a;
-    if (a < RW && iy < F.n[1]) {
-      T sx = 0;
-      const long long rowoff = F.off + (long long)iy * F.n[0];
+  for (int j = 0; j < NL; ++j) sIn[tid + 256 * j] = wv[j];
+  __syncthreads();
+  const int wxn = tl.wn[0], wyn = tl.wn[1];
+  for (int e = tid; e < wyn * XT; e += 256) {
+    const int r = e / XT, ox = e % XT;
+    const int b0 = sLo[0][ox];
+    T sx = 0;
 #pragma unroll
-      for (int b = 0; b < MAXW; ++b) {
-        const int ix = lx + b;
-        if (b < RW && ix < F.n[0]) sx += vx[b] * (wf[rowoff + ix] * rf[rowoff + ix]);
-      }
-      s += vy[a] * sx;
+    for (int b = 0; b < MAXW; ++b)
+      if (b < W && b0 + b < wxn) sx += sV[0][ox][b] * sIn[r * XW + b0 + b];
+    sX[r * XT + ox] = sx;
+  }
+  __syncthreads();
+  const int tx = tid % XT, ty = tid / XT;
+  if (tx < tl.no[0] && ty < tl.no[1]) {
+    const int a0 = sLo[1][ty];
+    T sy = 0;
+#pragma unroll
+    for (int a = 0; a < MAXW; ++a)
+      if (a < W && a0 + a < wyn) sy += sV[1][ty][a] * sX[(a0 + a) * XT + tx];
+    const long long t = tl.out_off + (long long)(tl.o0[1] + ty) * tl.out_nx + tl.o0[0] + tx;
+    if (RESTRICT) {
+      out[t] = mask_out[t] ? sy : (T)0;
+      if (zero_out) zero_out[t] = 0;
+    } else if (mask_out[t]) {
+      out[t] += sy;
     }
   }
-  rc[t] = s;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void prolong2d_kernel(const PatchDev *pf, const PatchDev *pc,
-                                                        int K, const int *Plo, const T *Pval,
-                                                        int PW, const T *ec,
-                                                        const unsigned char *maskf,
-                                                        long long nf_tot, T *uf, long long vsc) {
-  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= nf_tot) return;
-  ec += (long long)blockIdx.y * vsc;
-  uf += (long long)blockIdx.y * nf_tot;
-  int k = 0;
-  while (k + 1 < K && pf[k + 1].off <= t) ++k;
-  const PatchDev &F = pf[k], &C = pc[k];
-  if (!maskf[t]) return;
-  long long loc = t - F.off;
-  const int ix = (int)(loc % F.n[0]), iy = (int)(loc / F.n[0]);
-  const int px = F.xp[0] + ix, py = F.xp[1] + iy;
-  const int lx = Plo[px], ly = Plo[py];
-  T vx[MAXW], vy[MAXW];
-#pragma unroll
-  for (int a = 0; a < MAXW; ++a) {
-    vx[a] = a < PW ? Pval[(long long)px * PW + a] : (T)0;
-    vy[a] = a < PW ? Pval[(long long)py * PW + a] : (T)0;
-  }
-  T s = 0;
-#pragma unroll
-  for (int a = 0; a < MAXW; ++a) {
-    const int jy = ly + a;
-    if (a < PW && jy < C.n[1]) {
-      T sx = 0;
-      const long long rowoff = C.off + (long long)jy * C.n[0];
-#pragma unroll
-      for (int b = 0; b < MAXW; ++b) {
-        const int jx = lx + b;
-        if (b < PW && jx < C.n[0]) sx += vx[b] * ec[rowoff + jx];
-      }
-      s += vy[a] * sx;
-    }
-  }
-  uf[t] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -1136,8 +1146,15 @@ template void k_gs_sweep<float>(Context &, LevelData &, bool, int);
 
 template <typename T, int NJ>
 static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
-  constexpr int WB = 64 * NJ;
-  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + 8 * WB) * sizeof(T);
+  constexpr int WB = Fd2Shape<NJ>::WB, KC = Fd2Shape<NJ>::KC;
+  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + KC * WB) * sizeof(T);
+  static bool lds_set = false;  // allow dynamic LDS beyond 64 KiB (gfx950: 160 KiB)
+  if (!lds_set) {
+    HIPCHK(hipFuncSetAttribute((const void *)fd2_kernel<T, NJ>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    lds_set = true;
+  }
+  if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
   dim3 grid((L.fd_rows + 15) / 16, L.n_fd, nrhs);
   fd2_kernel<T, NJ><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], L.fd_K1);
 }
@@ -1178,10 +1195,10 @@ template <typename T>
 void k_restrict(Context &c, LevelData &F, LevelData &C, const T *rf, T *rc, T *uc_zero, int nrhs) {
   TimeScope ts(c, "restrict", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
-  dim3 grid(nblocks(C.Ntorn), nrhs);
-  restrict2d_kernel<T><<<grid, BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_R_lo, F.arr<T>().R_val,
-                                                  F.RW, rf, F.arr<T>().weight, C.d_mask, C.Ntorn,
-                                                  rc, uc_zero, F.Ntorn);
+  dim3 grid(F.n_rtiles, nrhs);
+  transfer2d_kernel<T, true><<<grid, 256, 0, c.stream>>>(F.d_rtiles, F.d_R_lo, F.arr<T>().R_val,
+                                                         F.RW, rf, F.arr<T>().weight, C.d_mask, rc,
+                                                         uc_zero, F.Ntorn, C.Ntorn);
 }
 template void k_restrict<double>(Context &, LevelData &, LevelData &, const double *, double *,
                                  double *, int);
@@ -1192,9 +1209,10 @@ template <typename T>
 void k_prolong_add(Context &c, LevelData &F, LevelData &C, const T *ec, T *uf, int nrhs) {
   TimeScope ts(c, "prolong", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
-  dim3 grid(nblocks(F.Ntorn), nrhs);
-  prolong2d_kernel<T><<<grid, BS, 0, c.stream>>>(F.d_pd, C.d_pd, F.K, F.d_P_lo, F.arr<T>().P_val,
-                                                 F.PW, ec, F.d_mask, F.Ntorn, uf, C.Ntorn);
+  dim3 grid(F.n_ptiles, nrhs);
+  transfer2d_kernel<T, false><<<grid, 256, 0, c.stream>>>(F.d_ptiles, F.d_P_lo, F.arr<T>().P_val,
+                                                          F.PW, ec, nullptr, F.d_mask, uf, nullptr,
+                                                          C.Ntorn, F.Ntorn);
 }
 template void k_prolong_add<double>(Context &, LevelData &, LevelData &, const double *, double *,
                                     int);

@@ -844,6 +844,47 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
       F.pd[k].xr[g] = tb.rrow;
     }
   if (PW > 12 || RW > 12) fail(IGAMG_EUNSUPPORTED, "transfer band wider than the kernels hold");
+  // output tiles of XT x XT entries; the input window of a tile must fit the
+  // kernel's LDS window of XW x XW values
+  constexpr int XT = 16, XW = 64;
+  auto tiles_of = [&](const LevelData &Li, const LevelData &Lo, const std::vector<int> &lo, int W,
+                      bool coarse_side) {
+    std::vector<XferTile> out;
+    for (int k = 0; k < Lo.K; ++k) {
+      const PatchDev &pi = Li.pd[k], &po = Lo.pd[k];
+      for (int y0 = 0; y0 < po.n[1]; y0 += XT)
+        for (int x0 = 0; x0 < po.n[0]; x0 += XT) {
+          XferTile t{};
+          t.in_off = pi.off;
+          t.out_off = po.off;
+          t.in_nx = pi.n[0];
+          t.out_nx = po.n[0];
+          for (int g = 0; g < 2; ++g) {
+            const int o0 = g == 0 ? x0 : y0;
+            const int o1 = std::min(po.n[g], o0 + XT) - 1;
+            const int base = (coarse_side ? F.pd[k].xr[g] : F.pd[k].xp[g]) + o0;
+            int mn = lo[base], mx = lo[base];
+            for (int o = 0; o <= o1 - o0; ++o) {
+              mn = std::min(mn, lo[base + o]);
+              mx = std::max(mx, lo[base + o]);
+            }
+            t.o0[g] = o0;
+            t.no[g] = o1 - o0 + 1;
+            t.base[g] = base;
+            t.w0[g] = mn;
+            t.wn[g] = std::min(mx + W, pi.n[g]) - mn;
+            if (t.wn[g] > XW || mn < 0) fail(IGAMG_EUNSUPPORTED, "transfer window exceeds the kernel's LDS tile");
+          }
+          out.push_back(t);
+        }
+    }
+    return out;
+  };
+  std::vector<XferTile> rt = tiles_of(F, C, Rlo, RW, true), pt = tiles_of(C, F, Plo, PW, false);
+  F.n_rtiles = (int)rt.size();
+  F.n_ptiles = (int)pt.size();
+  F.d_rtiles = c.arena.upload(rt, c.stream);
+  F.d_ptiles = c.arena.upload(pt, c.stream);
   F.PW = PW;
   F.RW = RW;
   F.d_P_lo = c.arena.upload(Plo, c.stream);
