@@ -185,6 +185,76 @@ int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, double *by
                        double *flops);
 
 int igamg_destroy(igamg_ctx *ctx);
+
+/* Host only: number of unknowns N of the finest level (compact ordering) and
+ * number of levels of a problem, as igamg_setup would build it.  Errors as
+ * igamg_setup's argument checks. */
+int igamg_problem_size(const igamg_patches *patches, int degree, const igamg_options *o,
+                       int64_t *n_dofs, int *levels);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent solve requests on one GPU.
+ *
+ * A server owns `slots` worker threads, each with its own HIP stream, and
+ * one device buffer of `memory_budget` bytes.  Requests are admitted in
+ * arrival order as soon as a slot is free and a contiguous block of the
+ * buffer holds the request's footprint (igamg_footprint of its problem plus
+ * its right-hand side and solution); the request then builds its hierarchy
+ * inside that block (setup, as igamg_setup), solves (as igamg_solve with one
+ * right-hand side), copies the solution to the host and returns the block.
+ * Requests of different patch layouts, degrees and sizes therefore run
+ * concurrently on the device, and requests arriving while others run start
+ * as slots and memory free up.  The method per request is the one of
+ * igamg_solve (Sections 2-6); each result is independent of the other
+ * requests in flight (the tests compare a mix with requests run alone).
+ * ------------------------------------------------------------------------- */
+typedef struct igamg_server igamg_server;
+
+typedef struct {
+  int slots;            /* requests on the GPU at the same time (1..64) */
+  size_t memory_budget; /* device bytes shared by admitted requests (>= 1 MiB) */
+  int device;           /* HIP device ordinal */
+} igamg_server_config;
+
+typedef struct {
+  int status;              /* status of the request (igamg_solve's, or an error) */
+  int iterations;          /* outer iterations */
+  double rel_residual;     /* recurrence residual at exit */
+  double true_rel_residual;/* float64 ||f - A u|| / ||f|| at exit */
+  int64_t n_dofs;          /* N */
+  size_t footprint;        /* bytes reserved for the request */
+  int fallback_allocations;/* arrays that did not fit the block (allocated by the driver) */
+  double t_submit, t_admit, t_ready, t_done; /* seconds since server creation:
+                              submitted, admitted, set up (rhs on the GPU), solved */
+} igamg_request_info;
+
+/* Create a server (allocates the budget, starts the workers).  Errors:
+ * IGAMG_EINVAL, IGAMG_ENOMEM (budget not allocatable), IGAMG_EHIP. */
+int igamg_server_create(const igamg_server_config *cfg, igamg_server **out);
+
+/* Queue one request: problem as for igamg_setup (host arrays, copied),
+ * options (max_rhs and timing are ignored; precision must be IGAMG_FP64,
+ * float32 requests return IGAMG_EUNSUPPORTED), rhs = host float64 array of
+ * n_dofs values (copied; n_dofs must equal igamg_problem_size's N), tol and
+ * maxit as for igamg_solve.  Returns at once with *request_id.  Input errors
+ * are returned here; setup/solve errors are reported by igamg_server_wait. */
+int igamg_server_submit(igamg_server *srv, const igamg_patches *patches, int degree,
+                        double penalty_sigma, const igamg_options *o, const double *rhs,
+                        int64_t n_dofs, double tol, int maxit, int64_t *request_id);
+
+/* Block until the request is done; copy its solution to host array u (n_dofs
+ * values, may be NULL) and its record to *info (may be NULL); release the
+ * request.  Returns the request's status (IGAMG_ENOMEM if its footprint
+ * exceeds the whole budget). */
+int igamg_server_wait(igamg_server *srv, int64_t request_id, double *u, igamg_request_info *info);
+
+/* Snapshot: queued and running requests, completed count, reserved and peak
+ * reserved bytes of the budget. */
+int igamg_server_status(igamg_server *srv, int *queued, int *running, int64_t *completed,
+                        size_t *reserved_bytes, size_t *peak_reserved_bytes);
+
+/* Finish every queued request, stop the workers, free the budget. */
+int igamg_server_destroy(igamg_server *srv);
 const char *igamg_strerror(int code);
 const char *igamg_last_error(void);
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libigamg.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["hostmath.cpp", "setup.cpp", "cycle.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["hostmath.cpp", "setup.cpp", "cycle.cpp", "capi.cpp", "serve.cpp", "kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

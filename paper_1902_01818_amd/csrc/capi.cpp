@@ -14,6 +14,13 @@ struct igamg_ctx {
 
 namespace {
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace igamg {
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace igamg
+
+namespace {
 
 template <typename F>
 int guarded(F &&f) {

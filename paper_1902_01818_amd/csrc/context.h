@@ -10,19 +10,36 @@
 
 namespace igamg {
 
-// device allocation owned by the context
+// Device allocation of a context.  By default every array is a hipMalloc of
+// its own.  A caller-provided region (the serving runtime's per-request block)
+// is bump-allocated instead, so that a request allocates nothing from the
+// driver while other requests run; arrays beyond the region fall back to
+// hipMalloc and are counted.
 struct Arena {
-  std::vector<void *> ptrs;
-  size_t bytes = 0;
-  template <typename T>
-  T *alloc(size_t n) {
-    if (n == 0) n = 1;
+  std::vector<void *> ptrs;      // hipMalloc'd (freed by release)
+  size_t bytes = 0;              // bytes handed out
+  char *region = nullptr;        // optional external region
+  size_t region_cap = 0, region_used = 0;
+  int fallbacks = 0;             // allocations that did not fit the region
+  void *raw(size_t nbytes) {
+    if (nbytes == 0) nbytes = 1;
+    const size_t a = (nbytes + 255) / 256 * 256;
+    bytes += a;
+    if (region && region_used + a <= region_cap) {
+      void *p = region + region_used;
+      region_used += a;
+      return p;
+    }
+    if (region) ++fallbacks;
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    hipError_t e = hipMalloc(&p, a);
     if (e != hipSuccess) fail(IGAMG_ENOMEM, "hipMalloc failed");
     ptrs.push_back(p);
-    bytes += n * sizeof(T);
-    return (T *)p;
+    return p;
+  }
+  template <typename T>
+  T *alloc(size_t n) {
+    return (T *)raw(n * sizeof(T));
   }
   template <typename T>
   T *upload(const std::vector<T> &v, hipStream_t s) {
@@ -47,7 +64,17 @@ struct Arena {
     for (void *p : ptrs) (void)hipFree(p);
     ptrs.clear();
     bytes = 0;
+    region_used = 0;
   }
+};
+
+// Resources a caller may lend to a context (serving runtime): a device region
+// for all arrays and pinned host memory for the scalar read-back.
+struct Lent {
+  void *device = nullptr;
+  size_t device_bytes = 0;
+  void *pinned = nullptr;
+  size_t pinned_bytes = 0;
 };
 
 struct GsClass {
@@ -167,6 +194,7 @@ struct Context {
   double *h_scal = nullptr;      // pinned host mirror
   int *d_active = nullptr;       // per right-hand side: 1 = still iterating
   int *h_active = nullptr;       // pinned host mirror (written only after a stream sync)
+  bool own_pinned = true;        // h_scal / h_active allocated by the context
   hipStream_t stream = nullptr;
   Arena arena;
   std::map<std::string, TimerFamily> timers;
@@ -178,8 +206,14 @@ struct Context {
   ~Context();
 };
 
+// Validate the input and build the topology (host only, no GPU work).
+void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
+                  const igamg_options *o);
+// Finest-level unknowns and level count of a problem (host only).
+void problem_size(const igamg_patches *P, int degree, const igamg_options *o, long long *n,
+                  int *levels);
 void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
-                   const igamg_options *o, hipStream_t s);
+                   const igamg_options *o, hipStream_t s, const Lent *lent = nullptr);
 size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_options *o);
 // algorithmic bytes / flops of one launch of a kernel family on a level
 void kernel_model(const Context &c, const std::string &family, int level, double *bytes,

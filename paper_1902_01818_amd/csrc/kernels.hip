@@ -1148,12 +1148,11 @@ template <typename T, int NJ>
 static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
   constexpr int WB = Fd2Shape<NJ>::WB, KC = Fd2Shape<NJ>::KC;
   const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + KC * WB) * sizeof(T);
-  static bool lds_set = false;  // allow dynamic LDS beyond 64 KiB (gfx950: 160 KiB)
-  if (!lds_set) {
-    HIPCHK(hipFuncSetAttribute((const void *)fd2_kernel<T, NJ>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    lds_set = true;
-  }
+  // allow dynamic LDS beyond 64 KiB (gfx950: 160 KiB); once per instance,
+  // thread-safe (function-local static initialization)
+  static const hipError_t lds_set = hipFuncSetAttribute(
+      (const void *)fd2_kernel<T, NJ>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  HIPCHK(lds_set);
   if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
   dim3 grid((L.fd_rows + 15) / 16, L.n_fd, nrhs);
   fd2_kernel<T, NJ><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], L.fd_K1);

@@ -5,7 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -21,6 +24,29 @@ namespace igamg {
 void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
 int vol_tile_2d(int p);
+
+namespace {
+// Host wall time of setup phases, printed to stderr when IGAMG_SETUP_TIMING is
+// set (diagnostics of the setup cost that serving latency includes).
+struct PhaseClock {
+  bool on = std::getenv("IGAMG_SETUP_TIMING") != nullptr;
+  std::map<std::string, double> acc;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void lap(const char *name, hipStream_t s = nullptr, bool sync = false) {
+    if (!on) return;
+    if (sync) (void)hipStreamSynchronize(s);
+    auto n = std::chrono::steady_clock::now();
+    acc[name] += std::chrono::duration<double>(n - t).count();
+    t = n;
+  }
+  void report(long long N) {
+    if (!on) return;
+    std::fprintf(stderr, "[igamg setup] N=%lld", N);
+    for (auto &kv : acc) std::fprintf(stderr, " %s=%.1fms", kv.first.c_str(), kv.second * 1e3);
+    std::fprintf(stderr, "\n");
+  }
+};
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // timing
@@ -67,8 +93,8 @@ Context::~Context() {
       (void)hipEventDestroy(pe.second);
     }
   }
-  if (h_scal) (void)hipHostFree(h_scal);
-  if (h_active) (void)hipHostFree(h_active);
+  if (own_pinned && h_scal) (void)hipHostFree(h_scal);
+  if (own_pinned && h_active) (void)hipHostFree(h_active);
   arena.release();
 }
 
@@ -925,8 +951,8 @@ static T *upload_vals(Context &c, const std::vector<double> &v) {
   return c.arena.upload_as<T>(v, c.stream);
 }
 
-void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
-                   const igamg_options *o, hipStream_t s) {
+void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
+                  const igamg_options *o) {
   if (!P || !o) fail(IGAMG_EINVAL, "null argument");
   if (P->dim != 2 && P->dim != 3) fail(IGAMG_EINVAL, "dim must be 2 or 3");
   if (P->dim == 3) fail(IGAMG_EUNSUPPORTED, "3D problems are not built yet");
@@ -936,7 +962,6 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   c.p = degree;
   c.K = P->n_patches;
   c.opt = *o;
-  c.stream = s;
   c.sigma_pen = sigma;
   if (c.opt.gs_tile <= 0) c.opt.gs_tile = 2 * (degree + 1);
   if (c.opt.gs_tile < degree) fail(IGAMG_EINVAL, "gs_tile must be >= degree");
@@ -946,7 +971,6 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   c.nb = c.opt.max_rhs > 0 ? c.opt.max_rhs : 1;
   if (c.opt.discretization == IGAMG_SIPG && !(sigma > 0)) fail(IGAMG_EINVAL, "penalty must be positive");
   const bool use_gs = c.opt.smoother != IGAMG_SMOOTHER_SCMS;
-  const bool use_scms = c.opt.smoother != IGAMG_SMOOTHER_GS;
   if (c.opt.discretization == IGAMG_CONFORMING && use_gs)
     fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel ordering is defined for the SIPG space only");
   if (use_gs && c.opt.gs_tile != 2 * (degree + 1))
@@ -955,7 +979,6 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     fail(IGAMG_EINVAL, "unknown precision");
   if (c.opt.outer < IGAMG_OUTER_PCG || c.opt.outer > IGAMG_OUTER_FCG)
     fail(IGAMG_EINVAL, "unknown outer iteration");
-  const bool f32 = c.fp32();
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
@@ -970,6 +993,32 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     }
   }
   build_topology(c);
+}
+
+void problem_size(const igamg_patches *P, int degree, const igamg_options *o, long long *n,
+                  int *levels) {
+  Context c;
+  init_problem(c, P, degree, 5.0, o);
+  auto lev_el = level_elements(c);
+  LevelData L;
+  build_level_dofs(c, L, lev_el.back());
+  *n = L.N;
+  *levels = (int)lev_el.size();
+}
+
+void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
+                   const igamg_options *o, hipStream_t s, const Lent *lent) {
+  PhaseClock pc;
+  init_problem(c, P, degree, sigma, o);
+  pc.lap("topology");
+  c.stream = s;
+  if (lent && lent->device) {
+    c.arena.region = (char *)lent->device;
+    c.arena.region_cap = lent->device_bytes;
+  }
+  const bool use_gs = c.opt.smoother != IGAMG_SMOOTHER_SCMS;
+  const bool use_scms = c.opt.smoother != IGAMG_SMOOTHER_GS;
+  const bool f32 = c.fp32();
   auto lev_el = level_elements(c);
   const int NL = (int)lev_el.size();
   c.lv.resize(NL);
@@ -983,8 +1032,11 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     LevelData &L = c.lv[l];
     L.l = l;
     const bool finest = l == NL - 1;
+    pc.lap("misc", c.stream, true);
     build_level_dofs(c, L, lev_el[l]);
+    pc.lap("dofs");
     if (c.opt.discretization == IGAMG_SIPG) build_interfaces(c, L);
+    pc.lap("interfaces");
     L.d_tabB = c.arena.upload(L.tabB, c.stream);
     L.d_tabD = c.arena.upload(L.tabD, c.stream);
     L.d_mask = c.arena.upload(L.mask, c.stream);
@@ -1066,14 +1118,19 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     else
       alloc_work<double>(c, L);
     if (l >= 1) {
+      pc.lap("misc", c.stream, true);
       build_transfer(c, L, c.lv[l - 1]);
+      pc.lap("transfer");
       if (use_gs) build_gs(c, L);
+      pc.lap("gs_tiles");
       if (use_scms) {
         if (f32)
           build_scms<float>(c, L);
         else
           build_scms<double>(c, L);
+        pc.lap("scms");
         build_pieces(c, L);
+        pc.lap("pieces");
       }
     }
     L.d_pd = c.arena.upload(L.pd, c.stream);
@@ -1081,7 +1138,11 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       // volume rows + same-side interface terms, assembled in float64
       double *st64 = nullptr, *id64 = nullptr;
       std::vector<void *> tmp;
-      if (f32) {
+      if (f32 && c.arena.region) {
+        // lent region: the float64 staging stays inside it (counted in the footprint)
+        st64 = c.arena.alloc<double>((size_t)L.Ntorn * SP);
+        id64 = c.arena.alloc<double>(L.Ntorn);
+      } else if (f32) {
         HIPCHK(hipMalloc((void **)&st64, (size_t)L.Ntorn * SP * sizeof(double)));
         tmp.push_back(st64);
         HIPCHK(hipMalloc((void **)&id64, (size_t)L.Ntorn * sizeof(double)));
@@ -1090,7 +1151,9 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
         st64 = L.a64.stencil = c.arena.alloc<double>((size_t)L.Ntorn * SP);
         id64 = L.a64.invdiag = c.arena.alloc<double>(L.Ntorn);
       }
+      pc.lap("misc", c.stream, true);
       k_stencil_assemble(c, L, st64);
+      pc.lap("stencil", c.stream, true);
       int *dr = c.arena.upload(srow, c.stream), *ds = c.arena.upload(sslot, c.stream);
       double *dv = c.arena.upload(sval, c.stream);
       k_stencil_add(dr, ds, dv, (int)srow.size(), st64, SP, c.stream);
@@ -1114,7 +1177,9 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     c.N0 = (int)L0.N;
     if ((size_t)c.N0 * sizeof(double) > 64 * 1024)
       fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve kernel");
+    pc.lap("misc", c.stream, true);
     std::vector<double> A0i = spd_inverse(A0, c.N0);
+    pc.lap("coarse_inverse");
     c.d_A0inv = c.arena.upload(A0i, c.stream);
     build_maps(c, L0, &c.d_c0_cp, &c.d_c0_cidx);
   }
@@ -1137,15 +1202,24 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   c.d_scal = c.arena.alloc<double>((size_t)S_COUNT * c.nb);
   k_fill(c.d_scal, 0.0, (long long)S_COUNT * c.nb, c.stream);
   c.d_active = c.arena.alloc<int>(c.nb);
-  HIPCHK(hipHostMalloc((void **)&c.h_active, (size_t)c.nb * sizeof(int), hipHostMallocDefault));
+  const size_t pinned_need = (size_t)S_COUNT * c.nb * sizeof(double) + (size_t)c.nb * sizeof(int);
+  if (lent && lent->pinned && lent->pinned_bytes >= pinned_need) {
+    c.own_pinned = false;
+    c.h_scal = (double *)lent->pinned;
+    c.h_active = (int *)(c.h_scal + (size_t)S_COUNT * c.nb);
+  } else {
+    HIPCHK(hipHostMalloc((void **)&c.h_active, (size_t)c.nb * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c.h_scal, (size_t)S_COUNT * c.nb * sizeof(double),
+                         hipHostMallocDefault));
+  }
   for (int j = 0; j < c.nb; ++j) c.h_active[j] = 1;
   HIPCHK(hipMemcpyAsync(c.d_active, c.h_active, c.nb * sizeof(int), hipMemcpyHostToDevice,
                         c.stream));
-  HIPCHK(hipHostMalloc((void **)&c.h_scal, (size_t)S_COUNT * c.nb * sizeof(double),
-                       hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(c.stream));
   HIPCHK(hipGetLastError());
   c.arena.staging.clear();
+  pc.lap("misc");
+  pc.report(c.lv.back().N);
 }
 
 // ---------------------------------------------------------------------------
@@ -1220,8 +1294,9 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
   double bytes = all_levels * per;
   // outer float64 vectors [nb][Ntorn]: x, r, z, p, q, f (+ r_old)
   bytes += fine * 8.0 * nb * (7 + (o->outer == IGAMG_OUTER_FCG ? 1 : 0));
-  // float32 setup assembles the stencil in float64 first (freed afterwards)
-  if (gs && wb == 4.0) bytes += fine * 8.0 * (SP + 1);
+  // float32 setup assembles the stencils in float64 first: freed afterwards
+  // with driver allocations, kept inside a lent region (every level)
+  if (gs && wb == 4.0) bytes += all_levels * 8.0 * (SP + 1);
   return (size_t)bytes + (64u << 20);
 }
 

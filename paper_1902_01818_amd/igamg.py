@@ -70,11 +70,40 @@ _lib.igamg_destroy.argtypes = [_vp]
 _lib.igamg_strerror.restype = ctypes.c_char_p
 _lib.igamg_last_error.restype = ctypes.c_char_p
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("memory_budget", ctypes.c_size_t),
+                ("device", ctypes.c_int)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("true_rel_residual", ctypes.c_double),
+                ("n_dofs", ctypes.c_int64), ("footprint", ctypes.c_size_t),
+                ("fallback_allocations", ctypes.c_int),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_ready", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+_lib.igamg_problem_size.argtypes = [ctypes.POINTER(Patches), ctypes.c_int, ctypes.POINTER(Options),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]
+_lib.igamg_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
+_lib.igamg_server_submit.argtypes = [_vp, ctypes.POINTER(Patches), ctypes.c_int, ctypes.c_double,
+                                     ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int64)]
+_lib.igamg_server_wait.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(RequestInfo)]
+_lib.igamg_server_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t)]
+_lib.igamg_server_destroy.argtypes = [_vp]
+
 EXPORTED = ["igamg_default_options", "igamg_footprint", "igamg_setup", "igamg_num_dofs",
             "igamg_num_levels", "igamg_apply", "igamg_vcycle", "igamg_solve",
             "igamg_load_manufactured", "igamg_memory", "igamg_kernel_stats",
             "igamg_kernel_model", "igamg_set_timing", "igamg_destroy", "igamg_strerror",
-            "igamg_last_error"]
+            "igamg_last_error", "igamg_problem_size", "igamg_server_create", "igamg_server_submit",
+            "igamg_server_wait", "igamg_server_status", "igamg_server_destroy"]
 
 
 class IgamgError(RuntimeError):
@@ -129,6 +158,68 @@ def footprint(corners, elems, degree, **opts):
     _check(_lib.igamg_footprint(ctypes.byref(P), degree, ctypes.byref(o), ctypes.byref(b)),
            "igamg_footprint")
     return int(b.value)
+
+
+def problem_size(corners, elems, degree, **opts):
+    """(N, levels) of a problem, computed on the host."""
+    P, keep = _patches(corners, elems)
+    o = make_options(**opts)
+    n, lv = ctypes.c_int64(), ctypes.c_int()
+    _check(_lib.igamg_problem_size(ctypes.byref(P), degree, ctypes.byref(o), ctypes.byref(n),
+                                   ctypes.byref(lv)), "igamg_problem_size")
+    return int(n.value), int(lv.value)
+
+
+class Server:
+    """igamg_server_*: continuous batching of solve requests (host arrays in/out)."""
+
+    def __init__(self, slots=4, memory_budget=8 << 30, device=0):
+        cfg = ServerConfig(slots, memory_budget, device)
+        h = _vp()
+        _check(_lib.igamg_server_create(ctypes.byref(cfg), ctypes.byref(h)), "igamg_server_create")
+        self._h = h
+        self._n = {}
+
+    def submit(self, corners, elems, degree, rhs, sigma=5.0, tol=1e-8, maxit=200, **opts):
+        P, keep = _patches(corners, elems)
+        o = make_options(**opts)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        rid = ctypes.c_int64()
+        _check(_lib.igamg_server_submit(self._h, ctypes.byref(P), degree, sigma, ctypes.byref(o),
+                                        rhs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        rhs.size, tol, maxit, ctypes.byref(rid)),
+               "igamg_server_submit")
+        self._n[rid.value] = rhs.size
+        return int(rid.value)
+
+    def wait(self, rid):
+        n = self._n.pop(rid)
+        u = np.empty(n)
+        info = RequestInfo()
+        code = _lib.igamg_server_wait(self._h, rid, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.byref(info))
+        d = {f: getattr(info, f) for f, _ in RequestInfo._fields_}
+        d["status"] = code
+        return u, d
+
+    def status(self):
+        q, r, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        used, peak = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.igamg_server_status(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(c),
+                                        ctypes.byref(used), ctypes.byref(peak)), "igamg_server_status")
+        return dict(queued=q.value, running=r.value, completed=c.value, reserved=used.value,
+                    peak_reserved=peak.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.igamg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _dptr(t, n):

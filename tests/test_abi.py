@@ -75,3 +75,18 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
     assert _setup_code(ig, sq, el, 2, gs_tile=10) == ig.EUNSUPPORTED      # tile != 2(p+1)
     cube = np.zeros((1, 8, 3))
     assert _setup_code(ig, cube, np.array([[2, 2, 2]], dtype=np.int32), 2) == ig.EUNSUPPORTED
+
+
+def test_problem_size_matches_oracle_numbering(ig):
+    import oracle
+    import workloads
+    from oracle.hierarchy import level_elements
+    for name, scale, n_expected in (("c1", 1, 1089), ("c2", 8, None), ("c2", 1, 115652)):
+        cfg = workloads.config(name, scale)
+        n, lv = ig.problem_size(cfg["corners"], cfg["elems"], cfg["p"], conforming=cfg["conforming"],
+                                smoother=cfg["smoother"])
+        if n_expected is None:
+            n_expected = oracle.setup(cfg["corners"], cfg["elems"], cfg["p"],
+                                      conforming=cfg["conforming"]).N
+        assert n == n_expected
+        assert lv == len(level_elements(cfg["elems"]))
