@@ -70,6 +70,37 @@ def cpu_baseline(cfg, f, its_gpu, budget_s=15.0):
                 iterations=its)
 
 
+def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2):
+    """64 right-hand sides of the p = 6, 256-element workload solved together
+    (float32 cycle inside float64 flexible CG, or float64 PCG)."""
+    cfg = workloads.config("c4")
+    outer = "fcg" if precision == "fp32" else "pcg"
+    t0 = time.perf_counter()
+    sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
+                      conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
+                      delta=cfg["delta"], precision=precision, outer=outer, max_rhs=nrhs)
+    setup_s = time.perf_counter() - t0
+    n = sv.n_dofs
+    F = torch.from_numpy(np.stack([workloads.normal_rhs(n, 4000 + j) for j in range(nrhs)])).cuda()
+    U = torch.zeros_like(F)
+    sv.solve(F, U, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = sv.solve(F, U, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    its = [i["iterations"] for i in info]
+    out = dict(workload="C2 geometry, p=6, 256 elements/patch, %d N(0,1) right-hand sides" % nrhs,
+               dofs=n, precision=precision, outer=outer, solves_per_s=nrhs / dt,
+               ms_per_batch=dt * 1e3, setup_s=setup_s, memory_gib=sv.memory() / (1 << 30),
+               iterations_max=max(its), iterations_min=min(its),
+               max_true_rel_residual=max(i["true_rel_residual"] for i in info),
+               all_converged=all(i["converged"] for i in info))
+    sv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +108,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-cycle run")
+    ap.add_argument("--serve-requests", type=int, default=96,
+                    help="requests of the serving sample (0 = skip)")
+    ap.add_argument("--c4", action="store_true", help="also time the 64-column p = 6 workload")
     ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy MIB MiB device to device (counter calibration)")
@@ -129,6 +163,8 @@ def main():
     dt = time.perf_counter() - t0
     st = sv.kernel_stats(reset=True)
     sv.set_timing(None)
+    print("bench: float64 solves timed (%.1f ms/solve)" % (dt / args.steps * 1e3), file=sys.stderr,
+          flush=True)
     key = "%s/%d" % (family, top)
     launches = st[key]["launches"]
     avg_s = st[key]["ms"] / 1e3 / max(launches, 1)
@@ -200,6 +236,18 @@ def main():
             "rel_error_vs_fp64_solution": float(torch.linalg.norm(um - u64) / torch.linalg.norm(u64)),
         }
         sm.close()
+        print("bench: float32-cycle solves timed", file=sys.stderr, flush=True)
+    # serving: a seeded sample of the heterogeneous request stream arrives at
+    # Poisson times (rate = load x the saturated rate of a calibration burst);
+    # latency = submission to result, setup included
+    if args.serve_requests > 0:
+        from paper_1902_01818_amd import serve
+        line["serving"] = serve.serve_benchmark(
+            n_requests=args.serve_requests, slots=4, budget_gib=64.0, load=0.7,
+            calibrate=min(32, args.serve_requests))
+    # batched right-hand sides (p = 6, 256 elements per patch, 64 columns)
+    if args.c4:
+        line["c4"] = c4_leg(igamg, torch, workloads)
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

@@ -180,6 +180,7 @@ struct Context {
   int n_colors = 1;
   std::vector<double> measure;
   std::vector<LevelData> lv;                      // level 0 = coarsest
+  int *d_bad = nullptr;  // set by setup kernels when a dense block is not SPD
   // coarse solve (float64 always)
   int N0 = 0;
   double *d_A0inv = nullptr;

