@@ -129,6 +129,8 @@ struct LevelData {
   // tiles
   VolTile *d_vtiles = nullptr;
   int n_vtiles = 0;
+  VolTile *d_stiles = nullptr;  // row tiles of the stencil assembly (first row in e0)
+  int n_stiles = 0;
   std::vector<GsClass> gs;  // classes in key order
   // SCMS interiors
   int n_fd = 0;

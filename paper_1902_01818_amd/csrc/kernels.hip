@@ -155,6 +155,142 @@ __global__ void stencil_kernel(const PatchDev *pd, int K, const double *tabB, co
   st[tid] = ok ? vol_entry<D>(pt, tabB, tabD, gr, p, i, j) : 0.0;
 }
 
+// Stencil rows of the 2D volume stiffness on an RT x RT tile of rows by sum
+// factorization, one element row at a time: for element row ey the metric
+// at its Gauss points is evaluated once (as in the operator kernel), the
+// x-direction is contracted into X_k[qy][row x][dx] for the four products
+// of values/derivatives (g00 D D, g01 D B, g01 B D, g11 B B), and the
+// y-direction accumulates into the rows' (2p+1)^2 entries held in registers.
+template <int P, int RT>
+__global__ __launch_bounds__(256) void stencil2d_kernel(const VolTile *tiles, const PatchDev *pd,
+                                                        const double *tabB, const double *tabD,
+                                                        GaussRule gr, double *st) {
+  constexpr int Q = P + 1, P1 = P + 1, S1 = 2 * P + 1, S = S1 * S1;
+  constexpr int SP = (S + 15) / 16 * 16;
+  constexpr int NE = RT + P;                  // element columns touching the tile
+  constexpr int NOUT = RT * RT * S;           // entries of the tile's rows
+  constexpr int OPT = (NOUT + 255) / 256;     // entries per thread
+  constexpr int NX = Q * RT * S1;             // stage-1 items per term
+  __shared__ double sG[3][NE * Q][Q];         // metric of element row ey
+  __shared__ double sX[4][Q][RT][S1];         // x-contracted products
+  __shared__ double sBx[NE * Q][P1], sDx[NE * Q][P1], sBy[Q][P1], sDy[Q][P1];
+  __shared__ double sC[4][3];
+  const VolTile tl = tiles[blockIdx.x];
+  const PatchDev &pt = pd[tl.patch];
+  const int tid = threadIdx.x;
+  const int x0 = tl.e0[0], y0 = tl.e0[1];     // first row of the tile (unknown indices)
+  const int nx = pt.n[0], ny = pt.n[1], nelx = pt.nel[0], nely = pt.nel[1];
+  const int ex0 = max(0, x0 - P), ex1 = min(nelx - 1, x0 + RT - 1);
+  const int ey0 = max(0, y0 - P), ey1 = min(nely - 1, y0 + RT - 1);
+  const double hx = 1.0 / nelx, hy = 1.0 / nely;
+  if (tid < 12) sC[tid / 3][tid % 3] = pt.corners[tid / 3][tid % 3];
+  for (int e = tid; e < NE * Q * P1; e += 256) {
+    const int r = e / P1, a = e % P1;
+    const int ex = ex0 + r / Q;
+    const bool ok = ex <= ex1;
+    const size_t row = (size_t)pt.tab[0] + ((size_t)ex * Q + r % Q) * P1 + a;
+    sBx[r][a] = ok ? tabB[row] : 0.0;
+    sDx[r][a] = ok ? tabD[row] : 0.0;
+  }
+  double acc[OPT];
+#pragma unroll
+  for (int u = 0; u < OPT; ++u) acc[u] = 0.0;
+  for (int ey = ey0; ey <= ey1; ++ey) {
+    __syncthreads();
+    // metric at the Gauss points of element row ey, y tables of ey
+    for (int e = tid; e < NE * Q * Q; e += 256) {
+      const int c = e / Q, qy = e % Q;
+      const int ex = ex0 + c / Q, qx = c % Q;
+      double g00 = 0.0, g01 = 0.0, g11 = 0.0;
+      if (ex <= ex1) {
+        const double xe = ((double)ex + gr.x[qx]) * hx;
+        const double ye = ((double)ey + gr.x[qy]) * hy;
+        const double j00 = (1.0 - ye) * (sC[1][0] - sC[0][0]) + ye * (sC[3][0] - sC[2][0]);
+        const double j10 = (1.0 - ye) * (sC[1][1] - sC[0][1]) + ye * (sC[3][1] - sC[2][1]);
+        const double j01 = (1.0 - xe) * (sC[2][0] - sC[0][0]) + xe * (sC[3][0] - sC[1][0]);
+        const double j11 = (1.0 - xe) * (sC[2][1] - sC[0][1]) + xe * (sC[3][1] - sC[1][1]);
+        const double det = j00 * j11 - j01 * j10;
+        const double sc = gr.w[qx] * hx * gr.w[qy] * hy / fabs(det);
+        g00 = sc * (j11 * j11 + j01 * j01);
+        g01 = -sc * (j11 * j10 + j01 * j00);
+        g11 = sc * (j10 * j10 + j00 * j00);
+      }
+      sG[0][c][qy] = g00;
+      sG[1][c][qy] = g01;
+      sG[2][c][qy] = g11;
+    }
+    for (int e = tid; e < Q * P1; e += 256) {
+      const size_t row = (size_t)pt.tab[1] + ((size_t)ey * Q + e / P1) * P1 + e % P1;
+      sBy[e / P1][e % P1] = tabB[row];
+      sDy[e / P1][e % P1] = tabD[row];
+    }
+    __syncthreads();
+    // stage 1: X_k[qy][rx][dx] = sum over elements ex of both supports and qx
+    for (int e = tid; e < NX; e += 256) {
+      const int qy = e / (RT * S1), rem = e % (RT * S1), rx = rem / S1, dxi = rem % S1;
+      const int ix = x0 + rx, jx = ix + dxi - P;
+      double x00 = 0.0, x01 = 0.0, x10 = 0.0, x11 = 0.0;
+      if (ix < nx && jx >= 0 && jx < nx) {
+        const int elo = max(max(ix, jx) - P, ex0), ehi = min(min(ix, jx), ex1);
+        for (int ex = elo; ex <= ehi; ++ex) {
+          const int c0 = (ex - ex0) * Q;
+#pragma unroll
+          for (int qx = 0; qx < Q; ++qx) {
+            const double bi = sBx[c0 + qx][ix - ex], di = sDx[c0 + qx][ix - ex];
+            const double bj = sBx[c0 + qx][jx - ex], dj = sDx[c0 + qx][jx - ex];
+            const double g00 = sG[0][c0 + qx][qy], g01 = sG[1][c0 + qx][qy];
+            const double g11 = sG[2][c0 + qx][qy];
+            x00 += g00 * di * dj;
+            x01 += g01 * di * bj;
+            x10 += g01 * bi * dj;
+            x11 += g11 * bi * bj;
+          }
+        }
+      }
+      sX[0][qy][rx][dxi] = x00;
+      sX[1][qy][rx][dxi] = x01;
+      sX[2][qy][rx][dxi] = x10;
+      sX[3][qy][rx][dxi] = x11;
+    }
+    __syncthreads();
+    // stage 2: entries (ry, dy, rx, dx) of rows whose y-support holds ey
+#pragma unroll
+    for (int u = 0; u < OPT; ++u) {
+      const int o = tid + 256 * u;
+      if (o >= NOUT) continue;
+      const int ry = o / (RT * S), rem = o % (RT * S), rx = rem / S, slot = rem % S;
+      const int dyi = slot / S1, dxi = slot % S1;
+      const int iy = y0 + ry, jy = iy + dyi - P;
+      if (iy >= ny || jy < 0 || jy >= ny) continue;
+      if (ey < max(iy, jy) - P || ey > min(iy, jy)) continue;
+      const int ai = iy - ey, aj = jy - ey;
+      double s = 0.0;
+#pragma unroll
+      for (int qy = 0; qy < Q; ++qy) {
+        const double bi = sBy[qy][ai], di = sDy[qy][ai], bj = sBy[qy][aj], dj = sDy[qy][aj];
+        s += sX[0][qy][rx][dxi] * bi * bj + sX[1][qy][rx][dxi] * bi * dj +
+             sX[2][qy][rx][dxi] * di * bj + sX[3][qy][rx][dxi] * di * dj;
+      }
+      acc[u] += s;
+    }
+  }
+  // rows of the tile, padded slots zero
+#pragma unroll
+  for (int u = 0; u < OPT; ++u) {
+    const int o = tid + 256 * u;
+    if (o >= NOUT) continue;
+    const int ry = o / (RT * S), rem = o % (RT * S), rx = rem / S, slot = rem % S;
+    const int ix = x0 + rx, iy = y0 + ry;
+    if (ix >= nx || iy >= ny) continue;
+    st[(pt.off + (long long)iy * nx + ix) * SP + slot] = acc[u];
+  }
+  for (int e = tid; e < RT * RT * (SP - S); e += 256) {
+    const int r = e / (SP - S), slot = S + e % (SP - S);
+    const int ix = x0 + r % RT, iy = y0 + r / RT;
+    if (ix < nx && iy < ny) st[(pt.off + (long long)iy * nx + ix) * SP + slot] = 0.0;
+  }
+}
+
 __global__ void stencil_add_kernel(const int *rows, const int *slots, const double *vals, int n,
                                    double *st, int S) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1149,14 +1285,31 @@ template void k_convert<double, float>(const double *, const float *, float *, l
 template void k_convert<float, double>(const float *, const double *, double *, long long, int,
                                        hipStream_t, double *, const int *);
 
+int stencil_tile_2d(int p) { return p <= 3 ? 8 : 4; }
+
+template <int P, int RT>
+static void launch_stencil2d(Context &c, LevelData &L, double *out) {
+  stencil2d_kernel<P, RT><<<L.n_stiles, 256, 0, c.stream>>>(L.d_stiles, L.d_pd, L.d_tabB, L.d_tabD,
+                                                            c.gr, out);
+}
+
 void k_stencil_assemble(Context &c, LevelData &L, double *out) {
   int S = 1;
   for (int d = 0; d < c.d; ++d) S *= (2 * c.p + 1);
   long long tot = L.Ntorn * ((S + 15) / 16 * 16);
-  if (c.d == 2)
-    stencil_kernel<2><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
-                                                         L.Ntorn, out);
-  else
+  if (c.d == 2) {
+    switch (c.p) {
+      case 1: launch_stencil2d<1, 8>(c, L, out); break;
+      case 2: launch_stencil2d<2, 8>(c, L, out); break;
+      case 3: launch_stencil2d<3, 8>(c, L, out); break;
+      case 4: launch_stencil2d<4, 4>(c, L, out); break;
+      case 5: launch_stencil2d<5, 4>(c, L, out); break;
+      case 6: launch_stencil2d<6, 4>(c, L, out); break;
+      case 7: launch_stencil2d<7, 4>(c, L, out); break;
+      case 8: launch_stencil2d<8, 4>(c, L, out); break;
+      default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+    }
+  } else
     stencil_kernel<3><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
                                                          L.Ntorn, out);
   HIPCHK(hipGetLastError());

@@ -24,6 +24,7 @@ namespace igamg {
 void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
 int vol_tile_2d(int p);
+int stencil_tile_2d(int p);
 
 namespace {
 // Host wall time of setup phases, printed to stderr when IGAMG_SETUP_TIMING is
@@ -1107,6 +1108,15 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
         for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, 0}});
     L.n_vtiles = (int)vt.size();
     L.d_vtiles = c.arena.upload(vt, c.stream);
+    if (use_gs && l >= 1) {
+      std::vector<VolTile> stl;
+      const int RT = stencil_tile_2d(c.p);
+      for (int k = 0; k < c.K; ++k)
+        for (int y = 0; y < L.pd[k].n[1]; y += RT)
+          for (int x = 0; x < L.pd[k].n[0]; x += RT) stl.push_back(VolTile{k, {x, y, 0}});
+      L.n_stiles = (int)stl.size();
+      L.d_stiles = c.arena.upload(stl, c.stream);
+    }
     // glue groups
     std::vector<int> gp{0}, gi;
     for (long long ci = 0; ci < L.N; ++ci)
