@@ -28,6 +28,9 @@ void k_load_manufactured(Context &c, LevelData &L, double *out);
 // in-place inverse of a dense SPD n x n matrix (blocked Gauss-Jordan);
 // bad[0] is set to 1 when a pivot is not positive (not SPD)
 void k_spd_inverse(double *A, int n, int *bad, hipStream_t s);
+// out[r][:] = st[rows[r]][:] (rows of SP values)
+void k_gather_rows(const double *st, int SP, const int *rows, int nrows, double *out,
+                   hipStream_t s);
 
 // operator: r = mask (beta fw.*f + alpha A u); volume part by sum factorization
 template <typename T>

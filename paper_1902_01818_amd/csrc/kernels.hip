@@ -1259,6 +1259,14 @@ __global__ __launch_bounds__(256) void gj_col_kernel(double *A, int n, int k0, i
   }
 }
 
+__global__ void gather_rows_kernel(const double *st, int SP, const int *rows, int nrows,
+                                   double *out) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)nrows * SP) return;
+  const int r = (int)(e / SP), o = (int)(e % SP);
+  out[e] = st[(long long)rows[r] * SP + o];
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1505,6 +1513,12 @@ void k_coarse_solve(Context &c, const T *f0, T *u0, int nrhs) {
 }
 template void k_coarse_solve<double>(Context &, const double *, double *, int);
 template void k_coarse_solve<float>(Context &, const float *, float *, int);
+
+void k_gather_rows(const double *st, int SP, const int *rows, int nrows, double *out,
+                   hipStream_t s) {
+  if (nrows <= 0) return;
+  gather_rows_kernel<<<nblocks((long long)nrows * SP), BS, 0, s>>>(st, SP, rows, nrows, out);
+}
 
 void k_spd_inverse(double *A, int n, int *bad, hipStream_t s) {
   if (n <= 0) return;

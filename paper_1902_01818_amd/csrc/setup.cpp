@@ -415,8 +415,17 @@ static void build_interfaces(Context &c, LevelData &L) {
     const int nact = nside * ntan;
     std::vector<long long> idx(2 * nact);
     std::vector<double> val(2 * nact), dn(2 * nact);
-    for (size_t i1 = 0; i1 < n1; ++i1)
-      for (size_t i0 = 0; i0 < n0; ++i0) {
+    // the q (q^2 in 3D) points of a merged segment lie in one element of each
+    // side: their contributions are summed in a dense local block that is
+    // added to the sparse accumulator once per segment
+    const int na2 = 2 * nact;
+    std::vector<double> Mloc((size_t)na2 * na2);
+    const size_t qs1 = d == 3 ? (size_t)q : 1;
+    for (size_t s1 = 0; s1 < n1; s1 += qs1)
+      for (size_t s0 = 0; s0 < n0; s0 += q) {
+      std::fill(Mloc.begin(), Mloc.end(), 0.0);
+      for (size_t i1 = s1; i1 < s1 + qs1; ++i1)
+      for (size_t i0 = s0; i0 < s0 + q; ++i0) {
         double tpar[2] = {pts[0][i0], d == 3 ? pts[1][i1] : 0.0};
         double wt = wts[0][i0] * (d == 3 ? wts[1][i1] : 1.0);
         // physical normal and surface element from side k
@@ -527,14 +536,19 @@ static void build_interfaces(Context &c, LevelData &L) {
           }
         }
         const double eta = f.eta;
-        for (int A = 0; A < 2 * nact; ++A) {
+        for (int A = 0; A < na2; ++A) {
           if (val[A] == 0.0 && dn[A] == 0.0) continue;
-          for (int B = 0; B < 2 * nact; ++B) {
-            double v = eta * val[A] * val[B] - 0.5 * dn[A] * val[B] - 0.5 * val[A] * dn[B];
-            if (v == 0.0) continue;
-            unsigned long long key = ((unsigned long long)idx[A] << 32) | (unsigned long long)idx[B];
-            acc[key] += w * v;
-          }
+          double *row = &Mloc[(size_t)A * na2];
+          for (int B = 0; B < na2; ++B)
+            row[B] += w * (eta * val[A] * val[B] - 0.5 * dn[A] * val[B] - 0.5 * val[A] * dn[B]);
+        }
+      }
+      for (int A = 0; A < na2; ++A)
+        for (int B = 0; B < na2; ++B) {
+          const double v = Mloc[(size_t)A * na2 + B];
+          if (v == 0.0) continue;
+          unsigned long long key = ((unsigned long long)idx[A] << 32) | (unsigned long long)idx[B];
+          acc[key] += v;
         }
       }
   }
@@ -611,10 +625,84 @@ static std::vector<double> dense_block(const Context &c, const LevelData &L,
   return A;
 }
 
+// Rows of the assembled float64 stencil (device) of the representatives of
+// compact unknowns, copied to the host ([n][SP]).
+static std::vector<double> stencil_rows_host(Context &c, const LevelData &L, const double *st64,
+                                             int SP, const std::vector<int> &comps) {
+  std::vector<int> rows(comps.size());
+  for (size_t a = 0; a < comps.size(); ++a) rows[a] = L.rep[comps[a]];
+  std::vector<double> out(rows.size() * SP);
+  if (rows.empty()) return out;
+  int *d_rows = nullptr;
+  double *d_out = nullptr;
+  const bool lent = c.arena.region != nullptr;  // inside a lent region: no driver calls
+  if (lent) {
+    d_rows = c.arena.alloc<int>(rows.size());
+    d_out = c.arena.alloc<double>(out.size());
+  } else {
+    HIPCHK(hipMalloc((void **)&d_rows, rows.size() * sizeof(int)));
+    HIPCHK(hipMalloc((void **)&d_out, out.size() * sizeof(double)));
+  }
+  HIPCHK(hipMemcpyAsync(d_rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice,
+                        c.stream));
+  k_gather_rows(st64, SP, d_rows, (int)rows.size(), d_out, c.stream);
+  HIPCHK(hipMemcpyAsync(out.data(), d_out, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  if (!lent) {
+    (void)hipFree(d_rows);
+    (void)hipFree(d_out);
+  }
+  return out;
+}
+
+// Dense P^T A P over compact unknowns of the SIPG space (one torn copy each)
+// from the assembled stencil rows (volume + same-patch interface terms) and
+// the cross-patch interface terms.
+static std::vector<double> dense_block_rows(const Context &c, const LevelData &L,
+                                            const std::vector<int> &comps,
+                                            const std::vector<double> &rows, int SP) {
+  const int p = c.p, S1 = 2 * p + 1;
+  const int n = (int)comps.size();
+  std::unordered_map<long long, int> loc;
+  loc.reserve(2 * n);
+  for (int a = 0; a < n; ++a) loc[L.rep[comps[a]]] = a;
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int a = 0; a < n; ++a) {
+    const long long t1 = L.rep[comps[a]];
+    int k = 0;
+    while (k + 1 < L.K && L.pd[k + 1].off <= t1) ++k;
+    const PatchDev &pt = L.pd[k];
+    const long long lc = t1 - pt.off;
+    const int ix = (int)(lc % pt.n[0]), iy = (int)(lc / pt.n[0]);
+    for (int o = 0; o < S1 * S1; ++o) {
+      const int jx = ix + o % S1 - p, jy = iy + o / S1 - p;
+      if (jx < 0 || jx >= pt.n[0] || jy < 0 || jy >= pt.n[1]) continue;
+      auto it = loc.find(pt.off + (long long)jy * pt.n[0] + jx);
+      if (it != loc.end()) A[(size_t)a * n + it->second] += rows[(size_t)a * SP + o];
+    }
+    if (!L.if_ptr.empty())
+      for (int e = L.if_ptr[t1]; e < L.if_ptr[t1 + 1]; ++e) {
+        if (!L.if_cross[e]) continue;
+        auto it = loc.find(L.if_col[e]);
+        if (it != loc.end()) A[(size_t)a * n + it->second] += L.if_val[e];
+      }
+  }
+  return A;
+}
+
 // ---------------------------------------------------------------------------
 // smoother data
 // ---------------------------------------------------------------------------
-static void build_pieces(Context &c, LevelData &L) {
+static std::vector<double> dense_block_rows(const Context &c, const LevelData &L,
+                                            const std::vector<int> &comps,
+                                            const std::vector<double> &rows, int SP);
+static std::vector<double> stencil_rows_host(Context &c, const LevelData &L, const double *st64,
+                                             int SP, const std::vector<int> &comps);
+
+// st64: the level's assembled float64 stencil rows on the device (SIPG), or
+// null (conforming: entries by quadrature on the host)
+static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
   const int d = c.d;
   std::map<std::vector<int>, int> key2piece;
   std::vector<std::vector<int>> members;
@@ -665,7 +753,8 @@ static void build_pieces(Context &c, LevelData &L) {
       for (int t : L.copies[ci]) cidx.push_back(t);
     }
     cp.push_back((int)cidx.size());
-    std::vector<double> A = dense_block(c, L, m);
+    std::vector<double> A = st64 ? dense_block_rows(c, L, m, stencil_rows_host(c, L, st64, SP, m), SP)
+                                 : dense_block(c, L, m);
     blocks.insert(blocks.end(), A.begin(), A.end());
     pcs.push_back(pc);
     L.max_piece = std::max(L.max_piece, pc.n);
@@ -1108,7 +1197,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
         for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, 0}});
     L.n_vtiles = (int)vt.size();
     L.d_vtiles = c.arena.upload(vt, c.stream);
-    if (use_gs && l >= 1) {
+    if ((use_gs && l >= 1) || c.opt.discretization == IGAMG_SIPG) {
       std::vector<VolTile> stl;
       const int RT = stencil_tile_2d(c.p);
       for (int k = 0; k < c.K; ++k)
@@ -1145,59 +1234,70 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
         else
           build_scms<double>(c, L);
         pc.lap("scms");
-        build_pieces(c, L);
-        pc.lap("pieces");
       }
     }
     L.d_pd = c.arena.upload(L.pd, c.stream);
-    if (l >= 1 && use_gs) {
-      // volume rows + same-side interface terms, assembled in float64
-      double *st64 = nullptr, *id64 = nullptr;
-      std::vector<void *> tmp;
-      if (f32 && c.arena.region) {
-        // lent region: the float64 staging stays inside it (counted in the footprint)
-        st64 = c.arena.alloc<double>((size_t)L.Ntorn * SP);
-        id64 = c.arena.alloc<double>(L.Ntorn);
-      } else if (f32) {
-        HIPCHK(hipMalloc((void **)&st64, (size_t)L.Ntorn * SP * sizeof(double)));
-        tmp.push_back(st64);
-        HIPCHK(hipMalloc((void **)&id64, (size_t)L.Ntorn * sizeof(double)));
-        tmp.push_back(id64);
-      } else {
+    // float64 stencil rows (volume + same-patch interface terms): the
+    // Gauss-Seidel rows, and in the SIPG space the source of the dense
+    // blocks of the interface pieces and of the coarse matrix
+    const bool sipg = c.opt.discretization == IGAMG_SIPG;
+    const bool gs_rows = l >= 1 && use_gs;
+    const bool need_st = gs_rows || (sipg && (l == 0 || use_scms));
+    double *st64 = nullptr, *id64 = nullptr;
+    std::vector<void *> tmp;
+    if (need_st) {
+      if (gs_rows && !f32) {
         st64 = L.a64.stencil = c.arena.alloc<double>((size_t)L.Ntorn * SP);
         id64 = L.a64.invdiag = c.arena.alloc<double>(L.Ntorn);
+      } else if (c.arena.region) {
+        // lent region: the float64 staging stays inside it (counted in the footprint)
+        st64 = c.arena.alloc<double>((size_t)L.Ntorn * SP);
+        if (gs_rows) id64 = c.arena.alloc<double>(L.Ntorn);
+      } else {
+        HIPCHK(hipMalloc((void **)&st64, (size_t)L.Ntorn * SP * sizeof(double)));
+        tmp.push_back(st64);
+        if (gs_rows) {
+          HIPCHK(hipMalloc((void **)&id64, (size_t)L.Ntorn * sizeof(double)));
+          tmp.push_back(id64);
+        }
       }
       pc.lap("misc", c.stream, true);
       k_stencil_assemble(c, L, st64);
-      pc.lap("stencil", c.stream, true);
       int *dr = c.arena.upload(srow, c.stream), *ds = c.arena.upload(sslot, c.stream);
       double *dv = c.arena.upload(sval, c.stream);
       k_stencil_add(dr, ds, dv, (int)srow.size(), st64, SP, c.stream);
-      k_invdiag(st64, SP, center, L.d_mask, id64, L.Ntorn, c.stream);
-      if (f32) {
-        L.a32.stencil = c.arena.alloc<float>((size_t)L.Ntorn * SP);
-        L.a32.invdiag = c.arena.alloc<float>(L.Ntorn);
-        k_convert<double, float>(st64, nullptr, L.a32.stencil, (long long)L.Ntorn * SP, 1, c.stream);
-        k_convert<double, float>(id64, nullptr, L.a32.invdiag, L.Ntorn, 1, c.stream);
-        HIPCHK(hipStreamSynchronize(c.stream));
-        for (void *q : tmp) HIPCHK(hipFree(q));
-      }
+      if (gs_rows) k_invdiag(st64, SP, center, L.d_mask, id64, L.Ntorn, c.stream);
+      pc.lap("stencil", c.stream, true);
     }
-  }
-  // coarse level: dense inverse of A_0 (Cholesky based), float64 always
-  {
-    LevelData &L0 = c.lv[0];
-    std::vector<int> all(L0.N);
-    std::iota(all.begin(), all.end(), 0);
-    std::vector<double> A0 = dense_block(c, L0, all);
-    c.N0 = (int)L0.N;
-    if ((size_t)c.N0 * sizeof(double) > 64 * 1024)
-      fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve kernel");
-    pc.lap("misc", c.stream, true);
-    c.d_A0inv = c.arena.upload(A0, c.stream);
-    k_spd_inverse(c.d_A0inv, c.N0, c.d_bad, c.stream);
-    pc.lap("coarse_inverse", c.stream, true);
-    build_maps(c, L0, &c.d_c0_cp, &c.d_c0_cidx);
+    if (l >= 1 && use_scms) {
+      build_pieces(c, L, sipg ? st64 : nullptr, SP);
+      pc.lap("pieces", c.stream, true);
+    }
+    if (l == 0) {
+      // coarse level: dense inverse of A_0, float64 always
+      std::vector<int> all(L.N);
+      std::iota(all.begin(), all.end(), 0);
+      c.N0 = (int)L.N;
+      if ((size_t)c.N0 * sizeof(double) > 64 * 1024)
+        fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve kernel");
+      std::vector<double> A0 = sipg ? dense_block_rows(c, L, all, stencil_rows_host(c, L, st64, SP, all), SP)
+                                    : dense_block(c, L, all);
+      pc.lap("coarse_matrix");
+      c.d_A0inv = c.arena.upload(A0, c.stream);
+      k_spd_inverse(c.d_A0inv, c.N0, c.d_bad, c.stream);
+      pc.lap("coarse_inverse", c.stream, true);
+      build_maps(c, L, &c.d_c0_cp, &c.d_c0_cidx);
+    }
+    if (gs_rows && f32) {
+      L.a32.stencil = c.arena.alloc<float>((size_t)L.Ntorn * SP);
+      L.a32.invdiag = c.arena.alloc<float>(L.Ntorn);
+      k_convert<double, float>(st64, nullptr, L.a32.stencil, (long long)L.Ntorn * SP, 1, c.stream);
+      k_convert<double, float>(id64, nullptr, L.a32.invdiag, L.Ntorn, 1, c.stream);
+    }
+    if (!tmp.empty()) {
+      HIPCHK(hipStreamSynchronize(c.stream));
+      for (void *q : tmp) HIPCHK(hipFree(q));
+    }
   }
   LevelData &LF = c.lv.back();
   build_maps(c, LF, &c.d_fin_cp, &c.d_fin_cidx);
@@ -1344,7 +1444,8 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
   // float32 setup assembles the stencils in float64 first: freed afterwards
   // with driver allocations, kept inside a lent region (every level)
   if (gs && wb == 4.0) bytes += all_levels * 8.0 * (SP + 1);
-  return (size_t)bytes + (64u << 20);
+  // margin for the terms estimated from counts (interface lists, tiles)
+  return (size_t)(bytes * 1.08) + (32u << 20);
 }
 
 }  // namespace igamg
