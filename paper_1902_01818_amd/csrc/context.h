@@ -128,6 +128,7 @@ struct LevelData {
   int *d_glue_ptr = nullptr, *d_glue_idx = nullptr;
   // tiles
   VolTile *d_vtiles = nullptr;
+  OpTile2 *d_optiles = nullptr;  // the same tiles with their patch fields (operator kernel)
   int n_vtiles = 0;
   VolTile *d_stiles = nullptr;  // row tiles of the stencil assembly (first row in e0)
   int n_stiles = 0;

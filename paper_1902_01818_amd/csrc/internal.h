@@ -52,6 +52,17 @@ struct VolTile {
   int e0[3];
 };
 
+// Element tile of the 2D operator kernel with the fields of its patch (the
+// tile record is the only load the kernel's data loads depend on).
+struct OpTile2 {
+  double corners[4][2];  // patch corners (x fastest)
+  long long off;         // patch offset in the level vector
+  int nx;                // unknowns per row of the patch tensor
+  int nel[2];            // elements per direction
+  int tab[2];            // 1D table offsets per direction
+  int e0[2];             // first element of the tile
+};
+
 // Output tile of a transfer kernel (2D): up to 16 x 16 outputs of one patch
 // and the window of input entries they read, all resolved at setup so that
 // the kernel's loads depend on this record only.
@@ -63,9 +74,12 @@ struct XferTile {
   int w0[2], wn[2];           // input window origin and extent per direction
 };
 
+// Gauss-Seidel tile with the fields of its patch that the kernel needs, so
+// that the tile record is the only load the kernel's data loads depend on.
 struct GsTile {
-  int patch;
-  int i0[3];
+  long long off;     // patch offset in the level vector
+  int nx, ny;        // patch tensor extents
+  int i0[2];         // first unknown of the tile
   int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
 };
 

@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
 // grid.x = tile, grid.y = right-hand side.
 // ---------------------------------------------------------------------------
 template <typename T, int P, int TE>
-__global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const PatchDev *pd,
+__global__ __launch_bounds__(256) void vol2d_kernel(const OpTile2 *tiles,
                                                     const double *tabB, const double *tabD,
                                                     GaussRule gr, const T *__restrict__ u,
                                                     T *__restrict__ r,
@@ -421,24 +421,24 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
   __shared__ T sA0[ND * NQ], sA1[ND * NQ];
   __shared__ T sV0[NQ * NQ], sV1[NQ * NQ];
   __shared__ T sBx[NQ * P1], sDx[NQ * P1], sBy[NQ * P1], sDy[NQ * P1];
-  __shared__ double sC[4][3];
-  const VolTile tl = tiles[blockIdx.x];
-  const PatchDev &pt = pd[tl.patch];
+  __shared__ double sC[4][2];
+  const OpTile2 tl = tiles[blockIdx.x];
   u += (long long)blockIdx.y * vs;
   r += (long long)blockIdx.y * vs;
   const int tid = threadIdx.x;
   const int ex0 = tl.e0[0], ey0 = tl.e0[1];
-  const int nex = min(TE, pt.nel[0] - ex0), ney = min(TE, pt.nel[1] - ey0);
-  const int nx = pt.n[0];
-  const long long off = pt.off;
-  if (tid < 12) sC[tid / 3][tid % 3] = pt.corners[tid / 3][tid % 3];
+  const int nex = min(TE, tl.nel[0] - ex0), ney = min(TE, tl.nel[1] - ey0);
+  const int nx = tl.nx;
+  const long long off = tl.off;
+  // corners read through the record (a lane-indexed copy would live in scratch)
+  if (tid < 8) sC[tid / 2][tid % 2] = tiles[blockIdx.x].corners[tid / 2][tid % 2];
   for (int i = tid; i < NQ * P1; i += blockDim.x) {
     int gq = i / P1;
     bool okx = gq < nex * Q, oky = gq < ney * Q;
-    sBx[i] = okx ? (T)tabB[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : (T)0;
-    sDx[i] = okx ? (T)tabD[pt.tab[0] + (size_t)ex0 * Q * P1 + i] : (T)0;
-    sBy[i] = oky ? (T)tabB[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
-    sDy[i] = oky ? (T)tabD[pt.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
+    sBx[i] = okx ? (T)tabB[tl.tab[0] + (size_t)ex0 * Q * P1 + i] : (T)0;
+    sDx[i] = okx ? (T)tabD[tl.tab[0] + (size_t)ex0 * Q * P1 + i] : (T)0;
+    sBy[i] = oky ? (T)tabB[tl.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
+    sDy[i] = oky ? (T)tabD[tl.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
   }
   for (int i = tid; i < ND * ND; i += blockDim.x) {
     int rr = i / ND, cc = i % ND;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const VolTile *tiles, const 
   }
   __syncthreads();
   // y-contraction + metric at the Gauss points
-  const double hx = 1.0 / pt.nel[0], hy = 1.0 / pt.nel[1];
+  const double hx = 1.0 / tl.nel[0], hy = 1.0 / tl.nel[1];
   for (int i = tid; i < NQ * NQ; i += blockDim.x) {
     int gy = i / NQ, gx = i % NQ;
     T v0 = 0, v1 = 0;
@@ -557,7 +557,7 @@ __global__ void glue_kernel(int ng, const int *ptr, const int *idx, T *y, long l
 // grid.x = tile, grid.y = right-hand side.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, const PatchDev *pd,
+__global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
                                                        const T *__restrict__ st,
                                                        const T *__restrict__ invd,
                                                        const int *__restrict__ cx_li,
@@ -579,13 +579,12 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles, cons
   __shared__ T2 sBD[TT * TT];
   __shared__ int sOff[C * 16];
   const GsTile tl = tiles[blockIdx.x];
-  const PatchDev &pt = pd[tl.patch];
   f += (long long)blockIdx.y * vs;
   u += (long long)blockIdx.y * vs;
-  const int nx = pt.n[0], ny = pt.n[1];
+  const int nx = tl.nx, ny = tl.ny;
   const int x0 = tl.i0[0], y0 = tl.i0[1];
   const int wx0 = x0 - P, wy0 = y0 - P;
-  const long long off = pt.off;
+  const long long off = tl.off;
   const int lane = threadIdx.x, grp = lane >> 4, l16 = lane & 15;
   const int ax = (grp & 1) * Q1, ay = (grp >> 1) * Q1;
   // Prologue: every global load that does not depend on another one is issued
@@ -1364,8 +1363,8 @@ int vol_tile_2d(int p) { return p <= 4 ? 8 : (p <= 6 ? 6 : 4); }
 template <typename T, int P, int TE>
 static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
   dim3 grid(L.n_vtiles, nrhs);
-  vol2d_kernel<T, P, TE><<<grid, 256, 0, c.stream>>>(L.d_vtiles, L.d_pd, L.d_tabB, L.d_tabD, c.gr,
-                                                     u, r, L.d_mask, alpha, L.Ntorn);
+  vol2d_kernel<T, P, TE><<<grid, 256, 0, c.stream>>>(L.d_optiles, L.d_tabB, L.d_tabD, c.gr, u, r,
+                                                     L.d_mask, alpha, L.Ntorn);
 }
 
 template <typename T>
@@ -1400,7 +1399,7 @@ template <typename T, int P>
 static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
   LevelArrays<T> &A = L.arr<T>();
   dim3 grid(cl.count, nrhs);
-  gs2d_wave_kernel<T, P><<<grid, 64, 0, c.stream>>>(cl.tiles, L.d_pd, A.stencil, A.invdiag,
+  gs2d_wave_kernel<T, P><<<grid, 64, 0, c.stream>>>(cl.tiles, A.stencil, A.invdiag,
                                                     L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
                                                     backward ? 1 : 0, L.Ntorn);
 }

@@ -860,7 +860,7 @@ static void build_gs(Context &c, LevelData &L) {
           for (int b0 = 0; b0 < nb[0]; ++b0) {
             int pr = (b0 & 1) | ((b1 & 1) << 1);
             if (pr != par) continue;
-            GsTile tl{k, {b0 * T, b1 * T, 0}, (int)li.size(), 0};
+            GsTile tl{pt.off, pt.n[0], pt.n[1], {b0 * T, b1 * T}, (int)li.size(), 0};
             // cross-patch couplings of the tile rows
             for (int iy = b1 * T; iy < std::min(pt.n[1], (b1 + 1) * T); ++iy)
               for (int ix = b0 * T; ix < std::min(pt.n[0], (b0 + 1) * T); ++ix) {
@@ -1197,6 +1197,25 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
         for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, 0}});
     L.n_vtiles = (int)vt.size();
     L.d_vtiles = c.arena.upload(vt, c.stream);
+    if (c.d == 2) {
+      std::vector<OpTile2> ot;
+      for (const VolTile &v : vt) {
+        const PatchDev &pt = L.pd[v.patch];
+        OpTile2 o{};
+        for (int b = 0; b < 4; ++b)
+          for (int a = 0; a < 2; ++a) o.corners[b][a] = pt.corners[b][a];
+        o.off = pt.off;
+        o.nx = pt.n[0];
+        o.nel[0] = pt.nel[0];
+        o.nel[1] = pt.nel[1];
+        o.tab[0] = pt.tab[0];
+        o.tab[1] = pt.tab[1];
+        o.e0[0] = v.e0[0];
+        o.e0[1] = v.e0[1];
+        ot.push_back(o);
+      }
+      L.d_optiles = c.arena.upload(ot, c.stream);
+    }
     if ((use_gs && l >= 1) || c.opt.discretization == IGAMG_SIPG) {
       std::vector<VolTile> stl;
       const int RT = stencil_tile_2d(c.p);
