@@ -8,8 +8,12 @@ checkerboard 64/96 elements per direction (non-matching interfaces),
 degree 4, penalty 5 p^2/h, V(1,1) cycle with the hybrid smoother
 (forward Gauss-Seidel + SCMS / SCMS + backward Gauss-Seidel, damping 0.25,
 scaling 0.1), float64 PCG, N(0,1) right-hand side (seed 2002), 115,652
-unknowns, 6 grid levels.  One step = one complete solve; the right-hand side
-is resident in HBM before the timed region starts.
+unknowns.  Levels: uniform halving down to 8/12 elements per patch (4 levels,
+dense direct solve of the 2,940-unknown coarsest level on the GPU);
+--coarse-min 2 halves down to 2/3 elements (6 levels).  One step = one
+complete solve; the right-hand side is resident in HBM before the timed
+region starts.  Also reported: the float32-cycle solve (float64 flexible CG)
+and a serving sample (p50/p99 latency).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
 """
@@ -111,6 +115,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests of the serving sample (0 = skip)")
     ap.add_argument("--c4", action="store_true", help="also time the 64-column p = 6 workload")
+    ap.add_argument("--coarse-min", type=int, default=8,
+                    help="halving stops before an element count falls below this: 8 puts the "
+                         "direct solve on the 8/12-element level (2,940 unknowns, 4 levels); "
+                         "2 halves down to 2/3 elements (6 levels)")
     ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy MIB MiB device to device (counter calibration)")
@@ -127,7 +135,7 @@ def main():
     cfg = workloads.config("c2")
     sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
                       conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
-                      delta=cfg["delta"], timing=False)
+                      delta=cfg["delta"], timing=False, coarse_min=args.coarse_min)
     N = sv.n_dofs
     f_host = workloads.normal_rhs(N, cfg["rhs"][1])
     f = torch.from_numpy(f_host).cuda()
@@ -199,10 +207,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "2D SIPG, 4x4 bilinear patches (10% seeded perturbation), "
-                               "checkerboard 64/96 elements, p=4, sigma=5, hybrid V(1,1), "
-                               "FP64 PCG to 1e-8",
-                   "dofs": N, "levels": sv.n_levels, "iterations": its,
+        "config": {"workload": "2D SIPG, 4x4 bilinear patches (10%% seeded perturbation), "
+                               "checkerboard 64/96 elements, p=4, sigma=5, hybrid V(1,1) over "
+                               "%d levels (dense direct solve on the coarsest), FP64 PCG to 1e-8"
+                               % sv.n_levels,
+                   "dofs": N, "levels": sv.n_levels, "coarse_min": args.coarse_min,
+                   "iterations": its,
                    "vcycles_per_s": value * (its + 1),
                    "true_rel_residual": infos[-1]["true_rel_residual"], "all_converged": ok},
         "roofline": roof,
@@ -213,7 +223,8 @@ def main():
         u64 = u.clone()
         sm = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
                           conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
-                          delta=cfg["delta"], precision="fp32", outer="fcg")
+                          delta=cfg["delta"], precision="fp32", outer="fcg",
+                          coarse_min=args.coarse_min)
         um = torch.zeros_like(f)
         for _ in range(args.warmup):
             sm.solve(f, um, tol=1e-8, maxit=200)

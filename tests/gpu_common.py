@@ -25,9 +25,11 @@ def gpu_solver(cfg, **over):
 
 
 @functools.lru_cache(maxsize=8)
-def cached_oracle(name, scale, gs_tile=None):
+def cached_oracle(name, scale, gs_tile=None, coarse_min=None):
     cfg = workloads.config(name, scale)
     over = {} if gs_tile is None else dict(gs_tile=gs_tile)
+    if coarse_min is not None:
+        over["coarse_min"] = coarse_min
     return cfg, oracle_problem(cfg, **over)
 
 

@@ -1,6 +1,7 @@
 """Parity at the full size of the benchmark workload (2D SIPG, 4x4 bilinear
-patches, 64/96 elements, p = 4, 115,652 unknowns, 6 levels), in the launch
-configuration the benchmark times."""
+patches, 64/96 elements, p = 4, 115,652 unknowns), with the hierarchy the
+halving rule gives (6 levels, coarsest 2/3 elements) and with the one the
+benchmark times (4 levels, direct solve on 8/12 elements)."""
 import numpy as np
 import pytest
 
@@ -11,18 +12,20 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def full_pair():
-    cfg, ob = cached_oracle("c2", 1)
-    sv = gpu_solver(cfg)           # library defaults, as in bench.py
+@pytest.fixture(scope="module", params=[2, 8], ids=["coarse2", "coarse8"])
+def full_pair(request):
+    cm = request.param
+    cfg, ob = cached_oracle("c2", 1, None, cm)
+    sv = gpu_solver(cfg, coarse_min=cm)   # library defaults otherwise, as in bench.py
     assert ob.gs_tile == 2 * (cfg["p"] + 1)
+    assert sv.n_levels == len(ob.levels) == (6 if cm == 2 else 4)
     yield cfg, ob, sv
     sv.close()
 
 
 def test_full_apply_and_cycle(full_pair):
     cfg, ob, sv = full_pair
-    assert sv.n_dofs == ob.N == 115652 and sv.n_levels == 6
+    assert sv.n_dofs == ob.N == 115652
     rng = np.random.default_rng(21)
     x = rng.standard_normal(ob.N)
     y = sv.apply(torch.from_numpy(x).cuda()).cpu().numpy()
