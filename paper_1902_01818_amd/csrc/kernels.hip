@@ -360,7 +360,9 @@ __global__ void load_kernel(const PatchDev *pd, int K, const double *tabB, Gauss
 // ---------------------------------------------------------------------------
 // interface terms: r = mask (beta fw.*f + alpha A_if u).  Blocks below nb_plain
 // handle unknowns without interface couplings (one thread each); the others
-// give 16 lanes to each unknown next to an interface.  grid.y = right-hand side.
+// give 16 lanes to each unknown next to an interface.  grid.x = right-hand
+// side (fastest, so that the right-hand sides of a row block share its
+// operator data in cache), grid.y = row block.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
@@ -374,19 +376,19 @@ __global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
                                                     const T *__restrict__ f,
                                                     const T *__restrict__ fw, T beta, T alpha,
                                                     T *__restrict__ r) {
-  const long long zo = (long long)blockIdx.y * n;
+  const long long zo = (long long)blockIdx.x * n;
   u += zo;
   r += zo;
   if (f) f += zo;
-  if ((int)blockIdx.x < nb_plain) {
-    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if ((int)blockIdx.y < nb_plain) {
+    long long t = blockIdx.y * (long long)blockDim.x + threadIdx.x;
     if (t >= n || has_if[t]) return;
     T v = 0;
     if (mask[t] && f) v = beta * (fw ? fw[t] : (T)1) * f[t];
     r[t] = v;
     return;
   }
-  const int g = ((int)blockIdx.x - nb_plain) * (blockDim.x / 16) + threadIdx.x / 16;
+  const int g = ((int)blockIdx.y - nb_plain) * (blockDim.x / 16) + threadIdx.x / 16;
   const int lane = threadIdx.x % 16;
   const bool ok = g < nrows;
   const int t = ok ? rows[g] : 0;
@@ -405,7 +407,8 @@ __global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
 // volume operator, 2D, sum factorization on a TE x TE element tile:
 // r += alpha * A_vol u (atomic accumulation of the tile's outputs).  The
 // geometry (metric) is evaluated in float64 and rounded to T.
-// grid.x = tile, grid.y = right-hand side.
+// grid.x = right-hand side (the batch shares the tile's tables in cache),
+// grid.y = tile.
 // ---------------------------------------------------------------------------
 template <typename T, int P, int TE>
 __global__ __launch_bounds__(256) void vol2d_kernel(const OpTile2 *tiles,
@@ -422,16 +425,16 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const OpTile2 *tiles,
   __shared__ T sV0[NQ * NQ], sV1[NQ * NQ];
   __shared__ T sBx[NQ * P1], sDx[NQ * P1], sBy[NQ * P1], sDy[NQ * P1];
   __shared__ double sC[4][2];
-  const OpTile2 tl = tiles[blockIdx.x];
-  u += (long long)blockIdx.y * vs;
-  r += (long long)blockIdx.y * vs;
+  const OpTile2 tl = tiles[blockIdx.y];
+  u += (long long)blockIdx.x * vs;
+  r += (long long)blockIdx.x * vs;
   const int tid = threadIdx.x;
   const int ex0 = tl.e0[0], ey0 = tl.e0[1];
   const int nex = min(TE, tl.nel[0] - ex0), ney = min(TE, tl.nel[1] - ey0);
   const int nx = tl.nx;
   const long long off = tl.off;
   // corners read through the record (a lane-indexed copy would live in scratch)
-  if (tid < 8) sC[tid / 2][tid % 2] = tiles[blockIdx.x].corners[tid / 2][tid % 2];
+  if (tid < 8) sC[tid / 2][tid % 2] = tiles[blockIdx.y].corners[tid / 2][tid % 2];
   for (int i = tid; i < NQ * P1; i += blockDim.x) {
     int gq = i / P1;
     bool okx = gq < nex * Q, oky = gq < ney * Q;
@@ -554,7 +557,8 @@ __global__ void glue_kernel(int ng, const int *ptr, const int *idx, T *y, long l
 // prefetched into registers; f minus the cross-patch couplings (neighbouring
 // patches carry another patch colour, so their values are constant during the
 // launch) and 1/a_ii sit in LDS as one pair per unknown.
-// grid.x = tile, grid.y = right-hand side.
+// grid.x = right-hand side (the batch shares the tile's stencil rows in
+// cache), grid.y = tile.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
 __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
@@ -578,9 +582,9 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
   __shared__ T sU[W * W];
   __shared__ T2 sBD[TT * TT];
   __shared__ int sOff[C * 16];
-  const GsTile tl = tiles[blockIdx.x];
-  f += (long long)blockIdx.y * vs;
-  u += (long long)blockIdx.y * vs;
+  const GsTile tl = tiles[blockIdx.y];
+  f += (long long)blockIdx.x * vs;
+  u += (long long)blockIdx.x * vs;
   const int nx = tl.nx, ny = tl.ny;
   const int x0 = tl.i0[0], y0 = tl.i0[1];
   const int wx0 = x0 - P, wy0 = y0 - P;
@@ -707,7 +711,7 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
 // columns cg + 64j; B is streamed through LDS in chunks of KC rows, the next
 // chunk held in registers while the current one is used.  Long chunks keep
 // the number of dependent global-load round trips per block small.
-// grid.x = row block, grid.y = item (patch), grid.z = right-hand side.
+// grid.x = right-hand side, grid.y = row block, grid.z = item (patch).
 // ---------------------------------------------------------------------------
 template <int NJ>
 struct Fd2Shape {
@@ -761,11 +765,11 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K
   constexpr int WB = Fd2Shape<NJ>::WB;
   extern __shared__ char smraw[];
   T *sm = (T *)smraw;
-  const Fd2Item<T> it = items[blockIdx.y];
-  const int i0 = blockIdx.x * 16;
+  const Fd2Item<T> it = items[blockIdx.z];
+  const int i0 = blockIdx.y * 16;
   if (i0 >= it.rows) return;
-  const T *M1 = it.M1 + (long long)blockIdx.z * it.m1_z;
-  T *O = it.O + (long long)blockIdx.z * it.o_z;
+  const T *M1 = it.M1 + (long long)blockIdx.x * it.m1_z;
+  T *O = it.O + (long long)blockIdx.x * it.o_z;
   const int lda = K1pad + 8;
   T *sL = sm;              // 16 x lda, zero padded
   T *sZ = sL + 16 * lda;   // 16 x WB
@@ -846,7 +850,7 @@ __device__ inline T block_rows_matvec(const T *M, int n, int row0, const T *sr, 
 }
 
 // interface pieces: u[copies] += tau inv(P^T A P) r[piece];
-// grid (piece, row block, right-hand side)
+// grid (right-hand side, piece, row block): the batch shares the inverse
 template <typename T>
 __global__ __launch_bounds__(1024) void piece_kernel(const PieceDev *pieces, const int *idx,
                                                      const int *cp, const int *cidx, const T *inv,
@@ -854,12 +858,12 @@ __global__ __launch_bounds__(1024) void piece_kernel(const PieceDev *pieces, con
   extern __shared__ char smraw[];
   T *sm = (T *)smraw;
   __shared__ T spart[16 * 64];
-  const PieceDev pc = pieces[blockIdx.x];
+  const PieceDev pc = pieces[blockIdx.y];
   const int n = pc.n;
-  const int row0 = blockIdx.y * 64;
+  const int row0 = blockIdx.z * 64;
   if (row0 >= n) return;
-  r += (long long)blockIdx.z * vs;
-  u += (long long)blockIdx.z * vs;
+  r += (long long)blockIdx.x * vs;
+  u += (long long)blockIdx.x * vs;
   for (int j = threadIdx.x; j < n; j += blockDim.x) sm[j] = r[idx[pc.idx_off + j]];
   __syncthreads();
   const T y = block_rows_matvec<T>(inv + pc.inv_off, n, row0, sm, spart);
@@ -901,7 +905,7 @@ __global__ __launch_bounds__(1024) void coarse_kernel(int n, const double *inv, 
 // embedding; the coarse iterate is cleared alongside.  Prolongation: in = the
 // coarse correction, out = fine iterate += (free rows only).  The tile's
 // input window is staged in LDS in one coalesced round of loads, then
-// contracted in x and in y.  grid.x = tile, grid.y = right-hand side.
+// contracted in x and in y.  grid.x = right-hand side, grid.y = tile.
 // ---------------------------------------------------------------------------
 constexpr int MAXW = 12;
 constexpr int XT = 16, XW = 64;
@@ -916,10 +920,10 @@ __global__ __launch_bounds__(256) void transfer2d_kernel(
   __shared__ T sX[XW * XT];
   __shared__ T sV[2][XT][MAXW];
   __shared__ int sLo[2][XT];
-  const XferTile tl = tiles[blockIdx.x];
-  in += (long long)blockIdx.y * vs_in;
-  out += (long long)blockIdx.y * vs_out;
-  if (zero_out) zero_out += (long long)blockIdx.y * vs_out;
+  const XferTile tl = tiles[blockIdx.y];
+  in += (long long)blockIdx.x * vs_in;
+  out += (long long)blockIdx.x * vs_out;
+  if (zero_out) zero_out += (long long)blockIdx.x * vs_out;
   const int tid = threadIdx.x;
   // one round of independent loads: window (row r = e / XW, column e % XW),
   // band starts and values
@@ -1348,7 +1352,7 @@ void k_iface_apply(Context &c, LevelData &L, const T *u, const T *f, const T *fw
   TimeScope ts(c, "iface_apply", L.l);
   const int nb_plain = (int)nblocks(L.Ntorn);
   const int nb_rows = (L.n_if_rows + 15) / 16;
-  dim3 grid(nb_plain + nb_rows, nrhs);
+  dim3 grid(nrhs, nb_plain + nb_rows);
   iface_kernel<T><<<grid, BS, 0, c.stream>>>(L.Ntorn, nb_plain, L.d_mask, L.d_has_if, L.d_if_rows,
                                              L.n_if_rows, L.d_if_ptr, L.d_if_col,
                                              L.arr<T>().if_val, u, f, fw, beta, alpha, r);
@@ -1362,7 +1366,7 @@ int vol_tile_2d(int p) { return p <= 4 ? 8 : (p <= 6 ? 6 : 4); }
 
 template <typename T, int P, int TE>
 static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
-  dim3 grid(L.n_vtiles, nrhs);
+  dim3 grid(nrhs, L.n_vtiles);
   vol2d_kernel<T, P, TE><<<grid, 256, 0, c.stream>>>(L.d_optiles, L.d_tabB, L.d_tabD, c.gr, u, r,
                                                      L.d_mask, alpha, L.Ntorn);
 }
@@ -1398,7 +1402,7 @@ template void k_glue_sum<float>(LevelData &, float *, int, hipStream_t);
 template <typename T, int P>
 static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
   LevelArrays<T> &A = L.arr<T>();
-  dim3 grid(cl.count, nrhs);
+  dim3 grid(nrhs, cl.count);
   gs2d_wave_kernel<T, P><<<grid, 64, 0, c.stream>>>(cl.tiles, A.stencil, A.invdiag,
                                                     L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
                                                     backward ? 1 : 0, L.Ntorn);
@@ -1440,7 +1444,7 @@ static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
       (const void *)fd2_kernel<T, NJ>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   HIPCHK(lds_set);
   if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
-  dim3 grid((L.fd_rows + 15) / 16, L.n_fd, nrhs);
+  dim3 grid(nrhs, (L.fd_rows + 15) / 16, L.n_fd);
   fd2_kernel<T, NJ><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], L.fd_K1);
 }
 
@@ -1468,7 +1472,7 @@ void k_pieces(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "pieces", L.l);
   if (L.n_pieces == 0) return;
   LevelArrays<T> &A = L.arr<T>();
-  dim3 grid(L.n_pieces, (L.max_piece + 63) / 64, nrhs);
+  dim3 grid(nrhs, L.n_pieces, (L.max_piece + 63) / 64);
   piece_kernel<T><<<grid, 1024, (size_t)L.max_piece * sizeof(T), c.stream>>>(
       L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, A.piece_inv, A.r, A.u,
       (T)c.opt.damping_tau, L.Ntorn);
@@ -1480,7 +1484,7 @@ template <typename T>
 void k_restrict(Context &c, LevelData &F, LevelData &C, const T *rf, T *rc, T *uc_zero, int nrhs) {
   TimeScope ts(c, "restrict", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
-  dim3 grid(F.n_rtiles, nrhs);
+  dim3 grid(nrhs, F.n_rtiles);
   transfer2d_kernel<T, true><<<grid, 256, 0, c.stream>>>(F.d_rtiles, F.d_R_lo, F.arr<T>().R_val,
                                                          F.RW, rf, F.arr<T>().weight, C.d_mask, rc,
                                                          uc_zero, F.Ntorn, C.Ntorn);
@@ -1494,7 +1498,7 @@ template <typename T>
 void k_prolong_add(Context &c, LevelData &F, LevelData &C, const T *ec, T *uf, int nrhs) {
   TimeScope ts(c, "prolong", F.l);
   if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
-  dim3 grid(F.n_ptiles, nrhs);
+  dim3 grid(nrhs, F.n_ptiles);
   transfer2d_kernel<T, false><<<grid, 256, 0, c.stream>>>(F.d_ptiles, F.d_P_lo, F.arr<T>().P_val,
                                                           F.PW, ec, nullptr, F.d_mask, uf, nullptr,
                                                           C.Ntorn, F.Ntorn);
