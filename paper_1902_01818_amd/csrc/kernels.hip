@@ -410,24 +410,24 @@ __global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
 // grid.x = right-hand side (the batch shares the tile's tables in cache),
 // grid.y = tile.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int TE>
+template <typename T, int P, int TE, int RC>
 __global__ __launch_bounds__(256) void vol2d_kernel(const OpTile2 *tiles,
                                                     const double *tabB, const double *tabD,
                                                     GaussRule gr, const T *__restrict__ u,
                                                     T *__restrict__ r,
                                                     const unsigned char *__restrict__ mask,
-                                                    T alpha, long long vs) {
+                                                    T alpha, long long vs, int nrhs) {
   constexpr int Q = P + 1, P1 = P + 1;
   constexpr int ND = TE + P;   // unknowns per direction touched by the tile
   constexpr int NQ = TE * Q;   // Gauss points per direction in the tile
+  constexpr int NG = RC > 1 ? NQ * NQ : 1;
   __shared__ T sU[ND * ND];
   __shared__ T sA0[ND * NQ], sA1[ND * NQ];
   __shared__ T sV0[NQ * NQ], sV1[NQ * NQ];
   __shared__ T sBx[NQ * P1], sDx[NQ * P1], sBy[NQ * P1], sDy[NQ * P1];
+  __shared__ T sG[3][NG];  // metric at the tile's Gauss points (batches only)
   __shared__ double sC[4][2];
   const OpTile2 tl = tiles[blockIdx.y];
-  u += (long long)blockIdx.x * vs;
-  r += (long long)blockIdx.x * vs;
   const int tid = threadIdx.x;
   const int ex0 = tl.e0[0], ey0 = tl.e0[1];
   const int nex = min(TE, tl.nel[0] - ex0), ney = min(TE, tl.nel[1] - ey0);
@@ -443,94 +443,122 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const OpTile2 *tiles,
     sBy[i] = oky ? (T)tabB[tl.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
     sDy[i] = oky ? (T)tabD[tl.tab[1] + (size_t)ey0 * Q * P1 + i] : (T)0;
   }
-  for (int i = tid; i < ND * ND; i += blockDim.x) {
-    int rr = i / ND, cc = i % ND;
-    sU[i] = (rr < ney + P && cc < nex + P) ? u[off + (long long)(ey0 + rr) * nx + ex0 + cc] : (T)0;
-  }
-  __syncthreads();
-  // x-contraction: A0 = values, A1 = derivatives, rows = unknown rows
-  for (int i = tid; i < ND * NQ; i += blockDim.x) {
-    int rr = i / NQ, gx = i % NQ;
-    int e = gx / Q;
-    T a0 = 0, a1 = 0;
-#pragma unroll
-    for (int a = 0; a < P1; ++a) {
-      T uv = sU[rr * ND + e + a];
-      a0 += sBx[gx * P1 + a] * uv;
-      a1 += sDx[gx * P1 + a] * uv;
-    }
-    sA0[i] = a0;
-    sA1[i] = a1;
-  }
-  __syncthreads();
-  // y-contraction + metric at the Gauss points
   const double hx = 1.0 / tl.nel[0], hy = 1.0 / tl.nel[1];
-  for (int i = tid; i < NQ * NQ; i += blockDim.x) {
-    int gy = i / NQ, gx = i % NQ;
-    T v0 = 0, v1 = 0;
-    if (gy < ney * Q && gx < nex * Q) {
-      int ey = gy / Q;
-      T ux = 0, uy = 0;
-#pragma unroll
-      for (int b = 0; b < P1; ++b) {
-        ux += sBy[gy * P1 + b] * sA1[(ey + b) * NQ + gx];
-        uy += sDy[gy * P1 + b] * sA0[(ey + b) * NQ + gx];
-      }
-      int ex = gx / Q;
-      int qx = gx - ex * Q, qy = gy - ey * Q;
-      // metric w |det J| J^-1 J^-T = (w / |det J|) adj(J) adj(J)^T: one division
-      const double xe = ((double)(ex0 + ex) + gr.x[qx]) * hx;
-      const double ye = ((double)(ey0 + ey) + gr.x[qy]) * hy;
-      const double j00 = (1.0 - ye) * (sC[1][0] - sC[0][0]) + ye * (sC[3][0] - sC[2][0]);
-      const double j10 = (1.0 - ye) * (sC[1][1] - sC[0][1]) + ye * (sC[3][1] - sC[2][1]);
-      const double j01 = (1.0 - xe) * (sC[2][0] - sC[0][0]) + xe * (sC[3][0] - sC[1][0]);
-      const double j11 = (1.0 - xe) * (sC[2][1] - sC[0][1]) + xe * (sC[3][1] - sC[1][1]);
-      const double det = j00 * j11 - j01 * j10;
-      const double sc = gr.w[qx] * hx * gr.w[qy] * hy / fabs(det);
-      const T g00 = (T)(sc * (j11 * j11 + j01 * j01));
-      const T g01 = (T)(-sc * (j11 * j10 + j01 * j00));
-      const T g11 = (T)(sc * (j10 * j10 + j00 * j00));
-      v0 = g00 * ux + g01 * uy;
-      v1 = g01 * ux + g11 * uy;
+  // metric w |det J| J^-1 J^-T = (w / |det J|) adj(J) adj(J)^T at Gauss point
+  // (gx, gy) of the tile: one division
+  auto metric = [&](int gx, int gy, T &g00, T &g01, T &g11) {
+    const int ex = gx / Q, ey = gy / Q;
+    const int qx = gx - ex * Q, qy = gy - ey * Q;
+    const double xe = ((double)(ex0 + ex) + gr.x[qx]) * hx;
+    const double ye = ((double)(ey0 + ey) + gr.x[qy]) * hy;
+    const double j00 = (1.0 - ye) * (sC[1][0] - sC[0][0]) + ye * (sC[3][0] - sC[2][0]);
+    const double j10 = (1.0 - ye) * (sC[1][1] - sC[0][1]) + ye * (sC[3][1] - sC[2][1]);
+    const double j01 = (1.0 - xe) * (sC[2][0] - sC[0][0]) + xe * (sC[3][0] - sC[1][0]);
+    const double j11 = (1.0 - xe) * (sC[2][1] - sC[0][1]) + xe * (sC[3][1] - sC[1][1]);
+    const double det = j00 * j11 - j01 * j10;
+    const double sc = gr.w[qx] * hx * gr.w[qy] * hy / fabs(det);
+    g00 = (T)(sc * (j11 * j11 + j01 * j01));
+    g01 = (T)(-sc * (j11 * j10 + j01 * j00));
+    g11 = (T)(sc * (j10 * j10 + j00 * j00));
+  };
+  if (RC > 1) {
+    __syncthreads();  // corners
+    for (int i = tid; i < NQ * NQ; i += blockDim.x) {
+      T g00 = 0, g01 = 0, g11 = 0;
+      if (i / NQ < ney * Q && i % NQ < nex * Q) metric(i % NQ, i / NQ, g00, g01, g11);
+      sG[0][i % NG] = g00;
+      sG[1][i % NG] = g01;
+      sG[2][i % NG] = g11;
     }
-    sV0[i] = v0;
-    sV1[i] = v1;
   }
-  __syncthreads();
-  // transposed y-contraction: rows = output unknown rows
-  for (int i = tid; i < ND * NQ; i += blockDim.x) {
-    int rr = i / NQ, gx = i % NQ;
-    T s1 = 0, s0 = 0;
-    int elo = max(0, rr - P), ehi = min(ney - 1, rr);
-    for (int e = elo; e <= ehi; ++e) {
-      int a = rr - e;
-#pragma unroll
-      for (int g = 0; g < Q; ++g) {
-        int gy = e * Q + g;
-        s1 += sBy[gy * P1 + a] * sV0[gy * NQ + gx];
-        s0 += sDy[gy * P1 + a] * sV1[gy * NQ + gx];
-      }
+  // the right-hand sides of this block share the tables and the metric
+  const int z0 = blockIdx.x * RC, z1 = min(nrhs, z0 + RC);  // RC = 1: z0 = blockIdx.x
+  for (int z = z0; z < z1; ++z) {
+    const T *uz = u + (long long)z * vs;
+    T *rz = r + (long long)z * vs;
+    if (z > z0) __syncthreads();  // previous right-hand side done with the LDS arrays
+    for (int i = tid; i < ND * ND; i += blockDim.x) {
+      int rr = i / ND, cc = i % ND;
+      sU[i] = (rr < ney + P && cc < nex + P) ? uz[off + (long long)(ey0 + rr) * nx + ex0 + cc] : (T)0;
     }
-    sA1[i] = s1;
-    sA0[i] = s0;
-  }
-  __syncthreads();
-  // transposed x-contraction and accumulation
-  for (int i = tid; i < ND * ND; i += blockDim.x) {
-    int rr = i / ND, cc = i % ND;
-    if (rr >= ney + P || cc >= nex + P) continue;
-    T y = 0;
-    int elo = max(0, cc - P), ehi = min(nex - 1, cc);
-    for (int e = elo; e <= ehi; ++e) {
-      int a = cc - e;
+    __syncthreads();
+    // x-contraction: A0 = values, A1 = derivatives, rows = unknown rows
+    for (int i = tid; i < ND * NQ; i += blockDim.x) {
+      int rr = i / NQ, gx = i % NQ;
+      int e = gx / Q;
+      T a0 = 0, a1 = 0;
 #pragma unroll
-      for (int g = 0; g < Q; ++g) {
-        int gx = e * Q + g;
-        y += sDx[gx * P1 + a] * sA1[rr * NQ + gx] + sBx[gx * P1 + a] * sA0[rr * NQ + gx];
+      for (int a = 0; a < P1; ++a) {
+        T uv = sU[rr * ND + e + a];
+        a0 += sBx[gx * P1 + a] * uv;
+        a1 += sDx[gx * P1 + a] * uv;
       }
+      sA0[i] = a0;
+      sA1[i] = a1;
     }
-    long long t = off + (long long)(ey0 + rr) * nx + ex0 + cc;
-    if (mask[t]) unsafeAtomicAdd(&r[t], alpha * y);
+    __syncthreads();
+    // y-contraction + metric at the Gauss points
+    for (int i = tid; i < NQ * NQ; i += blockDim.x) {
+      int gy = i / NQ, gx = i % NQ;
+      T v0 = 0, v1 = 0;
+      if (gy < ney * Q && gx < nex * Q) {
+        int ey = gy / Q;
+        T ux = 0, uy = 0;
+#pragma unroll
+        for (int b = 0; b < P1; ++b) {
+          ux += sBy[gy * P1 + b] * sA1[(ey + b) * NQ + gx];
+          uy += sDy[gy * P1 + b] * sA0[(ey + b) * NQ + gx];
+        }
+        T g00, g01, g11;
+        if (RC > 1) {
+          g00 = sG[0][i % NG];
+          g01 = sG[1][i % NG];
+          g11 = sG[2][i % NG];
+        } else {
+          metric(gx, gy, g00, g01, g11);
+        }
+        v0 = g00 * ux + g01 * uy;
+        v1 = g01 * ux + g11 * uy;
+      }
+      sV0[i] = v0;
+      sV1[i] = v1;
+    }
+    __syncthreads();
+    // transposed y-contraction: rows = output unknown rows
+    for (int i = tid; i < ND * NQ; i += blockDim.x) {
+      int rr = i / NQ, gx = i % NQ;
+      T s1 = 0, s0 = 0;
+      int elo = max(0, rr - P), ehi = min(ney - 1, rr);
+      for (int e = elo; e <= ehi; ++e) {
+        int a = rr - e;
+#pragma unroll
+        for (int g = 0; g < Q; ++g) {
+          int gy = e * Q + g;
+          s1 += sBy[gy * P1 + a] * sV0[gy * NQ + gx];
+          s0 += sDy[gy * P1 + a] * sV1[gy * NQ + gx];
+        }
+      }
+      sA1[i] = s1;
+      sA0[i] = s0;
+    }
+    __syncthreads();
+    // transposed x-contraction and accumulation
+    for (int i = tid; i < ND * ND; i += blockDim.x) {
+      int rr = i / ND, cc = i % ND;
+      if (rr >= ney + P || cc >= nex + P) continue;
+      T y = 0;
+      int elo = max(0, cc - P), ehi = min(nex - 1, cc);
+      for (int e = elo; e <= ehi; ++e) {
+        int a = cc - e;
+#pragma unroll
+        for (int g = 0; g < Q; ++g) {
+          int gx = e * Q + g;
+          y += sDx[gx * P1 + a] * sA1[rr * NQ + gx] + sBx[gx * P1 + a] * sA0[rr * NQ + gx];
+        }
+      }
+      long long t = off + (long long)(ey0 + rr) * nx + ex0 + cc;
+      if (mask[t]) unsafeAtomicAdd(&rz[t], alpha * y);
+    }
   }
 }
 
@@ -1364,11 +1392,13 @@ template void k_iface_apply<float>(Context &, LevelData &, const float *, const 
 
 int vol_tile_2d(int p) { return p <= 4 ? 8 : (p <= 6 ? 6 : 4); }
 
+// one right-hand side per block, the metric evaluated on the fly (measured
+// faster for batches too than sharing a stored metric across several
+// right-hand sides per block, which costs parallelism)
 template <typename T, int P, int TE>
 static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
-  dim3 grid(nrhs, L.n_vtiles);
-  vol2d_kernel<T, P, TE><<<grid, 256, 0, c.stream>>>(L.d_optiles, L.d_tabB, L.d_tabD, c.gr, u, r,
-                                                     L.d_mask, alpha, L.Ntorn);
+  vol2d_kernel<T, P, TE, 1><<<dim3(nrhs, L.n_vtiles), 256, 0, c.stream>>>(
+      L.d_optiles, L.d_tabB, L.d_tabD, c.gr, u, r, L.d_mask, alpha, L.Ntorn, nrhs);
 }
 
 template <typename T>
