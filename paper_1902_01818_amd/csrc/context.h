@@ -186,6 +186,8 @@ struct Context {
   int *d_bad = nullptr;  // set by setup kernels when a dense block is not SPD
   // coarse solve (float64 always)
   int N0 = 0;
+  int coarse_splits = 1;            // column splits of the dense solve
+  double *d_coarse_part = nullptr;  // partial row sums [nb][splits][N0]
   double *d_A0inv = nullptr;
   int *d_c0_cp = nullptr, *d_c0_cidx = nullptr;  // compact -> copies CSR
   // finest-level maps (ABI)

@@ -900,28 +900,61 @@ __global__ __launch_bounds__(1024) void piece_kernel(const PieceDev *pieces, con
     for (int c = cp[pc.cp_off + i]; c < cp[pc.cp_off + i + 1]; ++c) u[cidx[c]] += scale * y;
 }
 
-// coarse solve in float64 whatever T: gather (sum of copies), dense symmetric
-// inverse, scatter to all copies; grid (row block, right-hand side)
+// Coarse solve in float64 whatever T: y = inv(A_0) g with g the sum of the
+// copies of f, then y written to all copies.  The columns are split over
+// gridDim.y blocks per row block (enough blocks to stream the dense inverse
+// at full bandwidth); each writes its partial row sums, and the final kernel
+// adds the splits in a fixed order (deterministic).
+// grid (row block, column split, right-hand side)
 template <typename T>
-__global__ __launch_bounds__(1024) void coarse_kernel(int n, const double *inv, const int *cp,
-                                                      const int *cidx, const T *f, T *u,
-                                                      long long vs) {
-  extern __shared__ char smraw[];
-  double *sm = (double *)smraw;
+__global__ __launch_bounds__(1024) void coarse_partial_kernel(int n, const double *inv,
+                                                              const int *cp, const int *cidx,
+                                                              const T *f, double *part,
+                                                              long long vs) {
   __shared__ double spart[16 * 64];
-  f += (long long)blockIdx.y * vs;
-  u += (long long)blockIdx.y * vs;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  extern __shared__ char smraw[];
+  double *sm = (double *)smraw;  // gathered right-hand side of the column chunk
+  const int nsplit = gridDim.y, split = blockIdx.y;
+  const int chunk = (n + nsplit - 1) / nsplit;
+  const int j0 = split * chunk, j1 = min(n, j0 + chunk);
+  f += (long long)blockIdx.z * vs;
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
     double s = 0.0;
-    for (int c = cp[i]; c < cp[i + 1]; ++c) s += (double)f[cidx[c]];
-    sm[i] = s;
+    for (int c = cp[j]; c < cp[j + 1]; ++c) s += (double)f[cidx[c]];
+    sm[j - j0] = s;
   }
   __syncthreads();
-  const int row0 = blockIdx.x * 64;
-  const double y = block_rows_matvec<double>(inv, n, row0, sm, spart);
-  const int i = row0 + (int)threadIdx.x;
-  if (threadIdx.x < 64 && i < n)
-    for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = (T)y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  double s0 = 0.0, s1 = 0.0;
+  if (i < n) {
+    const double *col = inv + i;  // column i = row i (symmetric)
+    int j = j0 + w;
+    for (; j + 16 < j1; j += 32) {
+      s0 += col[(long long)j * n] * sm[j - j0];
+      s1 += col[(long long)(j + 16) * n] * sm[j + 16 - j0];
+    }
+    if (j < j1) s0 += col[(long long)j * n] * sm[j - j0];
+  }
+  spart[w * 64 + lane] = s0 + s1;
+  __syncthreads();
+  if (w == 0 && i < n) {
+    double y = 0.0;
+    for (int k = 0; k < 16; ++k) y += spart[k * 64 + lane];
+    part[((long long)blockIdx.z * nsplit + split) * n + i] = y;
+  }
+}
+
+template <typename T>
+__global__ void coarse_final_kernel(int n, int nsplit, const double *part, const int *cp,
+                                    const int *cidx, T *u, long long vs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  part += (long long)blockIdx.y * nsplit * n;
+  u += (long long)blockIdx.y * vs;
+  double y = 0.0;
+  for (int k = 0; k < nsplit; ++k) y += part[(long long)k * n + i];
+  for (int c = cp[i]; c < cp[i + 1]; ++c) u[cidx[c]] = (T)y;
 }
 
 // ---------------------------------------------------------------------------
@@ -1540,9 +1573,13 @@ template void k_prolong_add<float>(Context &, LevelData &, LevelData &, const fl
 template <typename T>
 void k_coarse_solve(Context &c, const T *f0, T *u0, int nrhs) {
   TimeScope ts(c, "coarse", 0);
-  dim3 grid((c.N0 + 63) / 64, nrhs);
-  coarse_kernel<T><<<grid, 1024, (size_t)c.N0 * sizeof(double), c.stream>>>(
-      c.N0, c.d_A0inv, c.d_c0_cp, c.d_c0_cidx, f0, u0, c.lv[0].Ntorn);
+  const int rb = (c.N0 + 63) / 64;
+  const int ns = c.coarse_splits;
+  const int chunk = (c.N0 + ns - 1) / ns;
+  coarse_partial_kernel<T><<<dim3(rb, ns, nrhs), 1024, (size_t)chunk * sizeof(double), c.stream>>>(
+      c.N0, c.d_A0inv, c.d_c0_cp, c.d_c0_cidx, f0, c.d_coarse_part, c.lv[0].Ntorn);
+  coarse_final_kernel<T><<<dim3((c.N0 + 255) / 256, nrhs), 256, 0, c.stream>>>(
+      c.N0, ns, c.d_coarse_part, c.d_c0_cp, c.d_c0_cidx, u0, c.lv[0].Ntorn);
 }
 template void k_coarse_solve<double>(Context &, const double *, double *, int);
 template void k_coarse_solve<float>(Context &, const float *, float *, int);

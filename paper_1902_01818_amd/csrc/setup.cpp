@@ -1297,13 +1297,17 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       std::vector<int> all(L.N);
       std::iota(all.begin(), all.end(), 0);
       c.N0 = (int)L.N;
-      if ((size_t)c.N0 * sizeof(double) > 64 * 1024)
-        fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve kernel");
+      if (c.N0 > 16384)
+        fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve");
       std::vector<double> A0 = sipg ? dense_block_rows(c, L, all, stencil_rows_host(c, L, st64, SP, all), SP)
                                     : dense_block(c, L, all);
       pc.lap("coarse_matrix");
       c.d_A0inv = c.arena.upload(A0, c.stream);
       k_spd_inverse(c.d_A0inv, c.N0, c.d_bad, c.stream);
+      // enough (row block, column split) blocks to stream the inverse from HBM
+      const int rb = (c.N0 + 63) / 64;
+      c.coarse_splits = std::max(1, std::min(16, (512 + rb - 1) / rb));
+      c.d_coarse_part = c.arena.alloc<double>((size_t)c.nb * c.coarse_splits * c.N0);
       pc.lap("coarse_inverse", c.stream, true);
       build_maps(c, L, &c.d_c0_cp, &c.d_c0_cidx);
     }
