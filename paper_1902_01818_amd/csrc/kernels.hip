@@ -788,7 +788,44 @@ __device__ inline void rowblock_product(const T *A, int lda, const T *__restrict
   }
 }
 
+// The whole of B (K <= 64 NJ rows) staged in LDS with one round of
+// independent loads (no chunk loop): for NJ <= 2, where it fits.
 template <typename T, int NJ>
+__device__ inline void rowblock_product_full(const T *A, int lda, const T *__restrict__ B,
+                                             long long b_r, int K, int N, T *sM, T acc[4][NJ]) {
+  constexpr int WB = Fd2Shape<NJ>::WB;
+  constexpr int MAXL = WB * WB / 256;  // loads per thread for K = WB
+  const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
+  const int Kp = (K + 7) / 8 * 8;
+  T pre[MAXL];
+  __syncthreads();  // sM free (a previous product may still read it)
+#pragma unroll
+  for (int x = 0; x < MAXL; ++x) {
+    const int e = tid + 256 * x;
+    const int kk = e / WB, col = e % WB;
+    pre[x] = (kk < K && col < N) ? B[(long long)kk * b_r + col] : (T)0;
+  }
+#pragma unroll
+  for (int x = 0; x < MAXL; ++x)
+    if (tid + 256 * x < Kp * WB) sM[tid + 256 * x] = pre[x];
+  __syncthreads();
+  for (int k8 = 0; k8 < K; k8 += 8) {
+#pragma unroll
+    for (int kk = k8; kk < k8 + 8; ++kk) {
+      T a[4], b[NJ];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + kk];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
+    }
+  }
+}
+
+template <typename T, int NJ, bool FULL>
 __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K1pad) {
   constexpr int WB = Fd2Shape<NJ>::WB;
   extern __shared__ char smraw[];
@@ -822,7 +859,10 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[r][j] = 0;
-  rowblock_product<T, NJ>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
+  if (FULL)
+    rowblock_product_full<T, NJ>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
+  else
+    rowblock_product<T, NJ>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -830,7 +870,10 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K
       sZ[(4 * rg + r) * WB + cg + 64 * j] = acc[r][j];
       acc[r][j] = 0;
     }
-  rowblock_product<T, NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
+  if (FULL)
+    rowblock_product_full<T, NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
+  else
+    rowblock_product<T, NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = 4 * rg + r;
@@ -1497,18 +1540,31 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs) {
 template void k_gs_sweep<double>(Context &, LevelData &, bool, int);
 template void k_gs_sweep<float>(Context &, LevelData &, bool, int);
 
-template <typename T, int NJ>
-static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
-  constexpr int WB = Fd2Shape<NJ>::WB, KC = Fd2Shape<NJ>::KC;
-  const size_t lds = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB + KC * WB) * sizeof(T);
+template <typename T, int NJ, bool FULL>
+static void launch_fd2_as(Context &c, LevelData &L, int stage, int nrhs, size_t lds) {
   // allow dynamic LDS beyond 64 KiB (gfx950: 160 KiB); once per instance,
   // thread-safe (function-local static initialization)
   static const hipError_t lds_set = hipFuncSetAttribute(
-      (const void *)fd2_kernel<T, NJ>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (const void *)fd2_kernel<T, NJ, FULL>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   HIPCHK(lds_set);
-  if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
   dim3 grid(nrhs, (L.fd_rows + 15) / 16, L.n_fd);
-  fd2_kernel<T, NJ><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], L.fd_K1);
+  fd2_kernel<T, NJ, FULL><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], L.fd_K1);
+}
+
+template <typename T, int NJ>
+static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
+  constexpr int WB = Fd2Shape<NJ>::WB, KC = Fd2Shape<NJ>::KC;
+  const size_t base = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB) * sizeof(T);
+  // whole B in LDS when it fits: one load round per product instead of a chunk loop
+  const int kmax = (std::max(L.fd_K1, L.fd_N) + 7) / 8 * 8;
+  const size_t lds_full = base + (size_t)kmax * WB * sizeof(T);
+  if (NJ <= 2 && kmax <= WB && lds_full <= 150 * 1024) {
+    launch_fd2_as<T, NJ, NJ <= 2>(c, L, stage, nrhs, lds_full);
+    return;
+  }
+  const size_t lds = base + (size_t)KC * WB * sizeof(T);
+  if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
+  launch_fd2_as<T, NJ, false>(c, L, stage, nrhs, lds);
 }
 
 template <typename T>
