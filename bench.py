@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-cycle run")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests of the serving sample (0 = skip)")
-    ap.add_argument("--c4", action="store_true", help="also time the 64-column p = 6 workload")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 64-column p = 6 workload")
     ap.add_argument("--coarse-min", type=int, default=8,
                     help="halving stops before an element count falls below this: 8 puts the "
                          "direct solve on the 8/12-element level (2,940 unknowns, 4 levels); "
@@ -257,8 +257,9 @@ def main():
             n_requests=args.serve_requests, slots=4, budget_gib=64.0, load=0.7,
             calibrate=min(32, args.serve_requests))
     # batched right-hand sides (p = 6, 256 elements per patch, 64 columns)
-    if args.c4:
-        line["c4"] = c4_leg(igamg, torch, workloads)
+    if not args.no_c4:
+        line["c4"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)
+        print("bench: 64-column p = 6 batch timed", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
