@@ -68,6 +68,20 @@ extern "C" {
 #define IGAMG_OUTER_PCG 0
 #define IGAMG_OUTER_MG 1
 #define IGAMG_OUTER_FCG 2
+/* Operator applies (the cycle's residuals and the float64 outer apply).
+ * AUTO: from the stored matrix rows on the levels that keep them (SIPG with
+ * a Gauss-Seidel smoother keeps the rows of every level above the coarsest:
+ * (2p+1)^2 same-patch entries per unknown plus the cross-patch couplings),
+ * by sum factorization elsewhere.  SUMFACT: matrix-free everywhere (eq.
+ * model, Section 2, evaluated by sum factorization; the SIPG interface terms
+ * of Section 3 as a sparse gather).  ROWS: the stored rows wherever the
+ * cycle has them; setup fails with IGAMG_EUNSUPPORTED when it has none.  In
+ * float32 cycles the rows also keep a float64 copy on the finest level for
+ * the outer apply.  Both forms apply the same matrix (assembled with the
+ * same quadrature); their results differ by rounding only. */
+#define IGAMG_APPLY_AUTO 0
+#define IGAMG_APPLY_SUMFACT 1
+#define IGAMG_APPLY_ROWS 2
 
 /* Multi-patch geometry (Section 2, eqs. omega:1/omega:2, Assumption 1).
  * Each patch map is the multilinear interpolation of its 2^dim corners; corner
@@ -95,6 +109,7 @@ typedef struct {
   int timing;         /* 1 = record per-kernel-family event timings (igamg_kernel_stats) */
   int max_rhs;        /* right-hand sides processed together by one call (work-vector
                          capacity, 0 = 1); larger nrhs are split into batches of max_rhs */
+  int operator_apply; /* IGAMG_APPLY_* */
 } igamg_options;
 
 typedef struct {
@@ -108,7 +123,7 @@ typedef struct {
 typedef struct igamg_ctx igamg_ctx;
 
 /* Fill *o with the defaults (SIPG, hybrid, V(1,1), tau 0.25, delta 0.1, FP64, PCG,
- * one right-hand side per batch). */
+ * one right-hand side per batch, operator applies IGAMG_APPLY_AUTO). */
 void igamg_default_options(igamg_options *o);
 
 /* Host only, no GPU work: device bytes igamg_setup will allocate for this

@@ -72,6 +72,7 @@ void igamg_default_options(igamg_options *o) {
   o->coarse_min = 0;
   o->timing = 0;
   o->max_rhs = 0;
+  o->operator_apply = IGAMG_APPLY_AUTO;
 }
 
 int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o,

@@ -133,6 +133,10 @@ struct LevelData {
   VolTile *d_stiles = nullptr;  // row tiles of the stencil assembly (first row in e0)
   int n_stiles = 0;
   std::vector<GsClass> gs;  // classes in key order
+  GsTile *d_atiles = nullptr;  // every Gauss-Seidel tile of the level (stored-row operator)
+  int n_atiles = 0;
+  // the cycle's residuals on this level use the stored rows (k_stencil_apply)
+  bool st_apply = false;
   // SCMS interiors
   int n_fd = 0;
   int fd_rows = 0, fd_K1 = 0, fd_N = 0;
@@ -192,6 +196,7 @@ struct Context {
   int *d_c0_cp = nullptr, *d_c0_cidx = nullptr;  // compact -> copies CSR
   // finest-level maps (ABI)
   int *d_fin_cp = nullptr, *d_fin_cidx = nullptr;
+  bool apply64_rows = false;  // the float64 finest-level apply reads the stored rows
   // outer iteration vectors (float64, torn layout, finest level, [nb][Ntorn])
   double *x = nullptr, *rr = nullptr, *z = nullptr, *pp = nullptr, *qq = nullptr, *ff = nullptr;
   double *rold = nullptr;        // previous residual (flexible CG)

@@ -28,6 +28,10 @@ namespace {
 // r = f - A u on level L (f distributed, result consistent)
 template <typename T>
 void residual(Context &c, LevelData &L, const T *u, const T *f, T *r, int nb) {
+  if (L.st_apply) {
+    k_stencil_apply<T>(c, L, L.arr<T>(), u, f, nullptr, (T)1, (T)-1, r, nb);
+    return;
+  }
   k_iface_apply<T>(c, L, u, f, nullptr, (T)1, (T)-1, r, nb);
   k_vol_apply<T>(c, L, u, r, (T)-1, nb);
   k_glue_sum<T>(L, r, nb, c.stream);
@@ -139,6 +143,10 @@ void upload_active(Context &c, int nb) {
 void apply64(Context &c, const double *u, const double *f, const double *fw, double *r,
              double alpha, int nb) {
   LevelData &L = c.lv.back();
+  if (c.apply64_rows) {
+    k_stencil_apply<double>(c, L, L.a64, u, f, fw, 1.0, alpha, r, nb);
+    return;
+  }
   k_iface_apply<double>(c, L, u, f, fw, 1.0, alpha, r, nb);
   k_vol_apply<double>(c, L, u, r, alpha, nb);
   k_glue_sum<double>(L, r, nb, c.stream);

@@ -40,6 +40,11 @@ template <typename T>
 void k_vol_apply(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs);
 template <typename T>
 void k_glue_sum(LevelData &L, T *y, int nrhs, hipStream_t s);
+// the same operator from the stored rows of levels that keep them (SIPG
+// Gauss-Seidel levels): r = mask (beta fw.*f + alpha A u), no glue needed
+template <typename T>
+void k_stencil_apply(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u, const T *f,
+                     const T *fw, T beta, T alpha, T *r, int nrhs);
 
 // smoothers (on L.arr<T>().f / .u / .r)
 template <typename T>

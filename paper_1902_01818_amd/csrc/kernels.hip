@@ -734,6 +734,127 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
 }
 
 // ---------------------------------------------------------------------------
+// Operator by the stored rows (levels that keep the Gauss-Seidel rows):
+//   r = mask (beta fw.*f + alpha (S u + X u)),
+// S = same-patch rows (volume + same-side interface terms, (2p+1)^2 per
+// unknown), X = the cross-patch couplings of each tile's rows.  The matrix is
+// the one the sum-factorized volume kernel and the interface kernel apply
+// (assembled with the same quadrature); it is read once per group of RB
+// right-hand sides instead of being recomputed for each of them.
+// One block per (tile of the Gauss-Seidel partition, group of RB right-hand
+// sides): the group's u windows sit in LDS and every 16-lane row group reads
+// a stencil row once and applies it to the RB right-hand sides.  1D grid:
+// consecutive block ids go to different XCDs (id mod 8), so the groups of one
+// tile get ids of equal residue and share one XCD's L2.
+// ---------------------------------------------------------------------------
+template <typename T, int P, int RB>
+__global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntiles, int ngroups,
+                                                   int nrhs, const T *__restrict__ st,
+                                                   const int *__restrict__ cx_li,
+                                                   const int *__restrict__ cx_col,
+                                                   const T *__restrict__ cx_val,
+                                                   const unsigned char *__restrict__ mask,
+                                                   const T *__restrict__ u,
+                                                   const T *__restrict__ f,
+                                                   const T *__restrict__ fw, T beta, T alpha,
+                                                   T *__restrict__ r, long long vs) {
+  constexpr int Q1 = P + 1, TT = 2 * Q1, W = TT + 2 * P, NT = TT * TT;
+  constexpr int S1 = 2 * P + 1, S = S1 * S1;
+  constexpr int C = (S + 15) / 16;
+  constexpr int SP = 16 * C;
+  __shared__ T sU[RB][W * W];
+  __shared__ T sX[RB][NT];
+  const int b = blockIdx.x;
+  const int slot = b >> 3;
+  const int tile = (slot / ngroups) * 8 + (b & 7);
+  if (tile >= ntiles) return;
+  const int z0 = (slot % ngroups) * RB;
+  const int nz = min(RB, nrhs - z0);
+  const GsTile tl = tiles[tile];
+  const int nx = tl.nx, ny = tl.ny;
+  const int x0 = tl.i0[0], y0 = tl.i0[1];
+  const int wx0 = x0 - P, wy0 = y0 - P;
+  const long long off = tl.off;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < RB * W * W; i += 256) {
+    const int z = i / (W * W), k = i - z * (W * W);
+    const int gy = wy0 + k / W, gx = wx0 + k % W;
+    const bool ok = z < nz && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    sU[z][k] = ok ? u[(long long)(z0 + z) * vs + off + (long long)gy * nx + gx] : (T)0;
+  }
+  for (int i = tid; i < RB * NT; i += 256) sX[i / NT][i % NT] = (T)0;
+  __syncthreads();
+  // cross-patch couplings: one wave per right-hand side, so the additions
+  // into a row come in a fixed order
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int z = wave; z < nz; z += 4) {
+    const T *uz = u + (long long)(z0 + z) * vs;
+    for (int e = lane; e < tl.cx_n; e += 64) {
+      const int q = tl.cx_off + e;
+      unsafeAtomicAdd(&sX[z][cx_li[q]], cx_val[q] * uz[cx_col[q]]);
+    }
+  }
+  const int g = tid >> 4, l16 = tid & 15;
+  int soff[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int k = l16 + 16 * c;
+    soff[c] = k < S ? (k / S1 - P) * W + (k % S1 - P) : 0;
+  }
+  // rows outside the patch (ragged last tiles) read the tile origin's row
+  // and are not written
+  auto row_ptr = [&](int li) {
+    const int ix = x0 + li % TT, iy = y0 + li / TT;
+    const bool ok = ix < nx && iy < ny;
+    const long long t = ok ? off + (long long)iy * nx + ix : off + (long long)y0 * nx + x0;
+    return st + t * SP + l16;
+  };
+  T a[C], an[C];
+  {
+    const T *sr = row_ptr(g);
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] = sr[16 * c];
+  }
+  __syncthreads();  // cross sums complete
+  for (int li = g; li < NT; li += 16) {
+    if (li + 16 < NT) {
+      const T *sr = row_ptr(li + 16);
+#pragma unroll
+      for (int c = 0; c < C; ++c) an[c] = sr[16 * c];
+    }
+    const int ix = x0 + li % TT, iy = y0 + li / TT;
+    if (ix < nx && iy < ny) {
+      const int wi = (iy - wy0) * W + (ix - wx0);
+#pragma unroll
+      for (int z = 0; z < RB; ++z) {
+        if (z >= nz) break;
+        T acc0 = 0, acc1 = 0;
+#pragma unroll
+        for (int c = 0; c < C; c += 2) acc0 += a[c] * sU[z][wi + soff[c]];
+#pragma unroll
+        for (int c = 1; c < C; c += 2) acc1 += a[c] * sU[z][wi + soff[c]];
+        const T acc = row16_scan(acc0 + acc1);
+        if (l16 == 15) sX[z][li] += acc;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] = an[c];
+  }
+  __syncthreads();
+  // coalesced write-back of the tile rows
+  for (int i = tid; i < RB * NT; i += 256) {
+    const int z = i / NT, li = i - z * NT;
+    const int ix = x0 + li % TT, iy = y0 + li / TT;
+    if (z >= nz || ix >= nx || iy >= ny) continue;
+    const long long t = off + (long long)iy * nx + ix;
+    const long long zo = (long long)(z0 + z) * vs;
+    T v = alpha * sX[z][li];
+    if (f) v += beta * (fw ? fw[t] : (T)1) * f[zo + t];
+    r[zo + t] = mask[t] ? v : (T)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Row-block products of the fast diagonalization (see Fd2Item).  A block of
 // 256 threads owns 16 rows: thread (rg, cg) accumulates rows 4rg..4rg+3 and
 // columns cg + 64j; B is streamed through LDS in chunks of KC rows, the next
@@ -1539,6 +1660,52 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs) {
 }
 template void k_gs_sweep<double>(Context &, LevelData &, bool, int);
 template void k_gs_sweep<float>(Context &, LevelData &, bool, int);
+
+template <typename T, int P, int RB>
+static void launch_sp2d(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u, const T *f,
+                        const T *fw, T beta, T alpha, T *r, int nrhs) {
+  const int ng = (nrhs + RB - 1) / RB;
+  const long long nblk = (long long)((L.n_atiles + 7) / 8) * 8 * ng;
+  sp2d_kernel<T, P, RB><<<(unsigned)nblk, 256, 0, c.stream>>>(
+      L.d_atiles, L.n_atiles, ng, nrhs, A.stencil, L.d_gcx_li, L.d_gcx_col, A.gcx_val, L.d_mask,
+      u, f, fw, beta, alpha, r, L.Ntorn);
+}
+
+// one right-hand side per block, or groups of 4 (float64) / 8 (float32)
+template <typename T, int P>
+static void launch_sp2d_rb(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u,
+                           const T *f, const T *fw, T beta, T alpha, T *r, int nrhs) {
+  constexpr int RBB = sizeof(T) == 8 ? 4 : 8;
+  if (nrhs == 1)
+    launch_sp2d<T, P, 1>(c, L, A, u, f, fw, beta, alpha, r, nrhs);
+  else
+    launch_sp2d<T, P, RBB>(c, L, A, u, f, fw, beta, alpha, r, nrhs);
+}
+
+template <typename T>
+void k_stencil_apply(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u, const T *f,
+                     const T *fw, T beta, T alpha, T *r, int nrhs) {
+  TimeScope ts(c, "stencil_apply", L.l);
+  if (c.d != 2 || !A.stencil || !L.d_atiles || L.n_atiles == 0)
+    fail(IGAMG_EUNSUPPORTED, "no stored operator rows on this level");
+  switch (c.p) {
+    case 1: launch_sp2d_rb<T, 1>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    case 2: launch_sp2d_rb<T, 2>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    case 3: launch_sp2d_rb<T, 3>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    case 4: launch_sp2d_rb<T, 4>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    case 5: launch_sp2d_rb<T, 5>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    case 6: launch_sp2d_rb<T, 6>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    case 7: launch_sp2d_rb<T, 7>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    case 8: launch_sp2d_rb<T, 8>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+    default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+  }
+}
+template void k_stencil_apply<double>(Context &, LevelData &, const LevelArrays<double> &,
+                                      const double *, const double *, const double *, double,
+                                      double, double *, int);
+template void k_stencil_apply<float>(Context &, LevelData &, const LevelArrays<float> &,
+                                     const float *, const float *, const float *, float, float,
+                                     float *, int);
 
 template <typename T, int NJ, bool FULL>
 static void launch_fd2_as(Context &c, LevelData &L, int stage, int nrhs, size_t lds) {

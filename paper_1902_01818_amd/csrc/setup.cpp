@@ -842,12 +842,15 @@ static void build_scms(Context &c, LevelData &L) {
   A.fd[1] = c.arena.upload(fb, c.stream);
 }
 
-static void build_gs(Context &c, LevelData &L) {
+// keep64: the float64 couplings are uploaded too (float32 cycle whose finest
+// level also serves the float64 outer apply from the stored rows)
+static void build_gs(Context &c, LevelData &L, bool keep64) {
   const int d = c.d, T = c.opt.gs_tile;
   if (T != 2 * (c.p + 1)) fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel tiles of width 2(p+1) only");
   if (d != 2) fail(IGAMG_EUNSUPPORTED, "3D Gauss-Seidel not built");
   std::vector<int> li, col;
   std::vector<double> val;
+  std::vector<GsTile> all;
   for (int colr = 0; colr < c.n_colors; ++colr)
     for (int par = 0; par < (1 << d); ++par) {
       std::vector<GsTile> tiles;
@@ -881,13 +884,14 @@ static void build_gs(Context &c, LevelData &L) {
       cl.count = (int)tiles.size();
       cl.tiles = c.arena.upload(tiles, c.stream);
       L.gs.push_back(cl);
+      all.insert(all.end(), tiles.begin(), tiles.end());
     }
+  L.n_atiles = (int)all.size();
+  L.d_atiles = c.arena.upload(all, c.stream);
   L.d_gcx_li = c.arena.upload(li, c.stream);
   L.d_gcx_col = c.arena.upload(col, c.stream);
-  if (c.fp32())
-    L.a32.gcx_val = c.arena.upload_as<float>(val, c.stream);
-  else
-    L.a64.gcx_val = c.arena.upload_as<double>(val, c.stream);
+  if (c.fp32()) L.a32.gcx_val = c.arena.upload_as<float>(val, c.stream);
+  if (!c.fp32() || keep64) L.a64.gcx_val = c.arena.upload_as<double>(val, c.stream);
 }
 
 static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
@@ -1073,6 +1077,11 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
     fail(IGAMG_EINVAL, "unknown precision");
   if (c.opt.outer < IGAMG_OUTER_PCG || c.opt.outer > IGAMG_OUTER_FCG)
     fail(IGAMG_EINVAL, "unknown outer iteration");
+  if (c.opt.operator_apply < IGAMG_APPLY_AUTO || c.opt.operator_apply > IGAMG_APPLY_ROWS)
+    fail(IGAMG_EINVAL, "unknown operator_apply");
+  if (c.opt.operator_apply == IGAMG_APPLY_ROWS &&
+      (c.opt.discretization != IGAMG_SIPG || !use_gs))
+    fail(IGAMG_EUNSUPPORTED, "stored operator rows exist for SIPG with a Gauss-Seidel smoother only");
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
@@ -1128,6 +1137,13 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     LevelData &L = c.lv[l];
     L.l = l;
     const bool finest = l == NL - 1;
+    // residuals from the stored rows (SIPG Gauss-Seidel levels); a float32
+    // cycle keeps the finest level's float64 rows for the outer apply
+    const bool rows = c.opt.operator_apply != IGAMG_APPLY_SUMFACT &&
+                      c.opt.discretization == IGAMG_SIPG && use_gs && l >= 1;
+    const bool keep64 = rows && f32 && finest;
+    L.st_apply = rows;
+    if (finest) c.apply64_rows = rows;
     pc.lap("misc", c.stream, true);
     build_level_dofs(c, L, lev_el[l]);
     pc.lap("dofs");
@@ -1245,7 +1261,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       pc.lap("misc", c.stream, true);
       build_transfer(c, L, c.lv[l - 1]);
       pc.lap("transfer");
-      if (use_gs) build_gs(c, L);
+      if (use_gs) build_gs(c, L, keep64);
       pc.lap("gs_tiles");
       if (use_scms) {
         if (f32)
@@ -1265,7 +1281,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     double *st64 = nullptr, *id64 = nullptr;
     std::vector<void *> tmp;
     if (need_st) {
-      if (gs_rows && !f32) {
+      if (gs_rows && (!f32 || keep64)) {
         st64 = L.a64.stencil = c.arena.alloc<double>((size_t)L.Ntorn * SP);
         id64 = L.a64.invdiag = c.arena.alloc<double>(L.Ntorn);
       } else if (c.arena.region) {

@@ -23,6 +23,7 @@ SIPG, CONFORMING = 0, 1
 SMOOTHERS = {"hybrid": 0, "scms": 1, "gs": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 OUTERS = {"pcg": 0, "mg": 1, "fcg": 2}
+APPLIES = {"auto": 0, "sumfact": 1, "rows": 2}
 
 
 class Patches(ctypes.Structure):
@@ -37,7 +38,8 @@ class Options(ctypes.Structure):
                 ("damping_tau", ctypes.c_double), ("scaling_delta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("outer", ctypes.c_int),
                 ("gs_tile", ctypes.c_int), ("coarse_min", ctypes.c_int),
-                ("timing", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("max_rhs", ctypes.c_int),
+                ("operator_apply", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -136,7 +138,8 @@ def _patches(corners, elems):
 
 
 def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1, nu=1,
-                 precision="fp64", outer="pcg", gs_tile=0, coarse_min=0, timing=False, max_rhs=0):
+                 precision="fp64", outer="pcg", gs_tile=0, coarse_min=0, timing=False, max_rhs=0,
+                 operator_apply="auto"):
     o = Options()
     _lib.igamg_default_options(ctypes.byref(o))
     o.discretization = CONFORMING if conforming else SIPG
@@ -148,6 +151,7 @@ def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1,
     o.gs_tile, o.coarse_min = gs_tile, coarse_min
     o.timing = 1 if timing else 0
     o.max_rhs = max_rhs
+    o.operator_apply = APPLIES[operator_apply]
     return o
 
 
@@ -296,7 +300,7 @@ class Solver:
         return int(b.value)
 
     def kernel_stats(self, reset=False):
-        cap = 64
+        cap = 256
         names = ctypes.create_string_buffer(32 * cap)
         ms = (ctypes.c_double * cap)()
         launches = (ctypes.c_int64 * cap)()

@@ -73,6 +73,10 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
     assert _setup_code(ig, sq, el, 2, max_rhs=-1) == ig.EINVAL
     assert _setup_code(ig, sq, el, 2, conforming=True, smoother="gs") == ig.EUNSUPPORTED
     assert _setup_code(ig, sq, el, 2, gs_tile=10) == ig.EUNSUPPORTED      # tile != 2(p+1)
+    # stored operator rows exist only with a Gauss-Seidel smoother in the SIPG space
+    assert _setup_code(ig, sq, el, 2, smoother="scms", operator_apply="rows") == ig.EUNSUPPORTED
+    assert _setup_code(ig, sq, el, 2, conforming=True, smoother="scms",
+                       operator_apply="rows") == ig.EUNSUPPORTED
     cube = np.zeros((1, 8, 3))
     assert _setup_code(ig, cube, np.array([[2, 2, 2]], dtype=np.int32), 2) == ig.EUNSUPPORTED
 

@@ -22,19 +22,21 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # (config, scale, Gauss-Seidel tile width; None = the default 2(p+1), the
-# only width the library's Gauss-Seidel kernel takes)
-CASES = [("c1", 1, None), ("c1", 2, None), ("c2", 16, None), ("c2", 8, None)]
+# only width the library's Gauss-Seidel kernel takes, operator applies: "auto"
+# = stored rows on the SIPG Gauss-Seidel levels, "sumfact" = matrix-free)
+CASES = [("c1", 1, None, "auto"), ("c1", 2, None, "auto"), ("c2", 16, None, "auto"),
+         ("c2", 8, None, "auto"), ("c2", 8, None, "sumfact")]
 
 
 def _to_gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
 
 
-@pytest.fixture(scope="module", params=CASES, ids=["%s/%d/T%s" % c for c in CASES])
+@pytest.fixture(scope="module", params=CASES, ids=["%s/%d/T%s/%s" % c for c in CASES])
 def pair(request):
-    name, scale, gs_tile = request.param
+    name, scale, gs_tile, apply = request.param
     cfg, ob = cached_oracle(name, scale, gs_tile)
-    sv = gpu_solver(cfg, gs_tile=ob.gs_tile if not cfg["conforming"] else 0)
+    sv = gpu_solver(cfg, gs_tile=ob.gs_tile if not cfg["conforming"] else 0, operator_apply=apply)
     yield cfg, ob, sv
     sv.close()
 
