@@ -62,6 +62,14 @@ extern "C" {
  * paper, which computes in float64 throughout). */
 #define IGAMG_FP64 0
 #define IGAMG_FP32 1
+/* float32 cycle as IGAMG_FP32 whose patch-interior solves of the subspace
+ * corrected mass smoother (Section 5, eq. Ldef, fast diagonalization) round
+ * their contraction operands to bfloat16 (nearest even) and accumulate in
+ * float32 on the matrix cores.  The eigenvector matrices are rounded once,
+ * the same rounded matrix serving both directions, so the interior solve
+ * stays symmetric in exact arithmetic; the outer iteration should be
+ * IGAMG_OUTER_FCG. */
+#define IGAMG_BF16_SCMS 2
 /* Outer iteration: PCG preconditioned by one cycle (Section 4); the cycle
  * used directly as the solver (Section 4); flexible CG (Polak-Ribiere beta,
  * robust to a preconditioner that is not exactly symmetric, e.g. float32). */
@@ -102,7 +110,7 @@ typedef struct {
   int nu;             /* smoothing steps (Algorithm 1/2) */
   double damping_tau; /* tau of eq. Ldef */
   double scaling_delta; /* SCMS scaling sigma = 1/(delta h^2), Section 5 */
-  int precision;      /* IGAMG_FP64 / IGAMG_FP32 (cycle arithmetic) */
+  int precision;      /* IGAMG_FP64 / IGAMG_FP32 / IGAMG_BF16_SCMS (cycle arithmetic) */
   int outer;          /* IGAMG_OUTER_* */
   int gs_tile;        /* Gauss-Seidel tile width T >= p of the colour ordering, 0 = 2(p+1) */
   int coarse_min;     /* halve element counts while all are even and their half >= coarse_min; 0 = 2 */

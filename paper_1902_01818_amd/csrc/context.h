@@ -211,7 +211,10 @@ struct Context {
   std::map<std::string, TimerFamily> timers;
   std::string timing_filter;  // time only families whose key starts with this
 
-  bool fp32() const { return opt.precision == IGAMG_FP32; }
+  // float32 cycle (IGAMG_FP32, or IGAMG_BF16_SCMS whose patch-interior
+  // contractions take bfloat16 operands)
+  bool fp32() const { return opt.precision != IGAMG_FP64; }
+  bool bf16_scms() const { return opt.precision == IGAMG_BF16_SCMS; }
   void launch_begin(const char *fam, hipEvent_t *b, hipEvent_t *e);
   void launch_end(const char *fam, hipEvent_t b, hipEvent_t e, int launches = 1);
   ~Context();

@@ -1014,6 +1014,213 @@ __global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K
 }
 
 // ---------------------------------------------------------------------------
+// The same two chained row-block products on the matrix cores.  Wave w of the
+// block owns the 16-column tiles w, w+4, ..., w+4(NJ-1) of the 16-row block;
+// a k-step issues one MFMA per tile, the A fragment shared by the tiles:
+//   float64: v_mfma_f64_16x16x4f64 on the stored operands;
+//   float32: v_mfma_f32_16x16x4f32 on the stored operands;
+//   bf16:    v_mfma_f32_16x16x32_bf16 on operands rounded to bfloat16
+//            (nearest even) with float32 accumulation.
+// Fragments of a 16 x 16 tile, lane l = 16 q + c (c < 16): A row c, k-block
+// q; B column c, k-block q; accumulator register r holds column c of row
+// 4q + r (float32 results), or of row q + 4r (float64 results).
+// LDS strides: A rows 2 (mod 32) words apart, so the 16 rows of a fragment
+// read hit distinct banks; B rows WB + 16 apart, so the two k-rows that half
+// a wave reads hit disjoint banks.
+// ---------------------------------------------------------------------------
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mf_b8 __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct MfAcc;
+template <>
+struct MfAcc<double> {
+  using type = mf_d4;
+};
+template <>
+struct MfAcc<float> {
+  using type = mf_f4;
+};
+
+// row of accumulator register r in lane group q (layouts above)
+template <typename T>
+__device__ constexpr int mf_row(int q, int r) {
+  return sizeof(T) == 8 ? q + 4 * r : 4 * q + r;
+}
+
+template <bool BF>
+struct MfK {
+  static constexpr int KS = BF ? 32 : 4;  // k per MFMA
+};
+
+template <int NJ, bool BF>
+struct Fd2mShape {
+  static constexpr int WB = 64 * NJ;  // columns of a block (tiles of all four waves)
+  static constexpr int LDB = WB + 16;  // B row stride in LDS
+  static constexpr int LDZ = WB + 2;   // Z row stride (A operand of the second product)
+  // B rows per streamed chunk (a multiple of the MFMA k; short chunks keep
+  // the registers of the next chunk few for wide blocks)
+  static constexpr int KC = (BF || NJ <= 2) ? 32 : 16;
+};
+
+// acc[j] += A[0:16, ka:ka+kn] B[0:kn, tile j] with A in LDS (row stride lda)
+// and B rows in LDS (stride LDB); tiles at or beyond ncols are skipped
+// (their accumulators stay as they are)
+template <typename T, bool BF, int NJ>
+__device__ inline void mfma_rows(const T *sA, int lda, int ka, const T *sB, int kn, int ncols,
+                                 typename MfAcc<T>::type acc[NJ]) {
+  constexpr int KS = MfK<BF>::KS, LDB = Fd2mShape<NJ, BF>::LDB;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, q = lane >> 4;
+#pragma unroll 2
+  for (int k = 0; k < kn; k += KS) {
+    if constexpr (!BF) {
+      const T a = sA[c * lda + ka + k + q];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int col = 16 * (w + 4 * j);
+        if (col < ncols) {
+          const T b = sB[(k + q) * LDB + col + c];
+          if constexpr (sizeof(T) == 8)
+            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+          else
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    } else {
+      mf_b8 a;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[t] = (__bf16)sA[c * lda + ka + k + 8 * q + t];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int col = 16 * (w + 4 * j);
+        if (col < ncols) {
+          mf_b8 b;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) b[t] = (__bf16)sB[(k + 8 * q + t) * LDB + col + c];
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// acc += A[16 x K] B[K x N]: B streamed from global memory through LDS, the
+// whole of it in one round of loads (FULL, K padded to the MFMA k <= WB) or in
+// chunks of KC rows with the next chunk held in registers.  Rows of B past K
+// and columns past N are stored as zero; A must be zero in columns K..Kp-1.
+template <typename T, bool BF, int NJ, bool FULL>
+__device__ inline void rowblock_mfma(const T *sA, int lda, const T *__restrict__ B, long long b_r,
+                                     int K, int N, T *sM, typename MfAcc<T>::type acc[NJ]) {
+  constexpr int WB = Fd2mShape<NJ, BF>::WB, LDB = Fd2mShape<NJ, BF>::LDB, KS = MfK<BF>::KS;
+  const int tid = threadIdx.x;
+  const int Kp = (K + KS - 1) / KS * KS;
+  if constexpr (FULL) {
+    constexpr int MAXL = WB * WB / 256;
+    T pre[MAXL];
+    __syncthreads();  // sM and A complete / free
+#pragma unroll
+    for (int x = 0; x < MAXL; ++x) {
+      const int e = tid + 256 * x;
+      const int kk = e / WB, col = e % WB;
+      pre[x] = (kk < K && col < N) ? B[(long long)kk * b_r + col] : (T)0;
+    }
+#pragma unroll
+    for (int x = 0; x < MAXL; ++x) {
+      const int e = tid + 256 * x;
+      const int kk = e / WB, col = e % WB;
+      if (kk < Kp) sM[kk * LDB + col] = pre[x];
+    }
+    __syncthreads();
+    mfma_rows<T, BF, NJ>(sA, lda, 0, sM, Kp, N, acc);
+  } else {
+    constexpr int KC = Fd2mShape<NJ, BF>::KC;
+    constexpr int LPT = KC * WB / 256;
+    T pre[LPT];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int x = 0; x < LPT; ++x) {
+        const int e = tid + 256 * x;
+        const int kk = e / WB, col = e % WB;
+        pre[x] = (k0 + kk < K && col < N) ? B[(long long)(k0 + kk) * b_r + col] : (T)0;
+      }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < Kp; k0 += KC) {
+      __syncthreads();
+#pragma unroll
+      for (int x = 0; x < LPT; ++x) {
+        const int e = tid + 256 * x;
+        sM[(e / WB) * LDB + e % WB] = pre[x];
+      }
+      __syncthreads();
+      if (k0 + KC < Kp) gload(k0 + KC);
+      mfma_rows<T, BF, NJ>(sA, lda, k0, sM, min(KC, Kp - k0), N, acc);
+    }
+  }
+}
+
+template <typename T, bool BF, int NJ, bool FULL>
+__global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int lda) {
+  using A4 = typename MfAcc<T>::type;
+  constexpr int LDZ = Fd2mShape<NJ, BF>::LDZ;
+  extern __shared__ char smraw[];
+  T *sm = (T *)smraw;
+  const Fd2Item<T> it = items[blockIdx.z];
+  const int i0 = blockIdx.y * 16;
+  if (i0 >= it.rows) return;
+  const T *M1 = it.M1 + (long long)blockIdx.x * it.m1_z;
+  T *O = it.O + (long long)blockIdx.x * it.o_z;
+  T *sL = sm;             // 16 x lda, zero beyond K1
+  T *sZ = sL + 16 * lda;  // 16 x LDZ
+  T *sM = sZ + 16 * LDZ;  // rows of B
+  const int tid = threadIdx.x;
+  const int nrow = min(16, it.rows - i0);
+  for (int e0 = 0; e0 < 16 * lda; e0 += 256 * 8) {
+    T v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + tid + 256 * j;
+      const int i = e / lda, a = e % lda;
+      v[j] = (e < 16 * lda && i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (e0 + tid + 256 * j < 16 * lda) sL[e0 + tid + 256 * j] = v[j];
+  }
+  A4 acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = A4{0, 0, 0, 0};
+  rowblock_mfma<T, BF, NJ, FULL>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
+  const int lane = tid & 63, w = tid >> 6, c = lane & 15, q = lane >> 4;
+  // Z (zero in the columns past N) becomes the A operand of the second product
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sZ[mf_row<T>(q, r) * LDZ + 16 * (w + 4 * j) + c] = acc[j][r];
+    acc[j] = A4{0, 0, 0, 0};
+  }
+  rowblock_mfma<T, BF, NJ, FULL>(sZ, LDZ, it.M2, it.m2_r, it.N, it.N, sM, acc);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int col = 16 * (w + 4 * j) + c;
+    if (col >= it.N) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = mf_row<T>(q, r);
+      if (i >= nrow) continue;
+      const T v = acc[j][r];
+      T *o = O + (long long)(i0 + i) * it.o_r + col;
+      if (it.lam_r)
+        *o = v / (it.sigma + it.lam_r[i0 + i] + it.lam_c[col]);
+      else
+        *o += it.scale * v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Dense solves with stored symmetric inverses: a block of 1024 threads owns 64
 // rows; wavefront w sums the columns j = w (mod 16) with lane = row, so the
 // 64 lanes read 64 consecutive entries of column j (= row j, by symmetry);
@@ -1734,21 +1941,62 @@ static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
   launch_fd2_as<T, NJ, false>(c, L, stage, nrhs, lds);
 }
 
+template <typename T, bool BF, int NJ, bool FULL>
+static void launch_fd2m_as(Context &c, LevelData &L, int stage, int nrhs, int lda, size_t lds) {
+  static const hipError_t lds_set =
+      hipFuncSetAttribute((const void *)fd2m_kernel<T, BF, NJ, FULL>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  HIPCHK(lds_set);
+  dim3 grid(nrhs, (L.fd_rows + 15) / 16, L.n_fd);
+  fd2m_kernel<T, BF, NJ, FULL><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], lda);
+}
+
+template <typename T, bool BF, int NJ>
+static void launch_fd2m(Context &c, LevelData &L, int stage, int nrhs) {
+  constexpr int WB = Fd2mShape<NJ, BF>::WB, LDB = Fd2mShape<NJ, BF>::LDB, LDZ = Fd2mShape<NJ, BF>::LDZ;
+  constexpr int KC = Fd2mShape<NJ, BF>::KC, KS = MfK<BF>::KS;
+  const int lda = (L.fd_K1 + 31) / 32 * 32 + 2;
+  const size_t base = (size_t)(16 * lda + 16 * LDZ) * sizeof(T);
+  const int kmax = (std::max(L.fd_K1, L.fd_N) + KS - 1) / KS * KS;
+  const size_t lds_full = base + (size_t)kmax * LDB * sizeof(T);
+  if (NJ <= 2 && kmax <= WB && lds_full <= 150 * 1024) {
+    launch_fd2m_as<T, BF, NJ, NJ <= 2>(c, L, stage, nrhs, lda, lds_full);
+    return;
+  }
+  const size_t lds = base + (size_t)KC * LDB * sizeof(T);
+  if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
+  launch_fd2m_as<T, BF, NJ, false>(c, L, stage, nrhs, lda, lds);
+}
+
+template <typename T, bool BF>
+static void scms_mfma(Context &c, LevelData &L, int nrhs) {
+  const int nj = (L.fd_N + 63) / 64;
+  for (int st = 0; st < 2; ++st) {
+    switch (nj) {
+      case 1: launch_fd2m<T, BF, 1>(c, L, st, nrhs); break;
+      case 2: launch_fd2m<T, BF, 2>(c, L, st, nrhs); break;
+      case 3: launch_fd2m<T, BF, 3>(c, L, st, nrhs); break;
+      case 4: launch_fd2m<T, BF, 4>(c, L, st, nrhs); break;
+      case 5: launch_fd2m<T, BF, 5>(c, L, st, nrhs); break;
+      default: fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
+    }
+  }
+}
+
+// patch interiors of the subspace corrected mass smoother: two launches of
+// chained products on the matrix cores (bfloat16 operands when the options
+// ask for them, float32 cycles only)
 template <typename T>
 void k_scms_interior(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "scms", L.l);
   if (L.n_fd == 0) return;
-  const int nj = (L.fd_N + 63) / 64;
-  for (int st = 0; st < 2; ++st) {
-    switch (nj) {
-      case 1: launch_fd2<T, 1>(c, L, st, nrhs); break;
-      case 2: launch_fd2<T, 2>(c, L, st, nrhs); break;
-      case 3: launch_fd2<T, 3>(c, L, st, nrhs); break;
-      case 4: launch_fd2<T, 4>(c, L, st, nrhs); break;
-      case 5: launch_fd2<T, 5>(c, L, st, nrhs); break;
-      default: fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
+  if constexpr (sizeof(T) == 4) {
+    if (c.bf16_scms()) {
+      scms_mfma<float, true>(c, L, nrhs);
+      return;
     }
   }
+  scms_mfma<T, false>(c, L, nrhs);
 }
 template void k_scms_interior<double>(Context &, LevelData &, int);
 template void k_scms_interior<float>(Context &, LevelData &, int);

@@ -1073,7 +1073,8 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
     fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel ordering is defined for the SIPG space only");
   if (use_gs && c.opt.gs_tile != 2 * (degree + 1))
     fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel tiles of width 2(p+1) only");
-  if (c.opt.precision != IGAMG_FP64 && c.opt.precision != IGAMG_FP32)
+  if (c.opt.precision != IGAMG_FP64 && c.opt.precision != IGAMG_FP32 &&
+      c.opt.precision != IGAMG_BF16_SCMS)
     fail(IGAMG_EINVAL, "unknown precision");
   if (c.opt.outer < IGAMG_OUTER_PCG || c.opt.outer > IGAMG_OUTER_FCG)
     fail(IGAMG_EINVAL, "unknown outer iteration");
@@ -1434,7 +1435,7 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
     fail(IGAMG_EINVAL, "invalid problem");
   const int d = P->dim, p = degree;
   const int nb = o->max_rhs > 0 ? o->max_rhs : 1;
-  const double wb = o->precision == IGAMG_FP32 ? 4.0 : 8.0;
+  const double wb = o->precision != IGAMG_FP64 ? 4.0 : 8.0;
   long long fine = 0;
   for (int k = 0; k < P->n_patches; ++k) {
     long long n = 1;

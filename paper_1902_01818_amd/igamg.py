@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOCONV = 0, -1, -2, -3, -4, 1
 SIPG, CONFORMING = 0, 1
 SMOOTHERS = {"hybrid": 0, "scms": 1, "gs": 2}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 OUTERS = {"pcg": 0, "mg": 1, "fcg": 2}
 APPLIES = {"auto": 0, "sumfact": 1, "rows": 2}
 

@@ -106,6 +106,25 @@ def test_fp32_cycle_fp64_outer_solve(c2_small, outer):
     sv.close()
 
 
+def test_bf16_scms_solve(c2_small):
+    """bfloat16 operands in the patch-interior contractions (float32
+    accumulation) inside float64 flexible CG: the float64 stopping test still
+    decides, so the true residual meets the tolerance; the coarser smoother
+    may cost iterations, bounded here by twice the float64 count."""
+    cfg, ob = c2_small
+    sv = gpu_solver(cfg, precision="bf16", outer="fcg", max_rhs=2)
+    F = _rhs_batch(ob.N, [2002, 2005])
+    U, info = sv.solve(_gpu(F), tol=1e-8, maxit=200)
+    U = U.cpu().numpy().reshape(2, ob.N)
+    for j in range(2):
+        _, its, _, _ = ob.pcg(F[j])
+        true_res = np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j])
+        assert info[j]["converged"]
+        assert true_res <= 1.05e-8, true_res
+        assert info[j]["iterations"] <= 2 * its, (info[j]["iterations"], its)
+    sv.close()
+
+
 def test_fp32_fullsize_solve():
     cfg, ob = cached_oracle("c2", 1)
     sv = gpu_solver(cfg, precision="fp32", outer="fcg")
