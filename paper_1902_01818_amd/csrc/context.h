@@ -94,7 +94,9 @@ struct LevelArrays {
   T *P_val = nullptr, *R_val = nullptr;        // banded 1D embeddings (from the coarser level)
   T *weight = nullptr;                         // 1 on the representative copy of a free unknown
   T *wscratch = nullptr;                       // fast-diagonalization intermediate
+  T *wscratch2 = nullptr;                      // second intermediate of the staged form
   Fd2Item<T> *fd[2] = {nullptr, nullptr};      // patch interiors: forward, backward
+  FdGemm<T> *fg[4] = {nullptr, nullptr, nullptr, nullptr};  // the same as four product stages
 };
 
 struct LevelData {
@@ -140,6 +142,8 @@ struct LevelData {
   // SCMS interiors
   int n_fd = 0;
   int fd_rows = 0, fd_K1 = 0, fd_N = 0;
+  int fg_tiles = 0;       // 64 x 64 output tiles of the largest stage item
+  long long fd_work = 0;  // sum over patches of my * mx * ceil(my / 16) (fused-form re-reads)
   long long wscratch_n = 0;
   // interface pieces
   PieceDev *d_pieces = nullptr;

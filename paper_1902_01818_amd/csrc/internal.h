@@ -103,6 +103,23 @@ struct Fd2Item {
   T scale;
 };
 
+// One product stage of the fast diagonalization on a batch: for every
+// right-hand side z, C_z = A_z B_z (mode 0), C_z = A_z B_z ./ (sigma + lam_r[i]
+// + lam_c[j]) (mode 1) or C_z += scale A_z B_z (mode 2).  Row-major operands;
+// *_z is the element stride between right-hand sides (0 = shared operand).
+template <typename T>
+struct FdGemm {
+  const T *A, *B;
+  T *C;
+  long long a_r, b_r, c_r;
+  long long a_z, b_z, c_z;
+  int M, N, K;
+  int tn;  // 64-column tiles of C
+  const T *lam_r, *lam_c;
+  T sigma, scale;
+  int mode;
+};
+
 // Interface piece of the additive smoother (eq. Ldef): dense inverse of P^T A P.
 struct PieceDev {
   long long inv_off;  // offset of the n x n inverse in the value array

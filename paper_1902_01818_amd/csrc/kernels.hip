@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <string>
 
 #include "geom.h"
@@ -1221,6 +1222,121 @@ __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int 
 }
 
 // ---------------------------------------------------------------------------
+// One product stage of the fast diagonalization over a batch (FdGemm): a
+// block computes a 64 x 64 tile of C_z; its four waves own 32 x 32 quarters
+// (2 x 2 MFMA tiles).  K is streamed in chunks of 32 through LDS, both
+// operands stored k-contiguous (B transposed on the way in), the next chunk
+// held in registers while the current one is multiplied.  Large batches
+// read every per-right-hand-side operand once per tile row/column instead of
+// once per 16-row block of the fused form.
+// grid.x = right-hand side, grid.y = tile, grid.z = item (patch).
+// ---------------------------------------------------------------------------
+#ifndef FDG_BF_KC
+#define FDG_BF_KC 32
+#endif
+
+template <typename T, bool BF>
+__global__ __launch_bounds__(256) void fdg_kernel(const FdGemm<T> *items) {
+  using A4 = typename MfAcc<T>::type;
+  // LDS operand type: bfloat16 fragments are rounded once, when staged
+  using ST = typename std::conditional<BF, __bf16, T>::type;
+  constexpr int KC = BF ? FDG_BF_KC : 32, KS = MfK<BF>::KS;
+  // row strides: 16-byte rows for the 8-wide bf16 fragments, 2 (mod 32)
+  // words for the single-value fragments (16 rows on distinct banks)
+  constexpr int LDK = BF ? KC + 8 : KC + 2;
+  constexpr int NL = 64 * KC / 256;  // loads per thread, operand and chunk
+  __shared__ ST sA[64 * LDK], sB[64 * LDK];
+  const FdGemm<T> g = items[blockIdx.z];
+  const int tm = blockIdx.y / g.tn, tc = blockIdx.y - tm * g.tn;
+  const int m0 = tm * 64, n0 = tc * 64;
+  if (m0 >= g.M) return;
+  const long long z = blockIdx.x;
+  const T *A = g.A + z * g.a_z, *B = g.B + z * g.b_z;
+  T *C = g.C + z * g.c_z;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, q = lane >> 4;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  T pa[NL], pb[NL];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int x = 0; x < NL; ++x) {
+      const int e = tid + 256 * x;
+      const int ar = e / KC, ak = e % KC;
+      pa[x] = (m0 + ar < g.M && k0 + ak < g.K) ? A[(long long)(m0 + ar) * g.a_r + k0 + ak] : (T)0;
+      const int bk = e / 64, bc = e % 64;
+      pb[x] = (k0 + bk < g.K && n0 + bc < g.N) ? B[(long long)(k0 + bk) * g.b_r + n0 + bc] : (T)0;
+    }
+  };
+  A4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = A4{0, 0, 0, 0};
+  gload(0);
+  for (int k0 = 0; k0 < g.K; k0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < NL; ++x) {
+      const int e = tid + 256 * x;
+      sA[(e / KC) * LDK + e % KC] = (ST)pa[x];
+      sB[(e % 64) * LDK + e / 64] = (ST)pb[x];
+    }
+    __syncthreads();
+    if (k0 + KC < g.K) gload(k0 + KC);
+#pragma unroll
+    for (int k = 0; k < KC; k += KS) {
+      if constexpr (!BF) {
+        T a[2], b[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) a[t] = sA[(wm + 16 * t + c) * LDK + k + q];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) b[u] = sB[(wn + 16 * u + c) * LDK + k + q];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if constexpr (sizeof(T) == 8)
+              acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+            else
+              acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[u], acc[t][u], 0, 0, 0);
+          }
+      } else {
+        mf_b8 a[2], b[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) a[t] = *(const mf_b8 *)&sA[(wm + 16 * t + c) * LDK + k + 8 * q];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) b[u] = *(const mf_b8 *)&sB[(wn + 16 * u + c) * LDK + k + 8 * q];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[u], acc[t][u], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = n0 + wn + 16 * u + c;
+      if (j >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm + 16 * t + mf_row<T>(q, r);
+        if (i >= g.M) continue;
+        const T v = acc[t][u][r];
+        T *o = C + (long long)i * g.c_r + j;
+        if (g.mode == 0)
+          *o = v;
+        else if (g.mode == 1)
+          *o = v / (g.sigma + g.lam_r[i] + g.lam_c[j]);
+        else
+          *o += g.scale * v;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Dense solves with stored symmetric inverses: a block of 1024 threads owns 64
 // rows; wavefront w sums the columns j = w (mod 16) with lane = row, so the
 // 64 lanes read 64 consecutive entries of column j (= row j, by symmetry);
@@ -1968,6 +2084,17 @@ static void launch_fd2m(Context &c, LevelData &L, int stage, int nrhs) {
   launch_fd2m_as<T, BF, NJ, false>(c, L, stage, nrhs, lda, lds);
 }
 
+#ifndef FD_STAGED_MIN
+#define FD_STAGED_MIN 5.0e6
+#endif
+
+template <typename T, bool BF>
+static void scms_staged(Context &c, LevelData &L, int nrhs) {
+  dim3 grid(nrhs, L.fg_tiles, L.n_fd);
+  for (int st = 0; st < 4; ++st)
+    fdg_kernel<T, BF><<<grid, 256, 0, c.stream>>>(L.arr<T>().fg[st]);
+}
+
 template <typename T, bool BF>
 static void scms_mfma(Context &c, LevelData &L, int nrhs) {
   const int nj = (L.fd_N + 63) / 64;
@@ -1990,13 +2117,22 @@ template <typename T>
 void k_scms_interior(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "scms", L.l);
   if (L.n_fd == 0) return;
+  // the fused form re-reads each right-hand side's operand once per 16-row
+  // block; past this much re-read work the four-stage form is faster
+  const bool staged = (double)L.fd_work * nrhs >= FD_STAGED_MIN;
   if constexpr (sizeof(T) == 4) {
     if (c.bf16_scms()) {
-      scms_mfma<float, true>(c, L, nrhs);
+      if (staged)
+        scms_staged<float, true>(c, L, nrhs);
+      else
+        scms_mfma<float, true>(c, L, nrhs);
       return;
     }
   }
-  scms_mfma<T, false>(c, L, nrhs);
+  if (staged)
+    scms_staged<T, false>(c, L, nrhs);
+  else
+    scms_mfma<T, false>(c, L, nrhs);
 }
 template void k_scms_interior<double>(Context &, LevelData &, int);
 template void k_scms_interior<float>(Context &, LevelData &, int);

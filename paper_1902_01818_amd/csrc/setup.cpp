@@ -810,7 +810,11 @@ static void build_scms(Context &c, LevelData &L) {
   for (int k = 0; k < L.K; ++k) scr += (size_t)(L.pd[k].n[0] - 2) * (L.pd[k].n[1] - 2);
   L.wscratch_n = (long long)scr;
   A.wscratch = c.arena.alloc<T>(scr * c.nb);
+  A.wscratch2 = c.arena.alloc<T>(scr * c.nb);
   std::vector<Fd2Item<T>> fa, fb;
+  std::vector<FdGemm<T>> g1, g2, g3, g4;
+  L.fg_tiles = 0;
+  L.fd_work = 0;
   size_t so = 0;
   L.fd_rows = L.fd_K1 = L.fd_N = 0;
   const long long nt = L.Ntorn, ns = (long long)scr;
@@ -832,6 +836,19 @@ static void build_scms(Context &c, LevelData &L) {
     // backward: U += scale (Qy W) Qx^T
     fb.push_back(Fd2Item<T>{qy.Q, Wk, qx.QT, uin, my, mx, mx, nx, ns, nt, my, my, mx, nullptr,
                             nullptr, (T)0, (T)pt.scms_scale});
+    // the same as four stages: Z = Qy^T R; W = Z Qx ./ D; Z = Qy W; U += scale Z Qx^T
+    T *Zk = Wk, *W2 = A.wscratch2 + (so - (size_t)mx * my);
+    const int tn = (mx + 63) / 64;
+    g1.push_back(FdGemm<T>{qy.QT, rin, Zk, my, nx, mx, 0, nt, ns, my, mx, my, tn, nullptr, nullptr,
+                           (T)0, (T)0, 0});
+    g2.push_back(FdGemm<T>{Zk, qx.Q, W2, mx, mx, mx, ns, 0, ns, my, mx, mx, tn, qy.lam, qx.lam,
+                           (T)pt.sigma, (T)0, 1});
+    g3.push_back(FdGemm<T>{qy.Q, W2, Zk, my, mx, mx, 0, ns, ns, my, mx, my, tn, nullptr, nullptr,
+                           (T)0, (T)0, 0});
+    g4.push_back(FdGemm<T>{Zk, qx.QT, uin, mx, mx, nx, ns, 0, nt, my, mx, mx, tn, nullptr, nullptr,
+                           (T)0, (T)pt.scms_scale, 2});
+    L.fg_tiles = std::max(L.fg_tiles, tn * ((my + 63) / 64));
+    L.fd_work += (long long)my * mx * ((my + 15) / 16);
     L.fd_rows = std::max(L.fd_rows, my);
     L.fd_K1 = std::max(L.fd_K1, my);
     L.fd_N = std::max(L.fd_N, mx);
@@ -840,6 +857,10 @@ static void build_scms(Context &c, LevelData &L) {
   L.n_fd = L.K;
   A.fd[0] = c.arena.upload(fa, c.stream);
   A.fd[1] = c.arena.upload(fb, c.stream);
+  A.fg[0] = c.arena.upload(g1, c.stream);
+  A.fg[1] = c.arena.upload(g2, c.stream);
+  A.fg[2] = c.arena.upload(g3, c.stream);
+  A.fg[3] = c.arena.upload(g4, c.stream);
 }
 
 // keep64: the float64 couplings are uploaded too (float32 cycle whose finest
@@ -1449,9 +1470,9 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
   const int SP = (S + 15) / 16 * 16;
   const bool gs = o->smoother != IGAMG_SMOOTHER_SCMS;
   const bool scms = o->smoother != IGAMG_SMOOTHER_GS;
-  // per unknown and level: f, u, r per right-hand side, SCMS intermediate,
+  // per unknown and level: f, u, r per right-hand side, two SCMS intermediates,
   // stencil row and 1/a_ii, weight, masks and index maps
-  double per = wb * (3.0 * nb + (scms ? nb : 0) + (gs ? SP + 1 : 0) + 1) + 16.0;
+  double per = wb * (3.0 * nb + (scms ? 2.0 * nb : 0) + (gs ? SP + 1 : 0) + 1) + 16.0;
   double bytes = all_levels * per;
   // dense inverses: interface pieces (both sides' boundary layers of every
   // interface, summed over levels) and the coarse level

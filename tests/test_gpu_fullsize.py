@@ -46,3 +46,19 @@ def test_full_solve(full_pair):
     assert info[0]["converged"] and abs(info[0]["iterations"] - its) <= 1
     assert rel_err(ug, uo) < 1e-9
     assert np.linalg.norm(f - ob.A[-1] @ ug) / np.linalg.norm(f) <= 1.01e-8
+
+
+def test_full_batch_cycle_staged_smoother(full_pair):
+    """64 right-hand sides at the full size: the patch-interior solves of the
+    finest level take the four-stage batched form (64 x (66^2 x 5 + 98^2 x
+    7) x 8 fused-form re-reads exceed its threshold); two columns of the
+    batched cycle match the oracle's cycle at the float64 cycle bar."""
+    cfg, ob, sv = full_pair
+    nb = 64
+    sb = gpu_solver(cfg, coarse_min=2 if sv.n_levels == 6 else 8, max_rhs=nb)
+    F = np.stack([workloads.normal_rhs(ob.N, 3000 + j) for j in range(nb)])
+    Z = sb.vcycle(torch.from_numpy(F).cuda(), torch.zeros(nb * ob.N, dtype=torch.float64).cuda())
+    Z = Z.cpu().numpy().reshape(nb, ob.N)
+    for j in (0, nb - 1):
+        assert rel_err(Z[j], ob.vcycle(F[j])) < 1e-10, j
+    sb.close()
