@@ -28,11 +28,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}   # GB/s, TFLOP/s (MI355X)
+# MI355X peaks: HBM GB/s; vector and MFMA TFLOP/s (dense MFMA: f64 78.6,
+# f32 157.3, bf16 2500)
+PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}
+MFMA_PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 
 
 KERNEL_OF_FAMILY = {"gauss_seidel": "gs2d_wave_kernel", "vol_apply": "vol2d_kernel",
-                    "scms": "fd2_kernel", "iface_apply": "iface_kernel"}
+                    "scms": "fd2m_kernel", "iface_apply": "iface_kernel",
+                    "stencil_apply": "sp2d_kernel"}
 
 
 def source_hash(family="gauss_seidel"):
@@ -76,9 +80,11 @@ def cpu_baseline(cfg, f, its_gpu, budget_s=15.0):
 
 def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2):
     """64 right-hand sides of the p = 6, 256-element workload solved together
-    (float32 cycle inside float64 flexible CG, or float64 PCG)."""
+    (float32 cycle, optionally with bfloat16 SCMS contractions, inside float64
+    flexible CG; or float64 PCG), with the matrix-core utilisation of the
+    finest level's SCMS application measured in one more, event-timed solve."""
     cfg = workloads.config("c4")
-    outer = "fcg" if precision == "fp32" else "pcg"
+    outer = "pcg" if precision == "fp64" else "fcg"
     t0 = time.perf_counter()
     sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
                       conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
@@ -101,6 +107,21 @@ def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2):
                iterations_max=max(its), iterations_min=min(its),
                max_true_rel_residual=max(i["true_rel_residual"] for i in info),
                all_converged=all(i["converged"] for i in info))
+    top = sv.n_levels - 1
+    key = "scms/%d" % top
+    sv.set_timing(key)
+    sv.solve(F, U, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    st = sv.kernel_stats(reset=True)
+    sv.set_timing(None)
+    if st.get(key, {}).get("launches"):
+        avg = st[key]["ms"] / 1e3 / st[key]["launches"]
+        _, fl = sv.kernel_model("scms", top, nrhs)
+        ach = fl / avg / 1e12
+        peak = MFMA_PEAK["bf16" if precision == "bf16" else precision]
+        out["scms_mfma"] = dict(kernel=key, bound="mfma", achieved=ach, peak=peak,
+                                unit="TFLOP/s", frac=ach / peak, avg_application_us=avg * 1e6,
+                                model_flops_per_application=fl)
     sv.close()
     return out
 
@@ -115,6 +136,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests of the serving sample (0 = skip)")
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-column p = 6 workload")
+    ap.add_argument("--c4-only", action="store_true",
+                    help="diagnostic: run only the 64-column p = 6 legs (float32 cycle, bf16 "
+                         "SCMS) and print their results (not the benchmark line)")
     ap.add_argument("--coarse-min", type=int, default=8,
                     help="halving stops before an element count falls below this: 8 puts the "
                          "direct solve on the 8/12-element level (2,940 unknowns, 4 levels); "
@@ -131,6 +155,13 @@ def main():
     import torch
     import workloads
     from paper_1902_01818_amd import igamg
+
+    if args.c4_only:
+        out = {"c4": c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)}
+        print("bench: 64-column p = 6 batch timed (float32 cycle)", file=sys.stderr, flush=True)
+        out["c4_bf16_scms"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="bf16", steps=1)
+        print(json.dumps(out))
+        return
 
     cfg = workloads.config("c2")
     sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
@@ -157,7 +188,7 @@ def main():
         for key, v in st.items():
             fam = key.split("/")[0]
             fams[fam] = fams.get(fam, 0.0) + v["ms"]
-        modelled = [k for k in ("gauss_seidel", "vol_apply", "scms", "iface_apply") if k in fams]
+        modelled = [k for k in KERNEL_OF_FAMILY if k in fams]
         family = max(modelled, key=lambda k: fams[k])
     # timed region: only the dominant family on the finest level is event-timed
     sv.set_timing("%s/%d" % (family, top))
@@ -176,10 +207,13 @@ def main():
     key = "%s/%d" % (family, top)
     launches = st[key]["launches"]
     avg_s = st[key]["ms"] / 1e3 / max(launches, 1)
-    mbytes, mflops = sv.kernel_model(family, top)
-    if family in ("vol_apply", "scms"):
+    mbytes, mflops = sv.kernel_model(family, top, 1)
+    if family == "vol_apply":
         achieved = mflops / avg_s / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK["fp64"], unit="TFLOP/s")
+    elif family == "scms":
+        achieved = mflops / avg_s / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=MFMA_PEAK["fp64"], unit="TFLOP/s")
     else:
         achieved = mbytes / avg_s / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s")
@@ -259,7 +293,9 @@ def main():
     # batched right-hand sides (p = 6, 256 elements per patch, 64 columns)
     if not args.no_c4:
         line["c4"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)
-        print("bench: 64-column p = 6 batch timed", file=sys.stderr, flush=True)
+        print("bench: 64-column p = 6 batch timed (float32 cycle)", file=sys.stderr, flush=True)
+        line["c4_bf16_scms"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="bf16", steps=1)
+        print("bench: 64-column p = 6 batch timed (bf16 SCMS)", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

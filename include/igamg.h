@@ -201,10 +201,15 @@ int igamg_kernel_stats(igamg_ctx *ctx, int cap, char (*names)[32], double *ms,
  * stream around every matching launch. */
 int igamg_set_timing(igamg_ctx *ctx, const char *filter);
 
-/* Algorithmic bytes moved and flops of one launch of a kernel family
- * ("vol_apply", "gauss_seidel", "scms_gemm", "iface_apply") on a level
- * (level < 0: finest): the roofline model of the library's kernels. */
-int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, double *bytes,
+/* Algorithmic bytes moved and flops of one timed launch of a kernel family
+ * on a level (level < 0: finest) for a batch of nrhs right-hand sides: the
+ * roofline model of the library's kernels.  Families: "stencil_apply" and
+ * "vol_apply" + "iface_apply" (operator, eq. model:discr2), "gauss_seidel"
+ * (one colour class), "scms" (one application to all patch interiors, eq.
+ * Ldef).  Operator data shared by the batch counts once; vectors once per
+ * right-hand side.  Errors: IGAMG_EINVAL for an unknown family, a level out
+ * of range or nrhs < 1. */
+int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, int nrhs, double *bytes,
                        double *flops);
 
 int igamg_destroy(igamg_ctx *ctx);

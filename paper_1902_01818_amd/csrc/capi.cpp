@@ -223,14 +223,15 @@ int igamg_kernel_stats(igamg_ctx *ctx, int cap, char (*names)[32], double *ms, i
   });
 }
 
-int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, double *bytes,
+int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, int nrhs, double *bytes,
                        double *flops) {
   return guarded([&] {
     if (!ctx || !family || !bytes || !flops) igamg::fail(IGAMG_EINVAL, "null argument");
     igamg::Context &c = ctx->c;
     if (level < 0) level = (int)c.lv.size() - 1;
     if (level >= (int)c.lv.size()) igamg::fail(IGAMG_EINVAL, "level out of range");
-    igamg::kernel_model(c, family, level, bytes, flops);
+    if (nrhs < 1) igamg::fail(IGAMG_EINVAL, "nrhs must be positive");
+    igamg::kernel_model(c, family, level, nrhs, bytes, flops);
     return IGAMG_OK;
   });
 }

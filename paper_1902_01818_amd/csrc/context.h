@@ -233,9 +233,10 @@ void problem_size(const igamg_patches *P, int degree, const igamg_options *o, lo
 void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
                    const igamg_options *o, hipStream_t s, const Lent *lent = nullptr);
 size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_options *o);
-// algorithmic bytes / flops of one launch of a kernel family on a level
-void kernel_model(const Context &c, const std::string &family, int level, double *bytes,
-                  double *flops);
+// algorithmic bytes / flops of one launch of a kernel family on a level for a
+// batch of nrhs right-hand sides
+void kernel_model(const Context &c, const std::string &family, int level, int nrhs,
+                  double *bytes, double *flops);
 
 // cycle / outer iteration (cycle.cpp); vectors in torn layout, nrhs <= c.nb
 void apply64(Context &c, const double *u, const double *f, const double *fw, double *r,

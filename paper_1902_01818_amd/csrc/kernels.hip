@@ -856,168 +856,14 @@ __global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntil
 }
 
 // ---------------------------------------------------------------------------
-// Row-block products of the fast diagonalization (see Fd2Item).  A block of
-// 256 threads owns 16 rows: thread (rg, cg) accumulates rows 4rg..4rg+3 and
-// columns cg + 64j; B is streamed through LDS in chunks of KC rows, the next
-// chunk held in registers while the current one is used.  Long chunks keep
-// the number of dependent global-load round trips per block small.
-// grid.x = right-hand side, grid.y = row block, grid.z = item (patch).
-// ---------------------------------------------------------------------------
-template <int NJ>
-struct Fd2Shape {
-  static constexpr int WB = 64 * NJ;            // LDS row length of a chunk
-  static constexpr int KC = NJ <= 3 ? 32 : 16;  // rows per chunk
-};
-
-template <typename T, int NJ>
-__device__ inline void rowblock_product(const T *A, int lda, const T *__restrict__ B, long long b_r,
-                                        int K, int N, T *sM, T acc[4][NJ]) {
-  constexpr int WB = Fd2Shape<NJ>::WB, KC = Fd2Shape<NJ>::KC;
-  constexpr int LPT = KC * WB / 256;  // loads per thread and chunk
-  const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
-  T pre[LPT];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int x = 0; x < LPT; ++x) {
-      const int e = tid + 256 * x;
-      const int kk = e / WB, col = e % WB;
-      pre[x] = (k0 + kk < K && col < N) ? B[(long long)(k0 + kk) * b_r + col] : (T)0;
-    }
-  };
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    __syncthreads();
-#pragma unroll
-    for (int x = 0; x < LPT; ++x) sM[tid + 256 * x] = pre[x];
-    __syncthreads();
-    if (k0 + KC < K) gload(k0 + KC);
-    // groups of 8 rows, fully unrolled so that their LDS reads go out
-    // together; rows past K are zero in sM and in A's padding
-    for (int k8 = 0; k8 < KC && k0 + k8 < K; k8 += 8) {
-#pragma unroll
-      for (int kk = k8; kk < k8 + 8; ++kk) {
-        T a[4], b[NJ];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + k0 + kk];
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
-      }
-    }
-  }
-}
-
-// The whole of B (K <= 64 NJ rows) staged in LDS with one round of
-// independent loads (no chunk loop): for NJ <= 2, where it fits.
-template <typename T, int NJ>
-__device__ inline void rowblock_product_full(const T *A, int lda, const T *__restrict__ B,
-                                             long long b_r, int K, int N, T *sM, T acc[4][NJ]) {
-  constexpr int WB = Fd2Shape<NJ>::WB;
-  constexpr int MAXL = WB * WB / 256;  // loads per thread for K = WB
-  const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
-  const int Kp = (K + 7) / 8 * 8;
-  T pre[MAXL];
-  __syncthreads();  // sM free (a previous product may still read it)
-#pragma unroll
-  for (int x = 0; x < MAXL; ++x) {
-    const int e = tid + 256 * x;
-    const int kk = e / WB, col = e % WB;
-    pre[x] = (kk < K && col < N) ? B[(long long)kk * b_r + col] : (T)0;
-  }
-#pragma unroll
-  for (int x = 0; x < MAXL; ++x)
-    if (tid + 256 * x < Kp * WB) sM[tid + 256 * x] = pre[x];
-  __syncthreads();
-  for (int k8 = 0; k8 < K; k8 += 8) {
-#pragma unroll
-    for (int kk = k8; kk < k8 + 8; ++kk) {
-      T a[4], b[NJ];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = A[(4 * rg + r) * lda + kk];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) b[j] = sM[kk * WB + cg + 64 * j];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[r][j] += a[r] * b[j];
-    }
-  }
-}
-
-template <typename T, int NJ, bool FULL>
-__global__ __launch_bounds__(256) void fd2_kernel(const Fd2Item<T> *items, int K1pad) {
-  constexpr int WB = Fd2Shape<NJ>::WB;
-  extern __shared__ char smraw[];
-  T *sm = (T *)smraw;
-  const Fd2Item<T> it = items[blockIdx.z];
-  const int i0 = blockIdx.y * 16;
-  if (i0 >= it.rows) return;
-  const T *M1 = it.M1 + (long long)blockIdx.x * it.m1_z;
-  T *O = it.O + (long long)blockIdx.x * it.o_z;
-  const int lda = K1pad + 8;
-  T *sL = sm;              // 16 x lda, zero padded
-  T *sZ = sL + 16 * lda;   // 16 x WB
-  T *sM = sZ + 16 * WB;    // KC x WB
-  const int tid = threadIdx.x, cg = tid & 63, rg = tid >> 6;
-  const int nrow = min(16, it.rows - i0);
-  // rows of L: eight independent loads per thread and round trip
-  for (int e0 = 0; e0 < 16 * lda; e0 += 256 * 8) {
-    T v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int e = e0 + tid + 256 * j;
-      const int i = e / lda, a = e % lda;
-      v[j] = (e < 16 * lda && i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : (T)0;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (e0 + tid + 256 * j < 16 * lda) sL[e0 + tid + 256 * j] = v[j];
-  }
-  T acc[4][NJ];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[r][j] = 0;
-  if (FULL)
-    rowblock_product_full<T, NJ>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
-  else
-    rowblock_product<T, NJ>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      sZ[(4 * rg + r) * WB + cg + 64 * j] = acc[r][j];
-      acc[r][j] = 0;
-    }
-  if (FULL)
-    rowblock_product_full<T, NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
-  else
-    rowblock_product<T, NJ>(sZ, WB, it.M2, it.m2_r, it.N, it.N, sM, acc);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = 4 * rg + r;
-    if (i >= nrow) continue;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int col = cg + 64 * j;
-      if (col >= it.N) continue;
-      T v = acc[r][j];
-      T *o = O + (long long)(i0 + i) * it.o_r + col;
-      if (it.lam_r)
-        *o = v / (it.sigma + it.lam_r[i0 + i] + it.lam_c[col]);
-      else
-        *o += it.scale * v;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The same two chained row-block products on the matrix cores.  Wave w of the
-// block owns the 16-column tiles w, w+4, ..., w+4(NJ-1) of the 16-row block;
-// a k-step issues one MFMA per tile, the A fragment shared by the tiles:
+// Fast-diagonalization step of the subspace corrected mass smoother on the
+// matrix cores, fused form (Fd2Item): a block of 256 threads owns 16 rows of
+// the output and computes Z = L[rows, :] M1 (Z kept in LDS), then R = Z M2,
+// then the item's epilogue.  B operands are streamed through LDS (all of B
+// in one round of loads when it fits, else chunks of KC rows with the next
+// chunk held in registers).  Wave w owns the 16-column tiles w, w+4, ...,
+// w+4(NJ-1) of the block; a k-step issues one MFMA per tile, the A fragment
+// shared by the tiles:
 //   float64: v_mfma_f64_16x16x4f64 on the stored operands;
 //   float32: v_mfma_f32_16x16x4f32 on the stored operands;
 //   bf16:    v_mfma_f32_16x16x32_bf16 on operands rounded to bfloat16
@@ -2029,33 +1875,6 @@ template void k_stencil_apply<double>(Context &, LevelData &, const LevelArrays<
 template void k_stencil_apply<float>(Context &, LevelData &, const LevelArrays<float> &,
                                      const float *, const float *, const float *, float, float,
                                      float *, int);
-
-template <typename T, int NJ, bool FULL>
-static void launch_fd2_as(Context &c, LevelData &L, int stage, int nrhs, size_t lds) {
-  // allow dynamic LDS beyond 64 KiB (gfx950: 160 KiB); once per instance,
-  // thread-safe (function-local static initialization)
-  static const hipError_t lds_set = hipFuncSetAttribute(
-      (const void *)fd2_kernel<T, NJ, FULL>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  HIPCHK(lds_set);
-  dim3 grid(nrhs, (L.fd_rows + 15) / 16, L.n_fd);
-  fd2_kernel<T, NJ, FULL><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], L.fd_K1);
-}
-
-template <typename T, int NJ>
-static void launch_fd2(Context &c, LevelData &L, int stage, int nrhs) {
-  constexpr int WB = Fd2Shape<NJ>::WB, KC = Fd2Shape<NJ>::KC;
-  const size_t base = (size_t)(16 * (L.fd_K1 + 8) + 16 * WB) * sizeof(T);
-  // whole B in LDS when it fits: one load round per product instead of a chunk loop
-  const int kmax = (std::max(L.fd_K1, L.fd_N) + 7) / 8 * 8;
-  const size_t lds_full = base + (size_t)kmax * WB * sizeof(T);
-  if (NJ <= 2 && kmax <= WB && lds_full <= 150 * 1024) {
-    launch_fd2_as<T, NJ, NJ <= 2>(c, L, stage, nrhs, lds_full);
-    return;
-  }
-  const size_t lds = base + (size_t)KC * WB * sizeof(T);
-  if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
-  launch_fd2_as<T, NJ, false>(c, L, stage, nrhs, lds);
-}
 
 template <typename T, bool BF, int NJ, bool FULL>
 static void launch_fd2m_as(Context &c, LevelData &L, int stage, int nrhs, int lda, size_t lds) {

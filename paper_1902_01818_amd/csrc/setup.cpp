@@ -660,8 +660,8 @@ static std::vector<double> stencil_rows_host(Context &c, const LevelData &L, con
 // from the assembled stencil rows (volume + same-patch interface terms) and
 // the cross-patch interface terms.
 static std::vector<double> dense_block_rows(const Context &c, const LevelData &L,
-                                            const std::vector<int> &comps,
-                                            const std::vector<double> &rows, int SP) {
+                                            const std::vector<int> &comps, const double *rows,
+                                            int SP) {
   const int p = c.p, S1 = 2 * p + 1;
   const int n = (int)comps.size();
   std::unordered_map<long long, int> loc;
@@ -695,8 +695,8 @@ static std::vector<double> dense_block_rows(const Context &c, const LevelData &L
 // smoother data
 // ---------------------------------------------------------------------------
 static std::vector<double> dense_block_rows(const Context &c, const LevelData &L,
-                                            const std::vector<int> &comps,
-                                            const std::vector<double> &rows, int SP);
+                                            const std::vector<int> &comps, const double *rows,
+                                            int SP);
 static std::vector<double> stencil_rows_host(Context &c, const LevelData &L, const double *st64,
                                              int SP, const std::vector<int> &comps);
 
@@ -741,6 +741,14 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
   std::vector<int> idx, cp, cidx;
   std::vector<double> blocks;  // P_T^T A P_T of every piece, inverted on the GPU
   L.max_piece = 0;
+  // the stencil rows of all piece unknowns in one gather (one device round trip)
+  std::vector<double> rows;
+  if (st64) {
+    std::vector<int> all;
+    for (auto &m : members) all.insert(all.end(), m.begin(), m.end());
+    rows = stencil_rows_host(c, L, st64, SP, all);
+  }
+  size_t row0 = 0;
   for (auto &m : members) {
     PieceDev pc{};
     pc.n = (int)m.size();
@@ -753,8 +761,9 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
       for (int t : L.copies[ci]) cidx.push_back(t);
     }
     cp.push_back((int)cidx.size());
-    std::vector<double> A = st64 ? dense_block_rows(c, L, m, stencil_rows_host(c, L, st64, SP, m), SP)
+    std::vector<double> A = st64 ? dense_block_rows(c, L, m, rows.data() + row0 * SP, SP)
                                  : dense_block(c, L, m);
+    row0 += m.size();
     blocks.insert(blocks.end(), A.begin(), A.end());
     pcs.push_back(pc);
     L.max_piece = std::max(L.max_piece, pc.n);
@@ -1337,7 +1346,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       c.N0 = (int)L.N;
       if (c.N0 > 16384)
         fail(IGAMG_EUNSUPPORTED, "coarsest level too large for the direct solve");
-      std::vector<double> A0 = sipg ? dense_block_rows(c, L, all, stencil_rows_host(c, L, st64, SP, all), SP)
+      std::vector<double> A0 = sipg ? dense_block_rows(c, L, all, stencil_rows_host(c, L, st64, SP, all).data(), SP)
                                     : dense_block(c, L, all);
       pc.lap("coarse_matrix");
       c.d_A0inv = c.arena.upload(A0, c.stream);
@@ -1408,14 +1417,16 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
 // roofline model: algorithmic work of one launch (not counting redundant
 // loads of tile halos or recomputation)
 // ---------------------------------------------------------------------------
-void kernel_model(const Context &c, const std::string &fam, int level, double *bytes,
+void kernel_model(const Context &c, const std::string &fam, int level, int nrhs, double *bytes,
                   double *flops) {
   const LevelData &L = c.lv[level];
   const double nt = (double)L.Ntorn;
   const double wb = c.fp32() ? 4.0 : 8.0;  // bytes of a value in the cycle arithmetic
+  const double nb = nrhs < 1 ? 1.0 : (double)nrhs;
   const int q = c.p + 1, P1 = c.p + 1;
   int S = 1;
   for (int g = 0; g < c.d; ++g) S *= (2 * c.p + 1);
+  const double SP = (S + 15) / 16 * 16;
   double nnz = L.if_col.size(), ncross = 0;
   for (unsigned char x : L.if_cross) ncross += x;
   *bytes = 0;
@@ -1430,22 +1441,33 @@ void kernel_model(const Context &c, const std::string &fam, int level, double *b
       *flops += 4.0 * pt.n[1] * Qx * P1;        // transposed y-contraction
       *flops += 4.0 * pt.n[1] * pt.n[0] * Qx / pt.nel[0] * P1;  // transposed x-contraction
     }
-    *bytes = 3.0 * wb * nt;                     // read u, read and write r
+    *flops *= nb;
+    *bytes = 3.0 * wb * nt * nb;                // read u, read and write r
   } else if (fam == "gauss_seidel") {
+    // one colour-class launch; rows and 1/a_ii shared by the batch; per
+    // right-hand side f read, u read and written, cross columns read
     int launches = 0;
     for (const GsClass &cl : L.gs) launches += cl.count > 0;
     if (launches == 0) launches = 1;
-    *bytes = (nt * (wb * ((S + 15) / 16 * 16) + wb * 4) + ncross * (8.0 + 2.0 * wb)) / launches;
-    *flops = (2.0 * S * nt + 2.0 * ncross) / launches;
+    *bytes = (nt * wb * (SP + 1) + ncross * (8.0 + wb) + nb * (nt * 3.0 * wb + ncross * wb)) /
+             launches;
+    *flops = nb * (2.0 * S * nt + 2.0 * ncross) / launches;
+  } else if (fam == "stencil_apply") {
+    // rows, mask and cross couplings shared; per right-hand side u and f
+    // read, r written
+    *bytes = nt * (SP * wb + 1.0) + ncross * (8.0 + wb) + nb * (nt * 3.0 * wb + ncross * wb);
+    *flops = nb * (2.0 * S * nt + 2.0 * ncross);
   } else if (fam == "scms") {
+    // one application to the patch interiors: four products per patch;
+    // bytes: r read, u read and written per right-hand side, the factors once
     for (int k = 0; k < c.K; ++k) {
       double mx = L.pd[k].n[0] - 2, my = L.pd[k].n[1] - 2;
-      *flops += 2.0 * (mx * my * mx + my * my * mx + my * mx * mx + my * my * mx);
-      *bytes += wb * (mx * my * (1 + 2 + 4) + 2 * (mx * mx + my * my));
+      *flops += nb * 2.0 * (my * my * mx + my * mx * mx + my * my * mx + my * mx * mx);
+      *bytes += nb * 3.0 * wb * mx * my + wb * 2.0 * (mx * mx + my * my);
     }
   } else if (fam == "iface_apply") {
-    *bytes = nt * (wb + wb + 1.0 + 1.0) + nnz * (4.0 + wb + wb);
-    *flops = 2.0 * nnz;
+    *bytes = nt * 2.0 + nnz * (4.0 + wb) + nb * (nt * 2.0 * wb + nnz * wb);
+    *flops = nb * 2.0 * nnz;
   } else {
     fail(IGAMG_EINVAL, "no model for this kernel family");
   }
@@ -1481,6 +1503,8 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
     for (int a = 1; a < d; ++a) side *= (P->elems[(size_t)k * d + a] + p);
     bytes += 2.0 * d * (2.0 * side) * (2.0 * side) * 8.0 * ((1 << d) / ((1 << d) - 1.0)) / 2.0 *
              (wb == 4.0 ? 1.5 : 1.0);
+    // stencil rows of the piece unknowns gathered at setup (kept inside a lent region)
+    bytes += 2.0 * d * side * (SP * 8.0 + 4.0) * ((1 << d) / ((1 << d) - 1.0));
   }
   {
     // coarsest element counts by the halving rule of the hierarchy
@@ -1498,7 +1522,7 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
       for (int a = 0; a < d; ++a) m *= (e[(size_t)k * d + a] + p);
       n0 += m;
     }
-    bytes += n0 * n0 * 8.0;
+    bytes += n0 * n0 * 8.0 + n0 * (SP * 8.0 + 4.0);
   }
   // outer float64 vectors [nb][Ntorn]: x, r, z, p, q, f (+ r_old)
   bytes += fine * 8.0 * nb * (7 + (o->outer == IGAMG_OUTER_FCG ? 1 : 0));

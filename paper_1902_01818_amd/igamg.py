@@ -65,7 +65,7 @@ _lib.igamg_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
 _lib.igamg_kernel_stats.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
                                     ctypes.c_int]
-_lib.igamg_kernel_model.argtypes = [_vp, ctypes.c_char_p, ctypes.c_int,
+_lib.igamg_kernel_model.argtypes = [_vp, ctypes.c_char_p, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.igamg_set_timing.argtypes = [_vp, ctypes.c_char_p]
 _lib.igamg_destroy.argtypes = [_vp]
@@ -313,9 +313,9 @@ class Solver:
             out[nm] = dict(ms=ms[i], launches=int(launches[i]))
         return out
 
-    def kernel_model(self, family, level=-1):
+    def kernel_model(self, family, level=-1, nrhs=1):
         b, f = ctypes.c_double(), ctypes.c_double()
-        _check(_lib.igamg_kernel_model(self._h, family.encode(), level, ctypes.byref(b),
+        _check(_lib.igamg_kernel_model(self._h, family.encode(), level, nrhs, ctypes.byref(b),
                                        ctypes.byref(f)), "igamg_kernel_model")
         return b.value, f.value
 
