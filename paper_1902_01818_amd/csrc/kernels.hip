@@ -586,18 +586,19 @@ __global__ void glue_kernel(int ng, const int *ptr, const int *idx, T *y, long l
 // prefetched into registers; f minus the cross-patch couplings (neighbouring
 // patches carry another patch colour, so their values are constant during the
 // launch) and 1/a_ii sit in LDS as one pair per unknown.
-// grid.x = right-hand side (the batch shares the tile's stencil rows in
-// cache), grid.y = tile.
+// A block holds RBW wavefronts, one per right-hand side of a batch, on the
+// same tile: their stencil-row loads meet in the CU's L1 instead of each
+// going to L2.  grid.x = group of RBW right-hand sides, grid.y = tile.
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
+template <typename T, int P, int RBW>
+__global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles,
                                                        const T *__restrict__ st,
                                                        const T *__restrict__ invd,
                                                        const int *__restrict__ cx_li,
                                                        const int *__restrict__ cx_col,
                                                        const T *__restrict__ cx_val,
                                                        const T *__restrict__ f, T *u,
-                                                       int backward, long long vs) {
+                                                       int backward, long long vs, int nrhs) {
   using T2 = typename Pair2<T>::type;
   constexpr int Q1 = P + 1, TT = 2 * Q1, W = TT + 2 * P;
   constexpr int S1 = 2 * P + 1, S = S1 * S1;
@@ -608,17 +609,22 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
   // longer prologue outweighs the hidden latency)
   constexpr int D0 = (sizeof(T) == 8 ? 48 : 96) / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
-  __shared__ T sU[W * W];
-  __shared__ T2 sBD[TT * TT];
+  __shared__ T sUa[RBW][W * W];
+  __shared__ T2 sBDa[RBW][TT * TT];
   __shared__ int sOff[C * 16];
   const GsTile tl = tiles[blockIdx.y];
-  f += (long long)blockIdx.x * vs;
-  u += (long long)blockIdx.x * vs;
+  const int wid = threadIdx.x >> 6;
+  const int z = blockIdx.x * RBW + wid;
+  const bool zok = z < nrhs;  // waves past the batch run on column 0 and store nothing
+  f += (long long)(zok ? z : 0) * vs;
+  u += (long long)(zok ? z : 0) * vs;
+  T *sU = sUa[wid];
+  T2 *sBD = sBDa[wid];
   const int nx = tl.nx, ny = tl.ny;
   const int x0 = tl.i0[0], y0 = tl.i0[1];
   const int wx0 = x0 - P, wy0 = y0 - P;
   const long long off = tl.off;
-  const int lane = threadIdx.x, grp = lane >> 4, l16 = lane & 15;
+  const int lane = threadIdx.x & 63, grp = lane >> 4, l16 = lane & 15;
   const int ax = (grp & 1) * Q1, ay = (grp >> 1) * Q1;
   // Prologue: every global load that does not depend on another one is issued
   // before the first wait (u window, f, 1/a_ii -- zero on Dirichlet unknowns by
@@ -666,7 +672,8 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
       bd.y = dv[j];
       sBD[lane + 64 * j] = bd;
     }
-  for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
+  if (wid == 0)
+    for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 8; ++j)
@@ -728,6 +735,7 @@ __global__ __launch_bounds__(64) void gs2d_wave_kernel(const GsTile *tiles,
     asm volatile("" ::: "memory");
   }
   __syncthreads();
+  if (!zok) return;
   for (int i = lane; i < TT * TT; i += 64) {
     int iy = y0 + i / TT, ix = x0 + i % TT;
     if (ix < nx && iy < ny) u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
@@ -1798,10 +1806,18 @@ template void k_glue_sum<float>(LevelData &, float *, int, hipStream_t);
 template <typename T, int P>
 static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
   LevelArrays<T> &A = L.arr<T>();
-  dim3 grid(nrhs, cl.count);
-  gs2d_wave_kernel<T, P><<<grid, 64, 0, c.stream>>>(cl.tiles, A.stencil, A.invdiag,
-                                                    L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
-                                                    backward ? 1 : 0, L.Ntorn);
+  if (nrhs == 1) {
+    gs2d_wave_kernel<T, P, 1><<<dim3(1, cl.count), 64, 0, c.stream>>>(
+        cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
+        backward ? 1 : 0, L.Ntorn, nrhs);
+    return;
+  }
+  // batches: four right-hand sides of a tile per block
+  constexpr int RBW = 4;
+  dim3 grid((nrhs + RBW - 1) / RBW, cl.count);
+  gs2d_wave_kernel<T, P, RBW><<<grid, 64 * RBW, 0, c.stream>>>(
+      cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
+      backward ? 1 : 0, L.Ntorn, nrhs);
 }
 
 template <typename T>
