@@ -78,13 +78,14 @@ def cpu_baseline(cfg, f, its_gpu, budget_s=15.0):
                 iterations=its)
 
 
-def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2):
+def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2, outer=None):
     """64 right-hand sides of the p = 6, 256-element workload solved together
     (float32 cycle, optionally with bfloat16 SCMS contractions, inside float64
     flexible CG; or float64 PCG), with the matrix-core utilisation of the
     finest level's SCMS application measured in one more, event-timed solve."""
     cfg = workloads.config("c4")
-    outer = "pcg" if precision == "fp64" else "fcg"
+    if outer is None:
+        outer = "pcg" if precision == "fp64" else "fcg"
     t0 = time.perf_counter()
     sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
                       conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
@@ -225,6 +226,28 @@ def main():
     roof["model_bytes_per_launch"] = mbytes
     roof["model_flops_per_launch"] = mflops
 
+    # every modelled kernel family of the finest level (and the coarse solve)
+    # in one more, event-timed solve: mean launch time and achieved rate
+    sv.set_timing("")
+    sv.solve(f, u, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    st_all = sv.kernel_stats(reset=True)
+    sv.set_timing(None)
+    kernels = {}
+    for fam in ("gauss_seidel", "stencil_apply", "vol_apply", "iface_apply", "scms", "pieces",
+                "restrict", "prolong", "coarse"):
+        k = "%s/%d" % (fam, 0 if fam == "coarse" else top)
+        if not st_all.get(k, {}).get("launches"):
+            continue
+        t = st_all[k]["ms"] / 1e3 / st_all[k]["launches"]
+        b, fl = sv.kernel_model(fam, top, 1)
+        ent = {"avg_us": t * 1e6, "model_bytes": b, "model_flops": fl,
+               "gb_s": b / t / 1e9, "frac_hbm": b / t / 1e9 / PEAK["hbm"]}
+        if fam == "scms":
+            ent["tflop_s"] = fl / t / 1e12
+            ent["frac_mfma_fp64"] = ent["tflop_s"] / MFMA_PEAK["fp64"]
+        kernels[fam] = ent
+
     its = infos[-1]["iterations"]
     ok = all(i["converged"] and i["true_rel_residual"] <= 1e-8 * 1.01 for i in infos)
     value = args.steps / dt
@@ -250,6 +273,7 @@ def main():
                    "vcycles_per_s": value * (its + 1),
                    "true_rel_residual": infos[-1]["true_rel_residual"], "all_converged": ok},
         "roofline": roof,
+        "kernels_finest": kernels,
     }
     # mixed precision: float32 cycle inside float64 flexible CG, same workload,
     # same float64 stopping test; error reported against the float64 GPU solve
@@ -296,6 +320,10 @@ def main():
         print("bench: 64-column p = 6 batch timed (float32 cycle)", file=sys.stderr, flush=True)
         line["c4_bf16_scms"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="bf16", steps=1)
         print("bench: 64-column p = 6 batch timed (bf16 SCMS)", file=sys.stderr, flush=True)
+        line["c4_refinement"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32",
+                                       steps=1, outer="ir")
+        print("bench: 64-column p = 6 batch timed (float64 iterative refinement)", file=sys.stderr,
+              flush=True)
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

@@ -76,6 +76,13 @@ extern "C" {
 #define IGAMG_OUTER_PCG 0
 #define IGAMG_OUTER_MG 1
 #define IGAMG_OUTER_FCG 2
+/* Iterative refinement: x <- x + d with d an inner PCG solve of A d = f - A x
+ * (the residual in float64) whose operator applies and preconditioning cycle
+ * run in the cycle arithmetic, stopped at a 1e-4 relative reduction of the
+ * inner residual; the outer loop stops on the float64 residual.  maxit bounds
+ * the total inner iterations of each right-hand side; `iterations` reports
+ * that total (one cycle each). */
+#define IGAMG_OUTER_IR 3
 /* Operator applies (the cycle's residuals and the float64 outer apply).
  * AUTO: from the stored matrix rows on the levels that keep them (SIPG with
  * a Gauss-Seidel smoother keeps the rows of every level above the coarsest:
@@ -125,7 +132,9 @@ typedef struct {
   double rel_residual;     /* ||r_k|| / ||f|| of the outer recurrence at exit */
   double true_rel_residual;/* ||f - A u|| / ||f|| recomputed in float64 at exit */
   double seconds;          /* wall time of the solve on the host */
-  double *history;         /* optional host array [maxit+1] of relative residuals, or NULL */
+  double *history;         /* optional host array [maxit+1] of relative residuals, or NULL
+                              (entry k after outer iteration k; with IGAMG_OUTER_IR after
+                              refinement step k, the float64 residual) */
 } igamg_solve_info;
 
 typedef struct igamg_ctx igamg_ctx;
@@ -206,7 +215,8 @@ int igamg_set_timing(igamg_ctx *ctx, const char *filter);
  * roofline model of the library's kernels.  Families: "stencil_apply" and
  * "vol_apply" + "iface_apply" (operator, eq. model:discr2), "gauss_seidel"
  * (one colour class), "scms" (one application to all patch interiors, eq.
- * Ldef).  Operator data shared by the batch counts once; vectors once per
+ * Ldef), "pieces" (all interface pieces), "restrict" / "prolong" (level = the
+ * fine side), "coarse" (the direct solve; level ignored).  Operator data shared by the batch counts once; vectors once per
  * right-hand side.  Errors: IGAMG_EINVAL for an unknown family, a level out
  * of range or nrhs < 1. */
 int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, int nrhs, double *bytes,

@@ -148,6 +148,7 @@ struct LevelData {
   // interface pieces
   PieceDev *d_pieces = nullptr;
   int n_pieces = 0, max_piece = 0;
+  double piece_sq = 0, piece_n = 0;  // sums of n_T^2 and n_T over the pieces (kernel model)
   int *d_piece_idx = nullptr, *d_piece_cp = nullptr, *d_piece_cidx = nullptr;
   // transfer tables between this level and the next coarser one
   int *d_P_lo = nullptr, *d_R_lo = nullptr;
@@ -204,6 +205,7 @@ struct Context {
   // outer iteration vectors (float64, torn layout, finest level, [nb][Ntorn])
   double *x = nullptr, *rr = nullptr, *z = nullptr, *pp = nullptr, *qq = nullptr, *ff = nullptr;
   double *rold = nullptr;        // previous residual (flexible CG)
+  double *dd = nullptr, *rin = nullptr;  // inner correction and residual (refinement)
   double *d_red = nullptr;       // reduction partials [nb][RED_BLOCKS]
   double *d_scal = nullptr;      // device scalars [nb][S_COUNT]
   double *h_scal = nullptr;      // pinned host mirror

@@ -127,6 +127,28 @@ void precondition(Context &c, const double *r, int nb) {
   L.a64.f = f_saved;
 }
 
+// q = A p on the finest level in the cycle arithmetic (float64 vectors in and
+// out; a float32 cycle converts through its own finest work vectors, which
+// are free outside a cycle)
+void apply_inner(Context &c, const double *p, double *q, int nb) {
+  LevelData &L = c.lv.back();
+  const long long nt = L.Ntorn;
+  if (!c.fp32()) {
+    apply64(c, p, nullptr, nullptr, q, 1.0, nb);
+    return;
+  }
+  LevelArrays<float> &A = L.a32;
+  k_convert<double, float>(p, nullptr, A.u, nt, nb, c.stream);
+  if (L.st_apply) {
+    k_stencil_apply<float>(c, L, A, A.u, nullptr, nullptr, 0.0f, 1.0f, A.r, nb);
+  } else {
+    k_iface_apply<float>(c, L, A.u, nullptr, nullptr, 0.0f, 1.0f, A.r, nb);
+    k_vol_apply<float>(c, L, A.u, A.r, 1.0f, nb);
+    k_glue_sum<float>(L, A.r, nb, c.stream);
+  }
+  k_convert<float, double>(A.r, nullptr, q, nt, nb, c.stream);
+}
+
 void read_scalars(Context &c, int nb) {
   HIPCHK(hipMemcpyAsync(c.h_scal, c.d_scal, (size_t)nb * S_COUNT * sizeof(double),
                         hipMemcpyDeviceToHost, c.stream));
@@ -236,6 +258,71 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
         apply64(c, c.x, c.ff, L.a64.weight, c.rr, -1.0, nb);
         k_dot(c, c.rr, c.rr, nt, S_RR, 0, nb);
         check(it);
+      }
+    } else if (c.opt.outer == IGAMG_OUTER_IR) {
+      // iterative refinement: inner PCG in the cycle arithmetic on the
+      // float64 residual, to a fixed relative reduction; x += d; the float64
+      // residual decides convergence
+      constexpr double INNER_REDUCTION = 1e-4;
+      double *x_out = c.x, *r_out = c.rr;
+      std::vector<int> outer_active(c.h_active, c.h_active + nb);
+      std::vector<int> total(nb, 0);
+      std::vector<double> ref(nb);
+      for (int step = 1; step <= maxit && n_active > 0; ++step) {
+        for (int j = 0; j < nb; ++j) ref[j] = res[j] * nf[j];
+        HIPCHK(hipMemcpyAsync(c.rin, r_out, bytes, hipMemcpyDeviceToDevice, c.stream));
+        k_fill(c.dd, 0.0, nt * nb, c.stream);
+        c.x = c.dd;
+        c.rr = c.rin;
+        k_fill(c.z, 0.0, nt * nb, c.stream);
+        precondition(c, c.rr, nb);
+        k_dot(c, c.rr, c.z, nt, S_RZ, 0, nb);
+        HIPCHK(hipMemcpyAsync(c.pp, c.z, bytes, hipMemcpyDeviceToDevice, c.stream));
+        int inner_active = n_active;
+        for (int k = 1; inner_active > 0; ++k) {
+          apply_inner(c, c.pp, c.qq, nb);                // q = A p
+          k_dot(c, c.pp, c.qq, nt, S_PQ, 1, nb);          // alpha = rz / pq
+          k_pcg_update_xr(c, nt, nb, false);             // d += alpha p, r -= alpha q; z = 0
+          read_scalars(c, nb);
+          bool changed = false;
+          for (int j = 0; j < nb; ++j) {
+            if (!c.h_active[j]) continue;
+            ++total[j];
+            const double rin = std::sqrt(c.h_scal[(size_t)j * S_COUNT + S_RR]);
+            if (rin <= INNER_REDUCTION * ref[j] || total[j] >= maxit) {
+              c.h_active[j] = 0;
+              --inner_active;
+              changed = true;
+            }
+          }
+          if (inner_active == 0) break;
+          if (changed) upload_active(c, nb);
+          precondition(c, c.rr, nb);
+          k_dot(c, c.rr, c.z, nt, S_RZNEW, 2, nb);  // beta = rz_new / rz
+          k_pcg_update_p(c, nt, nb);                  // p = z + beta p
+        }
+        c.x = x_out;
+        c.rr = r_out;
+        for (int j = 0; j < nb; ++j) c.h_active[j] = outer_active[j];
+        upload_active(c, nb);
+        k_add_active(c, c.x, c.dd, nt, nb);                    // x += d
+        apply64(c, c.x, c.ff, L.a64.weight, c.rr, -1.0, nb);  // r = f - A x (float64)
+        k_dot(c, c.rr, c.rr, nt, S_RR, 0, nb);
+        read_scalars(c, nb);
+        bool changed = false;
+        for (int j = 0; j < nb; ++j) {
+          if (!outer_active[j]) continue;
+          res[j] = std::sqrt(c.h_scal[(size_t)j * S_COUNT + S_RR]) / nf[j];
+          its[j] = total[j];
+          if (info && info[j].history) info[j].history[step] = res[j];
+          if (res[j] <= tol || total[j] >= maxit) {
+            outer_active[j] = 0;
+            c.h_active[j] = 0;
+            --n_active;
+            changed = true;
+          }
+        }
+        if (changed && n_active > 0) upload_active(c, nb);
       }
     } else {
       const bool fcg = c.opt.outer == IGAMG_OUTER_FCG;

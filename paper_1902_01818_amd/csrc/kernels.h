@@ -79,5 +79,7 @@ void k_dot_fcg(Context &c, long long n, int nrhs);
 // x += alpha p, r -= alpha q, ||r||^2 into S_RR; zeroes z; optionally keeps r_old
 void k_pcg_update_xr(Context &c, long long n, int nrhs, bool keep_rold);
 void k_pcg_update_p(Context &c, long long n, int nrhs);
+// y += x for the active right-hand sides
+void k_add_active(Context &c, double *y, const double *x, long long n, int nrhs);
 
 }  // namespace igamg

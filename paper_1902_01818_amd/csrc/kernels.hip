@@ -1539,6 +1539,15 @@ __global__ void pcg_p_kernel(double *p, const double *z, long long n, const doub
     p[zo + i] = z[zo + i] + beta * p[zo + i];
 }
 
+__global__ void add_active_kernel(double *y, const double *x, long long n, const int *active) {
+  const int j = blockIdx.y;
+  if (!active[j]) return;
+  const long long zo = (long long)j * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[zo + i] += x[zo + i];
+}
+
 // ---------------------------------------------------------------------------
 // Setup: in-place inverse of a dense symmetric positive definite matrix by
 // blocked Gauss-Jordan elimination without pivoting (the Schur complements of
@@ -2079,6 +2088,12 @@ void k_pcg_update_xr(Context &c, long long n, int nrhs, bool keep_rold) {
       c.x, c.rr, c.pp, c.qq, c.lv.back().a64.weight, n, c.d_scal, c.d_red, c.z,
       keep_rold ? c.rold : nullptr, c.d_active);
   dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
+}
+
+void k_add_active(Context &c, double *y, const double *x, long long n, int nrhs) {
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
+  dim3 grid(std::min<unsigned>(nblocks(n), 2048), nrhs);
+  add_active_kernel<<<grid, BS, 0, c.stream>>>(y, x, n, c.d_active);
 }
 
 void k_pcg_update_p(Context &c, long long n, int nrhs) {

@@ -767,6 +767,8 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
     blocks.insert(blocks.end(), A.begin(), A.end());
     pcs.push_back(pc);
     L.max_piece = std::max(L.max_piece, pc.n);
+    L.piece_sq += (double)pc.n * pc.n;
+    L.piece_n += pc.n;
   }
   L.n_pieces = (int)pcs.size();
   L.d_pieces = c.arena.upload(pcs, c.stream);
@@ -1106,7 +1108,7 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
   if (c.opt.precision != IGAMG_FP64 && c.opt.precision != IGAMG_FP32 &&
       c.opt.precision != IGAMG_BF16_SCMS)
     fail(IGAMG_EINVAL, "unknown precision");
-  if (c.opt.outer < IGAMG_OUTER_PCG || c.opt.outer > IGAMG_OUTER_FCG)
+  if (c.opt.outer < IGAMG_OUTER_PCG || c.opt.outer > IGAMG_OUTER_IR)
     fail(IGAMG_EINVAL, "unknown outer iteration");
   if (c.opt.operator_apply < IGAMG_APPLY_AUTO || c.opt.operator_apply > IGAMG_APPLY_ROWS)
     fail(IGAMG_EINVAL, "unknown operator_apply");
@@ -1384,6 +1386,12 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     c.rold = c.arena.alloc<double>(nt);
     k_fill(c.rold, 0.0, (long long)nt, c.stream);
   }
+  if (c.opt.outer == IGAMG_OUTER_IR) {
+    c.dd = c.arena.alloc<double>(nt);
+    c.rin = c.arena.alloc<double>(nt);
+    k_fill(c.dd, 0.0, (long long)nt, c.stream);
+    k_fill(c.rin, 0.0, (long long)nt, c.stream);
+  }
   c.d_red = c.arena.alloc<double>((size_t)2 * RED_BLOCKS * c.nb);
   c.d_scal = c.arena.alloc<double>((size_t)S_COUNT * c.nb);
   k_fill(c.d_scal, 0.0, (long long)S_COUNT * c.nb, c.stream);
@@ -1465,6 +1473,21 @@ void kernel_model(const Context &c, const std::string &fam, int level, int nrhs,
       *flops += nb * 2.0 * (my * my * mx + my * mx * mx + my * my * mx + my * mx * mx);
       *bytes += nb * 3.0 * wb * mx * my + wb * 2.0 * (mx * mx + my * my);
     }
+  } else if (fam == "pieces") {
+    // stored inverses once, the pieces' residuals read and corrections added
+    *bytes = wb * L.piece_sq + L.piece_n * 8.0 + nb * 3.0 * wb * L.piece_n;
+    *flops = nb * 2.0 * L.piece_sq;
+  } else if (fam == "restrict" || fam == "prolong") {
+    // level = the fine side; restriction reads r_f and writes r_c (and clears
+    // the coarse iterate), prolongation reads e_c and updates u_f
+    if (level < 1) fail(IGAMG_EINVAL, "transfers start on level 1");
+    const double nc = (double)c.lv[level - 1].Ntorn;
+    *bytes = nb * wb * (fam == "restrict" ? nt + 2.0 * nc : nc + 2.0 * nt);
+    *flops = nb * 2.0 * nt * (L.PW + L.RW);
+  } else if (fam == "coarse") {
+    const double n0 = (double)c.N0;
+    *bytes = n0 * n0 * 8.0 + nb * 2.0 * 8.0 * n0;
+    *flops = nb * 2.0 * n0 * n0;
   } else if (fam == "iface_apply") {
     *bytes = nt * 2.0 + nnz * (4.0 + wb) + nb * (nt * 2.0 * wb + nnz * wb);
     *flops = nb * 2.0 * nnz;
@@ -1525,7 +1548,8 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
     bytes += n0 * n0 * 8.0 + n0 * (SP * 8.0 + 4.0);
   }
   // outer float64 vectors [nb][Ntorn]: x, r, z, p, q, f (+ r_old)
-  bytes += fine * 8.0 * nb * (7 + (o->outer == IGAMG_OUTER_FCG ? 1 : 0));
+  bytes += fine * 8.0 * nb *
+           (7 + (o->outer == IGAMG_OUTER_FCG ? 1 : 0) + (o->outer == IGAMG_OUTER_IR ? 2 : 0));
   // float32 setup assembles the stencils in float64 first: freed afterwards
   // with driver allocations, kept inside a lent region (every level)
   if (gs && wb == 4.0) bytes += all_levels * 8.0 * (SP + 1);

@@ -22,7 +22,7 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOCONV = 0, -1, -2, -3, -4, 1
 SIPG, CONFORMING = 0, 1
 SMOOTHERS = {"hybrid": 0, "scms": 1, "gs": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
-OUTERS = {"pcg": 0, "mg": 1, "fcg": 2}
+OUTERS = {"pcg": 0, "mg": 1, "fcg": 2, "ir": 3}
 APPLIES = {"auto": 0, "sumfact": 1, "rows": 2}
 
 

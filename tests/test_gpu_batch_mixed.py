@@ -125,6 +125,28 @@ def test_bf16_scms_solve(c2_small):
     sv.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_iterative_refinement(c2_small, precision):
+    """Float64 iterative refinement around inner PCG solves in the cycle
+    arithmetic (relative reduction 1e-4 per refinement step): the float64
+    residual decides, so the true residual meets the tolerance; restarting
+    the Krylov space at every step may cost iterations, bounded here by twice
+    the float64 PCG count."""
+    cfg, ob = c2_small
+    sv = gpu_solver(cfg, precision=precision, outer="ir", max_rhs=2)
+    F = _rhs_batch(ob.N, [2002, 2005])
+    U, info = sv.solve(_gpu(F), tol=1e-8, maxit=200, history=True)
+    U = U.cpu().numpy().reshape(2, ob.N)
+    for j in range(2):
+        _, its, _, _ = ob.pcg(F[j])
+        true_res = np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j])
+        assert info[j]["converged"], info[j]
+        assert true_res <= 1.05e-8, true_res
+        assert abs(info[j]["true_rel_residual"] - true_res) < 1e-12
+        assert info[j]["iterations"] <= 2 * its, (info[j]["iterations"], its)
+    sv.close()
+
+
 def test_fp32_fullsize_solve():
     cfg, ob = cached_oracle("c2", 1)
     sv = gpu_solver(cfg, precision="fp32", outer="fcg")
