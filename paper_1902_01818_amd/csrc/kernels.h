@@ -28,6 +28,10 @@ void k_load_manufactured(Context &c, LevelData &L, double *out);
 // in-place inverse of a dense SPD n x n matrix (blocked Gauss-Jordan);
 // bad[0] is set to 1 when a pivot is not positive (not SPD)
 void k_spd_inverse(double *A, int n, int *bad, hipStream_t s);
+// the same for nmat matrices at base + offs[z] of orders ns[z] <= nmax (device
+// arrays), one launch per kernel and block step for the whole batch
+void k_spd_inverse_batch(double *base, const long long *offs, const int *ns, int nmat, int nmax,
+                         int *bad, hipStream_t s);
 // out[r][:] = st[rows[r]][:] (rows of SP values)
 void k_gather_rows(const double *st, int SP, const int *rows, int nrows, double *out,
                    hipStream_t s);

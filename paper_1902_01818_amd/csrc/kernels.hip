@@ -1558,9 +1558,28 @@ __global__ void add_active_kernel(double *y, const double *x, long long n, const
 // ---------------------------------------------------------------------------
 constexpr int GJB = 32;
 
+// Matrix z of a batch: A = base + offs[z] with order ns[z] (offs == null:
+// one matrix of order n1 at base); false when step k0 is past its order.
+__device__ inline bool gj_matrix(double *base, const long long *offs, const int *ns, int n1,
+                                 int k0, double *&A, int &n, int &nb) {
+  if (offs) {
+    A = base + offs[blockIdx.z];
+    n = ns[blockIdx.z];
+  } else {
+    A = base;
+    n = n1;
+  }
+  nb = min(GJB, n - k0);
+  return k0 < n;
+}
+
 // scalar Gauss-Jordan on the diagonal block (1024 threads = 32 x 32)
-__global__ __launch_bounds__(1024) void gj_diag_kernel(double *A, int n, int k0, int nb,
+__global__ __launch_bounds__(1024) void gj_diag_kernel(double *base, const long long *offs,
+                                                       const int *ns, int n1, int k0,
                                                        int *bad) {
+  double *A;
+  int n, nb;
+  if (!gj_matrix(base, offs, ns, n1, k0, A, n, nb)) return;
   __shared__ double S[GJB][GJB + 1];
   const int c = threadIdx.x % GJB, r = threadIdx.x / GJB;
   const bool in = r < nb && c < nb;
@@ -1588,7 +1607,12 @@ __global__ __launch_bounds__(1024) void gj_diag_kernel(double *A, int n, int k0,
 }
 
 // A_kj <- P A_kj for every column j outside the block (one thread per column)
-__global__ __launch_bounds__(256) void gj_row_kernel(double *A, int n, int k0, int nb) {
+__global__ __launch_bounds__(256) void gj_row_kernel(double *base, const long long *offs,
+                                                     const int *ns, int n1, int k0) {
+  double *A;
+  int n, nb;
+  if (!gj_matrix(base, offs, ns, n1, k0, A, n, nb)) return;
+  if (blockIdx.x * blockDim.x >= (unsigned)n) return;
   __shared__ double P[GJB][GJB];
   for (int e = threadIdx.x; e < GJB * GJB; e += blockDim.x) {
     const int r = e / GJB, c = e % GJB;
@@ -1611,10 +1635,15 @@ __global__ __launch_bounds__(256) void gj_row_kernel(double *A, int n, int k0, i
 
 // A_ij <- A_ij - A_ik A_kj for i, j outside the block: 64 x 64 tiles, each
 // thread 4 x 4 entries, inner dimension nb <= 32 staged in LDS
-__global__ __launch_bounds__(256) void gj_update_kernel(double *A, int n, int k0, int nb) {
+__global__ __launch_bounds__(256) void gj_update_kernel(double *base, const long long *offs,
+                                                        const int *ns, int n1, int k0) {
+  double *A;
+  int n, nb;
+  if (!gj_matrix(base, offs, ns, n1, k0, A, n, nb)) return;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  if (i0 >= n || j0 >= n) return;
   __shared__ double Ci[64][GJB + 1];  // A_ik rows of the tile
   __shared__ double Rj[GJB][64 + 1];  // A_kj columns of the tile
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   for (int e = threadIdx.x; e < 64 * GJB; e += blockDim.x) {
     const int a = e / GJB, t = e % GJB;
     const int i = i0 + a;
@@ -1652,7 +1681,12 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *A, int n, int k0
 }
 
 // A_ik <- -A_ik P for every row i outside the block (one thread per row)
-__global__ __launch_bounds__(256) void gj_col_kernel(double *A, int n, int k0, int nb) {
+__global__ __launch_bounds__(256) void gj_col_kernel(double *base, const long long *offs,
+                                                     const int *ns, int n1, int k0) {
+  double *A;
+  int n, nb;
+  if (!gj_matrix(base, offs, ns, n1, k0, A, n, nb)) return;
+  if (blockIdx.x * blockDim.x >= (unsigned)n) return;
   __shared__ double P[GJB][GJB];
   for (int e = threadIdx.x; e < GJB * GJB; e += blockDim.x) {
     const int r = e / GJB, c = e % GJB;
@@ -2041,19 +2075,30 @@ void k_gather_rows(const double *st, int SP, const int *rows, int nrows, double 
   gather_rows_kernel<<<nblocks((long long)nrows * SP), BS, 0, s>>>(st, SP, rows, nrows, out);
 }
 
-void k_spd_inverse(double *A, int n, int *bad, hipStream_t s) {
-  if (n <= 0) return;
-  const unsigned nbl = (unsigned)((n + 255) / 256);
-  const unsigned nt = (unsigned)((n + 63) / 64);
-  for (int k0 = 0; k0 < n; k0 += GJB) {
-    const int nb = std::min(GJB, n - k0);
-    gj_diag_kernel<<<1, 1024, 0, s>>>(A, n, k0, nb, bad);
-    if (n > nb) {
-      gj_row_kernel<<<nbl, 256, 0, s>>>(A, n, k0, nb);
-      gj_update_kernel<<<dim3(nt, nt), 256, 0, s>>>(A, n, k0, nb);
-      gj_col_kernel<<<nbl, 256, 0, s>>>(A, n, k0, nb);
+// one launch of each kernel per block step for the whole batch (offs/ns
+// device arrays of nmat entries; offs == null: one matrix of order nmax)
+static void gj_batch(double *base, const long long *offs, const int *ns, int nmat, int nmax,
+                     int *bad, hipStream_t s) {
+  if (nmax <= 0 || nmat <= 0) return;
+  const unsigned nbl = (unsigned)((nmax + 255) / 256);
+  const unsigned nt = (unsigned)((nmax + 63) / 64);
+  for (int k0 = 0; k0 < nmax; k0 += GJB) {
+    gj_diag_kernel<<<dim3(1, 1, nmat), 1024, 0, s>>>(base, offs, ns, nmax, k0, bad);
+    if (nmax > GJB) {
+      gj_row_kernel<<<dim3(nbl, 1, nmat), 256, 0, s>>>(base, offs, ns, nmax, k0);
+      gj_update_kernel<<<dim3(nt, nt, nmat), 256, 0, s>>>(base, offs, ns, nmax, k0);
+      gj_col_kernel<<<dim3(nbl, 1, nmat), 256, 0, s>>>(base, offs, ns, nmax, k0);
     }
   }
+}
+
+void k_spd_inverse(double *A, int n, int *bad, hipStream_t s) {
+  gj_batch(A, nullptr, nullptr, 1, n, bad, s);
+}
+
+void k_spd_inverse_batch(double *base, const long long *offs, const int *ns, int nmat, int nmax,
+                         int *bad, hipStream_t s) {
+  gj_batch(base, offs, ns, nmat, nmax, bad, s);
 }
 
 void k_scatter_compact(const double *xc, long long N, const int *cp, const int *cidx, double *xt,

@@ -13,6 +13,10 @@
 #include <map>
 #include <numeric>
 #include <unordered_map>
+#include <atomic>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 #include "context.h"
 #include "geom.h"
@@ -48,6 +52,51 @@ struct PhaseClock {
   }
 };
 }  // namespace
+
+// Host threads for setup loops: IGAMG_HOST_THREADS, else the hardware count,
+// at most 16.
+static int host_threads() {
+  static const int n = [] {
+    const char *e = std::getenv("IGAMG_HOST_THREADS");
+    int v = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(16, v));
+  }();
+  return n;
+}
+
+// fn(i) for i in [0, n) on up to host_threads() threads (dynamic
+// assignment); the first exception thrown by fn is rethrown after all
+// threads have joined.
+template <class F>
+static void parallel_for(int n, F fn) {
+  const int nt = std::min(n, host_threads());
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex em;
+  auto work = [&] {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) return;
+      try {
+        fn(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(em);
+        if (!err) err = std::current_exception();
+        next.store(n);
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto &t : th) t.join();
+  if (err) std::rethrow_exception(err);
+}
 
 // ---------------------------------------------------------------------------
 // timing
@@ -375,9 +424,14 @@ struct SideEval {
 static void build_interfaces(Context &c, LevelData &L) {
   const int d = c.d, p = c.p, q = p + 1;
   GaussRule gq = gauss_rule(q);
-  std::unordered_map<unsigned long long, double> acc;
-  acc.reserve(1 << 16);
-  for (auto &f : c.ifaces) {
+  // one sparse accumulator per interface (interfaces in parallel); the
+  // per-interface sums are added in interface order below, so the result
+  // does not depend on the number of threads
+  std::vector<std::vector<std::pair<unsigned long long, double>>> per(c.ifaces.size());
+  parallel_for((int)c.ifaces.size(), [&](int fi) {
+    const Context::Iface &f = c.ifaces[fi];
+    std::unordered_map<unsigned long long, double> acc;
+    acc.reserve(1 << 12);
     const PatchDev &pk = L.pd[f.k], &pl = L.pd[f.l];
     int tk[2], tl[2], nt = 0;
     for (int g = 0; g < d; ++g)
@@ -551,18 +605,31 @@ static void build_interfaces(Context &c, LevelData &L) {
           acc[key] += v;
         }
       }
+    per[fi].assign(acc.begin(), acc.end());
+    std::sort(per[fi].begin(), per[fi].end());
+  });
+  std::vector<std::pair<unsigned long long, double>> all;
+  for (auto &v : per) all.insert(all.end(), v.begin(), v.end());
+  std::stable_sort(all.begin(), all.end(),
+                   [](const std::pair<unsigned long long, double> &a,
+                      const std::pair<unsigned long long, double> &b) { return a.first < b.first; });
+  std::vector<std::pair<unsigned long long, double>> ent;
+  ent.reserve(all.size());
+  for (auto &e : all) {
+    if (!ent.empty() && ent.back().first == e.first)
+      ent.back().second += e.second;
+    else
+      ent.push_back(e);
   }
   // CSR over torn rows (Dirichlet rows / columns dropped)
-  std::vector<std::pair<unsigned long long, double>> ent(acc.begin(), acc.end());
-  std::sort(ent.begin(), ent.end());
   L.if_ptr.assign(L.Ntorn + 1, 0);
   L.if_col.clear();
   L.if_val.clear();
   L.if_cross.clear();
+  std::vector<long long> offs(L.K);
+  for (int k = 0; k < L.K; ++k) offs[k] = L.pd[k].off;
   auto patch_of = [&](long long t) {
-    int k = 0;
-    while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
-    return k;
+    return (int)(std::upper_bound(offs.begin(), offs.end(), t) - offs.begin()) - 1;
   };
   for (auto &e : ent) {
     long long r = (long long)(e.first >> 32), cc = (long long)(e.first & 0xffffffffULL);
@@ -748,8 +815,16 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
     for (auto &m : members) all.insert(all.end(), m.begin(), m.end());
     rows = stencil_rows_host(c, L, st64, SP, all);
   }
-  size_t row0 = 0;
-  for (auto &m : members) {
+  // dense blocks of the pieces (pieces in parallel, kept in piece order)
+  std::vector<size_t> row0(members.size() + 1, 0);
+  for (size_t i = 0; i < members.size(); ++i) row0[i + 1] = row0[i] + members[i].size();
+  std::vector<std::vector<double>> dense(members.size());
+  parallel_for((int)members.size(), [&](int i) {
+    dense[i] = st64 ? dense_block_rows(c, L, members[i], rows.data() + row0[i] * SP, SP)
+                    : dense_block(c, L, members[i]);
+  });
+  for (size_t i = 0; i < members.size(); ++i) {
+    const std::vector<int> &m = members[i];
     PieceDev pc{};
     pc.n = (int)m.size();
     pc.inv_off = (long long)blocks.size();
@@ -761,9 +836,7 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
       for (int t : L.copies[ci]) cidx.push_back(t);
     }
     cp.push_back((int)cidx.size());
-    std::vector<double> A = st64 ? dense_block_rows(c, L, m, rows.data() + row0 * SP, SP)
-                                 : dense_block(c, L, m);
-    row0 += m.size();
+    std::vector<double> A = std::move(dense[i]);
     blocks.insert(blocks.end(), A.begin(), A.end());
     pcs.push_back(pc);
     L.max_piece = std::max(L.max_piece, pc.n);
@@ -777,7 +850,17 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
   L.d_piece_cidx = c.arena.upload(cidx, c.stream);
   // float64 inverses in place; float32 mode rounds them into their own array
   double *inv64 = c.arena.upload(blocks, c.stream);
-  for (const PieceDev &pc : pcs) k_spd_inverse(inv64 + pc.inv_off, pc.n, c.d_bad, c.stream);
+  {
+    std::vector<long long> offs;
+    std::vector<int> ns;
+    for (const PieceDev &pc : pcs) {
+      offs.push_back(pc.inv_off);
+      ns.push_back(pc.n);
+    }
+    long long *d_offs = c.arena.upload(offs, c.stream);
+    int *d_ns = c.arena.upload(ns, c.stream);
+    k_spd_inverse_batch(inv64, d_offs, d_ns, (int)pcs.size(), L.max_piece, c.d_bad, c.stream);
+  }
   if (c.fp32()) {
     L.a32.piece_inv = c.arena.alloc<float>(blocks.size());
     k_convert<double, float>(inv64, nullptr, L.a32.piece_inv, (long long)blocks.size(), 1, c.stream);
