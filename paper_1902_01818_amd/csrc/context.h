@@ -109,7 +109,29 @@ struct LevelData {
   std::vector<unsigned char> mask;          // 1 = free, 0 = Dirichlet
   std::vector<int> comp;                    // torn -> compact (-1 Dirichlet)
   std::vector<int> rep;                     // compact -> representative torn
-  std::vector<std::vector<int>> copies;     // compact -> all torn copies (conforming)
+  std::vector<int> copy_ptr, copy_idx;      // compact -> all torn copies (CSR; conforming
+                                            // glue gives several, SIPG exactly one)
+  struct Span {
+    const int *b, *e;
+    const int *begin() const { return b; }
+    const int *end() const { return e; }
+    size_t size() const { return (size_t)(e - b); }
+  };
+  // patch holding torn index t (patches are stored in offset order)
+  int patch_of(long long t) const {
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (pd[mid].off <= t)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    return lo;
+  }
+  Span copies(long long ci) const {
+    return Span{copy_idx.data() + copy_ptr[ci], copy_idx.data() + copy_ptr[ci + 1]};
+  }
   // element tables of this level (distinct element counts share entries)
   std::vector<double> tabB, tabD;
   double *d_tabB = nullptr, *d_tabD = nullptr;

@@ -394,23 +394,32 @@ static void build_level_dofs(Context &c, LevelData &L, const std::vector<std::ar
   // compact numbering
   L.comp.assign(L.Ntorn, -1);
   L.rep.clear();
-  L.copies.clear();
   std::vector<int> gcomp(ngroups, -1);
   for (long long t = 0; t < L.Ntorn; ++t) {
     if (!L.mask[t]) continue;
     int g = group[t];
     if (g >= 0 && gcomp[g] >= 0) {
       L.comp[t] = gcomp[g];
-      L.copies[gcomp[g]].push_back((int)t);
       continue;
     }
     int ci = (int)L.rep.size();
     L.comp[t] = ci;
     L.rep.push_back((int)t);
-    L.copies.push_back({(int)t});
     if (g >= 0) gcomp[g] = ci;
   }
   L.N = (long long)L.rep.size();
+  // copies of every compact unknown (CSR, increasing torn index: the
+  // representative first)
+  L.copy_ptr.assign(L.N + 1, 0);
+  for (long long t = 0; t < L.Ntorn; ++t)
+    if (L.comp[t] >= 0) ++L.copy_ptr[L.comp[t] + 1];
+  for (long long ci = 0; ci < L.N; ++ci) L.copy_ptr[ci + 1] += L.copy_ptr[ci];
+  L.copy_idx.assign(L.copy_ptr[L.N], 0);
+  {
+    std::vector<int> fillp(L.copy_ptr.begin(), L.copy_ptr.end() - 1);
+    for (long long t = 0; t < L.Ntorn; ++t)
+      if (L.comp[t] >= 0) L.copy_idx[fillp[L.comp[t]]++] = (int)t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -657,12 +666,11 @@ static std::vector<double> dense_block(const Context &c, const LevelData &L,
   const int n = (int)comps.size();
   std::unordered_map<long long, int> loc;  // torn copy -> local index
   for (int a = 0; a < n; ++a)
-    for (int t : L.copies[comps[a]]) loc[t] = a;
+    for (int t : L.copies(comps[a])) loc[t] = a;
   std::vector<double> A((size_t)n * n, 0.0);
   for (int a = 0; a < n; ++a)
-    for (int t1 : L.copies[comps[a]]) {
-      int k = 0;
-      while (k + 1 < L.K && L.pd[k + 1].off <= t1) ++k;
+    for (int t1 : L.copies(comps[a])) {
+      const int k = L.patch_of(t1);
       const PatchDev &pt = L.pd[k];
       long long lc = t1 - pt.off;
       int i[3] = {(int)(lc % pt.n[0]), (int)((lc / pt.n[0]) % pt.n[1]),
@@ -737,8 +745,7 @@ static std::vector<double> dense_block_rows(const Context &c, const LevelData &L
   std::vector<double> A((size_t)n * n, 0.0);
   for (int a = 0; a < n; ++a) {
     const long long t1 = L.rep[comps[a]];
-    int k = 0;
-    while (k + 1 < L.K && L.pd[k + 1].off <= t1) ++k;
+    const int k = L.patch_of(t1);
     const PatchDev &pt = L.pd[k];
     const long long lc = t1 - pt.off;
     const int ix = (int)(lc % pt.n[0]), iy = (int)(lc / pt.n[0]);
@@ -775,8 +782,7 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
   std::vector<std::vector<int>> members;
   for (long long ci = 0; ci < L.N; ++ci) {
     long long t = L.rep[ci];
-    int k = 0;
-    while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
+    const int k = L.patch_of(t);
     const PatchDev &pt = L.pd[k];
     long long lc = t - pt.off;
     int i[3] = {(int)(lc % pt.n[0]), (int)((lc / pt.n[0]) % pt.n[1]),
@@ -833,7 +839,7 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
     for (int ci : m) {
       idx.push_back(L.rep[ci]);
       cp.push_back((int)cidx.size());
-      for (int t : L.copies[ci]) cidx.push_back(t);
+      for (int t : L.copies(ci)) cidx.push_back(t);
     }
     cp.push_back((int)cidx.size());
     std::vector<double> A = std::move(dense[i]);
@@ -1141,7 +1147,7 @@ static void build_maps(Context &c, const LevelData &L, int **d_cp, int **d_cidx)
   std::vector<int> cp, cidx;
   for (long long ci = 0; ci < L.N; ++ci) {
     cp.push_back((int)cidx.size());
-    for (int t : L.copies[ci]) cidx.push_back(t);
+    for (int t : L.copies(ci)) cidx.push_back(t);
   }
   cp.push_back((int)cidx.size());
   *d_cp = c.arena.upload(cp, c.stream);
@@ -1291,8 +1297,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       if (L.if_ptr.empty()) continue;
       for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e) {
         if (L.if_cross[e]) continue;
-        int k = 0;
-        while (k + 1 < L.K && L.pd[k + 1].off <= t) ++k;
+        const int k = L.patch_of(t);
         const PatchDev &pt = L.pd[k];
         long long a = t - pt.off, b = L.if_col[e] - pt.off;
         int slot = 0, m = 1;
@@ -1360,8 +1365,8 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     // glue groups
     std::vector<int> gp{0}, gi;
     for (long long ci = 0; ci < L.N; ++ci)
-      if (L.copies[ci].size() > 1) {
-        for (int t : L.copies[ci]) gi.push_back(t);
+      if (L.copies(ci).size() > 1) {
+        for (int t : L.copies(ci)) gi.push_back(t);
         gp.push_back((int)gi.size());
       }
     L.n_glue = (int)gp.size() - 1;
