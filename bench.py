@@ -161,6 +161,8 @@ def main():
         out = {"c4": c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)}
         print("bench: 64-column p = 6 batch timed (float32 cycle)", file=sys.stderr, flush=True)
         out["c4_bf16_scms"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="bf16", steps=1)
+        print("bench: 64-column p = 6 batch timed (bf16 SCMS)", file=sys.stderr, flush=True)
+        out["c4_fp64"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp64", steps=1)
         print(json.dumps(out))
         return
 
@@ -324,6 +326,11 @@ def main():
                                        steps=1, outer="ir")
         print("bench: 64-column p = 6 batch timed (float64 iterative refinement)", file=sys.stderr,
               flush=True)
+        line["c4_fp64"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp64", steps=1)
+        line["c4_fp64"]["mixed_speedup"] = {
+            k: line[k]["solves_per_s"] / line["c4_fp64"]["solves_per_s"]
+            for k in ("c4", "c4_bf16_scms", "c4_refinement")}
+        print("bench: 64-column p = 6 batch timed (float64 cycle)", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
