@@ -94,3 +94,32 @@ def test_problem_size_matches_oracle_numbering(ig):
                                       conforming=cfg["conforming"]).N
         assert n == n_expected
         assert lv == len(level_elements(cfg["elems"]))
+
+
+def test_binding_constants_match_header(ig):
+    """The binding's option and status values are the header's #defines."""
+    import re
+    text = open(os.path.join(ROOT, "include", "igamg.h")).read()
+    defs = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"#define (IGAMG_\w+) \(?(-?\d+)\)?", text)}
+    assert (ig.OK, ig.EINVAL, ig.EUNSUPPORTED, ig.ENOMEM, ig.EHIP, ig.ENOCONV) == tuple(
+        defs["IGAMG_" + k] for k in ("OK", "EINVAL", "EUNSUPPORTED", "ENOMEM", "EHIP", "ENOCONV"))
+    assert (ig.SIPG, ig.CONFORMING) == (defs["IGAMG_SIPG"], defs["IGAMG_CONFORMING"])
+    assert ig.SMOOTHERS == {"hybrid": defs["IGAMG_SMOOTHER_HYBRID"],
+                            "scms": defs["IGAMG_SMOOTHER_SCMS"], "gs": defs["IGAMG_SMOOTHER_GS"]}
+    assert ig.PRECISIONS == {"fp64": defs["IGAMG_FP64"], "fp32": defs["IGAMG_FP32"],
+                             "bf16": defs["IGAMG_BF16_SCMS"]}
+    assert ig.OUTERS == {"pcg": defs["IGAMG_OUTER_PCG"], "mg": defs["IGAMG_OUTER_MG"],
+                         "fcg": defs["IGAMG_OUTER_FCG"], "ir": defs["IGAMG_OUTER_IR"]}
+    assert ig.APPLIES == {"auto": defs["IGAMG_APPLY_AUTO"], "sumfact": defs["IGAMG_APPLY_SUMFACT"],
+                          "rows": defs["IGAMG_APPLY_ROWS"]}
+
+
+def test_options_struct_layout_matches_header(ig):
+    """The ctypes mirror of igamg_options lists the header's fields in order."""
+    import re
+    text = open(os.path.join(ROOT, "include", "igamg.h")).read()
+    body = text[text.index("typedef struct {\n  int discretization;"):]
+    body = body[:body.index("} igamg_options;")]
+    fields = re.findall(r"^\s+(?:int|double) (\w+);", body, re.M)
+    assert fields == [f for f, _ in ig.Options._fields_]

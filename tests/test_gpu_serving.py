@@ -103,3 +103,19 @@ def test_request_larger_than_budget_is_rejected():
     recs, summ, _ = _run(problems, slots=2, budget=int((small + big) / 2))
     codes = sorted(r[1]["status"] for r in recs)
     assert codes == [-3, 0]   # IGAMG_ENOMEM for the request that can never fit
+
+
+def test_float32_requests_rejected_at_submission():
+    """Float32 requests are refused before they are queued (the server runs
+    float64 requests only); no solve is started."""
+    from paper_1902_01818_amd import igamg
+    pb = serve.prepare(_specs()[:1], "fp32", "fcg")[0]
+    srv = igamg.Server(slots=1, memory_budget=1 << 30)
+    try:
+        with pytest.raises(igamg.IgamgError) as e:
+            srv.submit(pb["corners"], pb["elems"], pb["p"], pb["rhs"], sigma=pb["sigma"],
+                       **pb["opts"])
+        assert e.value.code == igamg.EUNSUPPORTED
+        assert srv.status()["queued"] == 0
+    finally:
+        srv.close()
