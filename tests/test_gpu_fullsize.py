@@ -62,3 +62,28 @@ def test_full_batch_cycle_staged_smoother(full_pair):
     for j in (0, nb - 1):
         assert rel_err(Z[j], ob.vcycle(F[j])) < 1e-10, j
     sb.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_full_batch_low_precision_staged_smoother(full_pair, precision):
+    """64 right-hand sides at the full size in float32 (and with bf16 SCMS
+    operands): the patch interiors go through the four-stage batched form in
+    that arithmetic.  float32: two columns of one cycle match the oracle's
+    float64 cycle at the float32 cycle bar (2e-5); both: every column of a
+    flexible CG solve meets the float64 true residual 1e-8."""
+    cfg, ob, sv = full_pair
+    nb = 64
+    sb = gpu_solver(cfg, coarse_min=2 if sv.n_levels == 6 else 8, max_rhs=nb,
+                    precision=precision, outer="fcg")
+    F = np.stack([workloads.normal_rhs(ob.N, 3000 + j) for j in range(nb)])
+    if precision == "fp32":
+        Z = sb.vcycle(torch.from_numpy(F).cuda(), torch.zeros(nb * ob.N, dtype=torch.float64).cuda())
+        Z = Z.cpu().numpy().reshape(nb, ob.N)
+        for j in (0, nb - 1):
+            assert rel_err(Z[j], ob.vcycle(F[j])) < 2e-5, j
+    U, info = sb.solve(torch.from_numpy(F).cuda(), tol=1e-8, maxit=200)
+    U = U.cpu().numpy().reshape(nb, ob.N)
+    assert all(i["converged"] for i in info)
+    for j in (0, nb - 1):
+        assert np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j]) <= 1.05e-8, j
+    sb.close()
