@@ -867,9 +867,9 @@ __global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntil
 // Fast-diagonalization step of the subspace corrected mass smoother on the
 // matrix cores, fused form (Fd2Item): a block of 256 threads owns 16 rows of
 // the output and computes Z = L[rows, :] M1 (Z kept in LDS), then R = Z M2,
-// then the item's epilogue.  B operands are streamed through LDS (all of B
-// in one round of loads when it fits, else chunks of KC rows with the next
-// chunk held in registers).  Wave w owns the 16-column tiles w, w+4, ...,
+// then the item's epilogue.  B operands are streamed through LDS in chunks
+// of KC rows, the next chunk held in registers.  Wave w owns the 16-column
+// tiles w, w+4, ...,
 // w+4(NJ-1) of the block; a k-step issues one MFMA per tile, the A fragment
 // shared by the tiles:
 //   float64: v_mfma_f64_16x16x4f64 on the stored operands;
@@ -961,62 +961,43 @@ __device__ inline void mfma_rows(const T *sA, int lda, int ka, const T *sB, int 
   }
 }
 
-// acc += A[16 x K] B[K x N]: B streamed from global memory through LDS, the
-// whole of it in one round of loads (FULL, K padded to the MFMA k <= WB) or in
-// chunks of KC rows with the next chunk held in registers.  Rows of B past K
-// and columns past N are stored as zero; A must be zero in columns K..Kp-1.
-template <typename T, bool BF, int NJ, bool FULL>
+// acc += A[16 x K] B[K x N]: B streamed from global memory through LDS in
+// chunks of KC rows, the next chunk held in registers while the current one
+// is multiplied (measured faster than staging all of B at once, which leaves
+// one block per CU).  Rows of B past K and columns past N are stored as zero;
+// A must be zero in columns K..Kp-1.
+template <typename T, bool BF, int NJ>
 __device__ inline void rowblock_mfma(const T *sA, int lda, const T *__restrict__ B, long long b_r,
                                      int K, int N, T *sM, typename MfAcc<T>::type acc[NJ]) {
   constexpr int WB = Fd2mShape<NJ, BF>::WB, LDB = Fd2mShape<NJ, BF>::LDB, KS = MfK<BF>::KS;
+  constexpr int KC = Fd2mShape<NJ, BF>::KC;
+  constexpr int LPT = KC * WB / 256;
   const int tid = threadIdx.x;
   const int Kp = (K + KS - 1) / KS * KS;
-  if constexpr (FULL) {
-    constexpr int MAXL = WB * WB / 256;
-    T pre[MAXL];
-    __syncthreads();  // sM and A complete / free
+  T pre[LPT];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int x = 0; x < MAXL; ++x) {
+    for (int x = 0; x < LPT; ++x) {
       const int e = tid + 256 * x;
       const int kk = e / WB, col = e % WB;
-      pre[x] = (kk < K && col < N) ? B[(long long)kk * b_r + col] : (T)0;
+      pre[x] = (k0 + kk < K && col < N) ? B[(long long)(k0 + kk) * b_r + col] : (T)0;
     }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < Kp; k0 += KC) {
+    __syncthreads();
 #pragma unroll
-    for (int x = 0; x < MAXL; ++x) {
+    for (int x = 0; x < LPT; ++x) {
       const int e = tid + 256 * x;
-      const int kk = e / WB, col = e % WB;
-      if (kk < Kp) sM[kk * LDB + col] = pre[x];
+      sM[(e / WB) * LDB + e % WB] = pre[x];
     }
     __syncthreads();
-    mfma_rows<T, BF, NJ>(sA, lda, 0, sM, Kp, N, acc);
-  } else {
-    constexpr int KC = Fd2mShape<NJ, BF>::KC;
-    constexpr int LPT = KC * WB / 256;
-    T pre[LPT];
-    auto gload = [&](int k0) {
-#pragma unroll
-      for (int x = 0; x < LPT; ++x) {
-        const int e = tid + 256 * x;
-        const int kk = e / WB, col = e % WB;
-        pre[x] = (k0 + kk < K && col < N) ? B[(long long)(k0 + kk) * b_r + col] : (T)0;
-      }
-    };
-    gload(0);
-    for (int k0 = 0; k0 < Kp; k0 += KC) {
-      __syncthreads();
-#pragma unroll
-      for (int x = 0; x < LPT; ++x) {
-        const int e = tid + 256 * x;
-        sM[(e / WB) * LDB + e % WB] = pre[x];
-      }
-      __syncthreads();
-      if (k0 + KC < Kp) gload(k0 + KC);
-      mfma_rows<T, BF, NJ>(sA, lda, k0, sM, min(KC, Kp - k0), N, acc);
-    }
+    if (k0 + KC < Kp) gload(k0 + KC);
+    mfma_rows<T, BF, NJ>(sA, lda, k0, sM, min(KC, Kp - k0), N, acc);
   }
 }
 
-template <typename T, bool BF, int NJ, bool FULL>
+template <typename T, bool BF, int NJ>
 __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int lda) {
   using A4 = typename MfAcc<T>::type;
   constexpr int LDZ = Fd2mShape<NJ, BF>::LDZ;
@@ -1047,7 +1028,7 @@ __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int 
   A4 acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = A4{0, 0, 0, 0};
-  rowblock_mfma<T, BF, NJ, FULL>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
+  rowblock_mfma<T, BF, NJ>(sL, lda, M1, it.m1_r, it.K1, it.N, sM, acc);
   const int lane = tid & 63, w = tid >> 6, c = lane & 15, q = lane >> 4;
   // Z (zero in the columns past N) becomes the A operand of the second product
 #pragma unroll
@@ -1056,7 +1037,7 @@ __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int 
     for (int r = 0; r < 4; ++r) sZ[mf_row<T>(q, r) * LDZ + 16 * (w + 4 * j) + c] = acc[j][r];
     acc[j] = A4{0, 0, 0, 0};
   }
-  rowblock_mfma<T, BF, NJ, FULL>(sZ, LDZ, it.M2, it.m2_r, it.N, it.N, sM, acc);
+  rowblock_mfma<T, BF, NJ>(sZ, LDZ, it.M2, it.m2_r, it.N, it.N, sM, acc);
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int col = 16 * (w + 4 * j) + c;
@@ -1940,31 +1921,19 @@ template void k_stencil_apply<float>(Context &, LevelData &, const LevelArrays<f
                                      const float *, const float *, const float *, float, float,
                                      float *, int);
 
-template <typename T, bool BF, int NJ, bool FULL>
-static void launch_fd2m_as(Context &c, LevelData &L, int stage, int nrhs, int lda, size_t lds) {
+template <typename T, bool BF, int NJ>
+static void launch_fd2m(Context &c, LevelData &L, int stage, int nrhs) {
+  constexpr int LDB = Fd2mShape<NJ, BF>::LDB, LDZ = Fd2mShape<NJ, BF>::LDZ;
+  constexpr int KC = Fd2mShape<NJ, BF>::KC;
+  const int lda = (L.fd_K1 + 31) / 32 * 32 + 2;
+  const size_t lds = (size_t)(16 * lda + 16 * LDZ + KC * LDB) * sizeof(T);
+  if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
   static const hipError_t lds_set =
-      hipFuncSetAttribute((const void *)fd2m_kernel<T, BF, NJ, FULL>,
+      hipFuncSetAttribute((const void *)fd2m_kernel<T, BF, NJ>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   HIPCHK(lds_set);
   dim3 grid(nrhs, (L.fd_rows + 15) / 16, L.n_fd);
-  fd2m_kernel<T, BF, NJ, FULL><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], lda);
-}
-
-template <typename T, bool BF, int NJ>
-static void launch_fd2m(Context &c, LevelData &L, int stage, int nrhs) {
-  constexpr int WB = Fd2mShape<NJ, BF>::WB, LDB = Fd2mShape<NJ, BF>::LDB, LDZ = Fd2mShape<NJ, BF>::LDZ;
-  constexpr int KC = Fd2mShape<NJ, BF>::KC, KS = MfK<BF>::KS;
-  const int lda = (L.fd_K1 + 31) / 32 * 32 + 2;
-  const size_t base = (size_t)(16 * lda + 16 * LDZ) * sizeof(T);
-  const int kmax = (std::max(L.fd_K1, L.fd_N) + KS - 1) / KS * KS;
-  const size_t lds_full = base + (size_t)kmax * LDB * sizeof(T);
-  if (NJ <= 2 && kmax <= WB && lds_full <= 150 * 1024) {
-    launch_fd2m_as<T, BF, NJ, NJ <= 2>(c, L, stage, nrhs, lda, lds_full);
-    return;
-  }
-  const size_t lds = base + (size_t)KC * LDB * sizeof(T);
-  if (lds > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
-  launch_fd2m_as<T, BF, NJ, false>(c, L, stage, nrhs, lda, lds);
+  fd2m_kernel<T, BF, NJ><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], lda);
 }
 
 #ifndef FD_STAGED_MIN
