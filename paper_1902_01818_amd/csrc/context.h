@@ -78,8 +78,9 @@ struct Lent {
 };
 
 struct GsClass {
-  GsTile *tiles;
-  int count;
+  GsTile *tiles = nullptr;    // 2D tiles
+  GsTile3 *tiles3 = nullptr;  // 3D tiles
+  int count = 0;
 };
 
 // Arrays of one level in one arithmetic precision.  Work vectors hold a batch
@@ -158,6 +159,7 @@ struct LevelData {
   int n_stiles = 0;
   std::vector<GsClass> gs;  // classes in key order
   GsTile *d_atiles = nullptr;  // every Gauss-Seidel tile of the level (stored-row operator)
+  GsTile3 *d_atiles3 = nullptr;  // the same for 3D patches
   int n_atiles = 0;
   // the cycle's residuals on this level use the stored rows (k_stencil_apply)
   bool st_apply = false;

@@ -83,6 +83,15 @@ struct GsTile {
   int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
 };
 
+// Gauss-Seidel tile of a 3D patch (2(p+1) unknowns per direction), with the
+// fields of its patch that the kernels need.
+struct GsTile3 {
+  long long off;     // patch offset in the level vector
+  int n[3];          // patch tensor extents
+  int i0[3];         // first unknown of the tile
+  int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
+};
+
 // Two chained products on a block of 16 rows (fast-diagonalization step of the
 // subspace corrected mass smoother): Z = L[rows, :] M1, R = Z M2, then either
 // O[rows, :] = R / (sigma + lam_r[row] + lam_c[col]) (lam_r != null) or

@@ -864,6 +864,278 @@ __global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntil
 }
 
 // ---------------------------------------------------------------------------
+// 3D patches.  A tile holds TT^3 unknowns (TT = 2(p+1)); its u window with a
+// halo of p on every side sits in LDS.  Stencil rows ((2p+1)^3 entries padded
+// to 16-lane groups) are read by one 16-lane group per row; slot k of a row
+// is the neighbour (k mod S1 - p, k / S1 mod S1 - p, k / S1^2 - p).
+// ---------------------------------------------------------------------------
+template <int P>
+struct Tile3 {
+  static constexpr int Q1 = P + 1, TT = 2 * Q1, W = TT + 2 * P;
+  static constexpr int NT = TT * TT * TT, NW = W * W * W;
+  static constexpr int S1 = 2 * P + 1, S = S1 * S1 * S1;
+  static constexpr int C = (S + 15) / 16, SP = 16 * C;
+  static constexpr int NPH = Q1 * Q1 * Q1;
+  // window offset of stencil slot k (0 for the zero padding slots)
+  __device__ static int slot_off(int k) {
+    return k < S ? ((k / (S1 * S1) - P) * W + (k / S1 % S1 - P)) * W + (k % S1 - P) : 0;
+  }
+};
+
+// window of u (halo p, zero outside the patch) into LDS
+template <typename T, int P>
+__device__ inline void load_window3(const GsTile3 &tl, const T *u, T *sU, int tid, int nthr) {
+  using G = Tile3<P>;
+  const int wx0 = tl.i0[0] - P, wy0 = tl.i0[1] - P, wz0 = tl.i0[2] - P;
+  for (int i = tid; i < G::NW; i += nthr) {
+    const int gx = wx0 + i % G::W, gy = wy0 + i / G::W % G::W, gz = wz0 + i / (G::W * G::W);
+    const bool ok = gx >= 0 && gx < tl.n[0] && gy >= 0 && gy < tl.n[1] && gz >= 0 && gz < tl.n[2];
+    sU[i] = ok ? u[tl.off + ((long long)gz * tl.n[1] + gy) * tl.n[0] + gx] : (T)0;
+  }
+}
+
+// Multicolour Gauss-Seidel on 3D tiles: one block of 8 row groups (16 lanes
+// each) per tile and right-hand side.  Phase s of the sweep updates the eight
+// unknowns of the tile whose index mod (p+1) is (s mod Q1, s / Q1 mod Q1,
+// s / Q1^2) -- one colour class of the ordering -- and a block barrier
+// separates the phases.  f minus the cross-patch couplings (values of
+// neighbouring patches, another patch colour, constant during the launch) and
+// 1/a_ii sit in LDS.  grid.x = right-hand side, grid.y = tile.
+template <typename T, int P>
+__global__ __launch_bounds__(128) void gs3d_kernel(const GsTile3 *tiles, const T *__restrict__ st,
+                                                   const T *__restrict__ invd,
+                                                   const int *__restrict__ cx_li,
+                                                   const int *__restrict__ cx_col,
+                                                   const T *__restrict__ cx_val,
+                                                   const T *__restrict__ f, T *u, int backward,
+                                                   long long vs) {
+  using G = Tile3<P>;
+  constexpr int Q1 = G::Q1, TT = G::TT, W = G::W, C = G::C, SP = G::SP, NPH = G::NPH;
+  __shared__ T sU[G::NW];
+  __shared__ T sB[G::NT];
+  __shared__ T sD[G::NT];
+  const GsTile3 tl = tiles[blockIdx.y];
+  f += (long long)blockIdx.x * vs;
+  u += (long long)blockIdx.x * vs;
+  const int tid = threadIdx.x;
+  const int nx = tl.n[0], ny = tl.n[1], nz = tl.n[2];
+  const int x0 = tl.i0[0], y0 = tl.i0[1], z0 = tl.i0[2];
+  load_window3<T, P>(tl, u, sU, tid, 128);
+  for (int i = tid; i < G::NT; i += 128) {
+    const int ix = x0 + i % TT, iy = y0 + i / TT % TT, iz = z0 + i / (TT * TT);
+    const bool ok = ix < nx && iy < ny && iz < nz;
+    const long long t = tl.off + ((long long)iz * ny + iy) * nx + ix;
+    sB[i] = ok ? f[t] : (T)0;
+    sD[i] = ok ? invd[t] : (T)0;
+  }
+  __syncthreads();
+  // cross couplings by the first wave (a fixed order of the additions)
+  if (tid < 64)
+    for (int e = tid; e < tl.cx_n; e += 64) {
+      const int q = tl.cx_off + e;
+      unsafeAtomicAdd(&sB[cx_li[q]], -cx_val[q] * u[cx_col[q]]);
+    }
+  const int grp = tid >> 4, l16 = tid & 15;
+  const int ax = (grp & 1) * Q1, ay = (grp >> 1 & 1) * Q1, az = (grp >> 2) * Q1;
+  int soff[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) soff[c] = G::slot_off(l16 + 16 * c);
+  // row of this group in phase s; rows outside the patch read the tile
+  // origin's row and are not updated
+  auto row_of = [&](int s, int &wi, int &li, bool &ok) {
+    const int ph = backward ? NPH - 1 - s : s;
+    const int dx = ph % Q1 + ax, dy = ph / Q1 % Q1 + ay, dz = ph / (Q1 * Q1) + az;
+    ok = x0 + dx < nx && y0 + dy < ny && z0 + dz < nz;
+    wi = ((dz + P) * W + dy + P) * W + dx + P;
+    li = (dz * TT + dy) * TT + dx;
+    const long long t = ok ? tl.off + ((long long)(z0 + dz) * ny + y0 + dy) * nx + x0 + dx
+                           : tl.off + ((long long)z0 * ny + y0) * nx + x0;
+    return st + t * SP + l16;
+  };
+  T a[C], an[C];
+  {
+    int wi, li;
+    bool ok;
+    const T *sr = row_of(0, wi, li, ok);
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] = sr[16 * c];
+  }
+  __syncthreads();  // cross sums complete
+  for (int s = 0; s < NPH; ++s) {
+    int wi, li;
+    bool ok;
+    row_of(s, wi, li, ok);
+    if (s + 1 < NPH) {
+      int wn, ln;
+      bool okn;
+      const T *sr = row_of(s + 1, wn, ln, okn);
+#pragma unroll
+      for (int c = 0; c < C; ++c) an[c] = sr[16 * c];
+    }
+    T acc0 = 0, acc1 = 0;
+#pragma unroll
+    for (int c = 0; c < C; c += 2) acc0 += a[c] * sU[wi + soff[c]];
+#pragma unroll
+    for (int c = 1; c < C; c += 2) acc1 += a[c] * sU[wi + soff[c]];
+    const T acc = row16_scan(acc0 + acc1);
+    if (l16 == 15 && ok) sU[wi] = sU[wi] + (sB[li] - acc) * sD[li];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] = an[c];
+  }
+  for (int i = tid; i < G::NT; i += 128) {
+    const int dx = i % TT, dy = i / TT % TT, dz = i / (TT * TT);
+    if (x0 + dx < nx && y0 + dy < ny && z0 + dz < nz)
+      u[tl.off + ((long long)(z0 + dz) * ny + y0 + dy) * nx + x0 + dx] =
+          sU[((dz + P) * W + dy + P) * W + dx + P];
+  }
+}
+
+// Operator by the stored rows on 3D tiles: r = mask (beta fw.*f + alpha (S u
+// + X u)) as in 2D; one block of 16 row groups per tile and right-hand side.
+// grid.x = tile, grid.y = right-hand side.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void sp3d_kernel(const GsTile3 *tiles, const T *__restrict__ st,
+                                                   const int *__restrict__ cx_li,
+                                                   const int *__restrict__ cx_col,
+                                                   const T *__restrict__ cx_val,
+                                                   const unsigned char *__restrict__ mask,
+                                                   const T *__restrict__ u,
+                                                   const T *__restrict__ f,
+                                                   const T *__restrict__ fw, T beta, T alpha,
+                                                   T *__restrict__ r, long long vs) {
+  using G = Tile3<P>;
+  constexpr int TT = G::TT, W = G::W, C = G::C, SP = G::SP, NT = G::NT;
+  __shared__ T sU[G::NW];
+  __shared__ T sX[NT];
+  const GsTile3 tl = tiles[blockIdx.x];
+  const long long zo = (long long)blockIdx.y * vs;
+  u += zo;
+  const int tid = threadIdx.x;
+  const int nx = tl.n[0], ny = tl.n[1], nz = tl.n[2];
+  const int x0 = tl.i0[0], y0 = tl.i0[1], z0 = tl.i0[2];
+  load_window3<T, P>(tl, u, sU, tid, 256);
+  for (int i = tid; i < NT; i += 256) sX[i] = (T)0;
+  __syncthreads();
+  if (tid < 64)
+    for (int e = tid; e < tl.cx_n; e += 64) {
+      const int q = tl.cx_off + e;
+      unsafeAtomicAdd(&sX[cx_li[q]], cx_val[q] * u[cx_col[q]]);
+    }
+  const int g = tid >> 4, l16 = tid & 15;
+  int soff[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) soff[c] = G::slot_off(l16 + 16 * c);
+  auto row_ptr = [&](int li) {
+    const int dx = li % TT, dy = li / TT % TT, dz = li / (TT * TT);
+    const bool ok = x0 + dx < nx && y0 + dy < ny && z0 + dz < nz;
+    const long long t = ok ? tl.off + ((long long)(z0 + dz) * ny + y0 + dy) * nx + x0 + dx
+                           : tl.off + ((long long)z0 * ny + y0) * nx + x0;
+    return st + t * SP + l16;
+  };
+  T a[C], an[C];
+  {
+    const T *sr = row_ptr(g);
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] = sr[16 * c];
+  }
+  __syncthreads();  // cross sums complete
+  for (int li = g; li < NT; li += 16) {
+    if (li + 16 < NT) {
+      const T *sr = row_ptr(li + 16);
+#pragma unroll
+      for (int c = 0; c < C; ++c) an[c] = sr[16 * c];
+    }
+    const int dx = li % TT, dy = li / TT % TT, dz = li / (TT * TT);
+    if (x0 + dx < nx && y0 + dy < ny && z0 + dz < nz) {
+      const int wi = ((dz + P) * W + dy + P) * W + dx + P;
+      T acc0 = 0, acc1 = 0;
+#pragma unroll
+      for (int c = 0; c < C; c += 2) acc0 += a[c] * sU[wi + soff[c]];
+#pragma unroll
+      for (int c = 1; c < C; c += 2) acc1 += a[c] * sU[wi + soff[c]];
+      const T acc = row16_scan(acc0 + acc1);
+      if (l16 == 15) sX[li] += acc;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] = an[c];
+  }
+  __syncthreads();
+  for (int li = tid; li < NT; li += 256) {
+    const int dx = li % TT, dy = li / TT % TT, dz = li / (TT * TT);
+    if (x0 + dx >= nx || y0 + dy >= ny || z0 + dz >= nz) continue;
+    const long long t = tl.off + ((long long)(z0 + dz) * ny + y0 + dy) * nx + x0 + dx;
+    T v = alpha * sX[li];
+    if (f) v += beta * (fw ? fw[t] : (T)1) * f[zo + t];
+    r[zo + t] = mask[t] ? v : (T)0;
+  }
+}
+
+// Transfer between dyadic 3D levels, one output entry per thread: the
+// tensor product of the three 1D band rows (prolongation rows of the fine
+// level's embedding, or its columns for the restriction) applied to the input
+// patch tensor.  Restriction weights the fine input (consistent ->
+// distributed) and writes the masked coarse result; prolongation adds into
+// the free fine entries.  grid.y = right-hand side.
+template <typename T, bool RESTRICT>
+__global__ __launch_bounds__(256) void transfer3d_kernel(
+    const PatchDev *__restrict__ pd_in, const PatchDev *__restrict__ pd_out,
+    const PatchDev *__restrict__ pd_fine, int K, long long n_out, const int *__restrict__ lo,
+    const T *__restrict__ val, int W, const T *__restrict__ in, const T *__restrict__ win,
+    const unsigned char *__restrict__ mask_out, T *out, T *zero_out, long long vs_in,
+    long long vs_out) {
+  const long long t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= n_out) return;
+  in += (long long)blockIdx.y * vs_in;
+  const long long to = (long long)blockIdx.y * vs_out + t;
+  int k = 0, hi = K - 1;
+  while (k < hi) {  // last patch with off <= t
+    const int mid = (k + hi + 1) >> 1;
+    if (pd_out[mid].off <= t)
+      k = mid;
+    else
+      hi = mid - 1;
+  }
+  const PatchDev &po = pd_out[k], &pi = pd_in[k], &pf = pd_fine[k];
+  long long loc = t - po.off;
+  const int ox = (int)(loc % po.n[0]);
+  loc /= po.n[0];
+  const int oy = (int)(loc % po.n[1]), oz = (int)(loc / po.n[1]);
+  if (!RESTRICT && !mask_out[t]) return;
+  const int rx = (RESTRICT ? pf.xr[0] : pf.xp[0]) + ox;
+  const int ry = (RESTRICT ? pf.xr[1] : pf.xp[1]) + oy;
+  const int rz = (RESTRICT ? pf.xr[2] : pf.xp[2]) + oz;
+  const int lx = lo[rx], ly = lo[ry], lz = lo[rz];
+  T sum = 0;
+  for (int c = 0; c < W; ++c) {
+    const int jz = lz + c;
+    const T vz = val[(long long)rz * W + c];
+    if (jz >= pi.n[2] || vz == (T)0) continue;
+    for (int b = 0; b < W; ++b) {
+      const int jy = ly + b;
+      const T vy = val[(long long)ry * W + b];
+      if (jy >= pi.n[1] || vy == (T)0) continue;
+      T sx = 0;
+      for (int a = 0; a < W; ++a) {
+        const int jx = lx + a;
+        if (jx >= pi.n[0]) break;
+        const long long j = pi.off + ((long long)jz * pi.n[1] + jy) * pi.n[0] + jx;
+        T v = in[j];
+        if (RESTRICT) v *= win[j];
+        sx += val[(long long)rx * W + a] * v;
+      }
+      sum += vz * vy * sx;
+    }
+  }
+  if (RESTRICT) {
+    out[to] = mask_out[t] ? sum : (T)0;
+    if (zero_out) zero_out[to] = 0;
+  } else {
+    out[to] += sum;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fast-diagonalization step of the subspace corrected mass smoother on the
 // matrix cores, fused form (Fd2Item): a block of 256 threads owns 16 rows of
 // the output and computes Z = L[rows, :] M1 (Z kept in LDS), then R = Z M2,
@@ -1849,6 +2121,14 @@ static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backwa
       backward ? 1 : 0, L.Ntorn, nrhs);
 }
 
+template <typename T, int P>
+static void launch_gs3d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
+  LevelArrays<T> &A = L.arr<T>();
+  gs3d_kernel<T, P><<<dim3(nrhs, cl.count), 128, 0, c.stream>>>(
+      cl.tiles3, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
+      backward ? 1 : 0, L.Ntorn);
+}
+
 template <typename T>
 void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs) {
   // one event pair around the sweep (its class launches run back to back)
@@ -1859,6 +2139,16 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs) {
     const GsClass &cl = L.gs[backward ? nc - 1 - ii : ii];
     if (cl.count == 0) continue;
     ++ts.n;
+    if (c.d == 3) {
+      switch (c.p) {
+        case 1: launch_gs3d<T, 1>(c, L, cl, backward, nrhs); break;
+        case 2: launch_gs3d<T, 2>(c, L, cl, backward, nrhs); break;
+        case 3: launch_gs3d<T, 3>(c, L, cl, backward, nrhs); break;
+        case 4: launch_gs3d<T, 4>(c, L, cl, backward, nrhs); break;
+        default: fail(IGAMG_EUNSUPPORTED, "3D degree out of range 1..4");
+      }
+      continue;
+    }
     switch (c.p) {
       case 1: launch_gs2d<T, 1>(c, L, cl, backward, nrhs); break;
       case 2: launch_gs2d<T, 2>(c, L, cl, backward, nrhs); break;
@@ -1896,10 +2186,30 @@ static void launch_sp2d_rb(Context &c, LevelData &L, const LevelArrays<T> &A, co
     launch_sp2d<T, P, RBB>(c, L, A, u, f, fw, beta, alpha, r, nrhs);
 }
 
+template <typename T, int P>
+static void launch_sp3d(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u, const T *f,
+                        const T *fw, T beta, T alpha, T *r, int nrhs) {
+  sp3d_kernel<T, P><<<dim3(L.n_atiles, nrhs), 256, 0, c.stream>>>(
+      L.d_atiles3, A.stencil, L.d_gcx_li, L.d_gcx_col, A.gcx_val, L.d_mask, u, f, fw, beta, alpha,
+      r, L.Ntorn);
+}
+
 template <typename T>
 void k_stencil_apply(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u, const T *f,
                      const T *fw, T beta, T alpha, T *r, int nrhs) {
   TimeScope ts(c, "stencil_apply", L.l);
+  if (c.d == 3) {
+    if (!A.stencil || !L.d_atiles3 || L.n_atiles == 0)
+      fail(IGAMG_EUNSUPPORTED, "no stored operator rows on this level");
+    switch (c.p) {
+      case 1: launch_sp3d<T, 1>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+      case 2: launch_sp3d<T, 2>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+      case 3: launch_sp3d<T, 3>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+      case 4: launch_sp3d<T, 4>(c, L, A, u, f, fw, beta, alpha, r, nrhs); break;
+      default: fail(IGAMG_EUNSUPPORTED, "3D degree out of range 1..4");
+    }
+    return;
+  }
   if (c.d != 2 || !A.stencil || !L.d_atiles || L.n_atiles == 0)
     fail(IGAMG_EUNSUPPORTED, "no stored operator rows on this level");
   switch (c.p) {
@@ -2005,7 +2315,12 @@ template void k_pieces<float>(Context &, LevelData &, int);
 template <typename T>
 void k_restrict(Context &c, LevelData &F, LevelData &C, const T *rf, T *rc, T *uc_zero, int nrhs) {
   TimeScope ts(c, "restrict", F.l);
-  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
+  if (c.d == 3) {
+    transfer3d_kernel<T, true><<<dim3(nblocks(C.Ntorn), nrhs), 256, 0, c.stream>>>(
+        F.d_pd, C.d_pd, F.d_pd, F.K, C.Ntorn, F.d_R_lo, F.arr<T>().R_val, F.RW, rf,
+        F.arr<T>().weight, C.d_mask, rc, uc_zero, F.Ntorn, C.Ntorn);
+    return;
+  }
   dim3 grid(nrhs, F.n_rtiles);
   transfer2d_kernel<T, true><<<grid, 256, 0, c.stream>>>(F.d_rtiles, F.d_R_lo, F.arr<T>().R_val,
                                                          F.RW, rf, F.arr<T>().weight, C.d_mask, rc,
@@ -2019,7 +2334,12 @@ template void k_restrict<float>(Context &, LevelData &, LevelData &, const float
 template <typename T>
 void k_prolong_add(Context &c, LevelData &F, LevelData &C, const T *ec, T *uf, int nrhs) {
   TimeScope ts(c, "prolong", F.l);
-  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D transfer not built");
+  if (c.d == 3) {
+    transfer3d_kernel<T, false><<<dim3(nblocks(F.Ntorn), nrhs), 256, 0, c.stream>>>(
+        C.d_pd, F.d_pd, F.d_pd, F.K, F.Ntorn, F.d_P_lo, F.arr<T>().P_val, F.PW, ec, nullptr,
+        F.d_mask, uf, nullptr, C.Ntorn, F.Ntorn);
+    return;
+  }
   dim3 grid(nrhs, F.n_ptiles);
   transfer2d_kernel<T, false><<<grid, 256, 0, c.stream>>>(F.d_ptiles, F.d_P_lo, F.arr<T>().P_val,
                                                           F.PW, ec, nullptr, F.d_mask, uf, nullptr,

@@ -747,12 +747,24 @@ static std::vector<double> dense_block_rows(const Context &c, const LevelData &L
     const long long t1 = L.rep[comps[a]];
     const int k = L.patch_of(t1);
     const PatchDev &pt = L.pd[k];
-    const long long lc = t1 - pt.off;
-    const int ix = (int)(lc % pt.n[0]), iy = (int)(lc / pt.n[0]);
-    for (int o = 0; o < S1 * S1; ++o) {
-      const int jx = ix + o % S1 - p, jy = iy + o / S1 - p;
-      if (jx < 0 || jx >= pt.n[0] || jy < 0 || jy >= pt.n[1]) continue;
-      auto it = loc.find(pt.off + (long long)jy * pt.n[0] + jx);
+    long long lc = t1 - pt.off;
+    int i[3] = {0, 0, 0};
+    for (int g = 0; g < c.d; ++g) {
+      i[g] = (int)(lc % pt.n[g]);
+      lc /= pt.n[g];
+    }
+    int S = 1;
+    for (int g = 0; g < c.d; ++g) S *= S1;
+    for (int o = 0; o < S; ++o) {
+      int j[3] = {0, 0, 0}, oo = o;
+      bool in = true;
+      for (int g = 0; g < c.d; ++g) {
+        j[g] = i[g] + oo % S1 - p;
+        oo /= S1;
+        in = in && j[g] >= 0 && j[g] < pt.n[g];
+      }
+      if (!in) continue;
+      auto it = loc.find(torn_index(pt, j));
       if (it != loc.end()) A[(size_t)a * n + it->second] += rows[(size_t)a * SP + o];
     }
     if (!L.if_ptr.empty())
@@ -965,10 +977,65 @@ static void build_scms(Context &c, LevelData &L) {
 
 // keep64: the float64 couplings are uploaded too (float32 cycle whose finest
 // level also serves the float64 outer apply from the stored rows)
+// Tiles of T^3 unknowns in classes (patch colour, tile parity) in key order;
+// every tile carries the cross-patch couplings of its rows (local row index
+// (z T + y) T + x).
+static void build_gs3(Context &c, LevelData &L, bool keep64) {
+  const int T = c.opt.gs_tile;
+  std::vector<int> li, col;
+  std::vector<double> val;
+  std::vector<GsTile3> all;
+  for (int colr = 0; colr < c.n_colors; ++colr)
+    for (int par = 0; par < 8; ++par) {
+      std::vector<GsTile3> tiles;
+      for (int k = 0; k < L.K; ++k) {
+        if (c.color[k] != colr) continue;
+        const PatchDev &pt = L.pd[k];
+        int nb[3];
+        for (int g = 0; g < 3; ++g) nb[g] = (pt.n[g] + T - 1) / T;
+        for (int b2 = 0; b2 < nb[2]; ++b2)
+          for (int b1 = 0; b1 < nb[1]; ++b1)
+            for (int b0 = 0; b0 < nb[0]; ++b0) {
+              if (((b0 & 1) | ((b1 & 1) << 1) | ((b2 & 1) << 2)) != par) continue;
+              GsTile3 tl{pt.off, {pt.n[0], pt.n[1], pt.n[2]}, {b0 * T, b1 * T, b2 * T},
+                         (int)li.size(), 0};
+              if (!L.if_ptr.empty())
+                for (int iz = b2 * T; iz < std::min(pt.n[2], (b2 + 1) * T); ++iz)
+                  for (int iy = b1 * T; iy < std::min(pt.n[1], (b1 + 1) * T); ++iy)
+                    for (int ix = b0 * T; ix < std::min(pt.n[0], (b0 + 1) * T); ++ix) {
+                      const long long t = pt.off + ((long long)iz * pt.n[1] + iy) * pt.n[0] + ix;
+                      for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e)
+                        if (L.if_cross[e]) {
+                          li.push_back(((iz - b2 * T) * T + (iy - b1 * T)) * T + (ix - b0 * T));
+                          col.push_back(L.if_col[e]);
+                          val.push_back(L.if_val[e]);
+                        }
+                    }
+              tl.cx_n = (int)li.size() - tl.cx_off;
+              tiles.push_back(tl);
+            }
+      }
+      GsClass cl;
+      cl.count = (int)tiles.size();
+      cl.tiles3 = c.arena.upload(tiles, c.stream);
+      L.gs.push_back(cl);
+      all.insert(all.end(), tiles.begin(), tiles.end());
+    }
+  L.n_atiles = (int)all.size();
+  L.d_atiles3 = c.arena.upload(all, c.stream);
+  L.d_gcx_li = c.arena.upload(li, c.stream);
+  L.d_gcx_col = c.arena.upload(col, c.stream);
+  if (c.fp32()) L.a32.gcx_val = c.arena.upload_as<float>(val, c.stream);
+  if (!c.fp32() || keep64) L.a64.gcx_val = c.arena.upload_as<double>(val, c.stream);
+}
+
 static void build_gs(Context &c, LevelData &L, bool keep64) {
   const int d = c.d, T = c.opt.gs_tile;
   if (T != 2 * (c.p + 1)) fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel tiles of width 2(p+1) only");
-  if (d != 2) fail(IGAMG_EUNSUPPORTED, "3D Gauss-Seidel not built");
+  if (d == 3) {
+    build_gs3(c, L, keep64);
+    return;
+  }
   std::vector<int> li, col;
   std::vector<double> val;
   std::vector<GsTile> all;
@@ -1125,11 +1192,13 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
     }
     return out;
   };
-  std::vector<XferTile> rt = tiles_of(F, C, Rlo, RW, true), pt = tiles_of(C, F, Plo, PW, false);
-  F.n_rtiles = (int)rt.size();
-  F.n_ptiles = (int)pt.size();
-  F.d_rtiles = c.arena.upload(rt, c.stream);
-  F.d_ptiles = c.arena.upload(pt, c.stream);
+  if (d == 2) {
+    std::vector<XferTile> rt = tiles_of(F, C, Rlo, RW, true), pt = tiles_of(C, F, Plo, PW, false);
+    F.n_rtiles = (int)rt.size();
+    F.n_ptiles = (int)pt.size();
+    F.d_rtiles = c.arena.upload(rt, c.stream);
+    F.d_ptiles = c.arena.upload(pt, c.stream);
+  }
   F.PW = PW;
   F.RW = RW;
   F.d_P_lo = c.arena.upload(Plo, c.stream);
@@ -1174,7 +1243,6 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
                   const igamg_options *o) {
   if (!P || !o) fail(IGAMG_EINVAL, "null argument");
   if (P->dim != 2 && P->dim != 3) fail(IGAMG_EINVAL, "dim must be 2 or 3");
-  if (P->dim == 3) fail(IGAMG_EUNSUPPORTED, "3D problems are not built yet");
   if (P->n_patches < 1 || !P->corners || !P->elems) fail(IGAMG_EINVAL, "no patches");
   if (degree < 1 || degree > MAXP) fail(IGAMG_EINVAL, "degree out of range 1..8");
   c.d = P->dim;
@@ -1204,6 +1272,16 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
   if (c.opt.operator_apply == IGAMG_APPLY_ROWS &&
       (c.opt.discretization != IGAMG_SIPG || !use_gs))
     fail(IGAMG_EUNSUPPORTED, "stored operator rows exist for SIPG with a Gauss-Seidel smoother only");
+  if (c.d == 3) {
+    // 3D: SIPG, Gauss-Seidel levels, operator from the stored rows
+    if (c.opt.discretization != IGAMG_SIPG)
+      fail(IGAMG_EUNSUPPORTED, "3D problems: SIPG discretization only");
+    if (c.opt.smoother != IGAMG_SMOOTHER_GS)
+      fail(IGAMG_EUNSUPPORTED, "3D problems: Gauss-Seidel smoother only");
+    if (c.opt.operator_apply == IGAMG_APPLY_SUMFACT)
+      fail(IGAMG_EUNSUPPORTED, "3D problems apply the operator from the stored rows");
+    if (degree > 4) fail(IGAMG_EUNSUPPORTED, "3D problems: degree 1..4");
+  }
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
@@ -1218,6 +1296,10 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
     }
   }
   build_topology(c);
+  // 3D levels apply the operator from Gauss-Seidel rows, which the coarsest
+  // level (direct solve) does not keep
+  if (c.d == 3 && level_elements(c).size() < 2)
+    fail(IGAMG_EUNSUPPORTED, "3D problems need two levels or more");
 }
 
 void problem_size(const igamg_patches *P, int degree, const igamg_options *o, long long *n,
@@ -1353,7 +1435,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       }
       L.d_optiles = c.arena.upload(ot, c.stream);
     }
-    if ((use_gs && l >= 1) || c.opt.discretization == IGAMG_SIPG) {
+    if (c.d == 2 && ((use_gs && l >= 1) || c.opt.discretization == IGAMG_SIPG)) {
       std::vector<VolTile> stl;
       const int RT = stencil_tile_2d(c.p);
       for (int k = 0; k < c.K; ++k)

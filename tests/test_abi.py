@@ -77,8 +77,15 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
     assert _setup_code(ig, sq, el, 2, smoother="scms", operator_apply="rows") == ig.EUNSUPPORTED
     assert _setup_code(ig, sq, el, 2, conforming=True, smoother="scms",
                        operator_apply="rows") == ig.EUNSUPPORTED
-    cube = np.zeros((1, 8, 3))
-    assert _setup_code(ig, cube, np.array([[2, 2, 2]], dtype=np.int32), 2) == ig.EUNSUPPORTED
+    cube = np.array([[[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)]], dtype=np.float64)
+    e4 = np.array([[4, 4, 4]], dtype=np.int32)
+    # 3D: SIPG with the Gauss-Seidel smoother, stored-row operator, two levels or more
+    assert _setup_code(ig, cube, e4, 2, smoother="scms") == ig.EUNSUPPORTED
+    assert _setup_code(ig, cube, e4, 2, conforming=True, smoother="scms") == ig.EUNSUPPORTED
+    assert _setup_code(ig, cube, e4, 2, smoother="gs", operator_apply="sumfact") == ig.EUNSUPPORTED
+    assert _setup_code(ig, cube, e4, 5, smoother="gs") == ig.EUNSUPPORTED
+    assert _setup_code(ig, cube, np.array([[2, 2, 2]], dtype=np.int32), 2,
+                       smoother="gs") == ig.EUNSUPPORTED
 
 
 def test_problem_size_matches_oracle_numbering(ig):
@@ -94,6 +101,23 @@ def test_problem_size_matches_oracle_numbering(ig):
                                       conforming=cfg["conforming"]).N
         assert n == n_expected
         assert lv == len(level_elements(cfg["elems"]))
+
+
+def test_problem_size_3d_matches_oracle_numbering(ig):
+    """3D SIPG (trilinear 2x2x2 patches, checkerboard 48/64 at p = 3 and the
+    same layout divided by 8): unknown count after Dirichlet elimination and
+    level count equal the oracle's."""
+    import numpy as np
+    import workloads
+    from oracle.discretize import Topology, Level
+    from oracle.hierarchy import level_elements
+    for scale in (1, 8):
+        cfg = workloads.config("c3", scale)
+        n, lv = ig.problem_size(cfg["corners"], cfg["elems"], cfg["p"], smoother="gs")
+        lev = Level(Topology(cfg["corners"]), np.asarray(cfg["elems"]), cfg["p"], False, None)
+        assert n == lev.N
+        assert lv == len(level_elements(cfg["elems"]))
+    assert n == 6048
 
 
 def test_binding_constants_match_header(ig):
