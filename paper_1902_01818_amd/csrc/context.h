@@ -97,7 +97,8 @@ struct LevelArrays {
   T *wscratch = nullptr;                       // fast-diagonalization intermediate
   T *wscratch2 = nullptr;                      // second intermediate of the staged form
   Fd2Item<T> *fd[2] = {nullptr, nullptr};      // patch interiors: forward, backward
-  FdGemm<T> *fg[4] = {nullptr, nullptr, nullptr, nullptr};  // the same as four product stages
+  FdGemm<T> *fg[6] = {};                      // the same as product stages (2D: 4, 3D: 6)
+  T *lam_xy = nullptr;                         // 3D: lam_y[j] + lam_x[i] per patch (y-major)
 };
 
 struct LevelData {
@@ -167,6 +168,7 @@ struct LevelData {
   int n_fd = 0;
   int fd_rows = 0, fd_K1 = 0, fd_N = 0;
   int fg_tiles = 0;       // 64 x 64 output tiles of the largest stage item
+  int fg_n[6] = {}, fg_t[6] = {};  // 3D: items and largest tile count of each stage
   long long fd_work = 0;  // sum over patches of my * mx * ceil(my / 16) (fused-form re-reads)
   long long wscratch_n = 0;
   // interface pieces

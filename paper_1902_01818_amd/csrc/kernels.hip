@@ -2275,10 +2275,30 @@ static void scms_mfma(Context &c, LevelData &L, int nrhs) {
 // patch interiors of the subspace corrected mass smoother: two launches of
 // chained products on the matrix cores (bfloat16 operands when the options
 // ask for them, float32 cycles only)
+// 3D: six stages, each with its own item count and tile range
+template <typename T, bool BF>
+static void scms_staged3(Context &c, LevelData &L, int nrhs) {
+  for (int st = 0; st < 6; ++st) {
+    if (L.fg_n[st] == 0) continue;
+    dim3 grid(nrhs, L.fg_t[st], L.fg_n[st]);
+    fdg_kernel<T, BF><<<grid, 256, 0, c.stream>>>(L.arr<T>().fg[st]);
+  }
+}
+
 template <typename T>
 void k_scms_interior(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "scms", L.l);
   if (L.n_fd == 0) return;
+  if (c.d == 3) {
+    if constexpr (sizeof(T) == 4) {
+      if (c.bf16_scms()) {
+        scms_staged3<float, true>(c, L, nrhs);
+        return;
+      }
+    }
+    scms_staged3<T, false>(c, L, nrhs);
+    return;
+  }
   // the fused form re-reads each right-hand side's operand once per 16-row
   // block; past this much re-read work the four-stage form is faster
   const bool staged = (double)L.fd_work * nrhs >= FD_STAGED_MIN;

@@ -899,10 +899,114 @@ static std::vector<double> transpose(const std::vector<double> &A, int n) {
 // diag(1/(sigma + lam_y + lam_x)) (Qy x Qx)^T r, evaluated as
 //   W = (Qy^T R Qx) ./ D   and   U += (tau/gamma) Qy W Qx^T
 // on the interior block R of the patch tensor.
+// Patch interiors of a 3D level as six batched product stages on the
+// interior tensor R[z][y][x] (strides 1, nx, nx ny inside the patch tensor),
+// intermediates alternating between two scratch tensors W1, W2:
+//   1. W1_z = R_z Qx               (per z slice: Qx^T along x)
+//   2. W2_z = Qy^T W1_z            (per z slice: Qy^T along y)
+//   3. W1 = (Qz^T W2) ./ (sigma + lam_z[z] + lam_y[y] + lam_x[x])
+//                                  (W2 as an mz x (my mx) matrix)
+//   4. W2 = Qz W1
+//   5. W1_z = Qy W2_z
+//   6. U_z += scale W1_z Qx^T      (into the patch interior of u)
+template <typename T>
+static void build_scms3(Context &c, LevelData &L) {
+  const int p = c.p;
+  LevelArrays<T> &A = L.arr<T>();
+  struct QT {
+    T *Q, *QT;
+    std::vector<double> lam;
+  };
+  std::map<int, QT> qtab;
+  for (int k = 0; k < L.K; ++k)
+    for (int g = 0; g < 3; ++g) {
+      int ne = L.pd[k].nel[g];
+      if (qtab.count(ne)) continue;
+      std::vector<double> Q, lam;
+      scms_factors_1d(ne, p, Q, lam);
+      int n = ne + p - 2;
+      qtab[ne] = QT{c.arena.upload_as<T>(Q, c.stream),
+                    c.arena.upload_as<T>(transpose(Q, n), c.stream), lam};
+    }
+  size_t scr = 0, nxy = 0;
+  for (int k = 0; k < L.K; ++k) {
+    const PatchDev &pt = L.pd[k];
+    scr += (size_t)(pt.n[0] - 2) * (pt.n[1] - 2) * (pt.n[2] - 2);
+    nxy += (size_t)(pt.n[0] - 2) * (pt.n[1] - 2);
+  }
+  L.wscratch_n = (long long)scr;
+  A.wscratch = c.arena.alloc<T>(scr * c.nb);
+  A.wscratch2 = c.arena.alloc<T>(scr * c.nb);
+  // lam_y[j] + lam_x[i] of every patch, and lam_z per direction table
+  std::vector<double> lxy;
+  lxy.reserve(nxy);
+  std::map<int, T *> lamz;
+  for (auto &kv : qtab) lamz[kv.first] = c.arena.upload_as<T>(kv.second.lam, c.stream);
+  std::vector<FdGemm<T>> g[6];
+  const long long nt = L.Ntorn, ns = (long long)scr;
+  size_t so = 0, lo = 0;
+  std::vector<size_t> lxy_off;
+  for (int k = 0; k < L.K; ++k) {
+    const PatchDev &pt = L.pd[k];
+    const int mx = pt.n[0] - 2, my = pt.n[1] - 2;
+    const QT &qx = qtab[pt.nel[0]], &qy = qtab[pt.nel[1]];
+    lxy_off.push_back(lo);
+    for (int j = 0; j < my; ++j)
+      for (int i = 0; i < mx; ++i) lxy.push_back(qy.lam[j] + qx.lam[i]);
+    lo += (size_t)mx * my;
+  }
+  A.lam_xy = c.arena.upload_as<T>(lxy, c.stream);
+  for (int k = 0; k < L.K; ++k) {
+    PatchDev &pt = L.pd[k];
+    const int nx = pt.n[0], ny = pt.n[1];
+    const int mx = pt.n[0] - 2, my = pt.n[1] - 2, mz = pt.n[2] - 2;
+    const long long sxy = (long long)mx * my, nxy_p = (long long)nx * ny;
+    const QT &qx = qtab[pt.nel[0]], &qy = qtab[pt.nel[1]], &qz = qtab[pt.nel[2]];
+    T *W1 = A.wscratch + so, *W2 = A.wscratch2 + so;
+    so += (size_t)sxy * mz;
+    T *rin = A.r + pt.off + nxy_p + nx + 1;
+    T *uin = A.u + pt.off + nxy_p + nx + 1;
+    double h = 1.0 / std::max(pt.nel[0], std::max(pt.nel[1], pt.nel[2]));
+    pt.sigma = 1.0 / (c.opt.scaling_delta * h * h);
+    double gamma = std::pow(c.measure[k], (c.d - 2.0) / c.d);
+    pt.scms_scale = c.opt.damping_tau / gamma;
+    const int tx = (mx + 63) / 64, txy = (int)((sxy + 63) / 64);
+    for (int z = 0; z < mz; ++z) {
+      const long long zr = z * nxy_p, zs = z * sxy;
+      g[0].push_back(FdGemm<T>{rin + zr, qx.Q, W1 + zs, nx, mx, mx, nt, 0, ns, my, mx, mx, tx,
+                               nullptr, nullptr, (T)0, (T)0, 0});
+      g[1].push_back(FdGemm<T>{qy.QT, W1 + zs, W2 + zs, my, mx, mx, 0, ns, ns, my, mx, my, tx,
+                               nullptr, nullptr, (T)0, (T)0, 0});
+      g[4].push_back(FdGemm<T>{qy.Q, W2 + zs, W1 + zs, my, mx, mx, 0, ns, ns, my, mx, my, tx,
+                               nullptr, nullptr, (T)0, (T)0, 0});
+      g[5].push_back(FdGemm<T>{W1 + zs, qx.QT, uin + zr, mx, mx, nx, ns, 0, nt, my, mx, mx, tx,
+                               nullptr, nullptr, (T)0, (T)pt.scms_scale, 2});
+    }
+    g[2].push_back(FdGemm<T>{qz.QT, W2, W1, mz, sxy, sxy, 0, ns, ns, mz, (int)sxy, mz, txy,
+                             lamz[pt.nel[2]], A.lam_xy + lxy_off[k], (T)pt.sigma, (T)0, 1});
+    g[3].push_back(FdGemm<T>{qz.Q, W1, W2, mz, sxy, sxy, 0, ns, ns, mz, (int)sxy, mz, txy,
+                             nullptr, nullptr, (T)0, (T)0, 0});
+  }
+  for (int st = 0; st < 6; ++st) {
+    L.fg_n[st] = (int)g[st].size();
+    L.fg_t[st] = 0;
+    for (const FdGemm<T> &it : g[st])
+      L.fg_t[st] = std::max(L.fg_t[st], it.tn * ((it.M + 63) / 64));
+    A.fg[st] = c.arena.upload(g[st], c.stream);
+  }
+  L.n_fd = L.fg_n[2];
+  L.fd_work = 0;
+  for (int k = 0; k < L.K; ++k)
+    L.fd_work += (long long)(L.pd[k].n[0] - 2) * (L.pd[k].n[1] - 2) * (L.pd[k].n[2] - 2);
+}
+
 template <typename T>
 static void build_scms(Context &c, LevelData &L) {
   const int p = c.p;
-  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D SCMS not built");
+  if (c.d == 3) {
+    build_scms3<T>(c, L);
+    return;
+  }
   LevelArrays<T> &A = L.arr<T>();
   struct QT {
     T *Q, *QT, *lam;
@@ -1276,8 +1380,8 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
     // 3D: SIPG, Gauss-Seidel levels, operator from the stored rows
     if (c.opt.discretization != IGAMG_SIPG)
       fail(IGAMG_EUNSUPPORTED, "3D problems: SIPG discretization only");
-    if (c.opt.smoother != IGAMG_SMOOTHER_GS)
-      fail(IGAMG_EUNSUPPORTED, "3D problems: Gauss-Seidel smoother only");
+    if (c.opt.smoother == IGAMG_SMOOTHER_SCMS)
+      fail(IGAMG_EUNSUPPORTED, "3D problems: Gauss-Seidel or hybrid smoother");
     if (c.opt.operator_apply == IGAMG_APPLY_SUMFACT)
       fail(IGAMG_EUNSUPPORTED, "3D problems apply the operator from the stored rows");
     if (degree > 4) fail(IGAMG_EUNSUPPORTED, "3D problems: degree 1..4");
@@ -1638,8 +1742,15 @@ void kernel_model(const Context &c, const std::string &fam, int level, int nrhs,
   } else if (fam == "scms") {
     // one application to the patch interiors: four products per patch;
     // bytes: r read, u read and written per right-hand side, the factors once
+    // (3D: six mode products, each m^3 times the contracted extent)
     for (int k = 0; k < c.K; ++k) {
       double mx = L.pd[k].n[0] - 2, my = L.pd[k].n[1] - 2;
+      if (c.d == 3) {
+        double mz = L.pd[k].n[2] - 2, m3 = mx * my * mz;
+        *flops += nb * 4.0 * m3 * (mx + my + mz);
+        *bytes += nb * 3.0 * wb * m3 + wb * 2.0 * (mx * mx + my * my + mz * mz);
+        continue;
+      }
       *flops += nb * 2.0 * (my * my * mx + my * mx * mx + my * my * mx + my * mx * mx);
       *bytes += nb * 3.0 * wb * mx * my + wb * 2.0 * (mx * mx + my * my);
     }

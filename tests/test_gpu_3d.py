@@ -1,5 +1,7 @@
-"""Parity of the 3D SIPG path (Gauss-Seidel multigrid, operator from the
-stored rows) with the FP64 oracle, through the C ABI.
+"""Parity of the 3D SIPG path (Gauss-Seidel or hybrid multigrid -- SCMS
+patch interiors by six mode-product stages, face / edge / vertex pieces by
+dense inverses --, operator from the stored rows) with the FP64 oracle,
+through the C ABI.
 
 Inputs: trilinear 2 x 2 x 2 patch layouts with 5 % corner perturbation and
 checkerboard element counts (the C3 structure at reduced size), a 2 x 1 x 1
@@ -22,7 +24,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _case(name):
+def _case(name, smoother="gs"):
     if name == "c3/8":
         cfg = workloads.config("c3", 8)
     elif name == "2x2x2/p2":
@@ -36,29 +38,31 @@ def _case(name):
     else:
         raise KeyError(name)
     cfg = dict(cfg)
-    cfg["smoother"] = "gs"
+    cfg["smoother"] = smoother
     return cfg
 
 
-@functools.lru_cache(maxsize=4)
-def _oracle(name):
-    cfg = _case(name)
+@functools.lru_cache(maxsize=2)
+def _oracle(name, smoother):
+    cfg = _case(name, smoother)
     return cfg, oracle.setup(cfg["corners"], cfg["elems"], cfg["p"], sigma=cfg["sigma"],
-                             conforming=False, smoother="gs", tau=cfg["tau"], delta=cfg["delta"])
+                             conforming=False, smoother=smoother, tau=cfg["tau"],
+                             delta=cfg["delta"])
 
 
-CASES = ["2x2x2/p2", "2x1x1/p3", "c3/8"]
+CASES = [("2x2x2/p2", "gs"), ("2x1x1/p3", "gs"), ("c3/8", "gs"),
+         ("2x2x2/p2", "hybrid"), ("2x1x1/p3", "hybrid"), ("c3/8", "hybrid")]
 
 
 def _to_gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
 
 
-@pytest.fixture(scope="module", params=CASES)
+@pytest.fixture(scope="module", params=CASES, ids=["%s/%s" % c for c in CASES])
 def pair(request):
     print("3d case", request.param, flush=True)
-    cfg, ob = _oracle(request.param)
-    sv = gpu_solver(cfg, smoother="gs")
+    cfg, ob = _oracle(*request.param)
+    sv = gpu_solver(cfg)
     yield cfg, ob, sv
     sv.close()
 
@@ -120,7 +124,7 @@ def test_solve_final(pair):
 def test_batch_matches_single(pair):
     cfg, ob, sv = pair
     F = np.stack([workloads.normal_rhs(ob.N, 70 + j) for j in range(3)])
-    sb = gpu_solver(cfg, smoother="gs", max_rhs=3)
+    sb = gpu_solver(cfg, max_rhs=3)
     try:
         U, infos = sb.solve(_to_gpu(F), tol=1e-8, maxit=200)
         U = U.cpu().numpy()
@@ -140,7 +144,7 @@ def test_float32_cycle(pair, outer):
     cfg, ob, sv = pair
     f = ob.load_manufactured()
     uo, its, _, _ = ob.pcg(f)
-    s32 = gpu_solver(cfg, smoother="gs", precision="fp32", outer=outer)
+    s32 = gpu_solver(cfg, precision="fp32", outer=outer)
     try:
         u, info = s32.solve(_to_gpu(f), tol=1e-8, maxit=200)
         ug = u.cpu().numpy()
@@ -151,6 +155,27 @@ def test_float32_cycle(pair, outer):
         assert rel_err(ug, uo) < 1e-6
     finally:
         s32.close()
+
+
+def test_bf16_scms(pair):
+    """bfloat16 operands in the mode-product stages of the patch interiors
+    (float32 accumulation, float32 cycle) inside float64 flexible CG: the
+    float64 stopping test decides; iterations bounded by twice the float64
+    count."""
+    cfg, ob, sv = pair
+    if cfg["smoother"] != "hybrid":
+        pytest.skip("bfloat16 applies to the SCMS stages of the hybrid smoother")
+    f = ob.load_manufactured()
+    _, its, _, _ = ob.pcg(f)
+    sb = gpu_solver(cfg, precision="bf16", outer="fcg")
+    try:
+        u, info = sb.solve(_to_gpu(f), tol=1e-8, maxit=200)
+        ug = u.cpu().numpy()
+        assert info[0]["converged"]
+        assert np.linalg.norm(f - ob.A[-1] @ ug) / np.linalg.norm(f) <= 1.05e-8
+        assert info[0]["iterations"] <= 2 * its, (info[0]["iterations"], its)
+    finally:
+        sb.close()
 
 
 def test_unsupported_3d_options():
