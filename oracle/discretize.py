@@ -281,6 +281,41 @@ class Level:
                 A = A + Cg[a].T @ sp.diags(G[:, a, b]) @ Cg[b]
         return sp.csr_matrix(A)
 
+    def volume_row(self, k, i):
+        """Row of patch k's stiffness matrix (volume_matrix) for the basis
+        function with multi-index i (x first), integrated with the same Gauss
+        rule over the elements of its support only (elsewhere the row's
+        integrand vanishes).  Returns the row as a dense vector over the
+        patch's local unknowns.  Used to check single outputs of the operator
+        at sizes whose full assembly is out of reach."""
+        d, p, q = self.d, self.p, self.p + 1
+        pts1, wts1, B1, D1 = [], [], [], []
+        for delta in range(d):
+            ne = int(self.elems[k, delta])
+            x, w = bspline.element_quadrature(ne, q)
+            els = np.arange(max(0, int(i[delta]) - p), min(ne - 1, int(i[delta])) + 1)
+            sel = (els[:, None] * q + np.arange(q)[None, :]).ravel()
+            pts1.append(x[sel])
+            wts1.append(w[sel])
+            B1.append(collocation_1d(ne, p, x[sel], 0))
+            D1.append(collocation_1d(ne, p, x[sel], 1))
+        Cg = [kron_dirs([D1[delta] if delta == g else B1[delta] for delta in range(d)])
+              for g in range(d)]
+        W = tensor_weights(wts1)
+        _, J = multilinear(self.topo.corners[k], tensor_points(pts1))
+        detJ = np.linalg.det(J)
+        Jinv = np.linalg.inv(J)
+        G = np.einsum("qai,qbi->qab", Jinv, Jinv) * (W * detJ)[:, None, None]
+        li = 0
+        for delta in range(d - 1, -1, -1):
+            li = li * int(self.n[k, delta]) + int(i[delta])
+        row = np.zeros(int(self.sizes[k]))
+        for a in range(d):
+            ca = Cg[a][:, li].toarray().ravel()
+            for b in range(d):
+                row += Cg[b].T @ (ca * G[:, a, b])
+        return row
+
     def load_vector(self, k, f):
         """(f, phi_i)_{L2(Omega_k)} with q = p+1 Gauss points."""
         C0, _, W, xh = self.patch_collocation(k, self.p + 1)

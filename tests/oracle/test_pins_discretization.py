@@ -126,3 +126,43 @@ def test_sipg_tends_to_conforming():
         us = sip.levels[-1].E @ spla.spsolve(sip.A[-1].tocsc(), sip.load_manufactured())
         gaps.append(np.abs(us - uc).max())
     assert gaps[1] < gaps[0] / 50
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_volume_row_matches_assembled_rows(d):
+    """One stiffness row integrated over the support elements of its basis
+    function equals the row of the whole-patch assembly (perturbed
+    multilinear patches; interior, edge and corner basis functions)."""
+    counts = (2, 1) if d == 2 else (1, 1, 2)
+    corners = workloads.grid_corners(counts, frac=0.08, seed=7)
+    elems = np.array([[5, 4][:d] + [3] * (d - 2), [4, 6][:d] + [5] * (d - 2)])
+    lev = Level(Topology(corners), elems, 3, False, None)
+    rng = np.random.default_rng(3)
+    for k in range(2):
+        A = lev.volume_matrix(k).toarray()
+        n = lev.n[k]
+        picks = [np.zeros(d, dtype=int), n - 1, n // 2] + [rng.integers(0, n) for _ in range(4)]
+        for i in picks:
+            li = 0
+            for delta in range(d - 1, -1, -1):
+                li = li * int(n[delta]) + int(i[delta])
+            row = lev.volume_row(k, i)
+            assert np.allclose(row, A[li], rtol=0, atol=1e-13 * np.abs(A[li]).max())
+
+
+def test_volume_row_identity_cube_is_kronecker_sum():
+    """On the identity-mapped unit cube the stiffness is the Kronecker sum
+    K (x) M (x) M + M (x) K (x) M + M (x) M (x) K of the 1D mass and stiffness
+    matrices of the B-spline bases (separation of variables)."""
+    from oracle.smoothers import mass_stiffness_1d
+    corners = workloads.grid_corners((1, 1, 1))
+    ne = (3, 4, 5)
+    lev = Level(Topology(corners), np.array([ne]), 2, False, None)
+    M = [mass_stiffness_1d(e, 2)[0] for e in ne]
+    K = [mass_stiffness_1d(e, 2)[1] for e in ne]
+    A = (np.kron(M[2], np.kron(M[1], K[0])) + np.kron(M[2], np.kron(K[1], M[0]))
+         + np.kron(K[2], np.kron(M[1], M[0])))
+    n = lev.n[0]
+    for i in ([0, 0, 0], [2, 3, 4], [4, 5, 6], [1, 2, 3]):
+        li = (i[2] * n[1] + i[1]) * n[0] + i[0]
+        assert np.allclose(lev.volume_row(0, i), A[li], rtol=0, atol=1e-13 * np.abs(A[li]).max())
