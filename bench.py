@@ -127,6 +127,46 @@ def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2, outer=No
     return out
 
 
+def c3_leg(igamg, torch, workloads, precision="fp32", steps=2):
+    """The 3D workload at full size (2x2x2 trilinear patches, 48/64 elements,
+    p = 3, 1.65 M unknowns, manufactured right-hand side), hybrid cycle in
+    the given arithmetic inside float64 flexible CG (float64: PCG), plus the
+    time per kernel family of one more, event-timed solve."""
+    cfg = workloads.config("c3")
+    outer = "pcg" if precision == "fp64" else cfg["outer"]
+    t0 = time.perf_counter()
+    sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
+                      conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
+                      delta=cfg["delta"], precision=precision, outer=outer)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    f = sv.load_manufactured()
+    u, info = sv.solve(f, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, info = sv.solve(f, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = dict(workload="3D SIPG, 2x2x2 trilinear patches, 48/64 elements, p=3, manufactured",
+               dofs=sv.n_dofs, levels=sv.n_levels, precision=precision, outer=outer,
+               solves_per_s=1.0 / dt, ms_per_solve=dt * 1e3, setup_s=setup_s,
+               memory_gib=sv.memory() / (1 << 30), iterations=info[0]["iterations"],
+               true_rel_residual=info[0]["true_rel_residual"], converged=info[0]["converged"])
+    sv.set_timing("")
+    sv.solve(f, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    st = sv.kernel_stats(reset=True)
+    sv.set_timing(None)
+    fam = {}
+    for k, v in st.items():
+        name = k.split("/")[0]
+        fam[name] = fam.get(name, 0.0) + v["ms"]
+    out["ms_per_family_timed_solve"] = {k: round(v, 3) for k, v in sorted(fam.items())}
+    sv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +180,9 @@ def main():
     ap.add_argument("--c4-only", action="store_true",
                     help="diagnostic: run only the 64-column p = 6 legs (float32 cycle, bf16 "
                          "SCMS) and print their results (not the benchmark line)")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="diagnostic: run only the full-size 3D workload (float32 and float64 "
+                         "cycles) and print its results (not the benchmark line)")
     ap.add_argument("--coarse-min", type=int, default=8,
                     help="halving stops before an element count falls below this: 8 puts the "
                          "direct solve on the 8/12-element level (2,940 unknowns, 4 levels); "
@@ -156,6 +199,13 @@ def main():
     import torch
     import workloads
     from paper_1902_01818_amd import igamg
+
+    if args.c3_only:
+        out = {"c3": c3_leg(igamg, torch, workloads, precision="fp32")}
+        print("bench: 3D workload timed (float32 cycle)", file=sys.stderr, flush=True)
+        out["c3_fp64"] = c3_leg(igamg, torch, workloads, precision="fp64")
+        print(json.dumps(out))
+        return
 
     if args.c4_only:
         out = {"c4": c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)}
