@@ -99,6 +99,8 @@ struct LevelArrays {
   Fd2Item<T> *fd[2] = {nullptr, nullptr};      // patch interiors: forward, backward
   FdGemm<T> *fg[6] = {};                      // the same as product stages (2D: 4, 3D: 6)
   T *lam_xy = nullptr;                         // 3D: lam_y[j] + lam_x[i] per patch (y-major)
+  T *x_val = nullptr;                          // 3D: cross-patch couplings (CSR of coupled rows)
+  T *xsum = nullptr;                           // 3D: sum of a colour's cross couplings per row
 };
 
 struct LevelData {
@@ -161,6 +163,11 @@ struct LevelData {
   std::vector<GsClass> gs;  // classes in key order
   GsTile *d_atiles = nullptr;  // every Gauss-Seidel tile of the level (stored-row operator)
   GsTile3 *d_atiles3 = nullptr;  // the same for 3D patches
+  // 3D: cross-patch couplings as a CSR over the coupled rows, rows grouped by
+  // patch colour (x_cptr[c] .. x_cptr[c+1])
+  int *d_x_rows = nullptr, *d_x_ptr = nullptr, *d_x_col = nullptr;
+  int x_n = 0;
+  std::vector<int> x_cptr;
   int n_atiles = 0;
   // the cycle's residuals on this level use the stored rows (k_stencil_apply)
   bool st_apply = false;

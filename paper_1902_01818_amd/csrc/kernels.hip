@@ -824,7 +824,7 @@ __global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntil
 #pragma unroll
     for (int c = 0; c < C; ++c) a[c] = sr[16 * c];
   }
-  __syncthreads();  // cross sums complete
+  __syncthreads();  // window and zeroed sums complete
   for (int li = g; li < NT; li += 16) {
     if (li + 16 < NT) {
       const T *sr = row_ptr(li + 16);
@@ -894,53 +894,100 @@ __device__ inline void load_window3(const GsTile3 &tl, const T *u, T *sU, int ti
   }
 }
 
-// Multicolour Gauss-Seidel on 3D tiles: one block of 8 row groups (16 lanes
-// each) per tile and right-hand side.  Phase s of the sweep updates the eight
-// unknowns of the tile whose index mod (p+1) is (s mod Q1, s / Q1 mod Q1,
-// s / Q1^2) -- one colour class of the ordering -- and a block barrier
-// separates the phases.  f minus the cross-patch couplings (values of
-// neighbouring patches, another patch colour, constant during the launch) and
-// 1/a_ii sit in LDS.  grid.x = right-hand side, grid.y = tile.
+// Cross-patch couplings of 3D levels, one thread per coupled row r0 <= r < r1
+// (CSR order, two partial sums): ADD = false stores s = X_row u (the
+// Gauss-Seidel right-hand side correction of a patch colour), ADD = true adds
+// alpha s to the masked output row (operator apply).  grid.y = right-hand side.
+template <typename T, bool ADD>
+__global__ __launch_bounds__(256) void cross3d_kernel(const int *__restrict__ rows,
+                                                      const int *__restrict__ ptr,
+                                                      const int *__restrict__ col,
+                                                      const T *__restrict__ val, int r0, int r1,
+                                                      const unsigned char *__restrict__ mask,
+                                                      const T *__restrict__ u, T *out, T alpha,
+                                                      long long vs) {
+  const int r = r0 + blockIdx.x * 256 + threadIdx.x;
+  if (r >= r1) return;
+  const long long zo = (long long)blockIdx.y * vs;
+  const int t = rows[r];
+  int e = ptr[r];
+  const int e1 = ptr[r + 1];
+  T s0 = 0, s1 = 0;
+#pragma unroll 4
+  for (; e + 1 < e1; e += 2) {
+    s0 += val[e] * u[zo + col[e]];
+    s1 += val[e + 1] * u[zo + col[e + 1]];
+  }
+  if (e < e1) s0 += val[e] * u[zo + col[e]];
+  const T sum = s0 + s1;
+  if (ADD) {
+    if (mask[t]) out[zo + t] += alpha * sum;
+  } else {
+    out[zo + t] = sum;
+  }
+}
+
+// Sum over a wavefront: DPP scans inside the four rows of 16 lanes, then the
+// four row sums read from lanes 15, 31, 47, 63 (fixed order).
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <typename T>
+__device__ inline T wave_sum(T v) {
+  v = row16_scan(v);
+  return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+}
+
+// Multicolour Gauss-Seidel on 3D tiles: one block of eight wavefronts per
+// tile and right-hand side.  Phase s of the sweep updates the eight unknowns
+// of the tile whose index mod (p+1) is (s mod Q1, s / Q1 mod Q1, s / Q1^2)
+// -- one colour class of the ordering --, one unknown per wavefront, and a
+// block barrier separates the phases.  A lane holds SP/64 slots of a row, so
+// the rows of the next D phases fit in registers and their loads overlap the
+// phases before them.  f - xs (xs = the cross-patch couplings applied to the
+// neighbouring patches' values, another patch colour, constant during the
+// patch colour's launches; zero on rows without couplings) and 1/a_ii sit in
+// LDS.  grid.x = right-hand side, grid.y = tile.
 template <typename T, int P>
-__global__ __launch_bounds__(128) void gs3d_kernel(const GsTile3 *tiles, const T *__restrict__ st,
+__global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T *__restrict__ st,
                                                    const T *__restrict__ invd,
-                                                   const int *__restrict__ cx_li,
-                                                   const int *__restrict__ cx_col,
-                                                   const T *__restrict__ cx_val,
+                                                   const T *__restrict__ xs,
                                                    const T *__restrict__ f, T *u, int backward,
                                                    long long vs) {
   using G = Tile3<P>;
-  constexpr int Q1 = G::Q1, TT = G::TT, W = G::W, C = G::C, SP = G::SP, NPH = G::NPH;
+  constexpr int Q1 = G::Q1, TT = G::TT, W = G::W, SP = G::SP, NPH = G::NPH;
+  constexpr int CL = (SP + 63) / 64;           // slots per lane
+  constexpr int D = sizeof(T) == 8 ? 4 : 8;    // phases in flight
   __shared__ T sU[G::NW];
   __shared__ T sB[G::NT];
   __shared__ T sD[G::NT];
   const GsTile3 tl = tiles[blockIdx.y];
   f += (long long)blockIdx.x * vs;
+  xs += (long long)blockIdx.x * vs;
   u += (long long)blockIdx.x * vs;
   const int tid = threadIdx.x;
   const int nx = tl.n[0], ny = tl.n[1], nz = tl.n[2];
   const int x0 = tl.i0[0], y0 = tl.i0[1], z0 = tl.i0[2];
-  load_window3<T, P>(tl, u, sU, tid, 128);
-  for (int i = tid; i < G::NT; i += 128) {
+  load_window3<T, P>(tl, u, sU, tid, 512);
+  for (int i = tid; i < G::NT; i += 512) {
     const int ix = x0 + i % TT, iy = y0 + i / TT % TT, iz = z0 + i / (TT * TT);
     const bool ok = ix < nx && iy < ny && iz < nz;
     const long long t = tl.off + ((long long)iz * ny + iy) * nx + ix;
-    sB[i] = ok ? f[t] : (T)0;
+    sB[i] = ok ? f[t] - xs[t] : (T)0;
     sD[i] = ok ? invd[t] : (T)0;
   }
-  __syncthreads();
-  // cross couplings by the first wave (a fixed order of the additions)
-  if (tid < 64)
-    for (int e = tid; e < tl.cx_n; e += 64) {
-      const int q = tl.cx_off + e;
-      unsafeAtomicAdd(&sB[cx_li[q]], -cx_val[q] * u[cx_col[q]]);
-    }
-  const int grp = tid >> 4, l16 = tid & 15;
-  const int ax = (grp & 1) * Q1, ay = (grp >> 1 & 1) * Q1, az = (grp >> 2) * Q1;
-  int soff[C];
+  const int w = tid >> 6, lane = tid & 63;
+  const int ax = (w & 1) * Q1, ay = (w >> 1 & 1) * Q1, az = (w >> 2) * Q1;
+  int soff[CL];
 #pragma unroll
-  for (int c = 0; c < C; ++c) soff[c] = G::slot_off(l16 + 16 * c);
-  // row of this group in phase s; rows outside the patch read the tile
+  for (int c = 0; c < CL; ++c) soff[c] = G::slot_off(lane + 64 * c);
+  // row of this wavefront in phase s; rows outside the patch read the tile
   // origin's row and are not updated
   auto row_of = [&](int s, int &wi, int &li, bool &ok) {
     const int ph = backward ? NPH - 1 - s : s;
@@ -950,40 +997,44 @@ __global__ __launch_bounds__(128) void gs3d_kernel(const GsTile3 *tiles, const T
     li = (dz * TT + dy) * TT + dx;
     const long long t = ok ? tl.off + ((long long)(z0 + dz) * ny + y0 + dy) * nx + x0 + dx
                            : tl.off + ((long long)z0 * ny + y0) * nx + x0;
-    return st + t * SP + l16;
+    return st + t * SP;
   };
-  T a[C], an[C];
-  {
+  auto load_row = [&](int s, T *a) {
     int wi, li;
     bool ok;
-    const T *sr = row_of(0, wi, li, ok);
+    const T *sr = row_of(s, wi, li, ok);
 #pragma unroll
-    for (int c = 0; c < C; ++c) a[c] = sr[16 * c];
-  }
-  __syncthreads();  // cross sums complete
-  for (int s = 0; s < NPH; ++s) {
-    int wi, li;
-    bool ok;
-    row_of(s, wi, li, ok);
-    if (s + 1 < NPH) {
-      int wn, ln;
-      bool okn;
-      const T *sr = row_of(s + 1, wn, ln, okn);
-#pragma unroll
-      for (int c = 0; c < C; ++c) an[c] = sr[16 * c];
+    for (int c = 0; c < CL; ++c) {
+      const int k = lane + 64 * c;
+      a[c] = k < SP ? sr[k] : (T)0;
     }
-    T acc0 = 0, acc1 = 0;
+  };
+  T buf[D][CL];
 #pragma unroll
-    for (int c = 0; c < C; c += 2) acc0 += a[c] * sU[wi + soff[c]];
+  for (int j = 0; j < D; ++j)
+    if (j < NPH) load_row(j, buf[j]);
+  __syncthreads();
+  for (int s0 = 0; s0 < NPH; s0 += D) {
 #pragma unroll
-    for (int c = 1; c < C; c += 2) acc1 += a[c] * sU[wi + soff[c]];
-    const T acc = row16_scan(acc0 + acc1);
-    if (l16 == 15 && ok) sU[wi] = sU[wi] + (sB[li] - acc) * sD[li];
-    __syncthreads();
+    for (int j = 0; j < D; ++j) {
+      const int s = s0 + j;
+      if (s < NPH) {
+        int wi, li;
+        bool ok;
+        row_of(s, wi, li, ok);
+        T acc0 = 0, acc1 = 0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) a[c] = an[c];
+        for (int c = 0; c < CL; c += 2) acc0 += buf[j][c] * sU[wi + soff[c]];
+#pragma unroll
+        for (int c = 1; c < CL; c += 2) acc1 += buf[j][c] * sU[wi + soff[c]];
+        if (s + D < NPH) load_row(s + D, buf[j]);
+        const T acc = wave_sum(acc0 + acc1);
+        if (lane == 0 && ok) sU[wi] = sU[wi] + (sB[li] - acc) * sD[li];
+        __syncthreads();
+      }
+    }
   }
-  for (int i = tid; i < G::NT; i += 128) {
+  for (int i = tid; i < G::NT; i += 512) {
     const int dx = i % TT, dy = i / TT % TT, dz = i / (TT * TT);
     if (x0 + dx < nx && y0 + dy < ny && z0 + dz < nz)
       u[tl.off + ((long long)(z0 + dz) * ny + y0 + dy) * nx + x0 + dx] =
@@ -991,14 +1042,12 @@ __global__ __launch_bounds__(128) void gs3d_kernel(const GsTile3 *tiles, const T
   }
 }
 
-// Operator by the stored rows on 3D tiles: r = mask (beta fw.*f + alpha (S u
-// + X u)) as in 2D; one block of 16 row groups per tile and right-hand side.
-// grid.x = tile, grid.y = right-hand side.
+// Operator by the stored rows on 3D tiles: r = mask (beta fw.*f + alpha S u);
+// the cross-patch part alpha X u follows in cross3d_kernel.  One block of 16
+// row groups per tile and right-hand side.  grid.x = tile, grid.y = right-hand
+// side.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void sp3d_kernel(const GsTile3 *tiles, const T *__restrict__ st,
-                                                   const int *__restrict__ cx_li,
-                                                   const int *__restrict__ cx_col,
-                                                   const T *__restrict__ cx_val,
                                                    const unsigned char *__restrict__ mask,
                                                    const T *__restrict__ u,
                                                    const T *__restrict__ f,
@@ -1016,12 +1065,6 @@ __global__ __launch_bounds__(256) void sp3d_kernel(const GsTile3 *tiles, const T
   const int x0 = tl.i0[0], y0 = tl.i0[1], z0 = tl.i0[2];
   load_window3<T, P>(tl, u, sU, tid, 256);
   for (int i = tid; i < NT; i += 256) sX[i] = (T)0;
-  __syncthreads();
-  if (tid < 64)
-    for (int e = tid; e < tl.cx_n; e += 64) {
-      const int q = tl.cx_off + e;
-      unsafeAtomicAdd(&sX[cx_li[q]], cx_val[q] * u[cx_col[q]]);
-    }
   const int g = tid >> 4, l16 = tid & 15;
   int soff[C];
 #pragma unroll
@@ -1039,7 +1082,7 @@ __global__ __launch_bounds__(256) void sp3d_kernel(const GsTile3 *tiles, const T
 #pragma unroll
     for (int c = 0; c < C; ++c) a[c] = sr[16 * c];
   }
-  __syncthreads();  // cross sums complete
+  __syncthreads();  // window and zeroed sums complete
   for (int li = g; li < NT; li += 16) {
     if (li + 16 < NT) {
       const T *sr = row_ptr(li + 16);
@@ -2124,9 +2167,23 @@ static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backwa
 template <typename T, int P>
 static void launch_gs3d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
   LevelArrays<T> &A = L.arr<T>();
-  gs3d_kernel<T, P><<<dim3(nrhs, cl.count), 128, 0, c.stream>>>(
-      cl.tiles3, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
-      backward ? 1 : 0, L.Ntorn);
+  gs3d_kernel<T, P><<<dim3(nrhs, cl.count), 512, 0, c.stream>>>(
+      cl.tiles3, A.stencil, A.invdiag, A.xsum, A.f, A.u, backward ? 1 : 0, L.Ntorn);
+}
+
+// couplings of the coupled rows r0 .. r1 (CSR order): xs = X u, or out +=
+// alpha mask X u
+template <typename T>
+static void launch_cross3d(Context &c, LevelData &L, const T *val, int r0, int r1, const T *u,
+                           T *out, bool add, T alpha, int nrhs) {
+  if (r1 <= r0) return;
+  dim3 grid((unsigned)((r1 - r0 + 255) / 256), nrhs);
+  if (add)
+    cross3d_kernel<T, true><<<grid, 256, 0, c.stream>>>(L.d_x_rows, L.d_x_ptr, L.d_x_col, val, r0,
+                                                        r1, L.d_mask, u, out, alpha, L.Ntorn);
+  else
+    cross3d_kernel<T, false><<<grid, 256, 0, c.stream>>>(L.d_x_rows, L.d_x_ptr, L.d_x_col, val, r0,
+                                                         r1, L.d_mask, u, out, alpha, L.Ntorn);
 }
 
 template <typename T>
@@ -2136,7 +2193,15 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs) {
   ts.n = 0;
   int nc = (int)L.gs.size();
   for (int ii = 0; ii < nc; ++ii) {
-    const GsClass &cl = L.gs[backward ? nc - 1 - ii : ii];
+    const int ci = backward ? nc - 1 - ii : ii;
+    const GsClass &cl = L.gs[ci];
+    if (c.d == 3 && ci % 8 == (backward ? 7 : 0)) {
+      // first class of a patch colour: its rows' cross couplings
+      LevelArrays<T> &A = L.arr<T>();
+      const int colr = ci / 8;
+      launch_cross3d<T>(c, L, A.x_val, L.x_cptr[colr], L.x_cptr[colr + 1], A.u, A.xsum, false,
+                        (T)0, nrhs);
+    }
     if (cl.count == 0) continue;
     ++ts.n;
     if (c.d == 3) {
@@ -2190,8 +2255,8 @@ template <typename T, int P>
 static void launch_sp3d(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u, const T *f,
                         const T *fw, T beta, T alpha, T *r, int nrhs) {
   sp3d_kernel<T, P><<<dim3(L.n_atiles, nrhs), 256, 0, c.stream>>>(
-      L.d_atiles3, A.stencil, L.d_gcx_li, L.d_gcx_col, A.gcx_val, L.d_mask, u, f, fw, beta, alpha,
-      r, L.Ntorn);
+      L.d_atiles3, A.stencil, L.d_mask, u, f, fw, beta, alpha, r, L.Ntorn);
+  launch_cross3d<T>(c, L, A.x_val, 0, L.x_n, u, r, true, alpha, nrhs);
 }
 
 template <typename T>
