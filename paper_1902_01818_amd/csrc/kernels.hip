@@ -156,6 +156,110 @@ __global__ void stencil_kernel(const PatchDev *pd, int K, const double *tabB, co
   st[tid] = ok ? vol_entry<D>(pt, tabB, tabD, gr, p, i, j) : 0.0;
 }
 
+// 3D stencil rows in two steps over a slab of element layers of one patch:
+// (1) the element stiffness matrices, one block per element: the metric at the
+// element's q^3 Gauss points and its 1D tables in LDS, then every entry
+// (a, b) of the (p+1)^3 x (p+1)^3 matrix summed over the points;
+// (2) every row entry (i, j) as the sum of K_e[i - e][j - e] over the common
+// elements e in a fixed order (z, y, x), so the rows do not depend on the
+// slab partition or on scheduling.
+template <int P>
+__global__ __launch_bounds__(256) void elem3d_kernel(const PatchDev *pd, int k, int ez0,
+                                                     const double *tabB, const double *tabD,
+                                                     GaussRule gr, double *Ke) {
+  constexpr int P1 = P + 1, Q = P + 1, NB = P1 * P1 * P1, NQ = Q * Q * Q;
+  __shared__ double sG[6][NQ];
+  __shared__ double sB[3][Q][P1], sD[3][Q][P1];
+  const PatchDev &pt = pd[k];
+  const int nelx = pt.nel[0], nely = pt.nel[1];
+  const long long le = blockIdx.x;
+  const int el[3] = {(int)(le % nelx), (int)(le / nelx % nely), ez0 + (int)(le / ((long long)nelx * nely))};
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 3 * Q * P1; e += 256) {
+    const int g = e / (Q * P1), r = e % (Q * P1), qq = r / P1, a = r % P1;
+    const size_t row = (size_t)pt.tab[g] + ((size_t)el[g] * Q + qq) * P1 + a;
+    sB[g][qq][a] = tabB[row];
+    sD[g][qq][a] = tabD[row];
+  }
+  for (int qi = tid; qi < NQ; qi += 256) {
+    const int qx = qi % Q, qy = qi / Q % Q, qz = qi / (Q * Q);
+    const int qd[3] = {qx, qy, qz};
+    double xh[3], w = 1.0;
+    for (int g = 0; g < 3; ++g) {
+      xh[g] = ((double)el[g] + gr.x[qd[g]]) / (double)pt.nel[g];
+      w *= gr.w[qd[g]] / (double)pt.nel[g];
+    }
+    double G[3][3];
+    metric<3>(pt.corners, xh, w, G);
+    sG[0][qi] = G[0][0];
+    sG[1][qi] = G[0][1];
+    sG[2][qi] = G[0][2];
+    sG[3][qi] = G[1][1];
+    sG[4][qi] = G[1][2];
+    sG[5][qi] = G[2][2];
+  }
+  __syncthreads();
+  double *out = Ke + le * (long long)(NB * NB);
+  for (int ent = tid; ent < NB * NB; ent += 256) {
+    const int a = ent / NB, b = ent % NB;
+    const int ax = a % P1, ay = a / P1 % P1, az = a / (P1 * P1);
+    const int bx = b % P1, by = b / P1 % P1, bz = b / (P1 * P1);
+    double sum = 0.0;
+    for (int qz = 0; qz < Q; ++qz)
+      for (int qy = 0; qy < Q; ++qy)
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+          const int qi = (qz * Q + qy) * Q + qx;
+          const double Bax = sB[0][qx][ax], Bay = sB[1][qy][ay], Baz = sB[2][qz][az];
+          const double Bbx = sB[0][qx][bx], Bby = sB[1][qy][by], Bbz = sB[2][qz][bz];
+          const double ga0 = sD[0][qx][ax] * Bay * Baz, ga1 = Bax * sD[1][qy][ay] * Baz,
+                       ga2 = Bax * Bay * sD[2][qz][az];
+          const double gb0 = sD[0][qx][bx] * Bby * Bbz, gb1 = Bbx * sD[1][qy][by] * Bbz,
+                       gb2 = Bbx * Bby * sD[2][qz][bz];
+          const double G00 = sG[0][qi], G01 = sG[1][qi], G02 = sG[2][qi];
+          const double G11 = sG[3][qi], G12 = sG[4][qi], G22 = sG[5][qi];
+          sum += ga0 * (G00 * gb0 + G01 * gb1 + G02 * gb2) + ga1 * (G01 * gb0 + G11 * gb1 + G12 * gb2) +
+                 ga2 * (G02 * gb0 + G12 * gb1 + G22 * gb2);
+        }
+    out[ent] = sum;
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void gather3d_kernel(const PatchDev *pd, int k, int iz0, int iz1,
+                                                       int ez0, const double *Ke, double *st) {
+  constexpr int P1 = P + 1, NB = P1 * P1 * P1, S1 = 2 * P + 1, S = S1 * S1 * S1;
+  constexpr int SP = (S + 15) / 16 * 16;
+  const PatchDev &pt = pd[k];
+  const int nx = pt.n[0], ny = pt.n[1], nz = pt.n[2];
+  const int nelx = pt.nel[0], nely = pt.nel[1], nelz = pt.nel[2];
+  const long long nrow = (long long)nx * ny * (iz1 - iz0);
+  const long long tid = blockIdx.x * 256LL + threadIdx.x;
+  if (tid >= nrow * SP) return;
+  const long long rl = tid / SP;
+  const int o = (int)(tid % SP);
+  const int ix = (int)(rl % nx), iy = (int)(rl / nx % ny), iz = iz0 + (int)(rl / ((long long)nx * ny));
+  const long long t = pt.off + ((long long)iz * ny + iy) * nx + ix;
+  double sum = 0.0;
+  if (o < S) {
+    const int jx = ix + o % S1 - P, jy = iy + o / S1 % S1 - P, jz = iz + o / (S1 * S1) - P;
+    if (jx >= 0 && jx < nx && jy >= 0 && jy < ny && jz >= 0 && jz < nz) {
+      const int zlo = max(max(iz, jz) - P, 0), zhi = min(min(iz, jz), nelz - 1);
+      const int ylo = max(max(iy, jy) - P, 0), yhi = min(min(iy, jy), nely - 1);
+      const int xlo = max(max(ix, jx) - P, 0), xhi = min(min(ix, jx), nelx - 1);
+      for (int ez = zlo; ez <= zhi; ++ez)
+        for (int ey = ylo; ey <= yhi; ++ey)
+          for (int ex = xlo; ex <= xhi; ++ex) {
+            const int a = ((iz - ez) * P1 + iy - ey) * P1 + ix - ex;
+            const int b = ((jz - ez) * P1 + jy - ey) * P1 + jx - ex;
+            const long long le = ((long long)(ez - ez0) * nely + ey) * nelx + ex;
+            sum += Ke[le * NB * NB + a * NB + b];
+          }
+    }
+  }
+  st[t * SP + o] = sum;
+}
+
 // Stencil rows of the 2D volume stiffness on an RT x RT tile of rows by sum
 // factorization, one element row at a time: for element row ey the metric
 // at its Gauss points is evaluated once (as in the operator kernel), the
@@ -2050,6 +2154,43 @@ static void launch_stencil2d(Context &c, LevelData &L, double *out) {
                                                             c.gr, out);
 }
 
+// element matrices of at most this many bytes at a time (z slabs of a patch)
+constexpr size_t ASSEMBLE3D_SCRATCH = (size_t)2 << 30;
+
+template <int P>
+static void assemble3d(Context &c, LevelData &L, double *out) {
+  constexpr int P1 = P + 1, NB = P1 * P1 * P1, S1 = 2 * P + 1;
+  constexpr int SP = (S1 * S1 * S1 + 15) / 16 * 16;
+  const size_t per_el = (size_t)NB * NB * sizeof(double);
+  // rows per slab: the slab's element layers (rows + P) fit the scratch
+  std::vector<int> rows_per(L.K);
+  size_t cap = 0;
+  for (int k = 0; k < L.K; ++k) {
+    const PatchDev &pt = L.pd[k];
+    const size_t layer = (size_t)pt.nel[0] * pt.nel[1] * per_el;
+    const int fit = (int)std::max<size_t>(1, ASSEMBLE3D_SCRATCH / layer);
+    const int R = std::max(1, fit - P);
+    rows_per[k] = R;
+    cap = std::max(cap, (size_t)std::min(pt.nel[2], R + P) * layer);
+  }
+  double *Ke = nullptr;
+  HIPCHK(hipMalloc((void **)&Ke, cap));
+  for (int k = 0; k < L.K; ++k) {
+    const PatchDev &pt = L.pd[k];
+    for (int iz0 = 0; iz0 < pt.n[2]; iz0 += rows_per[k]) {
+      const int iz1 = std::min(pt.n[2], iz0 + rows_per[k]);
+      const int ez0 = std::max(0, iz0 - P), ez1 = std::min(pt.nel[2] - 1, iz1 - 1);
+      const long long nel = (long long)pt.nel[0] * pt.nel[1] * (ez1 - ez0 + 1);
+      elem3d_kernel<P><<<(unsigned)nel, 256, 0, c.stream>>>(L.d_pd, k, ez0, L.d_tabB, L.d_tabD,
+                                                            c.gr, Ke);
+      const long long n = (long long)pt.n[0] * pt.n[1] * (iz1 - iz0) * SP;
+      gather3d_kernel<P><<<nblocks(n), 256, 0, c.stream>>>(L.d_pd, k, iz0, iz1, ez0, Ke, out);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c.stream));
+  HIPCHK(hipFree(Ke));
+}
+
 void k_stencil_assemble(Context &c, LevelData &L, double *out) {
   int S = 1;
   for (int d = 0; d < c.d; ++d) S *= (2 * c.p + 1);
@@ -2066,9 +2207,18 @@ void k_stencil_assemble(Context &c, LevelData &L, double *out) {
       case 8: launch_stencil2d<8, 4>(c, L, out); break;
       default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
     }
-  } else
+  } else if (c.arena.region || c.p > 4) {
+    // inside a lent region (no scratch allocation): per-entry quadrature
     stencil_kernel<3><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
                                                          L.Ntorn, out);
+  } else {
+    switch (c.p) {
+      case 1: assemble3d<1>(c, L, out); break;
+      case 2: assemble3d<2>(c, L, out); break;
+      case 3: assemble3d<3>(c, L, out); break;
+      case 4: assemble3d<4>(c, L, out); break;
+    }
+  }
   HIPCHK(hipGetLastError());
 }
 
