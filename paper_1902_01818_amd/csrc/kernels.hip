@@ -1126,14 +1126,24 @@ __global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T
         int wi, li;
         bool ok;
         row_of(s, wi, li, ok);
+        // every LDS value of the phase is read in one batch before the
+        // reduction: u + (b - a.u) d = (u + b d) - (a.u) d
+        T uv[CL];
+#pragma unroll
+        for (int c = 0; c < CL; ++c) uv[c] = sU[wi + soff[c]];
+        const T uold = sU[wi], bb = sB[li];
+        T dd = sD[li];
         T acc0 = 0, acc1 = 0;
 #pragma unroll
-        for (int c = 0; c < CL; c += 2) acc0 += buf[j][c] * sU[wi + soff[c]];
+        for (int c = 0; c < CL; c += 2) acc0 += buf[j][c] * uv[c];
 #pragma unroll
-        for (int c = 1; c < CL; c += 2) acc1 += buf[j][c] * sU[wi + soff[c]];
+        for (int c = 1; c < CL; c += 2) acc1 += buf[j][c] * uv[c];
+        T ubd = fma(bb, dd, uold);
+        T acc = acc0 + acc1;
+        asm volatile("" : "+v"(acc), "+v"(ubd), "+v"(dd));
         if (s + D < NPH) load_row(s + D, buf[j]);
-        const T acc = wave_sum(acc0 + acc1);
-        if (lane == 0 && ok) sU[wi] = sU[wi] + (sB[li] - acc) * sD[li];
+        acc = wave_sum(acc);
+        if (lane == 0 && ok) sU[wi] = fma(-acc, dd, ubd);
         __syncthreads();
       }
     }
