@@ -154,12 +154,10 @@ int igamg_footprint(const igamg_patches *patches, int degree, const igamg_option
  * smoother data (Section 5: SCMS factors, interface piece factorizations;
  * Section 4: Gauss-Seidel colouring) and the coarse Cholesky factorization.
  * degree >= 1; penalty_sigma > 0 (SIPG only).  Synchronizes `stream`.
- * dim 3 takes the SIPG space with the Gauss-Seidel or hybrid smoother,
- * degree 1..4 and at least two levels (the operator is applied from the
- * stored Gauss-Seidel rows); other 3D requests return IGAMG_EUNSUPPORTED.
+ * dim 3 takes degree 1..4 (higher degrees return IGAMG_EUNSUPPORTED).
  * Errors: IGAMG_EINVAL (dim, degree, non-positive Jacobian, conforming
  * interface mismatch), IGAMG_EUNSUPPORTED (flipped interface orientation,
- * Gauss-Seidel with the conforming space, the 3D limits above),
+ * Gauss-Seidel with the conforming space, 3D degree above 4),
  * IGAMG_ENOMEM, IGAMG_EHIP.
  * On success *out owns the context. */
 int igamg_setup(const igamg_patches *patches, int degree, double penalty_sigma,

@@ -7,6 +7,7 @@
 namespace igamg {
 
 constexpr int RED_BLOCKS = 256;  // partial sums per right-hand side of a reduction
+constexpr int VOL3D_TILE = 2;    // elements per direction of a 3D volume-operator tile
 
 // elementwise (batched: n values per right-hand side, nrhs of them)
 template <typename T>

@@ -668,6 +668,190 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const OpTile2 *tiles,
 }
 
 // ---------------------------------------------------------------------------
+// volume operator, 3D, sum factorization on a TE^3 element tile:
+// r += alpha * A_vol u (atomic accumulation of the tile's outputs).  Stages
+// (all in LDS): x-, y-, z-contractions of the u window with the value and
+// derivative tables give the parameter gradient at the tile's Gauss points;
+// the metric w |det J| J^-1 J^-T (float64 from the trilinear corners, rounded
+// to T) multiplies it; the transposed z-, y-, x-contractions return to the
+// unknowns.  grid.x = tile, grid.y = right-hand side.
+// ---------------------------------------------------------------------------
+template <typename T, int P, int TE>
+__global__ __launch_bounds__(256) void vol3d_kernel(const VolTile *tiles, const PatchDev *pd,
+                                                    const double *tabB, const double *tabD,
+                                                    GaussRule gr, const T *__restrict__ u,
+                                                    T *__restrict__ r,
+                                                    const unsigned char *__restrict__ mask,
+                                                    T alpha, long long vs) {
+  constexpr int Q = P + 1, P1 = P + 1, ND = TE + P, NQ = TE * Q;
+  constexpr int N2 = ND * ND, NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
+  __shared__ T sU[ND * N2];         // u window [z][y][x]
+  __shared__ T sA[2][N2 * NQ];      // [rz][ry][gx]
+  __shared__ T sB[3][ND * NQ2];     // [rz][gy][gx]
+  __shared__ T sV[3][NQ3];          // [gz][gy][gx]
+  __shared__ T sTB[3][NQ][P1], sTD[3][NQ][P1];
+  __shared__ double sC[8][3];
+  const VolTile tl = tiles[blockIdx.x];
+  const PatchDev &pt = pd[tl.patch];
+  const int tid = threadIdx.x;
+  const long long zo = (long long)blockIdx.y * vs;
+  u += zo;
+  r += zo;
+  int ne[3], nel[3];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    nel[g] = pt.nel[g];
+    ne[g] = min(TE, nel[g] - tl.e0[g]);
+  }
+  const int nx = pt.n[0], ny = pt.n[1];
+  const long long off = pt.off;
+  if (tid < 24) sC[tid / 3][tid % 3] = pt.corners[tid / 3][tid % 3];
+  for (int i = tid; i < 3 * NQ * P1; i += 256) {
+    // per-direction fields selected without indexing by a lane value
+    const int g = i / (NQ * P1), gq = i / P1 % NQ, a = i % P1;
+    const int neg = g == 0 ? ne[0] : (g == 1 ? ne[1] : ne[2]);
+    const int e0g = g == 0 ? tl.e0[0] : (g == 1 ? tl.e0[1] : tl.e0[2]);
+    const int tabg = g == 0 ? pt.tab[0] : (g == 1 ? pt.tab[1] : pt.tab[2]);
+    const bool ok = gq < neg * Q;
+    const size_t row = (size_t)tabg + ((size_t)e0g * Q + gq) * P1 + a;
+    sTB[g][gq][a] = ok ? (T)tabB[row] : (T)0;
+    sTD[g][gq][a] = ok ? (T)tabD[row] : (T)0;
+  }
+  for (int i = tid; i < ND * N2; i += 256) {
+    const int rz = i / N2, ry = i / ND % ND, rx = i % ND;
+    const bool ok = rz < ne[2] + P && ry < ne[1] + P && rx < ne[0] + P;
+    sU[i] = ok ? u[off + ((long long)(tl.e0[2] + rz) * ny + tl.e0[1] + ry) * nx + tl.e0[0] + rx]
+               : (T)0;
+  }
+  __syncthreads();
+  // x: A0 = values, A1 = derivatives
+  for (int i = tid; i < N2 * NQ; i += 256) {
+    const int rzy = i / NQ, gx = i % NQ, ex = gx / Q;
+    T a0 = 0, a1 = 0;
+#pragma unroll
+    for (int a = 0; a < P1; ++a) {
+      const T uv = sU[rzy * ND + ex + a];
+      a0 += sTB[0][gx][a] * uv;
+      a1 += sTD[0][gx][a] * uv;
+    }
+    sA[0][i] = a0;
+    sA[1][i] = a1;
+  }
+  __syncthreads();
+  // y: B0 = (val, val), B1 = (val, d), B2 = (d, val)
+  for (int i = tid; i < ND * NQ2; i += 256) {
+    const int rz = i / NQ2, gy = i / NQ % NQ, gx = i % NQ, ey = gy / Q;
+    T b0 = 0, b1 = 0, b2 = 0;
+#pragma unroll
+    for (int b = 0; b < P1; ++b) {
+      const int j = (rz * ND + ey + b) * NQ + gx;
+      b0 += sTB[1][gy][b] * sA[0][j];
+      b1 += sTD[1][gy][b] * sA[0][j];
+      b2 += sTB[1][gy][b] * sA[1][j];
+    }
+    sB[0][i] = b0;
+    sB[1][i] = b1;
+    sB[2][i] = b2;
+  }
+  __syncthreads();
+  // z: parameter gradient at the Gauss points, times the metric
+  for (int i = tid; i < NQ3; i += 256) {
+    const int gz = i / NQ2, gy = i / NQ % NQ, gx = i % NQ, ez = gz / Q;
+    T v0 = 0, v1 = 0, v2 = 0;
+    if (gx < ne[0] * Q && gy < ne[1] * Q && gz < ne[2] * Q) {
+      T ux = 0, uy = 0, uz = 0;
+#pragma unroll
+      for (int c = 0; c < P1; ++c) {
+        const int j = ((ez + c) * NQ + gy) * NQ + gx;
+        ux += sTB[2][gz][c] * sB[2][j];
+        uy += sTB[2][gz][c] * sB[1][j];
+        uz += sTD[2][gz][c] * sB[0][j];
+      }
+      const int gq[3] = {gx, gy, gz};
+      double xh[3], w = 1.0;
+#pragma unroll
+      for (int g = 0; g < 3; ++g) {
+        const int e = gq[g] / Q, q = gq[g] - e * Q;
+        // Gauss node and weight selected without indexing by a lane value
+        double xq = gr.x[0], wq = gr.w[0];
+#pragma unroll
+        for (int m = 1; m < Q; ++m)
+          if (q == m) {
+            xq = gr.x[m];
+            wq = gr.w[m];
+          }
+        xh[g] = ((double)(tl.e0[g] + e) + xq) / (double)nel[g];
+        w *= wq / (double)nel[g];
+      }
+      double G[3][3];
+      metric<3>(sC, xh, w, G);
+      v0 = (T)G[0][0] * ux + (T)G[0][1] * uy + (T)G[0][2] * uz;
+      v1 = (T)G[1][0] * ux + (T)G[1][1] * uy + (T)G[1][2] * uz;
+      v2 = (T)G[2][0] * ux + (T)G[2][1] * uy + (T)G[2][2] * uz;
+    }
+    sV[0][i] = v0;
+    sV[1][i] = v1;
+    sV[2][i] = v2;
+  }
+  __syncthreads();
+  // transposed z (into sB): C0 -> (Dx, By), C1 -> (Bx, Dy), C2 -> (Bx, By)
+  for (int i = tid; i < ND * NQ2; i += 256) {
+    const int rz = i / NQ2, gyx = i % NQ2;
+    T c0 = 0, c1 = 0, c2 = 0;
+    const int elo = max(0, rz - P), ehi = min(ne[2] - 1, rz);
+    for (int e = elo; e <= ehi; ++e) {
+      const int a = rz - e;
+#pragma unroll
+      for (int g = 0; g < Q; ++g) {
+        const int gz = e * Q + g, j = gz * NQ2 + gyx;
+        c0 += sTB[2][gz][a] * sV[0][j];
+        c1 += sTB[2][gz][a] * sV[1][j];
+        c2 += sTD[2][gz][a] * sV[2][j];
+      }
+    }
+    sB[0][i] = c0;
+    sB[1][i] = c1;
+    sB[2][i] = c2;
+  }
+  __syncthreads();
+  // transposed y (into sA): E0 -> Dx, E1 -> Bx
+  for (int i = tid; i < N2 * NQ; i += 256) {
+    const int rz = i / (ND * NQ), ry = i / NQ % ND, gx = i % NQ;
+    T e0 = 0, e1 = 0;
+    const int elo = max(0, ry - P), ehi = min(ne[1] - 1, ry);
+    for (int e = elo; e <= ehi; ++e) {
+      const int a = ry - e;
+#pragma unroll
+      for (int g = 0; g < Q; ++g) {
+        const int gy = e * Q + g, j = (rz * NQ + gy) * NQ + gx;
+        e0 += sTB[1][gy][a] * sB[0][j];
+        e1 += sTD[1][gy][a] * sB[1][j] + sTB[1][gy][a] * sB[2][j];
+      }
+    }
+    sA[0][i] = e0;
+    sA[1][i] = e1;
+  }
+  __syncthreads();
+  // transposed x and accumulation
+  for (int i = tid; i < ND * N2; i += 256) {
+    const int rz = i / N2, ry = i / ND % ND, rx = i % ND;
+    if (rz >= ne[2] + P || ry >= ne[1] + P || rx >= ne[0] + P) continue;
+    T y = 0;
+    const int elo = max(0, rx - P), ehi = min(ne[0] - 1, rx);
+    for (int e = elo; e <= ehi; ++e) {
+      const int a = rx - e;
+#pragma unroll
+      for (int g = 0; g < Q; ++g) {
+        const int gx = e * Q + g, j = (rz * ND + ry) * NQ + gx;
+        y += sTD[0][gx][a] * sA[0][j] + sTB[0][gx][a] * sA[1][j];
+      }
+    }
+    const long long t = off + ((long long)(tl.e0[2] + rz) * ny + tl.e0[1] + ry) * nx + tl.e0[0] + rx;
+    if (mask[t]) unsafeAtomicAdd(&r[t], alpha * y);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // glue (conforming): y <- sum of copies on every copy; grid.y = right-hand side
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -2279,10 +2463,25 @@ static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, in
       L.d_optiles, L.d_tabB, L.d_tabD, c.gr, u, r, L.d_mask, alpha, L.Ntorn, nrhs);
 }
 
+template <typename T, int P>
+static void launch_vol3d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
+  vol3d_kernel<T, P, VOL3D_TILE><<<dim3(L.n_vtiles, nrhs), 256, 0, c.stream>>>(
+      L.d_vtiles, L.d_pd, L.d_tabB, L.d_tabD, c.gr, u, r, L.d_mask, alpha, L.Ntorn);
+}
+
 template <typename T>
 void k_vol_apply(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
   TimeScope ts(c, "vol_apply", L.l);
-  if (c.d != 2) fail(IGAMG_EUNSUPPORTED, "3D volume operator not built");
+  if (c.d == 3) {
+    switch (c.p) {
+      case 1: launch_vol3d<T, 1>(c, L, u, r, alpha, nrhs); break;
+      case 2: launch_vol3d<T, 2>(c, L, u, r, alpha, nrhs); break;
+      case 3: launch_vol3d<T, 3>(c, L, u, r, alpha, nrhs); break;
+      case 4: launch_vol3d<T, 4>(c, L, u, r, alpha, nrhs); break;
+      default: fail(IGAMG_EUNSUPPORTED, "3D degree out of range 1..4");
+    }
+    return;
+  }
   switch (c.p) {
     case 1: launch_vol2d<T, 1, 8>(c, L, u, r, alpha, nrhs); break;
     case 2: launch_vol2d<T, 2, 8>(c, L, u, r, alpha, nrhs); break;

@@ -1399,16 +1399,7 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
   if (c.opt.operator_apply == IGAMG_APPLY_ROWS &&
       (c.opt.discretization != IGAMG_SIPG || !use_gs))
     fail(IGAMG_EUNSUPPORTED, "stored operator rows exist for SIPG with a Gauss-Seidel smoother only");
-  if (c.d == 3) {
-    // 3D: SIPG, Gauss-Seidel levels, operator from the stored rows
-    if (c.opt.discretization != IGAMG_SIPG)
-      fail(IGAMG_EUNSUPPORTED, "3D problems: SIPG discretization only");
-    if (c.opt.smoother == IGAMG_SMOOTHER_SCMS)
-      fail(IGAMG_EUNSUPPORTED, "3D problems: Gauss-Seidel or hybrid smoother");
-    if (c.opt.operator_apply == IGAMG_APPLY_SUMFACT)
-      fail(IGAMG_EUNSUPPORTED, "3D problems apply the operator from the stored rows");
-    if (degree > 4) fail(IGAMG_EUNSUPPORTED, "3D problems: degree 1..4");
-  }
+  if (c.d == 3 && degree > 4) fail(IGAMG_EUNSUPPORTED, "3D problems: degree 1..4");
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
@@ -1423,10 +1414,6 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
     }
   }
   build_topology(c);
-  // 3D levels apply the operator from Gauss-Seidel rows, which the coarsest
-  // level (direct solve) does not keep
-  if (c.d == 3 && level_elements(c).size() < 2)
-    fail(IGAMG_EUNSUPPORTED, "3D problems need two levels or more");
 }
 
 void problem_size(const igamg_patches *P, int degree, const igamg_options *o, long long *n,
@@ -1537,10 +1524,11 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     }
     // volume tiles
     std::vector<VolTile> vt;
-    int TE = vol_tile_2d(c.p);
+    const int TE = c.d == 2 ? vol_tile_2d(c.p) : VOL3D_TILE;
     for (int k = 0; k < c.K; ++k)
-      for (int e1 = 0; e1 < L.pd[k].nel[1]; e1 += TE)
-        for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, 0}});
+      for (int e2 = 0; e2 < (c.d == 3 ? L.pd[k].nel[2] : 1); e2 += TE)
+        for (int e1 = 0; e1 < L.pd[k].nel[1]; e1 += TE)
+          for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, e2}});
     L.n_vtiles = (int)vt.size();
     L.d_vtiles = c.arena.upload(vt, c.stream);
     if (c.d == 2) {
@@ -1736,7 +1724,15 @@ void kernel_model(const Context &c, const std::string &fam, int level, int nrhs,
   for (unsigned char x : L.if_cross) ncross += x;
   *bytes = 0;
   *flops = 0;
-  if (fam == "vol_apply") {
+  if (fam == "vol_apply" && c.d == 3) {
+    // per element: the three contractions and their transposes over the
+    // tile's Gauss points, the metric (~150 flops) and its product
+    double el = 0;
+    for (int k = 0; k < c.K; ++k) el += (double)L.pd[k].nel[0] * L.pd[k].nel[1] * L.pd[k].nel[2];
+    const double q4 = (double)q * q * q * q, q3 = (double)q * q * q;
+    *flops = nb * el * (32.0 * q4 + 170.0 * q3);
+    *bytes = 3.0 * wb * nt * nb;
+  } else if (fam == "vol_apply") {
     for (int k = 0; k < c.K; ++k) {
       const PatchDev &pt = L.pd[k];
       double Qx = (double)pt.nel[0] * q, Qy = (double)pt.nel[1] * q;

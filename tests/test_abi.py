@@ -79,14 +79,10 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
                        operator_apply="rows") == ig.EUNSUPPORTED
     cube = np.array([[[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)]], dtype=np.float64)
     e4 = np.array([[4, 4, 4]], dtype=np.int32)
-    # 3D: SIPG with the Gauss-Seidel or hybrid smoother, stored-row operator,
-    # two levels or more
-    assert _setup_code(ig, cube, e4, 2, smoother="scms") == ig.EUNSUPPORTED
-    assert _setup_code(ig, cube, e4, 2, conforming=True, smoother="scms") == ig.EUNSUPPORTED
-    assert _setup_code(ig, cube, e4, 2, smoother="gs", operator_apply="sumfact") == ig.EUNSUPPORTED
+    # 3D: degree 1..4; the space / smoother / operator-form rules of 2D
     assert _setup_code(ig, cube, e4, 5, smoother="gs") == ig.EUNSUPPORTED
-    assert _setup_code(ig, cube, np.array([[2, 2, 2]], dtype=np.int32), 2,
-                       smoother="gs") == ig.EUNSUPPORTED
+    assert _setup_code(ig, cube, e4, 2, conforming=True, smoother="gs") == ig.EUNSUPPORTED
+    assert _setup_code(ig, cube, e4, 2, smoother="scms", operator_apply="rows") == ig.EUNSUPPORTED
 
 
 def test_problem_size_matches_oracle_numbering(ig):

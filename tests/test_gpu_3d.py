@@ -1,7 +1,8 @@
-"""Parity of the 3D SIPG path (Gauss-Seidel or hybrid multigrid -- SCMS
-patch interiors by six mode-product stages, face / edge / vertex pieces by
-dense inverses --, operator from the stored rows) with the FP64 oracle,
-through the C ABI.
+"""Parity of the 3D path with the FP64 oracle, through the C ABI: SIPG with
+the Gauss-Seidel, hybrid and SCMS smoothers (SCMS patch interiors by six
+mode-product stages, face / edge / vertex pieces by dense inverses), the
+conforming space with SCMS, the operator from the stored rows or by sum
+factorization, and a one-level hierarchy.
 
 Inputs: trilinear 2 x 2 x 2 patch layouts with 5 % corner perturbation and
 checkerboard element counts (the C3 structure at reduced size), a 2 x 1 x 1
@@ -35,6 +36,16 @@ def _case(name, smoother="gs"):
         cfg = dict(workloads.config("c3", 8))
         cfg.update(corners=workloads.grid_corners((2, 1, 1), frac=0.05, seed=32),
                    elems=np.array([[8, 8, 8], [8, 8, 8]]), p=3)
+    elif name == "conforming/p2":
+        # matching interfaces (Assumption 2), glued unknowns
+        cfg = dict(workloads.config("c3", 8))
+        cfg.update(corners=workloads.grid_corners((2, 2, 2), frac=0.05, seed=33),
+                   elems=np.full((8, 3), 4), p=2, conforming=True)
+    elif name == "one-level/p3":
+        # 2 elements per direction: the direct solve is the whole hierarchy
+        cfg = dict(workloads.config("c3", 8))
+        cfg.update(corners=workloads.grid_corners((2, 1, 1), frac=0.05, seed=34),
+                   elems=np.full((2, 3), 2), p=3)
     else:
         raise KeyError(name)
     cfg = dict(cfg)
@@ -46,23 +57,30 @@ def _case(name, smoother="gs"):
 def _oracle(name, smoother):
     cfg = _case(name, smoother)
     return cfg, oracle.setup(cfg["corners"], cfg["elems"], cfg["p"], sigma=cfg["sigma"],
-                             conforming=False, smoother=smoother, tau=cfg["tau"],
+                             conforming=cfg["conforming"], smoother=smoother, tau=cfg["tau"],
                              delta=cfg["delta"])
 
 
-CASES = [("2x2x2/p2", "gs"), ("2x1x1/p3", "gs"), ("c3/8", "gs"),
-         ("2x2x2/p2", "hybrid"), ("2x1x1/p3", "hybrid"), ("c3/8", "hybrid")]
+# (layout, smoother, operator form: "auto" = stored rows on Gauss-Seidel
+# levels, "sumfact" = matrix-free sum factorization everywhere)
+CASES = [("2x2x2/p2", "gs", "auto"), ("2x1x1/p3", "gs", "auto"), ("c3/8", "gs", "auto"),
+         ("2x2x2/p2", "hybrid", "auto"), ("2x1x1/p3", "hybrid", "auto"),
+         ("c3/8", "hybrid", "auto"), ("2x2x2/p2", "hybrid", "sumfact"),
+         ("c3/8", "scms", "auto"), ("conforming/p2", "scms", "auto"),
+         ("one-level/p3", "hybrid", "auto")]
 
 
 def _to_gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
 
 
-@pytest.fixture(scope="module", params=CASES, ids=["%s/%s" % c for c in CASES])
+@pytest.fixture(scope="module", params=CASES, ids=["%s/%s/%s" % c for c in CASES])
 def pair(request):
     print("3d case", request.param, flush=True)
-    cfg, ob = _oracle(*request.param)
-    sv = gpu_solver(cfg)
+    name, smoother, apply = request.param
+    cfg, ob = _oracle(name, smoother)
+    cfg = dict(cfg, operator_apply=apply)
+    sv = gpu_solver(cfg, operator_apply=apply)
     yield cfg, ob, sv
     sv.close()
 
@@ -124,7 +142,7 @@ def test_solve_final(pair):
 def test_batch_matches_single(pair):
     cfg, ob, sv = pair
     F = np.stack([workloads.normal_rhs(ob.N, 70 + j) for j in range(3)])
-    sb = gpu_solver(cfg, max_rhs=3)
+    sb = gpu_solver(cfg, max_rhs=3, operator_apply=cfg["operator_apply"])
     try:
         U, infos = sb.solve(_to_gpu(F), tol=1e-8, maxit=200)
         U = U.cpu().numpy()
@@ -144,7 +162,7 @@ def test_float32_cycle(pair, outer):
     cfg, ob, sv = pair
     f = ob.load_manufactured()
     uo, its, _, _ = ob.pcg(f)
-    s32 = gpu_solver(cfg, precision="fp32", outer=outer)
+    s32 = gpu_solver(cfg, precision="fp32", outer=outer, operator_apply=cfg["operator_apply"])
     try:
         u, info = s32.solve(_to_gpu(f), tol=1e-8, maxit=200)
         ug = u.cpu().numpy()
@@ -163,11 +181,11 @@ def test_bf16_scms(pair):
     float64 stopping test decides; iterations bounded by twice the float64
     count."""
     cfg, ob, sv = pair
-    if cfg["smoother"] != "hybrid":
-        pytest.skip("bfloat16 applies to the SCMS stages of the hybrid smoother")
+    if cfg["smoother"] == "gs":
+        pytest.skip("bfloat16 applies to the SCMS stages")
     f = ob.load_manufactured()
     _, its, _, _ = ob.pcg(f)
-    sb = gpu_solver(cfg, precision="bf16", outer="fcg")
+    sb = gpu_solver(cfg, precision="bf16", outer="fcg", operator_apply=cfg["operator_apply"])
     try:
         u, info = sb.solve(_to_gpu(f), tol=1e-8, maxit=200)
         ug = u.cpu().numpy()
@@ -181,10 +199,13 @@ def test_bf16_scms(pair):
 def test_unsupported_3d_options():
     from paper_1902_01818_amd import igamg
     cfg = _case("2x2x2/p2")
-    for over in (dict(smoother="scms"), dict(conforming=True, smoother="scms"),
-                 dict(operator_apply="sumfact")):
+    for over in (dict(conforming=True, smoother="gs"), dict(conforming=True),
+                 dict(smoother="scms", operator_apply="rows")):
         with pytest.raises(igamg.IgamgError) as e:
             o = dict(smoother="gs")
             o.update(over)
             gpu_solver(cfg, **o)
         assert e.value.code == igamg.EUNSUPPORTED
+    with pytest.raises(igamg.IgamgError) as e:
+        gpu_solver(dict(cfg, p=5), smoother="gs")
+    assert e.value.code == igamg.EUNSUPPORTED
