@@ -127,7 +127,7 @@ def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2, outer=No
     return out
 
 
-def c3_leg(igamg, torch, workloads, precision="fp32", steps=2):
+def c3_leg(igamg, torch, workloads, precision="fp32", steps=2, operator_apply="auto"):
     """The 3D workload at full size (2x2x2 trilinear patches, 48/64 elements,
     p = 3, 1.65 M unknowns, manufactured right-hand side), hybrid cycle in
     the given arithmetic inside float64 flexible CG (float64: PCG), plus the
@@ -137,7 +137,8 @@ def c3_leg(igamg, torch, workloads, precision="fp32", steps=2):
     t0 = time.perf_counter()
     sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
                       conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
-                      delta=cfg["delta"], precision=precision, outer=outer)
+                      delta=cfg["delta"], precision=precision, outer=outer,
+                      operator_apply=operator_apply)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     f = sv.load_manufactured()
@@ -150,6 +151,7 @@ def c3_leg(igamg, torch, workloads, precision="fp32", steps=2):
     dt = (time.perf_counter() - t0) / steps
     out = dict(workload="3D SIPG, 2x2x2 trilinear patches, 48/64 elements, p=3, manufactured",
                dofs=sv.n_dofs, levels=sv.n_levels, precision=precision, outer=outer,
+               operator_apply=operator_apply,
                solves_per_s=1.0 / dt, ms_per_solve=dt * 1e3, setup_s=setup_s,
                memory_gib=sv.memory() / (1 << 30), iterations=info[0]["iterations"],
                true_rel_residual=info[0]["true_rel_residual"], converged=info[0]["converged"])
@@ -163,6 +165,15 @@ def c3_leg(igamg, torch, workloads, precision="fp32", steps=2):
         name = k.split("/")[0]
         fam[name] = fam.get(name, 0.0) + v["ms"]
     out["ms_per_family_timed_solve"] = {k: round(v, 3) for k, v in sorted(fam.items())}
+    # the finest level's operator kernels: average launch and model rate
+    top = sv.n_levels - 1
+    for famname in ("vol_apply", "stencil_apply"):
+        key = "%s/%d" % (famname, top)
+        if st.get(key, {}).get("launches"):
+            avg = st[key]["ms"] / 1e3 / st[key]["launches"]
+            b, fl = sv.kernel_model(famname, top, 1)
+            out["finest_" + famname] = dict(avg_us=avg * 1e6, model_gb_s=b / avg / 1e9,
+                                            model_tflop_s=fl / avg / 1e12)
     sv.close()
     return out
 
@@ -204,6 +215,9 @@ def main():
         out = {"c3": c3_leg(igamg, torch, workloads, precision="fp32")}
         print("bench: 3D workload timed (float32 cycle)", file=sys.stderr, flush=True)
         out["c3_fp64"] = c3_leg(igamg, torch, workloads, precision="fp64")
+        print("bench: 3D workload timed (float64 cycle)", file=sys.stderr, flush=True)
+        out["c3_sumfact"] = c3_leg(igamg, torch, workloads, precision="fp32",
+                                   operator_apply="sumfact")
         print(json.dumps(out))
         return
 
