@@ -196,6 +196,14 @@ int igamg_solve(igamg_ctx *ctx, const double *rhs, double *u, int nrhs, double t
  * Section 2), Gauss quadrature with p+1 points; f device [N]. */
 int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream);
 
+/* Discretization error ||u_h - prod sin(pi x)||_{L2(Omega)} of the finest-level
+ * coefficient vector u (device [N], compact ordering, caller-owned) against
+ * the exact solution of igamg_load_manufactured (Section 2, model problem),
+ * Gauss quadrature with p+3 points per element and direction, summed in a
+ * fixed order.  Writes *err_host (host); synchronizes `stream`; allocates and
+ * frees its own scratch.  Errors: IGAMG_EINVAL (null argument), IGAMG_EHIP. */
+int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stream);
+
 /* Device bytes owned by the context. */
 int igamg_memory(const igamg_ctx *ctx, size_t *bytes);
 

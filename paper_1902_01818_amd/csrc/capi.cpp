@@ -2,10 +2,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
+#include <vector>
 
 #include "context.h"
+#include "hostmath.h"
 #include "kernels.h"
 
 struct igamg_ctx {
@@ -184,6 +188,63 @@ int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream) {
     // every copy holds its patch's integral: the assembled value is their sum
     igamg::k_gather_compact(c.qq, L.N, c.d_fin_cp, c.d_fin_cidx, 1, f, L.Ntorn, 1, c.stream);
     HIPCHK(hipGetLastError());
+    return IGAMG_OK;
+  });
+}
+
+int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stream) {
+  return guarded([&] {
+    if (!ctx || !u || !err_host) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    igamg::Context &c = ctx->c;
+    c.stream = (hipStream_t)stream;
+    igamg::LevelData &L = c.lv.back();
+    // tables of the (p+3)-point rule per distinct element count
+    const igamg::GaussRule gq = igamg::gauss_rule(c.p + 3);
+    std::vector<double> tB;
+    std::vector<int> tab(3 * L.K, 0);
+    std::vector<long long> el_off{0};
+    std::map<int, int> tab_of;
+    for (int k = 0; k < L.K; ++k) {
+      long long ne = 1;
+      for (int g = 0; g < c.d; ++g) {
+        const int n = L.pd[k].nel[g];
+        ne *= n;
+        auto it = tab_of.find(n);
+        if (it == tab_of.end()) {
+          std::vector<double> B, D;
+          igamg::element_tables(n, c.p, gq, B, D);
+          it = tab_of.emplace(n, (int)tB.size()).first;
+          tB.insert(tB.end(), B.begin(), B.end());
+        }
+        tab[3 * k + g] = it->second;
+      }
+      el_off.push_back(el_off.back() + ne);
+    }
+    const long long nel = el_off.back();
+    double *d_tB = nullptr, *d_part = nullptr, *d_out = nullptr;
+    int *d_tab = nullptr;
+    long long *d_eloff = nullptr;
+    HIPCHK(hipMalloc((void **)&d_tB, tB.size() * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&d_tab, tab.size() * sizeof(int)));
+    HIPCHK(hipMalloc((void **)&d_eloff, el_off.size() * sizeof(long long)));
+    HIPCHK(hipMalloc((void **)&d_part, (size_t)nel * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&d_out, sizeof(double)));
+    HIPCHK(hipMemcpyAsync(d_tB, tB.data(), tB.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c.stream));
+    HIPCHK(hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice,
+                          c.stream));
+    HIPCHK(hipMemcpyAsync(d_eloff, el_off.data(), el_off.size() * sizeof(long long),
+                          hipMemcpyHostToDevice, c.stream));
+    const long long nt = L.Ntorn;
+    igamg::k_fill(c.x, 0.0, nt, c.stream);
+    igamg::k_scatter_compact(u, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, nt, 1, c.stream);
+    igamg::k_l2_error(c, L, c.x, d_eloff, d_tab, d_tB, gq, d_part, nel, d_out);
+    double e2 = 0.0;
+    HIPCHK(hipMemcpyAsync(&e2, d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    for (void *ptr : {(void *)d_tB, (void *)d_tab, (void *)d_eloff, (void *)d_part, (void *)d_out})
+      (void)hipFree(ptr);
+    *err_host = std::sqrt(e2);
     return IGAMG_OK;
   });
 }

@@ -25,6 +25,11 @@ void k_stencil_add(const int *rows, const int *slots, const double *vals, int n,
                    int S, hipStream_t s);
 void k_invdiag(const double *stencil, int S, int center, const unsigned char *mask, double *invd,
                long long n, hipStream_t s);
+// squared L2 error of torn coefficients ut against prod sin(pi x), summed in a
+// fixed order into out[0] (part: nel scratch values)
+void k_l2_error(Context &c, LevelData &L, const double *ut, const long long *el_off,
+                const int *tab, const double *tB, const GaussRule &gq, double *part,
+                long long nel, double *out);
 void k_load_manufactured(Context &c, LevelData &L, double *out);
 // in-place inverse of a dense SPD n x n matrix (blocked Gauss-Jordan);
 // bad[0] is set to 1 when a pivot is not positive (not SPD)

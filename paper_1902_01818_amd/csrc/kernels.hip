@@ -409,6 +409,80 @@ __global__ void invdiag_kernel(const double *st, int S, int center, const unsign
 }
 
 // (f, phi_i) for f = d pi^2 prod sin(pi x), gather over the support of phi_i
+// Squared L2 error of u_h (torn coefficients) against prod sin(pi x) on one
+// element per thread: qe-point Gauss rule per direction, 1D tables of all
+// basis values at those points (tab: offset of the element count's table per
+// patch and direction, rows [e][g][a]).  el_off: first element of each patch.
+template <int D>
+__global__ void l2err_kernel(const PatchDev *pd, int K, const long long *el_off,
+                             const int *tab, const double *tB, GaussRule gq, int p,
+                             const double *ut, double *part) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= el_off[K]) return;
+  int k = 0;
+  while (k + 1 < K && el_off[k + 1] <= t) ++k;
+  const PatchDev &pt = pd[k];
+  long long loc = t - el_off[k];
+  int e[3] = {0, 0, 0};
+  for (int d = 0; d < D; ++d) {
+    e[d] = (int)(loc % pt.nel[d]);
+    loc /= pt.nel[d];
+  }
+  const int q = gq.q, P1 = p + 1;
+  double sum = 0.0;
+  int g[3] = {0, 0, 0};
+  for (;;) {
+    double xh[D], w = 1.0;
+    const double *row[3];
+    for (int d = 0; d < D; ++d) {
+      xh[d] = ((double)e[d] + gq.x[g[d]]) / (double)pt.nel[d];
+      w *= gq.w[g[d]] / (double)pt.nel[d];
+      row[d] = tB + (size_t)tab[k * 3 + d] + ((size_t)e[d] * q + g[d]) * P1;
+    }
+    double uh = 0.0;
+    int a[3] = {0, 0, 0};
+    for (;;) {
+      double phi = 1.0;
+      long long idx = pt.off;
+      for (int d = 0; d < D; ++d) {
+        phi *= row[d][a[d]];
+        idx += (long long)(e[d] + a[d]) * pt.stride[d];
+      }
+      uh += phi * ut[idx];
+      int d = 0;
+      while (d < D && ++a[d] == P1) a[d++] = 0;
+      if (d == D) break;
+    }
+    double J[D][D], Ji[D][D], X[D];
+    multilinear_jac<D>(pt.corners, xh, J);
+    const double det = inverse<D>(J, Ji);
+    multilinear_map<D>(pt.corners, xh, X);
+    double ex = 1.0;
+    for (int d = 0; d < D; ++d) ex *= sin(M_PI * X[d]);
+    sum += w * (det < 0 ? -det : det) * (uh - ex) * (uh - ex);
+    int d = 0;
+    while (d < D && ++g[d] == q) g[d++] = 0;
+    if (d == D) break;
+  }
+  part[t] = sum;
+}
+
+// sum of n values by one block in a fixed order (strided partial sums, then a
+// tree over the 1024 partials)
+__global__ __launch_bounds__(1024) void sum_fixed_kernel(const double *x, long long n,
+                                                         double *out) {
+  __shared__ double sp[1024];
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 1024) s += x[i];
+  sp[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sp[threadIdx.x] += sp[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sp[0];
+}
+
 template <int D>
 __global__ void load_kernel(const PatchDev *pd, int K, const double *tabB, GaussRule gr, int p,
                             const unsigned char *mask, long long ntorn, double *out) {
@@ -2434,6 +2508,19 @@ void k_load_manufactured(Context &c, LevelData &L, double *out) {
   else
     load_kernel<3><<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, c.gr, c.p,
                                                           L.d_mask, L.Ntorn, out);
+}
+
+void k_l2_error(Context &c, LevelData &L, const double *ut, const long long *el_off,
+                const int *tab, const double *tB, const GaussRule &gq, double *part,
+                long long nel, double *out) {
+  if (c.d == 2)
+    l2err_kernel<2><<<nblocks(nel), BS, 0, c.stream>>>(L.d_pd, L.K, el_off, tab, tB, gq, c.p, ut,
+                                                       part);
+  else
+    l2err_kernel<3><<<nblocks(nel), BS, 0, c.stream>>>(L.d_pd, L.K, el_off, tab, tB, gq, c.p, ut,
+                                                       part);
+  sum_fixed_kernel<<<1, 1024, 0, c.stream>>>(part, nel, out);
+  HIPCHK(hipGetLastError());
 }
 
 template <typename T>

@@ -139,6 +139,16 @@ def test_solve_final(pair):
     assert np.linalg.norm(f - A @ ug) / np.linalg.norm(f) <= 1.01e-8
 
 
+def test_l2_error(pair):
+    """L2 error against the manufactured solution in 3D: same vector, library
+    and oracle quadrature agree to 1e-8 relative."""
+    cfg, ob, sv = pair
+    uo, _, _, _ = ob.pcg(ob.load_manufactured())
+    eg = sv.l2_error(_to_gpu(uo))
+    eo = ob.l2_error(uo)
+    assert abs(eg - eo) <= 1e-8 * eo, (eg, eo)
+
+
 def test_batch_matches_single(pair):
     cfg, ob, sv = pair
     F = np.stack([workloads.normal_rhs(ob.N, 70 + j) for j in range(3)])

@@ -82,3 +82,11 @@ def test_full_solve_reaches_tolerance(c3_full):
     # the hybrid cycle's iteration count is robust in h: the divided-by-8
     # layout takes 17 float64 iterations
     assert info[0]["iterations"] <= 20
+    # discretization error of the manufactured solution at h = 1/48..1/64,
+    # p = 3: O(h^4) (the oracle's pins fix order p+1 on small grids); the
+    # oracle's error on the divided-by-8 layout (h 8x larger) is 1.94e-6, so
+    # order p+1 = 4 predicts 1.94e-6 / 8^4 = 4.7e-10 here (measured 4.8e-10);
+    # allowed: within a factor 2 of that
+    err = sv.l2_error(u)
+    print("c3 full-size L2 error %.3e" % err, flush=True)
+    assert 0 < err < 2 * 1.94e-6 / 8 ** 4

@@ -97,3 +97,18 @@ def test_solve_final(pair):
     assert abs(info[0]["true_rel_residual"] - np.linalg.norm(f - A @ ug) / np.linalg.norm(f)) < 1e-12
     np.testing.assert_allclose(info[0]["history"][:len(hist)], hist[:len(info[0]["history"])],
                                rtol=1e-6, atol=1e-14)
+
+
+def test_l2_error(pair):
+    """L2 error against the manufactured solution (p+3 Gauss points) of the
+    oracle's solution and of a perturbed copy: the library's fixed-order sum
+    equals the oracle's quadrature up to rounding (the error is the
+    difference of two O(1) functions: 1e-8 relative)."""
+    cfg, ob, sv = pair
+    f = ob.load_manufactured()
+    uo, _, _, _ = ob.pcg(f)
+    rng = np.random.default_rng(13)
+    for u in (uo, uo + 1e-3 * rng.standard_normal(ob.N)):
+        eg = sv.l2_error(_to_gpu(u))
+        eo = ob.l2_error(u)
+        assert abs(eg - eo) <= 1e-8 * eo, (eg, eo)
