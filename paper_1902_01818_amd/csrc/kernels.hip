@@ -952,7 +952,7 @@ __global__ void glue_kernel(int ng, const int *ptr, const int *idx, T *y, long l
 // same tile: their stencil-row loads meet in the CU's L1 instead of each
 // going to L2.  grid.x = group of RBW right-hand sides, grid.y = tile.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int RBW>
+template <typename T, int P, int RBW, bool BWD>
 __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles,
                                                        const T *__restrict__ st,
                                                        const T *__restrict__ invd,
@@ -960,7 +960,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
                                                        const int *__restrict__ cx_col,
                                                        const T *__restrict__ cx_val,
                                                        const T *__restrict__ f, T *u,
-                                                       int backward, long long vs, int nrhs) {
+                                                       long long vs, int nrhs) {
   using T2 = typename Pair2<T>::type;
   constexpr int Q1 = P + 1, TT = 2 * Q1, W = TT + 2 * P;
   constexpr int S1 = 2 * P + 1, S = S1 * S1;
@@ -1046,7 +1046,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   // row of this lane's group in class s; rows outside the patch read the
   // tile origin (always inside) and are not updated
   auto row_ptr = [&](int s) {
-    const int ph = backward ? NPH - 1 - s : s;
+    const int ph = BWD ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
     const bool ok = ix < nx && iy < ny;
     const long long t = ok ? off + (long long)iy * nx + ix : off + (long long)y0 * nx + x0;
@@ -1065,7 +1065,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   for (int c = 0; c < C; ++c) soff[c] = sOff[l16 + 16 * c];
 #pragma unroll
   for (int s = 0; s < NPH; ++s) {
-    const int ph = backward ? NPH - 1 - s : s;
+    const int ph = BWD ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
     const int wi = (iy - wy0) * W + (ix - wx0);
     const int li = (iy - y0) * TT + (ix - x0);
@@ -1316,12 +1316,11 @@ __device__ inline T wave_sum(T v) {
 // neighbouring patches' values, another patch colour, constant during the
 // patch colour's launches; zero on rows without couplings) and 1/a_ii sit in
 // LDS.  grid.x = right-hand side, grid.y = tile.
-template <typename T, int P>
+template <typename T, int P, bool BWD>
 __global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T *__restrict__ st,
                                                    const T *__restrict__ invd,
                                                    const T *__restrict__ xs,
-                                                   const T *__restrict__ f, T *u, int backward,
-                                                   long long vs) {
+                                                   const T *__restrict__ f, T *u, long long vs) {
   using G = Tile3<P>;
   constexpr int Q1 = G::Q1, TT = G::TT, W = G::W, SP = G::SP, NPH = G::NPH;
   constexpr int CL = (SP + 63) / 64;           // slots per lane
@@ -1352,7 +1351,7 @@ __global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T
   // row of this wavefront in phase s; rows outside the patch read the tile
   // origin's row and are not updated
   auto row_of = [&](int s, int &wi, int &li, bool &ok) {
-    const int ph = backward ? NPH - 1 - s : s;
+    const int ph = BWD ? NPH - 1 - s : s;
     const int dx = ph % Q1 + ax, dy = ph / Q1 % Q1 + ay, dz = ph / (Q1 * Q1) + az;
     ok = x0 + dx < nx && y0 + dy < ny && z0 + dz < nz;
     wi = ((dz + P) * W + dy + P) * W + dx + P;
@@ -1376,6 +1375,8 @@ __global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T
   for (int j = 0; j < D; ++j)
     if (j < NPH) load_row(j, buf[j]);
   __syncthreads();
+  // fully unrolled: the phase offsets are compile-time constants
+#pragma unroll
   for (int s0 = 0; s0 < NPH; s0 += D) {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -2593,28 +2594,41 @@ void k_glue_sum(LevelData &L, T *y, int nrhs, hipStream_t s) {
 template void k_glue_sum<double>(LevelData &, double *, int, hipStream_t);
 template void k_glue_sum<float>(LevelData &, float *, int, hipStream_t);
 
+template <typename T, int P, int RBW, bool BWD>
+static void launch_gs2d_dir(Context &c, LevelData &L, const GsClass &cl, int nrhs) {
+  LevelArrays<T> &A = L.arr<T>();
+  dim3 grid((nrhs + RBW - 1) / RBW, cl.count);
+  gs2d_wave_kernel<T, P, RBW, BWD><<<grid, 64 * RBW, 0, c.stream>>>(
+      cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u, L.Ntorn, nrhs);
+}
+
+// the sweep direction is a template parameter: the unrolled class steps then
+// address their rows with compile-time offsets
 template <typename T, int P>
 static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
-  LevelArrays<T> &A = L.arr<T>();
-  if (nrhs == 1) {
-    gs2d_wave_kernel<T, P, 1><<<dim3(1, cl.count), 64, 0, c.stream>>>(
-        cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
-        backward ? 1 : 0, L.Ntorn, nrhs);
-    return;
-  }
   // batches: four right-hand sides of a tile per block
-  constexpr int RBW = 4;
-  dim3 grid((nrhs + RBW - 1) / RBW, cl.count);
-  gs2d_wave_kernel<T, P, RBW><<<grid, 64 * RBW, 0, c.stream>>>(
-      cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u,
-      backward ? 1 : 0, L.Ntorn, nrhs);
+  if (nrhs == 1) {
+    if (backward)
+      launch_gs2d_dir<T, P, 1, true>(c, L, cl, nrhs);
+    else
+      launch_gs2d_dir<T, P, 1, false>(c, L, cl, nrhs);
+  } else {
+    if (backward)
+      launch_gs2d_dir<T, P, 4, true>(c, L, cl, nrhs);
+    else
+      launch_gs2d_dir<T, P, 4, false>(c, L, cl, nrhs);
+  }
 }
 
 template <typename T, int P>
 static void launch_gs3d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
   LevelArrays<T> &A = L.arr<T>();
-  gs3d_kernel<T, P><<<dim3(nrhs, cl.count), 512, 0, c.stream>>>(
-      cl.tiles3, A.stencil, A.invdiag, A.xsum, A.f, A.u, backward ? 1 : 0, L.Ntorn);
+  if (backward)
+    gs3d_kernel<T, P, true><<<dim3(nrhs, cl.count), 512, 0, c.stream>>>(
+        cl.tiles3, A.stencil, A.invdiag, A.xsum, A.f, A.u, L.Ntorn);
+  else
+    gs3d_kernel<T, P, false><<<dim3(nrhs, cl.count), 512, 0, c.stream>>>(
+        cl.tiles3, A.stencil, A.invdiag, A.xsum, A.f, A.u, L.Ntorn);
 }
 
 // couplings of the coupled rows r0 .. r1 (CSR order): xs = X u, or out +=
