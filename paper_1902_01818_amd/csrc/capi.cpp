@@ -221,14 +221,12 @@ int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stre
       el_off.push_back(el_off.back() + ne);
     }
     const long long nel = el_off.back();
-    double *d_tB = nullptr, *d_part = nullptr, *d_out = nullptr;
-    int *d_tab = nullptr;
-    long long *d_eloff = nullptr;
-    HIPCHK(hipMalloc((void **)&d_tB, tB.size() * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&d_tab, tab.size() * sizeof(int)));
-    HIPCHK(hipMalloc((void **)&d_eloff, el_off.size() * sizeof(long long)));
-    HIPCHK(hipMalloc((void **)&d_part, (size_t)nel * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&d_out, sizeof(double)));
+    igamg::DeviceScratch s_tB, s_tab, s_eloff, s_part, s_out;
+    double *d_tB = s_tB.alloc<double>(tB.size());
+    int *d_tab = s_tab.alloc<int>(tab.size());
+    long long *d_eloff = s_eloff.alloc<long long>(el_off.size());
+    double *d_part = s_part.alloc<double>((size_t)nel);
+    double *d_out = s_out.alloc<double>(1);
     HIPCHK(hipMemcpyAsync(d_tB, tB.data(), tB.size() * sizeof(double), hipMemcpyHostToDevice,
                           c.stream));
     HIPCHK(hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -241,9 +239,7 @@ int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stre
     igamg::k_l2_error(c, L, c.x, d_eloff, d_tab, d_tB, gq, d_part, nel, d_out);
     double e2 = 0.0;
     HIPCHK(hipMemcpyAsync(&e2, d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipStreamSynchronize(c.stream));
-    for (void *ptr : {(void *)d_tB, (void *)d_tab, (void *)d_eloff, (void *)d_part, (void *)d_out})
-      (void)hipFree(ptr);
+    HIPCHK(hipStreamSynchronize(c.stream));  // scratch freed at scope exit
     *err_host = std::sqrt(e2);
     return IGAMG_OK;
   });

@@ -68,6 +68,22 @@ struct Arena {
   }
 };
 
+// Device scratch owned for one scope (freed also when an error unwinds it).
+struct DeviceScratch {
+  void *p = nullptr;
+  DeviceScratch() = default;
+  DeviceScratch(const DeviceScratch &) = delete;
+  DeviceScratch &operator=(const DeviceScratch &) = delete;
+  template <typename T>
+  T *alloc(size_t n) {
+    HIPCHK(hipMalloc(&p, n * sizeof(T) > 0 ? n * sizeof(T) : 1));
+    return (T *)p;
+  }
+  ~DeviceScratch() {
+    if (p) (void)hipFree(p);
+  }
+};
+
 // Resources a caller may lend to a context (serving runtime): a device region
 // for all arrays and pinned host memory for the scalar read-back.
 struct Lent {

@@ -84,12 +84,12 @@ struct GsTile {
 };
 
 // Gauss-Seidel tile of a 3D patch (2(p+1) unknowns per direction), with the
-// fields of its patch that the kernels need.
+// fields of its patch that the kernels need (the cross-patch couplings of 3D
+// levels are a CSR over the coupled rows, not per tile).
 struct GsTile3 {
-  long long off;     // patch offset in the level vector
-  int n[3];          // patch tensor extents
-  int i0[3];         // first unknown of the tile
-  int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
+  long long off;  // patch offset in the level vector
+  int n[3];       // patch tensor extents
+  int i0[3];      // first unknown of the tile
 };
 
 // Two chained products on a block of 16 rows (fast-diagonalization step of the

@@ -2442,8 +2442,8 @@ static void assemble3d(Context &c, LevelData &L, double *out) {
     rows_per[k] = R;
     cap = std::max(cap, (size_t)std::min(pt.nel[2], R + P) * layer);
   }
-  double *Ke = nullptr;
-  HIPCHK(hipMalloc((void **)&Ke, cap));
+  DeviceScratch ke;
+  double *Ke = ke.alloc<double>(cap / sizeof(double));
   for (int k = 0; k < L.K; ++k) {
     const PatchDev &pt = L.pd[k];
     for (int iz0 = 0; iz0 < pt.n[2]; iz0 += rows_per[k]) {
@@ -2456,8 +2456,7 @@ static void assemble3d(Context &c, LevelData &L, double *out) {
       gather3d_kernel<P><<<nblocks(n), 256, 0, c.stream>>>(L.d_pd, k, iz0, iz1, ez0, Ke, out);
     }
   }
-  HIPCHK(hipStreamSynchronize(c.stream));
-  HIPCHK(hipFree(Ke));
+  HIPCHK(hipStreamSynchronize(c.stream));  // the scratch is freed at scope exit
 }
 
 void k_stencil_assemble(Context &c, LevelData &L, double *out) {

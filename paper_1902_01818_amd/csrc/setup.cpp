@@ -1143,7 +1143,7 @@ static void build_gs3(Context &c, LevelData &L, bool keep64) {
             for (int b0 = 0; b0 < nb[0]; ++b0) {
               if (((b0 & 1) | ((b1 & 1) << 1) | ((b2 & 1) << 2)) != par) continue;
               tiles.push_back(GsTile3{pt.off, {pt.n[0], pt.n[1], pt.n[2]},
-                                      {b0 * T, b1 * T, b2 * T}, 0, 0});
+                                      {b0 * T, b1 * T, b2 * T}});
             }
       }
       GsClass cl;
