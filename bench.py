@@ -167,6 +167,14 @@ def c3_leg(igamg, torch, workloads, precision="fp32", steps=2, operator_apply="a
     out["ms_per_family_timed_solve"] = {k: round(v, 3) for k, v in sorted(fam.items())}
     # the finest level's operator kernels: average launch and model rate
     top = sv.n_levels - 1
+    key = "scms/%d" % top
+    if st.get(key, {}).get("launches"):
+        avg = st[key]["ms"] / 1e3 / st[key]["launches"]
+        _, fl = sv.kernel_model("scms", top, 1)
+        peak = MFMA_PEAK["bf16" if precision == "bf16" else precision]
+        out["scms_mfma"] = dict(kernel=key, bound="mfma", achieved=fl / avg / 1e12, peak=peak,
+                                unit="TFLOP/s", frac=fl / avg / 1e12 / peak,
+                                avg_application_us=avg * 1e6, model_flops_per_application=fl)
     for famname in ("vol_apply", "stencil_apply"):
         key = "%s/%d" % (famname, top)
         if st.get(key, {}).get("launches"):
@@ -218,6 +226,10 @@ def main():
         print("bench: 3D workload timed (float64 cycle)", file=sys.stderr, flush=True)
         out["c3_sumfact"] = c3_leg(igamg, torch, workloads, precision="fp32",
                                    operator_apply="sumfact")
+        print("bench: 3D workload timed (matrix-free operator)", file=sys.stderr, flush=True)
+        out["c3_bf16_scms"] = c3_leg(igamg, torch, workloads, precision="bf16")
+        out["mixed_speedup"] = {k: out[k]["solves_per_s"] / out["c3_fp64"]["solves_per_s"]
+                                for k in ("c3", "c3_bf16_scms")}
         print(json.dumps(out))
         return
 
