@@ -1043,14 +1043,16 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   // tiles with more than 512 cross couplings (not produced by the layouts here)
   for (int e = 64 * 8 + lane; e < tl.cx_n; e += 64)
     unsafeAtomicAdd(&sBD[cx_li[tl.cx_off + e]].x, -cx_val[tl.cx_off + e] * u[cx_col[tl.cx_off + e]]);
-  // row of this lane's group in class s; rows outside the patch read the
-  // tile origin (always inside) and are not updated
+  // row of this lane's group in class s: a compile-time offset from the
+  // group's first row.  Rows of a ragged tile outside the patch fall on later
+  // rows or on the zero padding past the level's end (never beyond it: at
+  // most a tile height of rows plus a tile width past the patch) and are
+  // not updated.
+  const T *rowbase = st + (off + (long long)(y0 + ay) * nx + x0 + ax) * SP + l16;
+  const long long nxSP = (long long)nx * SP;
   auto row_ptr = [&](int s) {
     const int ph = BWD ? NPH - 1 - s : s;
-    const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
-    const bool ok = ix < nx && iy < ny;
-    const long long t = ok ? off + (long long)iy * nx + ix : off + (long long)y0 * nx + x0;
-    return st + t * SP + l16;
+    return rowbase + (ph / Q1) * nxSP + (ph % Q1) * SP;
   };
   T buf[D][C];
 #pragma unroll

@@ -1598,9 +1598,19 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     const bool need_st = gs_rows || (sipg && (l == 0 || use_scms));
     double *st64 = nullptr, *id64 = nullptr;
     std::vector<void *> tmp;
+    // 2D Gauss-Seidel rows are padded past the level's end: the rows of a
+    // ragged tile that lie outside their patch then read padding instead of
+    // being clamped (they are never applied)
+    long long gs_pad = 0;
+    if (gs_rows && c.d == 2) {
+      int maxnx = 0;
+      for (const PatchDev &pt : L.pd) maxnx = std::max(maxnx, pt.n[0]);
+      gs_pad = (long long)c.opt.gs_tile * (maxnx + 1);
+    }
     if (need_st) {
       if (gs_rows && (!f32 || keep64)) {
-        st64 = L.a64.stencil = c.arena.alloc<double>((size_t)L.Ntorn * SP);
+        st64 = L.a64.stencil = c.arena.alloc<double>((size_t)(L.Ntorn + gs_pad) * SP);
+        if (gs_pad) k_fill<double>(st64 + (size_t)L.Ntorn * SP, 0.0, gs_pad * SP, c.stream);
         id64 = L.a64.invdiag = c.arena.alloc<double>(L.Ntorn);
       } else if (c.arena.region) {
         // lent region: the float64 staging stays inside it (counted in the footprint)
@@ -1646,7 +1656,8 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       build_maps(c, L, &c.d_c0_cp, &c.d_c0_cidx);
     }
     if (gs_rows && f32) {
-      L.a32.stencil = c.arena.alloc<float>((size_t)L.Ntorn * SP);
+      L.a32.stencil = c.arena.alloc<float>((size_t)(L.Ntorn + gs_pad) * SP);
+      if (gs_pad) k_fill<float>(L.a32.stencil + (size_t)L.Ntorn * SP, 0.0f, gs_pad * SP, c.stream);
       L.a32.invdiag = c.arena.alloc<float>(L.Ntorn);
       k_convert<double, float>(st64, nullptr, L.a32.stencil, (long long)L.Ntorn * SP, 1, c.stream);
       k_convert<double, float>(id64, nullptr, L.a32.invdiag, L.Ntorn, 1, c.stream);
@@ -1853,6 +1864,13 @@ size_t estimate_footprint(const igamg_patches *P, int degree, const igamg_option
   // float32 setup assembles the stencils in float64 first: freed afterwards
   // with driver allocations, kept inside a lent region (every level)
   if (gs && wb == 4.0) bytes += all_levels * 8.0 * (SP + 1);
+  // padding rows past the end of the 2D Gauss-Seidel rows (one tile height
+  // of the widest patch per level; levels halve, so twice the finest bound)
+  if (gs && d == 2) {
+    int maxn = 0;
+    for (int k = 0; k < P->n_patches; ++k) maxn = std::max(maxn, P->elems[(size_t)k * d] + p);
+    bytes += 2.0 * (2.0 * (p + 1)) * (maxn + 1) * SP * (wb + (wb == 4.0 ? 8.0 : 0.0));
+  }
   // margin for the terms estimated from counts (interface lists, tiles)
   return (size_t)(bytes * 1.08) + (32u << 20);
 }
