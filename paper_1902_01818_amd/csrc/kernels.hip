@@ -1062,20 +1062,24 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     for (int c = 0; c < C; ++c) buf[s][c] = srow[16 * c];
   }
   __syncthreads();
-  int soff[C];
+  // LDS addresses of this lane's slots at the group's first row; a class adds
+  // a compile-time offset
+  const T *ub[C];
+  const int wl = (ay + P) * W + ax + P;
 #pragma unroll
-  for (int c = 0; c < C; ++c) soff[c] = sOff[l16 + 16 * c];
+  for (int c = 0; c < C; ++c) ub[c] = sU + wl + sOff[l16 + 16 * c];
+  T *uw = sU + wl;
+  const T2 *bdl = sBD + ay * TT + ax;
 #pragma unroll
   for (int s = 0; s < NPH; ++s) {
     const int ph = BWD ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
-    const int wi = (iy - wy0) * W + (ix - wx0);
-    const int li = (iy - y0) * TT + (ix - x0);
+    const int cw = (ph / Q1) * W + ph % Q1, cl = (ph / Q1) * TT + ph % Q1;
     T uv[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) uv[c] = sU[wi + soff[c]];
-    const T uold = sU[wi];
-    const T2 bd = sBD[li];
+    for (int c = 0; c < C; ++c) uv[c] = ub[c][cw];
+    const T uold = uw[cw];
+    const T2 bd = bdl[cl];
     // two independent partial sums halve the dependent multiply-add chain
     T acc0 = 0, acc1 = 0;
 #pragma unroll
@@ -1094,7 +1098,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
       for (int c = 0; c < C; ++c) buf[s % D][c] = srow[16 * c];
     }
     acc = row16_scan(acc);
-    if (l16 == 15 && ix < nx && iy < ny) sU[wi] = fma(-acc, dinv, ubd);
+    if (l16 == 15 && ix < nx && iy < ny) uw[cw] = fma(-acc, dinv, ubd);
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
   }
