@@ -42,8 +42,7 @@ template <typename T>
 void scms_step(Context &c, LevelData &L, int nb) {
   LevelArrays<T> &A = L.arr<T>();
   residual<T>(c, L, A.u, A.f, A.r, nb);
-  k_scms_interior<T>(c, L, nb);
-  k_pieces<T>(c, L, nb);
+  if (!k_scms_interior<T>(c, L, nb)) k_pieces<T>(c, L, nb);
 }
 
 template <typename T>

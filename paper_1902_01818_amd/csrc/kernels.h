@@ -59,8 +59,10 @@ void k_stencil_apply(Context &c, LevelData &L, const LevelArrays<T> &A, const T 
 // smoothers (on L.arr<T>().f / .u / .r)
 template <typename T>
 void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs);
+// patch interiors; returns true when the interface pieces ran in the same
+// launches (then k_pieces is not called for this step)
 template <typename T>
-void k_scms_interior(Context &c, LevelData &L, int nrhs);
+bool k_scms_interior(Context &c, LevelData &L, int nrhs);
 template <typename T>
 void k_pieces(Context &c, LevelData &L, int nrhs);
 

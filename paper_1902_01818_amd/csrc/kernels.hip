@@ -1691,12 +1691,65 @@ __device__ inline void rowblock_mfma(const T *sA, int lda, const T *__restrict__
   }
 }
 
+// Interface pieces run as extra blocks of the first fused SCMS launch (they
+// read the same residual and write only piece unknowns, the first stage only
+// its scratch): block (piece, 64-row block) of u[copies] += scale inv r.
+template <typename T>
+struct PieceArgs {
+  const PieceDev *pieces;
+  const int *idx, *cp, *cidx;
+  const T *inv;
+  const T *r;
+  T *u;
+  T scale;
+  long long vs;
+  int n_pieces;
+};
+
+// rows row0..row0+63 of one piece with 256 threads: wavefront w sums the
+// columns j = w (mod 4) (lane = row), the four partial sums added in order;
+// sm: dynamic LDS of at least n + 256 values
+template <typename T>
+__device__ inline void piece_rows256(const PieceArgs<T> &pa, int piece, int row0, T *sm) {
+  const PieceDev pc = pa.pieces[piece];
+  const int n = pc.n;
+  if (row0 >= n) return;  // uniform over the block
+  T *spart = sm + n;  // 4 x 64 partial sums after the gathered residual (dynamic LDS)
+  const T *r = pa.r + (long long)blockIdx.x * pa.vs;
+  T *u = pa.u + (long long)blockIdx.x * pa.vs;
+  for (int j = threadIdx.x; j < n; j += 256) sm[j] = r[pa.idx[pc.idx_off + j]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = row0 + lane;
+  T s0 = 0, s1 = 0;
+  if (i < n) {
+    const T *col = pa.inv + pc.inv_off + i;
+    int j = w;
+    for (; j + 4 < n; j += 8) {
+      s0 += col[(long long)j * n] * sm[j];
+      s1 += col[(long long)(j + 4) * n] * sm[j + 4];
+    }
+    if (j < n) s0 += col[(long long)j * n] * sm[j];
+  }
+  spart[w * 64 + lane] = s0 + s1;
+  __syncthreads();
+  if (w == 0 && i < n) {
+    const T y = (spart[lane] + spart[64 + lane]) + (spart[128 + lane] + spart[192 + lane]);
+    for (int c = pa.cp[pc.cp_off + i]; c < pa.cp[pc.cp_off + i + 1]; ++c) u[pa.cidx[c]] += pa.scale * y;
+  }
+}
+
 template <typename T, bool BF, int NJ>
-__global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int lda) {
+__global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int n_items, int lda,
+                                                   PieceArgs<T> pa) {
   using A4 = typename MfAcc<T>::type;
   constexpr int LDZ = Fd2mShape<NJ, BF>::LDZ;
   extern __shared__ char smraw[];
   T *sm = (T *)smraw;
+  if ((int)blockIdx.z >= n_items) {
+    piece_rows256<T>(pa, blockIdx.z - n_items, blockIdx.y * 64, sm);
+    return;
+  }
   const Fd2Item<T> it = items[blockIdx.z];
   const int i0 = blockIdx.y * 16;
   if (i0 >= it.rows) return;
@@ -2772,8 +2825,21 @@ static void launch_fd2m(Context &c, LevelData &L, int stage, int nrhs) {
       hipFuncSetAttribute((const void *)fd2m_kernel<T, BF, NJ>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   HIPCHK(lds_set);
-  dim3 grid(nrhs, (L.fd_rows + 15) / 16, L.n_fd);
-  fd2m_kernel<T, BF, NJ><<<grid, 256, lds, c.stream>>>(L.arr<T>().fd[stage], lda);
+  // the first stage also runs the interface pieces (extra blocks along z)
+  PieceArgs<T> pa{};
+  int gy = (L.fd_rows + 15) / 16, gz = L.n_fd;
+  size_t shm = lds;
+  if (stage == 0 && L.n_pieces > 0) {
+    LevelArrays<T> &A = L.arr<T>();
+    pa = PieceArgs<T>{L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, A.piece_inv, A.r,
+                      A.u, (T)c.opt.damping_tau, L.Ntorn, L.n_pieces};
+    gy = std::max(gy, (L.max_piece + 63) / 64);
+    gz += L.n_pieces;
+    shm = std::max(shm, (size_t)(L.max_piece + 4 * 64) * sizeof(T));
+    if (shm > 160 * 1024) fail(IGAMG_EUNSUPPORTED, "interface piece too large for the SCMS kernel");
+  }
+  dim3 grid(nrhs, gy, gz);
+  fd2m_kernel<T, BF, NJ><<<grid, 256, shm, c.stream>>>(L.arr<T>().fd[stage], L.n_fd, lda, pa);
 }
 
 #ifndef FD_STAGED_MIN
@@ -2816,21 +2882,22 @@ static void scms_staged3(Context &c, LevelData &L, int nrhs) {
 }
 
 template <typename T>
-void k_scms_interior(Context &c, LevelData &L, int nrhs) {
+bool k_scms_interior(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "scms", L.l);
-  if (L.n_fd == 0) return;
+  if (L.n_fd == 0) return false;
   if (c.d == 3) {
     if constexpr (sizeof(T) == 4) {
       if (c.bf16_scms()) {
         scms_staged3<float, true>(c, L, nrhs);
-        return;
+        return false;
       }
     }
     scms_staged3<T, false>(c, L, nrhs);
-    return;
+    return false;
   }
   // the fused form re-reads each right-hand side's operand once per 16-row
-  // block; past this much re-read work the four-stage form is faster
+  // block; past this much re-read work the four-stage form is faster.  The
+  // fused form runs the interface pieces in its first launch (returns true).
   const bool staged = (double)L.fd_work * nrhs >= FD_STAGED_MIN;
   if constexpr (sizeof(T) == 4) {
     if (c.bf16_scms()) {
@@ -2838,16 +2905,17 @@ void k_scms_interior(Context &c, LevelData &L, int nrhs) {
         scms_staged<float, true>(c, L, nrhs);
       else
         scms_mfma<float, true>(c, L, nrhs);
-      return;
+      return !staged;
     }
   }
   if (staged)
     scms_staged<T, false>(c, L, nrhs);
   else
     scms_mfma<T, false>(c, L, nrhs);
+  return !staged;
 }
-template void k_scms_interior<double>(Context &, LevelData &, int);
-template void k_scms_interior<float>(Context &, LevelData &, int);
+template bool k_scms_interior<double>(Context &, LevelData &, int);
+template bool k_scms_interior<float>(Context &, LevelData &, int);
 
 template <typename T>
 void k_pieces(Context &c, LevelData &L, int nrhs) {
