@@ -127,6 +127,65 @@ def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2, outer=No
     return out
 
 
+def c1_leg(igamg, torch, workloads, steps=20, batch=1000):
+    """The conforming 2x2 workload (p = 2, 16 elements, SCMS V(1,1), float64
+    PCG): single-solve and V-cycle rates, a batch of `batch` right-hand sides
+    solved together, and the L2 error of the manufactured solution on a
+    ladder of element counts with the observed order."""
+    cfg = workloads.config("c1")
+    opts = dict(conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
+                delta=cfg["delta"])
+    sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"], **opts)
+    f = sv.load_manufactured()
+    u, info = sv.solve(f, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, info = sv.solve(f, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    v = torch.zeros_like(f)
+    sv.vcycle(f, v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10 * steps):
+        sv.vcycle(f, v)
+    torch.cuda.synchronize()
+    dv = (time.perf_counter() - t0) / (10 * steps)
+    out = dict(workload="conforming 2x2 identity patches, p=2, 16 elements, SCMS V(1,1), "
+                        "manufactured", dofs=sv.n_dofs, levels=sv.n_levels,
+               iterations=info[0]["iterations"], solves_per_s=1.0 / dt, vcycles_per_s=1.0 / dv,
+               l2_error=sv.l2_error(u))
+    sv.close()
+    # many instances of the problem at once: one right-hand side each
+    sb = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"], max_rhs=batch, **opts)
+    F = torch.from_numpy(np.stack([workloads.normal_rhs(sb.n_dofs, 6000 + j)
+                                   for j in range(batch)])).cuda()
+    U, infos = sb.solve(F, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, infos = sb.solve(F, tol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    out["batched"] = dict(rhs=batch, solves_per_s=batch / (time.perf_counter() - t0),
+                          iterations_max=max(i["iterations"] for i in infos),
+                          all_converged=all(i["converged"] for i in infos))
+    sb.close()
+    # L2 error ladder (order p+1 = 3 expected)
+    ladder = []
+    for ne in (4, 8, 16, 32, 64):
+        el = np.full((4, 2), ne)
+        s2 = igamg.Solver(cfg["corners"], el, cfg["p"], cfg["sigma"], **opts)
+        g = s2.load_manufactured()
+        w, _ = s2.solve(g, tol=1e-12, maxit=200)
+        ladder.append((ne, s2.l2_error(w)))
+        s2.close()
+    out["l2_ladder"] = [dict(elements=ne, l2_error=e,
+                             order=(None if i == 0 else
+                                    float(np.log2(ladder[i - 1][1] / e))))
+                        for i, (ne, e) in enumerate(ladder)]
+    return out
+
+
 def c3_leg(igamg, torch, workloads, precision="fp32", steps=2, operator_apply="auto"):
     """The 3D workload at full size (2x2x2 trilinear patches, 48/64 elements,
     p = 3, 1.65 M unknowns, manufactured right-hand side), hybrid cycle in
@@ -199,6 +258,9 @@ def main():
     ap.add_argument("--c4-only", action="store_true",
                     help="diagnostic: run only the 64-column p = 6 legs (float32 cycle, bf16 "
                          "SCMS) and print their results (not the benchmark line)")
+    ap.add_argument("--c1-only", action="store_true",
+                    help="diagnostic: run only the conforming 2x2 workload (rates, a batch of "
+                         "1000 right-hand sides, L2 error ladder) and print its results")
     ap.add_argument("--c3-only", action="store_true",
                     help="diagnostic: run only the full-size 3D workload (float32 and float64 "
                          "cycles) and print its results (not the benchmark line)")
@@ -218,6 +280,10 @@ def main():
     import torch
     import workloads
     from paper_1902_01818_amd import igamg
+
+    if args.c1_only:
+        print(json.dumps({"c1": c1_leg(igamg, torch, workloads)}))
+        return
 
     if args.c3_only:
         out = {"c3": c3_leg(igamg, torch, workloads, precision="fp32")}
