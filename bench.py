@@ -252,6 +252,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-cycle run")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+                    help="device memory the serving runtime admits requests into")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests of the serving sample (0 = skip)")
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-column p = 6 workload")
@@ -456,8 +458,8 @@ def main():
     if args.serve_requests > 0:
         from paper_1902_01818_amd import serve
         line["serving"] = serve.serve_benchmark(
-            n_requests=args.serve_requests, slots=4, budget_gib=64.0, load=0.7,
-            calibrate=min(32, args.serve_requests))
+            n_requests=args.serve_requests, slots=4, budget_gib=args.serve_budget_gib, load=0.7,
+            calibrate=min(max(32, args.serve_requests // 16), args.serve_requests))
     # batched right-hand sides (p = 6, 256 elements per patch, 64 columns)
     if not args.no_c4:
         line["c4"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)

@@ -104,7 +104,9 @@ def serve_benchmark(n_requests=2000, slots=4, budget_gib=200.0, load=0.7, calibr
     problems = prepare(reqs, precision, outer)
     srv = igamg.Server(slots=slots, memory_budget=int(budget_gib * (1 << 30)))
     try:
-        _, cal = run(srv, problems[:calibrate], rate=None, progress=16)
+        # saturated throughput of an evenly spaced sample of the whole stream
+        stride = max(1, len(problems) // max(1, calibrate))
+        _, cal = run(srv, problems[::stride][:calibrate], rate=None, progress=16)
         rate = load * cal["solves_per_s"]
         _, summ = run(srv, problems, rate=rate, seed=master_seed, progress=16)
         st = srv.status()
