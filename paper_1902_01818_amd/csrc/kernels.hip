@@ -1163,10 +1163,29 @@ __global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntil
   __syncthreads();
   // cross-patch couplings: one wave per right-hand side, so the additions
   // into a row come in a fixed order
+  // Up to 512 couplings per wave are loaded in one batch (indices and values,
+  // then the u gathers) before the additions, in the order e = lane + 64 j.
   const int wave = tid >> 6, lane = tid & 63;
   for (int z = wave; z < nz; z += 4) {
     const T *uz = u + (long long)(z0 + z) * vs;
-    for (int e = lane; e < tl.cx_n; e += 64) {
+    const int ncx = tl.cx_n < 64 * 8 ? tl.cx_n : 64 * 8;
+    int cl[8], cc[8];
+    T cv[8], cu[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = lane + 64 * j;
+      const bool ok = e < ncx;
+      cl[j] = ok ? cx_li[tl.cx_off + e] : -1;
+      cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
+      cv[j] = ok ? cx_val[tl.cx_off + e] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cu[j] = uz[cc[j]];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (cl[j] >= 0) unsafeAtomicAdd(&sX[z][cl[j]], cv[j] * cu[j]);
+    // tiles with more than 512 cross couplings (not produced by the layouts here)
+    for (int e = 64 * 8 + lane; e < tl.cx_n; e += 64) {
       const int q = tl.cx_off + e;
       unsafeAtomicAdd(&sX[z][cx_li[q]], cx_val[q] * uz[cx_col[q]]);
     }
