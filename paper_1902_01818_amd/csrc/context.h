@@ -256,6 +256,7 @@ struct Context {
   double *rold = nullptr;        // previous residual (flexible CG)
   double *dd = nullptr, *rin = nullptr;  // inner correction and residual (refinement)
   double *d_red = nullptr;       // reduction partials [nb][RED_BLOCKS]
+  hipEvent_t ev_scal = nullptr;  // marks the scalars' copy to the host mirror
   double *d_scal = nullptr;      // device scalars [nb][S_COUNT]
   double *h_scal = nullptr;      // pinned host mirror
   int *d_active = nullptr;       // per right-hand side: 1 = still iterating

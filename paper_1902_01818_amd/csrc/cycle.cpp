@@ -223,12 +223,14 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
     n_active += c.h_active[j];
   }
   upload_active(c, nb);
-  // host-side convergence bookkeeping after an update of S_RR
-  auto check = [&](int it) {
-    read_scalars(c, nb);
+  // host-side convergence bookkeeping after an update of S_RR (the host
+  // mirror must hold the scalars of iteration it)
+  std::vector<double> res_prev(nb, 0.0);  // relative residual one step before res
+  auto tally = [&](int it) {
     bool changed = false;
     for (int j = 0; j < nb; ++j) {
       if (!c.h_active[j]) continue;
+      res_prev[j] = res[j];
       res[j] = std::sqrt(c.h_scal[(size_t)j * S_COUNT + S_RR]) / nf[j];
       its[j] = it;
       if (info && info[j].history) info[j].history[it] = res[j];
@@ -239,6 +241,10 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
       }
     }
     if (changed && n_active > 0) upload_active(c, nb);
+  };
+  auto check = [&](int it) {
+    read_scalars(c, nb);
+    tally(it);
   };
   if (n_active > 0) {
     if (c.opt.outer == IGAMG_OUTER_MG) {
@@ -333,14 +339,41 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
         apply64(c, c.pp, nullptr, nullptr, c.qq, 1.0, nb);  // q = A p
         k_dot(c, c.pp, c.qq, nt, S_PQ, 1, nb);               // alpha = rz / pq
         k_pcg_update_xr(c, nt, nb, fcg);  // x += alpha p, r -= alpha q, rr; z = 0
-        check(it);
+        HIPCHK(hipMemcpyAsync(c.h_scal, c.d_scal, (size_t)nb * S_COUNT * sizeof(double),
+                              hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipEventRecord(c.ev_scal, c.stream));
+        // The next step's preconditioner is queued before the convergence
+        // test waits, so the device does not idle during it, unless this
+        // step is predicted to converge (residual times its last reduction
+        // within 3 tol for some right-hand side), where a queued cycle would
+        // only delay the return.  It writes only z and p: the iterate and
+        // residual of a right-hand side that has converged at this step stay
+        // as they are (the updated mask freezes them from the next update on).
+        bool ahead = it < maxit;
+        for (int j = 0; j < nb && ahead; ++j) {
+          if (!c.h_active[j]) continue;
+          const double rate = res_prev[j] > 0 ? res[j] / res_prev[j] : 1.0;
+          if (res[j] * rate <= 3.0 * tol) ahead = false;
+        }
+        if (ahead) {
+          precondition(c, c.rr, nb);
+          if (fcg)
+            k_dot_fcg(c, nt, nb);  // beta = (z, r - r_old) / rz
+          else
+            k_dot(c, c.rr, c.z, nt, S_RZNEW, 2, nb);  // beta = rz_new / rz
+          k_pcg_update_p(c, nt, nb);                  // p = z + beta p
+        }
+        HIPCHK(hipEventSynchronize(c.ev_scal));
+        tally(it);
         if (n_active == 0) break;
-        precondition(c, c.rr, nb);
-        if (fcg)
-          k_dot_fcg(c, nt, nb);  // beta = (z, r - r_old) / rz
-        else
-          k_dot(c, c.rr, c.z, nt, S_RZNEW, 2, nb);  // beta = rz_new / rz
-        k_pcg_update_p(c, nt, nb);                  // p = z + beta p
+        if (!ahead && it < maxit) {
+          precondition(c, c.rr, nb);
+          if (fcg)
+            k_dot_fcg(c, nt, nb);
+          else
+            k_dot(c, c.rr, c.z, nt, S_RZNEW, 2, nb);
+          k_pcg_update_p(c, nt, nb);
+        }
       }
     }
   }

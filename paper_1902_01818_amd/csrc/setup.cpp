@@ -143,6 +143,7 @@ Context::~Context() {
       (void)hipEventDestroy(pe.second);
     }
   }
+  if (ev_scal) (void)hipEventDestroy(ev_scal);
   if (own_pinned && h_scal) (void)hipHostFree(h_scal);
   if (own_pinned && h_active) (void)hipHostFree(h_active);
   arena.release();
@@ -1433,6 +1434,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   init_problem(c, P, degree, sigma, o);
   pc.lap("topology");
   c.stream = s;
+  HIPCHK(hipEventCreateWithFlags(&c.ev_scal, hipEventDisableTiming));
   if (lent && lent->device) {
     c.arena.region = (char *)lent->device;
     c.arena.region_cap = lent->device_bytes;
