@@ -1,19 +1,26 @@
 // HIP kernels of the multigrid cycle for gfx950 (MI355X).
 //
 //  * volume operator: per-patch stiffness (Section 2, eq. model) applied
-//    matrix-free by sum factorization over element tiles staged in LDS, the
-//    metric |det J| J^-1 J^-T recomputed from the patch corners at every
-//    Gauss point;
+//    matrix-free by sum factorization over element tiles staged in LDS (2D
+//    and 3D), the metric |det J| J^-1 J^-T recomputed from the patch corners
+//    at every Gauss point, or from the stored stencil rows of the
+//    Gauss-Seidel levels;
 //  * interface terms of the SIPG form (Section 3, eq. model:discr2) as a
-//    sparse row-gather over the unknowns next to interfaces;
+//    sparse row-gather over the unknowns next to interfaces, or in the
+//    stored rows plus the cross-patch couplings (per tile in 2D, per coupled
+//    row in 3D);
 //  * multicolour Gauss-Seidel (Section 4): one wavefront per tile of a fixed
-//    colour order;
+//    colour order in 2D, one block of eight wavefronts per tile in 3D;
 //  * the subspace corrected mass smoother (Section 5, eq. Ldef): patch
-//    interiors by fast diagonalization (two fused row-block kernels),
+//    interiors by fast diagonalization on the matrix cores (fused row-block
+//    products or batched product stages; six mode-product stages in 3D),
 //    interface pieces by dense inverses of P^T A P;
 //  * canonical embedding / its transpose between dyadic levels (Section 4);
 //  * direct coarse solve (float64) and deterministic reductions of the outer
-//    conjugate gradient iteration.
+//    conjugate gradient iteration;
+//  * setup: stencil rows (sum factorization in 2D, element matrices and a
+//    fixed-order gather in 3D), batched Gauss-Jordan inverses, and the L2
+//    error against the manufactured solution.
 // Cycle kernels are templates on the storage / arithmetic type (double or
 // float) and process a batch of right-hand sides (a grid dimension) that
 // share all operator data; vectors of the batch follow each other with
