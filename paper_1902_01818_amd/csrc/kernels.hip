@@ -1321,21 +1321,27 @@ __global__ __launch_bounds__(256) void cross3d_kernel(const int *__restrict__ ro
   }
 }
 
-// Sum over a wavefront: DPP scans inside the four rows of 16 lanes, then the
-// four row sums read from lanes 15, 31, 47, 63 (fixed order).
-__device__ inline double lane_value(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+// Sum over a wavefront, valid in lane 63: DPP scans inside the four rows of
+// 16 lanes, then row_bcast:15 adds the last lane of rows 0 and 2 into rows 1
+// and 3, and row_bcast:31 adds lane 31 into rows 2 and 3.  Lane 63 ends with
+// (r3 + r2) + (r1 + r0), a fixed order, with no scalar round trip.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_bcast(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWS, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ inline float lane_value(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+template <int CTRL, int ROWS>
+__device__ inline float dpp_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
 }
 template <typename T>
-__device__ inline T wave_sum(T v) {
+__device__ inline T wave_sum_last(T v) {
   v = row16_scan(v);
-  return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+  v += dpp_bcast<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_bcast<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+  return v;
 }
 
 // Multicolour Gauss-Seidel on 3D tiles: one block of eight wavefronts per
@@ -1433,8 +1439,8 @@ __global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T
         T acc = acc0 + acc1;
         asm volatile("" : "+v"(acc), "+v"(ubd), "+v"(dd));
         if (s + D < NPH) load_row(s + D, buf[j]);
-        acc = wave_sum(acc);
-        if (lane == 0 && ok) sU[wi] = fma(-acc, dd, ubd);
+        acc = wave_sum_last(acc);
+        if (lane == 63 && ok) sU[wi] = fma(-acc, dd, ubd);
         __syncthreads();
       }
     }
