@@ -1,21 +1,25 @@
-"""Benchmark: solves/s of the hybrid-smoother multigrid PCG solver to relative
-residual 1e-8 on one MI355X, with the roofline position of the dominant
-kernel and the FP64 CPU oracle timed on the host beside it.
+"""Benchmark: solves/s to relative residual 1e-8 on one MI355X, mixed
+precision against float64, with the roofline position of the dominant kernel
+and the FP64 CPU oracle timed on the host beside it.
 
-Workload (default): 2D SIPG on the unit square split into 4x4 bilinear
-patches (corners perturbed by up to 10% of the patch width, seed 1902),
-checkerboard 64/96 elements per direction (non-matching interfaces),
-degree 4, penalty 5 p^2/h, V(1,1) cycle with the hybrid smoother
-(forward Gauss-Seidel + SCMS / SCMS + backward Gauss-Seidel, damping 0.25,
-scaling 0.1), float64 PCG, N(0,1) right-hand side (seed 2002), 115,652
-unknowns.  Levels: uniform halving down to 8/12 elements per patch (4 levels,
-dense direct solve of the 2,940-unknown coarsest level on the GPU);
---coarse-min 2 halves down to 2/3 elements (6 levels).  One step = one
-complete solve; the right-hand side is resident in HBM before the timed
-region starts.  Also reported: the float32-cycle solve (float64 flexible CG)
-and a serving sample (p50/p99 latency).
+Headline workload (the 64-column degree-6 configuration): 2D SIPG on the unit
+square split into 4x4 bilinear patches (corners perturbed by up to 10% of the
+patch width, seed 1902), 256 elements per patch direction, degree 6, penalty
+5 p^2/h, 1,094,116 unknowns, 64 N(0,1) right-hand sides (seeds 4000..4063)
+solved together; hybrid V(1,1) cycle (forward Gauss-Seidel + SCMS / SCMS +
+backward Gauss-Seidel, damping 0.25, scaling 0.1) in float32 (operator rows,
+smoother, transfers), float64 iterative refinement (float64 residual, update
+and stopping test; coarse solve float64).  One step = one complete solve of
+the 64 columns; the right-hand sides are resident in HBM before the timed
+region starts; value = right-hand sides solved per second.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+Beside it: the same batch with the float64 cycle (float64 PCG: the
+mixed-vs-float64 speedup), flexible CG around the float32 cycle, bf16 SCMS
+operands; the 3D workload (1.65 M unknowns) with float32 and float64 cycles;
+the 4x4 degree-4 workload (115,652 unknowns) in float64 and float32; a
+serving sample (p50/p99 latency).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--quick]
 """
 import argparse
 import json
@@ -35,8 +39,8 @@ MFMA_PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 
 
 KERNEL_OF_FAMILY = {"gauss_seidel": "gs2d_wave_kernel", "vol_apply": "vol2d_kernel",
-                    "scms": "fd2m_kernel", "iface_apply": "iface_kernel",
-                    "stencil_apply": "sp2d_kernel"}
+                    "scms": "fdg_kernel", "iface_apply": "iface_kernel",
+                    "stencil_apply": "sp2d_kernel", "outer_apply": "sp2d_kernel"}
 
 
 def source_hash(family="gauss_seidel"):
@@ -51,18 +55,26 @@ def source_hash(family="gauss_seidel"):
     return hashlib.sha256(src[i:j].encode()).hexdigest()[:16]
 
 
-def cpu_baseline(cfg, f, its_gpu, budget_s=15.0):
-    """Oracle (plain FP64 CPU reference) on the same workload: setup excluded
-    (as on the GPU), full PCG solves repeated until budget_s of CPU work."""
+def cpu_baseline(cfg_name, scale, n_full, budget_s=15.0):
+    """The oracle (plain FP64 CPU reference, as it stands) on a bounded sample
+    of the headline workload: the same layout with every element count
+    divided by `scale`, one right-hand side, float64 PCG solves to 1e-8
+    repeated for about budget_s seconds (setup excluded, as on the GPU).  The
+    rate is scaled to the full size by the ratio of unknowns (the solve's work
+    is linear in the unknowns at a flat iteration count) and reported per
+    right-hand side."""
     import oracle
+    import workloads
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = 1
+    cfg = workloads.config(cfg_name, scale)
     pb = oracle.setup(cfg["corners"], cfg["elems"], cfg["p"], sigma=cfg["sigma"],
                       conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
                       delta=cfg["delta"])
+    f = workloads.normal_rhs(pb.N, 4000)
     n = 0
     t0 = time.perf_counter()
     its = None
@@ -72,59 +84,135 @@ def cpu_baseline(cfg, f, its_gpu, budget_s=15.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="solves/s", cores=int(threads), kind="oracle",
-                sample="%d full PCG solve(s) of the benchmark problem (%d iterations each, "
-                       "setup excluded), %.1f s" % (n, its, dt),
-                iterations=its)
+    ratio = n_full / pb.N
+    return dict(value=n / dt / ratio, unit="solves/s", cores=int(threads), kind="oracle",
+                sample="%d float64 PCG solve(s) of the headline layout with element counts / %d "
+                       "(%d unknowns, one right-hand side, %d iterations each, setup excluded) in "
+                       "%.1f s; rate scaled to %d unknowns by the ratio of unknowns (%.1f)"
+                       % (n, scale, pb.N, its, dt, n_full, ratio),
+                measured_solves_per_s=n / dt, iterations=its, cpu_model=_cpu_model())
 
 
-def c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=2, outer=None):
-    """64 right-hand sides of the p = 6, 256-element workload solved together
-    (float32 cycle, optionally with bfloat16 SCMS contractions, inside float64
-    flexible CG; or float64 PCG), with the matrix-core utilisation of the
-    finest level's SCMS application measured in one more, event-timed solve."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+ROOF_FAMILIES = ("gauss_seidel", "stencil_apply", "outer_apply", "scms", "pieces", "restrict",
+                 "prolong", "coarse", "vol_apply")
+
+
+def family_times(st):
+    fams = {}
+    for key, v in st.items():
+        fam = key.split("/")[0]
+        fams[fam] = fams.get(fam, 0.0) + v["ms"]
+    return fams
+
+
+def roofline_entry(sv, family, level, nrhs, avg_s, precision):
+    """Achieved rate of one launch of a kernel family against its roofline:
+    algorithmic bytes (or flops) per launch from the library's model divided
+    by the event-timed average launch."""
+    mbytes, mflops = sv.kernel_model(family, level, nrhs)
+    if family == "vol_apply":
+        ach = mflops / avg_s / 1e12
+        roof = dict(bound="alu", achieved=ach, peak=PEAK["fp64" if precision == "fp64" else "fp32"],
+                    unit="TFLOP/s")
+    elif family == "scms":
+        ach = mflops / avg_s / 1e12
+        roof = dict(bound="mfma", achieved=ach,
+                    peak=MFMA_PEAK["bf16" if precision == "bf16" else precision], unit="TFLOP/s")
+    else:
+        ach = mbytes / avg_s / 1e9
+        roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm"], unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["model_bytes_per_launch"] = mbytes
+    roof["model_flops_per_launch"] = mflops
+    return roof
+
+
+def c4_solver(igamg, workloads, precision, outer, nrhs=64):
     cfg = workloads.config("c4")
-    if outer is None:
-        outer = "pcg" if precision == "fp64" else "fcg"
     t0 = time.perf_counter()
     sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
                       conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
                       delta=cfg["delta"], precision=precision, outer=outer, max_rhs=nrhs)
-    setup_s = time.perf_counter() - t0
-    n = sv.n_dofs
-    F = torch.from_numpy(np.stack([workloads.normal_rhs(n, 4000 + j) for j in range(nrhs)])).cuda()
-    U = torch.zeros_like(F)
-    sv.solve(F, U, tol=1e-8, maxit=200)
+    return cfg, sv, time.perf_counter() - t0
+
+
+def c4_rhs(torch, workloads, n, nrhs=64, seed=4000):
+    return torch.from_numpy(np.stack([workloads.normal_rhs(n, seed + j) for j in range(nrhs)])).cuda()
+
+
+def timed_solves(torch, sv, F, U, steps, warmup):
+    for _ in range(warmup):
+        sv.solve(F, U, tol=1e-8, maxit=200)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    infos = []
     for _ in range(steps):
         _, info = sv.solve(F, U, tol=1e-8, maxit=200)
+        infos.append(info)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    its = [i["iterations"] for i in info]
-    out = dict(workload="C2 geometry, p=6, 256 elements/patch, %d N(0,1) right-hand sides" % nrhs,
-               dofs=n, precision=precision, outer=outer, solves_per_s=nrhs / dt,
-               ms_per_batch=dt * 1e3, setup_s=setup_s, memory_gib=sv.memory() / (1 << 30),
-               iterations_max=max(its), iterations_min=min(its),
-               max_true_rel_residual=max(i["true_rel_residual"] for i in info),
-               all_converged=all(i["converged"] for i in info))
+    return (time.perf_counter() - t0) / steps, infos
+
+
+def column_errors(torch, U, Uref):
+    """Relative error of every column of U against Uref (max, median)."""
+    d = torch.linalg.norm(U - Uref, dim=1) / torch.linalg.norm(Uref, dim=1)
+    d = d.cpu().numpy()
+    return dict(max=float(d.max()), median=float(np.median(d)))
+
+
+def finest_kernels(torch, sv, F, U, nrhs, precision):
+    """Every modelled kernel family of the finest level in one more,
+    event-timed solve: mean launch time and rate against its roofline."""
     top = sv.n_levels - 1
-    key = "scms/%d" % top
-    sv.set_timing(key)
+    sv.set_timing("")
     sv.solve(F, U, tol=1e-8, maxit=200)
     torch.cuda.synchronize()
     st = sv.kernel_stats(reset=True)
     sv.set_timing(None)
-    if st.get(key, {}).get("launches"):
-        avg = st[key]["ms"] / 1e3 / st[key]["launches"]
-        _, fl = sv.kernel_model("scms", top, nrhs)
-        ach = fl / avg / 1e12
-        peak = MFMA_PEAK["bf16" if precision == "bf16" else precision]
-        out["scms_mfma"] = dict(kernel=key, bound="mfma", achieved=ach, peak=peak,
-                                unit="TFLOP/s", frac=ach / peak, avg_application_us=avg * 1e6,
-                                model_flops_per_application=fl)
-    sv.close()
+    out = {}
+    for fam in ROOF_FAMILIES:
+        k = "%s/%d" % (fam, 0 if fam == "coarse" else top)
+        if not st.get(k, {}).get("launches"):
+            continue
+        t = st[k]["ms"] / 1e3 / st[k]["launches"]
+        r = roofline_entry(sv, fam, top, nrhs, t, precision)
+        out[fam] = dict(avg_us=t * 1e6, launches=st[k]["launches"], bound=r["bound"],
+                        achieved=r["achieved"], unit=r["unit"], frac=r["frac"])
+    out["ms_per_family_all_levels"] = {k: round(v, 3) for k, v in sorted(family_times(st).items())}
     return out
+
+
+def c4_leg(igamg, torch, workloads, precision, outer, steps=2, warmup=1, Uref=None):
+    """The 64 columns of the degree-6 workload with the given cycle
+    arithmetic and outer iteration: rate, iterations, true residuals, kernel
+    rates of the finest level, error per column against Uref."""
+    cfg, sv, setup_s = c4_solver(igamg, workloads, precision, outer)
+    F = c4_rhs(torch, workloads, sv.n_dofs)
+    U = torch.zeros_like(F)
+    dt, infos = timed_solves(torch, sv, F, U, steps, warmup)
+    info = infos[-1]
+    its = [i["iterations"] for i in info]
+    out = dict(precision=precision, outer=outer, solves_per_s=F.shape[0] / dt,
+               ms_per_batch=dt * 1e3, setup_s=setup_s, memory_gib=sv.memory() / (1 << 30),
+               iterations_max=max(its), iterations_min=min(its),
+               max_true_rel_residual=max(i["true_rel_residual"] for i in info),
+               all_converged=all(i["converged"] and i["true_rel_residual"] <= 1e-8 for i in info))
+    if Uref is not None:
+        out["rel_error_vs_fp64_solution"] = column_errors(torch, U, Uref)
+    out["kernels_finest"] = finest_kernels(torch, sv, F, U, F.shape[0], precision)
+    sv.close()
+    return out, U
 
 
 def c1_leg(igamg, torch, workloads, steps=20, batch=1000):
@@ -186,7 +274,7 @@ def c1_leg(igamg, torch, workloads, steps=20, batch=1000):
     return out
 
 
-def c3_leg(igamg, torch, workloads, precision="fp32", steps=2, operator_apply="auto"):
+def c3_leg(igamg, torch, workloads, precision="fp32", steps=2, operator_apply="auto", uref=None):
     """The 3D workload at full size (2x2x2 trilinear patches, 48/64 elements,
     p = 3, 1.65 M unknowns, manufactured right-hand side), hybrid cycle in
     the given arithmetic inside float64 flexible CG (float64: PCG), plus the
@@ -201,75 +289,77 @@ def c3_leg(igamg, torch, workloads, precision="fp32", steps=2, operator_apply="a
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     f = sv.load_manufactured()
-    u, info = sv.solve(f, tol=1e-8, maxit=200)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        u, info = sv.solve(f, tol=1e-8, maxit=200)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    u = torch.zeros_like(f)
+    dt, infos = timed_solves(torch, sv, f, u, steps, 1)
+    info = infos[-1]
     out = dict(workload="3D SIPG, 2x2x2 trilinear patches, 48/64 elements, p=3, manufactured",
                dofs=sv.n_dofs, levels=sv.n_levels, precision=precision, outer=outer,
                operator_apply=operator_apply,
                solves_per_s=1.0 / dt, ms_per_solve=dt * 1e3, setup_s=setup_s,
                memory_gib=sv.memory() / (1 << 30), iterations=info[0]["iterations"],
-               true_rel_residual=info[0]["true_rel_residual"], converged=info[0]["converged"])
-    sv.set_timing("")
-    sv.solve(f, tol=1e-8, maxit=200)
-    torch.cuda.synchronize()
-    st = sv.kernel_stats(reset=True)
-    sv.set_timing(None)
-    fam = {}
-    for k, v in st.items():
-        name = k.split("/")[0]
-        fam[name] = fam.get(name, 0.0) + v["ms"]
-    out["ms_per_family_timed_solve"] = {k: round(v, 3) for k, v in sorted(fam.items())}
-    # the finest level's operator kernels: average launch and model rate
-    top = sv.n_levels - 1
-    key = "scms/%d" % top
-    if st.get(key, {}).get("launches"):
-        avg = st[key]["ms"] / 1e3 / st[key]["launches"]
-        _, fl = sv.kernel_model("scms", top, 1)
-        peak = MFMA_PEAK["bf16" if precision == "bf16" else precision]
-        out["scms_mfma"] = dict(kernel=key, bound="mfma", achieved=fl / avg / 1e12, peak=peak,
-                                unit="TFLOP/s", frac=fl / avg / 1e12 / peak,
-                                avg_application_us=avg * 1e6, model_flops_per_application=fl)
-    for famname in ("vol_apply", "stencil_apply"):
-        key = "%s/%d" % (famname, top)
-        if st.get(key, {}).get("launches"):
-            avg = st[key]["ms"] / 1e3 / st[key]["launches"]
-            b, fl = sv.kernel_model(famname, top, 1)
-            out["finest_" + famname] = dict(avg_us=avg * 1e6, model_gb_s=b / avg / 1e9,
-                                            model_tflop_s=fl / avg / 1e12)
+               true_rel_residual=info[0]["true_rel_residual"],
+               converged=info[0]["converged"] and info[0]["true_rel_residual"] <= 1e-8,
+               l2_error_manufactured=sv.l2_error(u))
+    if uref is not None:
+        out["rel_error_vs_fp64_solution"] = float(torch.linalg.norm(u - uref) /
+                                                  torch.linalg.norm(uref))
+    out["kernels_finest"] = finest_kernels(torch, sv, f, u, 1, precision)
     sv.close()
+    return out, u
+
+
+def c2_legs(igamg, torch, workloads, steps=10, warmup=2, coarse_min=8):
+    """The 4x4 degree-4 workload (115,652 unknowns, one right-hand side):
+    float64 PCG and the float32 cycle inside float64 flexible CG."""
+    cfg = workloads.config("c2")
+    out = {}
+    u64 = None
+    for precision, outer in (("fp64", "pcg"), ("fp32", "fcg")):
+        sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
+                          conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
+                          delta=cfg["delta"], precision=precision, outer=outer,
+                          coarse_min=coarse_min)
+        f = torch.from_numpy(workloads.normal_rhs(sv.n_dofs, cfg["rhs"][1])).cuda()
+        u = torch.zeros_like(f)
+        dt, infos = timed_solves(torch, sv, f, u, steps, warmup)
+        info = infos[-1]
+        ent = dict(workload="2D SIPG, 4x4 bilinear patches, 64/96 elements, p=4, %d levels"
+                            % sv.n_levels, dofs=sv.n_dofs, precision=precision, outer=outer,
+                   solves_per_s=1.0 / dt, ms_per_solve=dt * 1e3,
+                   iterations=info[0]["iterations"],
+                   vcycles_per_s=(info[0]["iterations"] + 1) / dt,
+                   true_rel_residual=info[0]["true_rel_residual"],
+                   converged=all(i[0]["converged"] and i[0]["true_rel_residual"] <= 1e-8
+                                 for i in infos))
+        if u64 is not None:
+            ent["rel_error_vs_fp64_solution"] = float(torch.linalg.norm(u - u64) /
+                                                      torch.linalg.norm(u64))
+        else:
+            u64 = u.clone()
+        ent["kernels_finest"] = finest_kernels(torch, sv, f, u, 1, precision)
+        out[precision] = ent
+        sv.close()
+    out["fp32"]["speedup_vs_fp64"] = out["fp32"]["solves_per_s"] / out["fp64"]["solves_per_s"]
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the float32-cycle run")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline and its float64 leg only (no 3D, degree-4, bf16, serving legs)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
                     help="device memory the serving runtime admits requests into")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests of the serving sample (0 = skip)")
-    ap.add_argument("--no-c4", action="store_true", help="skip the 64-column p = 6 workload")
-    ap.add_argument("--c4-only", action="store_true",
-                    help="diagnostic: run only the 64-column p = 6 legs (float32 cycle, bf16 "
-                         "SCMS) and print their results (not the benchmark line)")
     ap.add_argument("--c1-only", action="store_true",
                     help="diagnostic: run only the conforming 2x2 workload (rates, a batch of "
                          "1000 right-hand sides, L2 error ladder) and print its results")
     ap.add_argument("--c3-only", action="store_true",
-                    help="diagnostic: run only the full-size 3D workload (float32 and float64 "
-                         "cycles) and print its results (not the benchmark line)")
-    ap.add_argument("--coarse-min", type=int, default=8,
-                    help="halving stops before an element count falls below this: 8 puts the "
-                         "direct solve on the 8/12-element level (2,940 unknowns, 4 levels); "
-                         "2 halves down to 2/3 elements (6 levels)")
+                    help="diagnostic: run only the full-size 3D legs and print their results")
     ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy MIB MiB device to device (counter calibration)")
@@ -283,120 +373,72 @@ def main():
     import workloads
     from paper_1902_01818_amd import igamg
 
+    def note(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
     if args.c1_only:
         print(json.dumps({"c1": c1_leg(igamg, torch, workloads)}))
         return
 
     if args.c3_only:
-        out = {"c3": c3_leg(igamg, torch, workloads, precision="fp32")}
-        print("bench: 3D workload timed (float32 cycle)", file=sys.stderr, flush=True)
-        out["c3_fp64"] = c3_leg(igamg, torch, workloads, precision="fp64")
-        print("bench: 3D workload timed (float64 cycle)", file=sys.stderr, flush=True)
-        out["c3_sumfact"] = c3_leg(igamg, torch, workloads, precision="fp32",
-                                   operator_apply="sumfact")
-        print("bench: 3D workload timed (matrix-free operator)", file=sys.stderr, flush=True)
-        out["c3_bf16_scms"] = c3_leg(igamg, torch, workloads, precision="bf16")
-        out["mixed_speedup"] = {k: out[k]["solves_per_s"] / out["c3_fp64"]["solves_per_s"]
-                                for k in ("c3", "c3_bf16_scms")}
+        o64, u64 = c3_leg(igamg, torch, workloads, precision="fp64")
+        note("3D workload timed (float64 cycle)")
+        o32, _ = c3_leg(igamg, torch, workloads, precision="fp32", uref=u64)
+        note("3D workload timed (float32 cycle)")
+        obf, _ = c3_leg(igamg, torch, workloads, precision="bf16", uref=u64)
+        out = {"c3_fp64": o64, "c3_fp32": o32, "c3_bf16_scms": obf,
+               "mixed_speedup": {"fp32": o32["solves_per_s"] / o64["solves_per_s"],
+                                 "bf16_scms": obf["solves_per_s"] / o64["solves_per_s"]}}
         print(json.dumps(out))
         return
 
-    if args.c4_only:
-        out = {"c4": c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)}
-        print("bench: 64-column p = 6 batch timed (float32 cycle)", file=sys.stderr, flush=True)
-        out["c4_bf16_scms"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="bf16", steps=1)
-        print("bench: 64-column p = 6 batch timed (bf16 SCMS)", file=sys.stderr, flush=True)
-        out["c4_fp64"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp64", steps=1)
-        print(json.dumps(out))
-        return
-
-    cfg = workloads.config("c2")
-    sv = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
-                      conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
-                      delta=cfg["delta"], timing=False, coarse_min=args.coarse_min)
+    # ---- headline: 64 columns, float32 cycle in float64 iterative refinement
+    precision, outer, nrhs = "fp32", "ir", 64
+    cfg, sv, setup_s = c4_solver(igamg, workloads, precision, outer, nrhs)
     N = sv.n_dofs
-    f_host = workloads.normal_rhs(N, cfg["rhs"][1])
-    f = torch.from_numpy(f_host).cuda()
-    u = torch.zeros_like(f)
-    torch.cuda.synchronize()
+    F = c4_rhs(torch, workloads, N, nrhs)
+    U = torch.zeros_like(F)
     for _ in range(args.warmup):
-        sv.solve(f, u, tol=1e-8, maxit=200)
+        sv.solve(F, U, tol=1e-8, maxit=200)
     torch.cuda.synchronize()
-
-    # dominant kernel on the finest level: the family with the most event time
-    # in one untimed instrumented solve
     top = sv.n_levels - 1
     family = args.family
     if family is None:
+        # the family with the most event time over all levels in one
+        # instrumented (untimed) solve
         sv.set_timing("")
-        sv.solve(f, u, tol=1e-8, maxit=200)
-        st = sv.kernel_stats(reset=True)
-        fams = {}
-        for key, v in st.items():
-            fam = key.split("/")[0]
-            fams[fam] = fams.get(fam, 0.0) + v["ms"]
-        modelled = [k for k in KERNEL_OF_FAMILY if k in fams]
-        family = max(modelled, key=lambda k: fams[k])
-    # timed region: only the dominant family on the finest level is event-timed
-    sv.set_timing("%s/%d" % (family, top))
+        sv.solve(F, U, tol=1e-8, maxit=200)
+        fams = family_times(sv.kernel_stats(reset=True))
+        family = max([k for k in ROOF_FAMILIES if k in fams], key=lambda k: fams[k])
+    # timed region: only the dominant family's finest-level launches carry
+    # events (on the library's stream, where the kernels run)
+    key = "%s/%d" % (family, 0 if family == "coarse" else top)
+    sv.set_timing(key)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for _ in range(args.steps):
-        _, info = sv.solve(f, u, tol=1e-8, maxit=200)
-        infos.append(info[0])
+        _, info = sv.solve(F, U, tol=1e-8, maxit=200)
+        infos.append(info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = sv.kernel_stats(reset=True)
     sv.set_timing(None)
-    print("bench: float64 solves timed (%.1f ms/solve)" % (dt / args.steps * 1e3), file=sys.stderr,
-          flush=True)
-    key = "%s/%d" % (family, top)
+    note("headline timed (%.1f ms per batch of %d)" % (dt / args.steps * 1e3, nrhs))
     launches = st[key]["launches"]
     avg_s = st[key]["ms"] / 1e3 / max(launches, 1)
-    mbytes, mflops = sv.kernel_model(family, top, 1)
-    if family == "vol_apply":
-        achieved = mflops / avg_s / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=PEAK["fp64"], unit="TFLOP/s")
-    elif family == "scms":
-        achieved = mflops / avg_s / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=MFMA_PEAK["fp64"], unit="TFLOP/s")
-    else:
-        achieved = mbytes / avg_s / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = key
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["launches"] = launches
-    roof["model_bytes_per_launch"] = mbytes
-    roof["model_flops_per_launch"] = mflops
-
-    # every modelled kernel family of the finest level (and the coarse solve)
-    # in one more, event-timed solve: mean launch time and achieved rate
-    sv.set_timing("")
-    sv.solve(f, u, tol=1e-8, maxit=200)
-    torch.cuda.synchronize()
-    st_all = sv.kernel_stats(reset=True)
-    sv.set_timing(None)
-    kernels = {}
-    for fam in ("gauss_seidel", "stencil_apply", "vol_apply", "iface_apply", "scms", "pieces",
-                "restrict", "prolong", "coarse"):
-        k = "%s/%d" % (fam, 0 if fam == "coarse" else top)
-        if not st_all.get(k, {}).get("launches"):
-            continue
-        t = st_all[k]["ms"] / 1e3 / st_all[k]["launches"]
-        b, fl = sv.kernel_model(fam, top, 1)
-        ent = {"avg_us": t * 1e6, "model_bytes": b, "model_flops": fl,
-               "gb_s": b / t / 1e9, "frac_hbm": b / t / 1e9 / PEAK["hbm"]}
-        if fam == "scms":
-            ent["tflop_s"] = fl / t / 1e12
-            ent["frac_mfma_fp64"] = ent["tflop_s"] / MFMA_PEAK["fp64"]
-        kernels[fam] = ent
-
-    its = infos[-1]["iterations"]
-    ok = all(i["converged"] and i["true_rel_residual"] <= 1e-8 * 1.01 for i in infos)
-    value = args.steps / dt
+    roof = roofline_entry(sv, family, top, nrhs, avg_s, precision)
+    roof.update(traffic=None, kernel=key, avg_launch_us=avg_s * 1e6, launches=launches,
+                units_per_launch=("one colour class of a Gauss-Seidel sweep on the finest level "
+                                  "(the sweep's stencil rows and vectors split evenly over its "
+                                  "class launches), %d right-hand sides" % nrhs)
+                if family == "gauss_seidel" else
+                "one launch on the finest level, %d right-hand sides" % nrhs)
+    kernels = finest_kernels(torch, sv, F, U, nrhs, precision)
+    last = infos[-1]
+    value = nrhs * args.steps / dt
+    its = [i["iterations"] for i in last]
+    ok = all(i["converged"] and i["true_rel_residual"] <= 1e-8 for info in infos for i in info)
     line = {
         "metric": "solves/s to rel.res 1e-8 (mixed vs FP64 MG), p50/p99 latency, HBM GB/s",
         "value": value,
@@ -408,73 +450,57 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D SIPG, 4x4 bilinear patches (10%% seeded perturbation), "
-                               "checkerboard 64/96 elements, p=4, sigma=5, hybrid V(1,1) over "
-                               "%d levels (dense direct solve on the coarsest), FP64 PCG to 1e-8"
-                               % sv.n_levels,
-                   "dofs": N, "levels": sv.n_levels, "coarse_min": args.coarse_min,
-                   "iterations": its,
-                   "vcycles_per_s": value * (its + 1),
-                   "true_rel_residual": infos[-1]["true_rel_residual"], "all_converged": ok},
+        "config": {"workload": "2D SIPG, 4x4 bilinear patches (10%% seeded perturbation), 256 "
+                               "elements per patch direction, p=6, sigma=5, %d N(0,1) right-hand "
+                               "sides solved together; hybrid V(1,1) over %d levels in float32 "
+                               "(float64 coarse solve) inside float64 iterative refinement to "
+                               "rel. residual 1e-8" % (nrhs, sv.n_levels),
+                   "dofs": N, "nrhs": nrhs, "levels": sv.n_levels,
+                   "cycle_dtype": "f32", "outer_dtype": "f64", "outer": "iterative refinement",
+                   "iterations_max": max(its), "iterations_min": min(its),
+                   "batch_vcycles_per_s": args.steps * float(np.mean(its)) / dt,
+                   "max_true_rel_residual": max(i["true_rel_residual"] for i in last),
+                   "all_converged": ok, "setup_s": setup_s,
+                   "memory_gib": sv.memory() / (1 << 30)},
         "roofline": roof,
         "kernels_finest": kernels,
     }
-    # mixed precision: float32 cycle inside float64 flexible CG, same workload,
-    # same float64 stopping test; error reported against the float64 GPU solve
-    if not args.no_mixed:
-        u64 = u.clone()
-        sm = igamg.Solver(cfg["corners"], cfg["elems"], cfg["p"], cfg["sigma"],
-                          conforming=cfg["conforming"], smoother=cfg["smoother"], tau=cfg["tau"],
-                          delta=cfg["delta"], precision="fp32", outer="fcg",
-                          coarse_min=args.coarse_min)
-        um = torch.zeros_like(f)
-        for _ in range(args.warmup):
-            sm.solve(f, um, tol=1e-8, maxit=200)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        minfo = []
-        for _ in range(args.steps):
-            _, info = sm.solve(f, um, tol=1e-8, maxit=200)
-            minfo.append(info[0])
-        torch.cuda.synchronize()
-        dtm = time.perf_counter() - t0
-        line["mixed"] = {
-            "cycle_dtype": "f32", "outer_dtype": "f64", "outer": "flexible CG",
-            "value": args.steps / dtm, "unit": "solves/s", "ms_per_step": dtm / args.steps * 1e3,
-            "speedup_vs_fp64": (args.steps / dtm) / value,
-            "iterations": minfo[-1]["iterations"],
-            "true_rel_residual": minfo[-1]["true_rel_residual"],
-            "all_converged": all(i["converged"] and i["true_rel_residual"] <= 1e-8 * 1.01
-                                 for i in minfo),
-            "rel_error_vs_fp64_solution": float(torch.linalg.norm(um - u64) / torch.linalg.norm(u64)),
-        }
-        sm.close()
-        print("bench: float32-cycle solves timed", file=sys.stderr, flush=True)
-    # serving: a seeded sample of the heterogeneous request stream arrives at
-    # Poisson times (rate = load x the saturated rate of a calibration burst);
-    # latency = submission to result, setup included
-    if args.serve_requests > 0:
-        from paper_1902_01818_amd import serve
-        line["serving"] = serve.serve_benchmark(
-            n_requests=args.serve_requests, slots=4, budget_gib=args.serve_budget_gib, load=0.7,
-            calibrate=min(max(32, args.serve_requests // 16), args.serve_requests))
-    # batched right-hand sides (p = 6, 256 elements per patch, 64 columns)
-    if not args.no_c4:
-        line["c4"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32", steps=1)
-        print("bench: 64-column p = 6 batch timed (float32 cycle)", file=sys.stderr, flush=True)
-        line["c4_bf16_scms"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="bf16", steps=1)
-        print("bench: 64-column p = 6 batch timed (bf16 SCMS)", file=sys.stderr, flush=True)
-        line["c4_refinement"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp32",
-                                       steps=1, outer="ir")
-        print("bench: 64-column p = 6 batch timed (float64 iterative refinement)", file=sys.stderr,
-              flush=True)
-        line["c4_fp64"] = c4_leg(igamg, torch, workloads, nrhs=64, precision="fp64", steps=1)
-        line["c4_fp64"]["mixed_speedup"] = {
-            k: line[k]["solves_per_s"] / line["c4_fp64"]["solves_per_s"]
-            for k in ("c4", "c4_bf16_scms", "c4_refinement")}
-        print("bench: 64-column p = 6 batch timed (float64 cycle)", file=sys.stderr, flush=True)
+    sv.close()
+    Umixed = U
+    # ---- float64 cycle on the same batch (float64 PCG): the speedup's base
+    o64, U64 = c4_leg(igamg, torch, workloads, "fp64", "pcg", steps=2, warmup=1)
+    note("float64 batch timed")
+    line["fp64"] = o64
+    line["config"]["rel_error_vs_fp64_solution"] = column_errors(torch, Umixed, U64)
+    line["mixed_speedup_vs_fp64"] = value / o64["solves_per_s"]
+    del Umixed
+    if not args.quick:
+        for name, prec, out_ in (("fcg_fp32", "fp32", "fcg"), ("ir_bf16_scms", "bf16", "ir")):
+            o, _ = c4_leg(igamg, torch, workloads, prec, out_, steps=2, warmup=1, Uref=U64)
+            o["speedup_vs_fp64"] = o["solves_per_s"] / o64["solves_per_s"]
+            line[name] = o
+            note("%s batch timed" % name)
+    del U64
+    torch.cuda.empty_cache()
+    if not args.quick:
+        c3_64, u3 = c3_leg(igamg, torch, workloads, precision="fp64")
+        note("3D workload timed (float64 cycle)")
+        c3_32, _ = c3_leg(igamg, torch, workloads, precision="fp32", uref=u3)
+        note("3D workload timed (float32 cycle)")
+        c3_32["speedup_vs_fp64"] = c3_32["solves_per_s"] / c3_64["solves_per_s"]
+        line["c3"] = {"fp64": c3_64, "fp32": c3_32}
+        del u3
+        torch.cuda.empty_cache()
+        line["c2"] = c2_legs(igamg, torch, workloads)
+        note("degree-4 workload timed")
+        if args.serve_requests > 0:
+            from paper_1902_01818_amd import serve
+            line["serving"] = serve.serve_benchmark(
+                n_requests=args.serve_requests, slots=4, budget_gib=args.serve_budget_gib,
+                load=0.7, calibrate=min(max(32, args.serve_requests // 16), args.serve_requests))
+            note("serving sample done")
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -482,15 +508,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         line["calibration_copy_bytes"] = n * 8
-    traffic_file = os.path.join(ROOT, "profiles", "traffic_%s_c2_fp64.json" % family)
+    traffic_file = os.path.join(ROOT, "profiles", "traffic_%s_c4_ir.json" % family)
     if os.path.exists(traffic_file):
         with open(traffic_file) as fh:
             tr = json.load(fh)
         # counters taken on the same kernel source and workload (checked by hash)
-        if tr.get("source_hash") == source_hash(family) and tr.get("traffic_bytes"):
+        if (family in KERNEL_OF_FAMILY and tr.get("source_hash") == source_hash(family)
+                and tr.get("traffic_bytes")):
             roof["traffic"] = tr["traffic_bytes"]
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(cfg, f_host, its)
+        line["cpu_baseline"] = cpu_baseline("c4", 8, N)
+        note("cpu baseline done")
     print(json.dumps(line))
 
 

@@ -223,11 +223,15 @@ int igamg_set_timing(igamg_ctx *ctx, const char *filter);
 /* Algorithmic bytes moved and flops of one timed launch of a kernel family
  * on a level (level < 0: finest) for a batch of nrhs right-hand sides: the
  * roofline model of the library's kernels.  Families: "stencil_apply" and
- * "vol_apply" + "iface_apply" (operator, eq. model:discr2), "gauss_seidel"
- * (one colour class), "scms" (one application to all patch interiors, eq.
- * Ldef), "pieces" (all interface pieces), "restrict" / "prolong" (level = the
- * fine side), "coarse" (the direct solve; level ignored).  Operator data shared by the batch counts once; vectors once per
- * right-hand side.  Errors: IGAMG_EINVAL for an unknown family, a level out
+ * "vol_apply" + "iface_apply" (operator, eq. model:discr2), "outer_apply"
+ * (the float64 finest-level operator of a float32-cycle solve),
+ * "gauss_seidel" (one colour class), "scms" (one application to all patch
+ * interiors, eq. Ldef), "pieces" (all interface pieces), "restrict" /
+ * "prolong" (level = the fine side), "coarse" (the direct solve; level
+ * ignored).  Operator data shared by the batch counts once; vectors once per
+ * right-hand side.  The stored-row operator and Gauss-Seidel count the
+ * (2p+1)^d stencil of every compact unknown and three vector accesses per
+ * unknown and right-hand side, nothing for padding, masks or index lists.  Errors: IGAMG_EINVAL for an unknown family, a level out
  * of range or nrhs < 1. */
 int igamg_kernel_model(igamg_ctx *ctx, const char *family, int level, int nrhs, double *bytes,
                        double *flops);

@@ -2812,7 +2812,8 @@ static void launch_sp3d(Context &c, LevelData &L, const LevelArrays<T> &A, const
 template <typename T>
 void k_stencil_apply(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u, const T *f,
                      const T *fw, T beta, T alpha, T *r, int nrhs) {
-  TimeScope ts(c, "stencil_apply", L.l);
+  // the float64 operator of a float32-cycle solve is its own family
+  TimeScope ts(c, sizeof(T) == 8 && c.fp32() ? "outer_apply" : "stencil_apply", L.l);
   if (c.d == 3) {
     if (!A.stencil || !L.d_atiles3 || L.n_atiles == 0)
       fail(IGAMG_EUNSUPPORTED, "no stored operator rows on this level");

@@ -1732,9 +1732,7 @@ void kernel_model(const Context &c, const std::string &fam, int level, int nrhs,
   const int q = c.p + 1, P1 = c.p + 1;
   int S = 1;
   for (int g = 0; g < c.d; ++g) S *= (2 * c.p + 1);
-  const double SP = (S + 15) / 16 * 16;
-  double nnz = L.if_col.size(), ncross = 0;
-  for (unsigned char x : L.if_cross) ncross += x;
+  const double nnz = L.if_col.size();
   *bytes = 0;
   *flops = 0;
   if (fam == "vol_apply" && c.d == 3) {
@@ -1758,19 +1756,25 @@ void kernel_model(const Context &c, const std::string &fam, int level, int nrhs,
     *flops *= nb;
     *bytes = 3.0 * wb * nt * nb;                // read u, read and write r
   } else if (fam == "gauss_seidel") {
-    // one colour-class launch; rows and 1/a_ii shared by the batch; per
-    // right-hand side f read, u read and written, cross columns read
+    // one colour-class launch, algorithmic bytes only: the (2p+1)^d stencil
+    // of every unknown read once for the batch, f and u read and u written
+    // per right-hand side (compact unknowns: no padding, masks, Dirichlet
+    // rows or cross-patch coupling lists); a sweep is split evenly over its
+    // class launches
     int launches = 0;
     for (const GsClass &cl : L.gs) launches += cl.count > 0;
     if (launches == 0) launches = 1;
-    *bytes = (nt * wb * (SP + 1) + ncross * (8.0 + wb) + nb * (nt * 3.0 * wb + ncross * wb)) /
-             launches;
-    *flops = nb * (2.0 * S * nt + 2.0 * ncross) / launches;
-  } else if (fam == "stencil_apply") {
-    // rows, mask and cross couplings shared; per right-hand side u and f
-    // read, r written
-    *bytes = nt * (SP * wb + 1.0) + ncross * (8.0 + wb) + nb * (nt * 3.0 * wb + ncross * wb);
-    *flops = nb * (2.0 * S * nt + 2.0 * ncross);
+    const double n = (double)L.N;
+    *bytes = (n * wb * S + nb * n * 3.0 * wb) / launches;
+    *flops = nb * 2.0 * S * n / launches;
+  } else if (fam == "stencil_apply" || fam == "outer_apply") {
+    // algorithmic bytes: the (2p+1)^d stencil of every unknown once for the
+    // batch; u and f read and r written per right-hand side (outer_apply:
+    // the float64 finest-level operator of a mixed-precision solve)
+    const double b = fam == "outer_apply" ? 8.0 : wb;
+    const double n = (double)L.N;
+    *bytes = n * b * S + nb * n * 3.0 * b;
+    *flops = nb * 2.0 * S * n;
   } else if (fam == "scms") {
     // one application to the patch interiors: four products per patch;
     // bytes: r read, u read and written per right-hand side, the factors once

@@ -37,3 +37,21 @@ def rel_err(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def max_abs_rel(a, b):
+    """Element-wise bar: max_i |a_i - b_i| / max_i |b_i|."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def oracle_iterate(ob, f, k, its, iterates, outer="pcg"):
+    """The oracle's k-th iterate of the same outer iteration (k may exceed the
+    oracle's own iteration count by one when the library's recurrence
+    residual crosses the tolerance one step later)."""
+    if k <= its:
+        return iterates[k - 1]
+    if outer == "mg":
+        return ob.mg_iteration(f, tol=0.0, maxit=k)[0]
+    return ob.pcg(f, tol=0.0, maxit=k)[3][k - 1]

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.gpu_common import cached_oracle, gpu_solver, rel_err
+from tests.gpu_common import cached_oracle, gpu_solver, max_abs_rel, oracle_iterate, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -54,6 +54,7 @@ def test_batch_apply_cycle_equal_single(c2_small):
         assert rel_err(Ub[j], u1) < 1e-12
         assert rel_err(Yb[j], ob.apply(X[j])) < 1e-12
         assert rel_err(Ub[j], ob.vcycle(X[j])) < 1e-10
+        assert max_abs_rel(Ub[j], ob.vcycle(X[j])) < 1e-10
     s1.close()
     sb.close()
 
@@ -67,13 +68,17 @@ def test_batch_solve(c2_small, outer):
     U, info = sb.solve(_gpu(F), tol=1e-8, maxit=200)
     U = U.cpu().numpy().reshape(4, ob.N)
     for j in range(3):
+        kg = info[j]["iterations"]
         if outer == "pcg":
-            uo, its, _, _ = ob.pcg(F[j])
+            uo, its, _, iterates = ob.pcg(F[j])
+            ui = oracle_iterate(ob, F[j], kg, its, iterates)
         else:
             uo, its, _ = ob.mg_iteration(F[j])
-        assert info[j]["converged"] and abs(info[j]["iterations"] - its) <= 1, (j, info[j], its)
-        assert rel_err(U[j], uo) < 1e-9
-        assert np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j]) <= 1.01e-8
+            ui = uo if kg == its else ob.mg_iteration(F[j], tol=0.0, maxit=kg)[0]
+        assert info[j]["converged"] and abs(kg - its) <= 1, (j, info[j], its)
+        assert rel_err(U[j], ui) < 1e-10
+        assert max_abs_rel(U[j], ui) < 1e-10
+        assert np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j]) <= 1e-8
     assert info[3]["iterations"] == 0 and not np.any(U[3])
     sb.close()
 
@@ -99,10 +104,12 @@ def test_fp32_cycle_fp64_outer_solve(c2_small, outer):
         nf = np.linalg.norm(F[j])
         true_res = np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / nf
         assert info[j]["converged"]
-        assert true_res <= 1.05e-8, true_res
+        assert true_res <= 1e-8, true_res
         assert abs(info[j]["true_rel_residual"] - true_res) < 1e-12
         assert info[j]["iterations"] <= its + 2
-        assert rel_err(U[j], uo) < 1e-6
+        err = rel_err(U[j], ob.pcg(F[j], tol=1e-13)[0])
+        print("fp32 cycle, %s: column %d error vs oracle %.3e" % (outer, j, err))
+        assert err < 1e-6
     sv.close()
 
 
@@ -120,8 +127,11 @@ def test_bf16_scms_solve(c2_small):
         _, its, _, _ = ob.pcg(F[j])
         true_res = np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j])
         assert info[j]["converged"]
-        assert true_res <= 1.05e-8, true_res
+        assert true_res <= 1e-8, true_res
         assert info[j]["iterations"] <= 2 * its, (info[j]["iterations"], its)
+        err = rel_err(U[j], ob.pcg(F[j], tol=1e-13)[0])
+        print("bf16 SCMS: column %d error vs oracle %.3e" % (j, err))
+        assert err < 1e-6
     sv.close()
 
 
@@ -141,9 +151,12 @@ def test_iterative_refinement(c2_small, precision):
         _, its, _, _ = ob.pcg(F[j])
         true_res = np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j])
         assert info[j]["converged"], info[j]
-        assert true_res <= 1.05e-8, true_res
+        assert true_res <= 1e-8, true_res
         assert abs(info[j]["true_rel_residual"] - true_res) < 1e-12
         assert info[j]["iterations"] <= 2 * its, (info[j]["iterations"], its)
+        err = rel_err(U[j], ob.pcg(F[j], tol=1e-13)[0])
+        print("refinement, %s: column %d error vs oracle %.3e" % (precision, j, err))
+        assert err < 1e-6
     sv.close()
 
 
@@ -154,5 +167,5 @@ def test_fp32_fullsize_solve():
     u, info = sv.solve(_gpu(f), tol=1e-8, maxit=200)
     u = u.cpu().numpy()
     assert info[0]["converged"]
-    assert np.linalg.norm(f - ob.A[-1] @ u) / np.linalg.norm(f) <= 1.05e-8
+    assert np.linalg.norm(f - ob.A[-1] @ u) / np.linalg.norm(f) <= 1e-8
     sv.close()

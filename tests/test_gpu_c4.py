@@ -1,0 +1,139 @@
+"""Parity of the 64-column degree-6 workload (2D SIPG on the 4x4 bilinear
+layout, p = 6, 64 N(0,1) right-hand sides, hybrid V(1,1) cycle; float32
+cycle inside float64 iterative refinement as configured, plus float64 and
+flexible CG) with the FP64 oracle, through the C ABI.
+
+Size: the workload with every element count divided by 8 (32 elements per
+patch direction, 22,500 unknowns, 5 levels).  With 64 columns its finest
+SCMS interiors take the fused two-product form; a 128-column cycle takes the
+four-stage batched form.  The batch kernels (stored-row apply and
+Gauss-Seidel on groups of right-hand sides) run in every test.
+
+Bars (derived as in the other parity tests):
+  float64 apply             1e-12 relative, element-wise 1e-12 of max|y|
+  float64 cycle             1e-10 relative and element-wise (explicit
+                            inverses vs Cholesky solves, cond(A_0) eps)
+  float32 cycle             2e-5 relative (float32 operator data and
+                            arithmetic through the levels)
+  solves                    float64 true residual <= 1e-8 with the oracle's
+                            matrix; error against the oracle's float64
+                            solution (solved to 1e-13) reported per column
+                            and bounded by 1e-6 (a 1e-8 residual bounds the
+                            error only through the condition number)
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_common import cached_oracle, gpu_solver, max_abs_rel, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NRHS = 64
+COLS = (0, 21, 42, 63)
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def c4_8():
+    cfg, ob = cached_oracle("c4", 8)
+    assert cfg["p"] == 6 and cfg["nrhs"] == NRHS
+    F = np.stack([workloads.normal_rhs(ob.N, cfg["rhs"][1] + j) for j in range(NRHS)])
+    return cfg, ob, F
+
+
+@pytest.fixture(scope="module")
+def oracle_solutions(c4_8):
+    cfg, ob, F = c4_8
+    out = {}
+    for j in COLS:
+        u, its, _, _ = ob.pcg(F[j], tol=1e-13)
+        out[j] = u
+    return out
+
+
+def test_c4_apply_64(c4_8):
+    cfg, ob, F = c4_8
+    sv = gpu_solver(cfg, max_rhs=NRHS)
+    assert sv.n_dofs == ob.N
+    Y = sv.apply(_gpu(F)).cpu().numpy().reshape(NRHS, ob.N)
+    for j in COLS:
+        yo = ob.apply(F[j])
+        assert rel_err(Y[j], yo) < 1e-12, j
+        assert max_abs_rel(Y[j], yo) < 1e-12, j
+    sv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c4_one_cycle_64(c4_8, precision):
+    cfg, ob, F = c4_8
+    sv = gpu_solver(cfg, max_rhs=NRHS, precision=precision)
+    Z = sv.vcycle(_gpu(F), torch.zeros(NRHS * ob.N, dtype=torch.float64).cuda())
+    Z = Z.cpu().numpy().reshape(NRHS, ob.N)
+    bar = 1e-10 if precision == "fp64" else 2e-5
+    for j in COLS:
+        zo = ob.vcycle(F[j])
+        assert rel_err(Z[j], zo) < bar, (j, rel_err(Z[j], zo))
+        assert max_abs_rel(Z[j], zo) < bar, (j, max_abs_rel(Z[j], zo))
+    sv.close()
+
+
+@pytest.mark.parametrize("outer,precision", [("ir", "fp32"), ("fcg", "fp32"), ("pcg", "fp64"),
+                                             ("ir", "bf16")])
+def test_c4_solve_64(c4_8, oracle_solutions, outer, precision):
+    """All 64 columns converge; sampled columns meet the float64 true
+    residual 1e-8 with the oracle's matrix and are compared with the oracle's
+    solution (the error is printed per column)."""
+    cfg, ob, F = c4_8
+    sv = gpu_solver(cfg, max_rhs=NRHS, precision=precision, outer=outer)
+    U, info = sv.solve(_gpu(F), tol=1e-8, maxit=200)
+    U = U.cpu().numpy().reshape(NRHS, ob.N)
+    assert all(i["converged"] for i in info)
+    assert max(i["true_rel_residual"] for i in info) <= 1e-8
+    for j in COLS:
+        true_res = np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j])
+        err = rel_err(U[j], oracle_solutions[j])
+        print("c4/8 %s %s column %d: iterations %d, true residual %.3e, error vs oracle %.3e"
+              % (outer, precision, j, info[j]["iterations"], true_res, err))
+        assert true_res <= 1e-8, (j, true_res)
+        assert abs(info[j]["true_rel_residual"] - true_res) < 1e-12
+        assert err < 1e-6, (j, err)
+    sv.close()
+
+
+def test_c4_pcg_iterates_fp64(c4_8):
+    """float64 PCG on one column of the batch: iterates k = 1..4 and the
+    final solution at the oracle's iteration count agree to 1e-10."""
+    cfg, ob, F = c4_8
+    _, its, _, iterates = ob.pcg(F[0])
+    sv = gpu_solver(cfg, max_rhs=NRHS)
+    Fb = np.repeat(F[:1], 2, axis=0)
+    for k in (1, 2, 4, its):
+        U, info = sv.solve(_gpu(Fb), tol=1e-8, maxit=k)
+        u = U.cpu().numpy().reshape(2, ob.N)[1]
+        assert rel_err(u, iterates[k - 1]) < 1e-10, k
+        assert max_abs_rel(u, iterates[k - 1]) < 1e-10, k
+    sv.close()
+
+
+def test_c4_staged_cycle_128(c4_8):
+    """128 right-hand sides: the finest SCMS interiors of the batch exceed the
+    fused form's threshold and take the four-stage batched form at the
+    degree-6 shapes; sampled columns of one float64 cycle and one float32
+    cycle match the oracle's cycle."""
+    cfg, ob, _ = c4_8
+    nb = 2 * NRHS
+    F = np.stack([workloads.normal_rhs(ob.N, 5000 + j) for j in range(nb)])
+    for precision, bar in (("fp64", 1e-10), ("fp32", 2e-5)):
+        sv = gpu_solver(cfg, max_rhs=nb, precision=precision)
+        Z = sv.vcycle(_gpu(F), torch.zeros(nb * ob.N, dtype=torch.float64).cuda())
+        Z = Z.cpu().numpy().reshape(nb, ob.N)
+        for j in (0, 77, nb - 1):
+            zo = ob.vcycle(F[j])
+            assert rel_err(Z[j], zo) < bar, (precision, j)
+            assert max_abs_rel(Z[j], zo) < bar, (precision, j)
+        sv.close()

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.gpu_common import cached_oracle, gpu_solver, rel_err
+from tests.gpu_common import cached_oracle, gpu_solver, max_abs_rel, oracle_iterate, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -40,12 +40,15 @@ def test_full_apply_and_cycle(full_pair):
 def test_full_solve(full_pair):
     cfg, ob, sv = full_pair
     f = workloads.normal_rhs(ob.N, 2002)
-    uo, its, hist, _ = ob.pcg(f)
+    uo, its, hist, iterates = ob.pcg(f)
     u, info = sv.solve(torch.from_numpy(f).cuda(), tol=1e-8, maxit=200)
     ug = u.cpu().numpy()
-    assert info[0]["converged"] and abs(info[0]["iterations"] - its) <= 1
-    assert rel_err(ug, uo) < 1e-9
-    assert np.linalg.norm(f - ob.A[-1] @ ug) / np.linalg.norm(f) <= 1.01e-8
+    kg = info[0]["iterations"]
+    assert info[0]["converged"] and abs(kg - its) <= 1
+    ui = oracle_iterate(ob, f, kg, its, iterates)
+    assert rel_err(ug, ui) < 1e-10
+    assert max_abs_rel(ug, ui) < 1e-10
+    assert np.linalg.norm(f - ob.A[-1] @ ug) / np.linalg.norm(f) <= 1e-8
 
 
 def test_full_batch_cycle_staged_smoother(full_pair):
@@ -60,7 +63,9 @@ def test_full_batch_cycle_staged_smoother(full_pair):
     Z = sb.vcycle(torch.from_numpy(F).cuda(), torch.zeros(nb * ob.N, dtype=torch.float64).cuda())
     Z = Z.cpu().numpy().reshape(nb, ob.N)
     for j in (0, nb - 1):
-        assert rel_err(Z[j], ob.vcycle(F[j])) < 1e-10, j
+        zo = ob.vcycle(F[j])
+        assert rel_err(Z[j], zo) < 1e-10, j
+        assert max_abs_rel(Z[j], zo) < 1e-10, j
     sb.close()
 
 
@@ -85,5 +90,5 @@ def test_full_batch_low_precision_staged_smoother(full_pair, precision):
     U = U.cpu().numpy().reshape(nb, ob.N)
     assert all(i["converged"] for i in info)
     for j in (0, nb - 1):
-        assert np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j]) <= 1.05e-8, j
+        assert np.linalg.norm(F[j] - ob.A[-1] @ U[j]) / np.linalg.norm(F[j]) <= 1e-8, j
     sb.close()
