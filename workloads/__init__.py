@@ -61,6 +61,21 @@ def checkerboard_elems(counts, n_even, n_odd):
     return np.array(out, dtype=np.int64)
 
 
+def lshape_corners():
+    """The paper's L-shaped domain of three unit squares (Section 2: identity
+    and translations as geometry maps): (0,1)^2, (1,2) x (0,1), (0,1) x (1,2),
+    corner bit order x fastest."""
+    def square(x0, y0):
+        return [[x0, y0], [x0 + 1, y0], [x0, y0 + 1], [x0 + 1, y0 + 1]]
+    return np.array([square(0, 0), square(1, 0), square(0, 1)], dtype=np.float64)
+
+
+def lshape_elems(level, degrees=None):
+    """Element counts of the L-shape after `level` uniform refinements of one
+    element per patch: 2^level per direction."""
+    return np.full((3, 2), 2 ** int(level), dtype=np.int64)
+
+
 def normal_rhs(n, seed):
     return np.random.default_rng(seed).standard_normal(n)
 
