@@ -204,6 +204,22 @@ int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream);
  * frees its own scratch.  Errors: IGAMG_EINVAL (null argument), IGAMG_EHIP. */
 int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stream);
 
+/* igamg_l2_error without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and result as
+ * igamg_l2_error (the same fixed summation order, so the same value bit for
+ * bit).  Its scratch (tables, block partial sums, the result) lives in one
+ * static device array of 16 MiB per GPU, held until the process ends; the
+ * array's address is looked up once per device by igamg_setup.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two host threads) race and must be serialized by the caller.
+ * The current device must be the context's device.  Synchronizes `stream`.
+ * Errors: IGAMG_EINVAL (null argument, context of another device),
+ * IGAMG_EUNSUPPORTED (the problem's tables and partial sums need more than
+ * 16 MiB: about 500 million elements, or very large element counts per patch
+ * at high degree), IGAMG_EHIP. */
+int igamg_l2_error_noalloc(igamg_ctx *ctx, const double *u, double *err_host, void *stream);
+
 /* Device bytes owned by the context. */
 int igamg_memory(const igamg_ctx *ctx, size_t *bytes);
 

@@ -57,6 +57,68 @@ void flush_timers(igamg::Context &c) {
     kv.second.pending.clear();
   }
 }
+
+// Host tables of the L2 error: the (p+3)-point rule, per distinct element
+// count the basis values at its points, per patch and direction the table
+// offset, and the first element of every patch.
+struct L2Tables {
+  igamg::GaussRule gq;
+  std::vector<double> tB;
+  std::vector<int> tab;
+  std::vector<long long> el_off{0};
+  long long nel = 0;
+  explicit L2Tables(const igamg::Context &c) : gq(igamg::gauss_rule(c.p + 3)) {
+    const igamg::LevelData &L = c.lv.back();
+    tab.assign(3 * L.K, 0);
+    std::map<int, int> tab_of;
+    for (int k = 0; k < L.K; ++k) {
+      long long ne = 1;
+      for (int g = 0; g < c.d; ++g) {
+        const int n = L.pd[k].nel[g];
+        ne *= n;
+        auto it = tab_of.find(n);
+        if (it == tab_of.end()) {
+          std::vector<double> B, D;
+          igamg::element_tables(n, c.p, gq, B, D);
+          it = tab_of.emplace(n, (int)tB.size()).first;
+          tB.insert(tB.end(), B.begin(), B.end());
+        }
+        tab[3 * k + g] = it->second;
+      }
+      el_off.push_back(el_off.back() + ne);
+    }
+    nel = el_off.back();
+  }
+};
+
+// device arrays of one L2 error evaluation (scratch owned by the caller)
+struct L2Buffers {
+  double *tB = nullptr;
+  int *tab = nullptr;
+  long long *el_off = nullptr;
+  double *part = nullptr;  // l2_error_partials(nel) block sums
+  double *out = nullptr;   // one value
+};
+
+// Upload the tables, scatter u to the torn layout (context work vector x),
+// sum the squared error in a fixed order, read it back (synchronizes).
+double l2_error_run(igamg::Context &c, const L2Tables &t, const L2Buffers &b, const double *u) {
+  igamg::LevelData &L = c.lv.back();
+  HIPCHK(hipMemcpyAsync(b.tB, t.tB.data(), t.tB.size() * sizeof(double), hipMemcpyHostToDevice,
+                        c.stream));
+  HIPCHK(hipMemcpyAsync(b.tab, t.tab.data(), t.tab.size() * sizeof(int), hipMemcpyHostToDevice,
+                        c.stream));
+  HIPCHK(hipMemcpyAsync(b.el_off, t.el_off.data(), t.el_off.size() * sizeof(long long),
+                        hipMemcpyHostToDevice, c.stream));
+  const long long nt = L.Ntorn;
+  igamg::k_fill(c.x, 0.0, nt, c.stream);
+  igamg::k_scatter_compact(u, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, nt, 1, c.stream);
+  igamg::k_l2_error(c, L, c.x, b.el_off, b.tab, b.tB, t.gq, b.part, t.nel, b.out);
+  double e2 = 0.0;
+  HIPCHK(hipMemcpyAsync(&e2, b.out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return std::sqrt(e2);
+}
 }  // namespace
 
 extern "C" {
@@ -96,6 +158,9 @@ int igamg_setup(const igamg_patches *patches, int degree, double penalty_sigma,
     igamg_ctx *ctx = new igamg_ctx();
     try {
       igamg::build_context(ctx->c, patches, degree, penalty_sigma, o, (hipStream_t)stream);
+      // device scratch of the allocation-free entry points: its address on
+      // this device, looked up once per device
+      igamg::noalloc_scratch_init();
     } catch (...) {
       (void)hipStreamSynchronize((hipStream_t)stream);
       delete ctx;
@@ -197,50 +262,49 @@ int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stre
     if (!ctx || !u || !err_host) igamg::fail(IGAMG_EINVAL, "invalid argument");
     igamg::Context &c = ctx->c;
     c.stream = (hipStream_t)stream;
-    igamg::LevelData &L = c.lv.back();
-    // tables of the (p+3)-point rule per distinct element count
-    const igamg::GaussRule gq = igamg::gauss_rule(c.p + 3);
-    std::vector<double> tB;
-    std::vector<int> tab(3 * L.K, 0);
-    std::vector<long long> el_off{0};
-    std::map<int, int> tab_of;
-    for (int k = 0; k < L.K; ++k) {
-      long long ne = 1;
-      for (int g = 0; g < c.d; ++g) {
-        const int n = L.pd[k].nel[g];
-        ne *= n;
-        auto it = tab_of.find(n);
-        if (it == tab_of.end()) {
-          std::vector<double> B, D;
-          igamg::element_tables(n, c.p, gq, B, D);
-          it = tab_of.emplace(n, (int)tB.size()).first;
-          tB.insert(tB.end(), B.begin(), B.end());
-        }
-        tab[3 * k + g] = it->second;
-      }
-      el_off.push_back(el_off.back() + ne);
-    }
-    const long long nel = el_off.back();
+    L2Tables t(c);
     igamg::DeviceScratch s_tB, s_tab, s_eloff, s_part, s_out;
-    double *d_tB = s_tB.alloc<double>(tB.size());
-    int *d_tab = s_tab.alloc<int>(tab.size());
-    long long *d_eloff = s_eloff.alloc<long long>(el_off.size());
-    double *d_part = s_part.alloc<double>((size_t)nel);
-    double *d_out = s_out.alloc<double>(1);
-    HIPCHK(hipMemcpyAsync(d_tB, tB.data(), tB.size() * sizeof(double), hipMemcpyHostToDevice,
-                          c.stream));
-    HIPCHK(hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice,
-                          c.stream));
-    HIPCHK(hipMemcpyAsync(d_eloff, el_off.data(), el_off.size() * sizeof(long long),
-                          hipMemcpyHostToDevice, c.stream));
-    const long long nt = L.Ntorn;
-    igamg::k_fill(c.x, 0.0, nt, c.stream);
-    igamg::k_scatter_compact(u, L.N, c.d_fin_cp, c.d_fin_cidx, c.x, nt, 1, c.stream);
-    igamg::k_l2_error(c, L, c.x, d_eloff, d_tab, d_tB, gq, d_part, nel, d_out);
-    double e2 = 0.0;
-    HIPCHK(hipMemcpyAsync(&e2, d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipStreamSynchronize(c.stream));  // scratch freed at scope exit
-    *err_host = std::sqrt(e2);
+    L2Buffers b{s_tB.alloc<double>(t.tB.size()), s_tab.alloc<int>(t.tab.size()),
+                s_eloff.alloc<long long>(t.el_off.size()),
+                s_part.alloc<double>((size_t)igamg::l2_error_partials(t.nel)),
+                s_out.alloc<double>(1)};
+    *err_host = l2_error_run(c, t, b, u);  // synchronizes: scratch freed at scope exit
+    return IGAMG_OK;
+  });
+}
+
+int igamg_l2_error_noalloc(igamg_ctx *ctx, const double *u, double *err_host, void *stream) {
+  return guarded([&] {
+    if (!ctx || !u || !err_host) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    igamg::Context &c = ctx->c;
+    c.stream = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != c.device)
+      igamg::fail(IGAMG_EINVAL, "the context's device is not the current device");
+    // looked up once per device by igamg_setup (or here on the first call)
+    char *base = (char *)igamg::noalloc_scratch(dev);
+    if (!base) base = (char *)igamg::noalloc_scratch_init();
+    L2Tables t(c);
+    // carve the device scratch: each array on a 256-byte boundary
+    size_t at = 0;
+    auto carve = [&](size_t bytes) {
+      const size_t o = at;
+      at += (bytes + 255) / 256 * 256;
+      return base + o;
+    };
+    L2Buffers b;
+    b.out = (double *)carve(sizeof(double));
+    b.el_off = (long long *)carve(t.el_off.size() * sizeof(long long));
+    b.tab = (int *)carve(t.tab.size() * sizeof(int));
+    b.tB = (double *)carve(t.tB.size() * sizeof(double));
+    b.part = (double *)carve((size_t)igamg::l2_error_partials(t.nel) * sizeof(double));
+    if (at > igamg::NOALLOC_SCRATCH_BYTES)
+      igamg::fail(IGAMG_EUNSUPPORTED,
+                  "problem needs " + std::to_string(at) + " bytes of device scratch; the "
+                  "allocation-free L2 error holds at most " +
+                      std::to_string(igamg::NOALLOC_SCRATCH_BYTES) + " bytes");
+    *err_host = l2_error_run(c, t, b, u);
     return IGAMG_OK;
   });
 }

@@ -263,6 +263,7 @@ struct Context {
   int *h_active = nullptr;       // pinned host mirror (written only after a stream sync)
   bool own_pinned = true;        // h_scal / h_active allocated by the context
   hipStream_t stream = nullptr;
+  int device = 0;  // HIP device the context was built on
   Arena arena;
   std::map<std::string, TimerFamily> timers;
   std::string timing_filter;  // time only families whose key starts with this

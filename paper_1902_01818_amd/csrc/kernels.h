@@ -26,10 +26,18 @@ void k_stencil_add(const int *rows, const int *slots, const double *vals, int n,
 void k_invdiag(const double *stencil, int S, int center, const unsigned char *mask, double *invd,
                long long n, hipStream_t s);
 // squared L2 error of torn coefficients ut against prod sin(pi x), summed in a
-// fixed order into out[0] (part: nel scratch values)
+// fixed order into out[0] (part: l2_error_partials(nel) scratch values)
 void k_l2_error(Context &c, LevelData &L, const double *ut, const long long *el_off,
                 const int *tab, const double *tB, const GaussRule &gq, double *part,
                 long long nel, double *out);
+long long l2_error_partials(long long nel);
+// Device scratch of the allocation-free entry points: NOALLOC_SCRATCH_BYTES
+// per GPU.  noalloc_scratch_init() looks up its address on the current device
+// (once per device) and returns it; noalloc_scratch(device) returns the
+// address found for that device, or null before the lookup.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+void *noalloc_scratch_init();
+void *noalloc_scratch(int device);
 void k_load_manufactured(Context &c, LevelData &L, double *out);
 // in-place inverse of a dense SPD n x n matrix (blocked Gauss-Jordan);
 // bad[0] is set to 1 when a pivot is not positive (not SPD)

@@ -28,8 +28,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <type_traits>
+#include <map>
+#include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "geom.h"
 #include "kernels.h"
@@ -416,16 +418,14 @@ __global__ void invdiag_kernel(const double *st, int S, int center, const unsign
 }
 
 // (f, phi_i) for f = d pi^2 prod sin(pi x), gather over the support of phi_i
-// Squared L2 error of u_h (torn coefficients) against prod sin(pi x) on one
-// element per thread: qe-point Gauss rule per direction, 1D tables of all
-// basis values at those points (tab: offset of the element count's table per
-// patch and direction, rows [e][g][a]).  el_off: first element of each patch.
+// Squared L2 error of u_h (torn coefficients) against prod sin(pi x) on
+// element t: qe-point Gauss rule per direction, 1D tables of all basis values
+// at those points (tab: offset of the element count's table per patch and
+// direction, rows [e][g][a]).  el_off: first element of each patch.
 template <int D>
-__global__ void l2err_kernel(const PatchDev *pd, int K, const long long *el_off,
-                             const int *tab, const double *tB, GaussRule gq, int p,
-                             const double *ut, double *part) {
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= el_off[K]) return;
+__device__ double l2err_element(const PatchDev *pd, int K, const long long *el_off,
+                                const int *tab, const double *tB, GaussRule gq, int p,
+                                const double *ut, long long t) {
   int k = 0;
   while (k + 1 < K && el_off[k + 1] <= t) ++k;
   const PatchDev &pt = pd[k];
@@ -471,7 +471,26 @@ __global__ void l2err_kernel(const PatchDev *pd, int K, const long long *el_off,
     while (d < D && ++g[d] == q) g[d++] = 0;
     if (d == D) break;
   }
-  part[t] = sum;
+  return sum;
+}
+
+// Each block sums its elements' contributions by a fixed tree and writes one
+// partial (part[blockIdx.x]).
+template <int D>
+__global__ __launch_bounds__(256) void l2err_kernel(const PatchDev *pd, int K,
+                                                    const long long *el_off, const int *tab,
+                                                    const double *tB, GaussRule gq, int p,
+                                                    const double *ut, double *part) {
+  __shared__ double sp[256];
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const double sum = t < el_off[K] ? l2err_element<D>(pd, K, el_off, tab, tB, gq, p, ut, t) : 0.0;
+  sp[threadIdx.x] = sum;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sp[threadIdx.x] += sp[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sp[0];
 }
 
 // sum of n values by one block in a fixed order (strided partial sums, then a
@@ -2601,17 +2620,56 @@ void k_load_manufactured(Context &c, LevelData &L, double *out) {
                                                           L.d_mask, L.Ntorn, out);
 }
 
+long long l2_error_partials(long long nel) { return (nel + BS - 1) / BS; }
+
 void k_l2_error(Context &c, LevelData &L, const double *ut, const long long *el_off,
                 const int *tab, const double *tB, const GaussRule &gq, double *part,
                 long long nel, double *out) {
+  const long long nb = l2_error_partials(nel);
+  if (nb > 65535LL * 64) fail(IGAMG_EUNSUPPORTED, "too many elements for the L2 error kernel");
   if (c.d == 2)
-    l2err_kernel<2><<<nblocks(nel), BS, 0, c.stream>>>(L.d_pd, L.K, el_off, tab, tB, gq, c.p, ut,
+    l2err_kernel<2><<<(unsigned)nb, BS, 0, c.stream>>>(L.d_pd, L.K, el_off, tab, tB, gq, c.p, ut,
                                                        part);
   else
-    l2err_kernel<3><<<nblocks(nel), BS, 0, c.stream>>>(L.d_pd, L.K, el_off, tab, tB, gq, c.p, ut,
+    l2err_kernel<3><<<(unsigned)nb, BS, 0, c.stream>>>(L.d_pd, L.K, el_off, tab, tB, gq, c.p, ut,
                                                        part);
-  sum_fixed_kernel<<<1, 1024, 0, c.stream>>>(part, nel, out);
+  sum_fixed_kernel<<<1, 1024, 0, c.stream>>>(part, nb, out);
   HIPCHK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free entry points (igamg_l2_error_noalloc):
+// one array per GPU, held until the process ends.  In host code the array's
+// name is a host-side stand-in, not a device address; host code uses only
+// the address hipGetSymbolAddress returns for the current device, looked up
+// once per device and kept in noalloc_addr.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex noalloc_mu;
+std::map<int, void *> noalloc_addr;
+}  // namespace
+
+void *noalloc_scratch_init() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  auto it = noalloc_addr.find(dev);
+  if (it != noalloc_addr.end()) return it->second;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    fail(IGAMG_EHIP, std::string("hipGetSymbolAddress of the device scratch failed: ") +
+                         hipGetErrorString(e));
+  noalloc_addr[dev] = ptr;
+  return ptr;
+}
+
+void *noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  auto it = noalloc_addr.find(device);
+  return it == noalloc_addr.end() ? nullptr : it->second;
 }
 
 template <typename T>

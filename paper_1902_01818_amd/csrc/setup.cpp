@@ -1434,6 +1434,7 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   init_problem(c, P, degree, sigma, o);
   pc.lap("topology");
   c.stream = s;
+  HIPCHK(hipGetDevice(&c.device));
   HIPCHK(hipEventCreateWithFlags(&c.ev_scal, hipEventDisableTiming));
   if (lent && lent->device) {
     c.arena.region = (char *)lent->device;

@@ -62,6 +62,7 @@ _lib.igamg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctype
                              ctypes.c_int, ctypes.POINTER(SolveInfo), _vp]
 _lib.igamg_load_manufactured.argtypes = [_vp, _vp, _vp]
 _lib.igamg_l2_error.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
+_lib.igamg_l2_error_noalloc.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
 _lib.igamg_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
 _lib.igamg_kernel_stats.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
@@ -103,7 +104,8 @@ _lib.igamg_server_destroy.argtypes = [_vp]
 
 EXPORTED = ["igamg_default_options", "igamg_footprint", "igamg_setup", "igamg_num_dofs",
             "igamg_num_levels", "igamg_apply", "igamg_vcycle", "igamg_solve",
-            "igamg_load_manufactured", "igamg_l2_error", "igamg_memory", "igamg_kernel_stats",
+            "igamg_load_manufactured", "igamg_l2_error", "igamg_l2_error_noalloc",
+            "igamg_memory", "igamg_kernel_stats",
             "igamg_kernel_model", "igamg_set_timing", "igamg_destroy", "igamg_strerror",
             "igamg_last_error", "igamg_problem_size", "igamg_server_create", "igamg_server_submit",
             "igamg_server_wait", "igamg_server_status", "igamg_server_destroy"]
@@ -300,6 +302,15 @@ class Solver:
         e = ctypes.c_double()
         _check(_lib.igamg_l2_error(self._h, _dptr(u, self.n_dofs), ctypes.byref(e), _stream(stream)),
                "igamg_l2_error")
+        return e.value
+
+    def l2_error_noalloc(self, u, stream=None):
+        """As l2_error, through the entry point that allocates no device
+        memory (its scratch is a static device array shared by every call on
+        the GPU)."""
+        e = ctypes.c_double()
+        _check(_lib.igamg_l2_error_noalloc(self._h, _dptr(u, self.n_dofs), ctypes.byref(e),
+                                           _stream(stream)), "igamg_l2_error_noalloc")
         return e.value
 
     def memory(self):
