@@ -3013,8 +3013,16 @@ void k_pieces(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "pieces", L.l);
   if (L.n_pieces == 0) return;
   LevelArrays<T> &A = L.arr<T>();
+  // dynamic LDS: the piece's residual; static: 16 x 64 partial sums
+  const size_t shm = (size_t)L.max_piece * sizeof(T);
+  if (shm + 16 * 64 * sizeof(T) > 160 * 1024)
+    fail(IGAMG_EUNSUPPORTED, "interface piece too large for the piece kernel's LDS");
+  static const hipError_t lds_set = hipFuncSetAttribute(
+      (const void *)piece_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      160 * 1024 - 16 * 64 * (int)sizeof(T));
+  HIPCHK(lds_set);
   dim3 grid(nrhs, L.n_pieces, (L.max_piece + 63) / 64);
-  piece_kernel<T><<<grid, 1024, (size_t)L.max_piece * sizeof(T), c.stream>>>(
+  piece_kernel<T><<<grid, 1024, shm, c.stream>>>(
       L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, A.piece_inv, A.r, A.u,
       (T)c.opt.damping_tau, L.Ntorn);
 }

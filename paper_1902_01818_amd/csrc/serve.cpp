@@ -150,8 +150,10 @@ void igamg_server::worker_loop(int slot) {
     }
     cv_work.notify_all();  // the next head may fit as well
     int status = IGAMG_OK;
+    std::unique_ptr<igamg::Context> cp;
     try {
-      igamg::Context c;
+      cp = std::make_unique<igamg::Context>();
+      igamg::Context &c = *cp;
       igamg::Lent lent;
       lent.device = base + off;
       lent.device_bytes = r->footprint;
@@ -167,6 +169,7 @@ void igamg_server::worker_loop(int slot) {
       r->info.t_ready = now();
       igamg_solve_info si{};
       status = igamg::solve_batch(c, d_rhs, d_u, 1, r->tol, r->maxit, 0, &si);
+      HIPCHK(hipGetLastError());  // a launch that failed inside the solve
       r->u.resize(L.N);
       HIPCHK(hipMemcpyAsync(r->u.data(), d_u, L.N * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -177,11 +180,13 @@ void igamg_server::worker_loop(int slot) {
       r->info.fallback_allocations = c.arena.fallbacks;
     } catch (const igamg::Error &e) {
       status = e.code;
-      (void)hipStreamSynchronize(s);
     } catch (...) {
       status = IGAMG_EINVAL;
-      (void)hipStreamSynchronize(s);
     }
+    // the request's kernels finish before its context, and the arrays it
+    // allocated outside its block, are released
+    (void)hipStreamSynchronize(s);
+    cp.reset();
     {
       std::lock_guard<std::mutex> lk(m);
       pool.give(off, r->footprint);

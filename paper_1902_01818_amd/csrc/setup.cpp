@@ -863,6 +863,10 @@ static void build_pieces(Context &c, LevelData &L, const double *st64, int SP) {
     L.piece_n += pc.n;
   }
   L.n_pieces = (int)pcs.size();
+  // the piece kernel holds a piece's residual in LDS next to 16 x 64 partial
+  // sums (float64 here: the float32 cycle needs half of it)
+  if ((size_t)L.max_piece * sizeof(double) + 16 * 64 * sizeof(double) > 160 * 1024)
+    fail(IGAMG_EUNSUPPORTED, "interface piece too large for the piece kernel's LDS");
   L.d_pieces = c.arena.upload(pcs, c.stream);
   L.d_piece_idx = c.arena.upload(idx, c.stream);
   L.d_piece_cp = c.arena.upload(cp, c.stream);
