@@ -94,6 +94,18 @@ class Topology:
             while c in taken:
                 c += 1
             self.patch_color.append(c)
+        # greedy first-fit colouring of the vertex-sharing graph in patch order:
+        # patches with a common corner get different colours (the conforming
+        # Gauss-Seidel ordering, where a glued unknown couples every patch
+        # around its vertex or edge)
+        vset = [set(int(v) for v in self.vid[k]) for k in range(self.K)]
+        self.vertex_color = []
+        for k in range(self.K):
+            taken = {self.vertex_color[j] for j in range(k) if vset[j] & vset[k]}
+            c = 0
+            while c in taken:
+                c += 1
+            self.vertex_color.append(c)
         self.measure = np.array([patch_measure(corners[k]) for k in range(self.K)])
 
 

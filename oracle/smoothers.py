@@ -194,18 +194,32 @@ class SCMSSmoother:
 # multicolour Gauss-Seidel
 # ---------------------------------------------------------------------------
 def gs_color_keys(level, tile):
-    """Colour key of every compact unknown (SIPG torn DOFs, one copy each):
-    key = ((c_k * 2^d + pi) * (p+1)^d + s) with c_k the patch colour,
-    pi = sum_d (floor(i_d / tile) mod 2) 2^d the tile parity and
+    """Colour key of every compact unknown, taken at its first copy (patch k,
+    index i in k): key = ((c_k * 2^d + pi) * (p+1)^d + s) with c_k the patch
+    colour, pi = sum_d (floor(i_d / tile) mod 2) 2^d the tile parity and
     s = sum_d (i_d mod (p+1)) (p+1)^d the position inside the (p+1)^d block.
-    Unknowns with equal keys are never coupled: inside a patch two of them
-    differ by a multiple of p+1 >= p+1 in some index, across patches equal
-    colour means no common interface.  tile >= p keeps tiles of equal parity
-    uncoupled as well."""
+
+    SIPG space (one copy per unknown): c_k colours the face-adjacency graph.
+    Two unknowns of equal key are never coupled: inside a patch they differ
+    by a multiple of p+1 >= p+1 in some index, across patches equal colour
+    means no common interface.
+
+    Conforming space: c_k colours the vertex-sharing graph (a glued unknown
+    couples the patches around its vertex or edge).  Equal keys again mean no
+    coupling: two unknowns first seen in the same patch differ by >= p+1 in
+    some index of that patch, and a patch holding copies of both sees the
+    same distance along the side it shares with it; unknowns first seen in
+    different patches of one colour lie in patches without a common corner,
+    and a third patch holding copies of both would hold them on two of its
+    sides without a common corner, at least n_el + p - 1 >= p + 1 apart
+    (n_el >= 2 on every smoothed level).
+
+    tile >= p keeps tiles of equal parity uncoupled as well."""
     topo = level.topo
     d = level.d
     p = level.p
     assert tile >= p
+    color = topo.vertex_color if level.conforming else topo.patch_color
     keys = np.zeros(level.N, dtype=np.int64)
     for t in range(level.N_torn):
         c = level.comp_of_torn[t]
@@ -215,7 +229,7 @@ def gs_color_keys(level, tile):
         i = level.idx[k][t - level.offsets[k]]
         par = sum(((int(i[g]) // tile) % 2) << g for g in range(d))
         sub = sum((int(i[g]) % (p + 1)) * (p + 1) ** g for g in range(d))
-        keys[c] = (topo.patch_color[k] * 2 ** d + par) * (p + 1) ** d + sub
+        keys[c] = (color[k] * 2 ** d + par) * (p + 1) ** d + sub
     return keys
 
 

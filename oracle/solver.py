@@ -39,8 +39,6 @@ class OracleProblem:
         self.mu, self.nu = mu, nu
         self.tau, self.delta = tau, delta
         self.gs_tile = 2 * (p + 1) if gs_tile is None else gs_tile
-        if conforming and smoother in ("gs", "hybrid"):
-            raise NotImplementedError("Gauss-Seidel ordering is defined for SIPG only")
         self.eta = None if conforming else penalty(self.topo, elems, p, sigma)
         self.level_elems = level_elements(elems, coarse_min)
         self.levels = [Level(self.topo, e, p, conforming, self.eta) for e in self.level_elems]

@@ -76,6 +76,28 @@ def lshape_elems(level, degrees=None):
     return np.full((3, 2), 2 ** int(level), dtype=np.int64)
 
 
+def fichera_corners():
+    """The Fichera corner: the cube (0,2)^3 without the octant (1,2)^3, as
+    seven axis-aligned unit cubes (identity and translations as geometry
+    maps), listed with x fastest, then y, then z; corner bit order x
+    fastest."""
+    cubes = []
+    for kz in range(2):
+        for ky in range(2):
+            for kx in range(2):
+                if kx == 1 and ky == 1 and kz == 1:
+                    continue
+                cubes.append([[kx + (b & 1), ky + ((b >> 1) & 1), kz + ((b >> 2) & 1)]
+                              for b in range(8)])
+    return np.array(cubes, dtype=np.float64)
+
+
+def fichera_elems(level):
+    """Element counts of the Fichera corner after `level` uniform refinements
+    of one element per patch: 2^level per direction."""
+    return np.full((7, 3), 2 ** int(level), dtype=np.int64)
+
+
 def normal_rhs(n, seed):
     return np.random.default_rng(seed).standard_normal(n)
 
