@@ -308,6 +308,75 @@ def c3_leg(igamg, torch, workloads, precision="fp32", steps=2, operator_apply="a
     return out, u
 
 
+def _printed(name):
+    """Iteration counts a table of the paper prints (tests/golden fixture):
+    {L: row} with None where the paper prints no count."""
+    rows = {}
+    with open(os.path.join(ROOT, "tests", "golden", name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                v = [None if x == "-" else int(x) for x in line.split()]
+                rows[v[0]] = v[1:]
+    return rows
+
+
+def paper_tables(igamg, torch, workloads, maxit=150):
+    """The paper's conforming experiments on the GPU, each count beside the
+    printed one: Table GS1 (L-shape, Gauss-Seidel V-cycle, multigrid used
+    directly and as PCG preconditioner; L = 4..8, p = 2..8), Table SCMS1
+    (L-shape, SCMS V-cycle, damping 1, scaling 0.12) and Table HYB3 (a)
+    (Fichera corner, hybrid V-cycle with PCG, scaling 0.12, L = 2..5,
+    p = 2..4; damping 0.5, the largest for which this build's reading of the
+    piece smoother keeps the cycle positive, and the paper's 1).  A count of
+    None means no convergence within maxit cycles."""
+    out = {}
+
+    def run(corners, elems, p, smoother, tau, outer, conforming=True):
+        t0 = time.perf_counter()
+        sv = igamg.Solver(corners, elems, p, 5.0, conforming=conforming, smoother=smoother,
+                          tau=tau, delta=0.12, coarse_min=1, outer=outer)
+        setup = time.perf_counter() - t0
+        f = sv.load_manufactured()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info = sv.solve(f, tol=1e-8, maxit=maxit)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = info[0]["converged"] and info[0]["true_rel_residual"] <= 1e-8
+        rec = dict(iterations=info[0]["iterations"] if ok else None, solve_s=dt, setup_s=setup,
+                   dofs=sv.n_dofs)
+        sv.close()
+        return rec
+
+    for table, smoother, tau, golden in (("GS1", "gs", 0.25, "gs1_lshape_conforming.txt"),
+                                         ("SCMS1", "scms", 1.0, "scms1_lshape_conforming.txt")):
+        printed = _printed(golden)
+        rows = []
+        for L in range(4, 9):
+            for p in range(2, 9):
+                for blk, outer in (("a", "mg"), ("b", "pcg")):
+                    col = (p - 2) + (0 if blk == "a" else 7)
+                    r = run(workloads.lshape_corners(), workloads.lshape_elems(L), p, smoother,
+                            tau, outer)
+                    r.update(L=L, p=p, block=blk, printed=printed[L][col])
+                    rows.append(r)
+        out[table] = rows
+        print("bench: table %s done" % table, file=sys.stderr, flush=True)
+    printed = _printed("hyb3_fichera.txt")
+    rows = []
+    for tau in (0.5, 1.0):
+        for L in range(2, 6):
+            for p in range(2, 5):
+                r = run(workloads.fichera_corners(), workloads.fichera_elems(L), p, "hybrid",
+                        tau, "pcg")
+                r.update(L=L, p=p, block="a", damping=tau, printed=printed[L][p - 2])
+                rows.append(r)
+    out["HYB3a"] = rows
+    print("bench: table HYB3 (a) done", file=sys.stderr, flush=True)
+    return out
+
+
 def c2_legs(igamg, torch, workloads, steps=10, warmup=2, coarse_min=8):
     """The 4x4 degree-4 workload (115,652 unknowns, one right-hand side):
     float64 PCG and the float32 cycle inside float64 flexible CG."""
@@ -360,6 +429,9 @@ def main():
                          "1000 right-hand sides, L2 error ladder) and print its results")
     ap.add_argument("--c3-only", action="store_true",
                     help="diagnostic: run only the full-size 3D legs and print their results")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="run only the paper's conforming experiments (Tables GS1, SCMS1, "
+                         "HYB3 (a)) and print the counts beside the printed ones")
     ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy MIB MiB device to device (counter calibration)")
@@ -378,6 +450,10 @@ def main():
 
     if args.c1_only:
         print(json.dumps({"c1": c1_leg(igamg, torch, workloads)}))
+        return
+
+    if args.paper_tables:
+        print(json.dumps(paper_tables(igamg, torch, workloads)))
         return
 
     if args.c3_only:

@@ -166,6 +166,12 @@ struct LevelData {
   int n_if_rows = 0;
   // cross-patch couplings per Gauss-Seidel tile: (row inside tile, column)
   int *d_gcx_li = nullptr, *d_gcx_col = nullptr;
+  // conforming Gauss-Seidel levels: the cross-patch couplings of every owner
+  // row (first copy of a compact unknown) as a CSR over torn rows (host), and
+  // the mirror writes of the tiles (row inside tile, torn copy to overwrite)
+  std::vector<int> cf_ptr, cf_col;
+  std::vector<double> cf_val;
+  int *d_mr_li = nullptr, *d_mr_dst = nullptr;
   unsigned char *d_mask = nullptr;
   // glue groups (conforming): CSR of torn copies of every shared unknown
   int n_glue = 0;

@@ -81,15 +81,18 @@ struct GsTile {
   int nx, ny;        // patch tensor extents
   int i0[2];         // first unknown of the tile
   int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
+  int mr_off, mr_n;  // conforming: copies in other patches of the tile's owned glued
+                     // unknowns (mirror writes, in the level's flat lists)
 };
 
 // Gauss-Seidel tile of a 3D patch (2(p+1) unknowns per direction), with the
 // fields of its patch that the kernels need (the cross-patch couplings of 3D
 // levels are a CSR over the coupled rows, not per tile).
 struct GsTile3 {
-  long long off;  // patch offset in the level vector
-  int n[3];       // patch tensor extents
-  int i0[3];      // first unknown of the tile
+  long long off;     // patch offset in the level vector
+  int n[3];          // patch tensor extents
+  int i0[3];         // first unknown of the tile
+  int mr_off, mr_n;  // conforming: mirror writes of the tile's owned glued unknowns
 };
 
 // Two chained products on a block of 16 rows (fast-diagonalization step of the

@@ -964,6 +964,21 @@ __global__ void glue_kernel(int ng, const int *ptr, const int *idx, T *y, long l
   for (int e = ptr[g]; e < ptr[g + 1]; ++e) y[idx[e]] = s;
 }
 
+// Conforming Gauss-Seidel levels: a distributed right-hand side gathered on
+// the first copy of every glued unknown (the row the sweep updates); the
+// other copies become 0, so the copies' sum, and with it the distributed
+// form the residuals assume, is unchanged.  Fixed summation order.
+template <typename T>
+__global__ void glue_first_kernel(int ng, const int *ptr, const int *idx, T *y, long long vs) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  y += (long long)blockIdx.y * vs;
+  T s = 0;
+  for (int e = ptr[g]; e < ptr[g + 1]; ++e) s += y[idx[e]];
+  y[idx[ptr[g]]] = s;
+  for (int e = ptr[g] + 1; e < ptr[g + 1]; ++e) y[idx[e]] = (T)0;
+}
+
 // ---------------------------------------------------------------------------
 // Multicolour Gauss-Seidel, one wavefront per tile of 2(p+1) x 2(p+1)
 // unknowns: the four unknowns of a colour class inside the tile are updated
@@ -985,6 +1000,8 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
                                                        const int *__restrict__ cx_li,
                                                        const int *__restrict__ cx_col,
                                                        const T *__restrict__ cx_val,
+                                                       const int *__restrict__ mr_li,
+                                                       const int *__restrict__ mr_dst,
                                                        const T *__restrict__ f, T *u,
                                                        long long vs, int nrhs) {
   using T2 = typename Pair2<T>::type;
@@ -1133,6 +1150,12 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   for (int i = lane; i < TT * TT; i += 64) {
     int iy = y0 + i / TT, ix = x0 + i % TT;
     if (ix < nx && iy < ny) u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
+  }
+  // conforming: the tile's owned glued unknowns into their copies in other
+  // patches (those patches carry other colours: nothing else writes there)
+  for (int e = lane; e < tl.mr_n; e += 64) {
+    const int lt = mr_li[tl.mr_off + e];
+    u[mr_dst[tl.mr_off + e]] = sU[(lt / TT + P) * W + lt % TT + P];
   }
 }
 
@@ -1377,6 +1400,8 @@ template <typename T, int P, bool BWD>
 __global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T *__restrict__ st,
                                                    const T *__restrict__ invd,
                                                    const T *__restrict__ xs,
+                                                   const int *__restrict__ mr_li,
+                                                   const int *__restrict__ mr_dst,
                                                    const T *__restrict__ f, T *u, long long vs) {
   using G = Tile3<P>;
   constexpr int Q1 = G::Q1, TT = G::TT, W = G::W, SP = G::SP, NPH = G::NPH;
@@ -1469,6 +1494,12 @@ __global__ __launch_bounds__(512) void gs3d_kernel(const GsTile3 *tiles, const T
     if (x0 + dx < nx && y0 + dy < ny && z0 + dz < nz)
       u[tl.off + ((long long)(z0 + dz) * ny + y0 + dy) * nx + x0 + dx] =
           sU[((dz + P) * W + dy + P) * W + dx + P];
+  }
+  // conforming: the tile's owned glued unknowns into their other copies
+  for (int e = tid; e < tl.mr_n; e += 512) {
+    const int lt = mr_li[tl.mr_off + e];
+    const int dx = lt % TT, dy = lt / TT % TT, dz = lt / (TT * TT);
+    u[mr_dst[tl.mr_off + e]] = sU[((dz + P) * W + dy + P) * W + dx + P];
   }
 }
 
@@ -2747,7 +2778,8 @@ static void launch_gs2d_dir(Context &c, LevelData &L, const GsClass &cl, int nrh
   LevelArrays<T> &A = L.arr<T>();
   dim3 grid((nrhs + RBW - 1) / RBW, cl.count);
   gs2d_wave_kernel<T, P, RBW, BWD><<<grid, 64 * RBW, 0, c.stream>>>(
-      cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, A.f, A.u, L.Ntorn, nrhs);
+      cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, L.d_mr_li, L.d_mr_dst,
+      A.f, A.u, L.Ntorn, nrhs);
 }
 
 // the sweep direction is a template parameter: the unrolled class steps then
@@ -2773,10 +2805,10 @@ static void launch_gs3d(Context &c, LevelData &L, const GsClass &cl, bool backwa
   LevelArrays<T> &A = L.arr<T>();
   if (backward)
     gs3d_kernel<T, P, true><<<dim3(nrhs, cl.count), 512, 0, c.stream>>>(
-        cl.tiles3, A.stencil, A.invdiag, A.xsum, A.f, A.u, L.Ntorn);
+        cl.tiles3, A.stencil, A.invdiag, A.xsum, L.d_mr_li, L.d_mr_dst, A.f, A.u, L.Ntorn);
   else
     gs3d_kernel<T, P, false><<<dim3(nrhs, cl.count), 512, 0, c.stream>>>(
-        cl.tiles3, A.stencil, A.invdiag, A.xsum, A.f, A.u, L.Ntorn);
+        cl.tiles3, A.stencil, A.invdiag, A.xsum, L.d_mr_li, L.d_mr_dst, A.f, A.u, L.Ntorn);
 }
 
 // couplings of the coupled rows r0 .. r1 (CSR order): xs = X u, or out +=
@@ -2799,6 +2831,11 @@ void k_gs_sweep(Context &c, LevelData &L, bool backward, int nrhs) {
   // one event pair around the sweep (its class launches run back to back)
   TimeScope ts(c, "gauss_seidel", L.l);
   ts.n = 0;
+  if (c.opt.discretization == IGAMG_CONFORMING && L.n_glue > 0) {
+    glue_first_kernel<T><<<dim3(nblocks(L.n_glue), nrhs), BS, 0, c.stream>>>(
+        L.n_glue, L.d_glue_ptr, L.d_glue_idx, L.arr<T>().f, L.Ntorn);
+    ++ts.n;
+  }
   int nc = (int)L.gs.size();
   for (int ii = 0; ii < nc; ++ii) {
     const int ci = backward ? nc - 1 - ii : ii;

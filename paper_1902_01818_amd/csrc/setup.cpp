@@ -202,10 +202,26 @@ static void build_topology(Context &c) {
               c.boundary[l][2 * dl + sl] = 0;
             }
         }
+  // patch colours for the Gauss-Seidel order: SIPG separates patches with a
+  // common side; the conforming space separates patches with a common corner
+  // (a glued unknown couples every patch around its vertex or edge)
   std::vector<std::vector<int>> nbr(K);
-  for (auto &f : c.ifaces) {
-    nbr[f.k].push_back(f.l);
-    nbr[f.l].push_back(f.k);
+  if (c.opt.discretization == IGAMG_CONFORMING) {
+    for (int k = 0; k < K; ++k)
+      for (int l = k + 1; l < K; ++l) {
+        bool common = false;
+        for (int a : c.vid[k])
+          for (int b : c.vid[l]) common |= a == b;
+        if (common) {
+          nbr[k].push_back(l);
+          nbr[l].push_back(k);
+        }
+      }
+  } else {
+    for (auto &f : c.ifaces) {
+      nbr[f.k].push_back(f.l);
+      nbr[f.l].push_back(f.k);
+    }
   }
   c.color.assign(K, 0);
   c.n_colors = 1;
@@ -732,6 +748,137 @@ static std::vector<double> stencil_rows_host(Context &c, const LevelData &L, con
   return out;
 }
 
+// Rows of the assembled float64 stencil (device) at the given torn indices,
+// copied to the host ([n][SP]).
+static std::vector<double> torn_rows_host(Context &c, const double *st64, int SP,
+                                          const std::vector<int> &rows) {
+  std::vector<double> out(rows.size() * SP);
+  if (rows.empty()) return out;
+  int *d_rows = nullptr;
+  double *d_out = nullptr;
+  const bool lent = c.arena.region != nullptr;  // inside a lent region: no driver calls
+  if (lent) {
+    d_rows = c.arena.alloc<int>(rows.size());
+    d_out = c.arena.alloc<double>(out.size());
+  } else {
+    HIPCHK(hipMalloc((void **)&d_rows, rows.size() * sizeof(int)));
+    HIPCHK(hipMalloc((void **)&d_out, out.size() * sizeof(double)));
+  }
+  HIPCHK(hipMemcpyAsync(d_rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice,
+                        c.stream));
+  k_gather_rows(st64, SP, d_rows, (int)rows.size(), d_out, c.stream);
+  HIPCHK(hipMemcpyAsync(out.data(), d_out, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  if (!lent) {
+    (void)hipFree(d_rows);
+    (void)hipFree(d_out);
+  }
+  return out;
+}
+
+// Gauss-Seidel rows of the conforming space (Section 4 on the glued space of
+// eq. igaspace0).  The matrix row of a glued unknown is the sum of the
+// patch-local rows of its copies.  Its first copy (the owner, in patch k)
+// carries the whole row: an entry of another copy's row (patch m) whose
+// column has a copy in k inside the owner's (2p+1)^d stencil is added to
+// that stencil slot; every other entry becomes a cross-patch coupling of the
+// owner row, read at the column's copy in m.  The additions go to the device
+// rows (unique (row, slot) pairs, summed on the host in a fixed order); the
+// couplings are left in L.cf_* for the tile lists.  The couplings' columns
+// belong to patches of other colours (the vertex-sharing colouring), so they
+// are constant while the owner's colour is swept; a column of the owner's
+// colour outside its stencil would break that and is rejected.
+static void fold_conforming_rows(Context &c, LevelData &L, double *st64, int SP) {
+  const int d = c.d, p = c.p, S1 = 2 * p + 1;
+  int S = 1;
+  for (int g = 0; g < d; ++g) S *= S1;
+  std::vector<int> others;  // non-owner copies of glued unknowns, by compact index
+  for (long long ci = 0; ci < L.N; ++ci)
+    for (int t : L.copies(ci))
+      if (t != L.rep[ci]) others.push_back(t);
+  std::vector<double> rows = torn_rows_host(c, st64, SP, others);
+  auto local = [&](long long t, int k, int *i) {
+    long long a = t - L.pd[k].off;
+    for (int g = 0; g < 3; ++g) {
+      i[g] = g < d ? (int)(a % L.pd[k].n[g]) : 0;
+      if (g < d) a /= L.pd[k].n[g];
+    }
+  };
+  std::map<std::pair<int, int>, double> fold;              // (owner row, slot) -> sum
+  std::map<int, std::vector<std::pair<int, double>>> cross;  // owner row -> (column, value)
+  for (size_t q = 0; q < others.size(); ++q) {
+    const int tm = others[q];
+    const int ci = L.comp[tm];
+    const int to = L.rep[ci];
+    const int k = L.patch_of(to), m = L.patch_of(tm);
+    int a[3], b[3];
+    local(to, k, a);
+    local(tm, m, b);
+    const PatchDev &pm = L.pd[m];
+    for (int sl = 0; sl < S; ++sl) {
+      const double v = rows[q * SP + sl];
+      if (v == 0.0) continue;
+      int j[3] = {0, 0, 0};
+      bool inside = true;
+      for (int g = 0, r = sl; g < d; ++g, r /= S1) {
+        j[g] = b[g] + r % S1 - p;
+        inside &= j[g] >= 0 && j[g] < pm.n[g];
+      }
+      if (!inside) continue;
+      const long long tj = pm.off + j[0] + (long long)j[1] * pm.stride[1] +
+                           (long long)j[2] * pm.stride[2];
+      const int cj = L.comp[tj];
+      if (cj < 0) continue;  // Dirichlet column
+      int slot = -1;
+      for (int tk : L.copies(cj)) {
+        if (L.patch_of(tk) != k) continue;
+        int e[3];
+        local(tk, k, e);
+        int sk = 0;
+        bool in = true;
+        for (int g = 0, mul = 1; g < d; ++g, mul *= S1) {
+          in &= std::abs(e[g] - a[g]) <= p;
+          sk += (e[g] - a[g] + p) * mul;
+        }
+        if (in) slot = sk;
+      }
+      if (slot >= 0) {
+        fold[{to, slot}] += v;
+      } else {
+        if (c.color[L.patch_of(L.rep[cj])] == c.color[k])
+          fail(IGAMG_EUNSUPPORTED, "conforming coupling between unknowns of one patch colour "
+                                   "outside the stencil");
+        cross[to].push_back({(int)tj, v});
+      }
+    }
+  }
+  std::vector<int> frow, fslot;
+  std::vector<double> fval;
+  for (auto &kv : fold) {
+    frow.push_back(kv.first.first);
+    fslot.push_back(kv.first.second);
+    fval.push_back(kv.second);
+  }
+  if (!frow.empty()) {
+    int *dr = c.arena.upload(frow, c.stream), *ds = c.arena.upload(fslot, c.stream);
+    double *dv = c.arena.upload(fval, c.stream);
+    k_stencil_add(dr, ds, dv, (int)frow.size(), st64, SP, c.stream);
+  }
+  L.cf_ptr.assign(L.Ntorn + 1, 0);
+  L.cf_col.clear();
+  L.cf_val.clear();
+  for (long long t = 0; t < L.Ntorn; ++t) {
+    auto it = cross.find((int)t);
+    if (it != cross.end())
+      for (auto &cv : it->second) {
+        L.cf_col.push_back(cv.first);
+        L.cf_val.push_back(cv.second);
+      }
+    L.cf_ptr[t + 1] = (int)L.cf_col.size();
+  }
+}
+
 // Dense P^T A P over compact unknowns of the SIPG space (one torn copy each)
 // from the assembled stencil rows (volume + same-patch interface terms) and
 // the cross-patch interface terms.
@@ -1091,6 +1238,29 @@ static void build_scms(Context &c, LevelData &L) {
 // grouped by patch colour: a face of a 3D tile couples to thousands of
 // unknowns of the neighbouring patch, which one thread per row gathers in
 // parallel (and in a fixed order) far faster than a per-tile list.
+// Cross-patch couplings of torn row t (SIPG: the interface terms to other
+// patches; conforming: the couplings left by fold_conforming_rows)
+template <class F>
+static void for_cross_of(const LevelData &L, long long t, F fn) {
+  if (!L.cf_ptr.empty()) {
+    for (int e = L.cf_ptr[t]; e < L.cf_ptr[t + 1]; ++e) fn(L.cf_col[e], L.cf_val[e]);
+    return;
+  }
+  if (L.if_ptr.empty()) return;
+  for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e)
+    if (L.if_cross[e]) fn(L.if_col[e], L.if_val[e]);
+}
+
+// Conforming: the other copies of the glued unknown whose owner is torn row t
+template <class F>
+static void for_mirror_of(const LevelData &L, long long t, F fn) {
+  if (L.cf_ptr.empty()) return;
+  const int ci = L.comp[t];
+  if (ci < 0 || L.rep[ci] != t) return;
+  for (int tc : L.copies(ci))
+    if (tc != t) fn(tc);
+}
+
 static void build_gs3(Context &c, LevelData &L, bool keep64) {
   const int T = c.opt.gs_tile;
   {
@@ -1099,17 +1269,16 @@ static void build_gs3(Context &c, LevelData &L, bool keep64) {
     L.x_cptr.assign(1, 0);
     for (int colr = 0; colr < c.n_colors; ++colr) {
       for (int k = 0; k < L.K; ++k) {
-        if (c.color[k] != colr || L.if_ptr.empty()) continue;
+        if (c.color[k] != colr) continue;
         const PatchDev &pt = L.pd[k];
         const long long n = (long long)pt.n[0] * pt.n[1] * pt.n[2];
         for (long long t = pt.off; t < pt.off + n; ++t) {
           bool any = false;
-          for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e)
-            if (L.if_cross[e]) {
-              col.push_back(L.if_col[e]);
-              val.push_back(L.if_val[e]);
-              any = true;
-            }
+          for_cross_of(L, t, [&](int cc, double v) {
+            col.push_back(cc);
+            val.push_back(v);
+            any = true;
+          });
           if (any) {
             rows.push_back((int)t);
             ptr.push_back((int)col.size());
@@ -1135,6 +1304,7 @@ static void build_gs3(Context &c, LevelData &L, bool keep64) {
     }
   }
   std::vector<GsTile3> all;
+  std::vector<int> mli, mdst;
   for (int colr = 0; colr < c.n_colors; ++colr)
     for (int par = 0; par < 8; ++par) {
       std::vector<GsTile3> tiles;
@@ -1147,8 +1317,20 @@ static void build_gs3(Context &c, LevelData &L, bool keep64) {
           for (int b1 = 0; b1 < nb[1]; ++b1)
             for (int b0 = 0; b0 < nb[0]; ++b0) {
               if (((b0 & 1) | ((b1 & 1) << 1) | ((b2 & 1) << 2)) != par) continue;
-              tiles.push_back(GsTile3{pt.off, {pt.n[0], pt.n[1], pt.n[2]},
-                                      {b0 * T, b1 * T, b2 * T}});
+              GsTile3 tl{pt.off, {pt.n[0], pt.n[1], pt.n[2]}, {b0 * T, b1 * T, b2 * T},
+                         (int)mli.size(), 0};
+              // conforming: mirror copies of the tile's owned glued unknowns
+              for (int iz = b2 * T; iz < std::min(pt.n[2], (b2 + 1) * T); ++iz)
+                for (int iy = b1 * T; iy < std::min(pt.n[1], (b1 + 1) * T); ++iy)
+                  for (int ix = b0 * T; ix < std::min(pt.n[0], (b0 + 1) * T); ++ix) {
+                    const long long t = pt.off + ((long long)iz * pt.n[1] + iy) * pt.n[0] + ix;
+                    for_mirror_of(L, t, [&](int dst) {
+                      mli.push_back(((iz - b2 * T) * T + iy - b1 * T) * T + ix - b0 * T);
+                      mdst.push_back(dst);
+                    });
+                  }
+              tl.mr_n = (int)mli.size() - tl.mr_off;
+              tiles.push_back(tl);
             }
       }
       GsClass cl;
@@ -1159,6 +1341,8 @@ static void build_gs3(Context &c, LevelData &L, bool keep64) {
     }
   L.n_atiles = (int)all.size();
   L.d_atiles3 = c.arena.upload(all, c.stream);
+  L.d_mr_li = c.arena.upload(mli, c.stream);
+  L.d_mr_dst = c.arena.upload(mdst, c.stream);
 }
 
 static void build_gs(Context &c, LevelData &L, bool keep64) {
@@ -1168,7 +1352,9 @@ static void build_gs(Context &c, LevelData &L, bool keep64) {
     build_gs3(c, L, keep64);
     return;
   }
-  std::vector<int> li, col;
+  auto for_cross = [&](long long t, auto fn) { for_cross_of(L, t, fn); };
+  auto for_mirror = [&](long long t, auto fn) { for_mirror_of(L, t, fn); };
+  std::vector<int> li, col, mli, mdst;
   std::vector<double> val;
   std::vector<GsTile> all;
   for (int colr = 0; colr < c.n_colors; ++colr)
@@ -1183,20 +1369,26 @@ static void build_gs(Context &c, LevelData &L, bool keep64) {
           for (int b0 = 0; b0 < nb[0]; ++b0) {
             int pr = (b0 & 1) | ((b1 & 1) << 1);
             if (pr != par) continue;
-            GsTile tl{pt.off, pt.n[0], pt.n[1], {b0 * T, b1 * T}, (int)li.size(), 0};
-            // cross-patch couplings of the tile rows
+            GsTile tl{pt.off, pt.n[0],          pt.n[1], {b0 * T, b1 * T}, (int)li.size(), 0,
+                      (int)mli.size(), 0};
+            // cross-patch couplings of the tile rows; conforming: the mirror
+            // copies of the owned glued unknowns
             for (int iy = b1 * T; iy < std::min(pt.n[1], (b1 + 1) * T); ++iy)
               for (int ix = b0 * T; ix < std::min(pt.n[0], (b0 + 1) * T); ++ix) {
-                long long t = pt.off + (long long)iy * pt.n[0] + ix;
-                if (L.if_ptr.empty()) continue;
-                for (int e = L.if_ptr[t]; e < L.if_ptr[t + 1]; ++e)
-                  if (L.if_cross[e]) {
-                    li.push_back((iy - b1 * T) * T + (ix - b0 * T));
-                    col.push_back(L.if_col[e]);
-                    val.push_back(L.if_val[e]);
-                  }
+                const long long t = pt.off + (long long)iy * pt.n[0] + ix;
+                const int lt = (iy - b1 * T) * T + (ix - b0 * T);
+                for_cross(t, [&](int cc, double v) {
+                  li.push_back(lt);
+                  col.push_back(cc);
+                  val.push_back(v);
+                });
+                for_mirror(t, [&](int dst) {
+                  mli.push_back(lt);
+                  mdst.push_back(dst);
+                });
               }
             tl.cx_n = (int)li.size() - tl.cx_off;
+            tl.mr_n = (int)mli.size() - tl.mr_off;
             tiles.push_back(tl);
           }
       }
@@ -1210,6 +1402,8 @@ static void build_gs(Context &c, LevelData &L, bool keep64) {
   L.d_atiles = c.arena.upload(all, c.stream);
   L.d_gcx_li = c.arena.upload(li, c.stream);
   L.d_gcx_col = c.arena.upload(col, c.stream);
+  L.d_mr_li = c.arena.upload(mli, c.stream);
+  L.d_mr_dst = c.arena.upload(mdst, c.stream);
   if (c.fp32()) L.a32.gcx_val = c.arena.upload_as<float>(val, c.stream);
   if (!c.fp32() || keep64) L.a64.gcx_val = c.arena.upload_as<double>(val, c.stream);
 }
@@ -1390,8 +1584,6 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
   c.nb = c.opt.max_rhs > 0 ? c.opt.max_rhs : 1;
   if (c.opt.discretization == IGAMG_SIPG && !(sigma > 0)) fail(IGAMG_EINVAL, "penalty must be positive");
   const bool use_gs = c.opt.smoother != IGAMG_SMOOTHER_SCMS;
-  if (c.opt.discretization == IGAMG_CONFORMING && use_gs)
-    fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel ordering is defined for the SIPG space only");
   if (use_gs && c.opt.gs_tile != 2 * (degree + 1))
     fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel tiles of width 2(p+1) only");
   if (c.opt.precision != IGAMG_FP64 && c.opt.precision != IGAMG_FP32 &&
@@ -1586,8 +1778,6 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       pc.lap("misc", c.stream, true);
       build_transfer(c, L, c.lv[l - 1]);
       pc.lap("transfer");
-      if (use_gs) build_gs(c, L, keep64);
-      pc.lap("gs_tiles");
       if (use_scms) {
         if (f32)
           build_scms<float>(c, L);
@@ -1636,8 +1826,22 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       int *dr = c.arena.upload(srow, c.stream), *ds = c.arena.upload(sslot, c.stream);
       double *dv = c.arena.upload(sval, c.stream);
       k_stencil_add(dr, ds, dv, (int)srow.size(), st64, SP, c.stream);
-      if (gs_rows) k_invdiag(st64, SP, center, L.d_mask, id64, L.Ntorn, c.stream);
+      const unsigned char *gmask = L.d_mask;
+      if (gs_rows && !sipg) {
+        fold_conforming_rows(c, L, st64, SP);
+        // a sweep updates owner rows only: 1/a_ii = 0 on the other copies
+        std::vector<unsigned char> own(L.Ntorn, 0);
+        for (long long ci = 0; ci < L.N; ++ci) own[L.rep[ci]] = 1;
+        gmask = c.arena.upload(own, c.stream);
+      }
+      if (gs_rows) k_invdiag(st64, SP, center, gmask, id64, L.Ntorn, c.stream);
       pc.lap("stencil", c.stream, true);
+    }
+    // Gauss-Seidel tiles with their cross-patch couplings (conforming: those
+    // left by folding the copies' rows into the owner rows above)
+    if (gs_rows) {
+      build_gs(c, L, keep64);
+      pc.lap("gs_tiles");
     }
     if (l >= 1 && use_scms) {
       build_pieces(c, L, sipg ? st64 : nullptr, SP);

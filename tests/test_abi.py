@@ -71,7 +71,6 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
     assert _setup_code(ig, sq, el, 9) == ig.EINVAL
     assert _setup_code(ig, sq, el, 2, sigma=0.0) == ig.EINVAL              # SIPG penalty
     assert _setup_code(ig, sq, el, 2, max_rhs=-1) == ig.EINVAL
-    assert _setup_code(ig, sq, el, 2, conforming=True, smoother="gs") == ig.EUNSUPPORTED
     assert _setup_code(ig, sq, el, 2, gs_tile=10) == ig.EUNSUPPORTED      # tile != 2(p+1)
     # stored operator rows exist only with a Gauss-Seidel smoother in the SIPG space
     assert _setup_code(ig, sq, el, 2, smoother="scms", operator_apply="rows") == ig.EUNSUPPORTED
@@ -79,9 +78,8 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
                        operator_apply="rows") == ig.EUNSUPPORTED
     cube = np.array([[[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)]], dtype=np.float64)
     e4 = np.array([[4, 4, 4]], dtype=np.int32)
-    # 3D: degree 1..4; the space / smoother / operator-form rules of 2D
+    # 3D: degree 1..4; the smoother / operator-form rules of 2D
     assert _setup_code(ig, cube, e4, 5, smoother="gs") == ig.EUNSUPPORTED
-    assert _setup_code(ig, cube, e4, 2, conforming=True, smoother="gs") == ig.EUNSUPPORTED
     assert _setup_code(ig, cube, e4, 2, smoother="scms", operator_apply="rows") == ig.EUNSUPPORTED
 
 

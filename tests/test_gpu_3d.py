@@ -212,15 +212,17 @@ def test_bf16_scms(pair):
 
 
 def test_unsupported_3d_options():
+    """Stored operator rows without a Gauss-Seidel smoother and degrees above
+    4 are refused; the conforming space on non-matching faces is an invalid
+    argument (its interfaces must match)."""
     from paper_1902_01818_amd import igamg
     cfg = _case("2x2x2/p2")
-    for over in (dict(conforming=True, smoother="gs"), dict(conforming=True),
-                 dict(smoother="scms", operator_apply="rows")):
-        with pytest.raises(igamg.IgamgError) as e:
-            o = dict(smoother="gs")
-            o.update(over)
-            gpu_solver(cfg, **o)
-        assert e.value.code == igamg.EUNSUPPORTED
+    with pytest.raises(igamg.IgamgError) as e:
+        gpu_solver(cfg, smoother="scms", operator_apply="rows")
+    assert e.value.code == igamg.EUNSUPPORTED
+    with pytest.raises(igamg.IgamgError) as e:
+        gpu_solver(cfg, conforming=True, smoother="gs")
+    assert e.value.code == igamg.EINVAL
     with pytest.raises(igamg.IgamgError) as e:
         gpu_solver(dict(cfg, p=5), smoother="gs")
     assert e.value.code == igamg.EUNSUPPORTED
