@@ -185,8 +185,19 @@ struct LevelData {
   std::vector<GsClass> gs;  // classes in key order
   GsTile *d_atiles = nullptr;  // every Gauss-Seidel tile of the level (stored-row operator)
   GsTile3 *d_atiles3 = nullptr;  // the same for 3D patches
-  // 3D: cross-patch couplings as a CSR over the coupled rows, rows grouped by
-  // patch colour (x_cptr[c] .. x_cptr[c+1])
+  // 2D: row blocks (sp_rhs_bx(p) x 8) of the lane-per-right-hand-side operator
+  GsTile *d_sptiles = nullptr;
+  int n_sptiles = 0;
+  // its transposed right-hand sides: per group of 64, every patch with a halo
+  // of p zero rows and columns ([group][pad_tot + slack][64]; the halo is
+  // zeroed at setup and never written)
+  float *ut = nullptr;
+  long long *d_plines = nullptr;  // per patch line: torn offset, padded offset, length
+  int n_plines = 0;
+  long long pad_tot = 0;
+  // cross-patch couplings as a CSR over the coupled rows (3D: rows grouped by
+  // patch colour, x_cptr[c] .. x_cptr[c+1]; 2D: in torn order, for the
+  // lane-per-right-hand-side operator)
   int *d_x_rows = nullptr, *d_x_ptr = nullptr, *d_x_col = nullptr;
   int x_n = 0;
   std::vector<int> x_cptr;

@@ -83,6 +83,8 @@ struct GsTile {
   int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
   int mr_off, mr_n;  // conforming: copies in other patches of the tile's owned glued
                      // unknowns (mirror writes, in the level's flat lists)
+  long long pad_off; // lane-per-right-hand-side operator: the patch's offset in the
+                     // transposed copy with a halo of p zero rows and columns
 };
 
 // Gauss-Seidel tile of a 3D patch (2(p+1) unknowns per direction), with the

@@ -31,6 +31,11 @@ void k_l2_error(Context &c, LevelData &L, const double *ut, const long long *el_
                 const int *tab, const double *tB, const GaussRule &gq, double *part,
                 long long nel, double *out);
 long long l2_error_partials(long long nel);
+// strip width (rows of one line) of the lane-per-right-hand-side stored-row
+// operator for degree p, 0 = not available
+int sp_rhs_bx(int p);
+// float32 batches of at least this many right-hand sides take that operator
+constexpr int SP_RHS_MIN = 32;
 // Device scratch of the allocation-free entry points: NOALLOC_SCRATCH_BYTES
 // per GPU.  noalloc_scratch_init() looks up its address on the current device
 // (once per device) and returns it; noalloc_scratch(device) returns the

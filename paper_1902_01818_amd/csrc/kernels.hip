@@ -32,6 +32,7 @@
 #include <mutex>
 #include <string>
 #include <type_traits>
+#include <utility>
 
 #include "geom.h"
 #include "kernels.h"
@@ -989,11 +990,13 @@ __global__ void glue_first_kernel(int ng, const int *ptr, const int *idx, T *y, 
 // prefetched into registers; f minus the cross-patch couplings (neighbouring
 // patches carry another patch colour, so their values are constant during the
 // launch) and 1/a_ii sit in LDS as one pair per unknown.
-// A block holds RBW wavefronts, one per right-hand side of a batch, on the
-// same tile: their stencil-row loads meet in the CU's L1 instead of each
-// going to L2.  grid.x = group of RBW right-hand sides, grid.y = tile.
+// A wavefront sweeps NR right-hand sides of a batch through its tile at once:
+// every stencil row it loads serves the NR of them (their dot products and
+// scans are independent, so they also overlap each other's latency).  A
+// block holds RBW such wavefronts on the same tile, whose row loads meet in
+// the CU's L1.  grid.x = group of RBW * NR right-hand sides, grid.y = tile.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int RBW, bool BWD>
+template <typename T, int P, int RBW, int NR, bool BWD>
 __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles,
                                                        const T *__restrict__ st,
                                                        const T *__restrict__ invd,
@@ -1014,48 +1017,27 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   // longer prologue outweighs the hidden latency)
   constexpr int D0 = (sizeof(T) == 8 ? 48 : 96) / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
-  __shared__ T sUa[RBW][W * W];
-  __shared__ T2 sBDa[RBW][TT * TT];
+  __shared__ T sUa[RBW][NR][W * W];
+  __shared__ T2 sBDa[RBW][NR][TT * TT];
   __shared__ int sOff[C * 16];
   const GsTile tl = tiles[blockIdx.y];
   const int wid = threadIdx.x >> 6;
-  const int z = blockIdx.x * RBW + wid;
-  const bool zok = z < nrhs;  // waves past the batch run on column 0 and store nothing
-  f += (long long)(zok ? z : 0) * vs;
-  u += (long long)(zok ? z : 0) * vs;
-  T *sU = sUa[wid];
-  T2 *sBD = sBDa[wid];
+  const int zw = (blockIdx.x * RBW + wid) * NR;  // first right-hand side of this wave
   const int nx = tl.nx, ny = tl.ny;
   const int x0 = tl.i0[0], y0 = tl.i0[1];
   const int wx0 = x0 - P, wy0 = y0 - P;
   const long long off = tl.off;
   const int lane = threadIdx.x & 63, grp = lane >> 4, l16 = lane & 15;
   const int ax = (grp & 1) * Q1, ay = (grp >> 1) * Q1;
-  // Prologue: every global load that does not depend on another one is issued
-  // before the first wait (u window, f, 1/a_ii -- zero on Dirichlet unknowns by
-  // construction -- and the cross-coupling lists); u at the cross columns
-  // follows in a second round.
+  // Prologue, per right-hand side: every global load that does not depend on
+  // another one is issued before the first wait (u window, f, 1/a_ii -- zero
+  // on Dirichlet unknowns by construction -- and the cross-coupling lists);
+  // u at the cross columns follows in a second round.  Right-hand sides past
+  // the batch run on column 0 and store nothing.
   constexpr int NW = (W * W + 63) / 64, NT = (TT * TT + 63) / 64;
-  T wv[NW], fv[NT], dv[NT];
-#pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const int i = lane + 64 * j;
-    const int gy = wy0 + i / W, gx = wx0 + i % W;
-    const bool ok = i < W * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    wv[j] = ok ? u[off + (long long)gy * nx + gx] : (T)0;
-  }
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const int i = lane + 64 * j;
-    const int iy = y0 + i / TT, ix = x0 + i % TT;
-    const bool ok = i < TT * TT && ix < nx && iy < ny;
-    const long long t = off + (long long)iy * nx + ix;
-    fv[j] = ok ? f[t] : (T)0;
-    dv[j] = ok ? invd[t] : (T)0;
-  }
   const int ncx = tl.cx_n < 64 * 8 ? tl.cx_n : 64 * 8;
   int cl[8], cc[8];
-  T cv[8], cu[8];
+  T cv[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int e = lane + 64 * j;
@@ -1064,28 +1046,55 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
     cv[j] = ok ? cx_val[tl.cx_off + e] : (T)0;
   }
+  for (int r = 0; r < NR; ++r) {
+    const int z = zw + r < nrhs ? zw + r : 0;
+    const T *fz = f + (long long)z * vs;
+    const T *uz = u + (long long)z * vs;
+    T *sU = sUa[wid][r];
+    T2 *sBD = sBDa[wid][r];
+    T wv[NW], fv[NT], dv[NT], cu[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) cu[j] = u[cc[j]];
-#pragma unroll
-  for (int j = 0; j < NW; ++j)
-    if (lane + 64 * j < W * W) sU[lane + 64 * j] = wv[j];
-#pragma unroll
-  for (int j = 0; j < NT; ++j)
-    if (lane + 64 * j < TT * TT) {
-      T2 bd;
-      bd.x = fv[j];
-      bd.y = dv[j];
-      sBD[lane + 64 * j] = bd;
+    for (int j = 0; j < NW; ++j) {
+      const int i = lane + 64 * j;
+      const int gy = wy0 + i / W, gx = wx0 + i % W;
+      const bool ok = i < W * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      wv[j] = ok ? uz[off + (long long)gy * nx + gx] : (T)0;
     }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int i = lane + 64 * j;
+      const int iy = y0 + i / TT, ix = x0 + i % TT;
+      const bool ok = i < TT * TT && ix < nx && iy < ny;
+      const long long t = off + (long long)iy * nx + ix;
+      fv[j] = ok ? fz[t] : (T)0;
+      dv[j] = ok ? invd[t] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cu[j] = uz[cc[j]];
+#pragma unroll
+    for (int j = 0; j < NW; ++j)
+      if (lane + 64 * j < W * W) sU[lane + 64 * j] = wv[j];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      if (lane + 64 * j < TT * TT) {
+        T2 bd;
+        bd.x = fv[j];
+        bd.y = dv[j];
+        sBD[lane + 64 * j] = bd;
+      }
+    // a single wavefront: its LDS stores land in program order, so the
+    // corrections below see the pairs written above
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (cl[j] >= 0) unsafeAtomicAdd(&sBD[cl[j]].x, -cv[j] * cu[j]);
+    // tiles with more than 512 cross couplings
+    for (int e = 64 * 8 + lane; e < tl.cx_n; e += 64)
+      unsafeAtomicAdd(&sBD[cx_li[tl.cx_off + e]].x,
+                      -cx_val[tl.cx_off + e] * uz[cx_col[tl.cx_off + e]]);
+  }
   if (wid == 0)
     for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < 8; ++j)
-    if (cl[j] >= 0) unsafeAtomicAdd(&sBD[cl[j]].x, -cv[j] * cu[j]);
-  // tiles with more than 512 cross couplings (not produced by the layouts here)
-  for (int e = 64 * 8 + lane; e < tl.cx_n; e += 64)
-    unsafeAtomicAdd(&sBD[cx_li[tl.cx_off + e]].x, -cx_val[tl.cx_off + e] * u[cx_col[tl.cx_off + e]]);
   // row of this lane's group in class s: a compile-time offset from the
   // group's first row.  Rows of a ragged tile outside the patch fall on later
   // rows or on the zero padding past the level's end (never beyond it: at
@@ -1105,57 +1114,74 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     for (int c = 0; c < C; ++c) buf[s][c] = srow[16 * c];
   }
   __syncthreads();
-  // LDS addresses of this lane's slots at the group's first row; a class adds
-  // a compile-time offset
+  // LDS addresses of this lane's slots at the group's first row (first
+  // right-hand side; the others follow at compile-time offsets); a class
+  // adds a compile-time offset
   const T *ub[C];
   const int wl = (ay + P) * W + ax + P;
+  const T *sU0 = sUa[wid][0];
 #pragma unroll
-  for (int c = 0; c < C; ++c) ub[c] = sU + wl + sOff[l16 + 16 * c];
-  T *uw = sU + wl;
-  const T2 *bdl = sBD + ay * TT + ax;
+  for (int c = 0; c < C; ++c) ub[c] = sU0 + wl + sOff[l16 + 16 * c];
+  T *uw = sUa[wid][0] + wl;
+  const T2 *bdl = sBDa[wid][0] + ay * TT + ax;
 #pragma unroll
   for (int s = 0; s < NPH; ++s) {
     const int ph = BWD ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
-    const int cw = (ph / Q1) * W + ph % Q1, cl = (ph / Q1) * TT + ph % Q1;
-    T uv[C];
+    const int cw = (ph / Q1) * W + ph % Q1, cl2 = (ph / Q1) * TT + ph % Q1;
+    T uv[NR][C], uold[NR], acc[NR], ubd[NR], dinv[NR];
 #pragma unroll
-    for (int c = 0; c < C; ++c) uv[c] = ub[c][cw];
-    const T uold = uw[cw];
-    const T2 bd = bdl[cl];
-    // two independent partial sums halve the dependent multiply-add chain
-    T acc0 = 0, acc1 = 0;
+    for (int r = 0; r < NR; ++r) {
 #pragma unroll
-    for (int c = 0; c < C; c += 2) acc0 += buf[s % D][c] * uv[c];
+      for (int c = 0; c < C; ++c) uv[r][c] = ub[c][r * W * W + cw];
+      uold[r] = uw[r * W * W + cw];
+      const T2 bd = bdl[r * TT * TT + cl2];
+      // u + (b - a.u) d: every LDS value of the class is consumed before the
+      // scans, so the reads go out as one batch and none is sunk past them
+      ubd[r] = fma(bd.x, bd.y, uold[r]);
+      dinv[r] = bd.y;
+    }
 #pragma unroll
-    for (int c = 1; c < C; c += 2) acc1 += buf[s % D][c] * uv[c];
-    // u + (b - a.u) d: every LDS value of the class is consumed before the
-    // scan, so the reads go out as one batch and none is sunk past the scan
-    T ubd = fma(bd.x, bd.y, uold);
-    T acc = acc0 + acc1;
-    T dinv = bd.y;
-    asm volatile("" : "+v"(acc), "+v"(ubd), "+v"(dinv));
+    for (int r = 0; r < NR; ++r) {
+      // two independent partial sums halve the dependent multiply-add chain
+      T acc0 = 0, acc1 = 0;
+#pragma unroll
+      for (int c = 0; c < C; c += 2) acc0 += buf[s % D][c] * uv[r][c];
+#pragma unroll
+      for (int c = 1; c < C; c += 2) acc1 += buf[s % D][c] * uv[r][c];
+      acc[r] = acc0 + acc1;
+      asm volatile("" : "+v"(acc[r]), "+v"(ubd[r]), "+v"(dinv[r]));
+    }
     if (s + D < NPH) {
       const T *srow = row_ptr(s + D);
 #pragma unroll
       for (int c = 0; c < C; ++c) buf[s % D][c] = srow[16 * c];
     }
-    acc = row16_scan(acc);
-    if (l16 == 15 && ix < nx && iy < ny) uw[cw] = fma(-acc, dinv, ubd);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = row16_scan(acc[r]);
+    if (l16 == 15 && ix < nx && iy < ny) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) uw[r * W * W + cw] = fma(-acc[r], dinv[r], ubd[r]);
+    }
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
   }
   __syncthreads();
-  if (!zok) return;
-  for (int i = lane; i < TT * TT; i += 64) {
-    int iy = y0 + i / TT, ix = x0 + i % TT;
-    if (ix < nx && iy < ny) u[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
-  }
-  // conforming: the tile's owned glued unknowns into their copies in other
-  // patches (those patches carry other colours: nothing else writes there)
-  for (int e = lane; e < tl.mr_n; e += 64) {
-    const int lt = mr_li[tl.mr_off + e];
-    u[mr_dst[tl.mr_off + e]] = sU[(lt / TT + P) * W + lt % TT + P];
+  for (int r = 0; r < NR; ++r) {
+    const int z = zw + r;
+    if (z >= nrhs) break;
+    T *uz = u + (long long)z * vs;
+    const T *sU = sUa[wid][r];
+    for (int i = lane; i < TT * TT; i += 64) {
+      int iy = y0 + i / TT, ix = x0 + i % TT;
+      if (ix < nx && iy < ny) uz[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
+    }
+    // conforming: the tile's owned glued unknowns into their copies in other
+    // patches (those patches carry other colours: nothing else writes there)
+    for (int e = lane; e < tl.mr_n; e += 64) {
+      const int lt = mr_li[tl.mr_off + e];
+      uz[mr_dst[tl.mr_off + e]] = sU[(lt / TT + P) * W + lt % TT + P];
+    }
   }
 }
 
@@ -1296,6 +1322,202 @@ __global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntil
     T v = alpha * sX[z][li];
     if (f) v += beta * (fw ? fw[t] : (T)1) * f[zo + t];
     r[zo + t] = mask[t] ? v : (T)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Operator by the stored rows for a batch of float32 right-hand sides, one
+// right-hand side per lane (64 per wavefront):
+//   r = mask (beta fw.*f + alpha S u)
+// (S = the same-patch rows; the cross-patch couplings are added by a second
+// kernel over the coupled rows).  u is first transposed to uT[t][64] so that
+// the 64 values of a row are one contiguous line.  A wavefront takes BX
+// consecutive rows of one patch line and walks the 2p+1 stencil lines b: it
+// loads the BX + 2p values of line b once and applies them to all BX rows
+// (each serves up to 2p+1 products); the coefficients of a (row, b) pair are
+// the same for every lane: wave-uniform loads into scalar registers, used
+// directly as the scalar operand of the products.  No LDS, no cross-lane
+// reduction and no atomics: each lane owns its sums, summed in a fixed order
+// (even and odd stencil lines apart, then added).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void transpose64_kernel(const float *__restrict__ u, int nrhs,
+                                                          long long vs,
+                                                          const long long *__restrict__ lines,
+                                                          long long ptot,
+                                                          float *__restrict__ ut) {
+  // one patch line per block: its rows (torn offset lines[3 l], lines[3 l + 2]
+  // of them) go to the padded copy at lines[3 l + 1], 64 rows x 64 right-hand
+  // sides at a time through LDS (odd pitch), right-hand side group g at
+  // g * ptot rows
+  __shared__ float tile[64][65];
+  const long long tl0 = lines[3 * blockIdx.x], pl0 = lines[3 * blockIdx.x + 1];
+  const int nx = (int)lines[3 * blockIdx.x + 2];
+  const int z0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int x0 = 0; x0 < nx; x0 += 64) {
+    for (int zz = ty; zz < 64; zz += 4)
+      tile[zz][tx] = (z0 + zz < nrhs && x0 + tx < nx)
+                         ? u[(long long)(z0 + zz) * vs + tl0 + x0 + tx]
+                         : 0.0f;
+    __syncthreads();
+    for (int xx = ty; xx < 64 && x0 + xx < nx; xx += 4)
+      ut[((long long)blockIdx.y * ptot + pl0 + x0 + xx) * 64 + tx] = tile[tx][xx];
+    __syncthreads();
+  }
+}
+
+// acc += c[lane a of this lane's 16-lane row] * w: the coefficient comes from
+// lane a of each 16-lane row (DPP row_newbcast), so a register holding the
+// 13 coefficients of a stencil line in lanes 0..12 of every row serves all 64
+// lanes.  The leading s_nop keeps two wait states between any VALU write of
+// the coefficient register and its DPP read (it is written by loads only).
+template <int A>
+__device__ __forceinline__ void fmac_bcast(float &acc, float c, float w) {
+  if constexpr (A == 0)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(c), "v"(w));
+  else
+    asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(c), "v"(w), "n"(A));
+}
+// one stencil offset a for all rows q (independent sums back to back), then
+// the next offset; even and odd offsets into separate partial sums
+template <int A, int... Qs>
+__device__ __forceinline__ void fmac_offset(float *acc, const float *cf, const float *win,
+                                            std::integer_sequence<int, Qs...>) {
+  constexpr int BXN = sizeof...(Qs);
+  (fmac_bcast<A>(acc[(A & 1) * BXN + Qs], cf[Qs], win[Qs + A]), ...);
+}
+template <int BX, int... As>
+__device__ __forceinline__ void fmac_rows_by_offset(float *acc, const float *cf,
+                                                    const float *win,
+                                                    std::integer_sequence<int, As...>) {
+  (fmac_offset<As>(acc, cf, win, std::make_integer_sequence<int, BX>{}), ...);
+}
+template <int BX, int S1>
+__device__ __forceinline__ void fmac_rows(float *acc, const float *cf, const float *win) {
+  fmac_rows_by_offset<BX>(acc, cf, win, std::make_integer_sequence<int, S1>{});
+}
+
+template <int P, int BX>
+__global__ __launch_bounds__(256) void sp2d_rhs_kernel(const GsTile *tiles, int ntiles, int nrhs,
+                                                       const float *__restrict__ st,
+                                                       const unsigned char *__restrict__ mask,
+                                                       const float *__restrict__ ut,
+                                                       long long ptot,
+                                                       const float *__restrict__ f,
+                                                       const float *__restrict__ fw, float beta,
+                                                       float alpha, float *__restrict__ r,
+                                                       long long vs) {
+  constexpr int S1 = 2 * P + 1, S = S1 * S1, SP = (S + 15) / 16 * 16;
+  constexpr int WX = BX + 2 * P;
+  const int w = threadIdx.x >> 6;
+  // XCD-aware order: block ids go round-robin over the 8 XCDs, so XCD x
+  // takes the x-th contiguous eighth of the strip list (its window lines
+  // stay in that XCD's L2 from one line group to the next); the grid is
+  // padded to a multiple of 8 blocks
+  const int per = gridDim.x >> 3;
+  const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int item = lb * 4 + w;
+  if (item >= ntiles) return;
+  const GsTile tl = tiles[item];
+  const int lane = threadIdx.x & 63, l16 = lane & 15;
+  const int zg = blockIdx.y;
+  const int z = zg * 64 + lane;
+  const int nx = tl.nx;
+  const int x0 = tl.i0[0], y = tl.i0[1];
+  const long long off = tl.off;
+  // first row of the strip; rows of a ragged strip past the patch read the
+  // rows that follow (the next line, or the zero padding past the level's
+  // end: at most BX - 1 rows) and are not stored
+  const float *row0 = st + (off + (long long)y * nx + x0) * SP;
+  const int nq = nx - x0 < BX ? nx - x0 : BX;
+  // Window of stencil line b: BX + 2p consecutive values of the padded copy
+  // (zeros outside the patch), no conditions.  Beyond the padded line only
+  // rows past the patch read (they are not stored).
+  const int pw = nx + 2 * P;
+  const float *ug = ut + ((long long)zg * ptot + tl.pad_off + (long long)y * pw + x0) * 64 + lane;
+  auto load_line = [&](int b, float *win) {
+    const float *lb = ug + (long long)b * pw * 64;
+#pragma unroll
+    for (int i = 0; i < WX; ++i) win[i] = lb[i * 64];
+  };
+  // the strip's BX rows of coefficients (contiguous) into this wavefront's
+  // LDS slice, all loads in flight at once
+  __shared__ float sC[4][BX * SP];
+  float *sc = sC[w];
+  {
+    constexpr int N4 = BX * SP / 4, PER = (N4 + 63) / 64;
+    const float4 *src = reinterpret_cast<const float4 *>(row0);
+    float4 v[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = lane + 64 * m;
+      v[m] = e < N4 ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = lane + 64 * m;
+      if (e < N4) reinterpret_cast<float4 *>(sc)[e] = v[m];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // coefficients of stencil line b of the BX rows: lanes 0..12 of every
+  // 16-lane row hold the line's S1 values, one register per row
+  const int ka = l16 < S1 ? l16 : 0;
+  auto load_coef = [&](int b, float *cf) {
+    const float *cb = sc + b * S1 + ka;
+#pragma unroll
+    for (int q = 0; q < BX; ++q) cf[q] = cb[q * SP];
+  };
+  // Summation order (float32): each stencil line's products go into two
+  // partial sums (even and odd offsets), added into the row's line total;
+  // even and odd lines into two totals, added at the end -- chains of at
+  // most 7 additions, close to the tree of the 16-lane row kernels (a single
+  // running sum of all (2p+1)^2 products loses enough accuracy to cost the
+  // float64 iterative refinement an extra step)
+  float acc[2][BX];
+#pragma unroll
+  for (int q = 0; q < BX; ++q) acc[0][q] = acc[1][q] = 0.0f;
+  auto line = [&](float *tot, const float *cf, const float *win) {
+    float ls[2 * BX];
+#pragma unroll
+    for (int q = 0; q < 2 * BX; ++q) ls[q] = 0.0f;
+    fmac_rows<BX, S1>(ls, cf, win);
+#pragma unroll
+    for (int q = 0; q < BX; ++q) tot[q] += ls[q] + ls[BX + q];
+  };
+  float wa[WX], wb[WX], ca[BX], cb2[BX];
+  load_line(0, wa);
+  load_coef(0, ca);
+  // stencil lines in pairs: even lines from (wa, ca), odd from (wb, cb2);
+  // each pair's successor is loaded before its products
+#pragma unroll 1
+  for (int b = 0; b < S1; b += 2) {
+    if (b + 1 < S1) {
+      load_line(b + 1, wb);
+      load_coef(b + 1, cb2);
+    }
+    line(acc[0], ca, wa);
+    if (b + 1 < S1) {
+      if (b + 2 < S1) {
+        load_line(b + 2, wa);
+        load_coef(b + 2, ca);
+      }
+      line(acc[1], cb2, wb);
+    }
+  }
+  if (z >= nrhs) return;
+  const long long zo = (long long)z * vs;
+#pragma unroll
+  for (int q = 0; q < BX; ++q) {
+    if (q >= nq) break;
+    const long long t = off + (long long)y * nx + x0 + q;
+    float v = alpha * (acc[0][q] + acc[1][q]);
+    if (f) v += beta * (fw ? fw[t] : 1.0f) * f[zo + t];
+    r[zo + t] = mask[t] ? v : 0.0f;
   }
 }
 
@@ -2773,30 +2995,37 @@ void k_glue_sum(LevelData &L, T *y, int nrhs, hipStream_t s) {
 template void k_glue_sum<double>(LevelData &, double *, int, hipStream_t);
 template void k_glue_sum<float>(LevelData &, float *, int, hipStream_t);
 
-template <typename T, int P, int RBW, bool BWD>
+template <typename T, int P, int RBW, int NR, bool BWD>
 static void launch_gs2d_dir(Context &c, LevelData &L, const GsClass &cl, int nrhs) {
   LevelArrays<T> &A = L.arr<T>();
-  dim3 grid((nrhs + RBW - 1) / RBW, cl.count);
-  gs2d_wave_kernel<T, P, RBW, BWD><<<grid, 64 * RBW, 0, c.stream>>>(
+  dim3 grid((nrhs + RBW * NR - 1) / (RBW * NR), cl.count);
+  gs2d_wave_kernel<T, P, RBW, NR, BWD><<<grid, 64 * RBW, 0, c.stream>>>(
       cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, L.d_mr_li, L.d_mr_dst,
       A.f, A.u, L.Ntorn, nrhs);
 }
 
 // the sweep direction is a template parameter: the unrolled class steps then
 // address their rows with compile-time offsets
+#ifndef GS2D_NR
+#define GS2D_NR 2
+#endif
+#ifndef GS2D_RBW
+#define GS2D_RBW 2
+#endif
 template <typename T, int P>
 static void launch_gs2d(Context &c, LevelData &L, const GsClass &cl, bool backward, int nrhs) {
-  // batches: four right-hand sides of a tile per block
+  // one right-hand side: one wavefront per tile; batches: GS2D_NR right-hand
+  // sides per wavefront, GS2D_RBW wavefronts of a tile per block
   if (nrhs == 1) {
     if (backward)
-      launch_gs2d_dir<T, P, 1, true>(c, L, cl, nrhs);
+      launch_gs2d_dir<T, P, 1, 1, true>(c, L, cl, nrhs);
     else
-      launch_gs2d_dir<T, P, 1, false>(c, L, cl, nrhs);
+      launch_gs2d_dir<T, P, 1, 1, false>(c, L, cl, nrhs);
   } else {
     if (backward)
-      launch_gs2d_dir<T, P, 4, true>(c, L, cl, nrhs);
+      launch_gs2d_dir<T, P, GS2D_RBW, GS2D_NR, true>(c, L, cl, nrhs);
     else
-      launch_gs2d_dir<T, P, 4, false>(c, L, cl, nrhs);
+      launch_gs2d_dir<T, P, GS2D_RBW, GS2D_NR, false>(c, L, cl, nrhs);
   }
 }
 
@@ -2885,15 +3114,63 @@ static void launch_sp2d(Context &c, LevelData &L, const LevelArrays<T> &A, const
       u, f, fw, beta, alpha, r, L.Ntorn);
 }
 
-// one right-hand side per block, or groups of 4 (float64) / 8 (float32)
+// the strip width of the lane-per-right-hand-side operator: a Gauss-Seidel
+// tile width 2(p+1); 0 = none (a stencil line of 2p+1 > 16 coefficients does
+// not fit the 16-lane broadcast)
+template <int P>
+constexpr int sp_rhs_bx_of() {
+  return 2 * P + 1 <= 16 ? 2 * (P + 1) : 0;
+}
+
+template <int P>
+static void launch_sp2d_rhs(Context &c, LevelData &L, const LevelArrays<float> &A, const float *u,
+                            const float *f, const float *fw, float beta, float alpha, float *r,
+                            int nrhs) {
+  constexpr int BX = sp_rhs_bx_of<P>();
+  if constexpr (BX == 0) {
+    fail(IGAMG_EUNSUPPORTED, "no lane-per-right-hand-side operator for this degree");
+  } else {
+  const int ng = (nrhs + 63) / 64;
+  transpose64_kernel<<<dim3((unsigned)L.n_plines, ng), 256, 0, c.stream>>>(
+      u, nrhs, L.Ntorn, L.d_plines, L.pad_tot, L.ut);
+  dim3 grid((unsigned)(((L.n_sptiles + 3) / 4 + 7) / 8 * 8), ng);
+  sp2d_rhs_kernel<P, BX><<<grid, 256, 0, c.stream>>>(L.d_sptiles, L.n_sptiles, nrhs, A.stencil,
+                                                    L.d_mask, L.ut, L.pad_tot, f, fw, beta, alpha,
+                                                    r, L.Ntorn);
+  launch_cross3d<float>(c, L, A.x_val, 0, L.x_n, u, r, true, alpha, nrhs);
+  }
+}
+
+// one right-hand side per block, or groups of 4 (float64) / 8 (float32);
+// float32 batches of 32 and more: one right-hand side per lane
 template <typename T, int P>
 static void launch_sp2d_rb(Context &c, LevelData &L, const LevelArrays<T> &A, const T *u,
                            const T *f, const T *fw, T beta, T alpha, T *r, int nrhs) {
   constexpr int RBB = sizeof(T) == 8 ? 4 : 8;
+  if constexpr (sizeof(T) == 4) {
+    if (sp_rhs_bx_of<P>() > 0 && nrhs >= SP_RHS_MIN && L.d_sptiles && L.ut) {
+      launch_sp2d_rhs<P>(c, L, A, u, f, fw, beta, alpha, r, nrhs);
+      return;
+    }
+  }
   if (nrhs == 1)
     launch_sp2d<T, P, 1>(c, L, A, u, f, fw, beta, alpha, r, nrhs);
   else
     launch_sp2d<T, P, RBB>(c, L, A, u, f, fw, beta, alpha, r, nrhs);
+}
+
+int sp_rhs_bx(int p) {
+  switch (p) {
+    case 1: return sp_rhs_bx_of<1>();
+    case 2: return sp_rhs_bx_of<2>();
+    case 3: return sp_rhs_bx_of<3>();
+    case 4: return sp_rhs_bx_of<4>();
+    case 5: return sp_rhs_bx_of<5>();
+    case 6: return sp_rhs_bx_of<6>();
+    case 7: return sp_rhs_bx_of<7>();
+    case 8: return sp_rhs_bx_of<8>();
+    default: return 0;
+  }
 }
 
 template <typename T, int P>

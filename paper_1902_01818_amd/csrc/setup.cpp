@@ -1405,6 +1405,58 @@ static void build_gs(Context &c, LevelData &L, bool keep64) {
   L.d_mr_li = c.arena.upload(mli, c.stream);
   L.d_mr_dst = c.arena.upload(mdst, c.stream);
   if (c.fp32()) L.a32.gcx_val = c.arena.upload_as<float>(val, c.stream);
+  // float32 batches: row blocks of the lane-per-right-hand-side operator and
+  // the cross-patch couplings as a CSR over the coupled rows (torn order)
+  const int bx = sp_rhs_bx(c.p);
+  if (c.fp32() && bx > 0 && L.st_apply && c.nb >= SP_RHS_MIN) {
+    // strips of bx rows on one line; four consecutive lines of one strip
+    // column per block (their stencil-line windows overlap in the caches)
+    std::vector<GsTile> sp;
+    std::vector<long long> plines;
+    long long ptot = 0;
+    for (int k = 0; k < L.K; ++k) {
+      const PatchDev &pt = L.pd[k];
+      const int pw = pt.n[0] + 2 * c.p;
+      for (int y = 0; y < pt.n[1]; ++y) {
+        plines.push_back(pt.off + (long long)y * pt.n[0]);
+        plines.push_back(ptot + (long long)(y + c.p) * pw + c.p);
+        plines.push_back(pt.n[0]);
+      }
+      for (int y0 = 0; y0 < pt.n[1]; y0 += 4)
+        for (int x = 0; x < pt.n[0]; x += bx)
+          for (int y = y0; y < std::min(pt.n[1], y0 + 4); ++y)
+            sp.push_back(GsTile{pt.off, pt.n[0], pt.n[1], {x, y}, 0, 0, 0, 0, ptot});
+      ptot += (long long)(pt.n[0] + 2 * c.p) * (pt.n[1] + 2 * c.p);
+    }
+    L.pad_tot = ptot;
+    L.n_plines = (int)(plines.size() / 3);
+    L.d_plines = c.arena.upload(plines, c.stream);
+    // groups of 64 right-hand sides; slack of one strip past the end
+    const size_t nut = (size_t)((c.nb + 63) / 64) * (size_t)(ptot + bx) * 64;
+    L.ut = c.arena.alloc<float>(nut);
+    k_fill<float>(L.ut, 0.0f, (long long)nut, c.stream);
+    L.n_sptiles = (int)sp.size();
+    L.d_sptiles = c.arena.upload(sp, c.stream);
+    std::vector<int> xr, xp{0}, xc;
+    std::vector<double> xv;
+    for (long long t = 0; t < L.Ntorn; ++t) {
+      bool any = false;
+      for_cross_of(L, t, [&](int cc, double v) {
+        xc.push_back(cc);
+        xv.push_back(v);
+        any = true;
+      });
+      if (any) {
+        xr.push_back((int)t);
+        xp.push_back((int)xc.size());
+      }
+    }
+    L.x_n = (int)xr.size();
+    L.d_x_rows = c.arena.upload(xr, c.stream);
+    L.d_x_ptr = c.arena.upload(xp, c.stream);
+    L.d_x_col = c.arena.upload(xc, c.stream);
+    L.a32.x_val = c.arena.upload_as<float>(xv, c.stream);
+  }
   if (!c.fp32() || keep64) L.a64.gcx_val = c.arena.upload_as<double>(val, c.stream);
 }
 
