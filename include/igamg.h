@@ -144,15 +144,20 @@ typedef struct igamg_ctx igamg_ctx;
 void igamg_default_options(igamg_options *o);
 
 /* Host only, no GPU work: device bytes igamg_setup will allocate for this
- * problem (used for admission by memory footprint).  Errors: IGAMG_EINVAL. */
-int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o,
+ * problem with a batch capacity of nrhs right-hand sides (nrhs >= 1; 0 =
+ * o->max_rhs), used for admission by memory footprint.  An estimate from the
+ * sizes of every array setup allocates, with a 15 % margin.
+ * Errors: IGAMG_EINVAL. */
+int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o, int nrhs,
                     size_t *bytes);
 
 /* Build the grid hierarchy (uniform dyadic refinement, Section 2), the
  * operators of every level (SIPG: penalty sigma p^2/h with the finest h,
  * eq. a:galerkin), transfer operators (canonical embedding, Section 4),
- * smoother data (Section 5: SCMS factors, interface piece factorizations;
- * Section 4: Gauss-Seidel colouring) and the coarse Cholesky factorization.
+ * smoother data (Section 5: SCMS factors, dense inverses of the interface
+ * pieces P^T A P; Section 4: Gauss-Seidel colouring and stencil rows) and
+ * the dense inverse of the coarsest matrix (blocked Gauss-Jordan in
+ * float64; the paper fixes only a direct solve there).
  * degree >= 1; penalty_sigma > 0 (SIPG only).  Synchronizes `stream`.
  * dim 3 takes degree 1..4 (higher degrees return IGAMG_EUNSUPPORTED).
  * Errors: IGAMG_EINVAL (dim, degree, non-positive Jacobian, conforming
@@ -169,7 +174,9 @@ int igamg_num_dofs(const igamg_ctx *ctx, int64_t *n);
 int igamg_num_levels(const igamg_ctx *ctx, int *levels);
 
 /* y = A_L x (eq. linear:system / linear:system:0), float64; x, y device [nrhs][N].
- * The volume part is evaluated matrix-free by sum factorization. */
+ * With IGAMG_APPLY_AUTO the finest level's stored rows are applied where the
+ * level keeps them (SIPG with a Gauss-Seidel smoother), otherwise the volume
+ * part is evaluated matrix-free by sum factorization (see IGAMG_APPLY_*). */
 int igamg_apply(igamg_ctx *ctx, const double *x, double *y, int nrhs, void *stream);
 
 /* One multigrid cycle u <- MG(L, f, u) (Algorithm 1 or 2 per options), u
@@ -192,17 +199,23 @@ int igamg_vcycle(igamg_ctx *ctx, const double *f, double *u, int nrhs, void *str
 int igamg_solve(igamg_ctx *ctx, const double *rhs, double *u, int nrhs, double tol,
                 int maxit, int use_initial_guess, igamg_solve_info *info, void *stream);
 
-/* f_i = (f, phi_i) for f = d pi^2 prod sin(pi x) (exact solution prod sin(pi x),
- * Section 2), Gauss quadrature with p+1 points; f device [N]. */
-int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream);
+/* Manufactured solutions (Section 2, the experiments' choice):
+ * IGAMG_MANUFACTURED_SINE: u = prod_d sin(pi x_d), f = -Delta u = d pi^2 u. */
+#define IGAMG_MANUFACTURED_SINE 0
 
-/* Discretization error ||u_h - prod sin(pi x)||_{L2(Omega)} of the finest-level
- * coefficient vector u (device [N], compact ordering, caller-owned) against
- * the exact solution of igamg_load_manufactured (Section 2, model problem),
- * Gauss quadrature with p+3 points per element and direction, summed in a
- * fixed order.  Writes *err_host (host); synchronizes `stream`; allocates and
- * frees its own scratch.  Errors: IGAMG_EINVAL (null argument), IGAMG_EHIP. */
-int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stream);
+/* f_i = (f, phi_i) for the manufactured solution `which`, Gauss quadrature
+ * with p+1 points; f device [N].  Errors: IGAMG_EINVAL (null argument,
+ * unknown `which`). */
+int igamg_load_manufactured(igamg_ctx *ctx, int which, double *f, void *stream);
+
+/* Discretization error ||u_h - u||_{L2(Omega)} of the finest-level
+ * coefficient vector u_h (device [N], compact ordering, caller-owned) against
+ * the manufactured solution `which` (Section 2, model problem), Gauss
+ * quadrature with p+3 points per element and direction, summed in a fixed
+ * order.  Writes *err_host (host); synchronizes `stream`; allocates and frees
+ * its own scratch.  Errors: IGAMG_EINVAL (null argument, unknown `which`),
+ * IGAMG_EHIP. */
+int igamg_l2_error(igamg_ctx *ctx, const double *u, int which, double *err_host, void *stream);
 
 /* igamg_l2_error without any device allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
@@ -218,7 +231,8 @@ int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stre
  * IGAMG_EUNSUPPORTED (the problem's tables and partial sums need more than
  * 16 MiB: about 500 million elements, or very large element counts per patch
  * at high degree), IGAMG_EHIP. */
-int igamg_l2_error_noalloc(igamg_ctx *ctx, const double *u, double *err_host, void *stream);
+int igamg_l2_error_noalloc(igamg_ctx *ctx, const double *u, int which, double *err_host,
+                           void *stream);
 
 /* Device bytes owned by the context. */
 int igamg_memory(const igamg_ctx *ctx, size_t *bytes);

@@ -141,11 +141,13 @@ void igamg_default_options(igamg_options *o) {
   o->operator_apply = IGAMG_APPLY_AUTO;
 }
 
-int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o,
+int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o, int nrhs,
                     size_t *bytes) {
   return guarded([&] {
-    if (!bytes || !o) igamg::fail(IGAMG_EINVAL, "null argument");
-    *bytes = igamg::estimate_footprint(patches, degree, o);
+    if (!bytes || !o || nrhs < 0) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    igamg_options oo = *o;
+    if (nrhs > 0) oo.max_rhs = nrhs;
+    *bytes = igamg::estimate_footprint(patches, degree, &oo);
     return IGAMG_OK;
   });
 }
@@ -243,9 +245,10 @@ int igamg_solve(igamg_ctx *ctx, const double *rhs, double *u, int nrhs, double t
   });
 }
 
-int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream) {
+int igamg_load_manufactured(igamg_ctx *ctx, int which, double *f, void *stream) {
   return guarded([&] {
-    if (!ctx || !f) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    if (!ctx || !f || which != IGAMG_MANUFACTURED_SINE)
+      igamg::fail(IGAMG_EINVAL, "invalid argument");
     igamg::Context &c = ctx->c;
     c.stream = (hipStream_t)stream;
     igamg::LevelData &L = c.lv.back();
@@ -257,9 +260,10 @@ int igamg_load_manufactured(igamg_ctx *ctx, double *f, void *stream) {
   });
 }
 
-int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stream) {
+int igamg_l2_error(igamg_ctx *ctx, const double *u, int which, double *err_host, void *stream) {
   return guarded([&] {
-    if (!ctx || !u || !err_host) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    if (!ctx || !u || !err_host || which != IGAMG_MANUFACTURED_SINE)
+      igamg::fail(IGAMG_EINVAL, "invalid argument");
     igamg::Context &c = ctx->c;
     c.stream = (hipStream_t)stream;
     L2Tables t(c);
@@ -273,9 +277,11 @@ int igamg_l2_error(igamg_ctx *ctx, const double *u, double *err_host, void *stre
   });
 }
 
-int igamg_l2_error_noalloc(igamg_ctx *ctx, const double *u, double *err_host, void *stream) {
+int igamg_l2_error_noalloc(igamg_ctx *ctx, const double *u, int which, double *err_host,
+                           void *stream) {
   return guarded([&] {
-    if (!ctx || !u || !err_host) igamg::fail(IGAMG_EINVAL, "invalid argument");
+    if (!ctx || !u || !err_host || which != IGAMG_MANUFACTURED_SINE)
+      igamg::fail(IGAMG_EINVAL, "invalid argument");
     igamg::Context &c = ctx->c;
     c.stream = (hipStream_t)stream;
     int dev = 0;

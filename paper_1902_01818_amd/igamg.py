@@ -23,6 +23,7 @@ SIPG, CONFORMING = 0, 1
 SMOOTHERS = {"hybrid": 0, "scms": 1, "gs": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 OUTERS = {"pcg": 0, "mg": 1, "fcg": 2, "ir": 3}
+MANUFACTURED_SINE = 0
 APPLIES = {"auto": 0, "sumfact": 1, "rows": 2}
 
 
@@ -51,7 +52,7 @@ class SolveInfo(ctypes.Structure):
 _vp = ctypes.c_void_p
 _lib.igamg_default_options.argtypes = [ctypes.POINTER(Options)]
 _lib.igamg_footprint.argtypes = [ctypes.POINTER(Patches), ctypes.c_int, ctypes.POINTER(Options),
-                                 ctypes.POINTER(ctypes.c_size_t)]
+                                 ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
 _lib.igamg_setup.argtypes = [ctypes.POINTER(Patches), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(Options), _vp, ctypes.POINTER(_vp)]
 _lib.igamg_num_dofs.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
@@ -60,9 +61,10 @@ _lib.igamg_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp]
 _lib.igamg_vcycle.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp]
 _lib.igamg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, ctypes.POINTER(SolveInfo), _vp]
-_lib.igamg_load_manufactured.argtypes = [_vp, _vp, _vp]
-_lib.igamg_l2_error.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
-_lib.igamg_l2_error_noalloc.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
+_lib.igamg_load_manufactured.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+_lib.igamg_l2_error.argtypes = [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp]
+_lib.igamg_l2_error_noalloc.argtypes = [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        _vp]
 _lib.igamg_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
 _lib.igamg_kernel_stats.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
@@ -158,11 +160,13 @@ def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1,
     return o
 
 
-def footprint(corners, elems, degree, **opts):
+def footprint(corners, elems, degree, nrhs=0, **opts):
+    """Device bytes of a setup for a batch of nrhs right-hand sides (0 = the
+    options' max_rhs)."""
     P, keep = _patches(corners, elems)
     o = make_options(**opts)
     b = ctypes.c_size_t()
-    _check(_lib.igamg_footprint(ctypes.byref(P), degree, ctypes.byref(o), ctypes.byref(b)),
+    _check(_lib.igamg_footprint(ctypes.byref(P), degree, ctypes.byref(o), nrhs, ctypes.byref(b)),
            "igamg_footprint")
     return int(b.value)
 
@@ -291,25 +295,25 @@ class Solver:
             out.append(d)
         return u, out
 
-    def load_manufactured(self, stream=None):
+    def load_manufactured(self, which=MANUFACTURED_SINE, stream=None):
         f = torch.empty(self.n_dofs, dtype=torch.float64, device="cuda")
-        _check(_lib.igamg_load_manufactured(self._h, _dptr(f, self.n_dofs), _stream(stream)),
+        _check(_lib.igamg_load_manufactured(self._h, which, _dptr(f, self.n_dofs), _stream(stream)),
                "igamg_load_manufactured")
         return f
 
-    def l2_error(self, u, stream=None):
+    def l2_error(self, u, which=MANUFACTURED_SINE, stream=None):
         """||u_h - prod sin(pi x)||_{L2} of a finest-level coefficient vector."""
         e = ctypes.c_double()
-        _check(_lib.igamg_l2_error(self._h, _dptr(u, self.n_dofs), ctypes.byref(e), _stream(stream)),
-               "igamg_l2_error")
+        _check(_lib.igamg_l2_error(self._h, _dptr(u, self.n_dofs), which, ctypes.byref(e),
+                                   _stream(stream)), "igamg_l2_error")
         return e.value
 
-    def l2_error_noalloc(self, u, stream=None):
+    def l2_error_noalloc(self, u, which=MANUFACTURED_SINE, stream=None):
         """As l2_error, through the entry point that allocates no device
         memory (its scratch is a static device array shared by every call on
         the GPU)."""
         e = ctypes.c_double()
-        _check(_lib.igamg_l2_error_noalloc(self._h, _dptr(u, self.n_dofs), ctypes.byref(e),
+        _check(_lib.igamg_l2_error_noalloc(self._h, _dptr(u, self.n_dofs), which, ctypes.byref(e),
                                            _stream(stream)), "igamg_l2_error_noalloc")
         return e.value
 

@@ -132,6 +132,22 @@ def test_binding_constants_match_header(ig):
                          "fcg": defs["IGAMG_OUTER_FCG"], "ir": defs["IGAMG_OUTER_IR"]}
     assert ig.APPLIES == {"auto": defs["IGAMG_APPLY_AUTO"], "sumfact": defs["IGAMG_APPLY_SUMFACT"],
                           "rows": defs["IGAMG_APPLY_ROWS"]}
+    assert ig.MANUFACTURED_SINE == defs["IGAMG_MANUFACTURED_SINE"]
+
+
+def test_entry_point_arity_matches_header(ig):
+    """Every binding argtypes list has as many entries as the header's
+    prototype has parameters (a stale binding would pass garbage)."""
+    import re
+    text = open(os.path.join(ROOT, "include", "igamg.h")).read()
+    protos = {m.group(1): m.group(2) for m in
+              re.finditer(r"\b(igamg_\w+)\(([^;{]*?)\);", text, flags=re.S)}
+    for name in ig.EXPORTED:
+        args = protos[name].strip()
+        n = 0 if args in ("", "void") else args.count(",") + 1
+        fn = getattr(ig._lib, name)
+        if fn.argtypes is not None:
+            assert len(fn.argtypes) == n, (name, len(fn.argtypes), n)
 
 
 def test_options_struct_layout_matches_header(ig):
