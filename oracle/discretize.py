@@ -153,10 +153,12 @@ class Level:
     def __init__(self, topo, elems, p, conforming, eta=None):
         self.topo = topo
         self.d = topo.d
-        self.p = p
+        # degree per patch (an int: the same on every patch); p = the largest
+        self.pk = np.broadcast_to(np.asarray(p, dtype=np.int64), (topo.K,)).copy()
+        self.p = int(self.pk.max())
         self.conforming = conforming
         self.elems = np.asarray(elems, dtype=np.int64).reshape(topo.K, topo.d)
-        self.n = self.elems + p
+        self.n = self.elems + self.pk[:, None]
         self.sizes = np.prod(self.n, axis=1)
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)])
         self.N_torn = int(self.offsets[-1])
@@ -190,9 +192,10 @@ class Level:
     def _greville_points(self, k):
         d = self.d
         axes = []
+        pk = int(self.pk[k])
         for delta in range(d):
-            kn = bspline.open_uniform_knots(int(self.elems[k, delta]), self.p)
-            axes.append(bspline.greville(kn, self.p))
+            kn = bspline.open_uniform_knots(int(self.elems[k, delta]), pk)
+            axes.append(bspline.greville(kn, pk))
         pts = tensor_points(axes)
         X, _ = multilinear(self.topo.corners[k], pts)
         return X
@@ -269,8 +272,8 @@ class Level:
             x, w = bspline.element_quadrature(ne, q)
             pts1.append(x)
             wts1.append(w)
-            B1.append(collocation_1d(ne, self.p, x, 0))
-            D1.append(collocation_1d(ne, self.p, x, 1))
+            B1.append(collocation_1d(ne, int(self.pk[k]), x, 0))
+            D1.append(collocation_1d(ne, int(self.pk[k]), x, 1))
         C0 = kron_dirs(B1)
         Cg = []
         for g in range(d):
@@ -279,8 +282,9 @@ class Level:
 
     def volume_matrix(self, k):
         """Patch stiffness (grad u, grad v)_{L2(Omega_k)} with q = p+1 Gauss
-        points per element and direction (Section 2, eq. model)."""
-        C0, Cg, W, xh = self.patch_collocation(k, self.p + 1)
+        points per element and direction (Section 2, eq. model), p = the
+        patch's degree."""
+        C0, Cg, W, xh = self.patch_collocation(k, int(self.pk[k]) + 1)
         _, J = multilinear(self.topo.corners[k], xh)
         detJ = np.linalg.det(J)
         if np.any(detJ <= 0):
@@ -300,7 +304,8 @@ class Level:
         integrand vanishes).  Returns the row as a dense vector over the
         patch's local unknowns.  Used to check single outputs of the operator
         at sizes whose full assembly is out of reach."""
-        d, p, q = self.d, self.p, self.p + 1
+        d, p = self.d, int(self.pk[k])
+        q = p + 1
         pts1, wts1, B1, D1 = [], [], [], []
         for delta in range(d):
             ne = int(self.elems[k, delta])
@@ -330,7 +335,7 @@ class Level:
 
     def load_vector(self, k, f):
         """(f, phi_i)_{L2(Omega_k)} with q = p+1 Gauss points."""
-        C0, _, W, xh = self.patch_collocation(k, self.p + 1)
+        C0, _, W, xh = self.patch_collocation(k, int(self.pk[k]) + 1)
         X, J = multilinear(self.topo.corners[k], xh)
         detJ = np.abs(np.linalg.det(J))
         return C0.T @ (W * detJ * f(X))
@@ -347,8 +352,8 @@ class Level:
                 x = np.array([float(s)])
             else:
                 x = tpts[tang.index(g)]
-            val1.append(collocation_1d(ne, self.p, x, 0))
-            der1.append(collocation_1d(ne, self.p, x, 1))
+            val1.append(collocation_1d(ne, int(self.pk[k]), x, 0))
+            der1.append(collocation_1d(ne, int(self.pk[k]), x, 1))
         V = kron_dirs(val1)
         Gr = [kron_dirs([der1[h] if h == g else val1[h] for h in range(d)]) for g in range(d)]
         xh_axes = []
@@ -359,12 +364,13 @@ class Level:
     def interface_matrix(self):
         """sum over interfaces of eta([u],[v]) - ([u],{grad v}.n) - ([v],{grad u}.n)
         (eq. model:discr2) in torn numbering.  Quadrature: q = p+1 Gauss points
-        on every segment of the union of both sides' breakpoints."""
+        (p = the larger of the two sides' degrees) on every segment of the
+        union of both sides' breakpoints."""
         topo = self.topo
         d = self.d
-        q = self.p + 1
         rows, cols, vals = [], [], []
         for (k, dk, sk, l, dl, sl_) in topo.interfaces:
+            q = int(max(self.pk[k], self.pk[l])) + 1
             tk = [g for g in range(d) if g != dk]
             tl = [g for g in range(d) if g != dl]
             tpts_k, tw = [], []
@@ -437,10 +443,13 @@ class Level:
 def penalty(topo, elems_fine, p, sigma):
     """eta_kl = sigma p^2 / h_kl per interface, h from the finest grid on every
     level (Section 3, eq. a:galerkin).  h_kl = min(h_k, h_l) with the physical
-    element size h_s = |Omega_s|^(1/d) / max_delta n_el(s, delta)."""
+    element size h_s = |Omega_s|^(1/d) / max_delta n_el(s, delta); with a
+    degree per patch, p = max(p_k, p_l)."""
     d = topo.d
+    pk = np.broadcast_to(np.asarray(p, dtype=np.int64), (topo.K,))
     h = topo.measure ** (1.0 / d) / np.max(np.asarray(elems_fine).reshape(topo.K, d), axis=1)
     etas = {}
     for (k, dk, sk, l, dl, sl) in topo.interfaces:
-        etas[(k, l)] = sigma * p * p / min(h[k], h[l])
+        pkl = float(max(pk[k], pk[l]))
+        etas[(k, l)] = sigma * pkl * pkl / min(h[k], h[l])
     return etas

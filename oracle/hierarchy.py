@@ -67,7 +67,7 @@ def prolongation(level_c, level_f):
         for delta in range(level_c.d):
             nc = int(level_c.elems[k, delta])
             assert int(level_f.elems[k, delta]) == 2 * nc
-            mats.append(sp.csr_matrix(prolongation_1d(nc, level_c.p)))
+            mats.append(sp.csr_matrix(prolongation_1d(nc, int(level_c.pk[k]))))
         blocks.append(kron_dirs(mats))
     Pt = sp.block_diag(blocks, format="csr")
     P = (level_f.S @ Pt @ level_c.E).tocsr()

@@ -162,7 +162,8 @@ class SCMSSmoother:
         self.sigma = []
         self.gamma = []
         for k in range(topo.K):
-            self.factors.append([SCMS1D(int(level.elems[k, g]), level.p) for g in range(d)])
+            self.factors.append([SCMS1D(int(level.elems[k, g]), int(level.pk[k]))
+                                 for g in range(d)])
             h = 1.0 / float(np.max(level.elems[k]))
             self.sigma.append(1.0 / (delta_scal * h * h))
             self.gamma.append(topo.measure[k] ** ((d - 2.0) / d))
@@ -214,11 +215,13 @@ def gs_color_keys(level, tile):
     sides without a common corner, at least n_el + p - 1 >= p + 1 apart
     (n_el >= 2 on every smoothed level).
 
-    tile >= p keeps tiles of equal parity uncoupled as well."""
+    tile >= p keeps tiles of equal parity uncoupled as well.  With a degree
+    per patch, p and the tile are the patch's (tile None: 2(p_k+1)) and the
+    position s is counted in base (p_max+1), so keys of patches of different
+    degree share one order."""
     topo = level.topo
     d = level.d
-    p = level.p
-    assert tile >= p
+    pm = level.p
     color = topo.vertex_color if level.conforming else topo.patch_color
     keys = np.zeros(level.N, dtype=np.int64)
     for t in range(level.N_torn):
@@ -226,10 +229,13 @@ def gs_color_keys(level, tile):
         if c < 0 or level.rep_torn[c] != t:
             continue
         k = int(np.searchsorted(level.offsets, t, side="right") - 1)
+        p = int(level.pk[k])
+        tk = 2 * (p + 1) if tile is None else tile
+        assert tk >= p
         i = level.idx[k][t - level.offsets[k]]
-        par = sum(((int(i[g]) // tile) % 2) << g for g in range(d))
-        sub = sum((int(i[g]) % (p + 1)) * (p + 1) ** g for g in range(d))
-        keys[c] = (color[k] * 2 ** d + par) * (p + 1) ** d + sub
+        par = sum(((int(i[g]) // tk) % 2) << g for g in range(d))
+        sub = sum((int(i[g]) % (p + 1)) * (pm + 1) ** g for g in range(d))
+        keys[c] = (color[k] * 2 ** d + par) * (pm + 1) ** d + sub
     return keys
 
 

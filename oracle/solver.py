@@ -33,15 +33,20 @@ class OracleProblem:
         self.topo = Topology(corners)
         K, d = self.topo.K, self.topo.d
         elems = np.asarray(elems, dtype=np.int64).reshape(K, d)
-        self.p, self.d = p, d
+        # p: one degree, or a degree per patch (non-matching spaces of Section 5)
+        self.pk = np.broadcast_to(np.asarray(p, dtype=np.int64), (K,)).copy()
+        self.p, self.d = int(self.pk.max()), d
         self.conforming = conforming
         self.smoother = smoother
         self.mu, self.nu = mu, nu
         self.tau, self.delta = tau, delta
-        self.gs_tile = 2 * (p + 1) if gs_tile is None else gs_tile
-        self.eta = None if conforming else penalty(self.topo, elems, p, sigma)
+        if gs_tile is None and np.all(self.pk == self.p):
+            gs_tile = 2 * (self.p + 1)
+        self.gs_tile = gs_tile  # None: 2(p_k+1) per patch
+        self.eta = None if conforming else penalty(self.topo, elems, self.pk, sigma)
         self.level_elems = level_elements(elems, coarse_min)
-        self.levels = [Level(self.topo, e, p, conforming, self.eta) for e in self.level_elems]
+        self.levels = [Level(self.topo, e, self.pk, conforming, self.eta)
+                       for e in self.level_elems]
         self.A = [lev.assemble() for lev in self.levels]
         self.P = [None] + [prolongation(self.levels[l - 1], self.levels[l])
                            for l in range(1, len(self.levels))]
@@ -171,13 +176,13 @@ class OracleProblem:
         return self.levels[-1].load(f)
 
     def l2_error(self, u):
-        """||u_h - prod sin(pi x)||_{L2} with q = p+3 Gauss points."""
+        """||u_h - prod sin(pi x)||_{L2} with q = p+3 Gauss points (p = the
+        patch's degree)."""
         lev = self.levels[-1]
         ut = lev.to_torn(u)
         err2 = 0.0
-        q = self.p + 3
         for k in range(self.topo.K):
-            C0, _, W, xh = lev.patch_collocation(k, q)
+            C0, _, W, xh = lev.patch_collocation(k, int(self.pk[k]) + 3)
             X, J = multilinear(self.topo.corners[k], xh)
             uh = C0 @ ut[lev.offsets[k]:lev.offsets[k + 1]]
             ex = np.prod(np.sin(np.pi * X), axis=1)

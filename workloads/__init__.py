@@ -76,6 +76,22 @@ def lshape_elems(level, degrees=None):
     return np.full((3, 2), 2 ** int(level), dtype=np.int64)
 
 
+def nonmatching_spaces(elems_fine, p):
+    """The non-matching spaces of the paper's SIPG experiments (Section 5):
+    of every three patches (in patch order) the first keeps S_{p,h}, the
+    second takes S_{p+1,2h}, the third S_{p,2h}.  Returns (element counts,
+    degree per patch) from the element counts of S_{p,h} (even counts)."""
+    e = np.asarray(elems_fine, dtype=np.int64).copy()
+    deg = np.full(e.shape[0], int(p), dtype=np.int64)
+    for k in range(e.shape[0]):
+        if k % 3 == 1:
+            e[k] //= 2
+            deg[k] = p + 1
+        elif k % 3 == 2:
+            e[k] //= 2
+    return e, deg
+
+
 def fichera_corners():
     """The Fichera corner: the cube (0,2)^3 without the octant (1,2)^3, as
     seven axis-aligned unit cubes (identity and translations as geometry
