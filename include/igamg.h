@@ -108,6 +108,11 @@ typedef struct {
   int n_patches;          /* K >= 1 */
   const double *corners;  /* [n_patches][2^dim][dim] */
   const int32_t *elems;   /* [n_patches][dim] elements per direction on the finest level */
+  const int32_t *degrees; /* [n_patches] spline degree per patch, or NULL: `degree` of
+                             igamg_setup on every patch.  Different degrees (the
+                             non-matching spaces of Section 5) take the SIPG space with
+                             the SCMS smoother in 2D; the penalty of an interface uses
+                             the larger degree of its two sides */
 } igamg_patches;
 
 typedef struct {

@@ -176,13 +176,14 @@ class OracleProblem:
         return self.levels[-1].load(f)
 
     def l2_error(self, u):
-        """||u_h - prod sin(pi x)||_{L2} with q = p+3 Gauss points (p = the
-        patch's degree)."""
+        """||u_h - prod sin(pi x)||_{L2} with q = p+3 Gauss points per element
+        and direction on every patch (p = the largest degree)."""
         lev = self.levels[-1]
         ut = lev.to_torn(u)
         err2 = 0.0
+        q = self.p + 3
         for k in range(self.topo.K):
-            C0, _, W, xh = lev.patch_collocation(k, int(self.pk[k]) + 3)
+            C0, _, W, xh = lev.patch_collocation(k, q)
             X, J = multilinear(self.topo.corners[k], xh)
             uh = C0 @ ut[lev.offsets[k]:lev.offsets[k + 1]]
             ex = np.prod(np.sin(np.pi * X), axis=1)

@@ -67,20 +67,21 @@ struct L2Tables {
   std::vector<int> tab;
   std::vector<long long> el_off{0};
   long long nel = 0;
+  // (p+3)-point rule with p the largest degree, on every patch
   explicit L2Tables(const igamg::Context &c) : gq(igamg::gauss_rule(c.p + 3)) {
     const igamg::LevelData &L = c.lv.back();
     tab.assign(3 * L.K, 0);
-    std::map<int, int> tab_of;
+    std::map<std::pair<int, int>, int> tab_of;
     for (int k = 0; k < L.K; ++k) {
       long long ne = 1;
       for (int g = 0; g < c.d; ++g) {
         const int n = L.pd[k].nel[g];
         ne *= n;
-        auto it = tab_of.find(n);
+        auto it = tab_of.find({n, L.pd[k].p});
         if (it == tab_of.end()) {
           std::vector<double> B, D;
-          igamg::element_tables(n, c.p, gq, B, D);
-          it = tab_of.emplace(n, (int)tB.size()).first;
+          igamg::element_tables(n, L.pd[k].p, gq, B, D);
+          it = tab_of.emplace(std::make_pair(n, L.pd[k].p), (int)tB.size()).first;
           tB.insert(tB.end(), B.begin(), B.end());
         }
         tab[3 * k + g] = it->second;

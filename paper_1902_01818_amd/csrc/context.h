@@ -182,6 +182,9 @@ struct LevelData {
   int n_vtiles = 0;
   VolTile *d_stiles = nullptr;  // row tiles of the stencil assembly (first row in e0)
   int n_stiles = 0;
+  // tiles grouped by patch degree (degree, first tile, count): the volume
+  // operator (d_vtiles / d_optiles) and the stencil assembly (d_stiles)
+  std::vector<std::array<int, 3>> vgroups, sgroups;
   std::vector<GsClass> gs;  // classes in key order
   GsTile *d_atiles = nullptr;  // every Gauss-Seidel tile of the level (stored-row operator)
   GsTile3 *d_atiles3 = nullptr;  // the same for 3D patches
@@ -239,7 +242,10 @@ struct TimerFamily {
 };
 
 struct Context {
-  int d = 2, p = 2, K = 0;
+  int d = 2, p = 2, K = 0;  // p: the largest degree of the patches
+  std::vector<int> pk;      // degree per patch (the non-matching spaces of Section 5)
+  bool mixed = false;       // patches of different degrees
+  GaussRule *d_rules = nullptr;  // Gauss rules by number of points (device, [MAXQ + 1])
   igamg_options opt{};
   double sigma_pen = 5.0;
   GaussRule gr{};

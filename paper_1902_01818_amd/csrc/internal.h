@@ -43,6 +43,7 @@ struct PatchDev {
   int xp[3];         // prolongation rows from the coarser level: offset into lo / val tables
   int xr[3];         // restriction rows to the coarser level (on the coarse patch entry)
   int color;         // patch colour of the Gauss-Seidel ordering
+  int p;             // spline degree of the patch
   double scms_scale; // tau / gamma_k
   double sigma;      // SCMS scaling 1/(delta h^2)
 };

@@ -35,6 +35,7 @@
 #include <utility>
 
 #include "geom.h"
+#include "hostmath.h"
 #include "kernels.h"
 
 namespace igamg {
@@ -42,6 +43,16 @@ namespace igamg {
 namespace {
 
 constexpr int BS = 256;
+
+// Gauss rules by number of points, computed once
+const GaussRule &rule_of(int q) {
+  static const std::vector<GaussRule> rules = [] {
+    std::vector<GaussRule> v(MAXQ + 1);
+    for (int n = 1; n <= MAXQ; ++n) v[n] = gauss_rule(n);
+    return v;
+  }();
+  return rules[q];
+}
 
 inline unsigned nblocks(long long n, int bs = BS) {
   long long b = (n + bs - 1) / bs;
@@ -279,9 +290,10 @@ __global__ __launch_bounds__(256) void gather3d_kernel(const PatchDev *pd, int k
 template <int P, int RT>
 __global__ __launch_bounds__(256) void stencil2d_kernel(const VolTile *tiles, const PatchDev *pd,
                                                         const double *tabB, const double *tabD,
-                                                        GaussRule gr, double *st) {
+                                                        GaussRule gr, double *st, int SP) {
+  // SP: row stride of st (at least the padded (2p+1)^2 of this degree; a
+  // level with patches of higher degree uses theirs)
   constexpr int Q = P + 1, P1 = P + 1, S1 = 2 * P + 1, S = S1 * S1;
-  constexpr int SP = (S + 15) / 16 * 16;
   constexpr int NE = RT + P;                  // element columns touching the tile
   constexpr int NOUT = RT * RT * S;           // entries of the tile's rows
   constexpr int OPT = (NOUT + 255) / 256;     // entries per thread
@@ -436,7 +448,8 @@ __device__ double l2err_element(const PatchDev *pd, int K, const long long *el_o
     e[d] = (int)(loc % pt.nel[d]);
     loc /= pt.nel[d];
   }
-  const int q = gq.q, P1 = p + 1;
+  const int q = gq.q, P1 = pt.p + 1;  // the patch's degree (p: unused, the largest)
+  (void)p;
   double sum = 0.0;
   int g[3] = {0, 0, 0};
   for (;;) {
@@ -511,13 +524,17 @@ __global__ __launch_bounds__(1024) void sum_fixed_kernel(const double *x, long l
 }
 
 template <int D>
-__global__ void load_kernel(const PatchDev *pd, int K, const double *tabB, GaussRule gr, int p,
-                            const unsigned char *mask, long long ntorn, double *out) {
+__global__ void load_kernel(const PatchDev *pd, int K, const double *tabB,
+                            const GaussRule *rules, const unsigned char *mask, long long ntorn,
+                            double *out) {
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= ntorn) return;
   int k = 0;
   while (k + 1 < K && pd[k + 1].off <= t) ++k;
   const PatchDev &pt = pd[k];
+  // the patch's degree p and its (p+1)-point rule (the tables' rule)
+  const int p = pt.p;
+  const GaussRule &gr = rules[p + 1];
   long long loc = t - pt.off;
   int i[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int d = 0; d < D; ++d) {
@@ -2781,9 +2798,10 @@ template void k_convert<float, double>(const float *, const double *, double *, 
 int stencil_tile_2d(int p) { return p <= 3 ? 8 : 4; }
 
 template <int P, int RT>
-static void launch_stencil2d(Context &c, LevelData &L, double *out) {
-  stencil2d_kernel<P, RT><<<L.n_stiles, 256, 0, c.stream>>>(L.d_stiles, L.d_pd, L.d_tabB, L.d_tabD,
-                                                            c.gr, out);
+static void launch_stencil2d(Context &c, LevelData &L, double *out, int first, int count,
+                             int SP) {
+  stencil2d_kernel<P, RT><<<count, 256, 0, c.stream>>>(L.d_stiles + first, L.d_pd, L.d_tabB,
+                                                       L.d_tabD, rule_of(P + 1), out, SP);
 }
 
 // element matrices of at most this many bytes at a time (z slabs of a patch)
@@ -2825,18 +2843,22 @@ static void assemble3d(Context &c, LevelData &L, double *out) {
 void k_stencil_assemble(Context &c, LevelData &L, double *out) {
   int S = 1;
   for (int d = 0; d < c.d; ++d) S *= (2 * c.p + 1);
-  long long tot = L.Ntorn * ((S + 15) / 16 * 16);
+  const int SP = (S + 15) / 16 * 16;  // row stride: the level's largest degree
+  long long tot = L.Ntorn * SP;
   if (c.d == 2) {
-    switch (c.p) {
-      case 1: launch_stencil2d<1, 8>(c, L, out); break;
-      case 2: launch_stencil2d<2, 8>(c, L, out); break;
-      case 3: launch_stencil2d<3, 8>(c, L, out); break;
-      case 4: launch_stencil2d<4, 4>(c, L, out); break;
-      case 5: launch_stencil2d<5, 4>(c, L, out); break;
-      case 6: launch_stencil2d<6, 4>(c, L, out); break;
-      case 7: launch_stencil2d<7, 4>(c, L, out); break;
-      case 8: launch_stencil2d<8, 4>(c, L, out); break;
-      default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+    // one launch per patch degree (tiles grouped by degree)
+    for (const auto &g : L.sgroups) {
+      switch (g[0]) {
+        case 1: launch_stencil2d<1, 8>(c, L, out, g[1], g[2], SP); break;
+        case 2: launch_stencil2d<2, 8>(c, L, out, g[1], g[2], SP); break;
+        case 3: launch_stencil2d<3, 8>(c, L, out, g[1], g[2], SP); break;
+        case 4: launch_stencil2d<4, 4>(c, L, out, g[1], g[2], SP); break;
+        case 5: launch_stencil2d<5, 4>(c, L, out, g[1], g[2], SP); break;
+        case 6: launch_stencil2d<6, 4>(c, L, out, g[1], g[2], SP); break;
+        case 7: launch_stencil2d<7, 4>(c, L, out, g[1], g[2], SP); break;
+        case 8: launch_stencil2d<8, 4>(c, L, out, g[1], g[2], SP); break;
+        default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+      }
     }
   } else if (c.arena.region || c.p > 4) {
     // inside a lent region (no scratch allocation): per-entry quadrature
@@ -2866,10 +2888,10 @@ void k_invdiag(const double *stencil, int S, int center, const unsigned char *ma
 
 void k_load_manufactured(Context &c, LevelData &L, double *out) {
   if (c.d == 2)
-    load_kernel<2><<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, c.gr, c.p,
+    load_kernel<2><<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, c.d_rules,
                                                           L.d_mask, L.Ntorn, out);
   else
-    load_kernel<3><<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, c.gr, c.p,
+    load_kernel<3><<<nblocks(L.Ntorn), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, c.d_rules,
                                                           L.d_mask, L.Ntorn, out);
 }
 
@@ -2947,9 +2969,11 @@ int vol_tile_2d(int p) { return p <= 4 ? 8 : (p <= 6 ? 6 : 4); }
 // faster for batches too than sharing a stored metric across several
 // right-hand sides per block, which costs parallelism)
 template <typename T, int P, int TE>
-static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
-  vol2d_kernel<T, P, TE, 1><<<dim3(nrhs, L.n_vtiles), 256, 0, c.stream>>>(
-      L.d_optiles, L.d_tabB, L.d_tabD, c.gr, u, r, L.d_mask, alpha, L.Ntorn, nrhs);
+static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs, int first,
+                         int count) {
+  vol2d_kernel<T, P, TE, 1><<<dim3(nrhs, count), 256, 0, c.stream>>>(
+      L.d_optiles + first, L.d_tabB, L.d_tabD, rule_of(P + 1), u, r, L.d_mask, alpha, L.Ntorn,
+      nrhs);
 }
 
 template <typename T, int P>
@@ -2971,16 +2995,19 @@ void k_vol_apply(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) 
     }
     return;
   }
-  switch (c.p) {
-    case 1: launch_vol2d<T, 1, 8>(c, L, u, r, alpha, nrhs); break;
-    case 2: launch_vol2d<T, 2, 8>(c, L, u, r, alpha, nrhs); break;
-    case 3: launch_vol2d<T, 3, 8>(c, L, u, r, alpha, nrhs); break;
-    case 4: launch_vol2d<T, 4, 8>(c, L, u, r, alpha, nrhs); break;
-    case 5: launch_vol2d<T, 5, 6>(c, L, u, r, alpha, nrhs); break;
-    case 6: launch_vol2d<T, 6, 6>(c, L, u, r, alpha, nrhs); break;
-    case 7: launch_vol2d<T, 7, 4>(c, L, u, r, alpha, nrhs); break;
-    case 8: launch_vol2d<T, 8, 4>(c, L, u, r, alpha, nrhs); break;
-    default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+  // one launch per patch degree (tiles grouped by degree; disjoint outputs)
+  for (const auto &g : L.vgroups) {
+    switch (g[0]) {
+      case 1: launch_vol2d<T, 1, 8>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      case 2: launch_vol2d<T, 2, 8>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      case 3: launch_vol2d<T, 3, 8>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      case 4: launch_vol2d<T, 4, 8>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      case 5: launch_vol2d<T, 5, 6>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      case 6: launch_vol2d<T, 6, 6>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      case 7: launch_vol2d<T, 7, 4>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      case 8: launch_vol2d<T, 8, 4>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+      default: fail(IGAMG_EUNSUPPORTED, "degree out of range");
+    }
   }
 }
 template void k_vol_apply<double>(Context &, LevelData &, const double *, double *, double, int);

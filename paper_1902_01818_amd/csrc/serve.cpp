@@ -271,6 +271,8 @@ int igamg_server_submit(igamg_server *srv, const igamg_patches *patches, int deg
     // run aborted the process for a reason not yet identified
     if (o->precision != IGAMG_FP64)
       igamg::fail(IGAMG_EUNSUPPORTED, "the serving runtime takes float64 requests only");
+    if (patches->degrees)
+      igamg::fail(IGAMG_EUNSUPPORTED, "the serving runtime takes one degree per request");
     long long n = 0;
     int lv = 0;
     igamg::problem_size(patches, degree, o, &n, &lv);

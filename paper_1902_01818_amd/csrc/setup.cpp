@@ -274,7 +274,8 @@ static void build_topology(Context &c) {
       for (int a = 0; a < d; ++a) ne = std::max(ne, c.elems_fine[k][a]);
       return std::pow(c.measure[k], 1.0 / d) / ne;
     };
-    f.eta = c.sigma_pen * c.p * c.p / std::min(h(f.k), h(f.l));
+    const double pkl = std::max(c.pk[f.k], c.pk[f.l]);
+    f.eta = c.sigma_pen * pkl * pkl / std::min(h(f.k), h(f.l));
   }
 }
 
@@ -305,13 +306,16 @@ static long long torn_index(const PatchDev &pt, const int *i) {
 }
 
 static void build_level_dofs(Context &c, LevelData &L, const std::vector<std::array<int, 3>> &el) {
-  const int d = c.d, K = c.K, p = c.p;
+  const int d = c.d, K = c.K;
   L.K = K;
   L.pd.assign(K, PatchDev{});
-  std::map<int, int> tab_of_nel;
+  // element tables per (element count, degree), Gauss rule of p+1 points
+  std::map<std::pair<int, int>, int> tab_of_nel;
   long long off = 0;
   for (int k = 0; k < K; ++k) {
     PatchDev &pt = L.pd[k];
+    const int p = c.pk[k];
+    pt.p = p;
     for (int b = 0; b < (1 << d); ++b)
       for (int a = 0; a < d; ++a) pt.corners[b][a] = c.corners[k][b * 3 + a];
     for (int g = 0; g < 3; ++g) {
@@ -326,14 +330,14 @@ static void build_level_dofs(Context &c, LevelData &L, const std::vector<std::ar
     pt.color = c.color[k];
     for (int g = 0; g < d; ++g) {
       int ne = pt.nel[g];
-      auto it = tab_of_nel.find(ne);
+      auto it = tab_of_nel.find({ne, p});
       if (it == tab_of_nel.end()) {
         std::vector<double> B, D;
-        element_tables(ne, p, c.gr, B, D);
+        element_tables(ne, p, gauss_rule(p + 1), B, D);
         int o = (int)L.tabB.size();
         L.tabB.insert(L.tabB.end(), B.begin(), B.end());
         L.tabD.insert(L.tabD.end(), D.begin(), D.end());
-        it = tab_of_nel.emplace(ne, o).first;
+        it = tab_of_nel.emplace(std::make_pair(ne, p), o).first;
       }
       pt.tab[g] = it->second;
     }
@@ -358,6 +362,7 @@ static void build_level_dofs(Context &c, LevelData &L, const std::vector<std::ar
     std::map<std::array<long long, 3>, int> gkey;
     for (int k = 0; k < K; ++k) {
       const PatchDev &pt = L.pd[k];
+      const int p = pt.p;
       std::vector<std::vector<double>> grev(d);
       for (int g = 0; g < d; ++g) {
         std::vector<double> t = open_knots(pt.nel[g], p);
@@ -443,13 +448,8 @@ static void build_level_dofs(Context &c, LevelData &L, const std::vector<std::ar
 // SIPG interface terms (Section 3, eq. model:discr2) by Gauss quadrature on
 // the union of both sides' breakpoints
 // ---------------------------------------------------------------------------
-struct SideEval {
-  double v[MAXP + 1][MAXP + 1][2];          // unused placeholder (kept small)
-};
-
 static void build_interfaces(Context &c, LevelData &L) {
-  const int d = c.d, p = c.p, q = p + 1;
-  GaussRule gq = gauss_rule(q);
+  const int d = c.d;
   // one sparse accumulator per interface (interfaces in parallel); the
   // per-interface sums are added in interface order below, so the result
   // does not depend on the number of threads
@@ -459,6 +459,10 @@ static void build_interfaces(Context &c, LevelData &L) {
     std::unordered_map<unsigned long long, double> acc;
     acc.reserve(1 << 12);
     const PatchDev &pk = L.pd[f.k], &pl = L.pd[f.l];
+    // q = p+1 Gauss points per merged segment, p the larger degree of the sides
+    const int q = std::max(pk.p, pl.p) + 1;
+    const GaussRule gq = gauss_rule(q);
+    const int ps[2] = {pk.p, pl.p};
     int tk[2], tl[2], nt = 0;
     for (int g = 0; g < d; ++g)
       if (g != f.dk) tk[nt++] = g;
@@ -485,20 +489,26 @@ static void build_interfaces(Context &c, LevelData &L) {
     }
     std::vector<double> kn[2][3];
     for (int g = 0; g < d; ++g) {
-      kn[0][g] = open_knots(pk.nel[g], p);
-      kn[1][g] = open_knots(pl.nel[g], p);
+      kn[0][g] = open_knots(pk.nel[g], ps[0]);
+      kn[1][g] = open_knots(pl.nel[g], ps[1]);
     }
     size_t n0 = pts[0].size(), n1 = d == 3 ? pts[1].size() : 1;
     const int nside = 2;  // normal layers carrying value or derivative
-    int ntan = 1;
-    for (int j = 0; j < d - 1; ++j) ntan *= (p + 1);
-    const int nact = nside * ntan;
-    std::vector<long long> idx(2 * nact);
-    std::vector<double> val(2 * nact), dn(2 * nact);
+    // active functions of a side: two normal layers x (p_side+1)^(d-1)
+    // tangential ones; side 0's entries first, then side 1's
+    int nacts[2];
+    for (int side = 0; side < 2; ++side) {
+      int ntan = 1;
+      for (int j = 0; j < d - 1; ++j) ntan *= (ps[side] + 1);
+      nacts[side] = nside * ntan;
+    }
+    const int aoff[2] = {0, nacts[0]};
     // the q (q^2 in 3D) points of a merged segment lie in one element of each
     // side: their contributions are summed in a dense local block that is
     // added to the sparse accumulator once per segment
-    const int na2 = 2 * nact;
+    const int na2 = nacts[0] + nacts[1];
+    std::vector<long long> idx(na2);
+    std::vector<double> val(na2), dn(na2);
     std::vector<double> Mloc((size_t)na2 * na2);
     const size_t qs1 = d == 3 ? (size_t)q : 1;
     for (size_t s1 = 0; s1 < n1; s1 += qs1)
@@ -569,6 +579,7 @@ static void build_interfaces(Context &c, LevelData &L) {
           double cvec[3] = {0, 0, 0};  // J^-1 n
           for (int a = 0; a < d; ++a)
             for (int b = 0; b < d; ++b) cvec[a] += Jinv[a][b] * nrm[b];
+          const int p = ps[side], nact = nacts[side];
           double bv[3][MAXP + 1], bd[3][MAXP + 1];
           int first[3];
           for (int g = 0; g < d; ++g) {
@@ -610,9 +621,9 @@ static void build_interfaces(Context &c, LevelData &L) {
             for (int g = 0; g < d; ++g) dnv += grad[g] * cvec[g];
             int gi[3] = {0, 0, 0};
             for (int g = 0; g < d; ++g) gi[g] = first[g] + li[g];
-            idx[side * nact + a] = torn_index(pt, gi);
-            val[side * nact + a] = side ? -value : value;  // jump [u] = u_k - u_l
-            dn[side * nact + a] = dnv;
+            idx[aoff[side] + a] = torn_index(pt, gi);
+            val[aoff[side] + a] = side ? -value : value;  // jump [u] = u_k - u_l
+            dn[aoff[side] + a] = dnv;
           }
         }
         const double eta = f.eta;
@@ -885,7 +896,6 @@ static void fold_conforming_rows(Context &c, LevelData &L, double *st64, int SP)
 static std::vector<double> dense_block_rows(const Context &c, const LevelData &L,
                                             const std::vector<int> &comps, const double *rows,
                                             int SP) {
-  const int p = c.p, S1 = 2 * p + 1;
   const int n = (int)comps.size();
   std::unordered_map<long long, int> loc;
   loc.reserve(2 * n);
@@ -895,6 +905,7 @@ static std::vector<double> dense_block_rows(const Context &c, const LevelData &L
     const long long t1 = L.rep[comps[a]];
     const int k = L.patch_of(t1);
     const PatchDev &pt = L.pd[k];
+    const int p = pt.p, S1 = 2 * p + 1;  // the row's layout: its patch's degree
     long long lc = t1 - pt.off;
     int i[3] = {0, 0, 0};
     for (int g = 0; g < c.d; ++g) {
@@ -1063,7 +1074,7 @@ static std::vector<double> transpose(const std::vector<double> &A, int n) {
 //   6. U_z += scale W1_z Qx^T      (into the patch interior of u)
 template <typename T>
 static void build_scms3(Context &c, LevelData &L) {
-  const int p = c.p;
+  const int p = c.p;  // one degree in 3D
   LevelArrays<T> &A = L.arr<T>();
   struct QT {
     T *Q, *QT;
@@ -1154,7 +1165,6 @@ static void build_scms3(Context &c, LevelData &L) {
 
 template <typename T>
 static void build_scms(Context &c, LevelData &L) {
-  const int p = c.p;
   if (c.d == 3) {
     build_scms3<T>(c, L);
     return;
@@ -1163,16 +1173,18 @@ static void build_scms(Context &c, LevelData &L) {
   struct QT {
     T *Q, *QT, *lam;
   };
-  std::map<int, QT> qtab;
+  // 1D factors per (element count, degree)
+  std::map<std::pair<int, int>, QT> qtab;
   for (int k = 0; k < L.K; ++k)
     for (int g = 0; g < c.d; ++g) {
-      int ne = L.pd[k].nel[g];
-      if (qtab.count(ne)) continue;
+      const int ne = L.pd[k].nel[g], p = L.pd[k].p;
+      if (qtab.count({ne, p})) continue;
       std::vector<double> Q, lam;
       scms_factors_1d(ne, p, Q, lam);
       int n = ne + p - 2;
-      qtab[ne] = QT{c.arena.upload_as<T>(Q, c.stream), c.arena.upload_as<T>(transpose(Q, n), c.stream),
-                    c.arena.upload_as<T>(lam, c.stream)};
+      qtab[{ne, p}] = QT{c.arena.upload_as<T>(Q, c.stream),
+                         c.arena.upload_as<T>(transpose(Q, n), c.stream),
+                         c.arena.upload_as<T>(lam, c.stream)};
     }
   size_t scr = 0;
   for (int k = 0; k < L.K; ++k) scr += (size_t)(L.pd[k].n[0] - 2) * (L.pd[k].n[1] - 2);
@@ -1189,7 +1201,7 @@ static void build_scms(Context &c, LevelData &L) {
   for (int k = 0; k < L.K; ++k) {
     PatchDev &pt = L.pd[k];
     const int nx = pt.n[0], mx = pt.n[0] - 2, my = pt.n[1] - 2;
-    const QT &qx = qtab[pt.nel[0]], &qy = qtab[pt.nel[1]];
+    const QT &qx = qtab[{pt.nel[0], pt.p}], &qy = qtab[{pt.nel[1], pt.p}];
     T *Wk = A.wscratch + so;
     so += (size_t)mx * my;
     T *rin = A.r + pt.off + nx + 1;
@@ -1461,26 +1473,28 @@ static void build_gs(Context &c, LevelData &L, bool keep64) {
 }
 
 static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
-  const int p = c.p, d = c.d;
+  const int d = c.d;
   struct Tab {
     int prow, rrow;
   };
-  std::map<int, Tab> tabs;
+  // 1D embeddings per (coarse element count, degree)
+  std::map<std::pair<int, int>, Tab> tabs;
   std::vector<std::vector<double>> Ps;
-  std::vector<int> ncs;
+  std::vector<std::pair<int, int>> ncs;
   int PW = 1, RW = 1;
   for (int k = 0; k < F.K; ++k)
     for (int g = 0; g < d; ++g) {
-      int ncel = C.pd[k].nel[g];
+      const int ncel = C.pd[k].nel[g], p = C.pd[k].p;
       if (F.pd[k].nel[g] != 2 * ncel) fail(IGAMG_EINVAL, "levels are not dyadic");
-      if (tabs.count(ncel)) continue;
-      tabs[ncel] = Tab{0, 0};
+      if (tabs.count({ncel, p})) continue;
+      tabs[{ncel, p}] = Tab{0, 0};
       Ps.push_back(embedding_1d(ncel, p));
-      ncs.push_back(ncel);
+      ncs.push_back({ncel, p});
     }
   // widths
   for (size_t t = 0; t < Ps.size(); ++t) {
-    int nc = ncs[t] + p, nf = 2 * ncs[t] + p;
+    const int p = ncs[t].second;
+    int nc = ncs[t].first + p, nf = 2 * ncs[t].first + p;
     const std::vector<double> &P = Ps[t];
     for (int i = 0; i < nf; ++i) {
       int a = -1, b = -1;
@@ -1505,8 +1519,8 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
   std::vector<double> Pv, Rv;
   size_t t = 0;
   for (auto &kv : tabs) {
-    int ncel = kv.first;
-    size_t ti = std::find(ncs.begin(), ncs.end(), ncel) - ncs.begin();
+    const int ncel = kv.first.first, p = kv.first.second;
+    size_t ti = std::find(ncs.begin(), ncs.end(), kv.first) - ncs.begin();
     const std::vector<double> &P = Ps[ti];
     int nc = ncel + p, nf = 2 * ncel + p;
     kv.second.prow = (int)Plo.size();
@@ -1529,7 +1543,7 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
   }
   for (int k = 0; k < F.K; ++k)
     for (int g = 0; g < d; ++g) {
-      const Tab &tb = tabs[C.pd[k].nel[g]];
+      const Tab &tb = tabs[{C.pd[k].nel[g], C.pd[k].p}];
       F.pd[k].xp[g] = tb.prow;
       F.pd[k].xr[g] = tb.rrow;
     }
@@ -1624,8 +1638,16 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
   if (P->n_patches < 1 || !P->corners || !P->elems) fail(IGAMG_EINVAL, "no patches");
   if (degree < 1 || degree > MAXP) fail(IGAMG_EINVAL, "degree out of range 1..8");
   c.d = P->dim;
-  c.p = degree;
   c.K = P->n_patches;
+  c.pk.assign(c.K, degree);
+  if (P->degrees)
+    for (int k = 0; k < c.K; ++k) {
+      if (P->degrees[k] < 1 || P->degrees[k] > MAXP) fail(IGAMG_EINVAL, "degree out of range 1..8");
+      c.pk[k] = P->degrees[k];
+    }
+  c.p = *std::max_element(c.pk.begin(), c.pk.end());
+  c.mixed = *std::min_element(c.pk.begin(), c.pk.end()) != c.p;
+  degree = c.p;
   c.opt = *o;
   c.sigma_pen = sigma;
   if (c.opt.gs_tile <= 0) c.opt.gs_tile = 2 * (degree + 1);
@@ -1649,6 +1671,9 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
       (c.opt.discretization != IGAMG_SIPG || !use_gs))
     fail(IGAMG_EUNSUPPORTED, "stored operator rows exist for SIPG with a Gauss-Seidel smoother only");
   if (c.d == 3 && degree > 4) fail(IGAMG_EUNSUPPORTED, "3D problems: degree 1..4");
+  if (c.mixed && (c.d != 2 || c.opt.discretization != IGAMG_SIPG ||
+                  c.opt.smoother != IGAMG_SMOOTHER_SCMS))
+    fail(IGAMG_EUNSUPPORTED, "patches of different degrees: 2D SIPG with the SCMS smoother only");
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
@@ -1693,6 +1718,11 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
   const bool f32 = c.fp32();
   c.d_bad = c.arena.alloc<int>(1);
   k_fill<int>(c.d_bad, 0, 1, c.stream);
+  {
+    std::vector<GaussRule> rules(MAXQ + 1);
+    for (int n = 1; n <= MAXQ; ++n) rules[n] = gauss_rule(n);
+    c.d_rules = c.arena.upload(rules, c.stream);
+  }
   auto lev_el = level_elements(c);
   const int NL = (int)lev_el.size();
   c.lv.resize(NL);
@@ -1747,14 +1777,15 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
         const int k = L.patch_of(t);
         const PatchDev &pt = L.pd[k];
         long long a = t - pt.off, b = L.if_col[e] - pt.off;
+        // slot in the row of this patch's degree ((2p_k+1)^d entries)
         int slot = 0, m = 1;
         for (int g = 0; g < c.d; ++g) {
           int ia = (int)(a % pt.n[g]), ib = (int)(b % pt.n[g]);
           a /= pt.n[g];
           b /= pt.n[g];
-          if (std::abs(ib - ia) > c.p) fail(IGAMG_EINVAL, "interface coupling outside the stencil");
-          slot += (ib - ia + c.p) * m;
-          m *= S1;
+          if (std::abs(ib - ia) > pt.p) fail(IGAMG_EINVAL, "interface coupling outside the stencil");
+          slot += (ib - ia + pt.p) * m;
+          m *= 2 * pt.p + 1;
         }
         srow.push_back((int)t);
         sslot.push_back(slot);
@@ -1773,13 +1804,20 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       L.d_has_if = c.arena.upload(has, c.stream);
       L.d_if_rows = c.arena.upload(rows, c.stream);
     }
-    // volume tiles
+    // volume tiles, grouped by patch degree (one launch per degree)
     std::vector<VolTile> vt;
-    const int TE = c.d == 2 ? vol_tile_2d(c.p) : VOL3D_TILE;
-    for (int k = 0; k < c.K; ++k)
-      for (int e2 = 0; e2 < (c.d == 3 ? L.pd[k].nel[2] : 1); e2 += TE)
-        for (int e1 = 0; e1 < L.pd[k].nel[1]; e1 += TE)
-          for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, e2}});
+    L.vgroups.clear();
+    for (int pdeg = 1; pdeg <= MAXP; ++pdeg) {
+      const int first = (int)vt.size();
+      const int TE = c.d == 2 ? vol_tile_2d(pdeg) : VOL3D_TILE;
+      for (int k = 0; k < c.K; ++k) {
+        if (L.pd[k].p != pdeg) continue;
+        for (int e2 = 0; e2 < (c.d == 3 ? L.pd[k].nel[2] : 1); e2 += TE)
+          for (int e1 = 0; e1 < L.pd[k].nel[1]; e1 += TE)
+            for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, e2}});
+      }
+      if ((int)vt.size() > first) L.vgroups.push_back({pdeg, first, (int)vt.size() - first});
+    }
     L.n_vtiles = (int)vt.size();
     L.d_vtiles = c.arena.upload(vt, c.stream);
     if (c.d == 2) {
@@ -1803,10 +1841,17 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     }
     if (c.d == 2 && ((use_gs && l >= 1) || c.opt.discretization == IGAMG_SIPG)) {
       std::vector<VolTile> stl;
-      const int RT = stencil_tile_2d(c.p);
-      for (int k = 0; k < c.K; ++k)
-        for (int y = 0; y < L.pd[k].n[1]; y += RT)
-          for (int x = 0; x < L.pd[k].n[0]; x += RT) stl.push_back(VolTile{k, {x, y, 0}});
+      L.sgroups.clear();
+      for (int pdeg = 1; pdeg <= MAXP; ++pdeg) {
+        const int first = (int)stl.size();
+        const int RT = stencil_tile_2d(pdeg);
+        for (int k = 0; k < c.K; ++k) {
+          if (L.pd[k].p != pdeg) continue;
+          for (int y = 0; y < L.pd[k].n[1]; y += RT)
+            for (int x = 0; x < L.pd[k].n[0]; x += RT) stl.push_back(VolTile{k, {x, y, 0}});
+        }
+        if ((int)stl.size() > first) L.sgroups.push_back({pdeg, first, (int)stl.size() - first});
+      }
       L.n_stiles = (int)stl.size();
       L.d_stiles = c.arena.upload(stl, c.stream);
     }

@@ -30,7 +30,8 @@ APPLIES = {"auto": 0, "sumfact": 1, "rows": 2}
 class Patches(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_patches", ctypes.c_int),
                 ("corners", ctypes.POINTER(ctypes.c_double)),
-                ("elems", ctypes.POINTER(ctypes.c_int32))]
+                ("elems", ctypes.POINTER(ctypes.c_int32)),
+                ("degrees", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Options(ctypes.Structure):
@@ -132,14 +133,23 @@ def _stream(stream):
     return _vp(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-def _patches(corners, elems):
+def _patches(corners, elems, degree=None):
+    """The patch description; degree: an int (the same on every patch, passed
+    separately) or one degree per patch.  Returns (struct, arrays to keep
+    alive, the degree argument of the C call)."""
     corners = np.ascontiguousarray(corners, dtype=np.float64)
     elems = np.ascontiguousarray(elems, dtype=np.int32)
     K, nc, d = corners.shape
     assert nc == 2 ** d and elems.shape == (K, d)
+    degs = None
+    if degree is not None and np.ndim(degree) > 0:
+        degs = np.ascontiguousarray(degree, dtype=np.int32)
+        assert degs.shape == (K,)
+        degree = int(degs.max())
     P = Patches(d, K, corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                elems.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
-    return P, (corners, elems)
+                elems.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                None if degs is None else degs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return P, (corners, elems, degs), degree
 
 
 def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1, nu=1,
@@ -163,7 +173,7 @@ def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1,
 def footprint(corners, elems, degree, nrhs=0, **opts):
     """Device bytes of a setup for a batch of nrhs right-hand sides (0 = the
     options' max_rhs)."""
-    P, keep = _patches(corners, elems)
+    P, keep, degree = _patches(corners, elems, degree)
     o = make_options(**opts)
     b = ctypes.c_size_t()
     _check(_lib.igamg_footprint(ctypes.byref(P), degree, ctypes.byref(o), nrhs, ctypes.byref(b)),
@@ -173,7 +183,7 @@ def footprint(corners, elems, degree, nrhs=0, **opts):
 
 def problem_size(corners, elems, degree, **opts):
     """(N, levels) of a problem, computed on the host."""
-    P, keep = _patches(corners, elems)
+    P, keep, degree = _patches(corners, elems, degree)
     o = make_options(**opts)
     n, lv = ctypes.c_int64(), ctypes.c_int()
     _check(_lib.igamg_problem_size(ctypes.byref(P), degree, ctypes.byref(o), ctypes.byref(n),
@@ -192,7 +202,7 @@ class Server:
         self._n = {}
 
     def submit(self, corners, elems, degree, rhs, sigma=5.0, tol=1e-8, maxit=200, **opts):
-        P, keep = _patches(corners, elems)
+        P, keep, degree = _patches(corners, elems, degree)
         o = make_options(**opts)
         rhs = np.ascontiguousarray(rhs, dtype=np.float64)
         rid = ctypes.c_int64()
@@ -242,7 +252,8 @@ class Solver:
     """One problem instance: igamg_setup ... igamg_destroy."""
 
     def __init__(self, corners, elems, degree, sigma=5.0, stream=None, **opts):
-        P, keep = _patches(corners, elems)
+        """degree: an int, or one degree per patch."""
+        P, keep, degree = _patches(corners, elems, degree)
         o = make_options(**opts)
         h = _vp()
         _check(_lib.igamg_setup(ctypes.byref(P), degree, sigma, ctypes.byref(o), _stream(stream),
