@@ -321,15 +321,22 @@ def _printed(name):
     return rows
 
 
-def paper_tables(igamg, torch, workloads, maxit=150):
-    """The paper's conforming experiments on the GPU, each count beside the
-    printed one: Table GS1 (L-shape, Gauss-Seidel V-cycle, multigrid used
-    directly and as PCG preconditioner; L = 4..8, p = 2..8), Table SCMS1
-    (L-shape, SCMS V-cycle, damping 1, scaling 0.12) and Table HYB3 (a)
-    (Fichera corner, hybrid V-cycle with PCG, scaling 0.12, L = 2..5,
-    p = 2..4; damping 0.5, the largest for which this build's reading of the
-    piece smoother keeps the cycle positive, and the paper's 1).  A count of
-    None means no convergence within maxit cycles."""
+PAPER_TABLES = ("GS1", "SCMS1", "SCMS2", "HYB3a")
+
+
+def paper_tables(igamg, torch, workloads, maxit=150, tables=PAPER_TABLES):
+    """The paper's L-shape and Fichera experiments on the GPU, each count
+    beside the printed one: Table GS1 (L-shape, conforming, Gauss-Seidel
+    V-cycle, multigrid used directly and as PCG preconditioner; L = 4..8,
+    p = 2..8), Table SCMS1 (the same with the SCMS V-cycle, damping 1,
+    scaling 0.12), Table SCMS2 (SIPG on the L-shape with the non-matching
+    spaces S_{p,h}, S_{p+1,2h}, S_{p,2h}, SCMS V-cycle, scaling 0.12, the
+    paper's damping 0.9 and 0.5; p = 2..7, degree p+1 = 9 being beyond the
+    library's degree range) and Table HYB3 (a) (Fichera corner, hybrid
+    V-cycle with PCG, scaling 0.12, L = 2..5, p = 2..4; damping 0.5, the
+    largest for which this build's reading of the piece smoother keeps the
+    cycle positive, and the paper's 1).  A count of None means no
+    convergence within maxit cycles."""
     out = {}
 
     def run(corners, elems, p, smoother, tau, outer, conforming=True):
@@ -351,6 +358,8 @@ def paper_tables(igamg, torch, workloads, maxit=150):
 
     for table, smoother, tau, golden in (("GS1", "gs", 0.25, "gs1_lshape_conforming.txt"),
                                          ("SCMS1", "scms", 1.0, "scms1_lshape_conforming.txt")):
+        if table not in tables:
+            continue
         printed = _printed(golden)
         rows = []
         for L in range(4, 9):
@@ -363,6 +372,23 @@ def paper_tables(igamg, torch, workloads, maxit=150):
                     rows.append(r)
         out[table] = rows
         print("bench: table %s done" % table, file=sys.stderr, flush=True)
+    if "SCMS2" in tables:
+        printed = _printed("scms2_lshape_nonmatching.txt")
+        rows = []
+        for tau in (0.9, 0.5):
+            for L in range(4, 9):
+                for p in range(2, 8):
+                    elems, deg = workloads.nonmatching_spaces(workloads.lshape_elems(L), p)
+                    for blk, outer in (("a", "mg"), ("b", "pcg")):
+                        col = (p - 2) + (0 if blk == "a" else 7)
+                        r = run(workloads.lshape_corners(), elems, deg, "scms", tau, outer,
+                                conforming=False)
+                        r.update(L=L, p=p, block=blk, damping=tau, printed=printed[L][col])
+                        rows.append(r)
+        out["SCMS2"] = rows
+        print("bench: table SCMS2 done", file=sys.stderr, flush=True)
+    if "HYB3a" not in tables:
+        return out
     printed = _printed("hyb3_fichera.txt")
     rows = []
     for tau in (0.5, 1.0):
@@ -429,9 +455,11 @@ def main():
                          "1000 right-hand sides, L2 error ladder) and print its results")
     ap.add_argument("--c3-only", action="store_true",
                     help="diagnostic: run only the full-size 3D legs and print their results")
-    ap.add_argument("--paper-tables", action="store_true",
-                    help="run only the paper's conforming experiments (Tables GS1, SCMS1, "
-                         "HYB3 (a)) and print the counts beside the printed ones")
+    ap.add_argument("--paper-tables", nargs="?", const=",".join(PAPER_TABLES), default=None,
+                    metavar="T1,T2",
+                    help="run only the paper's L-shape and Fichera experiments (Tables GS1, "
+                         "SCMS1, SCMS2, HYB3a; default all) and print the counts beside the "
+                         "printed ones")
     ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy MIB MiB device to device (counter calibration)")
@@ -453,7 +481,12 @@ def main():
         return
 
     if args.paper_tables:
-        print(json.dumps(paper_tables(igamg, torch, workloads)))
+        tabs = tuple(t for t in args.paper_tables.split(",") if t)
+        bad = [t for t in tabs if t not in PAPER_TABLES]
+        if bad:
+            print("unknown table(s) %s; choose from %s" % (bad, PAPER_TABLES), file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(paper_tables(igamg, torch, workloads, tables=tabs)))
         return
 
     if args.c3_only:
