@@ -81,7 +81,15 @@ struct GsTile {
   long long off;     // patch offset in the level vector
   int nx, ny;        // patch tensor extents
   int i0[2];         // first unknown of the tile
-  int cx_off, cx_n;  // cross-patch couplings of the tile rows in the level's flat lists
+  // cross-patch couplings of the tile rows, in slots of the level's flat
+  // lists: cx_np passes of 64 slots (one per lane), cx_k entries per slot
+  // (entry k of the slot in lane l of pass q at cx_off + (q cx_k + k) 64 + l;
+  // padding: column -1), slot codes at cx_sl + 64 q + l (row | index of the
+  // slot in its row << 16 | slots of the row << 24, or -1); the slots of a
+  // row are consecutive lanes of one pass, at most cx_r of them
+  int cx_off, cx_k;
+  int cx_sl, cx_np;
+  int cx_r;
   int mr_off, mr_n;  // conforming: copies in other patches of the tile's owned glued
                      // unknowns (mirror writes, in the level's flat lists)
   long long pad_off; // lane-per-right-hand-side operator: the patch's offset in the

@@ -628,7 +628,10 @@ __global__ __launch_bounds__(256) void iface_kernel(long long n, int nb_plain,
 
 // ---------------------------------------------------------------------------
 // volume operator, 2D, sum factorization on a TE x TE element tile:
-// r += alpha * A_vol u (atomic accumulation of the tile's outputs).  The
+// r += alpha * A_vol u.  The tiles of one launch form one colour class whose
+// output windows (TE + P unknowns per direction) do not overlap, so every
+// output is read, added to and written by one thread, and the classes follow
+// each other in a fixed order: the sums do not depend on scheduling.  The
 // geometry (metric) is evaluated in float64 and rounded to T.
 // grid.x = right-hand side (the batch shares the tile's tables in cache),
 // grid.y = tile.
@@ -780,14 +783,15 @@ __global__ __launch_bounds__(256) void vol2d_kernel(const OpTile2 *tiles,
         }
       }
       long long t = off + (long long)(ey0 + rr) * nx + ex0 + cc;
-      if (mask[t]) unsafeAtomicAdd(&rz[t], alpha * y);
+      if (mask[t]) rz[t] += alpha * y;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // volume operator, 3D, sum factorization on a TE^3 element tile:
-// r += alpha * A_vol u (atomic accumulation of the tile's outputs).  Stages
+// r += alpha * A_vol u, one colour class of tiles with disjoint output
+// windows per launch (as in 2D: a fixed order of the sums).  Stages
 // (all in LDS): x-, y-, z-contractions of the u window with the value and
 // derivative tables give the parameter gradient at the tile's Gauss points;
 // the metric w |det J| J^-1 J^-T (float64 from the trilinear corners, rounded
@@ -965,7 +969,7 @@ __global__ __launch_bounds__(256) void vol3d_kernel(const VolTile *tiles, const 
       }
     }
     const long long t = off + ((long long)(tl.e0[2] + rz) * ny + tl.e0[1] + ry) * nx + tl.e0[0] + rx;
-    if (mask[t]) unsafeAtomicAdd(&r[t], alpha * y);
+    if (mask[t]) r[t] += alpha * y;
   }
 }
 
@@ -995,6 +999,60 @@ __global__ void glue_first_kernel(int ng, const int *ptr, const int *idx, T *y, 
   for (int e = ptr[g]; e < ptr[g + 1]; ++e) s += y[idx[e]];
   y[idx[ptr[g]]] = s;
   for (int e = ptr[g] + 1; e < ptr[g + 1]; ++e) y[idx[e]] = (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-patch couplings of a Gauss-Seidel tile: sum_j a_ij u_j over the
+// neighbouring patches' columns for every coupled row of the tile, in the
+// slot layout of GsTile.  Every lane sums its slot's entries in order; the
+// first lane of each row adds the sums of the row's slots in lane order
+// (register shuffles) and hands the total to `apply(row, totals)` -- one
+// call per row, so no two lanes update one row and the sums do not depend on
+// scheduling.  NR right-hand sides (uz[r]) share the entry loads.  Called by
+// all 64 lanes of a wavefront.
+// ---------------------------------------------------------------------------
+template <typename T, int NR, typename Apply>
+__device__ __forceinline__ void tile_cross(const GsTile &tl, const int *__restrict__ slots,
+                                           const int *__restrict__ cols,
+                                           const T *__restrict__ vals, const T *const *uz,
+                                           int lane, Apply apply) {
+  for (int q = 0; q < tl.cx_np; ++q) {
+    const int code = slots[tl.cx_sl + 64 * q + lane];
+    T acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = (T)0;
+    const long long base = tl.cx_off + (long long)q * tl.cx_k * 64 + lane;
+    for (int k0 = 0; k0 < tl.cx_k; k0 += 8) {
+      int cc[8];
+      T cv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bool ok = k0 + j < tl.cx_k;
+        cc[j] = ok ? cols[base + 64 * (k0 + j)] : -1;
+        cv[j] = ok ? vals[base + 64 * (k0 + j)] : (T)0;
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        T cu[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cu[j] = cc[j] >= 0 ? uz[r][cc[j]] : (T)0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[r] += cv[j] * cu[j];
+      }
+    }
+    const int ns = (code >= 0 && ((code >> 16) & 0xff) == 0) ? code >> 24 : 0;
+    T tot[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tot[r] = (T)0;
+    for (int s = 0; s < tl.cx_r; ++s) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const T v = __shfl(acc[r], (lane + s) & 63);
+        if (s < ns) tot[r] += v;
+      }
+    }
+    if (ns > 0) apply(code & 0xffff, tot);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1048,28 +1106,17 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   const int ax = (grp & 1) * Q1, ay = (grp >> 1) * Q1;
   // Prologue, per right-hand side: every global load that does not depend on
   // another one is issued before the first wait (u window, f, 1/a_ii -- zero
-  // on Dirichlet unknowns by construction -- and the cross-coupling lists);
-  // u at the cross columns follows in a second round.  Right-hand sides past
-  // the batch run on column 0 and store nothing.
+  // on Dirichlet unknowns by construction); the cross-patch couplings follow
+  // for all NR right-hand sides at once.  Right-hand sides past the batch run
+  // on column 0 and store nothing.
   constexpr int NW = (W * W + 63) / 64, NT = (TT * TT + 63) / 64;
-  const int ncx = tl.cx_n < 64 * 8 ? tl.cx_n : 64 * 8;
-  int cl[8], cc[8];
-  T cv[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int e = lane + 64 * j;
-    const bool ok = e < ncx;
-    cl[j] = ok ? cx_li[tl.cx_off + e] : -1;
-    cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
-    cv[j] = ok ? cx_val[tl.cx_off + e] : (T)0;
-  }
   for (int r = 0; r < NR; ++r) {
     const int z = zw + r < nrhs ? zw + r : 0;
     const T *fz = f + (long long)z * vs;
     const T *uz = u + (long long)z * vs;
     T *sU = sUa[wid][r];
     T2 *sBD = sBDa[wid][r];
-    T wv[NW], fv[NT], dv[NT], cu[8];
+    T wv[NW], fv[NT], dv[NT];
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
       const int i = lane + 64 * j;
@@ -1087,8 +1134,6 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
       dv[j] = ok ? invd[t] : (T)0;
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) cu[j] = uz[cc[j]];
-#pragma unroll
     for (int j = 0; j < NW; ++j)
       if (lane + 64 * j < W * W) sU[lane + 64 * j] = wv[j];
 #pragma unroll
@@ -1099,16 +1144,18 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
         bd.y = dv[j];
         sBD[lane + 64 * j] = bd;
       }
-    // a single wavefront: its LDS stores land in program order, so the
-    // corrections below see the pairs written above
-    __builtin_amdgcn_wave_barrier();
+  }
+  // f minus the cross-patch couplings (a single wavefront: its LDS stores
+  // land in program order, so the corrections see the pairs written above)
+  __builtin_amdgcn_wave_barrier();
+  {
+    const T *uzs[NR];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (cl[j] >= 0) unsafeAtomicAdd(&sBD[cl[j]].x, -cv[j] * cu[j]);
-    // tiles with more than 512 cross couplings
-    for (int e = 64 * 8 + lane; e < tl.cx_n; e += 64)
-      unsafeAtomicAdd(&sBD[cx_li[tl.cx_off + e]].x,
-                      -cx_val[tl.cx_off + e] * uz[cx_col[tl.cx_off + e]]);
+    for (int r = 0; r < NR; ++r) uzs[r] = u + (long long)(zw + r < nrhs ? zw + r : 0) * vs;
+    tile_cross<T, NR>(tl, cx_li, cx_col, cx_val, uzs, lane, [&](int row, const T *tot) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sBDa[wid][r][row].x -= tot[r];
+    });
   }
   if (wid == 0)
     for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
@@ -1253,34 +1300,13 @@ __global__ __launch_bounds__(256) void sp2d_kernel(const GsTile *tiles, int ntil
   }
   for (int i = tid; i < RB * NT; i += 256) sX[i / NT][i % NT] = (T)0;
   __syncthreads();
-  // cross-patch couplings: one wave per right-hand side, so the additions
-  // into a row come in a fixed order
-  // Up to 512 couplings per wave are loaded in one batch (indices and values,
-  // then the u gathers) before the additions, in the order e = lane + 64 j.
+  // cross-patch couplings: one wave per right-hand side (after the zeroing
+  // above: a block barrier), one update per row
   const int wave = tid >> 6, lane = tid & 63;
   for (int z = wave; z < nz; z += 4) {
-    const T *uz = u + (long long)(z0 + z) * vs;
-    const int ncx = tl.cx_n < 64 * 8 ? tl.cx_n : 64 * 8;
-    int cl[8], cc[8];
-    T cv[8], cu[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int e = lane + 64 * j;
-      const bool ok = e < ncx;
-      cl[j] = ok ? cx_li[tl.cx_off + e] : -1;
-      cc[j] = ok ? cx_col[tl.cx_off + e] : 0;
-      cv[j] = ok ? cx_val[tl.cx_off + e] : (T)0;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) cu[j] = uz[cc[j]];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (cl[j] >= 0) unsafeAtomicAdd(&sX[z][cl[j]], cv[j] * cu[j]);
-    // tiles with more than 512 cross couplings (not produced by the layouts here)
-    for (int e = 64 * 8 + lane; e < tl.cx_n; e += 64) {
-      const int q = tl.cx_off + e;
-      unsafeAtomicAdd(&sX[z][cx_li[q]], cx_val[q] * uz[cx_col[q]]);
-    }
+    const T *uzs[1] = {u + (long long)(z0 + z) * vs};
+    tile_cross<T, 1>(tl, cx_li, cx_col, cx_val, uzs, lane,
+                     [&](int row, const T *tot) { sX[z][row] += tot[0]; });
   }
   const int g = tid >> 4, l16 = tid & 15;
   int soff[C];
@@ -2977,25 +3003,27 @@ static void launch_vol2d(Context &c, LevelData &L, const T *u, T *r, T alpha, in
 }
 
 template <typename T, int P>
-static void launch_vol3d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
-  vol3d_kernel<T, P, VOL3D_TILE><<<dim3(L.n_vtiles, nrhs), 256, 0, c.stream>>>(
-      L.d_vtiles, L.d_pd, L.d_tabB, L.d_tabD, c.gr, u, r, L.d_mask, alpha, L.Ntorn);
+static void launch_vol3d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs, int first,
+                         int count) {
+  vol3d_kernel<T, P, VOL3D_TILE><<<dim3(count, nrhs), 256, 0, c.stream>>>(
+      L.d_vtiles + first, L.d_pd, L.d_tabB, L.d_tabD, c.gr, u, r, L.d_mask, alpha, L.Ntorn);
 }
 
 template <typename T>
 void k_vol_apply(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs) {
   TimeScope ts(c, "vol_apply", L.l);
+  // one launch per (patch degree, colour class of tiles): the outputs of one
+  // launch are disjoint, the classes run in a fixed order on the stream
   if (c.d == 3) {
-    switch (c.p) {
-      case 1: launch_vol3d<T, 1>(c, L, u, r, alpha, nrhs); break;
-      case 2: launch_vol3d<T, 2>(c, L, u, r, alpha, nrhs); break;
-      case 3: launch_vol3d<T, 3>(c, L, u, r, alpha, nrhs); break;
-      case 4: launch_vol3d<T, 4>(c, L, u, r, alpha, nrhs); break;
-      default: fail(IGAMG_EUNSUPPORTED, "3D degree out of range 1..4");
-    }
+    for (const auto &g : L.vgroups) switch (g[0]) {
+        case 1: launch_vol3d<T, 1>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+        case 2: launch_vol3d<T, 2>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+        case 3: launch_vol3d<T, 3>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+        case 4: launch_vol3d<T, 4>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;
+        default: fail(IGAMG_EUNSUPPORTED, "3D degree out of range 1..4");
+      }
     return;
   }
-  // one launch per patch degree (tiles grouped by degree; disjoint outputs)
   for (const auto &g : L.vgroups) {
     switch (g[0]) {
       case 1: launch_vol2d<T, 1, 8>(c, L, u, r, alpha, nrhs, g[1], g[2]); break;

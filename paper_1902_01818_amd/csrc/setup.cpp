@@ -1357,6 +1357,82 @@ static void build_gs3(Context &c, LevelData &L, bool keep64) {
   L.d_mr_dst = c.arena.upload(mdst, c.stream);
 }
 
+// Cross-patch couplings of one Gauss-Seidel tile (entries (row, column,
+// value), rows ascending) in the slot layout of GsTile: a row's couplings are
+// cut into slots of K entries in consecutive lanes of one pass, so that every
+// lane sums its slot in order and the row's first lane adds its slots' sums
+// in lane order.  K minimizes passes x (K + slots per row).
+static void pack_cross(const std::vector<int> &rl, const std::vector<int> &rc,
+                       const std::vector<double> &rv, GsTile &tl, std::vector<int> &slots,
+                       std::vector<int> &col, std::vector<double> &val) {
+  tl.cx_off = (int)col.size();
+  tl.cx_sl = (int)slots.size();
+  tl.cx_k = tl.cx_np = tl.cx_r = 0;
+  if (rl.empty()) return;
+  std::vector<std::array<int, 3>> rows;  // row, first entry, count
+  for (size_t i = 0; i < rl.size();) {
+    size_t j = i;
+    while (j < rl.size() && rl[j] == rl[i]) ++j;
+    if (!rows.empty() && rows.back()[0] >= rl[i]) fail(IGAMG_EUNSUPPORTED, "cross couplings out of row order");
+    rows.push_back({rl[i], (int)i, (int)(j - i)});
+    i = j;
+  }
+  int maxc = 0;
+  for (const auto &r : rows) maxc = std::max(maxc, r[2]);
+  auto plan = [&](int K, int &np, int &mr) {
+    np = 0;
+    mr = 0;
+    int used = 64;
+    for (const auto &r : rows) {
+      const int ns = (r[2] + K - 1) / K;
+      mr = std::max(mr, ns);
+      if (used + ns > 64) {
+        ++np;
+        used = 0;
+      }
+      used += ns;
+    }
+  };
+  int K = maxc;
+  long long best = -1;
+  for (int k = (maxc + 63) / 64; k <= maxc; ++k) {
+    int np, mr;
+    plan(k, np, mr);
+    const long long cost = (long long)np * (k + mr);
+    if (best < 0 || cost < best) {
+      best = cost;
+      K = k;
+    }
+  }
+  int np, mr;
+  plan(K, np, mr);
+  tl.cx_k = K;
+  tl.cx_np = np;
+  tl.cx_r = mr;
+  const size_t s0 = slots.size(), e0 = col.size();
+  slots.resize(s0 + (size_t)np * 64, -1);
+  col.resize(e0 + (size_t)np * K * 64, -1);
+  val.resize(col.size(), 0.0);
+  int q = -1, used = 64;
+  for (const auto &r : rows) {
+    const int ns = (r[2] + K - 1) / K;
+    if (used + ns > 64) {
+      ++q;
+      used = 0;
+    }
+    for (int sl = 0; sl < ns; ++sl) {
+      const int lane = used + sl;
+      slots[s0 + (size_t)q * 64 + lane] = r[0] | (sl << 16) | (ns << 24);
+      for (int k = 0; k < K && sl * K + k < r[2]; ++k) {
+        const size_t at = e0 + ((size_t)q * K + k) * 64 + lane;
+        col[at] = rc[r[1] + sl * K + k];
+        val[at] = rv[r[1] + sl * K + k];
+      }
+    }
+    used += ns;
+  }
+}
+
 static void build_gs(Context &c, LevelData &L, bool keep64) {
   const int d = c.d, T = c.opt.gs_tile;
   if (T != 2 * (c.p + 1)) fail(IGAMG_EUNSUPPORTED, "Gauss-Seidel tiles of width 2(p+1) only");
@@ -1381,25 +1457,32 @@ static void build_gs(Context &c, LevelData &L, bool keep64) {
           for (int b0 = 0; b0 < nb[0]; ++b0) {
             int pr = (b0 & 1) | ((b1 & 1) << 1);
             if (pr != par) continue;
-            GsTile tl{pt.off, pt.n[0],          pt.n[1], {b0 * T, b1 * T}, (int)li.size(), 0,
-                      (int)mli.size(), 0};
+            GsTile tl{};
+            tl.off = pt.off;
+            tl.nx = pt.n[0];
+            tl.ny = pt.n[1];
+            tl.i0[0] = b0 * T;
+            tl.i0[1] = b1 * T;
+            tl.mr_off = (int)mli.size();
             // cross-patch couplings of the tile rows; conforming: the mirror
             // copies of the owned glued unknowns
+            std::vector<int> rl, rc;
+            std::vector<double> rv;
             for (int iy = b1 * T; iy < std::min(pt.n[1], (b1 + 1) * T); ++iy)
               for (int ix = b0 * T; ix < std::min(pt.n[0], (b0 + 1) * T); ++ix) {
                 const long long t = pt.off + (long long)iy * pt.n[0] + ix;
                 const int lt = (iy - b1 * T) * T + (ix - b0 * T);
                 for_cross(t, [&](int cc, double v) {
-                  li.push_back(lt);
-                  col.push_back(cc);
-                  val.push_back(v);
+                  rl.push_back(lt);
+                  rc.push_back(cc);
+                  rv.push_back(v);
                 });
                 for_mirror(t, [&](int dst) {
                   mli.push_back(lt);
                   mdst.push_back(dst);
                 });
               }
-            tl.cx_n = (int)li.size() - tl.cx_off;
+            pack_cross(rl, rc, rv, tl, li, col, val);
             tl.mr_n = (int)mli.size() - tl.mr_off;
             tiles.push_back(tl);
           }
@@ -1436,8 +1519,16 @@ static void build_gs(Context &c, LevelData &L, bool keep64) {
       }
       for (int y0 = 0; y0 < pt.n[1]; y0 += 4)
         for (int x = 0; x < pt.n[0]; x += bx)
-          for (int y = y0; y < std::min(pt.n[1], y0 + 4); ++y)
-            sp.push_back(GsTile{pt.off, pt.n[0], pt.n[1], {x, y}, 0, 0, 0, 0, ptot});
+          for (int y = y0; y < std::min(pt.n[1], y0 + 4); ++y) {
+            GsTile g{};
+            g.off = pt.off;
+            g.nx = pt.n[0];
+            g.ny = pt.n[1];
+            g.i0[0] = x;
+            g.i0[1] = y;
+            g.pad_off = ptot;
+            sp.push_back(g);
+          }
       ptot += (long long)(pt.n[0] + 2 * c.p) * (pt.n[1] + 2 * c.p);
     }
     L.pad_tot = ptot;
@@ -1804,19 +1895,30 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
       L.d_has_if = c.arena.upload(has, c.stream);
       L.d_if_rows = c.arena.upload(rows, c.stream);
     }
-    // volume tiles, grouped by patch degree (one launch per degree)
+    // volume tiles, grouped by patch degree and colour class (one launch
+    // each).  A tile of TE elements writes TE + p unknowns per direction;
+    // tiles of one class lie m = floor((TE + p - 1) / TE) + 1 tiles apart per
+    // direction (TE + p - 1 < m TE), so their output windows are disjoint
     std::vector<VolTile> vt;
     L.vgroups.clear();
     for (int pdeg = 1; pdeg <= MAXP; ++pdeg) {
-      const int first = (int)vt.size();
       const int TE = c.d == 2 ? vol_tile_2d(pdeg) : VOL3D_TILE;
-      for (int k = 0; k < c.K; ++k) {
-        if (L.pd[k].p != pdeg) continue;
-        for (int e2 = 0; e2 < (c.d == 3 ? L.pd[k].nel[2] : 1); e2 += TE)
-          for (int e1 = 0; e1 < L.pd[k].nel[1]; e1 += TE)
-            for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) vt.push_back(VolTile{k, {e0, e1, e2}});
+      const int m = (TE + pdeg - 1) / TE + 1;
+      int ncls = 1;
+      for (int g = 0; g < c.d; ++g) ncls *= m;
+      for (int cls = 0; cls < ncls; ++cls) {
+        const int first = (int)vt.size();
+        for (int k = 0; k < c.K; ++k) {
+          if (L.pd[k].p != pdeg) continue;
+          for (int e2 = 0; e2 < (c.d == 3 ? L.pd[k].nel[2] : 1); e2 += TE)
+            for (int e1 = 0; e1 < L.pd[k].nel[1]; e1 += TE)
+              for (int e0 = 0; e0 < L.pd[k].nel[0]; e0 += TE) {
+                const int key = (e0 / TE) % m + m * ((e1 / TE) % m + m * ((e2 / TE) % m));
+                if (key == cls) vt.push_back(VolTile{k, {e0, e1, e2}});
+              }
+        }
+        if ((int)vt.size() > first) L.vgroups.push_back({pdeg, first, (int)vt.size() - first});
       }
-      if ((int)vt.size() > first) L.vgroups.push_back({pdeg, first, (int)vt.size() - first});
     }
     L.n_vtiles = (int)vt.size();
     L.d_vtiles = c.arena.upload(vt, c.stream);
