@@ -130,6 +130,10 @@ typedef struct {
   int max_rhs;        /* right-hand sides processed together by one call (work-vector
                          capacity, 0 = 1); larger nrhs are split into batches of max_rhs */
   int operator_apply; /* IGAMG_APPLY_* */
+  int graphs;         /* 1 = replay the outer iteration's preconditioner cycle (one per
+                         residual vector and batch size) from a HIP graph captured at
+                         its second use (the first runs launch by launch); 0 = launch
+                         kernel by kernel.  Ignored while timing is on */
 } igamg_options;
 
 typedef struct {
@@ -145,7 +149,7 @@ typedef struct {
 typedef struct igamg_ctx igamg_ctx;
 
 /* Fill *o with the defaults (SIPG, hybrid, V(1,1), tau 0.25, delta 0.1, FP64, PCG,
- * one right-hand side per batch, operator applies IGAMG_APPLY_AUTO). */
+ * one right-hand side per batch, operator applies IGAMG_APPLY_AUTO, no graphs). */
 void igamg_default_options(igamg_options *o);
 
 /* Host only, no GPU work: device bytes igamg_setup will allocate for this
@@ -288,7 +292,9 @@ int igamg_problem_size(const igamg_patches *patches, int degree, const igamg_opt
  * buffer holds the request's footprint (igamg_footprint of its problem plus
  * its right-hand side and solution); the request then builds its hierarchy
  * inside that block (setup, as igamg_setup), solves (as igamg_solve with one
- * right-hand side), copies the solution to the host and returns the block.
+ * right-hand side, its preconditioner cycle replayed from a captured HIP
+ * graph: option graphs = 1), copies the solution to the host and returns the
+ * block.
  * Requests of different patch layouts, degrees and sizes therefore run
  * concurrently on the device, and requests arriving while others run start
  * as slots and memory free up.  The method per request is the one of
@@ -320,7 +326,7 @@ typedef struct {
 int igamg_server_create(const igamg_server_config *cfg, igamg_server **out);
 
 /* Queue one request: problem as for igamg_setup (host arrays, copied),
- * options (max_rhs and timing are ignored; precision must be IGAMG_FP64,
+ * options (max_rhs, timing and graphs are ignored; precision must be IGAMG_FP64,
  * float32 requests return IGAMG_EUNSUPPORTED), rhs = host float64 array of
  * n_dofs values (copied; n_dofs must equal igamg_problem_size's N), tol and
  * maxit as for igamg_solve.  Returns at once with *request_id.  Input errors

@@ -140,6 +140,7 @@ void igamg_default_options(igamg_options *o) {
   o->timing = 0;
   o->max_rhs = 0;
   o->operator_apply = IGAMG_APPLY_AUTO;
+  o->graphs = 0;
 }
 
 int igamg_footprint(const igamg_patches *patches, int degree, const igamg_options *o, int nrhs,

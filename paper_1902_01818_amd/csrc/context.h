@@ -286,6 +286,17 @@ struct Context {
   int *h_active = nullptr;       // pinned host mirror (written only after a stream sync)
   bool own_pinned = true;        // h_scal / h_active allocated by the context
   hipStream_t stream = nullptr;
+  // preconditioner cycles replayed from HIP graphs (option graphs): one per
+  // (residual vector, batch size); uses counts first runs, captured at the
+  // second on a private stream (the caller's may be the null stream)
+  struct CycleGraph {
+    const double *r = nullptr;
+    int nb = 0;
+    int uses = 0;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<CycleGraph> graphs;
+  hipStream_t cap_stream = nullptr;
   int device = 0;  // HIP device the context was built on
   Arena arena;
   std::map<std::string, TimerFamily> timers;

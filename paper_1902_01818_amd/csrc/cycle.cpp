@@ -106,7 +106,7 @@ void set_cycle_rhs(Context &c, const double *x, int nb, bool zero_u) {
 
 // z = MG(L, r, 0) on the finest level (z = c.z).  In float64 z is the finest
 // iterate itself and must be zero on entry (the outer update clears it).
-void precondition(Context &c, const double *r, int nb) {
+void precondition_launches(Context &c, const double *r, int nb) {
   LevelData &L = c.lv.back();
   const long long nt = L.Ntorn;
   if (c.fp32()) {
@@ -124,6 +124,61 @@ void precondition(Context &c, const double *r, int nb) {
     L.a64.f = const_cast<double *>(r);
   mg<double>(c, (int)c.lv.size() - 1, nb);
   L.a64.f = f_saved;
+}
+
+// The same cycle as one graph launch (option graphs).  Its launches read
+// the device mask of active right-hand sides, so one graph serves every
+// iteration; pointers and the batch size are fixed in it, hence one graph
+// per (r, nb).  The first use runs launch by launch (one-time host work such
+// as kernel attributes happens there), the second is captured on the
+// context's private stream and replayed on c.stream from then on.  The
+// cycle issues kernels only (no memset, allocation or host wait).
+void precondition(Context &c, const double *r, int nb) {
+  if (!c.opt.graphs || c.opt.timing) {
+    precondition_launches(c, r, nb);
+    return;
+  }
+  Context::CycleGraph *g = nullptr;
+  for (auto &e : c.graphs)
+    if (e.r == r && e.nb == nb) g = &e;
+  if (!g) {
+    constexpr size_t MAX_GRAPHS = 8;
+    if (c.graphs.size() >= MAX_GRAPHS) {
+      precondition_launches(c, r, nb);
+      return;
+    }
+    c.graphs.push_back(Context::CycleGraph{r, nb, 0, nullptr});
+    g = &c.graphs.back();
+  }
+  if (g->exec) {
+    HIPCHK(hipGraphLaunch(g->exec, c.stream));
+    return;
+  }
+  if (++g->uses < 2) {
+    precondition_launches(c, r, nb);
+    return;
+  }
+  if (!c.cap_stream) HIPCHK(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+  hipStream_t user = c.stream;
+  c.stream = c.cap_stream;
+  HIPCHK(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    precondition_launches(c, r, nb);
+  } catch (...) {
+    c.stream = user;
+    if (hipStreamEndCapture(c.cap_stream, &graph) == hipSuccess && graph)
+      (void)hipGraphDestroy(graph);
+    throw;
+  }
+  c.stream = user;
+  HIPCHK(hipStreamEndCapture(c.cap_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(e);
+  g->exec = exec;
+  HIPCHK(hipGraphLaunch(exec, c.stream));
 }
 
 // q = A p on the finest level in the cycle arithmetic (float64 vectors in and

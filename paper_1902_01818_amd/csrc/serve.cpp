@@ -280,6 +280,7 @@ int igamg_server_submit(igamg_server *srv, const igamg_patches *patches, int deg
     igamg_options oo = *o;
     oo.max_rhs = 1;
     oo.timing = 0;
+    oo.graphs = 1;  // the preconditioner cycle of every request replays a captured graph
     size_t fp = igamg::estimate_footprint(patches, degree, &oo);
     fp += 2 * (size_t)n * sizeof(double) + (1u << 20);  // right-hand side, solution, slack
     auto r = std::make_unique<igamg::Request>();

@@ -143,6 +143,8 @@ Context::~Context() {
       (void)hipEventDestroy(pe.second);
     }
   }
+  for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (ev_scal) (void)hipEventDestroy(ev_scal);
   if (own_pinned && h_scal) (void)hipHostFree(h_scal);
   if (own_pinned && h_active) (void)hipHostFree(h_active);
@@ -1746,6 +1748,7 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
   if (c.opt.mu < 1) c.opt.mu = 1;
   if (c.opt.nu < 1) c.opt.nu = 1;
   if (c.opt.max_rhs < 0 || c.opt.max_rhs > 4096) fail(IGAMG_EINVAL, "max_rhs out of range 0..4096");
+  if (c.opt.graphs != 0 && c.opt.graphs != 1) fail(IGAMG_EINVAL, "graphs must be 0 or 1");
   c.nb = c.opt.max_rhs > 0 ? c.opt.max_rhs : 1;
   if (c.opt.discretization == IGAMG_SIPG && !(sigma > 0)) fail(IGAMG_EINVAL, "penalty must be positive");
   const bool use_gs = c.opt.smoother != IGAMG_SMOOTHER_SCMS;

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("outer", ctypes.c_int),
                 ("gs_tile", ctypes.c_int), ("coarse_min", ctypes.c_int),
                 ("timing", ctypes.c_int), ("max_rhs", ctypes.c_int),
-                ("operator_apply", ctypes.c_int)]
+                ("operator_apply", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -154,7 +154,7 @@ def _patches(corners, elems, degree=None):
 
 def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1, nu=1,
                  precision="fp64", outer="pcg", gs_tile=0, coarse_min=0, timing=False, max_rhs=0,
-                 operator_apply="auto"):
+                 operator_apply="auto", graphs=False):
     o = Options()
     _lib.igamg_default_options(ctypes.byref(o))
     o.discretization = CONFORMING if conforming else SIPG
@@ -167,6 +167,7 @@ def make_options(conforming=False, smoother="hybrid", tau=0.25, delta=0.1, mu=1,
     o.timing = 1 if timing else 0
     o.max_rhs = max_rhs
     o.operator_apply = APPLIES[operator_apply]
+    o.graphs = 1 if graphs else 0
     return o
 
 
