@@ -13,6 +13,7 @@
 // Every vector holds a batch of right-hand sides ([nrhs][Ntorn]).  The cycle
 // runs in the context's arithmetic T (float64 or float32); the outer
 // iteration, its residuals and the convergence test are float64 always.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -321,9 +322,11 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
       }
     } else if (c.opt.outer == IGAMG_OUTER_IR) {
       // iterative refinement: inner PCG in the cycle arithmetic on the
-      // float64 residual, to a fixed relative reduction; x += d; the float64
-      // residual decides convergence
-      constexpr double INNER_REDUCTION = 1e-4;
+      // float64 residual, to a fixed relative reduction or, when that is
+      // more than the tolerance still needs, to half the remaining gap
+      // (||r_in|| <= max(1e-4 ||r||, tol ||f|| / 2): the last step does not
+      // over-solve); x += d; the float64 residual decides convergence
+      constexpr double INNER_REDUCTION = 1e-4, LAST_STEP_MARGIN = 0.5;
       double *x_out = c.x, *r_out = c.rr;
       std::vector<int> outer_active(c.h_active, c.h_active + nb);
       std::vector<int> total(nb, 0);
@@ -349,7 +352,8 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
             if (!c.h_active[j]) continue;
             ++total[j];
             const double rin = std::sqrt(c.h_scal[(size_t)j * S_COUNT + S_RR]);
-            if (rin <= INNER_REDUCTION * ref[j] || total[j] >= maxit) {
+            const double target = std::max(INNER_REDUCTION * ref[j], LAST_STEP_MARGIN * tol * nf[j]);
+            if (rin <= target || total[j] >= maxit) {
               c.h_active[j] = 0;
               --inner_active;
               changed = true;
