@@ -114,6 +114,7 @@ struct LevelArrays {
   T *wscratch2 = nullptr;                      // second intermediate of the staged form
   Fd2Item<T> *fd[2] = {nullptr, nullptr};      // patch interiors: forward, backward
   FdGemm<T> *fg[6] = {};                      // the same as product stages (2D: 4, 3D: 6)
+  FdWide<T> *fw[4] = {};                       // 2D stages over a whole batch (wide tiles)
   T *lam_xy = nullptr;                         // 3D: lam_y[j] + lam_x[i] per patch (y-major)
   T *x_val = nullptr;                          // 3D: cross-patch couplings (CSR of coupled rows)
   T *xsum = nullptr;                           // 3D: sum of a colour's cross couplings per row
@@ -211,6 +212,7 @@ struct LevelData {
   int n_fd = 0;
   int fd_rows = 0, fd_K1 = 0, fd_N = 0;
   int fg_tiles = 0;       // 64 x 64 output tiles of the largest stage item
+  int fw_wide = 0, fw_cat = 0;  // 2D batch stages: largest wide and per-right-hand-side extents
   int fg_n[6] = {}, fg_t[6] = {};  // 3D: items and largest tile count of each stage
   long long fd_work = 0;  // sum over patches of my * mx * ceil(my / 16) (fused-form re-reads)
   long long wscratch_n = 0;

@@ -143,6 +143,25 @@ struct FdGemm {
   int mode;
 };
 
+// One product stage of the 2D fast diagonalization with the right-hand sides
+// of a batch concatenated along the per-right-hand-side dimension:
+//   left:  C_z[w][n] = sum_k S[w][k] X_z[k][n]    (X_z[k][n] at X + z x_z + k x_r + n)
+//   right: C_z[i][w] = sum_k X_z[i][k] S[w][k]    (X_z[i][k] at X + z x_z + i x_r + k)
+// S (the shared 1D factor, S[w][k] at S + w s_r + k) spans the wide dimension
+// (`wide` <= 320 entries, one block covers all of it); the concatenated
+// dimension runs over z * catn + (n or i).  C at C + z c_z + row c_r + col;
+// mode 0: C = v, 1: C = v / (sigma + lam_r[row] + lam_c[col]), 2: C += scale v.
+template <typename T>
+struct FdWide {
+  const T *S, *X;
+  T *C;
+  long long s_r, x_r, x_z, c_r, c_z;
+  int wide, catn, K;
+  const T *lam_r, *lam_c;
+  T sigma, scale;
+  int mode;
+};
+
 // Interface piece of the additive smoother (eq. Ldef): dense inverse of P^T A P.
 struct PieceDev {
   long long inv_off;  // offset of the n x n inverse in the value array

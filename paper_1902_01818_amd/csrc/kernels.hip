@@ -2271,6 +2271,166 @@ __global__ __launch_bounds__(256) void fdg_kernel(const FdGemm<T> *items) {
 }
 
 // ---------------------------------------------------------------------------
+// One product stage of the 2D fast diagonalization over a whole batch
+// (FdWide): the right-hand sides are concatenated along the dimension that
+// belongs to them, so it splits into exact 64-wide tiles, and a block covers
+// the whole wide dimension of the shared factor S (NT MFMA tiles of 16, NT
+// even, rows past the factor zero in LDS).  Only the wide dimension (to 32)
+// and K (to 16) are padded (260 unknowns: 288 x 272 computed, where 64 x 64
+// tiles of every right-hand side's product would compute 320 x 320).  Wave w owns the 16 concatenated indices
+// 16w..16w+15 of the block and all wide tiles; a k-step reads one fragment
+// of X and one of S per wide tile.  K streams through LDS in chunks of KC
+// (both operands k-contiguous), the next chunk held in registers.
+//   left:  MFMA A = S rows (wide), B = X columns (concatenated);
+//   right: MFMA A = X rows (concatenated), B = S rows read as columns (wide);
+// so the outputs' 16 lanes of a row run along the contiguous index of C.
+// grid.x = 64-wide tile of the concatenated dimension, grid.y = item.
+// ---------------------------------------------------------------------------
+template <typename T, bool BF, bool RIGHT, int NT>
+__global__ __launch_bounds__(256) void fdw_kernel(const FdWide<T> *items, int nrhs) {
+  using A4 = typename MfAcc<T>::type;
+  using ST = typename std::conditional<BF, __bf16, T>::type;
+  constexpr int KC = BF ? 32 : 16, KS = MfK<BF>::KS;
+  constexpr int LDK = BF ? KC + 8 : KC + 2;
+  constexpr int WT = 16 * NT;                     // wide rows held (zero past g.wide)
+  constexpr int NLS = WT * KC / 256, NLX = 64 * KC / 256;
+  constexpr int RS = 256 / KC;                    // S rows (right: X rows) per load round
+  __shared__ ST sS[WT * LDK], sX[64 * LDK];
+  const FdWide<T> g = items[blockIdx.y];
+  const int ncat = nrhs * g.catn;
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= ncat) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, c = lane & 15, q = lane >> 4;
+  // global loads, branch-free: clamped addresses, out-of-range values zeroed.
+  // S entry (row tid / KC + RS x, k tid % KC); X entry: left, column
+  // tid % 64 (one per thread) and k tid / 64 + 4 x; right, row tid / KC +
+  // RS x and k tid % KC
+  const int ks = tid % KC;
+  const T *sbase[NLS];
+  bool sok[NLS];
+#pragma unroll
+  for (int x = 0; x < NLS; ++x) {
+    const int row = tid / KC + RS * x;
+    sok[x] = row < g.wide;
+    sbase[x] = g.S + (long long)min(row, g.wide - 1) * g.s_r;
+  }
+  const T *xbase[NLX];
+  bool xok[NLX];
+#pragma unroll
+  for (int x = 0; x < NLX; ++x) {
+    const int cc = RIGHT ? tid / KC + RS * x : (tid & 63);
+    const int cg = min(c0 + cc, ncat - 1);
+    xok[x] = c0 + cc < ncat;
+    const int z = cg / g.catn, n = cg - z * g.catn;
+    xbase[x] = g.X + (long long)z * g.x_z + (RIGHT ? (long long)n * g.x_r : (long long)n);
+  }
+  // raw values of the next chunk (zeroed out of range when stored to LDS,
+  // so that no use of a load sits before the current chunk's products)
+  T ps[NLS], px[NLX];
+  auto gload = [&](int k0) {
+    const int kSc = min(k0 + ks, g.K - 1);
+#pragma unroll
+    for (int x = 0; x < NLS; ++x) ps[x] = sbase[x][kSc];
+#pragma unroll
+    for (int x = 0; x < NLX; ++x) {
+      const int kx = RIGHT ? k0 + ks : k0 + (tid >> 6) + 4 * x;
+      const int kxc = min(kx, g.K - 1);
+      px[x] = RIGHT ? xbase[x][kxc] : xbase[x][(long long)kxc * g.x_r];
+    }
+  };
+  A4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = A4{0, 0, 0, 0};
+  gload(0);
+  for (int k0 = 0; k0 < g.K; k0 += KC) {
+    __syncthreads();
+    const bool kokS = k0 + ks < g.K;
+#pragma unroll
+    for (int x = 0; x < NLS; ++x)
+      sS[(tid / KC + RS * x) * LDK + ks] = (ST)((sok[x] && kokS) ? ps[x] : (T)0);
+#pragma unroll
+    for (int x = 0; x < NLX; ++x) {
+      const int cc = RIGHT ? tid / KC + RS * x : (tid & 63);
+      const int kk = RIGHT ? ks : (tid >> 6) + 4 * x;
+      sX[cc * LDK + kk] = (ST)((xok[x] && k0 + kk < g.K) ? px[x] : (T)0);
+    }
+    __syncthreads();
+    if (k0 + KC < g.K) gload(k0 + KC);
+#pragma unroll
+    for (int k = 0; k < KC; k += KS) {
+      if constexpr (!BF) {
+        const T xf = sX[(16 * w + c) * LDK + k + q];
+        T sf[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sf[t] = sS[(16 * t + c) * LDK + k + q];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if constexpr (sizeof(T) == 8)
+            acc[t] = RIGHT ? __builtin_amdgcn_mfma_f64_16x16x4f64(xf, sf[t], acc[t], 0, 0, 0)
+                           : __builtin_amdgcn_mfma_f64_16x16x4f64(sf[t], xf, acc[t], 0, 0, 0);
+          else
+            acc[t] = RIGHT ? __builtin_amdgcn_mfma_f32_16x16x4f32(xf, sf[t], acc[t], 0, 0, 0)
+                           : __builtin_amdgcn_mfma_f32_16x16x4f32(sf[t], xf, acc[t], 0, 0, 0);
+        }
+      } else {
+        const mf_b8 xf = *(const mf_b8 *)&sX[(16 * w + c) * LDK + k + 8 * q];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const mf_b8 sf = *(const mf_b8 *)&sS[(16 * t + c) * LDK + k + 8 * q];
+          acc[t] = RIGHT ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(xf, sf, acc[t], 0, 0, 0)
+                         : __builtin_amdgcn_mfma_f32_16x16x32_bf16(sf, xf, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // epilogue: accumulator (t, r) of lane (c, q) holds MFMA row mf_row(q, r)
+  // and column c of tile t; the concatenated index of a lane does not
+  // depend on t (left: column c; right: row mf_row(q, r))
+  if constexpr (!RIGHT) {
+    const int cg = c0 + 16 * w + c;
+    if (cg >= ncat) return;
+    const int z = cg / g.catn, n = cg - z * g.catn;
+    T *cb = g.C + (long long)z * g.c_z + n;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int wide = 16 * t + mf_row<T>(q, r);
+        if (wide >= g.wide) continue;
+        T *o = cb + (long long)wide * g.c_r;
+        const T v = acc[t][r];
+        if (g.mode == 0)
+          *o = v;
+        else if (g.mode == 1)
+          *o = v / (g.sigma + g.lam_r[wide] + g.lam_c[n]);
+        else
+          *o += g.scale * v;
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cg = c0 + 16 * w + mf_row<T>(q, r);
+      if (cg >= ncat) continue;
+      const int z = cg / g.catn, n = cg - z * g.catn;
+      T *cb = g.C + (long long)z * g.c_z + (long long)n * g.c_r;
+      const T lr = g.mode == 1 ? g.sigma + g.lam_r[n] : (T)0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int wide = 16 * t + c;
+        if (wide >= g.wide) continue;
+        const T v = acc[t][r];
+        if (g.mode == 0)
+          cb[wide] = v;
+        else if (g.mode == 1)
+          cb[wide] = v / (lr + g.lam_c[wide]);
+        else
+          cb[wide] += g.scale * v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Dense solves with stored symmetric inverses: a block of 1024 threads owns 64
 // rows; wavefront w sums the columns j = w (mod 16) with lane = row, so the
 // 64 lanes read 64 consecutive entries of column j (= row j, by symmetry);
@@ -3313,6 +3473,36 @@ static void scms_staged(Context &c, LevelData &L, int nrhs) {
     fdg_kernel<T, BF><<<grid, 256, 0, c.stream>>>(L.arr<T>().fg[st]);
 }
 
+// the four stages with the batch concatenated (FdWide): left, right, left, right
+template <typename T, bool BF, int NT>
+static void launch_fdw(Context &c, LevelData &L, int nrhs) {
+  const dim3 grid((unsigned)((nrhs * (long long)L.fw_cat + 63) / 64), L.n_fd);
+  for (int st = 0; st < 4; ++st) {
+    if (st % 2)
+      fdw_kernel<T, BF, true, NT><<<grid, 256, 0, c.stream>>>(L.arr<T>().fw[st], nrhs);
+    else
+      fdw_kernel<T, BF, false, NT><<<grid, 256, 0, c.stream>>>(L.arr<T>().fw[st], nrhs);
+  }
+}
+
+// wide tiles rounded up to an even count (at most one zero tile computed)
+template <typename T, bool BF>
+static void scms_wide(Context &c, LevelData &L, int nrhs) {
+  switch ((L.fw_wide + 31) / 32) {
+    case 1: launch_fdw<T, BF, 2>(c, L, nrhs); break;
+    case 2: launch_fdw<T, BF, 4>(c, L, nrhs); break;
+    case 3: launch_fdw<T, BF, 6>(c, L, nrhs); break;
+    case 4: launch_fdw<T, BF, 8>(c, L, nrhs); break;
+    case 5: launch_fdw<T, BF, 10>(c, L, nrhs); break;
+    case 6: launch_fdw<T, BF, 12>(c, L, nrhs); break;
+    case 7: launch_fdw<T, BF, 14>(c, L, nrhs); break;
+    case 8: launch_fdw<T, BF, 16>(c, L, nrhs); break;
+    case 9: launch_fdw<T, BF, 18>(c, L, nrhs); break;
+    case 10: launch_fdw<T, BF, 20>(c, L, nrhs); break;
+    default: fail(IGAMG_EUNSUPPORTED, "patch too large for the SCMS kernel");
+  }
+}
+
 template <typename T, bool BF>
 static void scms_mfma(Context &c, LevelData &L, int nrhs) {
   const int nj = (L.fd_N + 63) / 64;
@@ -3362,15 +3552,20 @@ bool k_scms_interior(Context &c, LevelData &L, int nrhs) {
   if constexpr (sizeof(T) == 4) {
     if (c.bf16_scms()) {
       if (staged)
-        scms_staged<float, true>(c, L, nrhs);
+        scms_wide<float, true>(c, L, nrhs);
       else
         scms_mfma<float, true>(c, L, nrhs);
       return !staged;
     }
   }
-  if (staged)
-    scms_staged<T, false>(c, L, nrhs);
-  else
+  // float64 keeps the per-right-hand-side tiles (fdg_kernel): the batched
+  // form's float64 instantiation is switched off
+  if (staged) {
+    if constexpr (sizeof(T) == 4)
+      scms_wide<T, false>(c, L, nrhs);
+    else
+      scms_staged<T, false>(c, L, nrhs);
+  } else
     scms_mfma<T, false>(c, L, nrhs);
   return !staged;
 }

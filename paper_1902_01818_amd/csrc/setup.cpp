@@ -1195,7 +1195,9 @@ static void build_scms(Context &c, LevelData &L) {
   A.wscratch2 = c.arena.alloc<T>(scr * c.nb);
   std::vector<Fd2Item<T>> fa, fb;
   std::vector<FdGemm<T>> g1, g2, g3, g4;
+  std::vector<FdWide<T>> w1, w2, w3, w4;
   L.fg_tiles = 0;
+  L.fw_wide = L.fw_cat = 0;
   L.fd_work = 0;
   size_t so = 0;
   L.fd_rows = L.fd_K1 = L.fd_N = 0;
@@ -1229,6 +1231,19 @@ static void build_scms(Context &c, LevelData &L) {
                            (T)0, (T)0, 0});
     g4.push_back(FdGemm<T>{Zk, qx.QT, uin, mx, mx, nx, ns, 0, nt, my, mx, mx, tn, nullptr, nullptr,
                            (T)0, (T)pt.scms_scale, 2});
+    // the same four stages over the whole batch (right-hand sides
+    // concatenated along n for the left products, along the rows for the
+    // right ones)
+    w1.push_back(FdWide<T>{qy.QT, rin, Zk, my, nx, nt, mx, ns, my, mx, my, nullptr, nullptr,
+                           (T)0, (T)0, 0});
+    w2.push_back(FdWide<T>{qx.QT, Zk, W2, mx, mx, ns, mx, ns, mx, my, mx, qy.lam, qx.lam,
+                           (T)pt.sigma, (T)0, 1});
+    w3.push_back(FdWide<T>{qy.Q, W2, Zk, my, mx, ns, mx, ns, my, mx, my, nullptr, nullptr, (T)0,
+                           (T)0, 0});
+    w4.push_back(FdWide<T>{qx.Q, Zk, uin, mx, mx, ns, nx, nt, mx, my, mx, nullptr, nullptr, (T)0,
+                           (T)pt.scms_scale, 2});
+    L.fw_wide = std::max(L.fw_wide, std::max(mx, my));
+    L.fw_cat = std::max(L.fw_cat, std::max(mx, my));
     L.fg_tiles = std::max(L.fg_tiles, tn * ((my + 63) / 64));
     L.fd_work += (long long)my * mx * ((my + 15) / 16);
     L.fd_rows = std::max(L.fd_rows, my);
@@ -1243,6 +1258,10 @@ static void build_scms(Context &c, LevelData &L) {
   A.fg[1] = c.arena.upload(g2, c.stream);
   A.fg[2] = c.arena.upload(g3, c.stream);
   A.fg[3] = c.arena.upload(g4, c.stream);
+  A.fw[0] = c.arena.upload(w1, c.stream);
+  A.fw[1] = c.arena.upload(w2, c.stream);
+  A.fw[2] = c.arena.upload(w3, c.stream);
+  A.fw[3] = c.arena.upload(w4, c.stream);
 }
 
 // keep64: the float64 couplings are uploaded too (float32 cycle whose finest
