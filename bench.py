@@ -39,8 +39,9 @@ MFMA_PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 
 
 KERNEL_OF_FAMILY = {"gauss_seidel": "gs2d_wave_kernel", "vol_apply": "vol2d_kernel",
-                    "scms": "fdg_kernel", "iface_apply": "iface_kernel",
-                    "stencil_apply": "sp2d_kernel", "outer_apply": "sp2d_kernel"}
+                    "scms": "fdw_kernel", "iface_apply": "iface_kernel",
+                    "stencil_apply": "sp2d_kernel", "outer_apply": "sp2d_kernel",
+                    "stencil_rows": "sp2d_rhs_kernel"}
 
 
 def source_hash(family="gauss_seidel"):
@@ -104,8 +105,8 @@ def _cpu_model():
     return None
 
 
-ROOF_FAMILIES = ("gauss_seidel", "stencil_apply", "outer_apply", "scms", "pieces", "restrict",
-                 "prolong", "coarse", "vol_apply")
+ROOF_FAMILIES = ("gauss_seidel", "stencil_apply", "stencil_rows", "outer_apply", "scms", "pieces",
+                 "restrict", "prolong", "coarse", "vol_apply")
 
 
 def family_times(st):
@@ -519,6 +520,10 @@ def main():
         sv.solve(F, U, tol=1e-8, maxit=200)
         fams = family_times(sv.kernel_stats(reset=True))
         family = max([k for k in ROOF_FAMILIES if k in fams], key=lambda k: fams[k])
+        # a float32 batch applies the operator with three kernels: the entry
+        # is the row kernel's (its own event family)
+        if family == "stencil_apply" and "stencil_rows" in fams:
+            family = "stencil_rows"
     # timed region: only the dominant family's finest-level launches carry
     # events (on the library's stream, where the kernels run)
     key = "%s/%d" % (family, 0 if family == "coarse" else top)

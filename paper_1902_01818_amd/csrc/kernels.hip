@@ -1055,11 +1055,24 @@ __device__ __forceinline__ void tile_cross(const GsTile &tl, const int *__restri
   }
 }
 
+// Row stride of a Gauss-Seidel tile's u window in LDS by degree: the stride
+// in [w, w + 64) that minimizes the LDS cycles of a chunk read (32 banks, 32
+// lanes per cycle: the two row groups p+1 columns apart in a half-wavefront,
+// each reading 16 consecutive stencil slots), from an enumeration of the
+// strides; for p = 6, 52 takes 24 cycles per row where the unpadded 26 takes
+// 44 (22 without conflicts).  0: unpadded.
+__host__ __device__ constexpr int gs_window_stride(int p) {
+  constexpr int tab[9] = {0, 0, 12, 43, 46, 51, 52, 55, 0};
+  return p >= 0 && p <= 8 ? tab[p] : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Multicolour Gauss-Seidel, one wavefront per tile of 2(p+1) x 2(p+1)
 // unknowns: the four unknowns of a colour class inside the tile are updated
 // by four groups of 16 lanes; the row sum of each group comes out of a DPP
-// scan in its last lane.  A single wavefront executes its LDS operations in
+// scan in its last lane.  The u window's row stride in LDS is padded
+// (gs_window_stride) so that the two groups of a half-wavefront, p+1
+// columns apart, read nearly disjoint banks.  A single wavefront executes its LDS operations in
 // program order, so a class reads what the previous class wrote without a
 // barrier.  Stencil rows (padded to 16-lane groups) of the next D classes are
 // prefetched into registers; f minus the cross-patch couplings (neighbouring
@@ -1069,10 +1082,12 @@ __device__ __forceinline__ void tile_cross(const GsTile &tl, const int *__restri
 // every stencil row it loads serves the NR of them (their dot products and
 // scans are independent, so they also overlap each other's latency).  A
 // block holds RBW such wavefronts on the same tile, whose row loads meet in
-// the CU's L1.  grid.x = group of RBW * NR right-hand sides, grid.y = tile.
+// the CU's L1.  Blocks: (tile, group of RBW * NR right-hand sides) in an
+// XCD-aware order (below).
 // ---------------------------------------------------------------------------
 template <typename T, int P, int RBW, int NR, bool BWD>
-__global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles,
+__global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles, int ntiles,
+                                                       int ngroups,
                                                        const T *__restrict__ st,
                                                        const T *__restrict__ invd,
                                                        const int *__restrict__ cx_li,
@@ -1088,16 +1103,29 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   constexpr int C = (S + 15) / 16;
   constexpr int SP = 16 * C;  // padded row length (zero coefficients beyond S)
   constexpr int NPH = Q1 * Q1;
+  // window row stride: padded where the block's LDS stays within 64 KB
+  constexpr int WS0 = gs_window_stride(P) > W ? gs_window_stride(P) : W;
+  constexpr bool WFIT = (size_t)RBW * NR * (W * WS0 + 2 * TT * TT) * sizeof(T) + 16 * C * 4 <= 65536;
+  constexpr int WS = WFIT ? WS0 : W;
+  constexpr int WW = W * WS;  // window of one right-hand side
   // rows prefetched D classes ahead (deeper prefetch measured slower: the
   // longer prologue outweighs the hidden latency)
   constexpr int D0 = (sizeof(T) == 8 ? 48 : 96) / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
-  __shared__ T sUa[RBW][NR][W * W];
+  __shared__ T sUa[RBW][NR][WW];
   __shared__ T2 sBDa[RBW][NR][TT * TT];
   __shared__ int sOff[C * 16];
-  const GsTile tl = tiles[blockIdx.y];
+  // XCD-aware order: block ids go round-robin over the 8 XCDs; XCD x takes
+  // the x-th contiguous eighth of the (tile, group) list, groups fastest, so
+  // the groups of a tile run back to back on one XCD, whose L2 serves their
+  // repeated stencil-row reads (the grid is padded to a multiple of 8)
+  const int per = gridDim.x >> 3;
+  const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int tix = lb / ngroups, gid = lb - tix * ngroups;
+  if (tix >= ntiles) return;
+  const GsTile tl = tiles[tix];
   const int wid = threadIdx.x >> 6;
-  const int zw = (blockIdx.x * RBW + wid) * NR;  // first right-hand side of this wave
+  const int zw = (gid * RBW + wid) * NR;  // first right-hand side of this wave
   const int nx = tl.nx, ny = tl.ny;
   const int x0 = tl.i0[0], y0 = tl.i0[1];
   const int wx0 = x0 - P, wy0 = y0 - P;
@@ -1134,8 +1162,10 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
       dv[j] = ok ? invd[t] : (T)0;
     }
 #pragma unroll
-    for (int j = 0; j < NW; ++j)
-      if (lane + 64 * j < W * W) sU[lane + 64 * j] = wv[j];
+    for (int j = 0; j < NW; ++j) {
+      const int i = lane + 64 * j;
+      if (i < W * W) sU[(i / W) * WS + i % W] = wv[j];
+    }
 #pragma unroll
     for (int j = 0; j < NT; ++j)
       if (lane + 64 * j < TT * TT) {
@@ -1158,7 +1188,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     });
   }
   if (wid == 0)
-    for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * W + (o % S1 - P) : 0;
+    for (int o = lane; o < C * 16; o += 64) sOff[o] = o < S ? (o / S1 - P) * WS + (o % S1 - P) : 0;
   // row of this lane's group in class s: a compile-time offset from the
   // group's first row.  Rows of a ragged tile outside the patch fall on later
   // rows or on the zero padding past the level's end (never beyond it: at
@@ -1182,7 +1212,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   // right-hand side; the others follow at compile-time offsets); a class
   // adds a compile-time offset
   const T *ub[C];
-  const int wl = (ay + P) * W + ax + P;
+  const int wl = (ay + P) * WS + ax + P;
   const T *sU0 = sUa[wid][0];
 #pragma unroll
   for (int c = 0; c < C; ++c) ub[c] = sU0 + wl + sOff[l16 + 16 * c];
@@ -1192,13 +1222,13 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   for (int s = 0; s < NPH; ++s) {
     const int ph = BWD ? NPH - 1 - s : s;
     const int ix = x0 + ph % Q1 + ax, iy = y0 + ph / Q1 + ay;
-    const int cw = (ph / Q1) * W + ph % Q1, cl2 = (ph / Q1) * TT + ph % Q1;
+    const int cw = (ph / Q1) * WS + ph % Q1, cl2 = (ph / Q1) * TT + ph % Q1;
     T uv[NR][C], uold[NR], acc[NR], ubd[NR], dinv[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) uv[r][c] = ub[c][r * W * W + cw];
-      uold[r] = uw[r * W * W + cw];
+      for (int c = 0; c < C; ++c) uv[r][c] = ub[c][r * WW + cw];
+      uold[r] = uw[r * WW + cw];
       const T2 bd = bdl[r * TT * TT + cl2];
       // u + (b - a.u) d: every LDS value of the class is consumed before the
       // scans, so the reads go out as one batch and none is sunk past them
@@ -1225,7 +1255,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     for (int r = 0; r < NR; ++r) acc[r] = row16_scan(acc[r]);
     if (l16 == 15 && ix < nx && iy < ny) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) uw[r * W * W + cw] = fma(-acc[r], dinv[r], ubd[r]);
+      for (int r = 0; r < NR; ++r) uw[r * WW + cw] = fma(-acc[r], dinv[r], ubd[r]);
     }
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
@@ -1238,13 +1268,13 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     const T *sU = sUa[wid][r];
     for (int i = lane; i < TT * TT; i += 64) {
       int iy = y0 + i / TT, ix = x0 + i % TT;
-      if (ix < nx && iy < ny) uz[off + (long long)iy * nx + ix] = sU[(iy - wy0) * W + (ix - wx0)];
+      if (ix < nx && iy < ny) uz[off + (long long)iy * nx + ix] = sU[(iy - wy0) * WS + (ix - wx0)];
     }
     // conforming: the tile's owned glued unknowns into their copies in other
     // patches (those patches carry other colours: nothing else writes there)
     for (int e = lane; e < tl.mr_n; e += 64) {
       const int lt = mr_li[tl.mr_off + e];
-      uz[mr_dst[tl.mr_off + e]] = sU[(lt / TT + P) * W + lt % TT + P];
+      uz[mr_dst[tl.mr_off + e]] = sU[(lt / TT + P) * WS + lt % TT + P];
     }
   }
 }
@@ -3213,10 +3243,11 @@ template void k_glue_sum<float>(LevelData &, float *, int, hipStream_t);
 template <typename T, int P, int RBW, int NR, bool BWD>
 static void launch_gs2d_dir(Context &c, LevelData &L, const GsClass &cl, int nrhs) {
   LevelArrays<T> &A = L.arr<T>();
-  dim3 grid((nrhs + RBW * NR - 1) / (RBW * NR), cl.count);
-  gs2d_wave_kernel<T, P, RBW, NR, BWD><<<grid, 64 * RBW, 0, c.stream>>>(
-      cl.tiles, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val, L.d_mr_li, L.d_mr_dst,
-      A.f, A.u, L.Ntorn, nrhs);
+  const int ngroups = (nrhs + RBW * NR - 1) / (RBW * NR);
+  const long long nblk = ((long long)ngroups * cl.count + 7) / 8 * 8;
+  gs2d_wave_kernel<T, P, RBW, NR, BWD><<<(unsigned)nblk, 64 * RBW, 0, c.stream>>>(
+      cl.tiles, cl.count, ngroups, A.stencil, A.invdiag, L.d_gcx_li, L.d_gcx_col, A.gcx_val,
+      L.d_mr_li, L.d_mr_dst, A.f, A.u, L.Ntorn, nrhs);
 }
 
 // the sweep direction is a template parameter: the unrolled class steps then
@@ -3349,9 +3380,14 @@ static void launch_sp2d_rhs(Context &c, LevelData &L, const LevelArrays<float> &
   transpose64_kernel<<<dim3((unsigned)L.n_plines, ng), 256, 0, c.stream>>>(
       u, nrhs, L.Ntorn, L.d_plines, L.pad_tot, L.ut);
   dim3 grid((unsigned)(((L.n_sptiles + 3) / 4 + 7) / 8 * 8), ng);
-  sp2d_rhs_kernel<P, BX><<<grid, 256, 0, c.stream>>>(L.d_sptiles, L.n_sptiles, nrhs, A.stencil,
-                                                    L.d_mask, L.ut, L.pad_tot, f, fw, beta, alpha,
-                                                    r, L.Ntorn);
+  {
+    // the row kernel alone (without the transposition and the cross-patch
+    // couplings of the same apply): the family of its roofline entry
+    TimeScope ts(c, "stencil_rows", L.l);
+    sp2d_rhs_kernel<P, BX><<<grid, 256, 0, c.stream>>>(L.d_sptiles, L.n_sptiles, nrhs, A.stencil,
+                                                      L.d_mask, L.ut, L.pad_tot, f, fw, beta,
+                                                      alpha, r, L.Ntorn);
+  }
   launch_cross3d<float>(c, L, A.x_val, 0, L.x_n, u, r, true, alpha, nrhs);
   }
 }

@@ -2197,10 +2197,12 @@ void kernel_model(const Context &c, const std::string &fam, int level, int nrhs,
     const double n = (double)L.N;
     *bytes = (n * wb * S + nb * n * 3.0 * wb) / launches;
     *flops = nb * 2.0 * S * n / launches;
-  } else if (fam == "stencil_apply" || fam == "outer_apply") {
+  } else if (fam == "stencil_apply" || fam == "outer_apply" || fam == "stencil_rows") {
     // algorithmic bytes: the (2p+1)^d stencil of every unknown once for the
     // batch; u and f read and r written per right-hand side (outer_apply:
-    // the float64 finest-level operator of a mixed-precision solve)
+    // the float64 finest-level operator of a mixed-precision solve;
+    // stencil_rows: the row kernel of a float32 batch, whose transposed
+    // input and cross-patch couplings are launched beside it)
     const double b = fam == "outer_apply" ? 8.0 : wb;
     const double n = (double)L.N;
     *bytes = n * b * S + nb * n * 3.0 * b;

@@ -3,6 +3,7 @@
     python -m paper_1902_01818_amd.profile_summary stats <kernel_trace.csv> [--title T] [--cmd C]
     python -m paper_1902_01818_amd.profile_summary traffic <fetch.csv> <write.csv>
         --kernel NAME [--grid G | --sweep-total G] --copy-bytes B [--copy-kernel NAME]
+        [--copy-last]
 
 `stats` groups the kernel trace by kernel name and grid size (a grid size
 identifies the level) and prints calls, total and average durations.
@@ -97,18 +98,19 @@ def counter_per_dispatch(rows, kernel, grid, counter, sweep_total=None):
     return vals
 
 
-def traffic(fetch, write, kernel, grid, copy_bytes, copy_kernel, sweep_total=None):
+def traffic(fetch, write, kernel, grid, copy_bytes, copy_kernel, sweep_total=None, copy_last=False):
     fr, wr = pmc_rows(fetch), pmc_rows(write)
     f = counter_per_dispatch(fr, kernel, grid, "FETCH_SIZE", sweep_total)
     w = counter_per_dispatch(wr, kernel, grid, "WRITE_SIZE", sweep_total)
-    # calibration: the copy dispatch with the largest grid
+    # calibration: the copy dispatch with the largest grid (copy_last: the
+    # last dispatch of the copy kernel, the run's final calibration copy)
     def biggest(rows, counter):
         best = None
-        for r in rows:
+        for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
             if r.get("Counter_Name") != counter or copy_kernel not in r["Kernel_Name"]:
                 continue
             g = grid_of(r)
-            if best is None or g > best[0]:
+            if best is None or g > best[0] or copy_last:
                 best = (g, r["Dispatch_Id"])
         if best is None:
             return None
@@ -137,12 +139,14 @@ def main():
     ap.add_argument("--copy-kernel", default="copy")
     ap.add_argument("--sweep-total", type=int, default=None)
     ap.add_argument("--source-hash", default="")
+    ap.add_argument("--copy-last", action="store_true",
+                    help="calibrate on the last dispatch of the copy kernel")
     a = ap.parse_args()
     if a.mode == "stats":
         print(stats(a.files[0], a.title, a.cmd))
     else:
         res = traffic(a.files[0], a.files[1], a.kernel, a.grid, a.copy_bytes, a.copy_kernel,
-                      a.sweep_total)
+                      a.sweep_total, a.copy_last)
         res["source_hash"] = a.source_hash
         print(json.dumps(res, indent=1))
     return 0
