@@ -216,9 +216,10 @@ def gs_color_keys(level, tile):
     (n_el >= 2 on every smoothed level).
 
     tile >= p keeps tiles of equal parity uncoupled as well.  With a degree
-    per patch, p and the tile are the patch's (tile None: 2(p_k+1)) and the
-    position s is counted in base (p_max+1), so keys of patches of different
-    degree share one order."""
+    per patch the tile (None: 2(p+1)) and the positions (i mod (p+1)) are
+    those of the largest degree p on every patch: two unknowns of equal key
+    still differ by at least p+1 >= p_k+1 in some index, beyond the coupling
+    range p_k of their patch."""
     topo = level.topo
     d = level.d
     pm = level.p
@@ -229,12 +230,11 @@ def gs_color_keys(level, tile):
         if c < 0 or level.rep_torn[c] != t:
             continue
         k = int(np.searchsorted(level.offsets, t, side="right") - 1)
-        p = int(level.pk[k])
-        tk = 2 * (p + 1) if tile is None else tile
-        assert tk >= p
+        tk = 2 * (pm + 1) if tile is None else tile
+        assert tk >= pm
         i = level.idx[k][t - level.offsets[k]]
         par = sum(((int(i[g]) // tk) % 2) << g for g in range(d))
-        sub = sum((int(i[g]) % (p + 1)) * (pm + 1) ** g for g in range(d))
+        sub = sum((int(i[g]) % (pm + 1)) * (pm + 1) ** g for g in range(d))
         keys[c] = (color[k] * 2 ** d + par) * (pm + 1) ** d + sub
     return keys
 

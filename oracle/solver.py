@@ -40,9 +40,9 @@ class OracleProblem:
         self.smoother = smoother
         self.mu, self.nu = mu, nu
         self.tau, self.delta = tau, delta
-        if gs_tile is None and np.all(self.pk == self.p):
-            gs_tile = 2 * (self.p + 1)
-        self.gs_tile = gs_tile  # None: 2(p_k+1) per patch
+        if gs_tile is None:
+            gs_tile = 2 * (self.p + 1)  # the largest degree's on every patch
+        self.gs_tile = gs_tile
         self.eta = None if conforming else penalty(self.topo, elems, self.pk, sigma)
         self.level_elems = level_elements(elems, coarse_min)
         self.levels = [Level(self.topo, e, self.pk, conforming, self.eta)

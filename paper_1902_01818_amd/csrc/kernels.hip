@@ -290,9 +290,10 @@ __global__ __launch_bounds__(256) void gather3d_kernel(const PatchDev *pd, int k
 template <int P, int RT>
 __global__ __launch_bounds__(256) void stencil2d_kernel(const VolTile *tiles, const PatchDev *pd,
                                                         const double *tabB, const double *tabD,
-                                                        GaussRule gr, double *st, int SP) {
-  // SP: row stride of st (at least the padded (2p+1)^2 of this degree; a
-  // level with patches of higher degree uses theirs)
+                                                        GaussRule gr, double *st, int SP, int pm) {
+  // Rows are laid out for the level's largest degree pm >= P: entry (dx, dy)
+  // of this patch's (2P+1)^2 stencil sits at slot (dy + pm - P)(2pm + 1) +
+  // dx + pm - P of a row of stride SP; every other slot is zero
   constexpr int Q = P + 1, P1 = P + 1, S1 = 2 * P + 1, S = S1 * S1;
   constexpr int NE = RT + P;                  // element columns touching the tile
   constexpr int NOUT = RT * RT * S;           // entries of the tile's rows
@@ -401,7 +402,8 @@ __global__ __launch_bounds__(256) void stencil2d_kernel(const VolTile *tiles, co
       acc[u] += s;
     }
   }
-  // rows of the tile, padded slots zero
+  // rows of the tile in the level's layout; the other slots zero
+  const int S1m = 2 * pm + 1, sh = pm - P;
 #pragma unroll
   for (int u = 0; u < OPT; ++u) {
     const int o = tid + 256 * u;
@@ -409,12 +411,15 @@ __global__ __launch_bounds__(256) void stencil2d_kernel(const VolTile *tiles, co
     const int ry = o / (RT * S), rem = o % (RT * S), rx = rem / S, slot = rem % S;
     const int ix = x0 + rx, iy = y0 + ry;
     if (ix >= nx || iy >= ny) continue;
-    st[(pt.off + (long long)iy * nx + ix) * SP + slot] = acc[u];
+    const int so = (slot / S1 + sh) * S1m + slot % S1 + sh;
+    st[(pt.off + (long long)iy * nx + ix) * SP + so] = acc[u];
   }
-  for (int e = tid; e < RT * RT * (SP - S); e += 256) {
-    const int r = e / (SP - S), slot = S + e % (SP - S);
+  for (int e = tid; e < RT * RT * SP; e += 256) {
+    const int r = e / SP, so = e % SP;
+    const int dy = so / S1m - sh, dx = so % S1m - sh;
+    if (so < S1m * S1m && dy >= 0 && dy < S1 && dx >= 0 && dx < S1) continue;  // an entry
     const int ix = x0 + r % RT, iy = y0 + r / RT;
-    if (ix < nx && iy < ny) st[(pt.off + (long long)iy * nx + ix) * SP + slot] = 0.0;
+    if (ix < nx && iy < ny) st[(pt.off + (long long)iy * nx + ix) * SP + so] = 0.0;
   }
 }
 
@@ -3017,7 +3022,7 @@ template <int P, int RT>
 static void launch_stencil2d(Context &c, LevelData &L, double *out, int first, int count,
                              int SP) {
   stencil2d_kernel<P, RT><<<count, 256, 0, c.stream>>>(L.d_stiles + first, L.d_pd, L.d_tabB,
-                                                       L.d_tabD, rule_of(P + 1), out, SP);
+                                                       L.d_tabD, rule_of(P + 1), out, SP, c.p);
 }
 
 // element matrices of at most this many bytes at a time (z slabs of a patch)

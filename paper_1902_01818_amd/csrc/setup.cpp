@@ -907,7 +907,7 @@ static std::vector<double> dense_block_rows(const Context &c, const LevelData &L
     const long long t1 = L.rep[comps[a]];
     const int k = L.patch_of(t1);
     const PatchDev &pt = L.pd[k];
-    const int p = pt.p, S1 = 2 * p + 1;  // the row's layout: its patch's degree
+    const int p = c.p, S1 = 2 * p + 1;  // rows in the layout of the largest degree
     long long lc = t1 - pt.off;
     int i[3] = {0, 0, 0};
     for (int g = 0; g < c.d; ++g) {
@@ -1784,9 +1784,8 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
       (c.opt.discretization != IGAMG_SIPG || !use_gs))
     fail(IGAMG_EUNSUPPORTED, "stored operator rows exist for SIPG with a Gauss-Seidel smoother only");
   if (c.d == 3 && degree > 4) fail(IGAMG_EUNSUPPORTED, "3D problems: degree 1..4");
-  if (c.mixed && (c.d != 2 || c.opt.discretization != IGAMG_SIPG ||
-                  c.opt.smoother != IGAMG_SMOOTHER_SCMS))
-    fail(IGAMG_EUNSUPPORTED, "patches of different degrees: 2D SIPG with the SCMS smoother only");
+  if (c.mixed && (c.d != 2 || c.opt.discretization != IGAMG_SIPG))
+    fail(IGAMG_EUNSUPPORTED, "patches of different degrees: 2D SIPG only");
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
@@ -1890,15 +1889,16 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
         const int k = L.patch_of(t);
         const PatchDev &pt = L.pd[k];
         long long a = t - pt.off, b = L.if_col[e] - pt.off;
-        // slot in the row of this patch's degree ((2p_k+1)^d entries)
+        // slot in a row of the level's layout ((2p+1)^d entries, p the
+        // largest degree)
         int slot = 0, m = 1;
         for (int g = 0; g < c.d; ++g) {
           int ia = (int)(a % pt.n[g]), ib = (int)(b % pt.n[g]);
           a /= pt.n[g];
           b /= pt.n[g];
           if (std::abs(ib - ia) > pt.p) fail(IGAMG_EINVAL, "interface coupling outside the stencil");
-          slot += (ib - ia + pt.p) * m;
-          m *= 2 * pt.p + 1;
+          slot += (ib - ia + c.p) * m;
+          m *= 2 * c.p + 1;
         }
         srow.push_back((int)t);
         sslot.push_back(slot);

@@ -19,6 +19,8 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
+from scipy.sparse.linalg import spsolve_triangular
 
 import oracle
 import workloads
@@ -108,14 +110,30 @@ def test_nonmatching_lshape_order():
 
 
 def test_mixed_degree_color_classes_independent():
+    """The multicolour order with a degree per patch (the largest degree's
+    tile and positions on every patch): no two coupled unknowns share a key,
+    on every smoothed level, and the sweep equals the triangular solve with
+    the permuted lower part."""
     elems, deg = workloads.nonmatching_spaces(workloads.lshape_elems(4), 3)
     pb = oracle.setup(workloads.lshape_corners(), elems, deg, smoother="gs", coarse_min=1)
-    assert pb.gs_tile is None
+    assert pb.gs_tile == 2 * (int(deg.max()) + 1)
     for l in range(1, len(pb.levels)):
         A = pb.A[l].tocoo()
         off = A.row != A.col
         keys = gs_color_keys(pb.levels[l], None)
         assert not np.any(keys[A.row[off]] == keys[A.col[off]]), l
+    l = len(pb.levels) - 1
+    A = pb.A[l].tocsr()
+    keys = gs_color_keys(pb.levels[l], None)
+    perm = np.argsort(keys, kind="stable")
+    rng = np.random.default_rng(3)
+    f, u0 = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    Ap = A[perm][:, perm]
+    Lp = sp.tril(Ap, format="csr")
+    up = u0[perm] + spsolve_triangular(Lp, (f - A @ u0)[perm], lower=True)
+    ref = np.empty_like(up)
+    ref[perm] = up
+    assert np.allclose(pb.gs[l].forward(f, u0), ref, rtol=1e-12, atol=1e-12)
 
 
 def read_table(name):
