@@ -322,7 +322,7 @@ def _printed(name):
     return rows
 
 
-PAPER_TABLES = ("GS1", "SCMS1", "SCMS2", "HYB3a")
+PAPER_TABLES = ("GS1", "SCMS1", "SCMS2", "HYB3a", "HYB3b")
 
 
 def paper_tables(igamg, torch, workloads, maxit=150, tables=PAPER_TABLES):
@@ -336,8 +336,10 @@ def paper_tables(igamg, torch, workloads, maxit=150, tables=PAPER_TABLES):
     library's degree range) and Table HYB3 (a) (Fichera corner, hybrid
     V-cycle with PCG, scaling 0.12, L = 2..5, p = 2..4; damping 0.5, the
     largest for which this build's reading of the piece smoother keeps the
-    cycle positive, and the paper's 1).  A count of None means no
-    convergence within maxit cycles."""
+    cycle positive, and the paper's 1) and Table HYB3 (b) (the same with the
+    SIPG space and the non-matching spaces; p = 2, 3: degree p+1 <= 4, the
+    3D kernels' range).  A count of None means no convergence within maxit
+    cycles."""
     out = {}
 
     def run(corners, elems, p, smoother, tau, outer, conforming=True):
@@ -388,6 +390,19 @@ def paper_tables(igamg, torch, workloads, maxit=150, tables=PAPER_TABLES):
                         rows.append(r)
         out["SCMS2"] = rows
         print("bench: table SCMS2 done", file=sys.stderr, flush=True)
+    if "HYB3b" in tables:
+        printed = _printed("hyb3_fichera.txt")
+        rows = []
+        for tau in (0.5, 1.0):
+            for L in range(2, 6):
+                for p in (2, 3):
+                    elems, deg = workloads.nonmatching_spaces(workloads.fichera_elems(L), p)
+                    r = run(workloads.fichera_corners(), elems, deg, "hybrid", tau, "pcg",
+                            conforming=False)
+                    r.update(L=L, p=p, block="b", damping=tau, printed=printed[L][5 + p - 2])
+                    rows.append(r)
+        out["HYB3b"] = rows
+        print("bench: table HYB3 (b) done", file=sys.stderr, flush=True)
     if "HYB3a" not in tables:
         return out
     printed = _printed("hyb3_fichera.txt")
@@ -459,7 +474,7 @@ def main():
     ap.add_argument("--paper-tables", nargs="?", const=",".join(PAPER_TABLES), default=None,
                     metavar="T1,T2",
                     help="run only the paper's L-shape and Fichera experiments (Tables GS1, "
-                         "SCMS1, SCMS2, HYB3a; default all) and print the counts beside the "
+                         "SCMS1, SCMS2, HYB3a, HYB3b; default all) and print the counts beside the "
                          "printed ones")
     ap.add_argument("--family", default=None, help="kernel family for the roofline entry")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -246,11 +246,15 @@ __global__ __launch_bounds__(256) void elem3d_kernel(const PatchDev *pd, int k, 
   }
 }
 
+// Rows of patch k (degree P) in the level's layout: slots of the largest
+// degree pm ((2pm+1)^3, row stride SP); offsets beyond P get no element
+// (an empty range below) and hold zero.
 template <int P>
 __global__ __launch_bounds__(256) void gather3d_kernel(const PatchDev *pd, int k, int iz0, int iz1,
-                                                       int ez0, const double *Ke, double *st) {
-  constexpr int P1 = P + 1, NB = P1 * P1 * P1, S1 = 2 * P + 1, S = S1 * S1 * S1;
-  constexpr int SP = (S + 15) / 16 * 16;
+                                                       int ez0, const double *Ke, double *st,
+                                                       int SP, int pm) {
+  constexpr int P1 = P + 1, NB = P1 * P1 * P1;
+  const int S1 = 2 * pm + 1, S = S1 * S1 * S1;
   const PatchDev &pt = pd[k];
   const int nx = pt.n[0], ny = pt.n[1], nz = pt.n[2];
   const int nelx = pt.nel[0], nely = pt.nel[1], nelz = pt.nel[2];
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(256) void gather3d_kernel(const PatchDev *pd, int k
   const long long t = pt.off + ((long long)iz * ny + iy) * nx + ix;
   double sum = 0.0;
   if (o < S) {
-    const int jx = ix + o % S1 - P, jy = iy + o / S1 % S1 - P, jz = iz + o / (S1 * S1) - P;
+    const int jx = ix + o % S1 - pm, jy = iy + o / S1 % S1 - pm, jz = iz + o / (S1 * S1) - pm;
     if (jx >= 0 && jx < nx && jy >= 0 && jy < ny && jz >= 0 && jz < nz) {
       const int zlo = max(max(iz, jz) - P, 0), zhi = min(min(iz, jz), nelz - 1);
       const int ylo = max(max(iy, jy) - P, 0), yhi = min(min(iy, jy), nely - 1);
@@ -3028,16 +3032,18 @@ static void launch_stencil2d(Context &c, LevelData &L, double *out, int first, i
 // element matrices of at most this many bytes at a time (z slabs of a patch)
 constexpr size_t ASSEMBLE3D_SCRATCH = (size_t)2 << 30;
 
+// rows of the patches of degree P (element matrices with P+1 Gauss points
+// per direction), written in the level's layout of row stride SP
 template <int P>
-static void assemble3d(Context &c, LevelData &L, double *out) {
-  constexpr int P1 = P + 1, NB = P1 * P1 * P1, S1 = 2 * P + 1;
-  constexpr int SP = (S1 * S1 * S1 + 15) / 16 * 16;
+static void assemble3d(Context &c, LevelData &L, double *out, int SP) {
+  constexpr int P1 = P + 1, NB = P1 * P1 * P1;
   const size_t per_el = (size_t)NB * NB * sizeof(double);
   // rows per slab: the slab's element layers (rows + P) fit the scratch
   std::vector<int> rows_per(L.K);
   size_t cap = 0;
   for (int k = 0; k < L.K; ++k) {
     const PatchDev &pt = L.pd[k];
+    if (pt.p != P) continue;
     const size_t layer = (size_t)pt.nel[0] * pt.nel[1] * per_el;
     const int fit = (int)std::max<size_t>(1, ASSEMBLE3D_SCRATCH / layer);
     const int R = std::max(1, fit - P);
@@ -3046,16 +3052,19 @@ static void assemble3d(Context &c, LevelData &L, double *out) {
   }
   DeviceScratch ke;
   double *Ke = ke.alloc<double>(cap / sizeof(double));
+  if (cap == 0) return;
   for (int k = 0; k < L.K; ++k) {
     const PatchDev &pt = L.pd[k];
+    if (pt.p != P) continue;
     for (int iz0 = 0; iz0 < pt.n[2]; iz0 += rows_per[k]) {
       const int iz1 = std::min(pt.n[2], iz0 + rows_per[k]);
       const int ez0 = std::max(0, iz0 - P), ez1 = std::min(pt.nel[2] - 1, iz1 - 1);
       const long long nel = (long long)pt.nel[0] * pt.nel[1] * (ez1 - ez0 + 1);
       elem3d_kernel<P><<<(unsigned)nel, 256, 0, c.stream>>>(L.d_pd, k, ez0, L.d_tabB, L.d_tabD,
-                                                            c.gr, Ke);
+                                                            rule_of(P + 1), Ke);
       const long long n = (long long)pt.n[0] * pt.n[1] * (iz1 - iz0) * SP;
-      gather3d_kernel<P><<<nblocks(n), 256, 0, c.stream>>>(L.d_pd, k, iz0, iz1, ez0, Ke, out);
+      gather3d_kernel<P><<<nblocks(n), 256, 0, c.stream>>>(L.d_pd, k, iz0, iz1, ez0, Ke, out, SP,
+                                                           c.p);
     }
   }
   HIPCHK(hipStreamSynchronize(c.stream));  // the scratch is freed at scope exit
@@ -3083,15 +3092,15 @@ void k_stencil_assemble(Context &c, LevelData &L, double *out) {
     }
   } else if (c.arena.region || c.p > 4) {
     // inside a lent region (no scratch allocation): per-entry quadrature
+    if (c.mixed) fail(IGAMG_EUNSUPPORTED, "3D rows of mixed degrees inside a lent region");
     stencil_kernel<3><<<nblocks(tot), BS, 0, c.stream>>>(L.d_pd, L.K, L.d_tabB, L.d_tabD, c.gr, c.p,
                                                          L.Ntorn, out);
   } else {
-    switch (c.p) {
-      case 1: assemble3d<1>(c, L, out); break;
-      case 2: assemble3d<2>(c, L, out); break;
-      case 3: assemble3d<3>(c, L, out); break;
-      case 4: assemble3d<4>(c, L, out); break;
-    }
+    // one pass per degree present (each over its patches)
+    assemble3d<1>(c, L, out, SP);
+    assemble3d<2>(c, L, out, SP);
+    assemble3d<3>(c, L, out, SP);
+    assemble3d<4>(c, L, out, SP);
   }
   HIPCHK(hipGetLastError());
 }
@@ -3201,7 +3210,8 @@ template <typename T, int P>
 static void launch_vol3d(Context &c, LevelData &L, const T *u, T *r, T alpha, int nrhs, int first,
                          int count) {
   vol3d_kernel<T, P, VOL3D_TILE><<<dim3(count, nrhs), 256, 0, c.stream>>>(
-      L.d_vtiles + first, L.d_pd, L.d_tabB, L.d_tabD, c.gr, u, r, L.d_mask, alpha, L.Ntorn);
+      L.d_vtiles + first, L.d_pd, L.d_tabB, L.d_tabD, rule_of(P + 1), u, r, L.d_mask, alpha,
+      L.Ntorn);
 }
 
 template <typename T>

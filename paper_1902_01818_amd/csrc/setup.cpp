@@ -1076,22 +1076,22 @@ static std::vector<double> transpose(const std::vector<double> &A, int n) {
 //   6. U_z += scale W1_z Qx^T      (into the patch interior of u)
 template <typename T>
 static void build_scms3(Context &c, LevelData &L) {
-  const int p = c.p;  // one degree in 3D
   LevelArrays<T> &A = L.arr<T>();
   struct QT {
     T *Q, *QT;
     std::vector<double> lam;
   };
-  std::map<int, QT> qtab;
+  // factors by (elements, degree) of a direction
+  std::map<std::pair<int, int>, QT> qtab;
   for (int k = 0; k < L.K; ++k)
     for (int g = 0; g < 3; ++g) {
-      int ne = L.pd[k].nel[g];
-      if (qtab.count(ne)) continue;
+      const int ne = L.pd[k].nel[g], p = L.pd[k].p;
+      if (qtab.count({ne, p})) continue;
       std::vector<double> Q, lam;
       scms_factors_1d(ne, p, Q, lam);
       int n = ne + p - 2;
-      qtab[ne] = QT{c.arena.upload_as<T>(Q, c.stream),
-                    c.arena.upload_as<T>(transpose(Q, n), c.stream), lam};
+      qtab[{ne, p}] = QT{c.arena.upload_as<T>(Q, c.stream),
+                         c.arena.upload_as<T>(transpose(Q, n), c.stream), lam};
     }
   size_t scr = 0, nxy = 0;
   for (int k = 0; k < L.K; ++k) {
@@ -1105,7 +1105,7 @@ static void build_scms3(Context &c, LevelData &L) {
   // lam_y[j] + lam_x[i] of every patch, and lam_z per direction table
   std::vector<double> lxy;
   lxy.reserve(nxy);
-  std::map<int, T *> lamz;
+  std::map<std::pair<int, int>, T *> lamz;
   for (auto &kv : qtab) lamz[kv.first] = c.arena.upload_as<T>(kv.second.lam, c.stream);
   std::vector<FdGemm<T>> g[6];
   const long long nt = L.Ntorn, ns = (long long)scr;
@@ -1114,7 +1114,7 @@ static void build_scms3(Context &c, LevelData &L) {
   for (int k = 0; k < L.K; ++k) {
     const PatchDev &pt = L.pd[k];
     const int mx = pt.n[0] - 2, my = pt.n[1] - 2;
-    const QT &qx = qtab[pt.nel[0]], &qy = qtab[pt.nel[1]];
+    const QT &qx = qtab[{pt.nel[0], pt.p}], &qy = qtab[{pt.nel[1], pt.p}];
     lxy_off.push_back(lo);
     for (int j = 0; j < my; ++j)
       for (int i = 0; i < mx; ++i) lxy.push_back(qy.lam[j] + qx.lam[i]);
@@ -1126,7 +1126,7 @@ static void build_scms3(Context &c, LevelData &L) {
     const int nx = pt.n[0], ny = pt.n[1];
     const int mx = pt.n[0] - 2, my = pt.n[1] - 2, mz = pt.n[2] - 2;
     const long long sxy = (long long)mx * my, nxy_p = (long long)nx * ny;
-    const QT &qx = qtab[pt.nel[0]], &qy = qtab[pt.nel[1]], &qz = qtab[pt.nel[2]];
+    const QT &qx = qtab[{pt.nel[0], pt.p}], &qy = qtab[{pt.nel[1], pt.p}], &qz = qtab[{pt.nel[2], pt.p}];
     T *W1 = A.wscratch + so, *W2 = A.wscratch2 + so;
     so += (size_t)sxy * mz;
     T *rin = A.r + pt.off + nxy_p + nx + 1;
@@ -1148,7 +1148,7 @@ static void build_scms3(Context &c, LevelData &L) {
                                nullptr, nullptr, (T)0, (T)pt.scms_scale, 2});
     }
     g[2].push_back(FdGemm<T>{qz.QT, W2, W1, mz, sxy, sxy, 0, ns, ns, mz, (int)sxy, mz, txy,
-                             lamz[pt.nel[2]], A.lam_xy + lxy_off[k], (T)pt.sigma, (T)0, 1});
+                             lamz[{pt.nel[2], pt.p}], A.lam_xy + lxy_off[k], (T)pt.sigma, (T)0, 1});
     g[3].push_back(FdGemm<T>{qz.Q, W1, W2, mz, sxy, sxy, 0, ns, ns, mz, (int)sxy, mz, txy,
                              nullptr, nullptr, (T)0, (T)0, 0});
   }
@@ -1784,8 +1784,8 @@ void init_problem(Context &c, const igamg_patches *P, int degree, double sigma,
       (c.opt.discretization != IGAMG_SIPG || !use_gs))
     fail(IGAMG_EUNSUPPORTED, "stored operator rows exist for SIPG with a Gauss-Seidel smoother only");
   if (c.d == 3 && degree > 4) fail(IGAMG_EUNSUPPORTED, "3D problems: degree 1..4");
-  if (c.mixed && (c.d != 2 || c.opt.discretization != IGAMG_SIPG))
-    fail(IGAMG_EUNSUPPORTED, "patches of different degrees: 2D SIPG only");
+  if (c.mixed && c.opt.discretization != IGAMG_SIPG)
+    fail(IGAMG_EUNSUPPORTED, "patches of different degrees: SIPG only");
   c.gr = gauss_rule(degree + 1);
   const int nc = 1 << c.d;
   c.corners.assign(c.K, {});
