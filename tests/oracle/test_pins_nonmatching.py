@@ -169,3 +169,20 @@ def test_scms2_lshape_pcg_trend():
             assert its[level] <= tab[level][7 + p - 2], (p, level, its)
         assert its[5] <= its[4] + 2, (p, its)
     assert _scms2_its(2, 5, 0.9) > 2 * _scms2_its(2, 4, 0.9)
+
+
+def test_hyb3b_fichera_nonmatching_pcg_trend():
+    """Table HYB3 (b) as a trend (golden fixture): hybrid PCG on the Fichera
+    corner with the non-matching spaces, scaling 0.12, damping 0.5 (this
+    build's reading of the piece smoother; at the paper's damping 1 the
+    cycle is indefinite, as for column (a)): p = 2 on levels 2 and 3 within
+    one iteration of the printed counts and flat in the level."""
+    tab = read_table("hyb3_fichera.txt")
+    its = {}
+    for level in (2, 3):
+        elems, deg = workloads.nonmatching_spaces(workloads.fichera_elems(level), 2)
+        pb = oracle.setup(workloads.fichera_corners(), elems, deg, smoother="hybrid", tau=0.5,
+                          delta=0.12, coarse_min=1)
+        its[level] = pb.pcg(pb.load_manufactured())[1]
+        assert abs(its[level] - tab[level][5]) <= 1, (level, its)
+    assert abs(its[3] - its[2]) <= 1, its
