@@ -1448,43 +1448,60 @@ __global__ __launch_bounds__(256) void transpose64_kernel(const float *__restric
   }
 }
 
-// acc += c[lane a of this lane's 16-lane row] * w: the coefficient comes from
-// lane a of each 16-lane row (DPP row_newbcast), so a register holding the
-// 13 coefficients of a stencil line in lanes 0..12 of every row serves all 64
-// lanes.  The leading s_nop keeps two wait states between any VALU write of
-// the coefficient register and its DPP read (it is written by loads only).
-template <int A>
-__device__ __forceinline__ void fmac_bcast(float &acc, float c, float w) {
-  if constexpr (A == 0)
-    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(c), "v"(w));
-  else
-    asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(c), "v"(w), "n"(A));
+// acc = c * w (Init) or acc += c * w, where c is read from lane A of this
+// lane's 16-lane row (DPP row_newbcast): a register holding the 13
+// coefficients of a stencil line in lanes 0..12 of every row serves all 64
+// lanes.  The statements are volatile so that they keep the order written
+// below (one offset for all rows of a strip, so no product waits on the one
+// before it).  The leading s_nop of offset 0 keeps two wait states between any
+// VALU write of the coefficient register and its first DPP read (it is
+// written by LDS loads only).
+template <int A, bool Init>
+__device__ __forceinline__ void dpp_term(float &acc, float c, float w) {
+  if constexpr (Init) {
+    if constexpr (A == 0)
+      asm volatile("s_nop 1\n\tv_mul_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf"
+                   : "=v"(acc)
+                   : "v"(c), "v"(w));
+    else
+      asm volatile("v_mul_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                   : "=v"(acc)
+                   : "v"(c), "v"(w), "n"(A));
+  } else {
+    if constexpr (A == 0)
+      asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf"
+                   : "+v"(acc)
+                   : "v"(c), "v"(w));
+    else
+      asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                   : "+v"(acc)
+                   : "v"(c), "v"(w), "n"(A));
+  }
 }
-// one stencil offset a for all rows q (independent sums back to back), then
-// the next offset; even and odd offsets into separate partial sums
-template <int A, int... Qs>
-__device__ __forceinline__ void fmac_offset(float *acc, const float *cf, const float *win,
-                                            std::integer_sequence<int, Qs...>) {
+// stencil offset A of one line for every row q of the strip: even offsets
+// into ps[q], odd ones into ps[BX + q]; Init starts the sums (offsets 0, 1
+// of the first line of a pair)
+template <int A, bool Init, int... Qs>
+__device__ __forceinline__ void dpp_offset(float *ps, const float *cf, const float *win,
+                                           std::integer_sequence<int, Qs...>) {
   constexpr int BXN = sizeof...(Qs);
-  (fmac_bcast<A>(acc[(A & 1) * BXN + Qs], cf[Qs], win[Qs + A]), ...);
+  (dpp_term<A, Init && (A < 2)>(ps[(A & 1) * BXN + Qs], cf[Qs], win[Qs + A]), ...);
 }
-template <int BX, int... As>
-__device__ __forceinline__ void fmac_rows_by_offset(float *acc, const float *cf,
-                                                    const float *win,
-                                                    std::integer_sequence<int, As...>) {
-  (fmac_offset<As>(acc, cf, win, std::make_integer_sequence<int, BX>{}), ...);
+template <int BX, bool Init, int... As>
+__device__ __forceinline__ void dpp_line_offsets(float *ps, const float *cf, const float *win,
+                                                 std::integer_sequence<int, As...>) {
+  (dpp_offset<As, Init>(ps, cf, win, std::make_integer_sequence<int, BX>{}), ...);
 }
-template <int BX, int S1>
-__device__ __forceinline__ void fmac_rows(float *acc, const float *cf, const float *win) {
-  fmac_rows_by_offset<BX>(acc, cf, win, std::make_integer_sequence<int, S1>{});
+template <int BX, int S1, bool Init>
+__device__ __forceinline__ void dpp_line(float *ps, const float *cf, const float *win) {
+  dpp_line_offsets<BX, Init>(ps, cf, win, std::make_integer_sequence<int, S1>{});
 }
 
+#ifndef SP_RHS_WAVES_PER_EU
+#define SP_RHS_WAVES_PER_EU 3
+#endif
 template <int P, int BX>
-__global__ __launch_bounds__(256) void sp2d_rhs_kernel(const GsTile *tiles, int ntiles, int nrhs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SP_RHS_WAVES_PER_EU))) void sp2d_rhs_kernel(const GsTile *tiles, int ntiles, int nrhs,
                                                        const float *__restrict__ st,
                                                        const unsigned char *__restrict__ mask,
                                                        const float *__restrict__ ut,
@@ -1507,7 +1524,6 @@ __global__ __launch_bounds__(256) void sp2d_rhs_kernel(const GsTile *tiles, int 
   const GsTile tl = tiles[item];
   const int lane = threadIdx.x & 63, l16 = lane & 15;
   const int zg = blockIdx.y;
-  const int z = zg * 64 + lane;
   const int nx = tl.nx;
   const int x0 = tl.i0[0], y = tl.i0[1];
   const long long off = tl.off;
@@ -1527,8 +1543,11 @@ __global__ __launch_bounds__(256) void sp2d_rhs_kernel(const GsTile *tiles, int 
     for (int i = 0; i < WX; ++i) win[i] = lb[i * 64];
   };
   // the strip's BX rows of coefficients (contiguous) into this wavefront's
-  // LDS slice, all loads in flight at once
-  __shared__ float sC[4][BX * SP];
+  // LDS slice, all loads in flight at once; the slice holds the strip's
+  // results afterwards ([right-hand side][row], odd pitch BX + 1)
+  constexpr int OP = BX + 1;
+  constexpr int LW = BX * SP > 64 * OP ? BX * SP : 64 * OP;
+  __shared__ float sC[4][LW];
   float *sc = sC[w];
   {
     constexpr int N4 = BX * SP / 4, PER = (N4 + 63) / 64;
@@ -1554,23 +1573,15 @@ __global__ __launch_bounds__(256) void sp2d_rhs_kernel(const GsTile *tiles, int 
 #pragma unroll
     for (int q = 0; q < BX; ++q) cf[q] = cb[q * SP];
   };
-  // Summation order (float32): each stencil line's products go into two
-  // partial sums (even and odd offsets), added into the row's line total;
-  // even and odd lines into two totals, added at the end -- chains of at
-  // most 7 additions, close to the tree of the 16-lane row kernels (a single
-  // running sum of all (2p+1)^2 products loses enough accuracy to cost the
-  // float64 iterative refinement an extra step)
-  float acc[2][BX];
+  // Summation order (float32): the products of a pair of stencil lines go
+  // into two partial sums per row (even and odd offsets, chains of at most
+  // 14), added into the row's total once per pair (7 pairs) -- close to the
+  // tree of the 16-lane row kernels (a single running sum of all (2p+1)^2
+  // products loses enough accuracy to cost the float64 iterative refinement
+  // an extra step)
+  float tot[BX], ps[2 * BX];
 #pragma unroll
-  for (int q = 0; q < BX; ++q) acc[0][q] = acc[1][q] = 0.0f;
-  auto line = [&](float *tot, const float *cf, const float *win) {
-    float ls[2 * BX];
-#pragma unroll
-    for (int q = 0; q < 2 * BX; ++q) ls[q] = 0.0f;
-    fmac_rows<BX, S1>(ls, cf, win);
-#pragma unroll
-    for (int q = 0; q < BX; ++q) tot[q] += ls[q] + ls[BX + q];
-  };
+  for (int q = 0; q < BX; ++q) tot[q] = 0.0f;
   float wa[WX], wb[WX], ca[BX], cb2[BX];
   load_line(0, wa);
   load_coef(0, ca);
@@ -1582,24 +1593,39 @@ __global__ __launch_bounds__(256) void sp2d_rhs_kernel(const GsTile *tiles, int 
       load_line(b + 1, wb);
       load_coef(b + 1, cb2);
     }
-    line(acc[0], ca, wa);
+    dpp_line<BX, S1, true>(ps, ca, wa);
     if (b + 1 < S1) {
       if (b + 2 < S1) {
         load_line(b + 2, wa);
         load_coef(b + 2, ca);
       }
-      line(acc[1], cb2, wb);
+      dpp_line<BX, S1, false>(ps, cb2, wb);
     }
-  }
-  if (z >= nrhs) return;
-  const long long zo = (long long)z * vs;
 #pragma unroll
-  for (int q = 0; q < BX; ++q) {
-    if (q >= nq) break;
-    const long long t = off + (long long)y * nx + x0 + q;
-    float v = alpha * (acc[0][q] + acc[1][q]);
-    if (f) v += beta * (fw ? fw[t] : 1.0f) * f[zo + t];
-    r[zo + t] = mask[t] ? v : 0.0f;
+    for (int q = 0; q < BX; ++q) tot[q] += ps[q] + ps[BX + q];
+  }
+  // Results through LDS: lane z has the strip's BX totals of right-hand
+  // side z; 16 lanes then take the rows of one right-hand side (four per
+  // instruction), so that a load of f or a store of r covers the strip's
+  // consecutive rows of four right-hand sides instead of one value in each
+  // of 64 vectors
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int q = 0; q < BX; ++q) sc[lane * OP + q] = alpha * tot[q];
+  __builtin_amdgcn_wave_barrier();
+  const int qq = lane & 15, zs = lane >> 4;
+  if (qq >= nq) return;
+  const long long t = off + (long long)y * nx + x0 + qq;
+  const bool keep = mask[t] != 0;
+  const float wf = f ? beta * (fw ? fw[t] : 1.0f) : 0.0f;
+#pragma unroll 4
+  for (int zz = 0; zz < 16; ++zz) {
+    const int zl = zz * 4 + zs, zr = zg * 64 + zl;
+    if (zr >= nrhs) break;
+    float v = sc[zl * OP + qq];
+    const long long zo = (long long)zr * vs;
+    if (f) v += wf * f[zo + t];
+    r[zo + t] = keep ? v : 0.0f;
   }
 }
 
