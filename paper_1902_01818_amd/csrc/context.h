@@ -280,6 +280,10 @@ struct Context {
   double *x = nullptr, *rr = nullptr, *z = nullptr, *pp = nullptr, *qq = nullptr, *ff = nullptr;
   double *rold = nullptr;        // previous residual (flexible CG)
   double *dd = nullptr, *rin = nullptr;  // inner correction and residual (refinement)
+  // float32 cycles: the refinement's inner iteration in float32 vectors
+  // (correction, residual, direction, operator times direction; its
+  // preconditioned residual is the finest float32 iterate)
+  float *d32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
   double *d_red = nullptr;       // reduction partials [nb][RED_BLOCKS]
   hipEvent_t ev_scal = nullptr;  // marks the scalars' copy to the host mirror
   double *d_scal = nullptr;      // device scalars [nb][S_COUNT]
@@ -292,7 +296,7 @@ struct Context {
   // (residual vector, batch size); uses counts first runs, captured at the
   // second on a private stream (the caller's may be the null stream)
   struct CycleGraph {
-    const double *r = nullptr;
+    const void *r = nullptr;  // residual the cycle reads (float64 or float32)
     int nb = 0;
     int uses = 0;
     hipGraphExec_t exec = nullptr;

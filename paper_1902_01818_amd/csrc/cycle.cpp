@@ -127,6 +127,20 @@ void precondition_launches(Context &c, const double *r, int nb) {
   L.a64.f = f_saved;
 }
 
+// z = MG(L, r, 0) from a float32 residual (the refinement's inner
+// iteration): z is the finest float32 iterate itself and must be zero on
+// entry; in the SIPG space the cycle reads r directly.
+void precondition_launches(Context &c, const float *r, int nb) {
+  LevelData &L = c.lv.back();
+  float *f_saved = L.a32.f;
+  if (L.n_glue > 0)
+    k_convert<float, float>(r, L.a32.weight, L.a32.f, L.Ntorn, nb, c.stream);
+  else
+    L.a32.f = const_cast<float *>(r);
+  mg<float>(c, (int)c.lv.size() - 1, nb);
+  L.a32.f = f_saved;
+}
+
 // The same cycle as one graph launch (option graphs).  Its launches read
 // the device mask of active right-hand sides, so one graph serves every
 // iteration; pointers and the batch size are fixed in it, hence one graph
@@ -134,7 +148,8 @@ void precondition_launches(Context &c, const double *r, int nb) {
 // as kernel attributes happens there), the second is captured on the
 // context's private stream and replayed on c.stream from then on.  The
 // cycle issues kernels only (no memset, allocation or host wait).
-void precondition(Context &c, const double *r, int nb) {
+template <typename R>
+void precondition_any(Context &c, const R *r, int nb) {
   if (!c.opt.graphs || c.opt.timing) {
     precondition_launches(c, r, nb);
     return;
@@ -182,26 +197,25 @@ void precondition(Context &c, const double *r, int nb) {
   HIPCHK(hipGraphLaunch(exec, c.stream));
 }
 
-// q = A p on the finest level in the cycle arithmetic (float64 vectors in and
-// out; a float32 cycle converts through its own finest work vectors, which
-// are free outside a cycle)
-void apply_inner(Context &c, const double *p, double *q, int nb) {
+void precondition(Context &c, const double *r, int nb) { precondition_any(c, r, nb); }
+void precondition(Context &c, const float *r, int nb) { precondition_any(c, r, nb); }
+
+// q = A p on the finest level, float32 vectors in and out
+void apply_inner(Context &c, const float *p, float *q, int nb) {
   LevelData &L = c.lv.back();
-  const long long nt = L.Ntorn;
-  if (!c.fp32()) {
-    apply64(c, p, nullptr, nullptr, q, 1.0, nb);
-    return;
-  }
   LevelArrays<float> &A = L.a32;
-  k_convert<double, float>(p, nullptr, A.u, nt, nb, c.stream);
   if (L.st_apply) {
-    k_stencil_apply<float>(c, L, A, A.u, nullptr, nullptr, 0.0f, 1.0f, A.r, nb);
+    k_stencil_apply<float>(c, L, A, p, nullptr, nullptr, 0.0f, 1.0f, q, nb);
   } else {
-    k_iface_apply<float>(c, L, A.u, nullptr, nullptr, 0.0f, 1.0f, A.r, nb);
-    k_vol_apply<float>(c, L, A.u, A.r, 1.0f, nb);
-    k_glue_sum<float>(L, A.r, nb, c.stream);
+    k_iface_apply<float>(c, L, p, nullptr, nullptr, 0.0f, 1.0f, q, nb);
+    k_vol_apply<float>(c, L, p, q, 1.0f, nb);
+    k_glue_sum<float>(L, q, nb, c.stream);
   }
-  k_convert<float, double>(A.r, nullptr, q, nt, nb, c.stream);
+}
+
+// q = A p on the finest level, float64 vectors in and out
+void apply_inner(Context &c, const double *p, double *q, int nb) {
+  apply64(c, p, nullptr, nullptr, q, 1.0, nb);
 }
 
 void read_scalars(Context &c, int nb) {
@@ -333,19 +347,10 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
       std::vector<double> ref(nb);
       for (int step = 1; step <= maxit && n_active > 0; ++step) {
         for (int j = 0; j < nb; ++j) ref[j] = res[j] * nf[j];
-        HIPCHK(hipMemcpyAsync(c.rin, r_out, bytes, hipMemcpyDeviceToDevice, c.stream));
-        k_fill(c.dd, 0.0, nt * nb, c.stream);
-        c.x = c.dd;
-        c.rr = c.rin;
-        k_fill(c.z, 0.0, nt * nb, c.stream);
-        precondition(c, c.rr, nb);
-        k_dot(c, c.rr, c.z, nt, S_RZ, 0, nb);
-        HIPCHK(hipMemcpyAsync(c.pp, c.z, bytes, hipMemcpyDeviceToDevice, c.stream));
         int inner_active = n_active;
-        for (int k = 1; inner_active > 0; ++k) {
-          apply_inner(c, c.pp, c.qq, nb);                // q = A p
-          k_dot(c, c.pp, c.qq, nt, S_PQ, 1, nb);          // alpha = rz / pq
-          k_pcg_update_xr(c, nt, nb, false);             // d += alpha p, r -= alpha q; z = 0
+        // after an inner update of S_RR: stop the right-hand sides whose
+        // inner residual met its target; false once none is left
+        auto inner_continue = [&]() {
           read_scalars(c, nb);
           bool changed = false;
           for (int j = 0; j < nb; ++j) {
@@ -359,17 +364,57 @@ int solve_batch(Context &c, const double *rhs, double *u, int nb, double tol, in
               changed = true;
             }
           }
-          if (inner_active == 0) break;
+          if (inner_active == 0) return false;
           if (changed) upload_active(c, nb);
+          return true;
+        };
+        if (c.fp32()) {
+          // float32 cycle: the inner PCG runs in float32 vectors (sums in
+          // float64); z is the finest float32 iterate, cleared by each update
+          float *z32 = L.a32.u;
+          const size_t bytes32 = (size_t)nt * nb * sizeof(float);
+          k_convert<double, float>(r_out, nullptr, c.r32, nt, nb, c.stream);
+          k_fill(c.d32, 0.0f, nt * nb, c.stream);
+          k_fill(z32, 0.0f, nt * nb, c.stream);
+          precondition(c, c.r32, nb);
+          k_dot(c, c.r32, z32, nt, S_RZ, 0, nb);
+          HIPCHK(hipMemcpyAsync(c.p32, z32, bytes32, hipMemcpyDeviceToDevice, c.stream));
+          for (;;) {
+            apply_inner(c, c.p32, c.q32, nb);                          // q = A p
+            k_dot(c, c.p32, c.q32, nt, S_PQ, 1, nb);                   // alpha = rz / pq
+            k_pcg_update_xr(c, c.d32, c.r32, c.p32, c.q32, z32, nt, nb);  // z = 0
+            if (!inner_continue()) break;
+            precondition(c, c.r32, nb);
+            k_dot(c, c.r32, z32, nt, S_RZNEW, 2, nb);  // beta = rz_new / rz
+            k_pcg_update_p(c, c.p32, z32, nt, nb);     // p = z + beta p
+          }
+          for (int j = 0; j < nb; ++j) c.h_active[j] = outer_active[j];
+          upload_active(c, nb);
+          k_add_active(c, c.x, c.d32, nt, nb);  // x += d
+        } else {
+          HIPCHK(hipMemcpyAsync(c.rin, r_out, bytes, hipMemcpyDeviceToDevice, c.stream));
+          k_fill(c.dd, 0.0, nt * nb, c.stream);
+          c.x = c.dd;
+          c.rr = c.rin;
+          k_fill(c.z, 0.0, nt * nb, c.stream);
           precondition(c, c.rr, nb);
-          k_dot(c, c.rr, c.z, nt, S_RZNEW, 2, nb);  // beta = rz_new / rz
-          k_pcg_update_p(c, nt, nb);                  // p = z + beta p
+          k_dot(c, c.rr, c.z, nt, S_RZ, 0, nb);
+          HIPCHK(hipMemcpyAsync(c.pp, c.z, bytes, hipMemcpyDeviceToDevice, c.stream));
+          for (;;) {
+            apply_inner(c, c.pp, c.qq, nb);          // q = A p
+            k_dot(c, c.pp, c.qq, nt, S_PQ, 1, nb);    // alpha = rz / pq
+            k_pcg_update_xr(c, nt, nb, false);       // d += alpha p, r -= alpha q; z = 0
+            if (!inner_continue()) break;
+            precondition(c, c.rr, nb);
+            k_dot(c, c.rr, c.z, nt, S_RZNEW, 2, nb);  // beta = rz_new / rz
+            k_pcg_update_p(c, nt, nb);                  // p = z + beta p
+          }
+          c.x = x_out;
+          c.rr = r_out;
+          for (int j = 0; j < nb; ++j) c.h_active[j] = outer_active[j];
+          upload_active(c, nb);
+          k_add_active(c, c.x, c.dd, nt, nb);  // x += d
         }
-        c.x = x_out;
-        c.rr = r_out;
-        for (int j = 0; j < nb; ++j) c.h_active[j] = outer_active[j];
-        upload_active(c, nb);
-        k_add_active(c, c.x, c.dd, nt, nb);                    // x += d
         apply64(c, c.x, c.ff, L.a64.weight, c.rr, -1.0, nb);  // r = f - A x (float64)
         k_dot(c, c.rr, c.rr, nt, S_RR, 0, nb);
         read_scalars(c, nb);

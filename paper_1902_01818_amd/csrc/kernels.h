@@ -99,12 +99,20 @@ void k_gather_compact(const double *xt, long long N, const int *cp, const int *c
 enum Scalar { S_RZ = 0, S_PQ, S_RR, S_RZNEW, S_FF, S_ALPHA, S_BETA, S_TMP, S_ZRO, S_COUNT };
 // mode 0: scal[slot] = sum; 1: alpha = rz / sum; 2: beta = sum / rz, rz = sum
 void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode, int nrhs);
+void k_dot(Context &c, const float *a, const float *b, long long n, int slot, int mode, int nrhs);
 // flexible CG: beta = ((z, r) - (z, r_old)) / rz, rz = (z, r)
 void k_dot_fcg(Context &c, long long n, int nrhs);
 // x += alpha p, r -= alpha q, ||r||^2 into S_RR; zeroes z; optionally keeps r_old
 void k_pcg_update_xr(Context &c, long long n, int nrhs, bool keep_rold);
 void k_pcg_update_p(Context &c, long long n, int nrhs);
+// the same on float32 vectors given explicitly (the inner iteration of the
+// refinement): x += alpha p, r -= alpha q, ||r||^2 into S_RR, z_zero = 0;
+// p = z + beta p
+void k_pcg_update_xr(Context &c, float *x, float *r, const float *p, const float *q,
+                     float *z_zero, long long n, int nrhs);
+void k_pcg_update_p(Context &c, float *p, const float *z, long long n, int nrhs);
 // y += x for the active right-hand sides
 void k_add_active(Context &c, double *y, const double *x, long long n, int nrhs);
+void k_add_active(Context &c, double *y, const float *x, long long n, int nrhs);
 
 }  // namespace igamg

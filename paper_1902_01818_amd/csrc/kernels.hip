@@ -2731,7 +2731,10 @@ __device__ inline double block_sum(double v, double *sh) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const double *b,
+// vectors of type T (float64, or the float32 inner iteration of the
+// refinement), sums in float64
+template <typename T>
+__global__ __launch_bounds__(256) void dot_partial_kernel(const T *a, const T *b,
                                                           const double *w, long long n,
                                                           double *part) {
   __shared__ double sh[256];
@@ -2740,7 +2743,7 @@ __global__ __launch_bounds__(256) void dot_partial_kernel(const double *a, const
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    s += (w ? w[i] : 1.0) * a[i] * b[i];
+    s += (w ? w[i] : 1.0) * (double)a[i] * (double)b[i];
   double t = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
@@ -2805,12 +2808,13 @@ __global__ __launch_bounds__(256) void dot2_final_kernel(const double *part, int
 }
 
 // x += alpha p, r -= alpha q on the right-hand sides still iterating (r_old
-// keeps r before the update when given); ||r||_w^2 partials for all; z = 0
-__global__ __launch_bounds__(256) void pcg_xr_kernel(double *x, double *r, const double *p,
-                                                     const double *q, const double *w, long long n,
+// keeps r before the update when given); ||r||_w^2 partials for all; z = 0.
+// Vectors of type T, scalars and sums in float64 (each update rounded once).
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_xr_kernel(T *x, T *r, const T *p, const T *q,
+                                                     const double *w, long long n,
                                                      const double *scal, double *part,
-                                                     double *z_zero, double *rold,
-                                                     const int *active) {
+                                                     T *z_zero, T *rold, const int *active) {
   __shared__ double sh[256];
   const int j = blockIdx.y;
   const long long zo = (long long)j * n;
@@ -2819,13 +2823,13 @@ __global__ __launch_bounds__(256) void pcg_xr_kernel(double *x, double *r, const
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    z_zero[zo + i] = 0.0;
+    z_zero[zo + i] = (T)0;
     double ri = r[zo + i];
     if (act) {
-      if (rold) rold[zo + i] = ri;
-      x[zo + i] += alpha * p[zo + i];
-      ri -= alpha * q[zo + i];
-      r[zo + i] = ri;
+      if (rold) rold[zo + i] = (T)ri;
+      x[zo + i] = (T)(x[zo + i] + alpha * p[zo + i]);
+      ri = (double)(T)(ri - alpha * q[zo + i]);
+      r[zo + i] = (T)ri;
     }
     s += w[i] * ri * ri;
   }
@@ -2833,7 +2837,8 @@ __global__ __launch_bounds__(256) void pcg_xr_kernel(double *x, double *r, const
   if (threadIdx.x == 0) part[(long long)j * gridDim.x + blockIdx.x] = t;
 }
 
-__global__ void pcg_p_kernel(double *p, const double *z, long long n, const double *scal,
+template <typename T>
+__global__ void pcg_p_kernel(T *p, const T *z, long long n, const double *scal,
                              const int *active) {
   const int j = blockIdx.y;
   if (!active[j]) return;
@@ -2841,10 +2846,11 @@ __global__ void pcg_p_kernel(double *p, const double *z, long long n, const doub
   const double beta = scal[(long long)j * S_COUNT + S_BETA];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    p[zo + i] = z[zo + i] + beta * p[zo + i];
+    p[zo + i] = (T)(z[zo + i] + beta * p[zo + i]);
 }
 
-__global__ void add_active_kernel(double *y, const double *x, long long n, const int *active) {
+template <typename T>
+__global__ void add_active_kernel(double *y, const T *x, long long n, const int *active) {
   const int j = blockIdx.y;
   if (!active[j]) return;
   const long long zo = (long long)j * n;
@@ -3045,6 +3051,8 @@ template void k_convert<double, float>(const double *, const float *, float *, l
                                        hipStream_t, float *, const int *);
 template void k_convert<float, double>(const float *, const double *, double *, long long, int,
                                        hipStream_t, double *, const int *);
+template void k_convert<float, float>(const float *, const float *, float *, long long, int,
+                                      hipStream_t, float *, const int *);
 
 int stencil_tile_2d(int p) { return p <= 3 ? 8 : 4; }
 
@@ -3765,11 +3773,19 @@ void k_gather_compact(const double *xt, long long N, const int *cp, const int *c
   gather_compact_kernel<<<grid, BS, 0, s>>>(xt, N, cp, cidx, sum, xc, Ntorn);
 }
 
-void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode, int nrhs) {
+template <typename T>
+static void dot_any(Context &c, const T *a, const T *b, long long n, int slot, int mode,
+                    int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
-  dot_partial_kernel<<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(a, b, c.lv.back().a64.weight, n,
-                                                                    c.d_red);
+  dot_partial_kernel<T><<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
+      a, b, c.lv.back().a64.weight, n, c.d_red);
   dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, slot, mode);
+}
+void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode, int nrhs) {
+  dot_any(c, a, b, n, slot, mode, nrhs);
+}
+void k_dot(Context &c, const float *a, const float *b, long long n, int slot, int mode, int nrhs) {
+  dot_any(c, a, b, n, slot, mode, nrhs);
 }
 
 void k_dot_fcg(Context &c, long long n, int nrhs) {
@@ -3781,22 +3797,42 @@ void k_dot_fcg(Context &c, long long n, int nrhs) {
 
 void k_pcg_update_xr(Context &c, long long n, int nrhs, bool keep_rold) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
-  pcg_xr_kernel<<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
+  pcg_xr_kernel<double><<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
       c.x, c.rr, c.pp, c.qq, c.lv.back().a64.weight, n, c.d_scal, c.d_red, c.z,
       keep_rold ? c.rold : nullptr, c.d_active);
+  dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
+}
+
+void k_pcg_update_xr(Context &c, float *x, float *r, const float *p, const float *q,
+                     float *z_zero, long long n, int nrhs) {
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
+  pcg_xr_kernel<float><<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
+      x, r, p, q, c.lv.back().a64.weight, n, c.d_scal, c.d_red, z_zero, nullptr, c.d_active);
   dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
 }
 
 void k_add_active(Context &c, double *y, const double *x, long long n, int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   dim3 grid(std::min<unsigned>(nblocks(n), 2048), nrhs);
-  add_active_kernel<<<grid, BS, 0, c.stream>>>(y, x, n, c.d_active);
+  add_active_kernel<double><<<grid, BS, 0, c.stream>>>(y, x, n, c.d_active);
+}
+
+void k_add_active(Context &c, double *y, const float *x, long long n, int nrhs) {
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
+  dim3 grid(std::min<unsigned>(nblocks(n), 2048), nrhs);
+  add_active_kernel<float><<<grid, BS, 0, c.stream>>>(y, x, n, c.d_active);
 }
 
 void k_pcg_update_p(Context &c, long long n, int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   dim3 grid(std::min<unsigned>(nblocks(n), 2048), nrhs);
-  pcg_p_kernel<<<grid, BS, 0, c.stream>>>(c.pp, c.z, n, c.d_scal, c.d_active);
+  pcg_p_kernel<double><<<grid, BS, 0, c.stream>>>(c.pp, c.z, n, c.d_scal, c.d_active);
+}
+
+void k_pcg_update_p(Context &c, float *p, const float *z, long long n, int nrhs) {
+  TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
+  dim3 grid(std::min<unsigned>(nblocks(n), 2048), nrhs);
+  pcg_p_kernel<float><<<grid, BS, 0, c.stream>>>(p, z, n, c.d_scal, c.d_active);
 }
 
 }  // namespace igamg

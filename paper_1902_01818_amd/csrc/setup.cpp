@@ -2114,7 +2114,12 @@ void build_context(Context &c, const igamg_patches *P, int degree, double sigma,
     c.rold = c.arena.alloc<double>(nt);
     k_fill(c.rold, 0.0, (long long)nt, c.stream);
   }
-  if (c.opt.outer == IGAMG_OUTER_IR) {
+  if (c.opt.outer == IGAMG_OUTER_IR && f32) {
+    for (float **v : {&c.d32, &c.r32, &c.p32, &c.q32}) {
+      *v = c.arena.alloc<float>(nt);
+      k_fill(*v, 0.0f, (long long)nt, c.stream);
+    }
+  } else if (c.opt.outer == IGAMG_OUTER_IR) {
     c.dd = c.arena.alloc<double>(nt);
     c.rin = c.arena.alloc<double>(nt);
     k_fill(c.dd, 0.0, (long long)nt, c.stream);
