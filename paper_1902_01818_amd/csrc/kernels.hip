@@ -1112,16 +1112,26 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   constexpr int C = (S + 15) / 16;
   constexpr int SP = 16 * C;  // padded row length (zero coefficients beyond S)
   constexpr int NPH = Q1 * Q1;
-  // window row stride: padded where the block's LDS stays within 64 KB
+  // window row stride: padded where the block's LDS stays within 64 KB.
+  // A padded row holds K = WS / W windows side by side (right-hand side r
+  // at plane r / K, columns (r % K) W ..): a read of one right-hand side
+  // keeps the padded stride's bank pattern, and the padding is not wasted
+  // LDS (at p = 6, two windows of 26 columns in a row of 52)
   constexpr int WS0 = gs_window_stride(P) > W ? gs_window_stride(P) : W;
-  constexpr bool WFIT = (size_t)RBW * NR * (W * WS0 + 2 * TT * TT) * sizeof(T) + 16 * C * 4 <= 65536;
+  constexpr int K0 = WS0 / W, NPL0 = (NR + K0 - 1) / K0;
+  constexpr bool WFIT =
+      (size_t)RBW * (NPL0 * W * WS0 + NR * 2 * TT * TT) * sizeof(T) + 16 * C * 4 <= 65536;
   constexpr int WS = WFIT ? WS0 : W;
-  constexpr int WW = W * WS;  // window of one right-hand side
+  constexpr int KW = WS / W, NPL = (NR + KW - 1) / KW;
+  constexpr int WW = W * WS;  // one plane of windows
+  // LDS offset of right-hand side r's window
+  auto roff = [](int r) { return (r / KW) * WW + (r % KW) * W; };
   // rows prefetched D classes ahead (deeper prefetch measured slower: the
-  // longer prologue outweighs the hidden latency)
+  // longer prologue outweighs the hidden latency; 3 to 8 classes ahead time
+  // the same at p = 6)
   constexpr int D0 = (sizeof(T) == 8 ? 48 : 96) / C;
   constexpr int D = D0 < 1 ? 1 : (D0 > NPH ? NPH : D0);
-  __shared__ T sUa[RBW][NR][WW];
+  __shared__ T sUa[RBW][NPL * WW];
   __shared__ T2 sBDa[RBW][NR][TT * TT];
   __shared__ int sOff[C * 16];
   // XCD-aware order: block ids go round-robin over the 8 XCDs; XCD x takes
@@ -1151,7 +1161,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     const int z = zw + r < nrhs ? zw + r : 0;
     const T *fz = f + (long long)z * vs;
     const T *uz = u + (long long)z * vs;
-    T *sU = sUa[wid][r];
+    T *sU = sUa[wid] + roff(r);
     T2 *sBD = sBDa[wid][r];
     T wv[NW], fv[NT], dv[NT];
 #pragma unroll
@@ -1222,10 +1232,10 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
   // adds a compile-time offset
   const T *ub[C];
   const int wl = (ay + P) * WS + ax + P;
-  const T *sU0 = sUa[wid][0];
+  const T *sU0 = sUa[wid];
 #pragma unroll
   for (int c = 0; c < C; ++c) ub[c] = sU0 + wl + sOff[l16 + 16 * c];
-  T *uw = sUa[wid][0] + wl;
+  T *uw = sUa[wid] + wl;
   const T2 *bdl = sBDa[wid][0] + ay * TT + ax;
 #pragma unroll
   for (int s = 0; s < NPH; ++s) {
@@ -1236,8 +1246,8 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) uv[r][c] = ub[c][r * WW + cw];
-      uold[r] = uw[r * WW + cw];
+      for (int c = 0; c < C; ++c) uv[r][c] = ub[c][roff(r) + cw];
+      uold[r] = uw[roff(r) + cw];
       const T2 bd = bdl[r * TT * TT + cl2];
       // u + (b - a.u) d: every LDS value of the class is consumed before the
       // scans, so the reads go out as one batch and none is sunk past them
@@ -1264,7 +1274,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     for (int r = 0; r < NR; ++r) acc[r] = row16_scan(acc[r]);
     if (l16 == 15 && ix < nx && iy < ny) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) uw[r * WW + cw] = fma(-acc[r], dinv[r], ubd[r]);
+      for (int r = 0; r < NR; ++r) uw[roff(r) + cw] = fma(-acc[r], dinv[r], ubd[r]);
     }
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
@@ -1274,7 +1284,7 @@ __global__ __launch_bounds__(64 * RBW) void gs2d_wave_kernel(const GsTile *tiles
     const int z = zw + r;
     if (z >= nrhs) break;
     T *uz = u + (long long)z * vs;
-    const T *sU = sUa[wid][r];
+    const T *sU = sUa[wid] + roff(r);
     for (int i = lane; i < TT * TT; i += 64) {
       int iy = y0 + i / TT, ix = x0 + i % TT;
       if (ix < nx && iy < ny) uz[off + (long long)iy * nx + ix] = sU[(iy - wy0) * WS + (ix - wx0)];
