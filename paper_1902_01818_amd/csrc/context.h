@@ -226,6 +226,9 @@ struct LevelData {
   int PW = 0, RW = 0;
   XferTile *d_rtiles = nullptr, *d_ptiles = nullptr;  // coarse-side / fine-side output tiles
   int n_rtiles = 0, n_ptiles = 0;
+  // 2D output tiles 16 rows high: 32 coarse (restriction) / 64 fine
+  // (prolongation) columns wide, or 16 where a window exceeds those kernels'
+  bool r_wide = false, p_wide = false;
   LevelArrays<double> a64;
   LevelArrays<float> a32;
   template <typename T>

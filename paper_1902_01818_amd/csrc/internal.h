@@ -67,6 +67,11 @@ struct OpTile2 {
 // Output tile of a transfer kernel (2D): up to 16 x 16 outputs of one patch
 // and the window of input entries they read, all resolved at setup so that
 // the kernel's loads depend on this record only.
+// 2D transfer tiles (16 output rows): output columns per tile and the
+// largest input window (columns x rows) each kernel form stages in LDS
+constexpr int XFER_TX = 16, XFER_WX = 64;                        // any level
+constexpr int XFER_R_TX = 32, XFER_R_WX = 72, XFER_R_WY = 40;  // restriction
+constexpr int XFER_P_TX = 64, XFER_P_WX = 40, XFER_P_WY = 16;  // prolongation
 struct XferTile {
   long long in_off, out_off;  // patch offsets in the input / output level vectors
   int in_nx, out_nx;          // x extents of the input / output patch tensors

@@ -2614,83 +2614,102 @@ __global__ void coarse_final_kernel(int n, int nsplit, const double *part, const
 }
 
 // ---------------------------------------------------------------------------
-// Transfers (2D), one 16 x 16 output tile per block:
+// Transfers (2D), one output tile of 16 rows x TXO columns per block:
 //   out[oy, ox] (+)= sum_a sum_b vy[oy][a] vx[ox][b] in[lo_y[oy] + a, lo_x[ox] + b]
 // with the banded 1D factors (at most MAXW entries per output index).
 // Restriction: in = w .* r on the fine patch, out = coarse residual (zero on
 // Dirichlet rows), the band of coarse index j being column j of the 1D
 // embedding; the coarse iterate is cleared alongside.  Prolongation: in = the
 // coarse correction, out = fine iterate += (free rows only).  The tile's
-// input window is staged in LDS in one coalesced round of loads, then
-// contracted in x and in y.  grid.x = right-hand side, grid.y = tile.
+// input window (at most WYM x WXM values) is staged in LDS in one round of
+// loads over its actual extent (consecutive threads along its rows), then
+// contracted in x and in y; a tile row of TXO outputs is one contiguous
+// segment.  grid.x = right-hand side, grid.y = tile.
 // ---------------------------------------------------------------------------
 constexpr int MAXW = 12;
-constexpr int XT = 16, XW = 64;
+constexpr int XTY = 16;
 
-template <typename T, bool RESTRICT>
+template <typename T, bool RESTRICT, int TXO, int WXM, int WYM>
 __global__ __launch_bounds__(256) void transfer2d_kernel(
     const XferTile *tiles, const int *__restrict__ lo, const T *__restrict__ val, int W,
     const T *__restrict__ in, const T *__restrict__ win, const unsigned char *__restrict__ mask_out,
     T *out, T *zero_out, long long vs_in, long long vs_out) {
-  constexpr int NL = XW * XW / 256;  // window loads per thread
-  __shared__ T sIn[XW * XW];
-  __shared__ T sX[XW * XT];
-  __shared__ T sV[2][XT][MAXW];
-  __shared__ int sLo[2][XT];
+  constexpr int NL = (WXM * WYM + 255) / 256;  // window loads per thread
+  __shared__ T sIn[WYM * WXM];
+  __shared__ T sX[WYM * TXO];
+  // x band values [entry][output column]: the lanes of the x contraction
+  // (consecutive columns) read consecutive banks
+  __shared__ T sVx[MAXW][TXO], sVy[XTY][MAXW];
+  __shared__ int sLox[TXO], sLoy[XTY];
   const XferTile tl = tiles[blockIdx.y];
   in += (long long)blockIdx.x * vs_in;
   out += (long long)blockIdx.x * vs_out;
   if (zero_out) zero_out += (long long)blockIdx.x * vs_out;
   const int tid = threadIdx.x;
-  // one round of independent loads: window (row r = e / XW, column e % XW),
-  // band starts and values
+  const int wxn = tl.wn[0], wyn = tl.wn[1], nwin = wxn * wyn;
+  // one round of independent loads: window element e = (row e / wxn,
+  // column e % wxn), band starts and values
   T wv[NL];
+  int wo[NL];
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
-    const int e = tid + 256 * j, r = e / XW, cc = e % XW;
-    const bool ok = r < tl.wn[1] && cc < tl.wn[0];
+    const int e = tid + 256 * j, r = e / wxn, cc = e - r * wxn;
+    const bool ok = e < nwin;
     const long long t = tl.in_off + (long long)(tl.w0[1] + r) * tl.in_nx + tl.w0[0] + cc;
     T v = ok ? in[t] : (T)0;
     if (RESTRICT && ok) v *= win[t];
     wv[j] = v;
+    wo[j] = ok ? r * WXM + cc : -1;
   }
-  if (tid < 2 * XT) {
+  if (tid < TXO + XTY) {
     // per-direction fields selected without indexing the record by a lane value
-    const int g = tid / XT, o = tid % XT;
+    const int g = tid < TXO ? 0 : 1, o = g ? tid - TXO : tid;
     const int no = g ? tl.no[1] : tl.no[0];
     const int row = (g ? tl.base[1] : tl.base[0]) + min(o, no - 1);
-    sLo[g][o] = lo[row] - (g ? tl.w0[1] : tl.w0[0]);
+    const int l0 = lo[row] - (g ? tl.w0[1] : tl.w0[0]);
+    if (g)
+      sLoy[o] = l0;
+    else
+      sLox[o] = l0;
 #pragma unroll
-    for (int a = 0; a < MAXW; ++a)
-      sV[g][o][a] = (a < W && o < no) ? val[(long long)row * W + a] : (T)0;
+    for (int a = 0; a < MAXW; ++a) {
+      const T v = (a < W && o < no) ? val[(long long)row * W + a] : (T)0;
+      if (g)
+        sVy[o][a] = v;
+      else
+        sVx[a][o] = v;
+    }
   }
 #pragma unroll
-  for (int j = 0; j < NL; ++j) sIn[tid + 256 * j] = wv[j];
+  for (int j = 0; j < NL; ++j)
+    if (wo[j] >= 0) sIn[wo[j]] = wv[j];
   __syncthreads();
-  const int wxn = tl.wn[0], wyn = tl.wn[1];
-  for (int e = tid; e < wyn * XT; e += 256) {
-    const int r = e / XT, ox = e % XT;
-    const int b0 = sLo[0][ox];
+  for (int e = tid; e < wyn * TXO; e += 256) {
+    const int r = e / TXO, ox = e % TXO;
+    const int b0 = sLox[ox];
     T sx = 0;
 #pragma unroll
     for (int b = 0; b < MAXW; ++b)
-      if (b < W && b0 + b < wxn) sx += sV[0][ox][b] * sIn[r * XW + b0 + b];
-    sX[r * XT + ox] = sx;
+      if (b < W && b0 + b < wxn) sx += sVx[b][ox] * sIn[r * WXM + b0 + b];
+    sX[r * TXO + ox] = sx;
   }
   __syncthreads();
-  const int tx = tid % XT, ty = tid / XT;
-  if (tx < tl.no[0] && ty < tl.no[1]) {
-    const int a0 = sLo[1][ty];
-    T sy = 0;
 #pragma unroll
-    for (int a = 0; a < MAXW; ++a)
-      if (a < W && a0 + a < wyn) sy += sV[1][ty][a] * sX[(a0 + a) * XT + tx];
-    const long long t = tl.out_off + (long long)(tl.o0[1] + ty) * tl.out_nx + tl.o0[0] + tx;
-    if (RESTRICT) {
-      out[t] = mask_out[t] ? sy : (T)0;
-      if (zero_out) zero_out[t] = 0;
-    } else if (mask_out[t]) {
-      out[t] += sy;
+  for (int k = 0; k < XTY * TXO / 256; ++k) {
+    const int e = tid + 256 * k, tx = e % TXO, ty = e / TXO;
+    if (tx < tl.no[0] && ty < tl.no[1]) {
+      const int a0 = sLoy[ty];
+      T sy = 0;
+#pragma unroll
+      for (int a = 0; a < MAXW; ++a)
+        if (a < W && a0 + a < wyn) sy += sVy[ty][a] * sX[(a0 + a) * TXO + tx];
+      const long long t = tl.out_off + (long long)(tl.o0[1] + ty) * tl.out_nx + tl.o0[0] + tx;
+      if (RESTRICT) {
+        out[t] = mask_out[t] ? sy : (T)0;
+        if (zero_out) zero_out[t] = 0;
+      } else if (mask_out[t]) {
+        out[t] += sy;
+      }
     }
   }
 }
@@ -3698,9 +3717,14 @@ void k_restrict(Context &c, LevelData &F, LevelData &C, const T *rf, T *rc, T *u
     return;
   }
   dim3 grid(nrhs, F.n_rtiles);
-  transfer2d_kernel<T, true><<<grid, 256, 0, c.stream>>>(F.d_rtiles, F.d_R_lo, F.arr<T>().R_val,
-                                                         F.RW, rf, F.arr<T>().weight, C.d_mask, rc,
-                                                         uc_zero, F.Ntorn, C.Ntorn);
+  if (F.r_wide)
+    transfer2d_kernel<T, true, XFER_R_TX, XFER_R_WX, XFER_R_WY><<<grid, 256, 0, c.stream>>>(
+        F.d_rtiles, F.d_R_lo, F.arr<T>().R_val, F.RW, rf, F.arr<T>().weight, C.d_mask, rc,
+        uc_zero, F.Ntorn, C.Ntorn);
+  else
+    transfer2d_kernel<T, true, XFER_TX, XFER_WX, XFER_WX><<<grid, 256, 0, c.stream>>>(
+        F.d_rtiles, F.d_R_lo, F.arr<T>().R_val, F.RW, rf, F.arr<T>().weight, C.d_mask, rc,
+        uc_zero, F.Ntorn, C.Ntorn);
 }
 template void k_restrict<double>(Context &, LevelData &, LevelData &, const double *, double *,
                                  double *, int);
@@ -3717,9 +3741,14 @@ void k_prolong_add(Context &c, LevelData &F, LevelData &C, const T *ec, T *uf, i
     return;
   }
   dim3 grid(nrhs, F.n_ptiles);
-  transfer2d_kernel<T, false><<<grid, 256, 0, c.stream>>>(F.d_ptiles, F.d_P_lo, F.arr<T>().P_val,
-                                                          F.PW, ec, nullptr, F.d_mask, uf, nullptr,
-                                                          C.Ntorn, F.Ntorn);
+  if (F.p_wide)
+    transfer2d_kernel<T, false, XFER_P_TX, XFER_P_WX, XFER_P_WY><<<grid, 256, 0, c.stream>>>(
+        F.d_ptiles, F.d_P_lo, F.arr<T>().P_val, F.PW, ec, nullptr, F.d_mask, uf, nullptr,
+        C.Ntorn, F.Ntorn);
+  else
+    transfer2d_kernel<T, false, XFER_TX, XFER_WX, XFER_WX><<<grid, 256, 0, c.stream>>>(
+        F.d_ptiles, F.d_P_lo, F.arr<T>().P_val, F.PW, ec, nullptr, F.d_mask, uf, nullptr,
+        C.Ntorn, F.Ntorn);
 }
 template void k_prolong_add<double>(Context &, LevelData &, LevelData &, const double *, double *,
                                     int);

@@ -1660,16 +1660,15 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
       F.pd[k].xr[g] = tb.rrow;
     }
   if (PW > 12 || RW > 12) fail(IGAMG_EUNSUPPORTED, "transfer band wider than the kernels hold");
-  // output tiles of XT x XT entries; the input window of a tile must fit the
-  // kernel's LDS window of XW x XW values
-  constexpr int XT = 16, XW = 64;
+  // output tiles of 16 rows x tx columns; the input window of every tile
+  // must fit the kernel's LDS window of wxm x wym values (false otherwise)
   auto tiles_of = [&](const LevelData &Li, const LevelData &Lo, const std::vector<int> &lo, int W,
-                      bool coarse_side) {
-    std::vector<XferTile> out;
+                      bool coarse_side, int tx, int wxm, int wym, std::vector<XferTile> &out) {
+    out.clear();
     for (int k = 0; k < Lo.K; ++k) {
       const PatchDev &pi = Li.pd[k], &po = Lo.pd[k];
-      for (int y0 = 0; y0 < po.n[1]; y0 += XT)
-        for (int x0 = 0; x0 < po.n[0]; x0 += XT) {
+      for (int y0 = 0; y0 < po.n[1]; y0 += 16)
+        for (int x0 = 0; x0 < po.n[0]; x0 += tx) {
           XferTile t{};
           t.in_off = pi.off;
           t.out_off = po.off;
@@ -1677,7 +1676,7 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
           t.out_nx = po.n[0];
           for (int g = 0; g < 2; ++g) {
             const int o0 = g == 0 ? x0 : y0;
-            const int o1 = std::min(po.n[g], o0 + XT) - 1;
+            const int o1 = std::min(po.n[g], o0 + (g == 0 ? tx : 16)) - 1;
             const int base = (coarse_side ? F.pd[k].xr[g] : F.pd[k].xp[g]) + o0;
             int mn = lo[base], mx = lo[base];
             for (int o = 0; o <= o1 - o0; ++o) {
@@ -1689,15 +1688,21 @@ static void build_transfer(Context &c, LevelData &F, const LevelData &C) {
             t.base[g] = base;
             t.w0[g] = mn;
             t.wn[g] = std::min(mx + W, pi.n[g]) - mn;
-            if (t.wn[g] > XW || mn < 0) fail(IGAMG_EUNSUPPORTED, "transfer window exceeds the kernel's LDS tile");
+            if (t.wn[g] > (g == 0 ? wxm : wym) || mn < 0) return false;
           }
           out.push_back(t);
         }
     }
-    return out;
+    return true;
   };
   if (d == 2) {
-    std::vector<XferTile> rt = tiles_of(F, C, Rlo, RW, true), pt = tiles_of(C, F, Plo, PW, false);
+    std::vector<XferTile> rt, pt;
+    F.r_wide = tiles_of(F, C, Rlo, RW, true, XFER_R_TX, XFER_R_WX, XFER_R_WY, rt);
+    if (!F.r_wide && !tiles_of(F, C, Rlo, RW, true, XFER_TX, XFER_WX, XFER_WX, rt))
+      fail(IGAMG_EUNSUPPORTED, "transfer window exceeds the kernel's LDS tile");
+    F.p_wide = tiles_of(C, F, Plo, PW, false, XFER_P_TX, XFER_P_WX, XFER_P_WY, pt);
+    if (!F.p_wide && !tiles_of(C, F, Plo, PW, false, XFER_TX, XFER_WX, XFER_WX, pt))
+      fail(IGAMG_EUNSUPPORTED, "transfer window exceeds the kernel's LDS tile");
     F.n_rtiles = (int)rt.size();
     F.n_ptiles = (int)pt.size();
     F.d_rtiles = c.arena.upload(rt, c.stream);
