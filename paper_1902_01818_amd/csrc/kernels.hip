@@ -2661,6 +2661,20 @@ __global__ __launch_bounds__(256) void transfer2d_kernel(
     wv[j] = v;
     wo[j] = ok ? r * WXM + cc : -1;
   }
+  // the tile's outputs of this thread: masks, and for the prolongation the
+  // old values, loaded with the window
+  constexpr int NO = XTY * TXO / 256;
+  long long ot[NO];
+  bool om[NO];
+  T uo[NO];
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const int e = tid + 256 * k, tx = e % TXO, ty = e / TXO;
+    const bool in_tile = tx < tl.no[0] && ty < tl.no[1];
+    ot[k] = in_tile ? tl.out_off + (long long)(tl.o0[1] + ty) * tl.out_nx + tl.o0[0] + tx : -1;
+    om[k] = in_tile && mask_out[ot[k]];
+    uo[k] = (!RESTRICT && om[k]) ? out[ot[k]] : (T)0;
+  }
   if (tid < TXO + XTY) {
     // per-direction fields selected without indexing the record by a lane value
     const int g = tid < TXO ? 0 : 1, o = g ? tid - TXO : tid;
@@ -2695,20 +2709,20 @@ __global__ __launch_bounds__(256) void transfer2d_kernel(
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < XTY * TXO / 256; ++k) {
+  for (int k = 0; k < NO; ++k) {
     const int e = tid + 256 * k, tx = e % TXO, ty = e / TXO;
-    if (tx < tl.no[0] && ty < tl.no[1]) {
+    if (ot[k] >= 0) {
       const int a0 = sLoy[ty];
       T sy = 0;
 #pragma unroll
       for (int a = 0; a < MAXW; ++a)
         if (a < W && a0 + a < wyn) sy += sVy[ty][a] * sX[(a0 + a) * TXO + tx];
-      const long long t = tl.out_off + (long long)(tl.o0[1] + ty) * tl.out_nx + tl.o0[0] + tx;
+      const long long t = ot[k];
       if (RESTRICT) {
-        out[t] = mask_out[t] ? sy : (T)0;
+        out[t] = om[k] ? sy : (T)0;
         if (zero_out) zero_out[t] = 0;
-      } else if (mask_out[t]) {
-        out[t] += sy;
+      } else if (om[k]) {
+        out[t] = uo[k] + sy;
       }
     }
   }
