@@ -2005,6 +2005,17 @@ typedef __bf16 mf_b8 __attribute__((ext_vector_type(8)));
 
 template <typename T>
 struct MfAcc;
+
+// Global-memory views of pointers read from a work-item record: the compiler
+// cannot tell such a pointer's address space and emits flat accesses, which
+// count against the LDS wait counter as well as the vector-memory one, so a
+// wait for LDS operands would also wait for every load still in flight.
+template <typename T>
+using gptr = T __attribute__((address_space(1))) *;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T *p) {
+  return (gptr<T>)p;
+}
 template <>
 struct MfAcc<double> {
   using type = mf_d4;
@@ -2260,8 +2271,9 @@ __global__ __launch_bounds__(256) void fdg_kernel(const FdGemm<T> *items) {
   const int m0 = tm * 64, n0 = tc * 64;
   if (m0 >= g.M) return;
   const long long z = blockIdx.x;
-  const T *A = g.A + z * g.a_z, *B = g.B + z * g.b_z;
-  T *C = g.C + z * g.c_z;
+  const gptr<const T> A = gmem(g.A) + z * g.a_z, B = gmem(g.B) + z * g.b_z;
+  const gptr<T> C = gmem(g.C) + z * g.c_z;
+  const gptr<const T> lam_r = gmem(g.lam_r), lam_c = gmem(g.lam_c);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, q = lane >> 4;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
@@ -2334,11 +2346,11 @@ __global__ __launch_bounds__(256) void fdg_kernel(const FdGemm<T> *items) {
         const int i = m0 + wm + 16 * t + mf_row<T>(q, r);
         if (i >= g.M) continue;
         const T v = acc[t][u][r];
-        T *o = C + (long long)i * g.c_r + j;
+        const gptr<T> o = C + (long long)i * g.c_r + j;
         if (g.mode == 0)
           *o = v;
         else if (g.mode == 1)
-          *o = v / (g.sigma + g.lam_r[i] + g.lam_c[j]);
+          *o = v / (g.sigma + lam_r[i] + lam_c[j]);
         else
           *o += g.scale * v;
       }
@@ -2381,15 +2393,15 @@ __global__ __launch_bounds__(256) void fdw_kernel(const FdWide<T> *items, int nr
   // tid % 64 (one per thread) and k tid / 64 + 4 x; right, row tid / KC +
   // RS x and k tid % KC
   const int ks = tid % KC;
-  const T *sbase[NLS];
+  gptr<const T> sbase[NLS];
   bool sok[NLS];
 #pragma unroll
   for (int x = 0; x < NLS; ++x) {
     const int row = tid / KC + RS * x;
     sok[x] = row < g.wide;
-    sbase[x] = g.S + (long long)min(row, g.wide - 1) * g.s_r;
+    sbase[x] = gmem(g.S) + (long long)min(row, g.wide - 1) * g.s_r;
   }
-  const T *xbase[NLX];
+  gptr<const T> xbase[NLX];
   bool xok[NLX];
 #pragma unroll
   for (int x = 0; x < NLX; ++x) {
@@ -2397,7 +2409,7 @@ __global__ __launch_bounds__(256) void fdw_kernel(const FdWide<T> *items, int nr
     const int cg = min(c0 + cc, ncat - 1);
     xok[x] = c0 + cc < ncat;
     const int z = cg / g.catn, n = cg - z * g.catn;
-    xbase[x] = g.X + (long long)z * g.x_z + (RIGHT ? (long long)n * g.x_r : (long long)n);
+    xbase[x] = gmem(g.X) + (long long)z * g.x_z + (RIGHT ? (long long)n * g.x_r : (long long)n);
   }
   // raw values of the next chunk (zeroed out of range when stored to LDS,
   // so that no use of a load sits before the current chunk's products)
@@ -2465,19 +2477,20 @@ __global__ __launch_bounds__(256) void fdw_kernel(const FdWide<T> *items, int nr
     const int cg = c0 + 16 * w + c;
     if (cg >= ncat) return;
     const int z = cg / g.catn, n = cg - z * g.catn;
-    T *cb = g.C + (long long)z * g.c_z + n;
+    const gptr<T> cb = gmem(g.C) + (long long)z * g.c_z + n;
+    const gptr<const T> lam_r = gmem(g.lam_r), lam_c = gmem(g.lam_c);
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int wide = 16 * t + mf_row<T>(q, r);
         if (wide >= g.wide) continue;
-        T *o = cb + (long long)wide * g.c_r;
+        const gptr<T> o = cb + (long long)wide * g.c_r;
         const T v = acc[t][r];
         if (g.mode == 0)
           *o = v;
         else if (g.mode == 1)
-          *o = v / (g.sigma + g.lam_r[wide] + g.lam_c[n]);
+          *o = v / (g.sigma + lam_r[wide] + lam_c[n]);
         else
           *o += g.scale * v;
       }
@@ -2487,8 +2500,9 @@ __global__ __launch_bounds__(256) void fdw_kernel(const FdWide<T> *items, int nr
       const int cg = c0 + 16 * w + mf_row<T>(q, r);
       if (cg >= ncat) continue;
       const int z = cg / g.catn, n = cg - z * g.catn;
-      T *cb = g.C + (long long)z * g.c_z + (long long)n * g.c_r;
-      const T lr = g.mode == 1 ? g.sigma + g.lam_r[n] : (T)0;
+      const gptr<T> cb = gmem(g.C) + (long long)z * g.c_z + (long long)n * g.c_r;
+      const gptr<const T> lam_c = gmem(g.lam_c);
+      const T lr = g.mode == 1 ? g.sigma + gmem(g.lam_r)[n] : (T)0;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int wide = 16 * t + c;
@@ -2497,7 +2511,7 @@ __global__ __launch_bounds__(256) void fdw_kernel(const FdWide<T> *items, int nr
         if (g.mode == 0)
           cb[wide] = v;
         else if (g.mode == 1)
-          cb[wide] = v / (lr + g.lam_c[wide]);
+          cb[wide] = v / (lr + lam_c[wide]);
         else
           cb[wide] += g.scale * v;
       }
