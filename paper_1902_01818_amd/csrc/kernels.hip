@@ -2094,8 +2094,8 @@ __device__ inline void mfma_rows(const T *sA, int lda, int ka, const T *sB, int 
 // one block per CU).  Rows of B past K and columns past N are stored as zero;
 // A must be zero in columns K..Kp-1.
 template <typename T, bool BF, int NJ>
-__device__ inline void rowblock_mfma(const T *sA, int lda, const T *__restrict__ B, long long b_r,
-                                     int K, int N, T *sM, typename MfAcc<T>::type acc[NJ]) {
+__device__ inline void rowblock_mfma(const T *sA, int lda, gptr<const T> B, long long b_r, int K,
+                                     int N, T *sM, typename MfAcc<T>::type acc[NJ]) {
   constexpr int WB = Fd2mShape<NJ, BF>::WB, LDB = Fd2mShape<NJ, BF>::LDB, KS = MfK<BF>::KS;
   constexpr int KC = Fd2mShape<NJ, BF>::KC;
   constexpr int LPT = KC * WB / 256;
@@ -2148,15 +2148,16 @@ __device__ inline void piece_rows256(const PieceArgs<T> &pa, int piece, int row0
   const int n = pc.n;
   if (row0 >= n) return;  // uniform over the block
   T *spart = sm + n;  // 4 x 64 partial sums after the gathered residual (dynamic LDS)
-  const T *r = pa.r + (long long)blockIdx.x * pa.vs;
-  T *u = pa.u + (long long)blockIdx.x * pa.vs;
-  for (int j = threadIdx.x; j < n; j += 256) sm[j] = r[pa.idx[pc.idx_off + j]];
+  const gptr<const T> r = gmem(pa.r) + (long long)blockIdx.x * pa.vs;
+  const gptr<T> u = gmem(pa.u) + (long long)blockIdx.x * pa.vs;
+  const gptr<const int> idx = gmem(pa.idx), cp = gmem(pa.cp), cidx = gmem(pa.cidx);
+  for (int j = threadIdx.x; j < n; j += 256) sm[j] = r[idx[pc.idx_off + j]];
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = row0 + lane;
   T s0 = 0, s1 = 0;
   if (i < n) {
-    const T *col = pa.inv + pc.inv_off + i;
+    const gptr<const T> col = gmem(pa.inv) + pc.inv_off + i;
     int j = w;
     for (; j + 4 < n; j += 8) {
       s0 += col[(long long)j * n] * sm[j];
@@ -2168,7 +2169,7 @@ __device__ inline void piece_rows256(const PieceArgs<T> &pa, int piece, int row0
   __syncthreads();
   if (w == 0 && i < n) {
     const T y = (spart[lane] + spart[64 + lane]) + (spart[128 + lane] + spart[192 + lane]);
-    for (int c = pa.cp[pc.cp_off + i]; c < pa.cp[pc.cp_off + i + 1]; ++c) u[pa.cidx[c]] += pa.scale * y;
+    for (int c = cp[pc.cp_off + i]; c < cp[pc.cp_off + i + 1]; ++c) u[cidx[c]] += pa.scale * y;
   }
 }
 
@@ -2186,8 +2187,9 @@ __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int 
   const Fd2Item<T> it = items[blockIdx.z];
   const int i0 = blockIdx.y * 16;
   if (i0 >= it.rows) return;
-  const T *M1 = it.M1 + (long long)blockIdx.x * it.m1_z;
-  T *O = it.O + (long long)blockIdx.x * it.o_z;
+  const gptr<const T> M1 = gmem(it.M1) + (long long)blockIdx.x * it.m1_z;
+  const gptr<T> O = gmem(it.O) + (long long)blockIdx.x * it.o_z;
+  const gptr<const T> L = gmem(it.L);
   T *sL = sm;             // 16 x lda, zero beyond K1
   T *sZ = sL + 16 * lda;  // 16 x LDZ
   T *sM = sZ + 16 * LDZ;  // rows of B
@@ -2199,7 +2201,7 @@ __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int 
     for (int j = 0; j < 8; ++j) {
       const int e = e0 + tid + 256 * j;
       const int i = e / lda, a = e % lda;
-      v[j] = (e < 16 * lda && i < nrow && a < it.K1) ? it.L[(long long)(i0 + i) * it.l_r + a] : (T)0;
+      v[j] = (e < 16 * lda && i < nrow && a < it.K1) ? L[(long long)(i0 + i) * it.l_r + a] : (T)0;
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j)
@@ -2217,7 +2219,7 @@ __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int 
     for (int r = 0; r < 4; ++r) sZ[mf_row<T>(q, r) * LDZ + 16 * (w + 4 * j) + c] = acc[j][r];
     acc[j] = A4{0, 0, 0, 0};
   }
-  rowblock_mfma<T, BF, NJ>(sZ, LDZ, it.M2, it.m2_r, it.N, it.N, sM, acc);
+  rowblock_mfma<T, BF, NJ>(sZ, LDZ, gmem(it.M2), it.m2_r, it.N, it.N, sM, acc);
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int col = 16 * (w + 4 * j) + c;
@@ -2227,9 +2229,9 @@ __global__ __launch_bounds__(256) void fd2m_kernel(const Fd2Item<T> *items, int 
       const int i = mf_row<T>(q, r);
       if (i >= nrow) continue;
       const T v = acc[j][r];
-      T *o = O + (long long)(i0 + i) * it.o_r + col;
+      const gptr<T> o = O + (long long)(i0 + i) * it.o_r + col;
       if (it.lam_r)
-        *o = v / (it.sigma + it.lam_r[i0 + i] + it.lam_c[col]);
+        *o = v / (it.sigma + gmem(it.lam_r)[i0 + i] + gmem(it.lam_c)[col]);
       else
         *o += it.scale * v;
     }
@@ -2568,6 +2570,112 @@ __global__ __launch_bounds__(1024) void piece_kernel(const PieceDev *pieces, con
   const int i = row0 + (int)threadIdx.x;
   if (threadIdx.x < 64 && i < n)
     for (int c = cp[pc.cp_off + i]; c < cp[pc.cp_off + i + 1]; ++c) u[cidx[c]] += scale * y;
+}
+
+// Interface pieces of a float32 batch on the matrix cores: for each piece
+// the products Y = inv R of its n x n inverse with the residual columns of
+// 64 right-hand sides.  Block (64-row block, piece, group of 64 right-hand
+// sides); k runs in chunks of PIECE_KC.  The chunk's rows of R are gathered
+// through the piece's indices into LDS (row stride 65; thread t takes column
+// t / 4 and rows t % 4 + 4m, every index and value load of the chunk in
+// flight at once); wavefront w takes rows 16w.. of the block, its inverse
+// operands for the chunk loaded straight into registers (one contiguous row
+// segment per 16-lane row), and accumulates the four 16-column tiles of the
+// group over k in a fixed order.  Each row then adds scale Y into its copies.
+// Pieces of at most PIECE_MFMA_N unknowns (larger ones would gather R once
+// per 64 rows).
+constexpr int PIECE_MFMA_N = 1024, PIECE_KC = 120;
+__global__ __launch_bounds__(256) void piece_mfma_kernel(const PieceDev *pieces, const int *idx,
+                                                         const int *cp, const int *cidx,
+                                                         const float *inv, const float *r,
+                                                         float *u, float scale, long long vs,
+                                                         int nrhs) {
+  constexpr int LDR = 65, NJ = PIECE_KC / 4;
+  __shared__ float sR[PIECE_KC * LDR];
+  const PieceDev pc = pieces[blockIdx.y];
+  const int n = pc.n;
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= n) return;  // uniform over the block
+  const int z0 = blockIdx.z * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, c = lane & 15, q = lane >> 4;
+  const gptr<const int> gidx = gmem(idx) + pc.idx_off;
+  const gptr<const float> gr = gmem(r);
+  // this lane's inverse row (rows past n read row n - 1; their results are
+  // not stored)
+  const int arow = min(i0 + 16 * w + c, n - 1);
+  const gptr<const float> ga = gmem(inv) + pc.inv_off + (long long)arow * n;
+  const int gz = z0 + (tid >> 2), gj = tid & 3;  // gather column and first row
+  const bool zok = gz < nrhs;
+  const gptr<const float> grz = gr + (long long)(zok ? gz : 0) * vs;
+  // scatter targets of this lane's four rows, loaded ahead of the products:
+  // the copies e0 .. e1 - 1 of each row, the first one's torn index
+  const gptr<const int> gcp = gmem(cp) + pc.cp_off, gcidx = gmem(cidx);
+  int e0[4], e1[4], t0[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int i = i0 + 16 * w + mf_row<float>(q, rr);
+    e0[rr] = i < n ? gcp[i] : 0;
+    e1[rr] = i < n ? gcp[i + 1] : 0;
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) t0[rr] = e0[rr] < e1[rr] ? gcidx[e0[rr]] : -1;
+  typename MfAcc<float>::type acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < n; k0 += PIECE_KC) {
+    const int kn = min(PIECE_KC, n - k0);
+    int ix[NJ];
+    float rv[NJ], av[NJ];
+#pragma unroll
+    for (int m = 0; m < NJ; ++m) {
+      const int jj = gj + 4 * m;
+      ix[m] = gidx[k0 + min(jj, kn - 1)];
+    }
+#pragma unroll
+    for (int m = 0; m < NJ; ++m) av[m] = ga[k0 + min(4 * m + q, kn - 1)];
+#pragma unroll
+    for (int m = 0; m < NJ; ++m) rv[m] = grz[ix[m]];
+    __syncthreads();  // the previous chunk's R is consumed
+#pragma unroll
+    for (int m = 0; m < NJ; ++m) {
+      const int jj = gj + 4 * m;
+      sR[jj * LDR + (tid >> 2)] = (jj < kn && zok) ? rv[m] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NJ; ++m) {
+      const float a = 4 * m + q < kn ? av[m] : 0.0f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float b = sR[(4 * m + q) * LDR + 16 * t + c];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // first copies: every old value loaded before the stores (the rows and
+  // right-hand sides of a block are distinct unknowns), then any further
+  // copies of a row
+  float uo[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int z = z0 + 16 * t + c;
+    const gptr<float> uz = gmem(u) + (long long)(z < nrhs ? z : 0) * vs;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) uo[t][rr] = (z < nrhs && t0[rr] >= 0) ? uz[t0[rr]] : 0.0f;
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int z = z0 + 16 * t + c;
+    if (z >= nrhs) continue;
+    const gptr<float> uz = gmem(u) + (long long)z * vs;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      if (t0[rr] < 0) continue;
+      const float y = scale * acc[t][rr];
+      uz[t0[rr]] = uo[t][rr] + y;
+      for (int e = e0[rr] + 1; e < e1[rr]; ++e) uz[gcidx[e]] += y;
+    }
+  }
 }
 
 // Coarse solve in float64 whatever T: y = inv(A_0) g with g the sum of the
@@ -3714,6 +3822,10 @@ bool k_scms_interior(Context &c, LevelData &L, int nrhs) {
 template bool k_scms_interior<double>(Context &, LevelData &, int);
 template bool k_scms_interior<float>(Context &, LevelData &, int);
 
+// float32 batches of at least this many right-hand sides take the matrix-core
+// form of the interface pieces
+constexpr int PIECE_MFMA_MIN = 16;
+
 template <typename T>
 void k_pieces(Context &c, LevelData &L, int nrhs) {
   TimeScope ts(c, "pieces", L.l);
@@ -3727,6 +3839,15 @@ void k_pieces(Context &c, LevelData &L, int nrhs) {
       (const void *)piece_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
       160 * 1024 - 16 * 64 * (int)sizeof(T));
   HIPCHK(lds_set);
+  if constexpr (sizeof(T) == 4) {
+    if (nrhs >= PIECE_MFMA_MIN && L.max_piece <= PIECE_MFMA_N) {
+      dim3 g4((unsigned)((L.max_piece + 63) / 64), L.n_pieces, (nrhs + 63) / 64);
+      piece_mfma_kernel<<<g4, 256, 0, c.stream>>>(L.d_pieces, L.d_piece_idx, L.d_piece_cp,
+                                                   L.d_piece_cidx, A.piece_inv, A.r, A.u,
+                                                   (T)c.opt.damping_tau, L.Ntorn, nrhs);
+      return;
+    }
+  }
   dim3 grid(nrhs, L.n_pieces, (L.max_piece + 63) / 64);
   piece_kernel<T><<<grid, 1024, shm, c.stream>>>(
       L.d_pieces, L.d_piece_idx, L.d_piece_cp, L.d_piece_cidx, A.piece_inv, A.r, A.u,
