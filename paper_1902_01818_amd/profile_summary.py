@@ -83,8 +83,9 @@ def counter_per_dispatch(rows, kernel, grid, counter, sweep_total=None):
     seq = list(per.values())
     vals = []
     if sweep_total is None:
+        grids = None if grid is None else {int(x) for x in str(grid).split(",")}
         for name, g, v in seq:
-            if kernel in name and (grid is None or g == grid):
+            if kernel in name and (grids is None or g in grids):
                 vals.append(v)
         return vals
     run = []
@@ -98,7 +99,8 @@ def counter_per_dispatch(rows, kernel, grid, counter, sweep_total=None):
     return vals
 
 
-def traffic(fetch, write, kernel, grid, copy_bytes, copy_kernel, sweep_total=None, copy_last=False):
+def traffic(fetch, write, kernel, grid, copy_bytes, copy_kernel, sweep_total=None, copy_last=False,
+            per_launch=1):
     fr, wr = pmc_rows(fetch), pmc_rows(write)
     f = counter_per_dispatch(fr, kernel, grid, "FETCH_SIZE", sweep_total)
     w = counter_per_dispatch(wr, kernel, grid, "WRITE_SIZE", sweep_total)
@@ -123,7 +125,10 @@ def traffic(fetch, write, kernel, grid, copy_bytes, copy_kernel, sweep_total=Non
                fetch_kib=sum(f) / max(len(f), 1), write_kib=sum(w) / max(len(w), 1),
                copy_fetch_kib=cf, copy_write_kib=cw, scale_fetch=sf, scale_write=sw)
     if sf and sw:
-        res["traffic_bytes"] = res["fetch_kib"] * 1024 * sf + res["write_kib"] * 1024 * sw
+        # per launch of the timed unit: per_launch dispatches of the kernel
+        res["dispatches_per_launch"] = per_launch
+        res["traffic_bytes"] = per_launch * (res["fetch_kib"] * 1024 * sf
+                                             + res["write_kib"] * 1024 * sw)
     return res
 
 
@@ -134,11 +139,13 @@ def main():
     ap.add_argument("--title", default="rocprofv3 kernel trace")
     ap.add_argument("--cmd", default="")
     ap.add_argument("--kernel", default="")
-    ap.add_argument("--grid", type=int, default=None)
+    ap.add_argument("--grid", default=None, help="grid size, or a comma-separated list of them")
     ap.add_argument("--copy-bytes", type=float, default=0)
     ap.add_argument("--copy-kernel", default="copy")
     ap.add_argument("--sweep-total", type=int, default=None)
     ap.add_argument("--source-hash", default="")
+    ap.add_argument("--per-launch", type=int, default=1,
+                    help="dispatches of the kernel per launch of the timed unit")
     ap.add_argument("--copy-last", action="store_true",
                     help="calibrate on the last dispatch of the copy kernel")
     a = ap.parse_args()
@@ -146,7 +153,7 @@ def main():
         print(stats(a.files[0], a.title, a.cmd))
     else:
         res = traffic(a.files[0], a.files[1], a.kernel, a.grid, a.copy_bytes, a.copy_kernel,
-                      a.sweep_total, a.copy_last)
+                      a.sweep_total, a.copy_last, a.per_launch)
         res["source_hash"] = a.source_hash
         print(json.dumps(res, indent=1))
     return 0
