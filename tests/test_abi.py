@@ -72,7 +72,7 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
     assert _setup_code(ig, sq, el, 2, sigma=0.0) == ig.EINVAL              # SIPG penalty
     assert _setup_code(ig, sq, el, 2, max_rhs=-1) == ig.EINVAL
     assert _setup_code(ig, sq, el, 2, gs_tile=10) == ig.EUNSUPPORTED      # tile != 2(p+1)
-    # a degree per patch: 2D SIPG (any smoother); degrees 1..8
+    # a degree per patch: SIPG only, 2D and 3D (any smoother); degrees 1..8
     two = np.array([[[0, 0], [1, 0], [0, 1], [1, 1]], [[1, 0], [2, 0], [1, 1], [2, 1]]],
                    dtype=np.float64)
     el2 = np.array([[4, 4], [2, 2]], dtype=np.int32)
@@ -81,7 +81,9 @@ def test_setup_rejects_invalid_input_before_gpu_work(ig):
     cubes = np.array([[[x + a, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)]
                       for a in (0, 1)], dtype=np.float64)
     assert _setup_code(ig, cubes, np.full((2, 3), 2, dtype=np.int32), [2, 3],
-                       smoother="scms") == ig.EUNSUPPORTED
+                       smoother="scms", conforming=True) == ig.EUNSUPPORTED
+    assert _setup_code(ig, cubes, np.full((2, 3), 2, dtype=np.int32), [2, 5],
+                       smoother="scms") == ig.EUNSUPPORTED   # 3D degrees 1..4
     # stored operator rows exist only with a Gauss-Seidel smoother in the SIPG space
     assert _setup_code(ig, sq, el, 2, smoother="scms", operator_apply="rows") == ig.EUNSUPPORTED
     assert _setup_code(ig, sq, el, 2, conforming=True, smoother="scms",
