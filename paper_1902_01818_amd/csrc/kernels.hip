@@ -1441,17 +1441,28 @@ __global__ __launch_bounds__(256) void transpose64_kernel(const float *__restric
   // of them) go to the padded copy at lines[3 l + 1], 64 rows x 64 right-hand
   // sides at a time through LDS (odd pitch), right-hand side group g at
   // g * ptot rows
+  // the next 64 x 64 tile's loads are issued before the current tile's
+  // stores
   __shared__ float tile[64][65];
   const long long tl0 = lines[3 * blockIdx.x], pl0 = lines[3 * blockIdx.x + 1];
   const int nx = (int)lines[3 * blockIdx.x + 2];
   const int z0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  float v[16];
+  auto load = [&](int x0) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int zz = ty + 4 * m;
+      v[m] = (z0 + zz < nrhs && x0 + tx < nx) ? u[(long long)(z0 + zz) * vs + tl0 + x0 + tx]
+                                              : 0.0f;
+    }
+  };
+  load(0);
   for (int x0 = 0; x0 < nx; x0 += 64) {
-    for (int zz = ty; zz < 64; zz += 4)
-      tile[zz][tx] = (z0 + zz < nrhs && x0 + tx < nx)
-                         ? u[(long long)(z0 + zz) * vs + tl0 + x0 + tx]
-                         : 0.0f;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) tile[ty + 4 * m][tx] = v[m];
     __syncthreads();
+    if (x0 + 64 < nx) load(x0 + 64);
     for (int xx = ty; xx < 64 && x0 + xx < nx; xx += 4)
       ut[((long long)blockIdx.y * ptot + pl0 + x0 + xx) * 64 + tx] = tile[tx][xx];
     __syncthreads();
