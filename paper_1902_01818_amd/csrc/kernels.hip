@@ -2952,7 +2952,7 @@ __global__ __launch_bounds__(256) void dot2_partial_kernel(const double *z, cons
   double s1 = 0.0, s2 = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    const double zw = w[i] * z[zo + i];
+    const double zw = (w ? w[i] : 1.0) * z[zo + i];
     s1 += zw * r[zo + i];
     s2 += zw * ro[zo + i];
   }
@@ -3007,7 +3007,7 @@ __global__ __launch_bounds__(256) void pcg_xr_kernel(T *x, T *r, const T *p, con
       ri = (double)(T)(ri - alpha * q[zo + i]);
       r[zo + i] = (T)ri;
     }
-    s += w[i] * ri * ri;
+    s += (w ? w[i] : 1.0) * ri * ri;
   }
   double t = block_sum(s, sh);
   if (threadIdx.x == 0) part[(long long)j * gridDim.x + blockIdx.x] = t;
@@ -3972,12 +3972,22 @@ void k_gather_compact(const double *xt, long long N, const int *cp, const int *c
   gather_compact_kernel<<<grid, BS, 0, s>>>(xt, N, cp, cidx, sum, xc, Ntorn);
 }
 
+// Weights of the finest level's inner products: 1 on every unknown's
+// representative copy, 0 on the other copies and on Dirichlet entries (held
+// at zero in every vector the sums read).  Without glued copies the free
+// unknowns are all representatives, so the weights are dropped (same sums,
+// one vector read fewer per right-hand side).
+static const double *dot_weights(const Context &c) {
+  const LevelData &L = c.lv.back();
+  return L.n_glue > 0 ? L.a64.weight : nullptr;
+}
+
 template <typename T>
 static void dot_any(Context &c, const T *a, const T *b, long long n, int slot, int mode,
                     int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
-  dot_partial_kernel<T><<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
-      a, b, c.lv.back().a64.weight, n, c.d_red);
+  dot_partial_kernel<T><<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(a, b, dot_weights(c), n,
+                                                                       c.d_red);
   dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, slot, mode);
 }
 void k_dot(Context &c, const double *a, const double *b, long long n, int slot, int mode, int nrhs) {
@@ -3989,15 +3999,15 @@ void k_dot(Context &c, const float *a, const float *b, long long n, int slot, in
 
 void k_dot_fcg(Context &c, long long n, int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
-  dot2_partial_kernel<<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
-      c.z, c.rr, c.rold, c.lv.back().a64.weight, n, c.d_red);
+  dot2_partial_kernel<<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(c.z, c.rr, c.rold,
+                                                                     dot_weights(c), n, c.d_red);
   dot2_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal);
 }
 
 void k_pcg_update_xr(Context &c, long long n, int nrhs, bool keep_rold) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   pcg_xr_kernel<double><<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
-      c.x, c.rr, c.pp, c.qq, c.lv.back().a64.weight, n, c.d_scal, c.d_red, c.z,
+      c.x, c.rr, c.pp, c.qq, dot_weights(c), n, c.d_scal, c.d_red, c.z,
       keep_rold ? c.rold : nullptr, c.d_active);
   dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
 }
@@ -4006,7 +4016,7 @@ void k_pcg_update_xr(Context &c, float *x, float *r, const float *p, const float
                      float *z_zero, long long n, int nrhs) {
   TimeScope ts(c, "blas1", (int)c.lv.size() - 1);
   pcg_xr_kernel<float><<<dim3(RED_BLOCKS, nrhs), 256, 0, c.stream>>>(
-      x, r, p, q, c.lv.back().a64.weight, n, c.d_scal, c.d_red, z_zero, nullptr, c.d_active);
+      x, r, p, q, dot_weights(c), n, c.d_scal, c.d_red, z_zero, nullptr, c.d_active);
   dot_final_kernel<<<nrhs, 256, 0, c.stream>>>(c.d_red, RED_BLOCKS, c.d_scal, S_RR, 0);
 }
 
