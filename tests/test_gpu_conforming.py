@@ -140,3 +140,31 @@ def test_float32_cycle_lshape(outer):
     finally:
         s64.close()
         s32.close()
+
+
+@pytest.mark.parametrize("case", [("square", 8, 3, "hybrid", 0.5), ("lshape", 4, 2, "scms", 1.0)],
+                         ids=["square/8/p3/hybrid", "lshape/4/p2/scms"])
+def test_float32_batch_cycle(case):
+    """A float32 cycle on 16 right-hand sides at once in the glued space (at
+    this size the interface pieces run inside the fused SCMS launch and add
+    each row into every copy of its unknown) against the oracle's float64
+    cycle, column by column, to the float32 bar 2e-5."""
+    from paper_1902_01818_amd import igamg
+    name, lev, p, smoother, tau = case
+    corners, elems = _layout(name, lev)
+    print("conforming float32 batch case: %s %d p=%d %s" % (name, lev, p, smoother), flush=True)
+    ob = oracle.setup(corners, elems, p, conforming=True, smoother=smoother, tau=tau, delta=0.12,
+                      coarse_min=1)
+    sv = igamg.Solver(corners, elems, p, 5.0, conforming=True, smoother=smoother, tau=tau,
+                      delta=0.12, coarse_min=1, precision="fp32", max_rhs=16)
+    try:
+        rng = np.random.default_rng(23)
+        F = rng.standard_normal((16, ob.N))
+        U0 = 0.1 * rng.standard_normal((16, ob.N))
+        Ug = sv.vcycle(_to_gpu(F), _to_gpu(U0)).cpu().numpy().reshape(16, ob.N)
+        for j in range(16):
+            uo = ob.mg(ob.L, F[j], U0[j].copy())
+            assert rel_err(Ug[j], uo) < 2e-5, j
+            assert max_abs_rel(Ug[j], uo) < 2e-5, j
+    finally:
+        sv.close()
