@@ -2831,13 +2831,26 @@ __global__ __launch_bounds__(256) void transfer2d_kernel(
   for (int j = 0; j < NL; ++j)
     if (wo[j] >= 0) sIn[wo[j]] = wv[j];
   __syncthreads();
+  // contractions in groups of four band entries whose reads go out
+  // together: band values are zero past each row's band and past the patch
+  // (where the window is cut), so reads there are clamped into the window
+  // and add exact zeros (the sums are those of the band entries in order)
   for (int e = tid; e < wyn * TXO; e += 256) {
     const int r = e / TXO, ox = e % TXO;
     const int b0 = sLox[ox];
     T sx = 0;
 #pragma unroll
-    for (int b = 0; b < MAXW; ++b)
-      if (b < W && b0 + b < wxn) sx += sVx[b][ox] * sIn[r * WXM + b0 + b];
+    for (int bc = 0; bc < MAXW; bc += 4)
+      if (bc < W) {
+        T cf[4], v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cf[j] = sVx[bc + j][ox];
+          v[j] = sIn[r * WXM + min(b0 + bc + j, wxn - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sx += cf[j] * v[j];
+      }
     sX[r * TXO + ox] = sx;
   }
   __syncthreads();
@@ -2848,8 +2861,17 @@ __global__ __launch_bounds__(256) void transfer2d_kernel(
       const int a0 = sLoy[ty];
       T sy = 0;
 #pragma unroll
-      for (int a = 0; a < MAXW; ++a)
-        if (a < W && a0 + a < wyn) sy += sVy[ty][a] * sX[(a0 + a) * TXO + tx];
+      for (int ac = 0; ac < MAXW; ac += 4)
+        if (ac < W) {
+          T cf[4], v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cf[j] = sVy[ty][ac + j];
+            v[j] = sX[min(a0 + ac + j, wyn - 1) * TXO + tx];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) sy += cf[j] * v[j];
+        }
       const long long t = ot[k];
       if (RESTRICT) {
         out[t] = om[k] ? sy : (T)0;
