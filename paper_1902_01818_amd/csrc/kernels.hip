@@ -2532,32 +2532,36 @@ __global__ __launch_bounds__(256) void fdw_kernel(const FdWide<T> *items, int nr
   }
 }
 
-// ---------------------------------------------------------------------------
-// Dense solves with stored symmetric inverses: a block of 1024 threads owns 64
-// rows; wavefront w sums the columns j = w (mod 16) with lane = row, so the
-// 64 lanes read 64 consecutive entries of column j (= row j, by symmetry);
-// the 16 partial sums are added in a fixed order (deterministic).
-// ---------------------------------------------------------------------------
+// Rows row0..row0+63 of a dense symmetric matrix M (n x n, row-major) times
+// the vector sr (LDS) with 1024 threads: wavefront w takes rows row0 + 4w ..
+// row0 + 4w + 3, which are contiguous in M, its lanes striding along each row
+// (every load one 256-byte segment); each row's 64 lane sums are added by a
+// butterfly of fixed order.  spart: at least 64 values.
 template <typename T>
 __device__ inline T block_rows_matvec(const T *M, int n, int row0, const T *sr, T *spart) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = row0 + lane;
-  T s0 = 0, s1 = 0;
-  if (i < n) {
-    const T *col = M + i;
-    int j = w;
-    for (; j + 16 < n; j += 32) {
-      s0 += col[(long long)j * n] * sr[j];
-      s1 += col[(long long)(j + 16) * n] * sr[j + 16];
-    }
-    if (j < n) s0 += col[(long long)j * n] * sr[j];
+  const gptr<const T> Mg = gmem(M);
+  gptr<const T> rowp[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) rowp[q] = Mg + (long long)min(row0 + 4 * w + q, n - 1) * n;
+  T acc[4] = {0, 0, 0, 0};
+#pragma unroll 2
+  for (int j = lane; j < n; j += 64) {
+    const T x = sr[j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] += rowp[q][j] * x;
   }
-  spart[w * 64 + lane] = s0 + s1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T v = acc[q];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) spart[4 * w + q] = v;
+  }
   __syncthreads();
   T y = 0;
-  if (w == 0)
-    for (int k = 0; k < 16; ++k) y += spart[k * 64 + lane];
-  return y;  // valid in wavefront 0
+  if (w == 0) y = spart[lane];
+  return y;  // valid in wavefront 0 (rows past n: not to be stored)
 }
 
 // interface pieces: u[copies] += tau inv(P^T A P) r[piece];
